@@ -1,0 +1,134 @@
+"""Convergence of the oracle against closed-form solutions (Section 6.1):
+second order in L2 for displacement and stress with periodic and Dirichlet
+boundaries, and ablations that must lose it."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import Setup, Simulation
+
+
+def run_mms(N, sol_fn, mat, bc, tf=None, nsteps=None, dt=None, init_correction=True,
+            printed=0.0, exact_grads=True):
+    ux, uy = sol_fn(mat)
+    e = synth.Elastodynamics(ux, uy, mat)
+    dx = 1.0 / N
+    s = Setup(N, N, dx, dt(dx), (mat.cK2 - mat.cmu2) * mat.rho, mat.cmu2 * mat.rho, mat.rho, bc)
+    X, Y = s.nodes()
+    xb, yb = s.wall_points()
+    v0, sb0, u0 = e.fields(X, Y, 0.0)
+    df = e.field_gradients(X, Y, 0.0) if exact_grads else None
+    body = (lambda t: e.body_force(X, Y, t)) if e.has_body_force() else None
+    wall = (lambda t: np.stack([e.vx(xb, yb, t), e.vy(xb, yb, t)], 1)) if bc else None
+    sim = Simulation(s, v0, sb0, df, u0, body=body, wall=wall, init_correction=init_correction)
+    nrm = oracle.SpaceTimeNorms(dx, s.dt)
+
+    def rec(n, U, u):
+        v, sb, ue = e.fields(X, Y, n * s.dt)
+        nrm.add("u", u, ue)
+        nrm.add("s", s.fields_from_U(U)[1], sb)
+        nrm.add("v", U[:2], v)
+
+    if nsteps is None:
+        nsteps = int(round(tf / s.dt))
+    oracle.lib().orc_set_printed_wall_source(s.c if printed else 0.0)
+    try:
+        sim.advance(nsteps + 1, rec)   # records t_0 .. t_nsteps
+    finally:
+        oracle.lib().orc_set_printed_wall_source(0.0)
+    return nrm
+
+
+def ratios(Ns, **kw):
+    errs = [run_mms(N, **kw) for N in Ns]
+    out = {}
+    for key in ("u", "s", "v"):
+        e = [n.L2rel(key) for n in errs]
+        out[key] = [a / b for a, b in zip(e, e[1:])]
+        out[key + "_err"] = e
+    out["uinf"] = [a.Linfrel("u") / b.Linfrel("u") for a, b in zip(errs, errs[1:])]
+    return out
+
+
+def test_c1_standing_mms_periodic_second_order():
+    # periodic unit square, lambda = 1, mu = 1/2, rho = 1, half the CFL-like
+    # limit, u = sin(2 pi x) cos(2 pi y) cos(2 pi t) (1, 1) with matching body
+    # load; fixed end time, so 100/200/400 steps on 32/64/128 nodes per side
+    mat = synth.Material.from_lame(1.0, 0.5, 1.0)
+    dtf = lambda dx: synth.dt_at_cfl_fraction(dx, mat, 0.5)
+    r = {}
+    errs = []
+    for N, n in ((32, 100), (64, 200), (128, 400)):
+        errs.append(run_mms(N, lambda m: synth.standing_mms_solution(), mat, oracle.PERIODIC,
+                            nsteps=n, dt=dtf))
+    for key in ("u", "s", "v"):
+        e = [x.L2rel(key) for x in errs]
+        r[key] = [a / b for a, b in zip(e, e[1:])]
+    for key, rr in r.items():
+        for x in rr:
+            assert 3.8 < x < 4.2, (key, rr)
+
+
+@pytest.mark.parametrize("cK2,cmu2", [(1.1, 0.4), (1.4, 0.1)])
+def test_periodic_moving_mms(cK2, cmu2):
+    # Eq. periodic_moving on the periodic unit square, c = 2.5, t_f = 1/2
+    mat = synth.Material(cK2, cmu2, 1.0)
+    r = ratios((20, 40, 80), sol_fn=lambda m: synth.periodic_moving_solution(), mat=mat,
+               bc=oracle.PERIODIC, tf=0.5, dt=lambda dx: 0.4 * dx)
+    for key in ("u", "s", "uinf"):
+        assert all(3.7 < x < 4.3 for x in r[key]), (key, r[key])
+
+
+def test_dirichlet_moving_mms():
+    # same solution with Dirichlet walls: second order in L2 (Section 6.1)
+    mat = synth.Material(1.1, 0.4, 1.0)
+    r = ratios((20, 40, 80), sol_fn=lambda m: synth.periodic_moving_solution(), mat=mat,
+               bc=oracle.DIRICHLET, tf=0.5, dt=lambda dx: 0.4 * dx)
+    for key in ("u", "s"):
+        assert all(3.2 < x < 4.6 for x in r[key]), (key, r[key])
+
+
+def _plane_waves(m):
+    a = synth.plane_wave(2 * math.pi, 4 * math.pi, 0.1, 0.3, "P", m)
+    b = synth.plane_wave(4 * math.pi, -2 * math.pi, 0.1, 1.1, "S", m)
+    return a[0] + b[0], a[1] + b[1]
+
+
+@pytest.mark.parametrize("bc", [oracle.PERIODIC, oracle.DIRICHLET])
+def test_plane_waves_second_order(bc):
+    # textbook P and S waves (b = 0) with time-dependent wall data
+    mat = synth.Material.from_lame(0.8, 1.0, 1.3)
+    dtf = lambda dx: synth.dt_at_cfl_fraction(dx, mat, 0.5)
+    r = ratios((20, 40, 80), sol_fn=_plane_waves, mat=mat, bc=bc, tf=0.25, dt=dtf)
+    lo = 3.8 if bc == oracle.PERIODIC else 3.2
+    for key in ("u", "s", "v"):
+        assert all(lo < x < 4.6 for x in r[key]), (key, r[key])
+
+
+def test_central_difference_init_keeps_second_order():
+    # derivatives of U0 by central differences (multiplied by dx) instead of
+    # exact ones: still second order
+    mat = synth.Material(1.1, 0.4, 1.0)
+    r = ratios((20, 40, 80), sol_fn=lambda m: synth.periodic_moving_solution(), mat=mat,
+               bc=oracle.DIRICHLET, tf=0.25, dt=lambda dx: 0.4 * dx, exact_grads=False)
+    assert all(3.2 < x < 4.6 for x in r["u"]), r["u"]
+
+
+def test_ablation_equilibrium_init_loses_second_order():
+    # without the dt/8 correction of Eq. ic_second, U^(1)(x,0) != 0 (Section
+    # 4.2) and the stress error converges at first order only
+    mat = synth.Material(1.1, 0.4, 1.0)
+    r = ratios((20, 40, 80), sol_fn=lambda m: synth.periodic_moving_solution(), mat=mat,
+               bc=oracle.PERIODIC, tf=0.25, dt=lambda dx: 0.4 * dx, init_correction=False)
+    assert r["s"][-1] < 2.8, r["s"]
+
+
+def test_ablation_printed_wall_source_does_not_converge():
+    # printed S_ij rows 3-5 (c_K, c_mu instead of c_K/c, c_mu/c) at c = 2.5
+    mat = synth.Material.from_lame(0.8, 1.0, 1.3)
+    r = ratios((20, 40), sol_fn=_plane_waves, mat=mat, bc=oracle.DIRICHLET, tf=0.25,
+               dt=lambda dx: synth.dt_at_cfl_fraction(dx, mat, 0.5), printed=1.0)
+    assert r["u_err"][-1] > 0.3 and r["u"][0] < 1.5, r
