@@ -1,0 +1,215 @@
+#!/usr/bin/env python3
+"""Benchmark of the FP32 lattice Boltzmann step on one MI355X.
+
+Workload (one "step"): one time step of a 4096^2 periodic lattice plus one
+time step of a 2048x1024 Dirichlet lattice with time-dependent manufactured
+boundary displacement; Poisson ratio from a seed, mu = 1, rho = 1, time step at
+half the CFL-like limit; initial data are seeded plane-wave superpositions
+(exact solutions, b = 0).  Inputs are resident in HBM before timing starts.
+
+Prints one JSON line: GLUPS (lattice node updates per second, both lattices),
+the dominant kernel's achieved HBM bandwidth against the 8 TB/s peak, the FP64
+oracle's throughput on a bounded CPU sample, and the rel-L2 of the final
+periodic state against the exact discrete FP64 evolution.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "GLUPS + % HBM peak; surrogate vs plain LBM time at rel-L2 <= 1e-3"
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_LUP = 160  # 20 FP32 populations read + 20 written per node update
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--cpu-sample-steps", type=int, default=3)
+    return ap.parse_args()
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on exactly one GPU: the lattice workload is measured on one "
+              "GPU's share; multi-GPU runs are not part of this build (asked for --gpus %d)"
+              % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2408_01081_amd.lbm import Lattice
+
+    dev = torch.device("cuda:0")
+    K, W = args.steps, args.warmup
+    total = K + W
+
+    # ---- problems (config: 4096^2 periodic + 2048x1024 Dirichlet) -----------
+    t0 = time.time()
+    per = synth.plane_wave_problem(4096, 4096, synth.PERIODIC, seed=2)
+    dir_ = synth.plane_wave_problem(2048, 1024, synth.DIRICHLET, seed=2, dx=1.0 / 1024)
+    lats = []
+    for prob in (per, dir_):
+        v0, sb0 = prob.initial_fields()
+        lat = Lattice(prob.nx, prob.ny, prob.dx, prob.dt, prob.lam, prob.mu, prob.rho, prob.bc)
+        lat.init(torch.from_numpy(v0).to(dev), torch.from_numpy(sb0).to(dev))
+        if prob.bc == synth.DIRICHLET:
+            Wt, Tt = prob.wall_table(total)
+            lat.set_wall_velocity(torch.from_numpy(Wt).to(dev), torch.from_numpy(Tt).to(dev))
+        lats.append(lat)
+        del v0, sb0
+    torch.cuda.synchronize()
+    log("setup %.1fs" % (time.time() - t0))
+
+    nodes = per.nx * per.ny + dir_.nx * dir_.ny
+    for lat in lats:
+        lat.step(W)
+    torch.cuda.synchronize()
+
+    # ---- timed region ----------------------------------------------------------
+    stream = torch.cuda.current_stream(dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for lat in lats:
+        lat.step(K)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_total = e0.elapsed_time(e1)
+    ms_per_step = ms_total / K
+    glups = nodes * K / (ms_total * 1e-3) / 1e9
+    log("timed: %d steps in %.3f s (events %.3f s)" % (K, wall, ms_total * 1e-3))
+
+    # ---- dominant kernel: the 4096^2 periodic step, timed alone ----------------
+    reps = max(1, min(K, 500))
+    per_lat = lats[0]
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    per_lat.step(reps)
+    b.record(stream)
+    torch.cuda.synchronize()
+    kern_ms = a.elapsed_time(b) / reps
+    alg_bytes = BYTES_PER_LUP * per.nx * per.ny
+    achieved = alg_bytes / (kern_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": measured_traffic(),
+                "kernel": "k_step<periodic,vec4> 4096x4096", "kernel_ms": round(kern_ms, 5),
+                "algorithmic_bytes_per_launch": alg_bytes}
+
+    # ---- parity of the final periodic state vs the exact FP64 evolution -------
+    parity = None
+    if not args.no_parity:
+        try:
+            parity = periodic_parity(per, per_lat)
+        except Exception as ex:  # reported, never hidden
+            parity = {"error": repr(ex)}
+
+    # ---- CPU baseline: the FP64 oracle on a bounded sample ---------------------
+    cpu = None
+    if not args.no_cpu_baseline:
+        del lats, per_lat
+        torch.cuda.empty_cache()
+        cpu = cpu_baseline(per, dir_, args.cpu_sample_steps)
+
+    out = {
+        "metric": METRIC, "value": round(glups, 3), "unit": "GLUPS", "n_gpus": 1,
+        "steps": K, "warmup": W, "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "plain LBM FP32: periodic 4096x4096 + Dirichlet 2048x1024 "
+                               "(time-dependent manufactured walls), plane-wave data, "
+                               "nu seeded (%.4f / %.4f), rho = 1, half CFL limit"
+                               % (per.meta["nu"], dir_.meta["nu"]),
+                   "nodes_per_step": nodes, "precision": "FP32 populations, FP64 init"},
+        "hbm_frac": roofline["frac"],
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "parity": parity,
+        "wall_s": round(wall, 3),
+    }
+    print(json.dumps(out), flush=True)
+
+
+def measured_traffic():
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3
+    counter summary, if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "k_step_periodic_4096_traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+        from paper_2408_01081_amd import build as B
+        if d.get("source_sha256") != B.source_hash():
+            return None
+        return d.get("bytes_per_launch")
+    except Exception:
+        return None
+
+
+def periodic_parity(prob, lat, nsample=4096):
+    import numpy as np
+
+    import oracle
+    from oracle import spectral
+    n = lat.steps
+    s = oracle.Setup(prob.nx, prob.ny, prob.dx, prob.dt, prob.lam, prob.mu, prob.rho, prob.bc)
+    g = np.random.default_rng(123)
+    iy = g.integers(0, prob.ny, nsample)
+    ix = g.integers(0, prob.nx, nsample)
+    want = spectral.plane_wave_reference(s, prob.sol, n, iy, ix)
+    U = lat.moments_U()
+    import torch
+    got = U[:, torch.from_numpy(iy).to(U.device), torch.from_numpy(ix).to(U.device)]
+    got = got.double().cpu().numpy()
+    return {"against": "exact FP64 discrete evolution (per Fourier mode) of the same scheme",
+            "lattice": "periodic 4096x4096", "steps": n, "nodes_sampled": nsample,
+            "rel_l2": float(np.sqrt(np.sum((got - want) ** 2) / np.sum(want ** 2)))}
+
+
+def cpu_baseline(per, dir_, nsteps):
+    """Time the FP64 oracle (as it stands) on a bounded sample of the same
+    workload: nsteps steps of each lattice from its initial state."""
+    import oracle
+    t_total, lups = 0.0, 0
+    for prob in (per, dir_):
+        s = oracle.Setup(prob.nx, prob.ny, prob.dx, prob.dt, prob.lam, prob.mu, prob.rho,
+                         prob.bc)
+        v0, sb0 = prob.initial_fields()
+        f = oracle.init_populations(s, s.U_from_fields(v0, sb0))
+        del v0, sb0
+        t0 = time.perf_counter()
+        oracle.run_free(s, f, nsteps)
+        t_total += time.perf_counter() - t0
+        lups += prob.nx * prob.ny * nsteps
+        del f
+    return {"value": round(lups / t_total / 1e9, 5), "unit": "GLUPS",
+            "cores": int(oracle.lib().orc_threads()), "kind": "oracle",
+            "sample": "%d steps of each lattice (4096x4096 periodic, 2048x1024 Dirichlet with "
+                      "homogeneous walls), FP64, step loop only" % nsteps,
+            "seconds": round(t_total, 2)}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,158 @@
+/*
+ * lbm.h -- C ABI of the MI355X (gfx950) implementation of the vectorial
+ * lattice Boltzmann method for 2D linear elastodynamics
+ * (Boolakee, Geier, De Lorenzis, arXiv 2408.01081).
+ *
+ * Conventions for every entry point
+ * ---------------------------------
+ *  - C linkage, plain pointers and sizes; every function returns lbm_status
+ *    and never throws.  On error the context is left unchanged and
+ *    lbm_last_error() returns a thread-local message.
+ *  - "d_" pointers are device memory on the device that was current when the
+ *    context was created; "h_" pointers are host memory.
+ *  - The caller owns all device memory.  The library never allocates device
+ *    memory: the workspace passed to lbm_create holds the whole lattice state
+ *    and must outlive the context.  Input arrays must stay valid until the
+ *    stream has consumed them.
+ *  - All device work is enqueued on the HIP stream given at creation
+ *    (NULL = the null stream) and is asynchronous, except the calls that
+ *    return host scalars (lbm_energy, lbm_rel_l2), which synchronise the
+ *    stream.
+ *  - Field arrays are row-major [component][ny][nx] with x fastest.  Node
+ *    (k,l) sits at ((k+1/2)dx, (l+1/2)dx); for Dirichlet problems the walls
+ *    are the lines x = 0, x = nx dx, y = 0, y = ny dx, half a spacing outside
+ *    the outermost nodes (q_ij = 1/2, Eq. bc_q).
+ *  - Units are the caller's (physical).  Internally the scheme runs on the
+ *    first-order system's variables U = (v_x, v_y, j_s, j_d, j_xy)
+ *    (Eq. system) with populations in FP32.
+ *  - One context must not be used from two host threads at once.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_ctx lbm_ctx;
+
+typedef enum {
+  LBM_OK = 0,
+  LBM_E_ARG = 1,   /* invalid argument (null pointer, size, range)          */
+  LBM_E_CFL = 2,   /* 2 sqrt(c_K^2 + c_mu^2) >= dx/dt (Eq. stab_cond)        */
+  LBM_E_STATE = 3, /* call out of order (e.g. step before init)              */
+  LBM_E_SPACE = 4, /* workspace too small                                    */
+  LBM_E_HIP = 5    /* a HIP runtime call failed; see lbm_last_error()         */
+} lbm_status;
+
+typedef enum { LBM_PERIODIC = 0, LBM_DIRICHLET = 1 } lbm_bc;
+
+/* How lambda is read (Section 2.1, Eqs. 2D / plane_strain / plane_stress):
+ *   LBM_PLANE_STRAIN  lambda is the 3D Lame constant: c_K^2 = (lambda+mu)/rho
+ *   LBM_CONTINUUM_2D  lambda is the 2D Lame constant: c_K^2 = (lambda+mu)/rho
+ *   LBM_PLANE_STRESS  c_K^2 = (lambda* + mu)/rho, lambda* = 2 lambda mu/(lambda+2mu)
+ * In all cases c_mu^2 = mu/rho (Eq. all). */
+typedef enum { LBM_PLANE_STRAIN = 0, LBM_PLANE_STRESS = 1, LBM_CONTINUUM_2D = 2 } lbm_model;
+
+typedef struct {
+  int32_t nx, ny;      /* nodes per side, >= 1, nx * ny <= 2^31                   */
+  double dx, dt;       /* lattice spacing and time step; c = dx/dt               */
+  double lambda, mu;   /* Lame constants; mu > 0, lambda + mu > 0                 */
+  double rho;          /* density > 0                                            */
+  int32_t bc;          /* lbm_bc                                                 */
+  int32_t model;       /* lbm_model                                              */
+  uint32_t flags;      /* reserved, must be 0                                    */
+} lbm_params;
+
+/* Device bytes the workspace must provide for these parameters (0 if the
+ * parameters are invalid). */
+size_t lbm_workspace_bytes(const lbm_params* p);
+
+/* Validate parameters (including the CFL-like condition, Eq. stab_cond),
+ * derive the Courant numbers kK = c_K dt/dx, km = c_mu dt/dx and the norm
+ * weights k_ij = g_ij^{-1} (Eq. def_symmetrizer), bind the workspace and the
+ * stream.  *out receives a host-allocated context (free with lbm_destroy).
+ * d_ws must be 256-byte aligned. */
+lbm_status lbm_create(const lbm_params* p, void* d_ws, size_t ws_bytes, void* hip_stream,
+                      lbm_ctx** out);
+
+/* Second-order initialisation (Eq. ic_second) from physical initial data,
+ * computed in FP64 and rounded once to FP32, at time t = 0.
+ *   d_v0      [2][ny][nx] FP64  initial velocity v0 = d_t u0 (Eq. init_v)
+ *   d_sigma0  [3][ny][nx] FP64  initial Cauchy stress (xx, yy, xy) of u0
+ *   d_grad    nullable [2][5][ny][nx] FP64: d/dx then d/dy of
+ *             (v_x, v_y, sigma_xx, sigma_yy, sigma_xy) at the nodes; when
+ *             NULL the library uses second-order central differences
+ *             (periodic wrap; one-sided second order at Dirichlet walls).
+ * The stress is converted to U through Eq. sigma_num:
+ *   j_s = -(s_xx+s_yy)/(2 c_K), j_d = -(s_xx-s_yy)/(2 c_mu), j_xy = -s_xy/c_mu,
+ * s = sigma/rho.  Resets the step counter to 0. */
+lbm_status lbm_init(lbm_ctx* ctx, const double* d_v0, const double* d_sigma0,
+                    const double* d_grad);
+
+/* Load FP32 populations directly ([4][5][ny][nx], pre-collision, directions
+ * in the paper's order (1,0),(0,1),(-1,0),(0,-1), components of U) at step
+ * counter 0, with zero body load.  For checkpoints and parity tests. */
+lbm_status lbm_set_populations(lbm_ctx* ctx, const float* d_f);
+
+/* Time-dependent Dirichlet data (Eq. bc_ansatz with source Eq. bc_s) in
+ * separable form: the wall velocity du_D/dt at the midpoint x_b of wall link
+ * L at time t_n + dt/2 is  sum_r d_W[r][L][0..1] * d_T[n][r].
+ *   rank   R >= 0 (0 = homogeneous walls; pointers may then be NULL)
+ *   d_W    [R][2(nx+ny)][2] FP32, link order: left wall (node (0,l), l-major),
+ *          right wall (node (nx-1,l)), bottom wall (node (k,0)),
+ *          top wall (node (k,ny-1))
+ *   d_T    [nsteps][R] FP32, row n = time functions at t_n + dt/2
+ * Steps beyond nsteps are rejected by lbm_step.  The source rows 3-5 use
+ * c_K/c and c_mu/c (the leading-order bounce-back balance, Eq. bb0, carries
+ * the 1/c of the equilibrium; the printed speeds coincide only for c = 1).
+ * Pointers are kept (not copied) and must stay valid while stepping. */
+lbm_status lbm_set_wall_velocity(lbm_ctx* ctx, int32_t rank, const float* d_W,
+                                 const float* d_T, int64_t nsteps);
+
+/* Advance n >= 0 time steps (Section 3.6: collision with omega = 2, then
+ * streaming with periodic wrap or the Dirichlet rule), asynchronously. */
+lbm_status lbm_step(lbm_ctx* ctx, int64_t n);
+
+/* Steps taken since lbm_init / lbm_set_populations. */
+int64_t lbm_step_count(const lbm_ctx* ctx);
+
+/* Macroscopic output at the current step (Section 3.5):
+ *   d_out  [5][ny][nx] FP32: v_x, v_y, sigma_xx, sigma_yy, sigma_xy (Cauchy,
+ *          Eq. sigma_num times rho). */
+lbm_status lbm_moments(lbm_ctx* ctx, float* d_out);
+
+/* The first-order system's variables U_num = sum_ij f_ij + dt/2 B
+ * (Eq. cond_eq) at the current step, [5][ny][nx] FP32. */
+lbm_status lbm_moments_U(lbm_ctx* ctx, float* d_U);
+
+/* Pre-collision populations at the current step, [4][5][ny][nx] FP32. */
+lbm_status lbm_populations(lbm_ctx* ctx, float* d_f);
+
+/* Squared weighted L2 grid norm ||f||_P^2 = sum_x sum_ij f_ij^T k_ij f_ij
+ * (Definition grid_norm, Eq. def_symmetrizer), accumulated in FP64.
+ * Synchronises the stream. */
+lbm_status lbm_energy(lbm_ctx* ctx, double* h_out);
+
+/* Relative L2 difference ||U_num - U_ref|| / ||U_ref|| over all nodes and the
+ * five components of U, accumulated in FP64; d_ref is [5][ny][nx] FP64 in the
+ * first-order system's variables.  Synchronises the stream. */
+lbm_status lbm_rel_l2(lbm_ctx* ctx, const double* d_ref, double* h_out);
+
+/* Courant numbers (kK, kmu) and lattice speed c of a context. */
+lbm_status lbm_lattice_constants(const lbm_ctx* ctx, double* h_kK, double* h_kmu, double* h_c);
+
+/* Release the host context (the workspace stays with the caller). */
+lbm_status lbm_destroy(lbm_ctx* ctx);
+
+/* Message describing the last error on this thread ("" if none). */
+const char* lbm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

@@ -59,6 +59,7 @@ def lib():
         L.orc_wall_link.restype = i
         L.orc_run.argtypes = [i, i, i, d, d, dp, dp, dp, ctypes.c_long]
         L.orc_set_printed_wall_source.argtypes = [d]
+        L.orc_threads.restype = i
         _lib = L
     return _lib
 

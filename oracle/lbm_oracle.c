@@ -24,6 +24,7 @@
  * (q_ij = 1/2, Eq. bc_q).
  */
 #include <math.h>
+#include <omp.h>
 #include <stddef.h>
 #include <stdlib.h>
 #include <string.h>
@@ -386,3 +387,6 @@ void orc_run(int nx, int ny, int bc, double kK, double km, double* f, double* wo
   }
   if (a != f) memcpy(f, a, sizeof(double) * (size_t)NQ * NC * nx * ny);
 }
+
+/* Number of OpenMP threads a parallel region of the oracle uses. */
+int orc_threads(void) { return omp_get_max_threads(); }

@@ -75,3 +75,69 @@ def spectral_radius_periodic(kK: float, km: float, n: int = 16, omega: float = 2
             M = np.diag(np.repeat(ph, 5)) @ C
             r = max(r, float(np.abs(np.linalg.eigvals(M)).max()))
     return r
+
+
+# ---------------------------------------------------------------------------
+# Exact discrete evolution of periodic plane-wave data at any grid size
+# ---------------------------------------------------------------------------
+def _mode_table(fields):
+    """Fourier content of real fields given as SinSums at t = 0.
+
+    Returns {(a, b): complex[nf]} such that field_i(x, y) =
+    Re(sum_k C_k[i] exp(i (a x + b y)))."""
+    table = {}
+    nf = len(fields)
+    for i, s in enumerate(fields):
+        for A, a, b, w, p in s.simplified().terms:
+            z = -1j * A * np.exp(1j * p)       # A sin(th + p) = Re(-i A e^{ip} e^{i th})
+            if (a, b) < (0.0, 0.0):
+                a, b, z = -a, -b, np.conj(z)   # Re(z e^{-i th}) = Re(conj(z) e^{i th})
+            key = (round(a, 9), round(b, 9))
+            if key not in table:
+                table[key] = (a, b, np.zeros(nf, dtype=complex))
+            table[key][2][i] += z
+    return table
+
+
+def plane_wave_reference(setup, sol, nsteps: int, iy, ix):
+    """U(t_n) of the lattice scheme with central-difference initialisation,
+    for periodic plane-wave data, at the nodes (iy, ix).
+
+    The scheme is linear and shift invariant on a periodic lattice, so every
+    Fourier mode exp(i k.x) of the initial data evolves alone.  For each mode
+    the initial populations are obtained from the C oracle's initialisation
+    (Eq. ic_second) on a 5x5 patch (the centre node sees only interior central
+    differences), split into real and imaginary parts; the amplitudes are
+    advanced by (S(k) C)^n and summed at the requested nodes."""
+    import oracle  # the C oracle, for the initialisation on a patch
+
+    r = setup.rho
+    fields = [sol.vx, sol.vy, sol.sxx * r, sol.syy * r, sol.sxy * r]
+    table = _mode_table(fields)
+    dx = setup.dx
+    C = collision_matrix(setup.kK, setup.km)
+    patch = oracle.Setup(5, 5, dx, setup.dt, (setup.cK ** 2 - setup.cmu ** 2) * r,
+                         setup.cmu ** 2 * r, r, oracle.DIRICHLET)
+    xs = (np.arange(5) + 0.5) * dx
+    PX, PY = np.meshgrid(xs, xs)
+    xc, yc = xs[2], xs[2]
+    iy = np.asarray(iy)
+    ix = np.asarray(ix)
+    X = (ix + 0.5) * dx
+    Y = (iy + 0.5) * dx
+    out = np.zeros((5,) + iy.shape)
+    for a, b, Ck in table.values():
+        ph = np.exp(1j * (a * PX + b * PY))
+        parts = []
+        for comp in (np.real, np.imag):
+            v = np.stack([comp(Ck[i] * ph) for i in range(2)])
+            sb = np.stack([comp(Ck[i] * ph) for i in range(2, 5)])
+            U0 = setup.U_from_fields(v, sb)
+            parts.append(oracle.init_populations(patch, U0)[:, :, 2, 2].reshape(20))
+        amp = (parts[0] + 1j * parts[1]) * np.exp(-1j * (a * xc + b * yc))
+        phase = np.exp(-1j * (E[:, 0] * a * dx + E[:, 1] * b * dx))
+        M = np.diag(np.repeat(phase, 5)) @ C
+        an = np.linalg.matrix_power(M, nsteps) @ amp
+        Un = an.reshape(4, 5).sum(0)
+        out += np.real(Un[:, None] * np.exp(1j * (a * X + b * Y)).reshape(1, -1)).reshape(out.shape)
+    return out

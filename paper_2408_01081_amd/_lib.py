@@ -1,0 +1,72 @@
+"""ctypes loader of the in-tree HIP library (liblbm_hip.so).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels behind the C ABI declared in include/lbm.h.  There is no CPU
+fallback; a missing or unloadable library raises."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(HERE, "liblbm_hip.so")
+
+_lib = None
+
+
+class LbmError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("lbm status %d: %s" % (status, msg))
+        self.status = status
+
+
+class LbmParams(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("dx", ctypes.c_double), ("dt", ctypes.c_double),
+                ("lam", ctypes.c_double), ("mu", ctypes.c_double), ("rho", ctypes.c_double),
+                ("bc", ctypes.c_int32), ("model", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+# (name, restype, argtypes) of every exported entry point of include/lbm.h
+_VP, _I32, _I64, _D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+_PD = ctypes.POINTER(ctypes.c_double)
+SIGNATURES = [
+    ("lbm_workspace_bytes", ctypes.c_size_t, [ctypes.POINTER(LbmParams)]),
+    ("lbm_create", ctypes.c_int, [ctypes.POINTER(LbmParams), _VP, ctypes.c_size_t, _VP,
+                                  ctypes.POINTER(_VP)]),
+    ("lbm_init", ctypes.c_int, [_VP, _VP, _VP, _VP]),
+    ("lbm_set_populations", ctypes.c_int, [_VP, _VP]),
+    ("lbm_set_wall_velocity", ctypes.c_int, [_VP, _I32, _VP, _VP, _I64]),
+    ("lbm_step", ctypes.c_int, [_VP, _I64]),
+    ("lbm_step_count", _I64, [_VP]),
+    ("lbm_moments", ctypes.c_int, [_VP, _VP]),
+    ("lbm_moments_U", ctypes.c_int, [_VP, _VP]),
+    ("lbm_populations", ctypes.c_int, [_VP, _VP]),
+    ("lbm_energy", ctypes.c_int, [_VP, _PD]),
+    ("lbm_rel_l2", ctypes.c_int, [_VP, _VP, _PD]),
+    ("lbm_lattice_constants", ctypes.c_int, [_VP, _PD, _PD, _PD]),
+    ("lbm_destroy", ctypes.c_int, [_VP]),
+    ("lbm_last_error", ctypes.c_char_p, []),
+]
+
+
+def load(path: str = LIBPATH):
+    """Load the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError("HIP library %s is missing: build it with "
+                           "paper_2408_01081_amd/build.py (or __graft_entry__.build())" % path)
+    L = ctypes.CDLL(path)
+    for name, res, args in SIGNATURES:
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def check(status: int):
+    if status != 0:
+        raise LbmError(status, load().lbm_last_error().decode())

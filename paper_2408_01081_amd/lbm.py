@@ -1,0 +1,162 @@
+"""Python binding of the single-lattice C ABI (include/lbm.h).
+
+PyTorch provides the device memory (workspace, inputs, outputs) and the HIP
+stream; all computation happens in the library's kernels."""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _lib
+from ._lib import LbmParams, check
+
+PERIODIC, DIRICHLET = 0, 1
+PLANE_STRAIN, PLANE_STRESS, CONTINUUM_2D = 0, 1, 2
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("device tensor expected")
+    if not t.is_contiguous():
+        raise ValueError("contiguous tensor expected")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream_ptr(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class Lattice:
+    """One lattice problem on one GPU.
+
+    Parameters follow ``lbm_params``: nodes ``nx`` x ``ny``, spacing ``dx``,
+    time step ``dt``, Lame constants ``lam`` and ``mu``, density ``rho``,
+    boundary ``bc`` (PERIODIC or DIRICHLET) and material ``model``."""
+
+    def __init__(self, nx, ny, dx, dt, lam, mu, rho, bc=PERIODIC, model=PLANE_STRAIN,
+                 device="cuda:0"):
+        self.L = _lib.load()
+        self.device = torch.device(device)
+        self.nx, self.ny, self.bc = int(nx), int(ny), int(bc)
+        self.params = LbmParams(int(nx), int(ny), float(dx), float(dt), float(lam), float(mu),
+                                float(rho), int(bc), int(model), 0)
+        nbytes = self.L.lbm_workspace_bytes(ctypes.byref(self.params))
+        if nbytes == 0:
+            # re-run create to get the precise validation error
+            h = ctypes.c_void_p()
+            check(self.L.lbm_create(ctypes.byref(self.params), ctypes.c_void_p(256), 0, None,
+                                    ctypes.byref(h)))
+            raise RuntimeError("invalid parameters")
+        with torch.cuda.device(self.device):
+            self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+            off = (-self.ws.data_ptr()) % 256
+            self._ws_ptr = ctypes.c_void_p(self.ws.data_ptr() + off)
+            h = ctypes.c_void_p()
+            check(self.L.lbm_create(ctypes.byref(self.params), self._ws_ptr, nbytes,
+                                    _stream_ptr(self.device), ctypes.byref(h)))
+        self.ctx = h
+        self._keep = []  # inputs that must outlive queued kernels
+        kK, km, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        check(self.L.lbm_lattice_constants(self.ctx, ctypes.byref(kK), ctypes.byref(km),
+                                           ctypes.byref(c)))
+        self.kK, self.km, self.c = kK.value, km.value, c.value
+
+    def __del__(self):
+        ctx = getattr(self, "ctx", None)
+        if ctx:
+            try:
+                torch.cuda.synchronize(self.device)
+            except Exception:
+                pass
+            self.L.lbm_destroy(ctx)
+            self.ctx = None
+
+    # -- state set-up --------------------------------------------------------
+    def init(self, v0, sigma0, grad=None):
+        """Second-order initialisation from physical fields (float64 device
+        tensors [2][ny][nx], [3][ny][nx], optional [2][5][ny][nx])."""
+        ts = [t.to(self.device, torch.float64).contiguous() if t is not None else None
+              for t in (v0, sigma0, grad)]
+        self._check_shape(ts[0], (2, self.ny, self.nx))
+        self._check_shape(ts[1], (3, self.ny, self.nx))
+        if ts[2] is not None:
+            self._check_shape(ts[2], (2, 5, self.ny, self.nx))
+        check(self.L.lbm_init(self.ctx, _ptr(ts[0]), _ptr(ts[1]), _ptr(ts[2])))
+        self._keep = ts
+        return self
+
+    def set_populations(self, f):
+        t = f.to(self.device, torch.float32).contiguous()
+        self._check_shape(t, (4, 5, self.ny, self.nx))
+        check(self.L.lbm_set_populations(self.ctx, _ptr(t)))
+        self._keep = [t]
+        return self
+
+    def set_wall_velocity(self, W, T):
+        """Separable wall data: W [R][2(nx+ny)][2], T [nsteps][R] (float32)."""
+        if W is None or W.shape[0] == 0:
+            check(self.L.lbm_set_wall_velocity(self.ctx, 0, None, None, 0))
+            self._wall = None
+            return self
+        W = W.to(self.device, torch.float32).contiguous()
+        T = T.to(self.device, torch.float32).contiguous()
+        R = W.shape[0]
+        if W.shape != (R, 2 * (self.nx + self.ny), 2) or T.dim() != 2 or T.shape[1] != R:
+            raise ValueError("bad wall table shapes")
+        check(self.L.lbm_set_wall_velocity(self.ctx, R, _ptr(W), _ptr(T), T.shape[0]))
+        self._wall = (W, T)
+        return self
+
+    # -- stepping and output ---------------------------------------------------
+    def step(self, n=1):
+        check(self.L.lbm_step(self.ctx, int(n)))
+        return self
+
+    @property
+    def steps(self):
+        return int(self.L.lbm_step_count(self.ctx))
+
+    def moments(self, out=None):
+        """(v_x, v_y, sigma_xx, sigma_yy, sigma_xy) float32 [5][ny][nx]."""
+        out = self._out(out, (5, self.ny, self.nx))
+        check(self.L.lbm_moments(self.ctx, _ptr(out)))
+        return out
+
+    def moments_U(self, out=None):
+        out = self._out(out, (5, self.ny, self.nx))
+        check(self.L.lbm_moments_U(self.ctx, _ptr(out)))
+        return out
+
+    def populations(self, out=None):
+        out = self._out(out, (4, 5, self.ny, self.nx))
+        check(self.L.lbm_populations(self.ctx, _ptr(out)))
+        return out
+
+    def energy(self):
+        r = ctypes.c_double()
+        check(self.L.lbm_energy(self.ctx, ctypes.byref(r)))
+        return r.value
+
+    def rel_l2(self, refU):
+        t = refU.to(self.device, torch.float64).contiguous()
+        self._check_shape(t, (5, self.ny, self.nx))
+        r = ctypes.c_double()
+        check(self.L.lbm_rel_l2(self.ctx, _ptr(t), ctypes.byref(r)))
+        return r.value
+
+    # -- helpers ---------------------------------------------------------------
+    def _out(self, out, shape):
+        if out is None:
+            out = torch.empty(shape, dtype=torch.float32, device=self.device)
+        self._check_shape(out, shape)
+        if out.dtype != torch.float32:
+            raise ValueError("float32 output expected")
+        return out
+
+    @staticmethod
+    def _check_shape(t, shape):
+        if tuple(t.shape) != tuple(shape):
+            raise ValueError("shape %s expected, got %s" % (shape, tuple(t.shape)))

@@ -113,6 +113,18 @@ class SinSum:
             out += A * np.sin(a * x + b * y + w * t + p)
         return out
 
+    def on_grid(self, xs, ys, t=0.0):
+        """Evaluate on the tensor grid ys x xs (array [len(ys)][len(xs)]) with
+        sin(ax + by + c) = sin(ax + c) cos(by) + cos(ax + c) sin(by)."""
+        xs = np.asarray(xs, dtype=np.float64)
+        ys = np.asarray(ys, dtype=np.float64)
+        out = np.zeros((len(ys), len(xs)))
+        for A, a, b, w, p in self.terms:
+            ph = a * xs + (w * t + p)
+            out += np.outer(np.cos(b * ys), A * np.sin(ph))
+            out += np.outer(np.sin(b * ys), A * np.cos(ph))
+        return out
+
     def separable_in_time(self, x, y):
         """Split s(x_b, t) = sum_r W_r(x_b) T_r(t) at fixed points.
 
@@ -179,6 +191,14 @@ class Elastodynamics:
         sb = r * np.stack([self.sxx(x, y, t), self.syy(x, y, t), self.sxy(x, y, t)])
         u = np.stack([self.ux(x, y, t), self.uy(x, y, t)])
         return v, sb, u
+
+    def fields_on_grid(self, xs, ys, t):
+        """Like fields() on the tensor grid ys x xs, via separable evaluation."""
+        r = self.mat.rho
+        g = lambda s: s.on_grid(xs, ys, t)
+        v = np.stack([g(self.vx), g(self.vy)])
+        sb = r * np.stack([g(self.sxx), g(self.syy), g(self.sxy)])
+        return v, sb
 
     def field_gradients(self, x, y, t):
         """d/dx and d/dy of (vx, vy, sbxx, sbyy, sbxy): array [2][5][...]."""

@@ -78,9 +78,9 @@ class Problem:
     def initial_fields(self):
         if self.v0 is not None:
             return self.v0, self.sb0
-        X, Y = node_coords(self.nx, self.ny, self.dx)
-        v, sb, _ = self.sol.fields(X, Y, 0.0)
-        return v, sb
+        xs = (np.arange(self.nx) + 0.5) * self.dx
+        ys = (np.arange(self.ny) + 0.5) * self.dx
+        return self.sol.fields_on_grid(xs, ys, 0.0)
 
     def exact(self, t: float):
         X, Y = node_coords(self.nx, self.ny, self.dx)

@@ -1,0 +1,145 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Tolerances: the GPU stores FP32 populations; one step is a handful of FP32
+roundings per value (relative ~1e-7), 1000 steps accumulate to about 2e-6
+(a numpy FP32 emulation of the same operation order gives 2.0e-6 on a 256^2
+plane-wave problem), so the 1000-step bar is rel-L2 <= 1e-5."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+gpu = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _lattice(prob):
+    from paper_2408_01081_amd.lbm import Lattice
+    return Lattice(prob.nx, prob.ny, prob.dx, prob.dt, prob.lam, prob.mu, prob.rho, prob.bc)
+
+
+def _setup(prob):
+    return oracle.Setup(prob.nx, prob.ny, prob.dx, prob.dt, prob.lam, prob.mu, prob.rho, prob.bc)
+
+
+SIZES = [(1, 1), (3, 5), (4, 4), (7, 3), (67, 33), (64, 64), (260, 6), (1030, 3)]
+
+
+@gpu
+@pytest.mark.parametrize("bc", [synth.PERIODIC, synth.DIRICHLET])
+@pytest.mark.parametrize("nx,ny", SIZES)
+def test_one_step_random_populations(bc, nx, ny):
+    torch = _torch()
+    if bc == synth.DIRICHLET and min(nx, ny) < 1:
+        pytest.skip()
+    prob = synth.plane_wave_problem(nx, ny, bc, seed=nx * 31 + ny, nwaves=1, kmax=1)
+    f0 = synth.random_populations(nx + ny, nx, ny)
+    lat = _lattice(prob)
+    lat.set_populations(torch.from_numpy(f0.astype(np.float32)))
+    got0 = lat.populations().double().cpu().numpy()
+    # collide then un-collide in FP32: back to the input within a few ulp
+    assert np.abs(got0 - f0.astype(np.float32)).max() < 1e-5 * np.abs(f0).max()
+    s = _setup(prob)
+    want = f0.astype(np.float32).astype(np.float64)
+    for k in range(3):
+        lat.step(1)
+        want, _, _ = oracle.step(s, want)
+        got = lat.populations().double().cpu().numpy()
+        err = np.abs(got - want).max() / np.abs(want).max()
+        assert err < 2e-6 * (k + 1), (k, err)
+
+
+@gpu
+@pytest.mark.parametrize("bc", [synth.PERIODIC, synth.DIRICHLET])
+@pytest.mark.parametrize("nx,ny,exact", [(48, 40, True), (33, 17, False), (128, 64, False),
+                                         (2, 9, False), (5, 1, False)])
+def test_init_matches_oracle(bc, nx, ny, exact):
+    torch = _torch()
+    prob = synth.plane_wave_problem(nx, ny, bc, seed=3, nwaves=4, kmax=3)
+    v0, sb0 = prob.initial_fields()
+    X, Y = synth.node_coords(nx, ny, prob.dx)
+    grad = prob.sol.field_gradients(X, Y, 0.0) if exact else None
+    lat = _lattice(prob)
+    lat.init(torch.from_numpy(v0), torch.from_numpy(sb0),
+             None if grad is None else torch.from_numpy(grad))
+    got = lat.populations().double().cpu().numpy()
+    s = _setup(prob)
+    sim = oracle.Simulation(s, v0, sb0, grad)
+    scale = np.abs(sim.f).max()
+    assert np.abs(got - sim.f).max() < 1e-6 * scale
+    # the zeroth moment reproduces the initial state (Eq. ic_second identity)
+    U = lat.moments_U().double().cpu().numpy()
+    assert oracle.rel_l2(U, s.U_from_fields(v0, sb0)) < 1e-6
+    # physical moments
+    m = lat.moments().double().cpu().numpy()
+    assert oracle.rel_l2(m[:2], v0) < 1e-6 and oracle.rel_l2(m[2:], sb0) < 1e-6
+
+
+@gpu
+@pytest.mark.parametrize("bc,nx,ny,nsteps", [(synth.PERIODIC, 512, 512, 1000),
+                                             (synth.PERIODIC, 300, 97, 1000),
+                                             (synth.DIRICHLET, 384, 192, 1000),
+                                             (synth.DIRICHLET, 129, 67, 1000)])
+def test_many_steps_plane_waves(bc, nx, ny, nsteps):
+    torch = _torch()
+    prob = synth.plane_wave_problem(nx, ny, bc, seed=2, kmax=8)
+    v0, sb0 = prob.initial_fields()
+    lat = _lattice(prob)
+    lat.init(torch.from_numpy(v0), torch.from_numpy(sb0))
+    if bc == synth.DIRICHLET:
+        W, T = prob.wall_table(nsteps)
+        lat.set_wall_velocity(torch.from_numpy(W), torch.from_numpy(T))
+    lat.step(nsteps)
+    U = lat.moments_U().double().cpu().numpy()
+    s = _setup(prob)
+    sim = oracle.Simulation(s, v0, sb0, wall=prob.wall_velocity if bc else None)
+    sim.advance(nsteps)
+    Uo = sim.U()
+    err = oracle.rel_l2(U, Uo)
+    print("rel-L2 after %d steps, %dx%d bc=%d: %.3e" % (nsteps, nx, ny, bc, err))
+    assert err < 1e-5
+    # device-side FP64 rel-L2 agrees with the host computation
+    dev = lat.rel_l2(torch.from_numpy(Uo))
+    assert abs(dev - err) <= 1e-3 * err + 1e-12
+
+
+@gpu
+@pytest.mark.parametrize("bc", [synth.PERIODIC, synth.DIRICHLET])
+def test_energy_reduction_matches_oracle(bc):
+    torch = _torch()
+    prob = synth.plane_wave_problem(77, 45, bc, seed=9)
+    lat = _lattice(prob)
+    f0 = synth.random_populations(5, 77, 45).astype(np.float32)
+    lat.set_populations(torch.from_numpy(f0))
+    lat.step(17)
+    E = lat.energy()
+    f = lat.populations().double().cpu().numpy()
+    s = _setup(prob)
+    # collision is an isometry of ||.||_P, so the energy of the stored
+    # post-collision state equals that of the pre-collision populations
+    Eo = oracle.energy(s, f)
+    assert abs(E - Eo) / Eo < 1e-6
+    E0 = oracle.energy(s, f0.astype(np.float64))
+    assert abs(E - E0) / E0 < 1e-5   # homogeneous walls, b = 0: conserved
+
+
+@gpu
+def test_errors_reported():
+    _torch()
+    from paper_2408_01081_amd._lib import LbmError
+    from paper_2408_01081_amd.lbm import Lattice
+    with pytest.raises(LbmError) as e:
+        Lattice(16, 16, 1.0, 1.0, 1.0, 1.0, 1.0)   # CFL-like condition violated
+    assert e.value.status == 2
+    prob = synth.plane_wave_problem(16, 16, synth.DIRICHLET, seed=1)
+    lat = _lattice(prob)
+    with pytest.raises(LbmError) as e:
+        lat.step(1)                                  # step before init
+    assert e.value.status == 3

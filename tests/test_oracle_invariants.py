@@ -174,3 +174,21 @@ def test_rigid_translation_through_walls(printed, exact):
         oracle.lib().orc_set_printed_wall_source(0.0)
     err = np.abs(oracle.moments(s, f) - U0).max()
     assert (err < 1e-13) == exact, err
+
+
+@pytest.mark.parametrize("nx,ny,n", [(48, 32, 150), (40, 40, 333)])
+def test_plane_wave_reference_matches_c_oracle(nx, ny, n):
+    # per-mode exact discrete evolution (used for full-size GPU parity)
+    # equals the C oracle run on the whole grid
+    import synth
+    prob = synth.plane_wave_problem(nx, ny, synth.PERIODIC, seed=4, nwaves=5, kmax=6)
+    s = Setup(nx, ny, prob.dx, prob.dt, prob.lam, prob.mu, prob.rho, oracle.PERIODIC)
+    v0, sb0 = prob.initial_fields()
+    sim = oracle.Simulation(s, v0, sb0)
+    sim.advance(n)
+    want = sim.U()
+    g = np.random.default_rng(0)
+    iy = g.integers(0, ny, 300)
+    ix = g.integers(0, nx, 300)
+    got = spectral.plane_wave_reference(s, prob.sol, n, iy, ix)
+    assert np.abs(got - want[:, iy, ix]).max() < 1e-11 * np.abs(want).max()
