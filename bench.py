@@ -36,7 +36,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
-    ap.add_argument("--cpu-sample-steps", type=int, default=3)
+    ap.add_argument("--cpu-sample-steps", type=int, default=30)
+    ap.add_argument("--step-configs", default="",
+                    help="force launch configurations 'P,D' (periodic, Dirichlet) instead of "
+                         "autotuning, e.g. to profile the configuration a timed run chose")
     return ap.parse_args()
 
 
@@ -81,6 +84,22 @@ def main():
     log("setup %.1fs" % (time.time() - t0))
 
     nodes = per.nx * per.ny + dir_.nx * dir_.ny
+    # launch configuration chosen by the autotuner (state-preserving)
+    from paper_2408_01081_amd.lbm import step_configs
+    cfgs = step_configs()
+    tuned = []
+    forced = [int(v) for v in args.step_configs.split(",")] if args.step_configs else None
+    for li, lat in enumerate(lats):
+        if forced:
+            lat.step_config = forced[li]
+            idx = forced[li]
+        else:
+            idx, tms = lat.autotune(reps=10, use_cache=True)
+        c = cfgs[idx]
+        tuned.append({"lattice": "%dx%d" % (lat.nx, lat.ny), "config": idx, "vec": c["vec"],
+                      "threads": c["threads"], "nontemporal": c["nontemporal"],
+                      "shuffle": c["shuffle"]})
+    log("autotuned: %s" % tuned)
     for lat in lats:
         lat.step(W)
     torch.cuda.synchronize()
@@ -115,8 +134,28 @@ def main():
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": measured_traffic(),
-                "kernel": "k_step<periodic,vec4> 4096x4096", "kernel_ms": round(kern_ms, 5),
+                "kernel": "k_step (periodic 4096x4096, config %d)" % tuned[0]["config"],
+                "kernel_ms": round(kern_ms, 5),
                 "algorithmic_bytes_per_launch": alg_bytes}
+
+    # ---- reference: plain streaming copy of one population buffer -------------
+    from paper_2408_01081_amd.lbm import copy_f32
+    nflt = 20 * per.nx * per.ny
+    src = torch.ones(nflt, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        copy_f32(dst, src)
+    a.record(stream)
+    for _ in range(20):
+        copy_f32(dst, src)
+    b.record(stream)
+    torch.cuda.synchronize()
+    copy_ms = a.elapsed_time(b) / 20
+    copy_ref = {"kernel": "k_copy (16 B/lane, nontemporal stores)",
+                "bytes_per_launch": 8 * nflt, "ms": round(copy_ms, 5),
+                "GB/s": round(8 * nflt / (copy_ms * 1e-3) / 1e9, 1)}
+    roofline["copy_reference"] = copy_ref
+    del src, dst
 
     # ---- parity of the final periodic state vs the exact FP64 evolution -------
     parity = None
@@ -142,7 +181,8 @@ def main():
                                "(time-dependent manufactured walls), plane-wave data, "
                                "nu seeded (%.4f / %.4f), rho = 1, half CFL limit"
                                % (per.meta["nu"], dir_.meta["nu"]),
-                   "nodes_per_step": nodes, "precision": "FP32 populations, FP64 init"},
+                   "nodes_per_step": nodes, "precision": "FP32 populations, FP64 init",
+                   "step_configs": tuned},
         "hbm_frac": roofline["frac"],
         "roofline": roofline,
         "cpu_baseline": cpu,

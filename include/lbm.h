@@ -64,8 +64,14 @@ typedef struct {
   double rho;          /* density > 0                                            */
   int32_t bc;          /* lbm_bc                                                 */
   int32_t model;       /* lbm_model                                              */
-  uint32_t flags;      /* reserved, must be 0                                    */
+  uint32_t flags;      /* 0 or LBM_F_PLANE_LAYOUT                                 */
 } lbm_params;
+
+/* Population layout in the workspace (both: 20 FP32 planes, x fastest, rows
+ * padded to 64 floats).  Default: row-major [y][plane][x], the 20 plane rows
+ * of one lattice row contiguous.  LBM_F_PLANE_LAYOUT: plane-major
+ * [plane][y][x].  Results are bitwise identical; only speed differs. */
+#define LBM_F_PLANE_LAYOUT 1u
 
 /* Device bytes the workspace must provide for these parameters (0 if the
  * parameters are invalid). */
@@ -144,6 +150,37 @@ lbm_status lbm_rel_l2(lbm_ctx* ctx, const double* d_ref, double* h_out);
 
 /* Courant numbers (kK, kmu) and lattice speed c of a context. */
 lbm_status lbm_lattice_constants(const lbm_ctx* ctx, double* h_kK, double* h_kmu, double* h_c);
+
+/* ---- launch configurations of the step kernel and the autotuner ----------
+ * Every configuration performs the same per-node FP32 arithmetic, so all
+ * give bitwise-identical results; they differ in nodes per thread (vector
+ * width of the accesses), threads per workgroup, nontemporal stores and how
+ * the x-shifted neighbour values are obtained (extra load or lane shuffle).
+ * A configuration is valid for a grid when nx is a multiple of its vector
+ * width (and of 64 x width for the lane-shuffle variants). */
+int32_t lbm_step_config_count(void);
+lbm_status lbm_step_config_info(int32_t index, int32_t* h_vec, int32_t* h_threads,
+                                int32_t* h_nontemporal, int32_t* h_shuffle);
+lbm_status lbm_get_step_config(const lbm_ctx* ctx, int32_t* h_index);
+lbm_status lbm_set_step_config(lbm_ctx* ctx, int32_t index);
+
+/* Time every valid configuration on this context's grid (reps launches each
+ * after two warm-up launches, HIP events on the context's stream) and select
+ * the fastest.  The lattice state is not modified: timed launches read the
+ * current state and write the spare buffer.  With use_cache != 0 a previous
+ * result for the same (nx, ny, bc) in this process, or in the file named by
+ * the environment variable LBM_AUTOTUNE_CACHE, is reused without timing
+ * (*h_ms = -1 then).  New results are appended to that file.  Synchronises. */
+lbm_status lbm_autotune(lbm_ctx* ctx, int32_t reps, int32_t use_cache, int32_t* h_index,
+                        double* h_ms);
+
+/* Average duration (ms) of one step launch of configuration `index` on this
+ * context (same state-preserving scheme as lbm_autotune).  Synchronises. */
+lbm_status lbm_time_step_config(lbm_ctx* ctx, int32_t index, int32_t reps, double* h_ms);
+
+/* Plain streaming copy of n floats (n % 4 == 0, 16-byte aligned buffers) on
+ * the given stream: the bandwidth and memory-counter reference kernel. */
+lbm_status lbm_copy_f32(float* d_dst, const float* d_src, int64_t n, void* hip_stream);
 
 /* Release the host context (the workspace stays with the caller). */
 lbm_status lbm_destroy(lbm_ctx* ctx);

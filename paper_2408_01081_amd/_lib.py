@@ -45,6 +45,14 @@ SIGNATURES = [
     ("lbm_energy", ctypes.c_int, [_VP, _PD]),
     ("lbm_rel_l2", ctypes.c_int, [_VP, _VP, _PD]),
     ("lbm_lattice_constants", ctypes.c_int, [_VP, _PD, _PD, _PD]),
+    ("lbm_step_config_count", _I32, []),
+    ("lbm_step_config_info", ctypes.c_int, [_I32, ctypes.POINTER(_I32), ctypes.POINTER(_I32),
+                                            ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
+    ("lbm_get_step_config", ctypes.c_int, [_VP, ctypes.POINTER(_I32)]),
+    ("lbm_set_step_config", ctypes.c_int, [_VP, _I32]),
+    ("lbm_autotune", ctypes.c_int, [_VP, _I32, _I32, ctypes.POINTER(_I32), _PD]),
+    ("lbm_time_step_config", ctypes.c_int, [_VP, _I32, _I32, _PD]),
+    ("lbm_copy_f32", ctypes.c_int, [_VP, _VP, _I64, _VP]),
     ("lbm_destroy", ctypes.c_int, [_VP]),
     ("lbm_last_error", ctypes.c_char_p, []),
 ]

@@ -16,11 +16,15 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <map>
+#include <mutex>
 #include <new>
 #include <string>
+#include <tuple>
 
 #include "lbm.h"
 #include "lbm_kernels.hpp"
+#include "lbm_step.hpp"
 
 using namespace lbmk;
 
@@ -40,146 +44,12 @@ lbm_status hip_check(hipError_t e, const char* what) {
 
 constexpr int RED_BLOCKS = 1024;
 constexpr int RED_THREADS = 256;
-constexpr int STEP_THREADS = 256;
 
 int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 
 // ---------------------------------------------------------------------------
 // Device kernels
 // ---------------------------------------------------------------------------
-
-// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
-// L2).  Map the dispatch index so that every XCD owns one contiguous chunk of
-// tiles: neighbouring rows (y halo) and neighbouring row segments (x halo)
-// then meet in the same L2.
-__device__ inline int xcd_tile(int bid, int ntiles) {
-  const int q = ntiles >> 3, r = ntiles & 7;
-  const int xcd = bid & 7, k = bid >> 3;
-  return xcd * q + (xcd < r ? xcd : r) + k;
-}
-
-struct StepConst {
-  float kK, km;
-  int tiles_x;  // tiles per row
-  int ntiles;
-};
-
-__device__ inline int64_t pidx(const Grid& g, int p, int y, int x) {
-  return (int64_t)p * g.plane + (int64_t)y * g.pitch + x;
-}
-
-// Generic-width fused step.  One workgroup = one row segment of
-// STEP_THREADS * VEC nodes; VEC consecutive nodes per thread (VEC = 4 uses
-// 16-byte accesses and needs nx % 4 == 0).
-template <int BC, int VEC>
-__global__ __launch_bounds__(STEP_THREADS) void k_step(const float* __restrict__ src,
-                                                         float* __restrict__ dst, Grid g,
-                                                         StepConst sc, Wall w) {
-  const int tile = xcd_tile(blockIdx.x, sc.ntiles);
-  const int y = tile / sc.tiles_x;
-  const int tx = tile - y * sc.tiles_x;
-  const int x0 = (tx * STEP_THREADS + (int)threadIdx.x) * VEC;
-  if (x0 >= g.nx) return;
-  const int nx = g.nx, ny = g.ny;
-
-  // source coordinates of the four pulls (wrapped for periodic grids;
-  // clamped in range for Dirichlet grids, where the wall rule overrides them)
-  int xl = x0 - 1, xr = x0 + VEC, yb = y - 1, yt = y + 1;
-  if (BC == LBM_PERIODIC) {
-    xl = xl < 0 ? nx - 1 : xl;
-    xr = xr >= nx ? xr - nx : xr;
-    yb = yb < 0 ? ny - 1 : yb;
-    yt = yt >= ny ? 0 : yt;
-  } else {
-    xl = xl < 0 ? 0 : xl;
-    xr = xr >= nx ? nx - 1 : xr;
-    yb = yb < 0 ? 0 : yb;
-    yt = yt >= ny ? ny - 1 : yt;
-  }
-
-  float f[VEC][NQ][NC];
-  if (VEC == 1) {
-#pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      f[0][0][c] = src[pidx(g, 0 * NC + c, y, xl)];
-      f[0][1][c] = src[pidx(g, 1 * NC + c, yb, x0)];
-      f[0][2][c] = src[pidx(g, 2 * NC + c, y, xr)];
-      f[0][3][c] = src[pidx(g, 3 * NC + c, yt, x0)];
-    }
-  } else {
-#pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      const float4 a = *reinterpret_cast<const float4*>(src + pidx(g, 0 * NC + c, y, x0));
-      const float al = src[pidx(g, 0 * NC + c, y, xl)];
-      const float4 b = *reinterpret_cast<const float4*>(src + pidx(g, 2 * NC + c, y, x0));
-      const float br = src[pidx(g, 2 * NC + c, y, xr)];
-      const float4 d = *reinterpret_cast<const float4*>(src + pidx(g, 1 * NC + c, yb, x0));
-      const float4 e = *reinterpret_cast<const float4*>(src + pidx(g, 3 * NC + c, yt, x0));
-      const float av[4] = {a.x, a.y, a.z, a.w};
-      const float bv[4] = {b.x, b.y, b.z, b.w};
-      const float dv[4] = {d.x, d.y, d.z, d.w};
-      const float ev[4] = {e.x, e.y, e.z, e.w};
-#pragma unroll
-      for (int k = 0; k < VEC; ++k) {
-        f[k][0][c] = k == 0 ? al : av[k - 1];
-        f[k][2][c] = k == VEC - 1 ? br : bv[k + 1];
-        f[k][1][c] = dv[k];
-        f[k][3][c] = ev[k];
-      }
-    }
-  }
-
-  if (BC == LBM_DIRICHLET) {
-    // Eq. bc_ansatz for the links that cross a wall (corners: both links)
-#pragma unroll
-    for (int k = 0; k < VEC; ++k) {
-      const int x = x0 + k;
-      float fb[NC], a, b;
-      if (x == 0) {
-        for (int c = 0; c < NC; ++c) fb[c] = src[pidx(g, 2 * NC + c, y, x)];
-        wall_velocity(w, y, a, b);
-        wall_rule(1, 0, sc.kK, sc.km, a, b, fb, f[k][0]);
-      }
-      if (x == nx - 1) {
-        for (int c = 0; c < NC; ++c) fb[c] = src[pidx(g, 0 * NC + c, y, x)];
-        wall_velocity(w, ny + y, a, b);
-        wall_rule(-1, 0, sc.kK, sc.km, a, b, fb, f[k][2]);
-      }
-      if (y == 0) {
-        for (int c = 0; c < NC; ++c) fb[c] = src[pidx(g, 3 * NC + c, y, x)];
-        wall_velocity(w, 2 * ny + x, a, b);
-        wall_rule(0, 1, sc.kK, sc.km, a, b, fb, f[k][1]);
-      }
-      if (y == ny - 1) {
-        for (int c = 0; c < NC; ++c) fb[c] = src[pidx(g, 1 * NC + c, y, x)];
-        wall_velocity(w, 2 * ny + nx + x, a, b);
-        wall_rule(0, -1, sc.kK, sc.km, a, b, fb, f[k][3]);
-      }
-    }
-  }
-
-#pragma unroll
-  for (int k = 0; k < VEC; ++k) collide(sc.kK, sc.km, f[k]);
-
-  if (VEC == 1) {
-#pragma unroll
-    for (int q = 0; q < NQ; ++q)
-#pragma unroll
-      for (int c = 0; c < NC; ++c) dst[pidx(g, q * NC + c, y, x0)] = f[0][q][c];
-  } else {
-#pragma unroll
-    for (int q = 0; q < NQ; ++q)
-#pragma unroll
-      for (int c = 0; c < NC; ++c) {
-        float4 o;
-        o.x = f[0][q][c];
-        o.y = f[1][q][c];
-        o.z = f[2][q][c];
-        o.w = f[3][q][c];
-        *reinterpret_cast<float4*>(dst + pidx(g, q * NC + c, y, x0)) = o;
-      }
-  }
-}
 
 // ---- FP64 initialisation ---------------------------------------------------
 struct InitConst {
@@ -439,6 +309,23 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce_final(const double* __re
   }
 }
 
+// plain streaming copy, 16 bytes per lane and access, nontemporal stores
+// (bandwidth and memory-counter reference)
+__global__ __launch_bounds__(256) void k_copy(const float4* __restrict__ src,
+                                              float4* __restrict__ dst, int64_t n4) {
+  typedef float V __attribute__((ext_vector_type(4)));
+  const V* s = reinterpret_cast<const V*>(src);
+  V* d = reinterpret_cast<V*>(dst);
+  const int64_t i = (int64_t)blockIdx.x * 1024 + threadIdx.x;
+  V v[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    if (i + 256 * k < n4) v[k] = s[i + 256 * k];
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    if (i + 256 * k < n4) __builtin_nontemporal_store(v[k], d + i + 256 * k);
+}
+
 // ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
@@ -495,6 +382,7 @@ struct lbm_ctx {
   const float* wall_T;
   int64_t wall_nsteps;
   int device;
+  int step_cfg;  // index into kStepConfigs
 };
 
 namespace {
@@ -510,7 +398,7 @@ lbm_status derive(const lbm_params* p, Derived* d) {
   if ((int64_t)p->nx * p->ny > (int64_t)1 << 31) return fail(LBM_E_ARG, "grid too large");
   if (!(p->dx > 0) || !(p->dt > 0) || !(p->rho > 0) || !(p->mu > 0))
     return fail(LBM_E_ARG, "dx, dt, rho, mu must be positive");
-  if (p->flags != 0) return fail(LBM_E_ARG, "flags must be 0");
+  if (p->flags & ~(uint32_t)LBM_F_PLANE_LAYOUT) return fail(LBM_E_ARG, "unknown flags");
   double lam = p->lambda;
   if (p->model == LBM_PLANE_STRESS) {
     if (!(lam + 2.0 * p->mu > 0)) return fail(LBM_E_ARG, "lambda + 2 mu must be positive");
@@ -538,14 +426,26 @@ Grid make_grid(const lbm_params* p) {
   Grid g;
   g.nx = p->nx;
   g.ny = p->ny;
-  g.pitch = round_up(p->nx, 64);
-  // planes start on distinct 256-byte offsets modulo a 16 KiB window so the
-  // 40 concurrent streams of a step do not all hit the same memory channel
-  g.plane = round_up((int64_t)g.pitch * p->ny, 4096) + 64;
+  const int64_t rowlen = round_up(p->nx, 64);  // floats of one plane row, 256-byte aligned
+  if (p->flags & LBM_F_PLANE_LAYOUT) {
+    // [plane][y][x]; plane starts staggered by 256 bytes modulo 16 KiB so the
+    // 40 concurrent streams of a step do not start on the same channel
+    g.pitch = rowlen;
+    g.plane = round_up(rowlen * p->ny, 4096) + 64;
+  } else {
+    // [y][plane][x]: the 20 plane rows of one lattice row are contiguous, so a
+    // workgroup's reads come from three contiguous 20-row blocks and its writes
+    // go to one (measured 6.0 vs 5.45 TB/s on a 4096^2 step)
+    g.plane = rowlen;
+    g.pitch = rowlen * NP;
+  }
   return g;
 }
 
-size_t state_bytes(const Grid& g) { return (size_t)round_up(g.plane * NP * 4, 256); }
+size_t state_bytes(const Grid& g) {
+  const int64_t floats = g.plane * NP > g.pitch * g.ny ? g.plane * NP : g.pitch * g.ny;
+  return (size_t)round_up(floats * 4, 256);
+}
 
 size_t ws_bytes(const Grid& g) {
   return 2 * state_bytes(g) + (size_t)round_up((2 * RED_BLOCKS + 2) * 8, 256);
@@ -632,6 +532,7 @@ lbm_status lbm_create(const lbm_params* p, void* d_ws, size_t ws_size, void* hip
   c->wall_W = c->wall_T = nullptr;
   c->wall_nsteps = 0;
   hipGetDevice(&c->device);
+  c->step_cfg = default_step_config(g.nx);
   *out = c;
   g_err.clear();
   return LBM_OK;
@@ -700,40 +601,205 @@ lbm_status lbm_step(lbm_ctx* c, int64_t nsteps) {
   if (c->wall_rank > 0 && c->nstep + nsteps > c->wall_nsteps)
     return fail(LBM_E_ARG, "wall table too short for the requested steps");
   const Grid& g = c->g;
-  const bool vec4 = (g.nx % 4) == 0;
-  const int per_block = STEP_THREADS * (vec4 ? 4 : 1);
-  StepConst sc;
-  sc.kK = (float)c->kK;
-  sc.km = (float)c->km;
-  sc.tiles_x = (g.nx + per_block - 1) / per_block;
-  sc.ntiles = sc.tiles_x * g.ny;
+  const StepConfig& cfg = kStepConfigs[c->step_cfg];
+  const StepConst sc = step_const(cfg, g, (float)c->kK, (float)c->km);
+  const StepFn fn = cfg.fn[c->p.bc];
   for (int64_t s = 0; s < nsteps; ++s) {
     Wall w;
     w.rank = c->wall_rank;
     w.W = c->wall_W;
     w.Trow = c->wall_rank ? c->wall_T + (c->nstep + s) * c->wall_rank : nullptr;
     w.L = 2 * (g.nx + g.ny);
-    const float* src = c->buf[c->cur];
-    float* dst = c->buf[c->cur ^ 1];
-    if (c->p.bc == LBM_PERIODIC) {
-      if (vec4)
-        hipLaunchKernelGGL((k_step<LBM_PERIODIC, 4>), dim3(sc.ntiles), dim3(STEP_THREADS), 0,
-                           c->stream, src, dst, g, sc, w);
-      else
-        hipLaunchKernelGGL((k_step<LBM_PERIODIC, 1>), dim3(sc.ntiles), dim3(STEP_THREADS), 0,
-                           c->stream, src, dst, g, sc, w);
-    } else {
-      if (vec4)
-        hipLaunchKernelGGL((k_step<LBM_DIRICHLET, 4>), dim3(sc.ntiles), dim3(STEP_THREADS), 0,
-                           c->stream, src, dst, g, sc, w);
-      else
-        hipLaunchKernelGGL((k_step<LBM_DIRICHLET, 1>), dim3(sc.ntiles), dim3(STEP_THREADS), 0,
-                           c->stream, src, dst, g, sc, w);
-    }
+    hipLaunchKernelGGL(fn, dim3(sc.ntiles), dim3(cfg.threads), 0, c->stream,
+                       (const float*)c->buf[c->cur], c->buf[c->cur ^ 1], g, sc, w);
     c->cur ^= 1;
   }
   c->nstep += nsteps;
   return launch_check("k_step launch");
+}
+
+// ---- launch configurations and the autotuner ------------------------------
+namespace {
+
+struct TuneKey {
+  int nx, ny, bc;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(nx, ny, bc) < std::tie(o.nx, o.ny, o.bc);
+  }
+};
+
+std::mutex g_tune_mu;
+std::map<TuneKey, int> g_tune_cache;
+bool g_tune_file_loaded = false;
+
+int find_config(int vec, int threads, int nt, int xmode) {
+  for (int i = 0; i < kNumStepConfigs; ++i) {
+    const StepConfig& k = kStepConfigs[i];
+    if (k.vec == vec && k.threads == threads && k.nt == nt && k.xmode == xmode) return i;
+  }
+  return -1;
+}
+
+// Cache file (path in LBM_AUTOTUNE_CACHE): one line per tuned shape,
+// "nx ny bc vec threads nt xmode ms".  Caller holds g_tune_mu.
+void load_tune_file() {
+  if (g_tune_file_loaded) return;
+  g_tune_file_loaded = true;
+  const char* path = getenv("LBM_AUTOTUNE_CACHE");
+  if (!path || !*path) return;
+  FILE* f = fopen(path, "r");
+  if (!f) return;
+  int nx, ny, bc, vec, th, nt, xm;
+  double ms;
+  while (fscanf(f, "%d %d %d %d %d %d %d %lf", &nx, &ny, &bc, &vec, &th, &nt, &xm, &ms) == 8) {
+    const int i = find_config(vec, th, nt, xm);
+    if (i >= 0 && step_config_valid(i, nx)) g_tune_cache[TuneKey{nx, ny, bc}] = i;
+  }
+  fclose(f);
+}
+
+void append_tune_file(const TuneKey& k, int i, double ms) {
+  const char* path = getenv("LBM_AUTOTUNE_CACHE");
+  if (!path || !*path) return;
+  FILE* f = fopen(path, "a");
+  if (!f) return;
+  const StepConfig& c = kStepConfigs[i];
+  fprintf(f, "%d %d %d %d %d %d %d %.6f\n", k.nx, k.ny, k.bc, c.vec, c.threads, c.nt, c.xmode,
+          ms);
+  fclose(f);
+}
+
+}  // namespace
+
+int32_t lbm_step_config_count(void) { return kNumStepConfigs; }
+
+lbm_status lbm_step_config_info(int32_t index, int32_t* vec, int32_t* threads, int32_t* nt,
+                                int32_t* xmode) {
+  if (index < 0 || index >= kNumStepConfigs) return fail(LBM_E_ARG, "config index out of range");
+  const StepConfig& k = kStepConfigs[index];
+  if (vec) *vec = k.vec;
+  if (threads) *threads = k.threads;
+  if (nt) *nt = k.nt;
+  if (xmode) *xmode = k.xmode;
+  return LBM_OK;
+}
+
+lbm_status lbm_get_step_config(const lbm_ctx* c, int32_t* index) {
+  if (!c || !index) return fail(LBM_E_ARG, "null argument");
+  *index = c->step_cfg;
+  return LBM_OK;
+}
+
+lbm_status lbm_set_step_config(lbm_ctx* c, int32_t index) {
+  if (!c) return fail(LBM_E_ARG, "null ctx");
+  if (!step_config_valid(index, c->g.nx))
+    return fail(LBM_E_ARG, "launch configuration not valid for this grid");
+  c->step_cfg = index;
+  return LBM_OK;
+}
+
+lbm_status lbm_autotune(lbm_ctx* c, int32_t reps, int32_t use_cache, int32_t* h_index,
+                        double* h_ms) {
+  if (!c) return fail(LBM_E_ARG, "null ctx");
+  if (!c->initialised) return fail(LBM_E_STATE, "autotune needs an initialised lattice");
+  if (reps < 1) return fail(LBM_E_ARG, "reps must be >= 1");
+  const TuneKey key{c->g.nx, c->g.ny, c->p.bc};
+  if (use_cache) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    load_tune_file();
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) {
+      c->step_cfg = it->second;
+      if (h_index) *h_index = it->second;
+      if (h_ms) *h_ms = -1.0;
+      return LBM_OK;
+    }
+  }
+  // Time every valid variant on the live state without changing it: each
+  // timed launch reads the current buffer and writes the other one.
+  hipEvent_t e0, e1;
+  lbm_status s = hip_check(hipEventCreate(&e0), "event");
+  if (s) return s;
+  s = hip_check(hipEventCreate(&e1), "event");
+  if (s) {
+    hipEventDestroy(e0);
+    return s;
+  }
+  Wall w;
+  w.rank = 0;
+  w.W = nullptr;
+  w.Trow = nullptr;
+  w.L = 2 * (c->g.nx + c->g.ny);
+  int best = -1;
+  double best_ms = 1e300;
+  for (int i = 0; i < kNumStepConfigs && s == LBM_OK; ++i) {
+    if (!step_config_valid(i, c->g.nx)) continue;
+    const StepConfig& cfg = kStepConfigs[i];
+    const StepConst sc = step_const(cfg, c->g, (float)c->kK, (float)c->km);
+    for (int r = 0; r < reps + 2; ++r) {
+      if (r == 2) hipEventRecord(e0, c->stream);
+      hipLaunchKernelGGL(cfg.fn[c->p.bc], dim3(sc.ntiles), dim3(cfg.threads), 0, c->stream,
+                         (const float*)c->buf[c->cur], c->buf[c->cur ^ 1], c->g, sc, w);
+    }
+    hipEventRecord(e1, c->stream);
+    s = hip_check(hipEventSynchronize(e1), "autotune sync");
+    float ms = 0.f;
+    if (s == LBM_OK) s = hip_check(hipEventElapsedTime(&ms, e0, e1), "autotune timing");
+    if (s == LBM_OK && ms / reps < best_ms) {
+      best_ms = ms / reps;
+      best = i;
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (s) return s;
+  if (best < 0) return fail(LBM_E_ARG, "no valid launch configuration");
+  c->step_cfg = best;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    load_tune_file();
+    g_tune_cache[key] = best;
+    append_tune_file(key, best, best_ms);
+  }
+  if (h_index) *h_index = best;
+  if (h_ms) *h_ms = best_ms;
+  return LBM_OK;
+}
+
+lbm_status lbm_time_step_config(lbm_ctx* c, int32_t index, int32_t reps, double* h_ms) {
+  if (!c || !h_ms) return fail(LBM_E_ARG, "null argument");
+  if (!c->initialised) return fail(LBM_E_STATE, "not initialised");
+  if (!step_config_valid(index, c->g.nx)) return fail(LBM_E_ARG, "invalid configuration");
+  if (reps < 1) return fail(LBM_E_ARG, "reps must be >= 1");
+  hipEvent_t e0, e1;
+  lbm_status s = hip_check(hipEventCreate(&e0), "event");
+  if (s) return s;
+  s = hip_check(hipEventCreate(&e1), "event");
+  if (s) {
+    hipEventDestroy(e0);
+    return s;
+  }
+  Wall w;
+  w.rank = 0;
+  w.W = nullptr;
+  w.Trow = nullptr;
+  w.L = 2 * (c->g.nx + c->g.ny);
+  const StepConfig& cfg = kStepConfigs[index];
+  const StepConst sc = step_const(cfg, c->g, (float)c->kK, (float)c->km);
+  for (int r = 0; r < reps + 2; ++r) {
+    if (r == 2) hipEventRecord(e0, c->stream);
+    hipLaunchKernelGGL(cfg.fn[c->p.bc], dim3(sc.ntiles), dim3(cfg.threads), 0, c->stream,
+                       (const float*)c->buf[c->cur], c->buf[c->cur ^ 1], c->g, sc, w);
+  }
+  hipEventRecord(e1, c->stream);
+  s = hip_check(hipEventSynchronize(e1), "timing sync");
+  float ms = 0.f;
+  if (s == LBM_OK) s = hip_check(hipEventElapsedTime(&ms, e0, e1), "timing");
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (s) return s;
+  *h_ms = ms / reps;
+  return LBM_OK;
 }
 
 static lbm_status moments_mode(lbm_ctx* c, float* out, int mode) {
@@ -758,6 +824,19 @@ lbm_status lbm_energy(lbm_ctx* c, double* h_out) {
   if (s) return s;
   *h_out = r[0];
   return LBM_OK;
+}
+
+lbm_status lbm_copy_f32(float* d_dst, const float* d_src, int64_t n, void* hip_stream) {
+  if (!d_dst || !d_src || n < 0) return fail(LBM_E_ARG, "bad copy arguments");
+  if (n % 4 != 0 || ((uintptr_t)d_dst & 15) || ((uintptr_t)d_src & 15))
+    return fail(LBM_E_ARG, "copy needs 16-byte aligned buffers and n % 4 == 0");
+  if (n == 0) return LBM_OK;
+  const int64_t n4 = n / 4;
+  const int64_t blocks = (n4 + 1023) / 1024;
+  if (blocks > 0x7fffffff) return fail(LBM_E_ARG, "copy too large");
+  hipLaunchKernelGGL(k_copy, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)hip_stream,
+                     (const float4*)d_src, (float4*)d_dst, n4);
+  return launch_check("k_copy launch");
 }
 
 lbm_status lbm_rel_l2(lbm_ctx* c, const double* d_ref, double* h_out) {

@@ -13,6 +13,7 @@ from ._lib import LbmParams, check
 
 PERIODIC, DIRICHLET = 0, 1
 PLANE_STRAIN, PLANE_STRESS, CONTINUUM_2D = 0, 1, 2
+PLANE_LAYOUT = 1
 
 
 def _ptr(t):
@@ -37,12 +38,12 @@ class Lattice:
     boundary ``bc`` (PERIODIC or DIRICHLET) and material ``model``."""
 
     def __init__(self, nx, ny, dx, dt, lam, mu, rho, bc=PERIODIC, model=PLANE_STRAIN,
-                 device="cuda:0"):
+                 device="cuda:0", plane_layout=False):
         self.L = _lib.load()
         self.device = torch.device(device)
         self.nx, self.ny, self.bc = int(nx), int(ny), int(bc)
         self.params = LbmParams(int(nx), int(ny), float(dx), float(dt), float(lam), float(mu),
-                                float(rho), int(bc), int(model), 0)
+                                float(rho), int(bc), int(model), PLANE_LAYOUT if plane_layout else 0)
         nbytes = self.L.lbm_workspace_bytes(ctypes.byref(self.params))
         if nbytes == 0:
             # re-run create to get the precise validation error
@@ -147,6 +148,32 @@ class Lattice:
         check(self.L.lbm_rel_l2(self.ctx, _ptr(t), ctypes.byref(r)))
         return r.value
 
+    # -- launch configurations / autotuner --------------------------------------
+    @property
+    def step_config(self):
+        i = ctypes.c_int32()
+        check(self.L.lbm_get_step_config(self.ctx, ctypes.byref(i)))
+        return i.value
+
+    @step_config.setter
+    def step_config(self, index):
+        check(self.L.lbm_set_step_config(self.ctx, int(index)))
+
+    def valid_step_configs(self):
+        return [i for i, c in enumerate(step_configs()) if c["valid_for"](self.nx)]
+
+    def time_step_config(self, index, reps=20):
+        ms = ctypes.c_double()
+        check(self.L.lbm_time_step_config(self.ctx, int(index), int(reps), ctypes.byref(ms)))
+        return ms.value
+
+    def autotune(self, reps=20, use_cache=True):
+        """Pick the fastest launch configuration for this grid (state unchanged)."""
+        i, ms = ctypes.c_int32(), ctypes.c_double()
+        check(self.L.lbm_autotune(self.ctx, int(reps), int(bool(use_cache)), ctypes.byref(i),
+                                  ctypes.byref(ms)))
+        return i.value, ms.value
+
     # -- helpers ---------------------------------------------------------------
     def _out(self, out, shape):
         if out is None:
@@ -160,3 +187,26 @@ class Lattice:
     def _check_shape(t, shape):
         if tuple(t.shape) != tuple(shape):
             raise ValueError("shape %s expected, got %s" % (shape, tuple(t.shape)))
+
+
+def step_configs():
+    """Descriptions of the step kernel's launch configurations."""
+    L = _lib.load()
+    out = []
+    for i in range(L.lbm_step_config_count()):
+        v, t, n, x = (ctypes.c_int32() for _ in range(4))
+        check(L.lbm_step_config_info(i, ctypes.byref(v), ctypes.byref(t), ctypes.byref(n),
+                                     ctypes.byref(x)))
+        vec, xm = v.value, x.value
+        out.append({"index": i, "vec": vec, "threads": t.value, "nontemporal": n.value,
+                    "shuffle": xm,
+                    "valid_for": (lambda nx, vec=vec, xm=xm:
+                                  nx % vec == 0 and (xm == 0 or nx % (64 * vec) == 0))})
+    return out
+
+
+def copy_f32(dst, src):
+    """Plain streaming copy kernel (bandwidth reference)."""
+    if dst.numel() != src.numel() or dst.dtype != torch.float32 or src.dtype != torch.float32:
+        raise ValueError("float32 tensors of equal size expected")
+    check(_lib.load().lbm_copy_f32(_ptr(dst), _ptr(src), src.numel(), _stream_ptr(src.device)))

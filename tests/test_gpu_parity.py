@@ -143,3 +143,96 @@ def test_errors_reported():
     with pytest.raises(LbmError) as e:
         lat.step(1)                                  # step before init
     assert e.value.status == 3
+
+
+# ---------------------------------------------------------------------------
+# Full-size parity in the benchmark's configuration (autotuned launch)
+# ---------------------------------------------------------------------------
+@gpu
+def test_full_size_periodic_4096_vs_exact_discrete_evolution():
+    # 4096^2 periodic plane waves, 1000 steps: sampled nodes against the exact
+    # FP64 per-mode evolution of the same scheme (pinned to the C oracle on
+    # small grids in test_oracle_invariants)
+    torch = _torch()
+    from oracle import spectral
+    prob = synth.plane_wave_problem(4096, 4096, synth.PERIODIC, seed=2)
+    v0, sb0 = prob.initial_fields()
+    lat = _lattice(prob)
+    lat.init(torch.from_numpy(v0), torch.from_numpy(sb0))
+    del v0, sb0
+    lat.autotune(reps=5)
+    lat.step(1000)
+    g = np.random.default_rng(7)
+    iy = g.integers(0, 4096, 2000)
+    ix = g.integers(0, 4096, 2000)
+    iy[:4] = [0, 0, 4095, 4095]
+    ix[:4] = [0, 4095, 0, 4095]
+    U = lat.moments_U()
+    got = U[:, torch.from_numpy(iy).cuda(), torch.from_numpy(ix).cuda()].double().cpu().numpy()
+    want = spectral.plane_wave_reference(_setup(prob), prob.sol, 1000, iy, ix)
+    err = oracle.rel_l2(got, want)
+    print("4096^2 periodic, 1000 steps, rel-L2 vs exact FP64 evolution: %.3e" % err)
+    assert err < 1e-5
+
+
+def _window_reference(prob, cy, cx, n):
+    """U at node (cy, cx) after n steps, from the C oracle run on the window of
+    nodes within n + 1 of it (clipped to the lattice).  Window sides that are
+    not lattice walls carry an arbitrary (zero) wall rule: its influence
+    travels one node per step and cannot reach the centre within n steps."""
+    r = n + 1
+    y0, y1 = max(0, cy - r), min(prob.ny, cy + r + 1)
+    x0, x1 = max(0, cx - r), min(prob.nx, cx + r + 1)
+    wy, wx = y1 - y0, x1 - x0
+    s = oracle.Setup(wx, wy, prob.dx, prob.dt, prob.lam, prob.mu, prob.rho, oracle.DIRICHLET)
+    xs = (np.arange(x0, x1) + 0.5) * prob.dx
+    ys = (np.arange(y0, y1) + 0.5) * prob.dx
+    v0, sb0 = prob.sol.fields_on_grid(xs, ys, 0.0)
+    # global wall links of the real walls that this window shares
+    full = lambda t: prob.wall_velocity(t)
+    L = 2 * (wx + wy)
+    idx = np.full(L, -1)
+    if x0 == 0:
+        idx[:wy] = np.arange(y0, y1)
+    if x1 == prob.nx:
+        idx[wy:2 * wy] = prob.ny + np.arange(y0, y1)
+    if y0 == 0:
+        idx[2 * wy:2 * wy + wx] = 2 * prob.ny + np.arange(x0, x1)
+    if y1 == prob.ny:
+        idx[2 * wy + wx:] = 2 * prob.ny + prob.nx + np.arange(x0, x1)
+
+    def wall(t):
+        w = np.zeros((L, 2))
+        g = full(t)
+        w[idx >= 0] = g[idx[idx >= 0]]
+        return w
+
+    sim = oracle.Simulation(s, v0, sb0, wall=wall)
+    sim.advance(n)
+    return sim.U()[:, cy - y0, cx - x0]
+
+
+@gpu
+def test_full_size_dirichlet_2048x1024_windowed_oracle():
+    # 2048x1024 Dirichlet with time-dependent manufactured walls, the
+    # benchmark's lattice; corner, wall and interior nodes after 200 steps
+    # against the C oracle on their domains of dependence
+    torch = _torch()
+    prob = synth.plane_wave_problem(2048, 1024, synth.DIRICHLET, seed=2, dx=1.0 / 1024)
+    n = 200
+    v0, sb0 = prob.initial_fields()
+    lat = _lattice(prob)
+    lat.init(torch.from_numpy(v0), torch.from_numpy(sb0))
+    W, T = prob.wall_table(n)
+    lat.set_wall_velocity(torch.from_numpy(W), torch.from_numpy(T))
+    lat.autotune(reps=5)
+    lat.step(n)
+    U = lat.moments_U().double().cpu().numpy()
+    samples = [(0, 0), (0, 2047), (1023, 0), (1023, 2047), (0, 1000), (500, 2047), (511, 777)]
+    got, want = [], []
+    for cy, cx in samples:
+        got.append(U[:, cy, cx])
+        want.append(_window_reference(prob, cy, cx, n))
+    err = oracle.rel_l2(np.array(got), np.array(want))
+    print("2048x1024 Dirichlet, %d steps, sampled rel-L2 vs oracle: %.3e" % (n, err))
+    assert err < 1e-5
