@@ -182,6 +182,62 @@ lbm_status lbm_time_step_config(lbm_ctx* ctx, int32_t index, int32_t reps, doubl
  * the given stream: the bandwidth and memory-counter reference kernel. */
 lbm_status lbm_copy_f32(float* d_dst, const float* d_src, int64_t n, void* hip_stream);
 
+/* ---- batched lattices --------------------------------------------------------
+ * n independent instances, each with its own lbm_params (size, boundary,
+ * material, dx, dt; flags must be 0), advanced together: one launch per time
+ * step covers every row segment of every instance, with the same per-node
+ * arithmetic as lbm_step (results are bitwise identical to stepping each
+ * instance alone).  lbm_batch_step(n) executes the n launches as one hipGraph
+ * (built node by node and cached per step count while no instance has wall
+ * data).  The caller owns the workspace; the library never allocates device
+ * memory.
+ *
+ * Packed field arrays hold instance i's fields contiguously as
+ * [component][ny_i][nx_i], starting at (component count) x
+ * lbm_batch_node_offset(b, i); lbm_batch_node_offset(b, n) is the total number
+ * of nodes. */
+typedef struct lbm_batch lbm_batch;
+
+size_t lbm_batch_workspace_bytes(int32_t n, const lbm_params* h_params);
+lbm_status lbm_batch_create(int32_t n, const lbm_params* h_params, void* d_ws, size_t ws_bytes,
+                            void* hip_stream, lbm_batch** out);
+int64_t lbm_batch_node_offset(const lbm_batch* b, int32_t i);
+int64_t lbm_batch_step_count(const lbm_batch* b);
+
+/* FP64 second-order initialisation (Eq. ic_second, central-difference
+ * gradients) of every instance from packed physical fields:
+ * d_v0 [..][2][ny][nx], d_sigma0 [..][3][ny][nx] (Cauchy stress), FP64. */
+lbm_status lbm_batch_init(lbm_batch* b, const double* d_v0, const double* d_sigma0);
+
+/* Same, from one packed FP32 array [..][5][ny][nx] = (v_x, v_y, sigma_xx,
+ * sigma_yy, sigma_xy) per instance (the layout lbm_batch_moments writes);
+ * computed in FP64. */
+lbm_status lbm_batch_init_fields_f32(lbm_batch* b, const float* d_fields);
+
+/* Wall data of Dirichlet instance i, as lbm_set_wall_velocity. */
+lbm_status lbm_batch_set_wall_velocity(lbm_batch* b, int32_t i, int32_t rank, const float* d_W,
+                                       const float* d_T, int64_t nsteps);
+
+/* Advance every instance n steps: one hipGraph launch of n step kernels. */
+lbm_status lbm_batch_step(lbm_batch* b, int64_t n);
+
+/* Same steps launched one kernel at a time (no graph). */
+lbm_status lbm_batch_step_eager(lbm_batch* b, int64_t n);
+
+/* Packed FP32 moments: (v, sigma_bar) or the system variables U, [..][5][ny][nx]. */
+lbm_status lbm_batch_moments(lbm_batch* b, float* d_out);
+lbm_status lbm_batch_moments_U(lbm_batch* b, float* d_U);
+
+/* Per-instance ||f||_P^2 (FP64, fixed-order reduction) into h_out[n].  Synchronises. */
+lbm_status lbm_batch_energy(lbm_batch* b, double* h_out);
+
+/* Per-instance relative L2 difference between the current state and packed
+ * FP32 physical fields [..][5][ny][nx] (v, sigma_bar), measured on the system
+ * variables U: ||U - U(fields)|| / ||U|| (FP64) into h_out[n].  Synchronises. */
+lbm_status lbm_batch_rel_l2_fields(lbm_batch* b, const float* d_fields, double* h_out);
+
+lbm_status lbm_batch_destroy(lbm_batch* b);
+
 /* Release the host context (the workspace stays with the caller). */
 lbm_status lbm_destroy(lbm_ctx* ctx);
 

@@ -53,6 +53,21 @@ SIGNATURES = [
     ("lbm_autotune", ctypes.c_int, [_VP, _I32, _I32, ctypes.POINTER(_I32), _PD]),
     ("lbm_time_step_config", ctypes.c_int, [_VP, _I32, _I32, _PD]),
     ("lbm_copy_f32", ctypes.c_int, [_VP, _VP, _I64, _VP]),
+    ("lbm_batch_workspace_bytes", ctypes.c_size_t, [_I32, _VP]),
+    ("lbm_batch_create", ctypes.c_int, [_I32, _VP, _VP, ctypes.c_size_t, _VP,
+                                        ctypes.POINTER(_VP)]),
+    ("lbm_batch_node_offset", _I64, [_VP, _I32]),
+    ("lbm_batch_step_count", _I64, [_VP]),
+    ("lbm_batch_init", ctypes.c_int, [_VP, _VP, _VP]),
+    ("lbm_batch_init_fields_f32", ctypes.c_int, [_VP, _VP]),
+    ("lbm_batch_set_wall_velocity", ctypes.c_int, [_VP, _I32, _I32, _VP, _VP, _I64]),
+    ("lbm_batch_step", ctypes.c_int, [_VP, _I64]),
+    ("lbm_batch_step_eager", ctypes.c_int, [_VP, _I64]),
+    ("lbm_batch_moments", ctypes.c_int, [_VP, _VP]),
+    ("lbm_batch_moments_U", ctypes.c_int, [_VP, _VP]),
+    ("lbm_batch_energy", ctypes.c_int, [_VP, _PD]),
+    ("lbm_batch_rel_l2_fields", ctypes.c_int, [_VP, _VP, _PD]),
+    ("lbm_batch_destroy", ctypes.c_int, [_VP]),
     ("lbm_destroy", ctypes.c_int, [_VP]),
     ("lbm_last_error", ctypes.c_char_p, []),
 ]

@@ -25,103 +25,24 @@
 #include "lbm.h"
 #include "lbm_kernels.hpp"
 #include "lbm_step.hpp"
+#include "lbm_init.hpp"
+#include "lbm_host.hpp"
+
+thread_local std::string lbmh::g_err;
+using namespace lbmh;
 
 using namespace lbmk;
 
 namespace {
 
-thread_local std::string g_err;
-
-lbm_status fail(lbm_status s, const std::string& m) {
-  g_err = m;
-  return s;
-}
-
-lbm_status hip_check(hipError_t e, const char* what) {
-  if (e == hipSuccess) return LBM_OK;
-  return fail(LBM_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
-}
-
 constexpr int RED_BLOCKS = 1024;
 constexpr int RED_THREADS = 256;
 
-int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
+
 
 // ---------------------------------------------------------------------------
 // Device kernels
 // ---------------------------------------------------------------------------
-
-// ---- FP64 initialisation ---------------------------------------------------
-struct InitConst {
-  double kK, km, cK, cmu, rho, dx;
-  int bc;
-};
-
-// Phi_x(V)/c and Phi_y(V)/c in double precision
-__device__ inline void flux_x(const InitConst& k, const double V[NC], double o[NC]) {
-  o[0] = k.kK * V[2] + k.km * V[3];
-  o[1] = k.km * V[4];
-  o[2] = k.kK * V[0];
-  o[3] = k.km * V[0];
-  o[4] = k.km * V[1];
-}
-__device__ inline void flux_y(const InitConst& k, const double V[NC], double o[NC]) {
-  o[0] = k.km * V[4];
-  o[1] = k.kK * V[2] - k.km * V[3];
-  o[2] = k.kK * V[1];
-  o[3] = -k.km * V[1];
-  o[4] = k.km * V[0];
-}
-
-// U = (v, j) from velocity and Cauchy stress at a node (inverse of Eq. sigma_num)
-__device__ inline void to_U(const InitConst& k, double vx, double vy, double sxx, double syy,
-                            double sxy, double U[NC]) {
-  const double r = 1.0 / k.rho;
-  U[0] = vx;
-  U[1] = vy;
-  U[2] = -(sxx + syy) * r / (2.0 * k.cK);
-  U[3] = -(sxx - syy) * r / (2.0 * k.cmu);
-  U[4] = -sxy * r / k.cmu;
-}
-
-__device__ inline void node_U(const InitConst& k, const double* v0, const double* s0,
-                              int64_t n, int64_t id, double U[NC]) {
-  to_U(k, v0[id], v0[n + id], s0[id], s0[n + id], s0[2 * n + id], U);
-}
-
-// lattice derivative dx * dU/dx along one axis by central differences
-__device__ inline void lattice_grad(const InitConst& k, const double* v0, const double* s0,
-                                    int nx, int ny, int x, int y, int axis, double G[NC]) {
-  const int64_t n = (int64_t)nx * ny;
-  const int m = axis == 0 ? x : y, len = axis == 0 ? nx : ny;
-  auto id_of = [&](int mm) -> int64_t {
-    return axis == 0 ? (int64_t)y * nx + mm : (int64_t)mm * nx + x;
-  };
-  double A[NC], B[NC], C[NC];
-  if (len == 1) {
-    for (int c = 0; c < NC; ++c) G[c] = 0.0;
-    return;
-  }
-  if (k.bc == LBM_PERIODIC || (m > 0 && m < len - 1)) {
-    const int mp = m + 1 == len ? 0 : m + 1, mm = m == 0 ? len - 1 : m - 1;
-    node_U(k, v0, s0, n, id_of(mp), A);
-    node_U(k, v0, s0, n, id_of(mm), B);
-    for (int c = 0; c < NC; ++c) G[c] = 0.5 * (A[c] - B[c]);
-    return;
-  }
-  if (len == 2) {
-    node_U(k, v0, s0, n, id_of(1), A);
-    node_U(k, v0, s0, n, id_of(0), B);
-    for (int c = 0; c < NC; ++c) G[c] = A[c] - B[c];
-    return;
-  }
-  // one-sided second order at a wall
-  const int s = m == 0 ? 1 : -1;
-  node_U(k, v0, s0, n, id_of(m), A);
-  node_U(k, v0, s0, n, id_of(m + s), B);
-  node_U(k, v0, s0, n, id_of(m + 2 * s), C);
-  for (int c = 0; c < NC; ++c) G[c] = s * 0.5 * (-3.0 * A[c] + 4.0 * B[c] - C[c]);
-}
 
 __global__ __launch_bounds__(256) void k_init(const double* __restrict__ v0,
                                               const double* __restrict__ s0,
@@ -131,59 +52,7 @@ __global__ __launch_bounds__(256) void k_init(const double* __restrict__ v0,
   const int64_t n = (int64_t)g.nx * g.ny;
   if (id >= n) return;
   const int y = (int)(id / g.nx), x = (int)(id - (int64_t)y * g.nx);
-
-  double U[NC], UX[NC], UY[NC];
-  node_U(k, v0, s0, n, id, U);
-  if (grad) {
-    // physical derivatives of (v, sigma_bar) -> lattice derivatives of U
-    const double* gx = grad;
-    const double* gy = grad + 5 * n;
-    to_U(k, gx[id], gx[n + id], gx[2 * n + id], gx[3 * n + id], gx[4 * n + id], UX);
-    to_U(k, gy[id], gy[n + id], gy[2 * n + id], gy[3 * n + id], gy[4 * n + id], UY);
-    for (int c = 0; c < NC; ++c) {
-      UX[c] *= k.dx;
-      UY[c] *= k.dx;
-    }
-  } else {
-    lattice_grad(k, v0, s0, g.nx, g.ny, x, y, 0, UX);
-    lattice_grad(k, v0, s0, g.nx, g.ny, x, y, 1, UY);
-  }
-
-  // Eq. ic_second in lattice units (c dt = dx absorbed into UX, UY):
-  // f_q = 1/4 [U + 2 C_q U]
-  //   - 1/8 { i UX + (2i^2-1) X(UX) - 2 C_q X(UX) + j UY + (2j^2-1) Y(UY) - 2 C_q Y(UY) }
-  double XU[NC], YU[NC], XUX[NC], YUY[NC], XXUX[NC], YXUX[NC], XYUY[NC], YYUY[NC];
-  flux_x(k, U, XU);
-  flux_y(k, U, YU);
-  flux_x(k, UX, XUX);
-  flux_y(k, UY, YUY);
-  flux_x(k, XUX, XXUX);
-  flux_y(k, XUX, YXUX);
-  flux_x(k, YUY, XYUY);
-  flux_y(k, YUY, YYUY);
-  const int I[NQ] = {1, 0, -1, 0}, J[NQ] = {0, 1, 0, -1};
-  double f[NQ][NC];
-  for (int q = 0; q < NQ; ++q) {
-    const double i = I[q], j = J[q];
-    for (int c = 0; c < NC; ++c) {
-      const double eq = 0.25 * (U[c] + 2.0 * (i * XU[c] + j * YU[c]));
-      const double cx = i * UX[c] + (2.0 * i * i - 1.0) * XUX[c] - 2.0 * (i * XXUX[c] + j * YXUX[c]);
-      const double cy = j * UY[c] + (2.0 * j * j - 1.0) * YUY[c] - 2.0 * (i * XYUY[c] + j * YYUY[c]);
-      f[q][c] = eq - 0.125 * (cx + cy);
-    }
-  }
-  // first collision in FP64 (omega = 2): f* = 2 f_eq(U_num) - f, U_num = sum f
-  double Un[NC], Xn[NC], Yn[NC];
-  for (int c = 0; c < NC; ++c) Un[c] = (f[0][c] + f[1][c]) + (f[2][c] + f[3][c]);
-  flux_x(k, Un, Xn);
-  flux_y(k, Un, Yn);
-  for (int q = 0; q < NQ; ++q) {
-    const double i = I[q], j = J[q];
-    for (int c = 0; c < NC; ++c) {
-      const double fs = 0.5 * Un[c] + (i * Xn[c] + j * Yn[c]) - f[q][c];
-      dst[pidx(g, q * NC + c, y, x)] = (float)fs;
-    }
-  }
+  init_node<double>(v0, s0, grad, dst, g, k, x, y);
 }
 
 // load pre-collision FP32 populations [4][5][ny][nx] and collide (FP32)
@@ -330,39 +199,6 @@ __global__ __launch_bounds__(256) void k_copy(const float4* __restrict__ src,
 // Host side
 // ---------------------------------------------------------------------------
 
-// Inverse of a symmetric positive definite 5x5 matrix by Cholesky
-// factorisation; returns false if the matrix is not positive definite.
-bool spd_inverse5(const double A[NC][NC], double inv[NC][NC]) {
-  double Lm[NC][NC] = {};
-  for (int i = 0; i < NC; ++i)
-    for (int j = 0; j <= i; ++j) {
-      double s = A[i][j];
-      for (int k = 0; k < j; ++k) s -= Lm[i][k] * Lm[j][k];
-      if (i == j) {
-        if (s <= 0.0) return false;
-        Lm[i][i] = sqrt(s);
-      } else {
-        Lm[i][j] = s / Lm[j][j];
-      }
-    }
-  // solve A x = e_k column by column
-  for (int k = 0; k < NC; ++k) {
-    double z[NC], xk[NC];
-    for (int i = 0; i < NC; ++i) {
-      double s = (i == k) ? 1.0 : 0.0;
-      for (int j = 0; j < i; ++j) s -= Lm[i][j] * z[j];
-      z[i] = s / Lm[i][i];
-    }
-    for (int i = NC - 1; i >= 0; --i) {
-      double s = z[i];
-      for (int j = i + 1; j < NC; ++j) s -= Lm[j][i] * xk[j];
-      xk[i] = s / Lm[i][i];
-    }
-    for (int i = 0; i < NC; ++i) inv[i][k] = xk[i];
-  }
-  return true;
-}
-
 }  // namespace
 
 struct lbm_ctx {
@@ -387,71 +223,9 @@ struct lbm_ctx {
 
 namespace {
 
-struct Derived {
-  double cK, cmu, c, kK, km;
-};
-
-lbm_status derive(const lbm_params* p, Derived* d) {
-  if (!p) return fail(LBM_E_ARG, "null params");
-  if (p->nx < 1 || p->ny < 1) return fail(LBM_E_ARG, "nx, ny must be >= 1");
-  if (p->bc != LBM_PERIODIC && p->bc != LBM_DIRICHLET) return fail(LBM_E_ARG, "bad bc");
-  if ((int64_t)p->nx * p->ny > (int64_t)1 << 31) return fail(LBM_E_ARG, "grid too large");
-  if (!(p->dx > 0) || !(p->dt > 0) || !(p->rho > 0) || !(p->mu > 0))
-    return fail(LBM_E_ARG, "dx, dt, rho, mu must be positive");
-  if (p->flags & ~(uint32_t)LBM_F_PLANE_LAYOUT) return fail(LBM_E_ARG, "unknown flags");
-  double lam = p->lambda;
-  if (p->model == LBM_PLANE_STRESS) {
-    if (!(lam + 2.0 * p->mu > 0)) return fail(LBM_E_ARG, "lambda + 2 mu must be positive");
-    lam = 2.0 * lam * p->mu / (lam + 2.0 * p->mu);
-  } else if (p->model != LBM_PLANE_STRAIN && p->model != LBM_CONTINUUM_2D) {
-    return fail(LBM_E_ARG, "bad model");
-  }
-  const double cK2 = (lam + p->mu) / p->rho;
-  if (!(cK2 > 0)) return fail(LBM_E_ARG, "lambda + mu must be positive");
-  d->cK = sqrt(cK2);
-  d->cmu = sqrt(p->mu / p->rho);
-  d->c = p->dx / p->dt;
-  d->kK = d->cK / d->c;
-  d->km = d->cmu / d->c;
-  const double ratio = 2.0 * sqrt(d->kK * d->kK + d->km * d->km);
-  if (!(ratio < 1.0)) {
-    char b[160];
-    snprintf(b, sizeof b, "CFL-like condition violated: 2 sqrt(cK^2+cmu^2)/c = %.6f >= 1", ratio);
-    return fail(LBM_E_CFL, b);
-  }
-  return LBM_OK;
-}
-
-Grid make_grid(const lbm_params* p) {
-  Grid g;
-  g.nx = p->nx;
-  g.ny = p->ny;
-  const int64_t rowlen = round_up(p->nx, 64);  // floats of one plane row, 256-byte aligned
-  if (p->flags & LBM_F_PLANE_LAYOUT) {
-    // [plane][y][x]; plane starts staggered by 256 bytes modulo 16 KiB so the
-    // 40 concurrent streams of a step do not start on the same channel
-    g.pitch = rowlen;
-    g.plane = round_up(rowlen * p->ny, 4096) + 64;
-  } else {
-    // [y][plane][x]: the 20 plane rows of one lattice row are contiguous, so a
-    // workgroup's reads come from three contiguous 20-row blocks and its writes
-    // go to one (measured 6.0 vs 5.45 TB/s on a 4096^2 step)
-    g.plane = rowlen;
-    g.pitch = rowlen * NP;
-  }
-  return g;
-}
-
-size_t state_bytes(const Grid& g) {
-  const int64_t floats = g.plane * NP > g.pitch * g.ny ? g.plane * NP : g.pitch * g.ny;
-  return (size_t)round_up(floats * 4, 256);
-}
-
 size_t ws_bytes(const Grid& g) {
   return 2 * state_bytes(g) + (size_t)round_up((2 * RED_BLOCKS + 2) * 8, 256);
 }
-
-lbm_status launch_check(const char* what) { return hip_check(hipGetLastError(), what); }
 
 lbm_status reduce(lbm_ctx* c, int mode, const double* ref, double out[2]) {
   const int64_t n = (int64_t)c->g.nx * c->g.ny;
@@ -496,21 +270,7 @@ lbm_status lbm_create(const lbm_params* p, void* d_ws, size_t ws_size, void* hip
   const Grid g = make_grid(p);
   if (ws_size < ws_bytes(g)) return fail(LBM_E_SPACE, "workspace too small");
   NormConst nc;
-  for (int q = 0; q < NQ; ++q) {
-    // g_q = 1/4 I + (1/2)(i A_x + j A_y)/c  (Eq. stability_linear), inverted
-    const int I[NQ] = {1, 0, -1, 0}, J[NQ] = {0, 1, 0, -1};
-    double Ax[NC][NC] = {}, Ay[NC][NC] = {}, gq[NC][NC];
-    Ax[0][2] = Ax[2][0] = d.kK;
-    Ax[0][3] = Ax[3][0] = d.km;
-    Ax[1][4] = Ax[4][1] = d.km;
-    Ay[0][4] = Ay[4][0] = d.km;
-    Ay[1][2] = Ay[2][1] = d.kK;
-    Ay[1][3] = Ay[3][1] = -d.km;
-    for (int r = 0; r < NC; ++r)
-      for (int c = 0; c < NC; ++c)
-        gq[r][c] = (r == c ? 0.25 : 0.0) + 0.5 * (I[q] * Ax[r][c] + J[q] * Ay[r][c]);
-    if (!spd_inverse5(gq, nc.k[q])) return fail(LBM_E_CFL, "g_ij not positive definite");
-  }
+  if (!norm_weights(d.kK, d.km, nc.k)) return fail(LBM_E_CFL, "g_ij not positive definite");
   lbm_ctx* c = new (std::nothrow) lbm_ctx();
   if (!c) return fail(LBM_E_ARG, "out of host memory");
   c->p = *p;

@@ -84,13 +84,15 @@ __device__ inline void vstore(float* p, const float in[VEC]) {
     *reinterpret_cast<T*>(p) = v;
 }
 
+// One row segment (row y, segment tx) of one lattice: the body shared by the
+// single-lattice and the batched step kernels.
 template <int BC, int VEC, int THREADS, int NT, int XMODE>
-__global__ __launch_bounds__(THREADS) void k_step(const float* __restrict__ src,
-                                                  float* __restrict__ dst, Grid g, StepConst sc,
-                                                  Wall w) {
-  const int tile = xcd_tile(blockIdx.x, sc.ntiles);
-  const int y = tile / sc.tiles_x;
-  const int tx = tile - y * sc.tiles_x;
+__device__ inline void step_segment(const float* __restrict__ src, float* __restrict__ dst,
+                                    const Grid& g, float kK, float km, const Wall& w, int y,
+                                    int tx) {
+  StepConst sc;
+  sc.kK = kK;
+  sc.km = km;
   const int x0 = (tx * THREADS + (int)threadIdx.x) * VEC;
   const int nx = g.nx, ny = g.ny;
   if (x0 >= nx) return;  // XMODE 1: nx % (64 VEC) == 0, so whole waves exit together
@@ -188,6 +190,16 @@ __global__ __launch_bounds__(THREADS) void k_step(const float* __restrict__ src,
       for (int k = 0; k < VEC; ++k) o[k] = f[k][q][c];
       vstore<VEC, NT>(dst + pidx(g, q * NC + c, y, x0), o);
     }
+}
+
+template <int BC, int VEC, int THREADS, int NT, int XMODE>
+__global__ __launch_bounds__(THREADS) void k_step(const float* __restrict__ src,
+                                                  float* __restrict__ dst, Grid g, StepConst sc,
+                                                  Wall w) {
+  const int tile = xcd_tile(blockIdx.x, sc.ntiles);
+  const int y = tile / sc.tiles_x;
+  const int tx = tile - y * sc.tiles_x;
+  step_segment<BC, VEC, THREADS, NT, XMODE>(src, dst, g, sc.kK, sc.km, w, y, tx);
 }
 
 // ---------------------------------------------------------------------------

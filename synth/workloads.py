@@ -169,12 +169,13 @@ def gaussian_random_field(g: np.random.Generator, ny: int, nx: int, ell: float,
     """Periodic Gaussian random fields: white noise convolved with a periodic
     Gaussian of standard deviation ell/sqrt(2) cells (covariance length ell),
     normalised to zero mean and unit sample variance.  Shape [nfields][ny][nx]."""
+    import scipy.fft as sfft
     noise = g.standard_normal((nfields, ny, nx))
     s = ell / math.sqrt(2.0)
-    kx = 2 * math.pi * np.fft.fftfreq(nx)
+    kx = 2 * math.pi * np.fft.rfftfreq(nx)
     ky = 2 * math.pi * np.fft.fftfreq(ny)
     filt = np.exp(-0.5 * s * s * (ky[:, None] ** 2 + kx[None, :] ** 2))
-    f = np.real(np.fft.ifft2(np.fft.fft2(noise) * filt))
+    f = sfft.irfft2(sfft.rfft2(noise, workers=-1) * filt, s=(ny, nx), workers=-1)
     f -= f.mean(axis=(1, 2), keepdims=True)
     f /= f.std(axis=(1, 2), keepdims=True)
     return f
@@ -221,3 +222,23 @@ def random_populations(seed: int, nx: int, ny: int) -> np.ndarray:
     """Seeded standard-normal population array [4][5][ny][nx] (for invariant
     and parity tests that start from an arbitrary lattice state)."""
     return rng(seed).standard_normal((4, 5, ny, nx))
+
+
+def batched_instances(n: int, seed: int, side=(64, 512), rho_range=(0.5, 2.0), cfl=0.5,
+                      dirichlet_fraction=0.5):
+    """Seeded batch of GRF problems: side lengths uniform in [side], non-square,
+    the first round(n * dirichlet_fraction) of a seeded permutation Dirichlet,
+    Poisson ratio U[0, 0.49], mu = 1, rho uniform in rho_range, time step at
+    ``cfl`` of the CFL-like limit, GRF length scale U[8, 32] cells."""
+    g = rng(seed)
+    order = g.permutation(n)
+    nd = int(round(n * dirichlet_fraction))
+    bcs = np.zeros(n, dtype=int)
+    bcs[order[:nd]] = DIRICHLET
+    probs = []
+    for i in range(n):
+        nx = int(g.integers(side[0], side[1] + 1))
+        ny = int(g.integers(side[0], side[1] + 1))
+        probs.append(grf_problem(nx, ny, int(bcs[i]), seed=seed * 100003 + i,
+                                 rho_range=rho_range, cfl=cfl))
+    return probs
