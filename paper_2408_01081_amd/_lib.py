@@ -68,6 +68,15 @@ SIGNATURES = [
     ("lbm_batch_energy", ctypes.c_int, [_VP, _PD]),
     ("lbm_batch_rel_l2_fields", ctypes.c_int, [_VP, _VP, _PD]),
     ("lbm_batch_destroy", ctypes.c_int, [_VP]),
+    ("sg_workspace_bytes", ctypes.c_size_t, [_VP]),
+    ("sg_param_count", _I64, []),
+    ("sg_create", ctypes.c_int, [_VP, _VP, ctypes.c_size_t, _VP, ctypes.POINTER(_VP)]),
+    ("sg_destroy", ctypes.c_int, [_VP]),
+    ("sg_set_params", ctypes.c_int, [_VP, _VP]),
+    ("sg_get_params", ctypes.c_int, [_VP, _VP]),
+    ("sg_get_grads", ctypes.c_int, [_VP, _VP]),
+    ("sg_forward", ctypes.c_int, [_VP, _VP, _I32, _I32, _VP]),
+    ("sg_train_step", ctypes.c_int, [_VP, _VP, _VP, _I32, _I32, ctypes.c_float, _PD]),
     ("lbm_destroy", ctypes.c_int, [_VP]),
     ("lbm_last_error", ctypes.c_char_p, []),
 ]

@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 INCLUDE = os.path.join(ROOT, "include")
 CSRC = os.path.join(HERE, "csrc")
 LIBNAME = "liblbm_hip.so"
-SOURCES = ["lbm.hip", "lbm_batch.hip"]
+SOURCES = ["lbm.hip", "lbm_batch.hip", "sg.hip"]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [

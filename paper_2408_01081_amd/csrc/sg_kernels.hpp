@@ -1,0 +1,341 @@
+// Kernels of the learned window surrogate: a linear U-Net on the first-order
+// system's variables with FiLM gains, 3x3 convolutions as implicit GEMMs on
+// gfx950 BF16 matrix cores (v_mfma_f32_16x16x32_bf16, FP32 accumulation).
+//
+// Activations are FP32 NHWC ([batch][y][x][channel]).  A convolution operand
+// is rounded to BF16 when it is fed to the matrix core; with SPLIT = 3 each
+// FP32 operand x is carried as hi = bf16(x), lo = bf16(x - hi) and the product
+// is hi*hi + lo*hi + hi*lo (about 16 significant bits instead of 8).
+//
+// Every stored conv output z is pre-FiLM; a consumer multiplies it by the
+// layer's gain gamma[b][c] when it loads it ("scale on load"), which is also
+// exactly what the backward pass needs (dL/dz = gamma * dL/dy).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sgk {
+
+typedef __bf16 bf16;
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// round-to-nearest-even FP32 -> BF16 (finite inputs)
+__device__ __host__ inline unsigned short bf16_bits(float x) {
+  uint32_t u;
+  __builtin_memcpy(&u, &x, 4);
+  u = (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
+  return (unsigned short)u;
+}
+__device__ __host__ inline float bf16_value(unsigned short b) {
+  const uint32_t u = (uint32_t)b << 16;
+  float f;
+  __builtin_memcpy(&f, &u, 4);
+  return f;
+}
+__device__ inline bf16 as_bf16(unsigned short b) {
+  bf16 r;
+  __builtin_memcpy(&r, &b, 2);
+  return r;
+}
+
+// ---------------------------------------------------------------------------
+// 3x3 convolution, implicit GEMM.  Z[b,y,x,o] = sum_{t,i} Wt[t][o][i] * s[b,i] * X[b,y+dy,x+dx,i]
+// Operand layouts of v_mfma_f32_16x16x32_bf16 (checked on gfx950 by an
+// in-bounds probe): lane l holds A[l%16][8(l/16)+j], B[8(l/16)+j][l%16] for
+// j = 0..7, and D[4(l/16)+j][l%16] for j = 0..3.
+// One wave computes 16 pixels (one row piece, W % 16 == 0) x 16*NB output
+// channels; a workgroup is 4 waves (64 pixels).  Cin % 32 == 0.
+// Used for the forward pass (Wt = [9][Cout][Cin]) and, with the flipped and
+// transposed weights, for the data gradient.
+// ---------------------------------------------------------------------------
+template <int SPLIT, int NB>
+__global__ __launch_bounds__(256) void k_conv(const float* __restrict__ X,
+                                              const float* __restrict__ xscale,
+                                              const unsigned short* __restrict__ Whi,
+                                              const unsigned short* __restrict__ Wlo,
+                                              float* __restrict__ Z, int H, int W, int Cin,
+                                              int Cout, int circular, int accumulate) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t pix0 = (int64_t)blockIdx.x * 64 + wave * 16;
+  const int64_t HW = (int64_t)H * W;
+  const int b = (int)(pix0 / HW);
+  const int rem = (int)(pix0 - (int64_t)b * HW);
+  const int y = rem / W, x0 = rem - y * W;
+  const int m = lane & 15, kq = lane >> 4;
+  const int co0 = blockIdx.y * 16 * NB;
+  f32x4 acc[NB];
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) acc[nb] = (f32x4){0.f, 0.f, 0.f, 0.f};
+  const float* sc = xscale ? xscale + (int64_t)b * Cin : nullptr;
+
+  for (int t = 0; t < 9; ++t) {
+    const int dy = t / 3 - 1, dx = t % 3 - 1;
+    int ys = y + dy, xs = x0 + m + dx;
+    bool valid = true;
+    if (circular) {
+      ys = ys < 0 ? ys + H : (ys >= H ? ys - H : ys);
+      xs = xs < 0 ? xs + W : (xs >= W ? xs - W : xs);
+    } else {
+      valid = ys >= 0 && ys < H && xs >= 0 && xs < W;
+      ys = ys < 0 ? 0 : (ys >= H ? H - 1 : ys);
+      xs = xs < 0 ? 0 : (xs >= W ? W - 1 : xs);
+    }
+    const float* xp = X + (((int64_t)b * H + ys) * W + xs) * Cin + 8 * kq;
+    const int64_t wrow = ((int64_t)t * Cout + co0 + m) * Cin + 8 * kq;
+    for (int c0 = 0; c0 < Cin; c0 += 32) {
+      float a[8];
+      const float4 v0 = *reinterpret_cast<const float4*>(xp + c0);
+      const float4 v1 = *reinterpret_cast<const float4*>(xp + c0 + 4);
+      a[0] = v0.x; a[1] = v0.y; a[2] = v0.z; a[3] = v0.w;
+      a[4] = v1.x; a[5] = v1.y; a[6] = v1.z; a[7] = v1.w;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        a[j] = valid ? a[j] : 0.f;
+        if (sc) a[j] *= sc[c0 + 8 * kq + j];
+      }
+      bf16x8 ahi, alo;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const unsigned short h = bf16_bits(a[j]);
+        ahi[j] = as_bf16(h);
+        alo[j] = as_bf16(bf16_bits(a[j] - bf16_value(h)));
+      }
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const int64_t wo = wrow + (int64_t)(16 * nb) * Cin + c0;
+        const bf16x8 bhi = *reinterpret_cast<const bf16x8*>(Whi + wo);
+        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, bhi, acc[nb], 0, 0, 0);
+        if (SPLIT == 3) {
+          const bf16x8 blo = *reinterpret_cast<const bf16x8*>(Wlo + wo);
+          acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo, bhi, acc[nb], 0, 0, 0);
+          acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, blo, acc[nb], 0, 0, 0);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      float* zp = Z + (pix0 + 4 * kq + j) * Cout + co0 + 16 * nb + m;
+      *zp = accumulate ? *zp + acc[nb][j] : acc[nb][j];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Weight gradient.  dW[t][o][i] = sum_{b,p} G[b,p,o] * s_o[b,o] * X[b,p+off_t,i] * s_i[b,i]
+// As a GEMM: D (16 o x 16 i) += A (16 o x 32 pixels) B (32 pixels x 16 i).
+// grid: x = tap (9) * (Cout/16) * (Cin/(16 NI)), y = pixel split; each of the
+// 4 waves takes every 4th chunk of 32 pixels of the split, the waves' sums are
+// added in LDS in a fixed order and written to partial[split][t][o][i].
+// ---------------------------------------------------------------------------
+template <int SPLIT, int NI>
+__global__ __launch_bounds__(256) void k_wgrad(const float* __restrict__ G,
+                                               const float* __restrict__ gscale,
+                                               const float* __restrict__ X,
+                                               const float* __restrict__ xscale,
+                                               float* __restrict__ partial, int B, int H, int W,
+                                               int Cin, int Cout, int circular,
+                                               int64_t pix_per_split) {
+  __shared__ float red[4][16 * NI][16 + 1];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int m = lane & 15, kq = lane >> 4;
+  const int nib = Cin / (16 * NI), nob = Cout / 16;
+  int id = blockIdx.x;
+  const int t = id / (nob * nib);
+  id -= t * nob * nib;
+  const int ob = id / nib, ib = id - ob * nib;
+  const int dy = t / 3 - 1, dx = t % 3 - 1;
+  const int o = ob * 16 + m;  // A row for this lane
+  const int64_t HW = (int64_t)H * W;
+  const int64_t p_begin = (int64_t)blockIdx.y * pix_per_split;
+  f32x4 acc[NI];
+#pragma unroll
+  for (int k = 0; k < NI; ++k) acc[k] = (f32x4){0.f, 0.f, 0.f, 0.f};
+  for (int64_t pc = p_begin + 32 * wave; pc < p_begin + pix_per_split; pc += 128) {
+    float a[8], xv[NI][8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int64_t p = pc + 8 * kq + j;
+      const int b = (int)(p / HW);
+      const int r = (int)(p - (int64_t)b * HW);
+      const int yy = r / W, xx = r - yy * W;
+      a[j] = G[p * Cout + o] * (gscale ? gscale[(int64_t)b * Cout + o] : 1.f);
+      int ys = yy + dy, xs = xx + dx;
+      bool valid = true;
+      if (circular) {
+        ys = ys < 0 ? ys + H : (ys >= H ? ys - H : ys);
+        xs = xs < 0 ? xs + W : (xs >= W ? xs - W : xs);
+      } else {
+        valid = ys >= 0 && ys < H && xs >= 0 && xs < W;
+        ys = ys < 0 ? 0 : (ys >= H ? H - 1 : ys);
+        xs = xs < 0 ? 0 : (xs >= W ? W - 1 : xs);
+      }
+      const float* xp = X + (((int64_t)b * H + ys) * W + xs) * Cin;
+#pragma unroll
+      for (int k = 0; k < NI; ++k) {
+        const int i = (ib * NI + k) * 16 + m;
+        float v = valid ? xp[i] : 0.f;
+        if (xscale) v *= xscale[(int64_t)b * Cin + i];
+        xv[k][j] = v;
+      }
+    }
+    bf16x8 ahi, alo;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const unsigned short h = bf16_bits(a[j]);
+      ahi[j] = as_bf16(h);
+      alo[j] = as_bf16(bf16_bits(a[j] - bf16_value(h)));
+    }
+#pragma unroll
+    for (int k = 0; k < NI; ++k) {
+      bf16x8 bhi, blo;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const unsigned short h = bf16_bits(xv[k][j]);
+        bhi[j] = as_bf16(h);
+        blo[j] = as_bf16(bf16_bits(xv[k][j] - bf16_value(h)));
+      }
+      acc[k] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, bhi, acc[k], 0, 0, 0);
+      if (SPLIT == 3) {
+        acc[k] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo, bhi, acc[k], 0, 0, 0);
+        acc[k] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, blo, acc[k], 0, 0, 0);
+      }
+    }
+  }
+  // D[row = o (4kq + j)][col = i (m)]
+#pragma unroll
+  for (int k = 0; k < NI; ++k)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) red[wave][16 * k + m][4 * kq + j] = acc[k][j];
+  __syncthreads();
+  for (int e = threadIdx.x; e < 16 * 16 * NI; e += 256) {
+    const int ii = e % (16 * NI), oo = e / (16 * NI);
+    const float s = ((red[0][ii][oo] + red[1][ii][oo]) + red[2][ii][oo]) + red[3][ii][oo];
+    const int i = ib * NI * 16 + ii, oabs = ob * 16 + oo;
+    partial[(((int64_t)blockIdx.y * 9 + t) * Cout + oabs) * Cin + i] = s;
+  }
+}
+
+// sum the pixel splits in a fixed order: grad[o][i][t] (master layout)
+__global__ __launch_bounds__(256) void k_wgrad_reduce(const float* __restrict__ partial,
+                                                      int nsplit, int Cin, int Cout,
+                                                      float* __restrict__ grad) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t n = (int64_t)9 * Cout * Cin;
+  if (e >= n) return;
+  const int t = (int)(e / ((int64_t)Cout * Cin));
+  const int64_t oi = e - (int64_t)t * Cout * Cin;
+  const int o = (int)(oi / Cin), i = (int)(oi - (int64_t)o * Cin);
+  float s = 0.f;
+  for (int k = 0; k < nsplit; ++k) s += partial[(int64_t)k * n + e];
+  grad[((int64_t)o * Cin + i) * 9 + t] = s;
+}
+
+// master weights [o][i][3][3] FP32 -> BF16 hi/lo in [t][o][i] (forward) and
+// flipped/transposed [t][i][o] (data gradient)
+__global__ __launch_bounds__(256) void k_prep_weights(const float* __restrict__ w, int Cin,
+                                                      int Cout, unsigned short* __restrict__ fhi,
+                                                      unsigned short* __restrict__ flo,
+                                                      unsigned short* __restrict__ bhi,
+                                                      unsigned short* __restrict__ blo) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t n = (int64_t)9 * Cout * Cin;
+  if (e >= n) return;
+  const int o = (int)(e / (9 * Cin));
+  const int r = (int)(e - (int64_t)o * 9 * Cin);
+  const int i = r / 9, t = r - i * 9;
+  const float v = w[e];
+  const unsigned short h = bf16_bits(v);
+  const unsigned short l = bf16_bits(v - bf16_value(h));
+  fhi[((int64_t)t * Cout + o) * Cin + i] = h;
+  flo[((int64_t)t * Cout + o) * Cin + i] = l;
+  const int tb = 8 - t;
+  bhi[((int64_t)tb * Cin + i) * Cout + o] = h;
+  blo[((int64_t)tb * Cin + i) * Cout + o] = l;
+}
+
+// ---------------------------------------------------------------------------
+// pooling / up-sampling (NHWC, scale on load)
+// ---------------------------------------------------------------------------
+// out[b,Y,X,c] = 1/4 sum_{2x2} s[b,c] in[b,2Y+u,2X+v,c]
+__global__ __launch_bounds__(256) void k_pool(const float* __restrict__ in,
+                                              const float* __restrict__ scale,
+                                              float* __restrict__ out, int B, int Ho, int Wo,
+                                              int C) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t n = (int64_t)B * Ho * Wo * C;
+  if (e >= n) return;
+  const int c = (int)(e % C);
+  int64_t r = e / C;
+  const int X = (int)(r % Wo);
+  r /= Wo;
+  const int Y = (int)(r % Ho);
+  const int b = (int)(r / Ho);
+  const int Wi = 2 * Wo;
+  const float* p = in + (((int64_t)b * 2 * Ho + 2 * Y) * Wi + 2 * X) * C + c;
+  const float s = scale ? scale[(int64_t)b * C + c] : 1.f;
+  out[e] = 0.25f * s * ((p[0] + p[C]) + (p[(int64_t)Wi * C] + p[(int64_t)Wi * C + C]));
+}
+
+// out[b,y,x,c] = sc[b,c] coarse[b,y/2,x/2,c] + ss[b,c] skip[b,y,x,c]
+__global__ __launch_bounds__(256) void k_upadd(const float* __restrict__ coarse,
+                                               const float* __restrict__ sc,
+                                               const float* __restrict__ skip,
+                                               const float* __restrict__ ss,
+                                               float* __restrict__ out, int B, int H, int W,
+                                               int C) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t n = (int64_t)B * H * W * C;
+  if (e >= n) return;
+  const int c = (int)(e % C);
+  int64_t r = e / C;
+  const int x = (int)(r % W);
+  r /= W;
+  const int y = (int)(r % H);
+  const int b = (int)(r / H);
+  const float cv = coarse[(((int64_t)b * (H / 2) + y / 2) * (W / 2) + x / 2) * C + c];
+  const float a = (sc ? sc[(int64_t)b * C + c] : 1.f) * cv;
+  out[e] = a + (ss ? ss[(int64_t)b * C + c] : 1.f) * skip[e];
+}
+
+// backward of pooling, plus an optional addend:
+// out[b,y,x,c] = 1/4 g[b,y/2,x/2,c] + (add ? add[b,y,x,c] : 0)
+__global__ __launch_bounds__(256) void k_pool_back(const float* __restrict__ g,
+                                                   const float* __restrict__ add,
+                                                   float* __restrict__ out, int B, int H, int W,
+                                                   int C) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t n = (int64_t)B * H * W * C;
+  if (e >= n) return;
+  const int c = (int)(e % C);
+  int64_t r = e / C;
+  const int x = (int)(r % W);
+  r /= W;
+  const int y = (int)(r % H);
+  const int b = (int)(r / H);
+  const float v = 0.25f * g[(((int64_t)b * (H / 2) + y / 2) * (W / 2) + x / 2) * C + c];
+  out[e] = add ? v + add[e] : v;
+}
+
+// backward of nearest up-sampling: out[b,Y,X,c] = sum_{2x2} g[b,2Y+u,2X+v,c]
+__global__ __launch_bounds__(256) void k_up_back(const float* __restrict__ g,
+                                                 float* __restrict__ out, int B, int Ho, int Wo,
+                                                 int C) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t n = (int64_t)B * Ho * Wo * C;
+  if (e >= n) return;
+  const int c = (int)(e % C);
+  int64_t r = e / C;
+  const int X = (int)(r % Wo);
+  r /= Wo;
+  const int Y = (int)(r % Ho);
+  const int b = (int)(r / Ho);
+  const int Wi = 2 * Wo;
+  const float* p = g + (((int64_t)b * 2 * Ho + 2 * Y) * Wi + 2 * X) * C + c;
+  out[e] = (p[0] + p[C]) + (p[(int64_t)Wi * C] + p[(int64_t)Wi * C + C]);
+}
+
+}  // namespace sgk

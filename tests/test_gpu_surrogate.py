@@ -1,0 +1,126 @@
+"""Surrogate kernels (forward, loss gradient, Adam) against the FP64 CPU
+reference in oracle/surrogate_ref.py on the same seeded inputs and
+parameters.
+
+Tolerances: with hi/lo BF16 operands (split 3) the products carry ~16
+significant bits and accumulate in FP32, so outputs agree to ~1e-5 relative
+and gradients to ~1e-4; with plain BF16 operands (split 1) each operand is
+rounded to 8 bits (relative 2^-9 = 2e-3 per rounding)."""
+import numpy as np
+import pytest
+
+from oracle import surrogate_ref as R
+
+gpu = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _inputs(seed, B, H, W):
+    g = np.random.default_rng(seed)
+    import synth
+    inp = np.zeros((B, 8, H, W))
+    for b in range(B):
+        f = synth.gaussian_random_field(g, H, W, float(g.uniform(6, 16)), 5)
+        inp[b, :5] = f
+        nu = g.uniform(0, 0.49)
+        inp[b, 5] = 2 * nu / (1 - 2 * nu)
+        inp[b, 6] = 1.0
+        inp[b, 7] = g.uniform(0.5, 2.0)
+    tgt = inp[:, :5] + 0.05 * g.standard_normal((B, 5, H, W))
+    return inp, tgt
+
+
+def _params(seed):
+    from paper_2408_01081_amd import surrogate as S
+    P = S.init_params(seed=seed, out_scale=0.3)
+    g = np.random.default_rng(seed + 1)
+    for k in P:
+        if k.endswith(".a"):
+            P[k] = P[k] + 0.1 * g.standard_normal(P[k].shape)
+    return P
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
+
+
+@gpu
+@pytest.mark.parametrize("split,circular", [(3, True), (3, False), (1, True)])
+def test_forward_matches_reference(split, circular):
+    torch = _torch()
+    from paper_2408_01081_amd import surrogate as S
+    B, H, W = 3, 64, 128
+    inp, _ = _inputs(1, B, H, W)
+    P = _params(2)
+    net = S.Surrogate(B, H, W, split=split)
+    net.set_params(S.pack_params(P))
+    x = torch.from_numpy(inp.astype(np.float32)).cuda()
+    out = net.forward(x, circular=circular).double().cpu().numpy()
+    # reference on the FP32-rounded input and parameters
+    P32 = {k: v.astype(np.float32).astype(np.float64) for k, v in P.items()}
+    ref = R.Forward(P32, inp.astype(np.float32).astype(np.float64), circular)
+    d_out = out - inp[:, :5]
+    d_ref = ref.out - inp[:, :5]
+    err = _rel(d_out, d_ref)   # relative to the network's correction
+    print("split %d circular %d: forward rel err of the correction %.2e" % (split, circular, err))
+    assert err < (1e-4 if split == 3 else 3e-2)
+    if split == 3:
+        assert _rel(out, ref.out) < 1e-5
+
+
+@gpu
+@pytest.mark.parametrize("circular", [True, False])
+def test_gradients_match_reference(circular):
+    torch = _torch()
+    from paper_2408_01081_amd import surrogate as S
+    B, H, W = 2, 64, 128
+    inp, tgt = _inputs(3, B, H, W)
+    P = _params(4)
+    net = S.Surrogate(B, H, W, split=3, train=True)
+    net.set_params(S.pack_params(P))
+    x = torch.from_numpy(inp.astype(np.float32)).cuda()
+    t = torch.from_numpy(tgt.astype(np.float32)).cuda()
+    loss = net.train_step(x, t, circular=circular, lr=0.0)
+    G = S.unpack_params(net.get_grads().double().cpu().numpy())
+    P32 = {k: v.astype(np.float32).astype(np.float64) for k, v in P.items()}
+    ref = R.Forward(P32, inp.astype(np.float32).astype(np.float64), circular)
+    lref = ref.loss(tgt.astype(np.float32).astype(np.float64))
+    assert abs(loss - lref) / lref < 1e-5
+    Gr = ref.backward()
+    worst = 0.0
+    for k in Gr:
+        e = _rel(G[k], Gr[k])
+        worst = max(worst, e)
+        assert e < 1e-3, (k, e)
+    print("worst gradient block rel err %.2e" % worst)
+
+
+@gpu
+def test_adam_step_matches_reference_and_loss_decreases():
+    torch = _torch()
+    from paper_2408_01081_amd import surrogate as S
+    B, H, W = 2, 64, 128
+    inp, tgt = _inputs(5, B, H, W)
+    P = _params(6)
+    net = S.Surrogate(B, H, W, split=3, train=True)
+    v0 = S.pack_params(P).astype(np.float32)
+    net.set_params(v0)
+    x = torch.from_numpy(inp.astype(np.float32)).cuda()
+    t = torch.from_numpy(tgt.astype(np.float32)).cuda()
+    lr = 1e-3
+    net.train_step(x, t, circular=True, lr=lr)
+    g = net.get_grads().double().cpu().numpy()
+    v1 = net.get_params().double().cpu().numpy()
+    # reference Adam (first step) with the same gradient
+    m = 0.1 * g
+    vv = 0.001 * g * g
+    want = v0.astype(np.float64) - lr * (m / 0.1) / (np.sqrt(vv / 0.001) + 1e-8)
+    assert np.max(np.abs(v1 - want)) < 1e-6 + 1e-5 * lr
+    losses = [net.train_step(x, t, circular=True, lr=lr) for _ in range(30)]
+    assert losses[-1] < 0.5 * losses[0], losses

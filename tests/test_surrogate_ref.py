@@ -1,0 +1,105 @@
+"""Pins of the FP64 surrogate reference: convolution against scipy's
+correlation, adjoint identities, and finite-difference gradients of the whole
+network loss."""
+import math
+
+import numpy as np
+import pytest
+from scipy import signal
+
+from oracle import surrogate_ref as S
+
+
+@pytest.mark.parametrize("circular", [True, False])
+def test_conv_matches_scipy(circular):
+    g = np.random.default_rng(0)
+    x = g.standard_normal((2, 8, 6, 3))
+    w = g.standard_normal((4, 3, 3, 3))
+    z = S.conv3x3(x, w, circular)
+    for b in range(2):
+        for o in range(4):
+            ref = np.zeros((8, 6))
+            for i in range(3):
+                img = x[b, :, :, i]
+                if circular:
+                    img = np.pad(img, 1, mode="wrap")
+                    ref += signal.correlate2d(img, w[o, i], mode="valid")
+                else:
+                    ref += signal.correlate2d(img, w[o, i], mode="same", boundary="fill")
+            assert np.allclose(z[b, :, :, o], ref, atol=1e-12)
+
+
+@pytest.mark.parametrize("circular", [True, False])
+def test_conv_backward_is_adjoint(circular):
+    g = np.random.default_rng(1)
+    x = g.standard_normal((2, 5, 4, 3))
+    w = g.standard_normal((2, 3, 3, 3))
+    gz = g.standard_normal((2, 5, 4, 2))
+    gx, gw = S.conv3x3_backward(x, w, gz, circular)
+    # <conv(x), gz> = <x, gx>  and  d<conv(x;w), gz>/dw = gw
+    assert abs(np.sum(S.conv3x3(x, w, circular) * gz) - np.sum(x * gx)) < 1e-10
+    dw = g.standard_normal(w.shape)
+    lhs = np.sum(S.conv3x3(x, dw, circular) * gz)
+    assert abs(lhs - np.sum(dw * gw)) < 1e-10
+
+
+def test_pool_up_adjoints():
+    g = np.random.default_rng(2)
+    x = g.standard_normal((1, 4, 6, 2))
+    y = g.standard_normal((1, 2, 3, 2))
+    assert abs(np.sum(S.pool2(x) * y) - np.sum(x * S.pool2_backward(y))) < 1e-12
+    assert abs(np.sum(S.up2(y) * x) - np.sum(y * S.up2_backward(x))) < 1e-12
+
+
+def test_field_conversion_roundtrip():
+    g = np.random.default_rng(3)
+    inp = _input(g, 2, 16, 16)
+    cK, cm, rho = S.material_speeds(inp)
+    f = inp[:, :5]
+    assert np.allclose(S.U_to_fields(S.fields_to_U(f, cK, cm, rho), cK, cm, rho), f)
+
+
+def _input(g, B, H, W):
+    inp = np.zeros((B, 8, H, W))
+    inp[:, :5] = g.standard_normal((B, 5, H, W))
+    nu = g.uniform(0, 0.49, B)
+    lam = 2 * nu / (1 - 2 * nu)
+    rho = g.uniform(0.5, 2.0, B)
+    inp[:, 5] = lam[:, None, None]
+    inp[:, 6] = 1.0
+    inp[:, 7] = rho[:, None, None]
+    return inp
+
+
+@pytest.mark.parametrize("circular", [True, False])
+def test_network_gradient_finite_differences(circular):
+    g = np.random.default_rng(4)
+    inp = _input(g, 2, 16, 16)
+    tgt = inp[:, :5] + 0.1 * g.standard_normal((2, 5, 16, 16))
+    P = S.init_params(seed=5)
+    for k in P:
+        if k.endswith(".a"):
+            P[k] = P[k] + 0.2 * g.standard_normal(P[k].shape)
+    fw = S.Forward(P, inp, circular)
+    fw.loss(tgt)
+    G = fw.backward()
+    for key in ("in.w", "e1a.w", "e3b.w", "d1b.w", "out.w", "e2a.a", "out.a", "d0a.a"):
+        idx = tuple(g.integers(0, n) for n in P[key].shape)
+        h = 1e-6 * max(1.0, abs(P[key][idx]))
+        P[key][idx] += h
+        lp = S.Forward(P, inp, circular).loss(tgt)
+        P[key][idx] -= 2 * h
+        lm = S.Forward(P, inp, circular).loss(tgt)
+        P[key][idx] += h
+        fd = (lp - lm) / (2 * h)
+        assert abs(fd - G[key][idx]) <= 1e-6 * max(abs(fd), 1e-8) + 1e-11, (key, fd, G[key][idx])
+
+
+def test_identity_network_reproduces_input():
+    # zero output layer: the surrogate returns its input fields exactly
+    g = np.random.default_rng(6)
+    inp = _input(g, 2, 16, 16)
+    P = S.init_params(seed=1)
+    P["out.w"][:] = 0
+    fw = S.Forward(P, inp, True)
+    assert np.allclose(fw.out, inp[:, :5], atol=1e-12)
