@@ -39,6 +39,9 @@ def parse():
     ap.add_argument("--cpu-sample-steps", type=int, default=30)
     ap.add_argument("--batch-instances", type=int, default=512)
     ap.add_argument("--batch-steps", type=int, default=2000)
+    ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--surrogate-weights", default=os.path.join(
+        ROOT, "paper_2408_01081_amd", "weights", "surrogate.npy"))
     ap.add_argument("--step-configs", default="",
                     help="force launch configurations 'P,D' (periodic, Dirichlet) instead of "
                          "autotuning, e.g. to profile the configuration a timed run chose")
@@ -175,6 +178,14 @@ def main():
     if args.batch_instances > 0 and args.batch_steps > 0:
         batched = batched_leg(args.batch_instances, args.batch_steps)
 
+    # ---- learned surrogate: MFMA throughput and surrogate + judge rollout -----
+    surrogate = None
+    if not args.no_surrogate:
+        try:
+            surrogate = surrogate_leg(args.surrogate_weights)
+        except Exception as ex:  # reported, never hidden
+            surrogate = {"error": repr(ex)}
+
     # ---- CPU baseline: the FP64 oracle on a bounded sample ---------------------
     cpu = None
     if not args.no_cpu_baseline:
@@ -196,6 +207,7 @@ def main():
         "cpu_baseline": cpu,
         "parity": parity,
         "batched": batched,
+        "surrogate": surrogate,
         "wall_s": round(wall, 3),
     }
     print(json.dumps(out), flush=True)
@@ -271,6 +283,73 @@ def batched_leg(n, nsteps):
             "GLUPS": round(nodes * nsteps / (ms * 1e-3) / 1e9, 3),
             "GB/s": round(160 * nodes * nsteps / (ms * 1e-3) / 1e9, 1),
             "max_rel_energy_drift": drift}
+
+
+BF16_PEAK_TFLOPS = 2500.0
+
+
+def unet_flops(H, W, B):
+    """Multiply-add FLOPs of one U-Net forward (3x3 convolutions only)."""
+    from paper_2408_01081_amd.surrogate import LAYERS
+    levels = [0, 0, 0, 1, 1, 2, 2, 3, 3, 2, 2, 1, 1, 0, 0, 0]
+    return sum(2 * 9 * ci * co * (H >> lv) * (W >> lv) for (_, ci, co), lv in zip(LAYERS, levels)) * B
+
+
+def surrogate_leg(weights_path):
+    """MFMA throughput of the surrogate kernels and the serving comparison on
+    a 256x256 Dirichlet lattice: 4096 steps as 256 windows of 16 steps."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2408_01081_amd import serve
+    from paper_2408_01081_amd.surrogate import Surrogate, init_params, pack_params
+    out = {}
+    trained = os.path.exists(weights_path)
+    params = (np.load(weights_path, allow_pickle=False) if trained
+              else pack_params(init_params(0, 0.0)).astype(np.float32))
+    out["weights"] = os.path.relpath(weights_path, ROOT) if trained else "untrained (identity)"
+    # forward throughput at the serving size and training-step throughput
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for (B, H, split) in ((1, 256, 3), (32, 128, 3)):
+        net = Surrogate(B, H, H, split=split)
+        net.set_params(params)
+        x = torch.randn(B, 8, H, H, device="cuda")
+        x[:, 5], x[:, 6], x[:, 7] = 0.5, 1.0, 1.0
+        for _ in range(3):
+            net.forward(x)
+        e0.record()
+        for _ in range(20):
+            net.forward(x)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 20
+        fl = unet_flops(H, H, B)
+        out["forward_b%d_%d" % (B, H)] = {
+            "ms": round(ms, 4), "GFLOP": round(fl / 1e9, 2),
+            "TFLOP/s": round(fl / ms / 1e9, 2),
+            "mfma_TFLOP/s": round(split * fl / ms / 1e9, 2),
+            "frac_of_bf16_peak": round(split * fl / ms / 1e9 / BF16_PEAK_TFLOPS, 4)}
+        del net
+    # serving comparison (C5 shape): seeded material and GRF data
+    prob = synth.grf_problem(256, 256, synth.DIRICHLET, seed=5)
+    plain_ms, variant, plain_final, variants = serve.plain_time_to_solution(prob, 4096, reps=3)
+    net = Surrogate(1, 256, 256, split=3)
+    net.set_params(params)
+    ro_ms, state, st = serve.rollout_time_to_solution(net, prob, 256, chunk=32, tol=1e-3,
+                                                      reps=1)
+    a = state.double().flatten()
+    bref = plain_final.double().flatten()
+    out["serving"] = {
+        "workload": "256x256 Dirichlet, nu %.3f rho %.3f, GRF data, 4096 steps = 256 windows of 16"
+                    % (prob.meta["nu"], prob.lam * 0 + prob.rho),
+        "plain_lbm_ms": round(plain_ms, 3), "plain_variant": variant,
+        "plain_variants_ms": {k: round(v, 3) for k, v in variants.items()},
+        "surrogate_judge_ms": round(ro_ms, 2),
+        "speedup_vs_plain": round(plain_ms / ro_ms, 4),
+        "tolerance": 1e-3, **st,
+        "final_rel_l2_vs_plain_fields": float(((a - bref).norm() / bref.norm()).item())}
+    return out
 
 
 def cpu_baseline(per, dir_, nsteps):

@@ -1,0 +1,152 @@
+"""Serving: plain lattice Boltzmann time-to-solution, and the surrogate rollout
+checked window by window by the lattice scheme (judge) with fallback.
+
+Rollout with speculative chunks of P windows (K = 16 lattice steps each):
+  1. surrogate chain s_1 = S(m_w), ..., s_P = S(s_{P-1}) (sequential calls);
+  2. judge: one batched launch replays all P windows from their starting
+     states m_w, s_1, ..., s_{P-1} (second-order re-initialisation, 16 FP32
+     steps) and measures each window's relative L2 error (first-order system
+     variables, FP64) between the surrogate output and the replay;
+  3. accept the windows up to the first one above the tolerance; the first
+     rejected window is replaced by its lattice replay (fallback) and the next
+     chunk starts from there.
+The returned state is therefore always either an accepted surrogate output or
+a lattice result."""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+import torch
+
+from .batch import Batch
+from .lbm import Lattice
+
+K_WINDOW = 16
+
+
+def _inst(p):
+    return dict(nx=p.nx, ny=p.ny, dx=p.dx, dt=p.dt, lam=p.lam, mu=p.mu, rho=p.rho, bc=p.bc)
+
+
+def plain_time_to_solution(prob, nsteps, reps=3, device="cuda:0"):
+    """Best of (a) one hipGraph of nsteps launches (batch of one) and (b) eager
+    launches with the autotuned single-lattice kernel; each timed from the
+    initial fields on the device to the final moments on the device, median of
+    reps.  Returns (ms, variant, final fields [5][ny][nx] float32)."""
+    dev = torch.device(device)
+    v0 = torch.from_numpy(prob.v0).to(dev)
+    s0 = torch.from_numpy(prob.sb0).to(dev)
+    results = {}
+    # (a) graph
+    b = Batch([_inst(prob)], device=dev)
+    b.init(v0, s0).step(nsteps)          # builds and caches the graph
+    out = torch.empty(5 * prob.nx * prob.ny, dtype=torch.float32, device=dev)
+    times = []
+    for _ in range(reps):
+        torch.cuda.synchronize(dev)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.init(v0, s0).step(nsteps)
+        b.moments(out=out)
+        e1.record()
+        torch.cuda.synchronize(dev)
+        times.append(e0.elapsed_time(e1))
+    results["graph"] = (float(np.median(times)), out.view(5, prob.ny, prob.nx).clone())
+    # (b) eager, autotuned
+    lat = Lattice(prob.nx, prob.ny, prob.dx, prob.dt, prob.lam, prob.mu, prob.rho, prob.bc,
+                  device=dev)
+    lat.init(v0, s0)
+    lat.autotune(reps=10)
+    times = []
+    out2 = torch.empty((5, prob.ny, prob.nx), dtype=torch.float32, device=dev)
+    for _ in range(reps):
+        torch.cuda.synchronize(dev)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        lat.init(v0, s0).step(nsteps)
+        lat.moments(out=out2)
+        e1.record()
+        torch.cuda.synchronize(dev)
+        times.append(e0.elapsed_time(e1))
+    results["eager"] = (float(np.median(times)), out2.clone())
+    best = min(results, key=lambda k: results[k][0])
+    return results[best][0], best, results[best][1], {k: v[0] for k, v in results.items()}
+
+
+class Rollout:
+    """Surrogate + judge rollout for one lattice problem."""
+
+    def __init__(self, net, prob, chunk=32, tol=1e-3, device="cuda:0"):
+        self.net, self.prob, self.P, self.tol = net, prob, int(chunk), float(tol)
+        self.dev = torch.device(device)
+        H, W = prob.ny, prob.nx
+        if net.H != H or net.W != W:
+            raise ValueError("surrogate built for another grid size")
+        self.circular = prob.bc == 0
+        # chain buffers: X[k] = [8][H][W] input of call k (fields + material)
+        self.X = torch.empty((self.P + 1, 8, H, W), dtype=torch.float32, device=self.dev)
+        self.X[:, 5] = prob.lam
+        self.X[:, 6] = prob.mu
+        self.X[:, 7] = prob.rho
+        self.judge = Batch([_inst(prob)] * self.P, device=self.dev)
+        self.starts = torch.empty((self.P, 5, H, W), dtype=torch.float32, device=self.dev)
+        self.preds = torch.empty((self.P, 5, H, W), dtype=torch.float32, device=self.dev)
+        self.replay = torch.empty(5 * self.P * H * W, dtype=torch.float32, device=self.dev)
+
+    def run(self, fields0, nwindows):
+        """fields0: [5][H][W] float32 on the device.  Returns (final fields,
+        stats dict)."""
+        P = self.P
+        state = fields0.clone()
+        w = 0
+        accepted = rejected = chunks = 0
+        errs = []
+        while w < nwindows:
+            n = min(P, nwindows - w)
+            self.X[0, :5].copy_(state)
+            for k in range(n):        # surrogate chain; output k is input k+1
+                self.net.forward(self.X[k:k + 1], circular=self.circular,
+                                 out=self.X[k + 1:k + 2, :5])
+            self.starts[:n].copy_(self.X[:n, :5])
+            self.preds[:n].copy_(self.X[1:n + 1, :5])
+            if n < P:   # unused judge slots replay the last window again
+                self.starts[n:].copy_(self.X[n - 1:n, :5].expand(P - n, -1, -1, -1))
+                self.preds[n:].copy_(self.X[n:n + 1, :5].expand(P - n, -1, -1, -1))
+            self.judge.init_fields_f32(self.starts)
+            self.judge.step(K_WINDOW)
+            e = self.judge.rel_l2_fields(self.preds)[:n]   # synchronises
+            chunks += 1
+            ok = int(np.argmax(e > self.tol)) if np.any(e > self.tol) else n
+            errs.extend(e[:ok + (1 if ok < n else 0)].tolist())
+            if ok == n:
+                state = self.X[n, :5].clone()
+                accepted += n
+                w += n
+            else:
+                accepted += ok
+                rejected += 1
+                self.judge.moments(out=self.replay)
+                hw = self.prob.nx * self.prob.ny
+                state = self.replay[5 * ok * hw:5 * (ok + 1) * hw].view(5, self.prob.ny,
+                                                                        self.prob.nx).clone()
+                w += ok + 1
+        stats = {"windows": nwindows, "accepted": accepted, "fallbacks": rejected,
+                 "chunks": chunks, "acceptance": accepted / nwindows,
+                 "window_err_median": float(np.median(errs)) if errs else None,
+                 "window_err_max": float(np.max(errs)) if errs else None}
+        return state, stats
+
+
+def rollout_time_to_solution(net, prob, nwindows, chunk=32, tol=1e-3, reps=3, device="cuda:0"):
+    ro = Rollout(net, prob, chunk, tol, device)
+    f0 = torch.cat([torch.from_numpy(prob.v0), torch.from_numpy(prob.sb0)]).float().to(ro.dev)
+    state, stats = ro.run(f0, min(nwindows, chunk))   # warm-up (graph build)
+    times = []
+    for _ in range(reps):
+        torch.cuda.synchronize(ro.dev)
+        t0 = time.perf_counter()
+        state, stats = ro.run(f0, nwindows)
+        torch.cuda.synchronize(ro.dev)
+        times.append((time.perf_counter() - t0) * 1e3)
+    return float(np.median(times)), state, stats
