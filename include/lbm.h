@@ -165,14 +165,29 @@ lbm_status lbm_get_step_config(const lbm_ctx* ctx, int32_t* h_index);
 lbm_status lbm_set_step_config(lbm_ctx* ctx, int32_t index);
 
 /* Time every valid configuration on this context's grid (reps launches each
- * after two warm-up launches, HIP events on the context's stream) and select
- * the fastest.  The lattice state is not modified: timed launches read the
+ * after two warm-up launches, HIP events on the context's stream), including
+ * the two-step variants (per step), and select the fastest.  The lattice state is not modified: timed launches read the
  * current state and write the spare buffer.  With use_cache != 0 a previous
  * result for the same (nx, ny, bc) in this process, or in the file named by
  * the environment variable LBM_AUTOTUNE_CACHE, is reused without timing
  * (*h_ms = -1 then).  New results are appended to that file.  Synchronises. */
 lbm_status lbm_autotune(lbm_ctx* ctx, int32_t reps, int32_t use_cache, int32_t* h_index,
                         double* h_ms);
+
+/* ---- two time steps per launch (temporal blocking) --------------------------
+ * A wave owns a strip of 64 columns and sweeps a segment of rows, forming the
+ * intermediate time level in registers, so a pair of steps reads and writes
+ * the populations once (80 B + 80 B per node for two updates).  Bitwise
+ * identical to two single steps.  Variants differ in rows per segment and
+ * store type.  index -1 disables it; lbm_autotune selects it when it is
+ * faster per step than the best single-step configuration.  With it enabled
+ * lbm_step(n) runs n/2 two-step launches and, for odd n, one single step. */
+int32_t lbm_step2_config_count(void);
+lbm_status lbm_step2_config_info(int32_t index, int32_t* h_seg_rows, int32_t* h_nontemporal);
+lbm_status lbm_get_step2_config(const lbm_ctx* ctx, int32_t* h_index);
+lbm_status lbm_set_step2_config(lbm_ctx* ctx, int32_t index);
+/* Average duration (ms) of one two-step launch (state-preserving, synchronises). */
+lbm_status lbm_time_step2_config(lbm_ctx* ctx, int32_t index, int32_t reps, double* h_ms);
 
 /* Average duration (ms) of one step launch of configuration `index` on this
  * context (same state-preserving scheme as lbm_autotune).  Synchronises. */

@@ -25,6 +25,7 @@
 #include "lbm.h"
 #include "lbm_kernels.hpp"
 #include "lbm_step.hpp"
+#include "lbm_step2.hpp"
 #include "lbm_init.hpp"
 #include "lbm_host.hpp"
 
@@ -218,7 +219,8 @@ struct lbm_ctx {
   const float* wall_T;
   int64_t wall_nsteps;
   int device;
-  int step_cfg;  // index into kStepConfigs
+  int step_cfg;   // index into kStepConfigs
+  int step2_cfg;  // index into kStep2Configs, or -1 (single steps only)
 };
 
 namespace {
@@ -293,6 +295,7 @@ lbm_status lbm_create(const lbm_params* p, void* d_ws, size_t ws_size, void* hip
   c->wall_nsteps = 0;
   hipGetDevice(&c->device);
   c->step_cfg = default_step_config(g.nx);
+  c->step2_cfg = -1;
   *out = c;
   g_err.clear();
   return LBM_OK;
@@ -354,6 +357,39 @@ lbm_status lbm_set_wall_velocity(lbm_ctx* c, int32_t rank, const float* d_W, con
 
 int64_t lbm_step_count(const lbm_ctx* c) { return c ? c->nstep : -1; }
 
+namespace {
+
+typedef void (*Step2Fn)(const float*, float*, Grid, Step2Const, Wall, Wall);
+struct Step2Config {
+  int seg_rows, nt;
+  Step2Fn fn[2];
+};
+#define LBM_CFG2(S, N) {S, N, {&k_step2<LBM_PERIODIC, N>, &k_step2<LBM_DIRICHLET, N>}}
+const Step2Config kStep2Configs[] = {LBM_CFG2(16, 0), LBM_CFG2(32, 0), LBM_CFG2(64, 0),
+                                     LBM_CFG2(128, 0), LBM_CFG2(32, 1), LBM_CFG2(64, 1)};
+#undef LBM_CFG2
+constexpr int kNumStep2Configs = (int)(sizeof(kStep2Configs) / sizeof(kStep2Configs[0]));
+
+Wall wall_at(const lbm_ctx* c, int64_t step) {
+  Wall w;
+  w.rank = c->wall_rank;
+  w.W = c->wall_W;
+  w.Trow = c->wall_rank ? c->wall_T + step * c->wall_rank : nullptr;
+  w.L = 2 * (c->g.nx + c->g.ny);
+  return w;
+}
+
+void launch_step2(lbm_ctx* c, int index, const float* src, float* dst, const Wall& w0,
+                  const Wall& w1) {
+  const Step2Config& k = kStep2Configs[index];
+  const Step2Const sc = step2_const(c->g, (float)c->kK, (float)c->km, k.seg_rows);
+  const int ntiles = sc.nstrips * sc.nseg;
+  hipLaunchKernelGGL(k.fn[c->p.bc], dim3((unsigned)((ntiles + 3) / 4)), dim3(256), 0, c->stream,
+                     src, dst, c->g, sc, w0, w1);
+}
+
+}  // namespace
+
 lbm_status lbm_step(lbm_ctx* c, int64_t nsteps) {
   if (!c) return fail(LBM_E_ARG, "null ctx");
   if (!c->initialised) return fail(LBM_E_STATE, "lbm_step before lbm_init");
@@ -364,12 +400,17 @@ lbm_status lbm_step(lbm_ctx* c, int64_t nsteps) {
   const StepConfig& cfg = kStepConfigs[c->step_cfg];
   const StepConst sc = step_const(cfg, g, (float)c->kK, (float)c->km);
   const StepFn fn = cfg.fn[c->p.bc];
-  for (int64_t s = 0; s < nsteps; ++s) {
-    Wall w;
-    w.rank = c->wall_rank;
-    w.W = c->wall_W;
-    w.Trow = c->wall_rank ? c->wall_T + (c->nstep + s) * c->wall_rank : nullptr;
-    w.L = 2 * (g.nx + g.ny);
+  int64_t s = 0;
+  if (c->step2_cfg >= 0) {
+    // two time steps per launch
+    for (; s + 1 < nsteps; s += 2) {
+      launch_step2(c, c->step2_cfg, c->buf[c->cur], c->buf[c->cur ^ 1], wall_at(c, c->nstep + s),
+                   wall_at(c, c->nstep + s + 1));
+      c->cur ^= 1;
+    }
+  }
+  for (; s < nsteps; ++s) {
+    const Wall w = wall_at(c, c->nstep + s);
     hipLaunchKernelGGL(fn, dim3(sc.ntiles), dim3(cfg.threads), 0, c->stream,
                        (const float*)c->buf[c->cur], c->buf[c->cur ^ 1], g, sc, w);
     c->cur ^= 1;
@@ -388,8 +429,12 @@ struct TuneKey {
   }
 };
 
+struct TuneVal {
+  int cfg, cfg2;
+};
+
 std::mutex g_tune_mu;
-std::map<TuneKey, int> g_tune_cache;
+std::map<TuneKey, TuneVal> g_tune_cache;
 bool g_tune_file_loaded = false;
 
 int find_config(int vec, int threads, int nt, int xmode) {
@@ -401,7 +446,8 @@ int find_config(int vec, int threads, int nt, int xmode) {
 }
 
 // Cache file (path in LBM_AUTOTUNE_CACHE): one line per tuned shape,
-// "nx ny bc vec threads nt xmode ms".  Caller holds g_tune_mu.
+// "nx ny bc vec threads nt xmode step2 ms" (step2 = two-step variant or -1).
+// Caller holds g_tune_mu.
 void load_tune_file() {
   if (g_tune_file_loaded) return;
   g_tune_file_loaded = true;
@@ -409,23 +455,25 @@ void load_tune_file() {
   if (!path || !*path) return;
   FILE* f = fopen(path, "r");
   if (!f) return;
-  int nx, ny, bc, vec, th, nt, xm;
+  int nx, ny, bc, vec, th, nt, xm, s2;
   double ms;
-  while (fscanf(f, "%d %d %d %d %d %d %d %lf", &nx, &ny, &bc, &vec, &th, &nt, &xm, &ms) == 8) {
+  while (fscanf(f, "%d %d %d %d %d %d %d %d %lf", &nx, &ny, &bc, &vec, &th, &nt, &xm, &s2,
+                &ms) == 9) {
     const int i = find_config(vec, th, nt, xm);
-    if (i >= 0 && step_config_valid(i, nx)) g_tune_cache[TuneKey{nx, ny, bc}] = i;
+    if (i >= 0 && step_config_valid(i, nx) && s2 >= -1 && s2 < 64)
+      g_tune_cache[TuneKey{nx, ny, bc}] = TuneVal{i, s2};
   }
   fclose(f);
 }
 
-void append_tune_file(const TuneKey& k, int i, double ms) {
+void append_tune_file(const TuneKey& k, const TuneVal& v, double ms) {
   const char* path = getenv("LBM_AUTOTUNE_CACHE");
   if (!path || !*path) return;
   FILE* f = fopen(path, "a");
   if (!f) return;
-  const StepConfig& c = kStepConfigs[i];
-  fprintf(f, "%d %d %d %d %d %d %d %.6f\n", k.nx, k.ny, k.bc, c.vec, c.threads, c.nt, c.xmode,
-          ms);
+  const StepConfig& c = kStepConfigs[v.cfg];
+  fprintf(f, "%d %d %d %d %d %d %d %d %.6f\n", k.nx, k.ny, k.bc, c.vec, c.threads, c.nt,
+          c.xmode, v.cfg2, ms);
   fclose(f);
 }
 
@@ -469,8 +517,9 @@ lbm_status lbm_autotune(lbm_ctx* c, int32_t reps, int32_t use_cache, int32_t* h_
     load_tune_file();
     auto it = g_tune_cache.find(key);
     if (it != g_tune_cache.end()) {
-      c->step_cfg = it->second;
-      if (h_index) *h_index = it->second;
+      c->step_cfg = it->second.cfg;
+      c->step2_cfg = it->second.cfg2 < kNumStep2Configs ? it->second.cfg2 : -1;
+      if (h_index) *h_index = it->second.cfg;
       if (h_ms) *h_ms = -1.0;
       return LBM_OK;
     }
@@ -510,19 +559,93 @@ lbm_status lbm_autotune(lbm_ctx* c, int32_t reps, int32_t use_cache, int32_t* h_
       best = i;
     }
   }
+  // two-step variants: time per step = time per launch / 2
+  int best2 = -1;
+  double best2_ms = 1e300;
+  for (int i = 0; i < kNumStep2Configs && s == LBM_OK; ++i) {
+    for (int r = 0; r < reps + 2; ++r) {
+      if (r == 2) hipEventRecord(e0, c->stream);
+      launch_step2(c, i, c->buf[c->cur], c->buf[c->cur ^ 1], w, w);
+    }
+    hipEventRecord(e1, c->stream);
+    s = hip_check(hipEventSynchronize(e1), "autotune sync");
+    float ms = 0.f;
+    if (s == LBM_OK) s = hip_check(hipEventElapsedTime(&ms, e0, e1), "autotune timing");
+    if (s == LBM_OK && ms / reps / 2 < best2_ms) {
+      best2_ms = ms / reps / 2;
+      best2 = i;
+    }
+  }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   if (s) return s;
   if (best < 0) return fail(LBM_E_ARG, "no valid launch configuration");
   c->step_cfg = best;
+  c->step2_cfg = best2_ms < best_ms ? best2 : -1;
+  const double per_step = best2_ms < best_ms ? best2_ms : best_ms;
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     load_tune_file();
-    g_tune_cache[key] = best;
-    append_tune_file(key, best, best_ms);
+    g_tune_cache[key] = TuneVal{best, c->step2_cfg};
+    append_tune_file(key, TuneVal{best, c->step2_cfg}, per_step);
   }
   if (h_index) *h_index = best;
-  if (h_ms) *h_ms = best_ms;
+  if (h_ms) *h_ms = per_step;
+  return LBM_OK;
+}
+
+int32_t lbm_step2_config_count(void) { return kNumStep2Configs; }
+
+lbm_status lbm_step2_config_info(int32_t index, int32_t* seg_rows, int32_t* nt) {
+  if (index < 0 || index >= kNumStep2Configs) return fail(LBM_E_ARG, "config index out of range");
+  if (seg_rows) *seg_rows = kStep2Configs[index].seg_rows;
+  if (nt) *nt = kStep2Configs[index].nt;
+  return LBM_OK;
+}
+
+lbm_status lbm_get_step2_config(const lbm_ctx* c, int32_t* index) {
+  if (!c || !index) return fail(LBM_E_ARG, "null argument");
+  *index = c->step2_cfg;
+  return LBM_OK;
+}
+
+lbm_status lbm_set_step2_config(lbm_ctx* c, int32_t index) {
+  if (!c) return fail(LBM_E_ARG, "null ctx");
+  if (index < -1 || index >= kNumStep2Configs) return fail(LBM_E_ARG, "config index out of range");
+  c->step2_cfg = index;
+  return LBM_OK;
+}
+
+lbm_status lbm_time_step2_config(lbm_ctx* c, int32_t index, int32_t reps, double* h_ms) {
+  if (!c || !h_ms) return fail(LBM_E_ARG, "null argument");
+  if (!c->initialised) return fail(LBM_E_STATE, "not initialised");
+  if (index < 0 || index >= kNumStep2Configs) return fail(LBM_E_ARG, "invalid configuration");
+  if (reps < 1) return fail(LBM_E_ARG, "reps must be >= 1");
+  hipEvent_t e0, e1;
+  lbm_status s = hip_check(hipEventCreate(&e0), "event");
+  if (s) return s;
+  s = hip_check(hipEventCreate(&e1), "event");
+  if (s) {
+    hipEventDestroy(e0);
+    return s;
+  }
+  Wall w;
+  w.rank = 0;
+  w.W = nullptr;
+  w.Trow = nullptr;
+  w.L = 2 * (c->g.nx + c->g.ny);
+  for (int r = 0; r < reps + 2; ++r) {
+    if (r == 2) hipEventRecord(e0, c->stream);
+    launch_step2(c, index, c->buf[c->cur], c->buf[c->cur ^ 1], w, w);
+  }
+  hipEventRecord(e1, c->stream);
+  s = hip_check(hipEventSynchronize(e1), "timing sync");
+  float ms = 0.f;
+  if (s == LBM_OK) s = hip_check(hipEventElapsedTime(&ms, e0, e1), "timing");
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (s) return s;
+  *h_ms = ms / reps;
   return LBM_OK;
 }
 

@@ -226,7 +226,7 @@ __global__ __launch_bounds__(RT) void k_sum_partials(const double* __restrict__ 
   if (threadIdx.x == 0) *out = s;
 }
 
-// dgamma[b][c] = sum_p g[b,p,c] z[b,p,c]: one workgroup per (b, c)
+// dgamma[b][c] = sum_p g[b,p,c] z[b,p,c]: one workgroup per (b, c), fixed-order tree
 __global__ __launch_bounds__(RT) void k_film_grad(const float* __restrict__ g,
                                                   const float* __restrict__ z, int HW, int C,
                                                   float* __restrict__ dgam) {
@@ -389,6 +389,15 @@ namespace {
 
 inline unsigned grid1(int64_t n) { return (unsigned)((n + RT - 1) / RT); }
 
+template <int SPLIT, int NB, int PB>
+void launch_conv(sg_net* n, const Tensor& x, const float* xscale, const unsigned short* wh,
+                 const unsigned short* wl, Tensor& z, int cin, int cout, int accumulate) {
+  const int64_t pixels = (int64_t)n->B * x.H * x.W;
+  dim3 grid((unsigned)(pixels / (64 * PB)), (unsigned)(cout / (16 * NB)));
+  hipLaunchKernelGGL((k_conv<SPLIT, NB, PB>), grid, dim3(256), 0, n->stream, x.p, xscale, wh, wl,
+                     z.p, x.H, x.W, cin, cout, n->circular, accumulate);
+}
+
 void conv(sg_net* n, const Tensor& x, const float* xscale, int l, Tensor& z, bool backward,
           int accumulate) {
   const LayerSpec& L = kLayers[l];
@@ -396,22 +405,22 @@ void conv(sg_net* n, const Tensor& x, const float* xscale, int l, Tensor& z, boo
   const unsigned short* wh = (backward ? n->wbh : n->wfh) + n->P.wq_off[l];
   const unsigned short* wl = (backward ? n->wbl : n->wfl) + n->P.wq_off[l];
   const int64_t pixels = (int64_t)n->B * x.H * x.W;
-  const int nb = cout >= 64 ? 4 : 2;
-  dim3 grid((unsigned)(pixels / 64), (unsigned)(cout / (16 * nb)));
+  // two pixel blocks per wave where the grid stays large enough
+  const bool pb2 = pixels % 128 == 0 && pixels / 128 * (cout / 64 > 0 ? cout / 64 : 1) >= 512;
   if (n->P.split == 3) {
-    if (nb == 4)
-      hipLaunchKernelGGL((k_conv<3, 4>), grid, dim3(256), 0, n->stream, x.p, xscale, wh, wl, z.p,
-                         x.H, x.W, cin, cout, n->circular, accumulate);
+    if (cout >= 64)
+      pb2 ? launch_conv<3, 4, 2>(n, x, xscale, wh, wl, z, cin, cout, accumulate)
+          : launch_conv<3, 4, 1>(n, x, xscale, wh, wl, z, cin, cout, accumulate);
     else
-      hipLaunchKernelGGL((k_conv<3, 2>), grid, dim3(256), 0, n->stream, x.p, xscale, wh, wl, z.p,
-                         x.H, x.W, cin, cout, n->circular, accumulate);
+      pb2 ? launch_conv<3, 2, 2>(n, x, xscale, wh, wl, z, cin, cout, accumulate)
+          : launch_conv<3, 2, 1>(n, x, xscale, wh, wl, z, cin, cout, accumulate);
   } else {
-    if (nb == 4)
-      hipLaunchKernelGGL((k_conv<1, 4>), grid, dim3(256), 0, n->stream, x.p, xscale, wh, wl, z.p,
-                         x.H, x.W, cin, cout, n->circular, accumulate);
+    if (cout >= 64)
+      pb2 ? launch_conv<1, 4, 2>(n, x, xscale, wh, wl, z, cin, cout, accumulate)
+          : launch_conv<1, 4, 1>(n, x, xscale, wh, wl, z, cin, cout, accumulate);
     else
-      hipLaunchKernelGGL((k_conv<1, 2>), grid, dim3(256), 0, n->stream, x.p, xscale, wh, wl, z.p,
-                         x.H, x.W, cin, cout, n->circular, accumulate);
+      pb2 ? launch_conv<1, 2, 2>(n, x, xscale, wh, wl, z, cin, cout, accumulate)
+          : launch_conv<1, 2, 1>(n, x, xscale, wh, wl, z, cin, cout, accumulate);
   }
 }
 

@@ -45,83 +45,100 @@ __device__ inline bf16 as_bf16(unsigned short b) {
 // Operand layouts of v_mfma_f32_16x16x32_bf16 (checked on gfx950 by an
 // in-bounds probe): lane l holds A[l%16][8(l/16)+j], B[8(l/16)+j][l%16] for
 // j = 0..7, and D[4(l/16)+j][l%16] for j = 0..3.
-// One wave computes 16 pixels (one row piece, W % 16 == 0) x 16*NB output
-// channels; a workgroup is 4 waves (64 pixels).  Cin % 32 == 0.
+// One wave computes PB blocks of 16 pixels (each one row piece, W % 16 == 0)
+// x 16*NB output channels, so every weight fragment feeds PB products; a
+// workgroup is 4 waves (64 PB pixels).  Cin % 32 == 0.
 // Used for the forward pass (Wt = [9][Cout][Cin]) and, with the flipped and
 // transposed weights, for the data gradient.
 // ---------------------------------------------------------------------------
-template <int SPLIT, int NB>
+template <int SPLIT, int NB, int PB>
 __global__ __launch_bounds__(256) void k_conv(const float* __restrict__ X,
                                               const float* __restrict__ xscale,
                                               const unsigned short* __restrict__ Whi,
                                               const unsigned short* __restrict__ Wlo,
                                               float* __restrict__ Z, int H, int W, int Cin,
                                               int Cout, int circular, int accumulate) {
+  // PB blocks of 16 consecutive pixels per wave (each inside one image row);
+  // a workgroup covers 4 * 16 * PB pixels
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t pix0 = (int64_t)blockIdx.x * 64 + wave * 16;
   const int64_t HW = (int64_t)H * W;
-  const int b = (int)(pix0 / HW);
-  const int rem = (int)(pix0 - (int64_t)b * HW);
-  const int y = rem / W, x0 = rem - y * W;
   const int m = lane & 15, kq = lane >> 4;
   const int co0 = blockIdx.y * 16 * NB;
-  f32x4 acc[NB];
+  int64_t pix0[PB];
+  int bb[PB], yy[PB], xx[PB];
 #pragma unroll
-  for (int nb = 0; nb < NB; ++nb) acc[nb] = (f32x4){0.f, 0.f, 0.f, 0.f};
-  const float* sc = xscale ? xscale + (int64_t)b * Cin : nullptr;
+  for (int pb = 0; pb < PB; ++pb) {
+    pix0[pb] = ((int64_t)blockIdx.x * 4 * PB + wave * PB + pb) * 16;
+    bb[pb] = (int)(pix0[pb] / HW);
+    const int rem = (int)(pix0[pb] - (int64_t)bb[pb] * HW);
+    yy[pb] = rem / W;
+    xx[pb] = rem - yy[pb] * W + m;
+  }
+  f32x4 acc[PB][NB];
+#pragma unroll
+  for (int pb = 0; pb < PB; ++pb)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) acc[pb][nb] = (f32x4){0.f, 0.f, 0.f, 0.f};
 
-  for (int t = 0; t < 9; ++t) {
-    const int dy = t / 3 - 1, dx = t % 3 - 1;
-    int ys = y + dy, xs = x0 + m + dx;
-    bool valid = true;
-    if (circular) {
-      ys = ys < 0 ? ys + H : (ys >= H ? ys - H : ys);
-      xs = xs < 0 ? xs + W : (xs >= W ? xs - W : xs);
-    } else {
-      valid = ys >= 0 && ys < H && xs >= 0 && xs < W;
-      ys = ys < 0 ? 0 : (ys >= H ? H - 1 : ys);
-      xs = xs < 0 ? 0 : (xs >= W ? W - 1 : xs);
-    }
-    const float* xp = X + (((int64_t)b * H + ys) * W + xs) * Cin + 8 * kq;
-    const int64_t wrow = ((int64_t)t * Cout + co0 + m) * Cin + 8 * kq;
-    for (int c0 = 0; c0 < Cin; c0 += 32) {
-      float a[8];
-      const float4 v0 = *reinterpret_cast<const float4*>(xp + c0);
-      const float4 v1 = *reinterpret_cast<const float4*>(xp + c0 + 4);
-      a[0] = v0.x; a[1] = v0.y; a[2] = v0.z; a[3] = v0.w;
-      a[4] = v1.x; a[5] = v1.y; a[6] = v1.z; a[7] = v1.w;
+  for (int c0 = 0; c0 < Cin; c0 += 32) {
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        a[j] = valid ? a[j] : 0.f;
-        if (sc) a[j] *= sc[c0 + 8 * kq + j];
-      }
-      bf16x8 ahi, alo;
+    for (int t = 0; t < 9; ++t) {
+      const int dy = t / 3 - 1, dx = t % 3 - 1;
+      bf16x8 ahi[PB], alo[PB];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const unsigned short h = bf16_bits(a[j]);
-        ahi[j] = as_bf16(h);
-        alo[j] = as_bf16(bf16_bits(a[j] - bf16_value(h)));
+      for (int pb = 0; pb < PB; ++pb) {
+        int ys = yy[pb] + dy, xs = xx[pb] + dx;
+        bool valid = true;
+        if (circular) {
+          ys = ys < 0 ? ys + H : (ys >= H ? ys - H : ys);
+          xs = xs < 0 ? xs + W : (xs >= W ? xs - W : xs);
+        } else {
+          valid = ys >= 0 && ys < H && xs >= 0 && xs < W;
+          ys = ys < 0 ? 0 : (ys >= H ? H - 1 : ys);
+          xs = xs < 0 ? 0 : (xs >= W ? W - 1 : xs);
+        }
+        const float* xp = X + (((int64_t)bb[pb] * H + ys) * W + xs) * Cin + 8 * kq + c0;
+        float a[8];
+        const float4 v0 = *reinterpret_cast<const float4*>(xp);
+        const float4 v1 = *reinterpret_cast<const float4*>(xp + 4);
+        a[0] = v0.x; a[1] = v0.y; a[2] = v0.z; a[3] = v0.w;
+        a[4] = v1.x; a[5] = v1.y; a[6] = v1.z; a[7] = v1.w;
+        const float* sc = xscale ? xscale + (int64_t)bb[pb] * Cin + c0 + 8 * kq : nullptr;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          a[j] = valid ? a[j] : 0.f;
+          if (sc) a[j] *= sc[j];
+          const unsigned short h = bf16_bits(a[j]);
+          ahi[pb][j] = as_bf16(h);
+          alo[pb][j] = as_bf16(bf16_bits(a[j] - bf16_value(h)));
+        }
       }
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
-        const int64_t wo = wrow + (int64_t)(16 * nb) * Cin + c0;
+        const int64_t wo = ((int64_t)t * Cout + co0 + 16 * nb + m) * Cin + 8 * kq + c0;
         const bf16x8 bhi = *reinterpret_cast<const bf16x8*>(Whi + wo);
-        acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, bhi, acc[nb], 0, 0, 0);
-        if (SPLIT == 3) {
-          const bf16x8 blo = *reinterpret_cast<const bf16x8*>(Wlo + wo);
-          acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo, bhi, acc[nb], 0, 0, 0);
-          acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, blo, acc[nb], 0, 0, 0);
+        bf16x8 blo;
+        if (SPLIT == 3) blo = *reinterpret_cast<const bf16x8*>(Wlo + wo);
+#pragma unroll
+        for (int pb = 0; pb < PB; ++pb) {
+          acc[pb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[pb], bhi, acc[pb][nb], 0, 0, 0);
+          if (SPLIT == 3) {
+            acc[pb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo[pb], bhi, acc[pb][nb], 0, 0, 0);
+            acc[pb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[pb], blo, acc[pb][nb], 0, 0, 0);
+          }
         }
       }
     }
   }
 #pragma unroll
-  for (int nb = 0; nb < NB; ++nb)
+  for (int pb = 0; pb < PB; ++pb)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      float* zp = Z + (pix0 + 4 * kq + j) * Cout + co0 + 16 * nb + m;
-      *zp = accumulate ? *zp + acc[nb][j] : acc[nb][j];
-    }
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        float* zp = Z + (pix0[pb] + 4 * kq + j) * Cout + co0 + 16 * nb + m;
+        *zp = accumulate ? *zp + acc[pb][nb][j] : acc[pb][nb][j];
+      }
 }
 
 // ---------------------------------------------------------------------------

@@ -159,6 +159,29 @@ class Lattice:
     def step_config(self, index):
         check(self.L.lbm_set_step_config(self.ctx, int(index)))
 
+    @property
+    def step2_config(self):
+        i = ctypes.c_int32()
+        check(self.L.lbm_get_step2_config(self.ctx, ctypes.byref(i)))
+        return i.value
+
+    @step2_config.setter
+    def step2_config(self, index):
+        check(self.L.lbm_set_step2_config(self.ctx, int(index)))
+
+    def step2_configs(self):
+        out = []
+        for i in range(self.L.lbm_step2_config_count()):
+            sr, nt = ctypes.c_int32(), ctypes.c_int32()
+            check(self.L.lbm_step2_config_info(i, ctypes.byref(sr), ctypes.byref(nt)))
+            out.append({"index": i, "seg_rows": sr.value, "nontemporal": nt.value})
+        return out
+
+    def time_step2_config(self, index, reps=20):
+        ms = ctypes.c_double()
+        check(self.L.lbm_time_step2_config(self.ctx, int(index), int(reps), ctypes.byref(ms)))
+        return ms.value
+
     def valid_step_configs(self):
         return [i for i, c in enumerate(step_configs()) if c["valid_for"](self.nx)]
 

@@ -107,9 +107,14 @@ def window_errors(net, data, mat, circular, batch, max_pairs=4096, seed=0):
 
 
 def rel_l2_U(a, b, material):
-    """||U(a) - U(b)|| / ||U(b)|| per sample, U = first-order system variables."""
+    """||U(a) - U(b)|| / ||U(b)|| per sample, U = first-order system variables.
+    material: per sample [B][3] or per pixel [B][3][H][W] (lambda, mu, rho)."""
+    mt = material.double()
+    if mt.dim() == 2:
+        mt = mt[:, :, None, None]
+
     def U(f):
-        lam, mu, rho = material[:, 0:1].double(), material[:, 1:2].double(), material[:, 2:3].double()
+        lam, mu, rho = mt[:, 0:1], mt[:, 1:2], mt[:, 2:3]
         cK = torch.sqrt((lam + mu) / rho)
         cm = torch.sqrt(mu / rho)
         f = f.double()
@@ -121,10 +126,17 @@ def rel_l2_U(a, b, material):
     return (d / ub.flatten(1).norm(dim=1)).cpu().numpy()
 
 
-def train(net, sets, minutes, batch, lr0=2e-3, lr_end=5e-5, seed=0, log_every=200,
-          max_steps=None):
+def train(net, sets, minutes, batch, lr0=1e-3, lr_end=2e-5, seed=0, log_every=100,
+          max_steps=None, spike=1000.0):
     """Adam with a cosine learning-rate decay over the time budget.  sets is
-    a list of (data, mat, bc) training sets; batches alternate between them."""
+    a list of (data, mat, bc) training sets; batches alternate between them.
+
+    The network is linear in the fields and has no saturation, so an unlucky
+    update can make it diverge: every log_every steps the loss is checked, the
+    parameters of the last healthy check are kept on the device, and a loss
+    above `spike` times the best smoothed loss (or non-finite) restores them
+    and halves the learning rate.  Returns the parameters with the lowest
+    smoothed loss."""
     g = np.random.default_rng(seed)
     H = sets[0][0].shape[3]
     dev = sets[0][0].device
@@ -133,25 +145,41 @@ def train(net, sets, minutes, batch, lr0=2e-3, lr_end=5e-5, seed=0, log_every=20
     t0 = time.time()
     budget = minutes * 60.0
     step, hist = 0, []
+    good = net.get_params().clone()
+    best_params, best = good.clone(), float("inf")
+    smooth, scale, restores = None, 1.0, 0
     while True:
         el = time.time() - t0
         if el > budget or (max_steps and step >= max_steps):
             break
         frac = min(1.0, el / budget)
-        lr = lr_end + 0.5 * (lr0 - lr_end) * (1 + math.cos(math.pi * frac))
+        lr = scale * (lr_end + 0.5 * (lr0 - lr_end) * (1 + math.cos(math.pi * frac)))
         data, mat, bc = sets[step % len(sets)]
         n, W1 = data.shape[0], data.shape[1]
         idx = g.integers(0, n, batch)
         widx = g.integers(0, W1 - 1, batch)
         assemble(data, mat, idx, widx, xin, tgt)
-        want = (step % log_every) == 0
-        loss = net.train_step(xin, tgt, circular=(bc == 0), lr=lr, want_loss=want)
-        if want:
+        check = (step % log_every) == 0
+        loss = net.train_step(xin, tgt, circular=(bc == 0), lr=lr, want_loss=check)
+        if check:
+            if not math.isfinite(loss) or (smooth is not None and loss > spike * max(best, 1e-12)):
+                net.set_params(good)           # back to the last healthy parameters
+                scale *= 0.5
+                restores += 1
+                log("step %6d  loss %.3e: restored, lr scale %.3g" % (step, loss, scale))
+            else:
+                smooth = loss if smooth is None else 0.8 * smooth + 0.2 * loss
+                good = net.get_params().clone()
+                if smooth < best:
+                    best, best_params = smooth, good.clone()
             hist.append((step, round(time.time() - t0, 1), loss, lr))
-            log("step %6d  t %6.1fs  loss %.3e  lr %.2e" % (step, time.time() - t0, loss, lr))
+            if (step // log_every) % 5 == 0:
+                log("step %6d  t %6.1fs  loss %.3e  smooth %.3e  lr %.2e" %
+                    (step, time.time() - t0, loss, smooth if smooth else float("nan"), lr))
         step += 1
     torch.cuda.synchronize(dev)
-    return step, hist
+    net.set_params(best_params)
+    return step, hist, {"restores": restores, "best_smoothed_loss": best}
 
 
 def main():
@@ -164,7 +192,7 @@ def main():
     ap.add_argument("--windows", type=int, default=16)
     ap.add_argument("--batch", type=int, default=32)
     ap.add_argument("--split", type=int, default=3)
-    ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--lr", type=float, default=5e-4)
     ap.add_argument("--init", default="")
     ap.add_argument("--report", default="")
     args = ap.parse_args()
@@ -185,11 +213,11 @@ def main():
     net = Surrogate(args.batch, args.side, args.side, split=args.split, train=True)
     p0 = np.load(args.init, allow_pickle=False) if args.init else pack_params(init_params(0, 0.0))
     net.set_params(p0.astype(np.float32))
-    steps, hist = train(net, train_sets, args.minutes, args.batch, lr0=args.lr)
+    steps, hist, info = train(net, train_sets, args.minutes, args.batch, lr0=args.lr)
     params = net.get_params().cpu().numpy()
     np.save(args.out, params, allow_pickle=False)
     rep = {"steps": steps, "minutes": args.minutes, "data_seconds": round(t_gen, 1),
-           "history": hist[-20:], "validation": {}}
+           "history": hist[::max(1, len(hist) // 40)], "validation": {}, **info}
     for data, mat, bc in val_sets:
         e = window_errors(net, data, mat, bc == 0, args.batch)
         rep["validation"]["periodic" if bc == 0 else "dirichlet"] = {
@@ -199,6 +227,7 @@ def main():
         ident = rel_l2_U(data[:, :-1].reshape(-1, 5, args.side, args.side)[:512],
                          data[:, 1:].reshape(-1, 5, args.side, args.side)[:512],
                          mat.repeat_interleave(data.shape[1] - 1, 0)[:512].to(data.device))
+        # (the identity map = persistence, i.e. no surrogate at all)
         rep["validation"]["periodic" if bc == 0 else "dirichlet"]["identity_median"] = \
             float(np.median(ident))
     log(rep["validation"])

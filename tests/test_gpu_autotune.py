@@ -72,3 +72,51 @@ def test_copy_kernel():
     copy_f32(b, a)
     torch.cuda.synchronize()
     assert torch.equal(a, b)
+
+
+@gpu
+@pytest.mark.parametrize("bc", [synth.PERIODIC, synth.DIRICHLET])
+@pytest.mark.parametrize("nx,ny", [(512, 96), (300, 70), (64, 64), (61, 7), (1, 5), (130, 1),
+                                   (2, 2), (1024, 33)])
+def test_two_step_kernel_bitwise_equals_single_steps(bc, nx, ny):
+    # temporal blocking changes where values live, not the arithmetic
+    torch = _torch()
+    from paper_2408_01081_amd.lbm import Lattice
+    prob = synth.plane_wave_problem(nx, ny, bc, seed=13, kmax=2)
+    v0, sb0 = prob.initial_fields()
+    nsteps = 23                       # odd: the last step is a single step
+    W, T = prob.wall_table(nsteps)
+    ref = None
+    lat = Lattice(prob.nx, prob.ny, prob.dx, prob.dt, prob.lam, prob.mu, prob.rho, prob.bc)
+    for cfg2 in [-1] + [c["index"] for c in lat.step2_configs()]:
+        lat.init(torch.from_numpy(v0), torch.from_numpy(sb0))
+        if bc == synth.DIRICHLET:
+            lat.set_wall_velocity(torch.from_numpy(W), torch.from_numpy(T))
+        lat.step2_config = cfg2
+        lat.step(5).step(nsteps - 5)
+        f = lat.populations().cpu().numpy()
+        if ref is None:
+            ref = f
+        else:
+            assert np.array_equal(f.view(np.uint32), ref.view(np.uint32)), cfg2
+
+
+@gpu
+def test_two_step_kernel_matches_oracle_dirichlet_walls():
+    torch = _torch()
+    import oracle
+    from paper_2408_01081_amd.lbm import Lattice
+    prob = synth.plane_wave_problem(200, 130, synth.DIRICHLET, seed=14, kmax=4)
+    v0, sb0 = prob.initial_fields()
+    n = 300
+    W, T = prob.wall_table(n)
+    lat = Lattice(prob.nx, prob.ny, prob.dx, prob.dt, prob.lam, prob.mu, prob.rho, prob.bc)
+    lat.init(torch.from_numpy(v0), torch.from_numpy(sb0))
+    lat.set_wall_velocity(torch.from_numpy(W), torch.from_numpy(T))
+    lat.step2_config = 1
+    lat.step(n)
+    U = lat.moments_U().double().cpu().numpy()
+    s = oracle.Setup(prob.nx, prob.ny, prob.dx, prob.dt, prob.lam, prob.mu, prob.rho, prob.bc)
+    sim = oracle.Simulation(s, v0, sb0, wall=prob.wall_velocity)
+    sim.advance(n)
+    assert oracle.rel_l2(U, sim.U()) < 1e-5
