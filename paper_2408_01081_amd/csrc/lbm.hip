@@ -361,12 +361,14 @@ namespace {
 
 typedef void (*Step2Fn)(const float*, float*, Grid, Step2Const, Wall, Wall);
 struct Step2Config {
-  int seg_rows, nt;
+  int seg_rows, nt, pf;
   Step2Fn fn[2];
 };
-#define LBM_CFG2(S, N) {S, N, {&k_step2<LBM_PERIODIC, N>, &k_step2<LBM_DIRICHLET, N>}}
-const Step2Config kStep2Configs[] = {LBM_CFG2(16, 0), LBM_CFG2(32, 0), LBM_CFG2(64, 0),
-                                     LBM_CFG2(128, 0), LBM_CFG2(32, 1), LBM_CFG2(64, 1)};
+#define LBM_CFG2(S, N, F) \
+  {S, N, F, {&k_step2<LBM_PERIODIC, N, F>, &k_step2<LBM_DIRICHLET, N, F>}}
+const Step2Config kStep2Configs[] = {LBM_CFG2(16, 0, 1), LBM_CFG2(32, 0, 1), LBM_CFG2(64, 0, 1),
+                                     LBM_CFG2(128, 0, 1), LBM_CFG2(32, 1, 1), LBM_CFG2(64, 1, 1),
+                                     LBM_CFG2(32, 0, 2), LBM_CFG2(64, 0, 2), LBM_CFG2(128, 0, 2)};
 #undef LBM_CFG2
 constexpr int kNumStep2Configs = (int)(sizeof(kStep2Configs) / sizeof(kStep2Configs[0]));
 

@@ -91,7 +91,7 @@ __device__ inline void level_update(const float below[NP], const float at[NP],
     for (int c = 0; c < NC; ++c) out[q * NC + c] = f[q][c];
 }
 
-template <int BC, int NT>
+template <int BC, int NT, int PF>
 __global__ __launch_bounds__(256) void k_step2(const float* __restrict__ src,
                                                float* __restrict__ dst, Grid g, Step2Const sc,
                                                Wall w0, Wall w1) {
@@ -125,13 +125,19 @@ __global__ __launch_bounds__(256) void k_step2(const float* __restrict__ src,
   load(y0 + 1, n1);
   level_update<BC>(nm2, nm1, n0, xw, y0 - 1, nx, ny, sc.kK, sc.km, w0, m0);
   level_update<BC>(nm1, n0, n1, xw, y0, nx, ny, sc.kK, sc.km, w0, m1);
-  // m0 = level n+1 row r-1, m1 = row r; n0 = level n row r, n1 = row r+1
-  float pre[NP];
-  load(y0 + 2, pre);
+  // m0 = level n+1 row r-1, m1 = row r; n0 = level n row r, n1 = row r+1.
+  // PF rows are prefetched ahead of their use (pre[0] = row r+2, ...).
+  float pre[PF][NP];
+#pragma unroll
+  for (int k = 0; k < PF; ++k) load(y0 + 2 + k, pre[k]);
   for (int r = y0; r < y1; ++r) {
 #pragma unroll
-    for (int k = 0; k < NP; ++k) n2[k] = pre[k];
-    if (r + 1 < y1) load(r + 3, pre);  // prefetch the next row
+    for (int k = 0; k < NP; ++k) n2[k] = pre[0][k];
+#pragma unroll
+    for (int j = 0; j + 1 < PF; ++j)
+#pragma unroll
+      for (int k = 0; k < NP; ++k) pre[j][k] = pre[j + 1][k];
+    if (r + PF < y1) load(r + 2 + PF, pre[PF - 1]);  // prefetch
     level_update<BC>(n0, n1, n2, xw, r + 1, nx, ny, sc.kK, sc.km, w0, m2);  // n+1, row r+1
     level_update<BC>(m0, m1, m2, xw, r, nx, ny, sc.kK, sc.km, w1, o);       // n+2, row r
     if (store) {
