@@ -179,11 +179,18 @@ lbm_status lbm_autotune(lbm_ctx* ctx, int32_t reps, int32_t use_cache, int32_t* 
  * intermediate time level in registers, so a pair of steps reads and writes
  * the populations once (80 B + 80 B per node for two updates).  Bitwise
  * identical to two single steps.  Variants differ in rows per segment and
- * store type.  index -1 disables it; lbm_autotune selects it when it is
- * faster per step than the best single-step configuration.  With it enabled
- * lbm_step(n) runs n/2 two-step launches and, for odd n, one single step. */
+ * store type and rows prefetched ahead (h_prefetch); h_seg_rows 0 means the
+ * segment length is chosen at launch so that one wave per resident slot
+ * covers the grid.  index -1 disables it;
+ * lbm_autotune selects it when it is faster per step than the best
+ * single-step configuration.  With it enabled lbm_step(n) runs n/2 two-step
+ * launches and, for odd n, one single step.  Grids whose row byte offsets
+ * ((19 planes + one row) * 4 B) reach 2^31 cannot use it: setting or timing a
+ * variant then fails with LBM_E_ARG and the autotuner skips it.  Any output
+ * pointer may be NULL. */
 int32_t lbm_step2_config_count(void);
-lbm_status lbm_step2_config_info(int32_t index, int32_t* h_seg_rows, int32_t* h_nontemporal);
+lbm_status lbm_step2_config_info(int32_t index, int32_t* h_seg_rows, int32_t* h_nontemporal,
+                                 int32_t* h_prefetch);
 lbm_status lbm_get_step2_config(const lbm_ctx* ctx, int32_t* h_index);
 lbm_status lbm_set_step2_config(lbm_ctx* ctx, int32_t index);
 /* Average duration (ms) of one two-step launch (state-preserving, synchronises). */

@@ -221,6 +221,7 @@ struct lbm_ctx {
   int device;
   int step_cfg;   // index into kStepConfigs
   int step2_cfg;  // index into kStep2Configs, or -1 (single steps only)
+  int step2_slots[32];  // resident waves of a two-step variant on this device (0: not known)
 };
 
 namespace {
@@ -360,17 +361,21 @@ int64_t lbm_step_count(const lbm_ctx* c) { return c ? c->nstep : -1; }
 namespace {
 
 typedef void (*Step2Fn)(const float*, float*, Grid, Step2Const, Wall, Wall);
+// seg_rows 0: as many rows per segment as fill the device with one wave per
+// resident slot (one round of waves, no tail), rounded up to the ring length
 struct Step2Config {
   int seg_rows, nt, pf;
   Step2Fn fn[2];
 };
 #define LBM_CFG2(S, N, F) \
   {S, N, F, {&k_step2<LBM_PERIODIC, N, F>, &k_step2<LBM_DIRICHLET, N, F>}}
-const Step2Config kStep2Configs[] = {LBM_CFG2(16, 0, 1), LBM_CFG2(32, 0, 1), LBM_CFG2(64, 0, 1),
-                                     LBM_CFG2(128, 0, 1), LBM_CFG2(32, 1, 1), LBM_CFG2(64, 1, 1),
-                                     LBM_CFG2(32, 0, 2), LBM_CFG2(64, 0, 2), LBM_CFG2(128, 0, 2)};
+const Step2Config kStep2Configs[] = {
+    LBM_CFG2(0, 0, 1),  LBM_CFG2(0, 1, 1),  LBM_CFG2(0, 0, 2),   LBM_CFG2(0, 1, 2),
+    LBM_CFG2(16, 0, 1), LBM_CFG2(32, 0, 1), LBM_CFG2(64, 0, 1),  LBM_CFG2(128, 0, 1),
+    LBM_CFG2(32, 1, 1), LBM_CFG2(64, 1, 1), LBM_CFG2(40, 0, 2),  LBM_CFG2(80, 0, 2)};
 #undef LBM_CFG2
 constexpr int kNumStep2Configs = (int)(sizeof(kStep2Configs) / sizeof(kStep2Configs[0]));
+static_assert(kNumStep2Configs <= 32, "step2_slots size");
 
 Wall wall_at(const lbm_ctx* c, int64_t step) {
   Wall w;
@@ -381,10 +386,36 @@ Wall wall_at(const lbm_ctx* c, int64_t step) {
   return w;
 }
 
+int step2_seg_rows(lbm_ctx* c, int index) {
+  const Step2Config& k = kStep2Configs[index];
+  if (k.seg_rows > 0) return k.seg_rows;
+  int& slots = c->step2_slots[index];
+  if (slots == 0) {
+    int per_cu = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k.fn[c->p.bc], 256,
+                                                     0) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) !=
+            hipSuccess ||
+        per_cu < 1 || cus < 1) {
+      (void)hipGetLastError();
+      per_cu = 2;
+      cus = 256;
+    }
+    slots = per_cu * 4 * cus;
+  }
+  const int ring = 3 + k.pf;
+  const int nstrips = (c->g.nx + S2_VALID - 1) / S2_VALID;
+  int nseg = slots / nstrips;
+  if (nseg < 1) nseg = 1;
+  int rows = (c->g.ny + nseg - 1) / nseg;
+  rows = (rows + ring - 1) / ring * ring;
+  return rows;
+}
+
 void launch_step2(lbm_ctx* c, int index, const float* src, float* dst, const Wall& w0,
                   const Wall& w1) {
   const Step2Config& k = kStep2Configs[index];
-  const Step2Const sc = step2_const(c->g, (float)c->kK, (float)c->km, k.seg_rows);
+  const Step2Const sc = step2_const(c->g, (float)c->kK, (float)c->km, step2_seg_rows(c, index));
   const int ntiles = sc.nstrips * sc.nseg;
   hipLaunchKernelGGL(k.fn[c->p.bc], dim3((unsigned)((ntiles + 3) / 4)), dim3(256), 0, c->stream,
                      src, dst, c->g, sc, w0, w1);
@@ -520,7 +551,8 @@ lbm_status lbm_autotune(lbm_ctx* c, int32_t reps, int32_t use_cache, int32_t* h_
     auto it = g_tune_cache.find(key);
     if (it != g_tune_cache.end()) {
       c->step_cfg = it->second.cfg;
-      c->step2_cfg = it->second.cfg2 < kNumStep2Configs ? it->second.cfg2 : -1;
+      c->step2_cfg =
+          it->second.cfg2 < kNumStep2Configs && step2_fits(c->g) ? it->second.cfg2 : -1;
       if (h_index) *h_index = it->second.cfg;
       if (h_ms) *h_ms = -1.0;
       return LBM_OK;
@@ -564,7 +596,7 @@ lbm_status lbm_autotune(lbm_ctx* c, int32_t reps, int32_t use_cache, int32_t* h_
   // two-step variants: time per step = time per launch / 2
   int best2 = -1;
   double best2_ms = 1e300;
-  for (int i = 0; i < kNumStep2Configs && s == LBM_OK; ++i) {
+  for (int i = 0; i < kNumStep2Configs && s == LBM_OK && step2_fits(c->g); ++i) {
     for (int r = 0; r < reps + 2; ++r) {
       if (r == 2) hipEventRecord(e0, c->stream);
       launch_step2(c, i, c->buf[c->cur], c->buf[c->cur ^ 1], w, w);
@@ -598,10 +630,11 @@ lbm_status lbm_autotune(lbm_ctx* c, int32_t reps, int32_t use_cache, int32_t* h_
 
 int32_t lbm_step2_config_count(void) { return kNumStep2Configs; }
 
-lbm_status lbm_step2_config_info(int32_t index, int32_t* seg_rows, int32_t* nt) {
+lbm_status lbm_step2_config_info(int32_t index, int32_t* seg_rows, int32_t* nt, int32_t* pf) {
   if (index < 0 || index >= kNumStep2Configs) return fail(LBM_E_ARG, "config index out of range");
   if (seg_rows) *seg_rows = kStep2Configs[index].seg_rows;
   if (nt) *nt = kStep2Configs[index].nt;
+  if (pf) *pf = kStep2Configs[index].pf;
   return LBM_OK;
 }
 
@@ -614,6 +647,8 @@ lbm_status lbm_get_step2_config(const lbm_ctx* c, int32_t* index) {
 lbm_status lbm_set_step2_config(lbm_ctx* c, int32_t index) {
   if (!c) return fail(LBM_E_ARG, "null ctx");
   if (index < -1 || index >= kNumStep2Configs) return fail(LBM_E_ARG, "config index out of range");
+  if (index >= 0 && !step2_fits(c->g))
+    return fail(LBM_E_ARG, "grid too wide for the two-step kernel (row offsets exceed 2^31 B)");
   c->step2_cfg = index;
   return LBM_OK;
 }
@@ -622,6 +657,8 @@ lbm_status lbm_time_step2_config(lbm_ctx* c, int32_t index, int32_t reps, double
   if (!c || !h_ms) return fail(LBM_E_ARG, "null argument");
   if (!c->initialised) return fail(LBM_E_STATE, "not initialised");
   if (index < 0 || index >= kNumStep2Configs) return fail(LBM_E_ARG, "invalid configuration");
+  if (!step2_fits(c->g))
+    return fail(LBM_E_ARG, "grid too wide for the two-step kernel (row offsets exceed 2^31 B)");
   if (reps < 1) return fail(LBM_E_ARG, "reps must be >= 1");
   hipEvent_t e0, e1;
   lbm_status s = hip_check(hipEventCreate(&e0), "event");

@@ -5,11 +5,19 @@
 // one row ahead, forms the intermediate level f*(t_{n+1}) of the row above
 // the output row, then the output level f*(t_{n+2}) of the output row, and
 // stores only that: 80 B read + 80 B written per node for two updates.
-//   x neighbours: lane shuffles; the two edge lanes of the strip cannot see
-//     beyond it, so level n+1 is exact on lanes 1..62 and level n+2 on lanes
-//     2..61: strips overlap by 4 columns and store 60 columns each;
+//   x neighbours: one-lane DPP wave shifts; the two edge lanes of the strip
+//     cannot see beyond it, so level n+1 is exact on lanes 1..62 and level
+//     n+2 on lanes 2..61: strips overlap by 4 columns and store 60 columns;
 //   y neighbours: the previous and next rows of the sweep, kept in registers;
 //     a segment starts with two rows of warm-up.
+// Row buffers form rings whose slots rotate by renaming (the sweep is unrolled
+// by the ring length), so a prefetched row is never copied between registers
+// and the wait for it sits at its first use, PF rows after its load; the
+// stores of earlier rows stay in flight meanwhile.  Rows are addressed with
+// buffer instructions: a wave-uniform resource per row (scalar registers), the
+// plane offset as scalar offset and the column as 32-bit lane offset.  Lanes
+// that must not store give an offset beyond the resource's range, which the
+// hardware drops: the stores need no branch, so the wait counts stay exact.
 // Walls (Dirichlet) are applied at both levels with their own time rows.
 // Every node update is collide() on the same inputs as the single-step
 // kernel, so the result is bitwise identical to two launches of it.
@@ -32,17 +40,36 @@ struct Step2Const {
   int nstrips;   // strips across a row
   int seg_rows;  // output rows per segment
   int nseg;      // segments along y
+  int plane4;    // bytes between planes
+  int extent;    // bytes one row's resource covers: (NP - 1) planes + one row
 };
+
+constexpr int S2_RSRC_WORD3 = 0x00020000;  // raw 32-bit buffer access (gfx9 family)
+constexpr int S2_DROP = (int)0x80000000u;  // lane offset beyond every row's range
 
 __device__ inline int wrap_mod(int x, int n) {
   int r = x % n;
   return r < 0 ? r + n : r;
 }
 
+// row actually read for sweep row y (uniform): periodic wrap or wall clamp
 template <int BC>
 __device__ inline int row_index(int y, int ny) {
-  if (BC == LBM_PERIODIC) return wrap_mod(y, ny);
+  if (BC == LBM_PERIODIC) {
+    while (y < 0) y += ny;
+    while (y >= ny) y -= ny;
+    return y;
+  }
   return y < 0 ? 0 : (y >= ny ? ny - 1 : y);
+}
+
+// value held by lane - 1 (wave_shr:1) and by lane + 1 (wave_shl:1); the
+// lane without a source reads 0, and its result is never stored
+__device__ inline float from_lane_below(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, false));
+}
+__device__ inline float from_lane_above(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, false));
 }
 
 // one level-update of row y at this lane's column x from the rows below,
@@ -54,11 +81,9 @@ __device__ inline void level_update(const float below[NP], const float at[NP],
   float f[NQ][NC];
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
-    const float l = __shfl_up(at[0 * NC + c], 1, 64);    // f*_0 from x - 1
-    const float r = __shfl_down(at[2 * NC + c], 1, 64);  // f*_2 from x + 1
-    f[0][c] = l;
+    f[0][c] = from_lane_below(at[0 * NC + c]);  // f*_0 from x - 1
     f[1][c] = below[1 * NC + c];
-    f[2][c] = r;
+    f[2][c] = from_lane_above(at[2 * NC + c]);  // f*_2 from x + 1
     f[3][c] = above[3 * NC + c];
   }
   if (BC == LBM_DIRICHLET) {
@@ -95,67 +120,87 @@ template <int BC, int NT, int PF>
 __global__ __launch_bounds__(256) void k_step2(const float* __restrict__ src,
                                                float* __restrict__ dst, Grid g, Step2Const sc,
                                                Wall w0, Wall w1) {
+  constexpr int NB = 3 + PF;  // ring length: rows r-1 .. r+2+PF minus the freed one
   const int lane = threadIdx.x & 63;
   const int ntiles = sc.nstrips * sc.nseg;
   const int nwg = (ntiles + 3) / 4;
-  const int wid = xcd_tile(blockIdx.x, nwg) * 4 + (threadIdx.x >> 6);
+  // wave index: uniform by construction, stated to the compiler
+  const int wid = xcd_tile(blockIdx.x, nwg) * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (wid >= ntiles) return;  // whole waves exit together
   const int strip = wid % sc.nstrips, seg = wid / sc.nstrips;
   const int nx = g.nx, ny = g.ny;
   const int x = strip * S2_VALID - 2 + lane;  // unwrapped column of this lane
   const int xc = BC == LBM_PERIODIC ? wrap_mod(x, nx) : (x < 0 ? 0 : (x >= nx ? nx - 1 : x));
+  const uint32_t xr = (uint32_t)xc;  // column read by this lane
+  const uint32_t xs = (uint32_t)(x < 0 ? 0 : x);
   // column for the wall tests: out-of-range lanes never match a wall column
   const int xw = (x >= 0 && x < nx) ? x : -2;
   const bool store = lane >= 2 && lane < S2_LANES - 2 && x >= 0 && x < nx;
   const int y0 = seg * sc.seg_rows;
   const int y1 = y0 + sc.seg_rows < ny ? y0 + sc.seg_rows : ny;
 
+  const int xr4 = (int)(xr * 4u);
+  const int xs4 = store ? (int)(xs * 4u) : S2_DROP;
   auto load = [&](int y, float v[NP]) {
-    const float* p = src + (int64_t)row_index<BC>(y, ny) * g.pitch + xc;
+    const float* rp = src + (int64_t)row_index<BC>(y, ny) * g.pitch;
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc((void*)rp, (short)0, sc.extent, S2_RSRC_WORD3);
 #pragma unroll
-    for (int k = 0; k < NP; ++k) v[k] = p[(int64_t)k * g.plane];
+    for (int k = 0; k < NP; ++k)
+      v[k] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, xr4, k * sc.plane4, 0));
   };
 
-  float n0[NP], n1[NP], n2[NP], m0[NP], m1[NP], m2[NP], o[NP];
-  // warm-up: level n rows y0-2 .. y0+1, level n+1 rows y0-1, y0
-  float nm2[NP], nm1[NP];
-  load(y0 - 2, nm2);
-  load(y0 - 1, nm1);
-  load(y0, n0);
-  load(y0 + 1, n1);
-  level_update<BC>(nm2, nm1, n0, xw, y0 - 1, nx, ny, sc.kK, sc.km, w0, m0);
-  level_update<BC>(nm1, n0, n1, xw, y0, nx, ny, sc.kK, sc.km, w0, m1);
-  // m0 = level n+1 row r-1, m1 = row r; n0 = level n row r, n1 = row r+1.
-  // PF rows are prefetched ahead of their use (pre[0] = row r+2, ...).
-  float pre[PF][NP];
+  // level-n ring: row y in slot (y - y0) % NB; level-n+1 ring: row y in
+  // slot (y - y0 + 1) % NB
+  float nb[NB][NP], mb[NB][NP], o[NP];
+  {
+    float t0[NP], t1[NP];
+    load(y0 - 2, t0);
+    load(y0 - 1, t1);
+    load(y0, nb[0]);
+    load(y0 + 1, nb[1]);
+    // row y0 - 1 is -1 for the first segment: it is only read where a wall
+    // replaces it, and any valid row keeps its wall lookups in range
+    level_update<BC>(t0, t1, nb[0], xw, y0 > 0 ? y0 - 1 : 0, nx, ny, sc.kK, sc.km, w0, mb[0]);
+    level_update<BC>(t1, nb[0], nb[1], xw, y0, nx, ny, sc.kK, sc.km, w0, mb[1]);
+  }
 #pragma unroll
-  for (int k = 0; k < PF; ++k) load(y0 + 2 + k, pre[k]);
-  for (int r = y0; r < y1; ++r) {
+  for (int k = 0; k < PF; ++k) load(y0 + 2 + k, nb[2 + k]);
+
+  // The sweep runs in whole rings of NB rows; rows past the segment end are
+  // computed from valid (wrapped or clamped) rows and their stores dropped.
+  // No early exit inside a ring: a conditional exit would let the compiler
+  // sink each prefetch past it, next to its first use.
+  for (int r = y0; r < y1; r += NB) {
 #pragma unroll
-    for (int k = 0; k < NP; ++k) n2[k] = pre[0][k];
+    for (int j = 0; j < NB; ++j) {
+      const int rr = r + j;
+      const int ym = rr + 1 < ny ? rr + 1 : ny - 1;  // rows past the grid: any valid row
+      const int yo = rr < ny ? rr : ny - 1;
+      // prefetch level-n row rr+2+PF into the slot of row rr-1 (no longer
+      // read); unconditional, so the wait counts are the same on every path
+      // (the last PF rows of a segment fetch a row that is not used)
+      load(rr + 2 + PF, nb[(j + NB - 1) % NB]);
+      // keep the prefetch at the head of the row: the scheduler would sink it
+      // towards its first use and shorten the distance it hides
+      __builtin_amdgcn_sched_barrier(0);
+      // level n+1, row rr+1
+      level_update<BC>(nb[j], nb[(j + 1) % NB], nb[(j + 2) % NB], xw, ym, nx, ny, sc.kK, sc.km,
+                       w0, mb[(j + 2) % NB]);
+      // level n+2, row rr
+      level_update<BC>(mb[j], mb[(j + 1) % NB], mb[(j + 2) % NB], xw, yo, nx, ny, sc.kK, sc.km,
+                       w1, o);
+      {
+        const int off = rr < y1 ? xs4 : S2_DROP;
+        float* rp = dst + (int64_t)yo * g.pitch;
+        const __amdgpu_buffer_rsrc_t rs =
+            __builtin_amdgcn_make_buffer_rsrc((void*)rp, (short)0, sc.extent, S2_RSRC_WORD3);
 #pragma unroll
-    for (int j = 0; j + 1 < PF; ++j)
-#pragma unroll
-      for (int k = 0; k < NP; ++k) pre[j][k] = pre[j + 1][k];
-    if (r + PF < y1) load(r + 2 + PF, pre[PF - 1]);  // prefetch
-    level_update<BC>(n0, n1, n2, xw, r + 1, nx, ny, sc.kK, sc.km, w0, m2);  // n+1, row r+1
-    level_update<BC>(m0, m1, m2, xw, r, nx, ny, sc.kK, sc.km, w1, o);       // n+2, row r
-    if (store) {
-      float* p = dst + (int64_t)r * g.pitch + x;
-#pragma unroll
-      for (int k = 0; k < NP; ++k) {
-        if (NT)
-          __builtin_nontemporal_store(o[k], p + (int64_t)k * g.plane);
-        else
-          p[(int64_t)k * g.plane] = o[k];
+        for (int k = 0; k < NP; ++k)  // aux 2: nontemporal
+          __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(o[k]), rs, off, k * sc.plane4,
+                                                NT ? 2 : 0);
       }
-    }
-#pragma unroll
-    for (int k = 0; k < NP; ++k) {
-      n0[k] = n1[k];
-      n1[k] = n2[k];
-      m0[k] = m1[k];
-      m1[k] = m2[k];
+      __builtin_amdgcn_sched_barrier(0);
     }
   }
 }
@@ -167,7 +212,14 @@ inline Step2Const step2_const(const Grid& g, float kK, float km, int seg_rows) {
   sc.nstrips = (g.nx + S2_VALID - 1) / S2_VALID;
   sc.seg_rows = seg_rows;
   sc.nseg = (g.ny + seg_rows - 1) / seg_rows;
+  sc.plane4 = (int)(g.plane * 4);
+  sc.extent = (int)(((NP - 1) * g.plane + g.nx) * 4);
   return sc;
+}
+
+// the byte offsets of a row's resource must stay below 2^31
+inline bool step2_fits(const Grid& g) {
+  return ((NP - 1) * g.plane + g.pitch) * 4 < ((int64_t)1 << 31);
 }
 
 }  // namespace lbmk

@@ -172,9 +172,11 @@ class Lattice:
     def step2_configs(self):
         out = []
         for i in range(self.L.lbm_step2_config_count()):
-            sr, nt = ctypes.c_int32(), ctypes.c_int32()
-            check(self.L.lbm_step2_config_info(i, ctypes.byref(sr), ctypes.byref(nt)))
-            out.append({"index": i, "seg_rows": sr.value, "nontemporal": nt.value})
+            sr, nt, pf = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+            check(self.L.lbm_step2_config_info(i, ctypes.byref(sr), ctypes.byref(nt),
+                                               ctypes.byref(pf)))
+            out.append({"index": i, "seg_rows": sr.value, "nontemporal": nt.value,
+                        "prefetch": pf.value})
         return out
 
     def time_step2_config(self, index, reps=20):
