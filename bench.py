@@ -43,8 +43,10 @@ def parse():
     ap.add_argument("--surrogate-weights", default=os.path.join(
         ROOT, "paper_2408_01081_amd", "weights", "surrogate.npy"))
     ap.add_argument("--step-configs", default="",
-                    help="force launch configurations 'P,D' (periodic, Dirichlet) instead of "
-                         "autotuning, e.g. to profile the configuration a timed run chose")
+                    help="force single-step launch configurations 'P,D' (periodic, Dirichlet) "
+                         "instead of autotuning, e.g. to profile what a timed run chose")
+    ap.add_argument("--step2-configs", default="",
+                    help="with --step-configs: two-step variants 'P,D' (-1 = single steps only)")
     return ap.parse_args()
 
 
@@ -89,59 +91,83 @@ def main():
     log("setup %.1fs" % (time.time() - t0))
 
     nodes = per.nx * per.ny + dir_.nx * dir_.ny
-    # launch configuration chosen by the autotuner (state-preserving)
+    # launch configuration chosen by the autotuner (state-preserving): the best
+    # single-step configuration and, when faster per step, a two-step variant
     from paper_2408_01081_amd.lbm import step_configs
     cfgs = step_configs()
     tuned = []
     forced = [int(v) for v in args.step_configs.split(",")] if args.step_configs else None
+    forced2 = [int(v) for v in args.step2_configs.split(",")] if args.step2_configs else None
     for li, lat in enumerate(lats):
         if forced:
             lat.step_config = forced[li]
-            idx = forced[li]
+            lat.step2_config = forced2[li] if forced2 else -1
         else:
-            idx, tms = lat.autotune(reps=10, use_cache=True)
+            lat.autotune(reps=10, use_cache=True)
+        idx, idx2 = lat.step_config, lat.step2_config
         c = cfgs[idx]
-        tuned.append({"lattice": "%dx%d" % (lat.nx, lat.ny), "config": idx, "vec": c["vec"],
-                      "threads": c["threads"], "nontemporal": c["nontemporal"],
-                      "shuffle": c["shuffle"]})
+        t = {"lattice": "%dx%d" % (lat.nx, lat.ny), "config": idx, "vec": c["vec"],
+             "threads": c["threads"], "nontemporal": c["nontemporal"], "shuffle": c["shuffle"],
+             "step2_config": idx2}
+        if idx2 >= 0:
+            t["step2"] = lat.step2_configs()[idx2]
+        tuned.append(t)
     log("autotuned: %s" % tuned)
     for lat in lats:
         lat.step(W)
     torch.cuda.synchronize()
 
     # ---- timed region ----------------------------------------------------------
+    # events: start, after the periodic lattice's K steps, after the Dirichlet's
     stream = torch.cuda.current_stream(dev)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    e0.record(stream)
-    for lat in lats:
-        lat.step(K)
-    e1.record(stream)
+    ev[0].record(stream)
+    lats[0].step(K)
+    ev[1].record(stream)
+    lats[1].step(K)
+    ev[2].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    ms_total = e0.elapsed_time(e1)
+    ms_total = ev[0].elapsed_time(ev[2])
     ms_per_step = ms_total / K
     glups = nodes * K / (ms_total * 1e-3) / 1e9
     log("timed: %d steps in %.3f s (events %.3f s)" % (K, wall, ms_total * 1e-3))
 
-    # ---- dominant kernel: the 4096^2 periodic step, timed alone ----------------
-    reps = max(1, min(K, 500))
+    # ---- dominant kernel: the 4096^2 periodic lattice's kernel -----------------
+    # Its average launch duration comes from the periodic part of the timed
+    # region (HIP events on the stream the kernels run on).  Algorithmic bytes
+    # per launch: every node's 20 FP32 populations read once and written once
+    # (160 B per node), for one time step (k_step) or two (k_step2).
     per_lat = lats[0]
-    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    a.record(stream)
-    per_lat.step(reps)
-    b.record(stream)
-    torch.cuda.synchronize()
-    kern_ms = a.elapsed_time(b) / reps
+    two = tuned[0]["step2_config"] >= 0
+    per_ms = ev[0].elapsed_time(ev[1])
+    launches = K // 2 + K % 2 if two else K
+    kern_ms = per_ms / (K / 2.0 if two else K)   # an odd trailing single step counts half
     alg_bytes = BYTES_PER_LUP * per.nx * per.ny
     achieved = alg_bytes / (kern_ms * 1e-3) / 1e9
+    kname = "k_step2" if two else "k_step"
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": measured_traffic(),
-                "kernel": "k_step (periodic 4096x4096, config %d)" % tuned[0]["config"],
-                "kernel_ms": round(kern_ms, 5),
+                "traffic": measured_traffic(kname),
+                "kernel": "%s (periodic 4096x4096, %s)" % (
+                    kname, ("two-step variant %d" % tuned[0]["step2_config"]) if two
+                    else ("config %d" % tuned[0]["config"])),
+                "kernel_ms": round(kern_ms, 5), "launches": launches,
+                "steps_per_launch": 2 if two else 1,
+                "kernel_glups": round((2 if two else 1) * per.nx * per.ny / kern_ms / 1e6, 2),
                 "algorithmic_bytes_per_launch": alg_bytes}
+    if two:
+        # the best single-step kernel on the same lattice, for comparison: its
+        # bandwidth fraction is the kernel-quality figure of the one-step form
+        ms1 = per_lat.time_step_config(tuned[0]["config"], reps=50)
+        roofline["single_step_reference"] = {
+            "kernel": "k_step (config %d)" % tuned[0]["config"], "ms": round(ms1, 5),
+            "GB/s": round(alg_bytes / (ms1 * 1e-3) / 1e9, 1),
+            "frac": round(alg_bytes / (ms1 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "glups": round(per.nx * per.ny / ms1 / 1e6, 2)}
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
     # ---- reference: plain streaming copy of one population buffer -------------
     from paper_2408_01081_amd.lbm import copy_f32
@@ -213,10 +239,10 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def measured_traffic():
+def measured_traffic(kname):
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3
     counter summary, if it was taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", "k_step_periodic_4096_traffic.json")
+    path = os.path.join(ROOT, "profiles", "%s_periodic_4096_traffic.json" % kname)
     if not os.path.exists(path):
         return None
     try:

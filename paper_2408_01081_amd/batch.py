@@ -115,6 +115,10 @@ class Batch:
     def moments(self, out=None, system=False):
         if out is None:
             out = torch.empty(5 * self.total_nodes, dtype=torch.float32, device=self.device)
+        if (out.numel() != 5 * self.total_nodes or out.dtype != torch.float32
+                or not out.is_contiguous() or not out.is_cuda):
+            raise ValueError("out must be a contiguous float32 tensor of 5 * total_nodes "
+                             "elements on the batch's device")
         fn = self.L.lbm_batch_moments_U if system else self.L.lbm_batch_moments
         check(fn(self.ctx, _ptr(out)))
         return out

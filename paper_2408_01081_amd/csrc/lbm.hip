@@ -370,9 +370,9 @@ struct Step2Config {
 #define LBM_CFG2(S, N, F) \
   {S, N, F, {&k_step2<LBM_PERIODIC, N, F>, &k_step2<LBM_DIRICHLET, N, F>}}
 const Step2Config kStep2Configs[] = {
-    LBM_CFG2(0, 0, 1),  LBM_CFG2(0, 1, 1),  LBM_CFG2(0, 0, 2),   LBM_CFG2(0, 1, 2),
-    LBM_CFG2(16, 0, 1), LBM_CFG2(32, 0, 1), LBM_CFG2(64, 0, 1),  LBM_CFG2(128, 0, 1),
-    LBM_CFG2(32, 1, 1), LBM_CFG2(64, 1, 1), LBM_CFG2(40, 0, 2),  LBM_CFG2(80, 0, 2)};
+    LBM_CFG2(0, 0, 1),  LBM_CFG2(4, 0, 1),  LBM_CFG2(6, 0, 1),  LBM_CFG2(8, 0, 1),
+    LBM_CFG2(12, 0, 1), LBM_CFG2(16, 0, 1), LBM_CFG2(24, 0, 1), LBM_CFG2(32, 0, 1),
+    LBM_CFG2(64, 0, 1), LBM_CFG2(32, 1, 1), LBM_CFG2(64, 1, 1), LBM_CFG2(40, 0, 2)};
 #undef LBM_CFG2
 constexpr int kNumStep2Configs = (int)(sizeof(kStep2Configs) / sizeof(kStep2Configs[0]));
 static_assert(kNumStep2Configs <= 32, "step2_slots size");

@@ -116,82 +116,86 @@ __device__ inline void level_update(const float below[NP], const float at[NP],
     for (int c = 0; c < NC; ++c) out[q * NC + c] = f[q][c];
 }
 
-template <int BC, int NT, int PF>
-__global__ __launch_bounds__(256) void k_step2(const float* __restrict__ src,
-                                               float* __restrict__ dst, Grid g, Step2Const sc,
-                                               Wall w0, Wall w1) {
-  constexpr int NB = 3 + PF;  // ring length: rows r-1 .. r+2+PF minus the freed one
-  const int lane = threadIdx.x & 63;
-  const int ntiles = sc.nstrips * sc.nseg;
-  const int nwg = (ntiles + 3) / 4;
-  // wave index: uniform by construction, stated to the compiler
-  const int wid = xcd_tile(blockIdx.x, nwg) * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  if (wid >= ntiles) return;  // whole waves exit together
-  const int strip = wid % sc.nstrips, seg = wid / sc.nstrips;
-  const int nx = g.nx, ny = g.ny;
-  const int x = strip * S2_VALID - 2 + lane;  // unwrapped column of this lane
-  const int xc = BC == LBM_PERIODIC ? wrap_mod(x, nx) : (x < 0 ? 0 : (x >= nx ? nx - 1 : x));
-  const uint32_t xr = (uint32_t)xc;  // column read by this lane
-  const uint32_t xs = (uint32_t)(x < 0 ? 0 : x);
-  // column for the wall tests: out-of-range lanes never match a wall column
-  const int xw = (x >= 0 && x < nx) ? x : -2;
-  const bool store = lane >= 2 && lane < S2_LANES - 2 && x >= 0 && x < nx;
-  const int y0 = seg * sc.seg_rows;
-  const int y1 = y0 + sc.seg_rows < ny ? y0 + sc.seg_rows : ny;
+// Per-lane constants of one wave's strip.
+struct Strip {
+  int xw;       // column for the wall tests (-2 for lanes outside the grid)
+  int xr4;      // byte offset of the column this lane reads
+  int xs4;      // byte offset of the column this lane stores, or S2_DROP
+};
 
-  const int xr4 = (int)(xr * 4u);
-  const int xs4 = store ? (int)(xs * 4u) : S2_DROP;
-  auto load = [&](int y, float v[NP]) {
-    const float* rp = src + (int64_t)row_index<BC>(y, ny) * g.pitch;
-    const __amdgpu_buffer_rsrc_t rs =
-        __builtin_amdgcn_make_buffer_rsrc((void*)rp, (short)0, sc.extent, S2_RSRC_WORD3);
+template <int BC>
+__device__ inline void load_row(const float* __restrict__ src, const Grid& g,
+                                const Step2Const& sc, const Strip& st, int y, float v[NP]) {
+  const float* rp = src + (int64_t)row_index<BC>(y, g.ny) * g.pitch;
+  const __amdgpu_buffer_rsrc_t rs =
+      __builtin_amdgcn_make_buffer_rsrc((void*)rp, (short)0, sc.extent, S2_RSRC_WORD3);
 #pragma unroll
-    for (int k = 0; k < NP; ++k)
-      v[k] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, xr4, k * sc.plane4, 0));
-  };
+  for (int k = 0; k < NP; ++k)
+    v[k] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, st.xr4, k * sc.plane4, 0));
+}
 
-  // level-n ring: row y in slot (y - y0) % NB; level-n+1 ring: row y in
-  // slot (y - y0 + 1) % NB
+// update of row y from the rows below, at and above it; rows off the grid
+// (computed only to be dropped or replaced by a wall) use any valid row for
+// their wall lookups
+template <int BC>
+__device__ inline void row_update(const float below[NP], const float at[NP],
+                                  const float above[NP], int xw, int y, const Grid& g,
+                                  const Step2Const& sc, const Wall& w, float out[NP]) {
+  const int yc = y < 0 ? 0 : (y >= g.ny ? g.ny - 1 : y);
+  level_update<BC>(below, at, above, xw, yc, g.nx, g.ny, sc.kK, sc.km, w, out);
+}
+
+// One wave's sweep over output rows y0 .. y1-1: output row r needs level n+1
+// rows r-1 .. r+1 and level n rows r-2 .. r+2.
+template <int BC, int NT, int PF>
+__device__ inline void sweep(const float* __restrict__ src, float* __restrict__ dst,
+                             const Grid& g, const Step2Const& sc, const Strip& st, int y0, int y1,
+                             const Wall& w0, const Wall& w1) {
+  constexpr int NB = 3 + PF;  // ring length
+  const int count = y1 - y0;
+  const int last_in = y1 + 1;  // last level-n row the sweep needs
+
+  // level-n ring: row y0 + i in slot i % NB; level-n+1 ring: row y0 + i - 1
+  // in slot i % NB
   float nb[NB][NP], mb[NB][NP], o[NP];
   {
     float t0[NP], t1[NP];
-    load(y0 - 2, t0);
-    load(y0 - 1, t1);
-    load(y0, nb[0]);
-    load(y0 + 1, nb[1]);
-    // row y0 - 1 is -1 for the first segment: it is only read where a wall
-    // replaces it, and any valid row keeps its wall lookups in range
-    level_update<BC>(t0, t1, nb[0], xw, y0 > 0 ? y0 - 1 : 0, nx, ny, sc.kK, sc.km, w0, mb[0]);
-    level_update<BC>(t1, nb[0], nb[1], xw, y0, nx, ny, sc.kK, sc.km, w0, mb[1]);
+    load_row<BC>(src, g, sc, st, y0 - 2, t0);
+    load_row<BC>(src, g, sc, st, y0 - 1, t1);
+    load_row<BC>(src, g, sc, st, y0, nb[0]);
+    load_row<BC>(src, g, sc, st, y0 + 1, nb[1]);
+    row_update<BC>(t0, t1, nb[0], st.xw, y0 - 1, g, sc, w0, mb[0]);
+    row_update<BC>(t1, nb[0], nb[1], st.xw, y0, g, sc, w0, mb[1]);
   }
 #pragma unroll
-  for (int k = 0; k < PF; ++k) load(y0 + 2 + k, nb[2 + k]);
+  for (int k = 0; k < PF; ++k) load_row<BC>(src, g, sc, st, y0 + 2 + k, nb[2 + k]);
 
   // The sweep runs in whole rings of NB rows; rows past the segment end are
   // computed from valid (wrapped or clamped) rows and their stores dropped.
   // No early exit inside a ring: a conditional exit would let the compiler
   // sink each prefetch past it, next to its first use.
-  for (int r = y0; r < y1; r += NB) {
+  for (int i0 = 0; i0 < count; i0 += NB) {
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
-      const int rr = r + j;
-      const int ym = rr + 1 < ny ? rr + 1 : ny - 1;  // rows past the grid: any valid row
-      const int yo = rr < ny ? rr : ny - 1;
-      // prefetch level-n row rr+2+PF into the slot of row rr-1 (no longer
-      // read); unconditional, so the wait counts are the same on every path
-      // (the last PF rows of a segment fetch a row that is not used)
-      load(rr + 2 + PF, nb[(j + NB - 1) % NB]);
+      const int i = i0 + j;
+      const int rr = y0 + i;
+      // prefetch level-n row rr + 2 + PF into the slot of row rr - 1 (no
+      // longer read); unconditional, so the wait counts are the same on every
+      // path.  Past the last needed row it re-reads that row (a cache hit)
+      // instead of fetching one more from memory.
+      const int yl = rr + 2 + PF < last_in ? rr + 2 + PF : last_in;
+      load_row<BC>(src, g, sc, st, yl, nb[(j + NB - 1) % NB]);
       // keep the prefetch at the head of the row: the scheduler would sink it
       // towards its first use and shorten the distance it hides
       __builtin_amdgcn_sched_barrier(0);
-      // level n+1, row rr+1
-      level_update<BC>(nb[j], nb[(j + 1) % NB], nb[(j + 2) % NB], xw, ym, nx, ny, sc.kK, sc.km,
-                       w0, mb[(j + 2) % NB]);
+      // level n+1, row rr + 1
+      row_update<BC>(nb[j], nb[(j + 1) % NB], nb[(j + 2) % NB], st.xw, rr + 1, g, sc, w0,
+                     mb[(j + 2) % NB]);
       // level n+2, row rr
-      level_update<BC>(mb[j], mb[(j + 1) % NB], mb[(j + 2) % NB], xw, yo, nx, ny, sc.kK, sc.km,
-                       w1, o);
+      row_update<BC>(mb[j], mb[(j + 1) % NB], mb[(j + 2) % NB], st.xw, rr, g, sc, w1, o);
       {
-        const int off = rr < y1 ? xs4 : S2_DROP;
+        const int off = i < count ? st.xs4 : S2_DROP;
+        const int yo = rr < 0 ? 0 : (rr >= g.ny ? g.ny - 1 : rr);
         float* rp = dst + (int64_t)yo * g.pitch;
         const __amdgpu_buffer_rsrc_t rs =
             __builtin_amdgcn_make_buffer_rsrc((void*)rp, (short)0, sc.extent, S2_RSRC_WORD3);
@@ -203,6 +207,30 @@ __global__ __launch_bounds__(256) void k_step2(const float* __restrict__ src,
       __builtin_amdgcn_sched_barrier(0);
     }
   }
+}
+
+template <int BC, int NT, int PF>
+__global__ __launch_bounds__(256) void k_step2(const float* __restrict__ src,
+                                               float* __restrict__ dst, Grid g, Step2Const sc,
+                                               Wall w0, Wall w1) {
+  const int lane = threadIdx.x & 63;
+  const int ntiles = sc.nstrips * sc.nseg;
+  const int nwg = (ntiles + 3) / 4;
+  // wave index: uniform by construction, stated to the compiler
+  const int wid = xcd_tile(blockIdx.x, nwg) * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (wid >= ntiles) return;  // whole waves exit together
+  const int strip = wid % sc.nstrips, seg = wid / sc.nstrips;
+  const int nx = g.nx, ny = g.ny;
+  const int x = strip * S2_VALID - 2 + lane;  // unwrapped column of this lane
+  const int xc = BC == LBM_PERIODIC ? wrap_mod(x, nx) : (x < 0 ? 0 : (x >= nx ? nx - 1 : x));
+  const bool store = lane >= 2 && lane < S2_LANES - 2 && x >= 0 && x < nx;
+  Strip st;
+  st.xw = (x >= 0 && x < nx) ? x : -2;
+  st.xr4 = (int)((uint32_t)xc * 4u);
+  st.xs4 = store ? (int)((uint32_t)x * 4u) : S2_DROP;
+  const int y0 = seg * sc.seg_rows;
+  const int y1 = y0 + sc.seg_rows < ny ? y0 + sc.seg_rows : ny;
+  sweep<BC, NT, PF>(src, dst, g, sc, st, y0, y1, w0, w1);
 }
 
 inline Step2Const step2_const(const Grid& g, float kK, float km, int seg_rows) {

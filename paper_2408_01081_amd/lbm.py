@@ -172,7 +172,7 @@ class Lattice:
     def step2_configs(self):
         out = []
         for i in range(self.L.lbm_step2_config_count()):
-            sr, nt, pf = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+            sr, nt, pf = (ctypes.c_int32() for _ in range(3))
             check(self.L.lbm_step2_config_info(i, ctypes.byref(sr), ctypes.byref(nt),
                                                ctypes.byref(pf)))
             out.append({"index": i, "seg_rows": sr.value, "nontemporal": nt.value,

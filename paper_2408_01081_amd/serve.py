@@ -1,17 +1,20 @@
 """Serving: plain lattice Boltzmann time-to-solution, and the surrogate rollout
 checked window by window by the lattice scheme (judge) with fallback.
 
-Rollout with speculative chunks of P windows (K = 16 lattice steps each):
-  1. surrogate chain s_1 = S(m_w), ..., s_P = S(s_{P-1}) (sequential calls);
-  2. judge: one batched launch replays all P windows from their starting
-     states m_w, s_1, ..., s_{P-1} (second-order re-initialisation, 16 FP32
+Rollout with speculative chunks of n <= P windows (K = 16 lattice steps each):
+  1. surrogate chain s_1 = S(m_w), ..., s_n = S(s_{n-1}) (sequential calls);
+  2. judge: one batched launch replays all n windows from their starting
+     states m_w, s_1, ..., s_{n-1} (second-order re-initialisation, 16 FP32
      steps) and measures each window's relative L2 error (first-order system
      variables, FP64) between the surrogate output and the replay;
   3. accept the windows up to the first one above the tolerance; the first
      rejected window is replaced by its lattice replay (fallback) and the next
      chunk starts from there.
-The returned state is therefore always either an accepted surrogate output or
-a lattice result."""
+The chunk length adapts: it doubles after a fully accepted chunk and drops to
+twice the accepted run after a rejection, so little surrogate work is thrown
+away when windows are often rejected.  The judge for n windows is a batch of
+the smallest power of two >= n instances.  The returned state is always either
+an accepted surrogate output or a lattice result."""
 from __future__ import annotations
 
 import time
@@ -89,10 +92,19 @@ class Rollout:
         self.X[:, 5] = prob.lam
         self.X[:, 6] = prob.mu
         self.X[:, 7] = prob.rho
-        self.judge = Batch([_inst(prob)] * self.P, device=self.dev)
+        self.judges = {}
         self.starts = torch.empty((self.P, 5, H, W), dtype=torch.float32, device=self.dev)
         self.preds = torch.empty((self.P, 5, H, W), dtype=torch.float32, device=self.dev)
         self.replay = torch.empty(5 * self.P * H * W, dtype=torch.float32, device=self.dev)
+
+    def _judge(self, n):
+        m = 1
+        while m < n:
+            m *= 2
+        m = min(m, self.P)
+        if m not in self.judges:
+            self.judges[m] = Batch([_inst(self.prob)] * m, device=self.dev)
+        return m, self.judges[m]
 
     def run(self, fields0, nwindows):
         """fields0: [5][H][W] float32 on the device.  Returns (final fields,
@@ -100,22 +112,24 @@ class Rollout:
         P = self.P
         state = fields0.clone()
         w = 0
+        cur = P
         accepted = rejected = chunks = 0
         errs = []
         while w < nwindows:
-            n = min(P, nwindows - w)
+            n = min(cur, nwindows - w)
+            m, judge = self._judge(n)
             self.X[0, :5].copy_(state)
             for k in range(n):        # surrogate chain; output k is input k+1
                 self.net.forward(self.X[k:k + 1], circular=self.circular,
                                  out=self.X[k + 1:k + 2, :5])
             self.starts[:n].copy_(self.X[:n, :5])
             self.preds[:n].copy_(self.X[1:n + 1, :5])
-            if n < P:   # unused judge slots replay the last window again
-                self.starts[n:].copy_(self.X[n - 1:n, :5].expand(P - n, -1, -1, -1))
-                self.preds[n:].copy_(self.X[n:n + 1, :5].expand(P - n, -1, -1, -1))
-            self.judge.init_fields_f32(self.starts)
-            self.judge.step(K_WINDOW)
-            e = self.judge.rel_l2_fields(self.preds)[:n]   # synchronises
+            if n < m:   # unused judge slots replay the last window again
+                self.starts[n:m].copy_(self.X[n - 1:n, :5].expand(m - n, -1, -1, -1))
+                self.preds[n:m].copy_(self.X[n:n + 1, :5].expand(m - n, -1, -1, -1))
+            judge.init_fields_f32(self.starts[:m])
+            judge.step(K_WINDOW)
+            e = judge.rel_l2_fields(self.preds[:m])[:n]   # synchronises
             chunks += 1
             ok = int(np.argmax(e > self.tol)) if np.any(e > self.tol) else n
             errs.extend(e[:ok + (1 if ok < n else 0)].tolist())
@@ -123,10 +137,12 @@ class Rollout:
                 state = self.X[n, :5].clone()
                 accepted += n
                 w += n
+                cur = min(P, 2 * cur)
             else:
                 accepted += ok
                 rejected += 1
-                self.judge.moments(out=self.replay)
+                cur = max(1, min(P, 2 * (ok + 1)))
+                judge.moments(out=self.replay[:5 * m * self.prob.nx * self.prob.ny])
                 hw = self.prob.nx * self.prob.ny
                 state = self.replay[5 * ok * hw:5 * (ok + 1) * hw].view(5, self.prob.ny,
                                                                         self.prob.nx).clone()
