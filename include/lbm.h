@@ -115,7 +115,10 @@ lbm_status lbm_set_populations(lbm_ctx* ctx, const float* d_f);
  * Steps beyond nsteps are rejected by lbm_step.  The source rows 3-5 use
  * c_K/c and c_mu/c (the leading-order bounce-back balance, Eq. bb0, carries
  * the 1/c of the equilibrium; the printed speeds coincide only for c = 1).
- * Pointers are kept (not copied) and must stay valid while stepping. */
+ * lbm_step sums the series for chunks of up to 64 steps into a table inside
+ * the workspace (one small launch per chunk, FMA in rank order), so the step
+ * kernels read one velocity per wall link.  Pointers are kept (not copied)
+ * and must stay valid while stepping. */
 lbm_status lbm_set_wall_velocity(lbm_ctx* ctx, int32_t rank, const float* d_W,
                                  const float* d_T, int64_t nsteps);
 
@@ -166,8 +169,11 @@ lbm_status lbm_set_step_config(lbm_ctx* ctx, int32_t index);
 
 /* Time every valid configuration on this context's grid (reps launches each
  * after two warm-up launches, HIP events on the context's stream), including
- * the two-step variants (per step), and select the fastest.  The lattice state is not modified: timed launches read the
- * current state and write the spare buffer.  With use_cache != 0 a previous
+ * the two-step variants (per step), and select the fastest.  Launches are
+ * timed with the context's wall data at the current step when it has data for
+ * two more steps, else with resting walls.  The lattice state is not
+ * modified: timed launches read the current state and write the spare buffer.
+ * With use_cache != 0 a previous
  * result for the same (nx, ny, bc) in this process, or in the file named by
  * the environment variable LBM_AUTOTUNE_CACHE, is reused without timing
  * (*h_ms = -1 then).  New results are appended to that file.  Synchronises. */

@@ -222,12 +222,39 @@ struct lbm_ctx {
   int step_cfg;   // index into kStepConfigs
   int step2_cfg;  // index into kStep2Configs, or -1 (single steps only)
   int step2_slots[32];  // resident waves of a two-step variant on this device (0: not known)
+  float* wall_v;        // [WALL_CHUNK][2 (nx + ny)][2] wall velocities of upcoming steps
 };
 
 namespace {
 
+// steps whose wall velocities are summed ahead in one launch (even, so that
+// two-step launches pair steps inside a chunk)
+constexpr int WALL_CHUNK = 64;
+
+size_t wall_table_bytes(const Grid& g) {
+  return (size_t)round_up((int64_t)WALL_CHUNK * 2 * (g.nx + g.ny) * 2 * 4, 256);
+}
+
 size_t ws_bytes(const Grid& g) {
-  return 2 * state_bytes(g) + (size_t)round_up((2 * RED_BLOCKS + 2) * 8, 256);
+  return 2 * state_bytes(g) + (size_t)round_up((2 * RED_BLOCKS + 2) * 8, 256) +
+         wall_table_bytes(g);
+}
+
+// V[s][link][2] = wall velocity of step `step0 + s` at every link
+__global__ void k_wall_eval(const float* __restrict__ W, const float* __restrict__ T, int rank,
+                            int L, int nsteps, float* __restrict__ V) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)nsteps * L) return;
+  const int s = (int)(i / L), link = (int)(i - (int64_t)s * L);
+  Wall w;
+  w.W = W;
+  w.Trow = T + (int64_t)s * rank;
+  w.rank = rank;
+  w.L = L;
+  float a, b;
+  wall_series(w, link, a, b);
+  V[2 * i] = a;
+  V[2 * i + 1] = b;
 }
 
 lbm_status reduce(lbm_ctx* c, int mode, const double* ref, double out[2]) {
@@ -282,6 +309,8 @@ lbm_status lbm_create(const lbm_params* p, void* d_ws, size_t ws_size, void* hip
   c->buf[0] = (float*)d_ws;
   c->buf[1] = (float*)((char*)d_ws + state_bytes(g));
   c->partial = (double*)((char*)d_ws + 2 * state_bytes(g));
+  c->wall_v = (float*)((char*)d_ws + 2 * state_bytes(g) +
+                       (size_t)round_up((2 * RED_BLOCKS + 2) * 8, 256));
   c->cur = 0;
   c->initialised = false;
   c->nstep = 0;
@@ -370,19 +399,48 @@ struct Step2Config {
 #define LBM_CFG2(S, N, F) \
   {S, N, F, {&k_step2<LBM_PERIODIC, N, F>, &k_step2<LBM_DIRICHLET, N, F>}}
 const Step2Config kStep2Configs[] = {
-    LBM_CFG2(0, 0, 1),  LBM_CFG2(4, 0, 1),  LBM_CFG2(6, 0, 1),  LBM_CFG2(8, 0, 1),
-    LBM_CFG2(12, 0, 1), LBM_CFG2(16, 0, 1), LBM_CFG2(24, 0, 1), LBM_CFG2(32, 0, 1),
-    LBM_CFG2(64, 0, 1), LBM_CFG2(32, 1, 1), LBM_CFG2(64, 1, 1), LBM_CFG2(40, 0, 2)};
+    LBM_CFG2(4, 0, 1),  LBM_CFG2(5, 0, 2),  LBM_CFG2(6, 0, 3),  LBM_CFG2(3, 0, 1),
+    LBM_CFG2(8, 0, 1),  LBM_CFG2(12, 0, 1), LBM_CFG2(16, 0, 1), LBM_CFG2(32, 0, 1),
+    LBM_CFG2(0, 0, 1),  LBM_CFG2(4, 1, 1),  LBM_CFG2(8, 1, 1),  LBM_CFG2(64, 1, 1)};
 #undef LBM_CFG2
 constexpr int kNumStep2Configs = (int)(sizeof(kStep2Configs) / sizeof(kStep2Configs[0]));
 static_assert(kNumStep2Configs <= 32, "step2_slots size");
 
-Wall wall_at(const lbm_ctx* c, int64_t step) {
+// Sum the wall velocities of steps step0 .. step0 + n - 1 (n <= WALL_CHUNK)
+// into the context's table; no-op without wall data.
+void eval_walls(lbm_ctx* c, int64_t step0, int n) {
+  if (c->wall_rank == 0 || n <= 0) return;
+  const int L = 2 * (c->g.nx + c->g.ny);
+  const int64_t total = (int64_t)n * L;
+  hipLaunchKernelGGL(k_wall_eval, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, c->stream,
+                     c->wall_W, c->wall_T + step0 * c->wall_rank, c->wall_rank, L, n, c->wall_v);
+}
+
+Wall zero_wall(const lbm_ctx* c) {
   Wall w;
-  w.rank = c->wall_rank;
-  w.W = c->wall_W;
-  w.Trow = c->wall_rank ? c->wall_T + step * c->wall_rank : nullptr;
+  w.rank = 0;
+  w.W = nullptr;
+  w.Trow = nullptr;
   w.L = 2 * (c->g.nx + c->g.ny);
+  return w;
+}
+
+// For timing launches: sum the walls of the current and the next step into
+// the table when the context has wall data for them.
+bool timing_walls(lbm_ctx* c) {
+  if (c->wall_rank == 0 || c->nstep + 2 > c->wall_nsteps) return false;
+  eval_walls(c, c->nstep, 2);
+  return true;
+}
+
+// walls of table entry s (summed by eval_walls); zero velocity without data
+Wall wall_at(const lbm_ctx* c, int s) {
+  Wall w;
+  w.rank = 0;
+  w.W = nullptr;
+  w.Trow = nullptr;
+  w.L = 2 * (c->g.nx + c->g.ny);
+  w.V = c->wall_rank ? c->wall_v + (int64_t)s * w.L * 2 : nullptr;
   return w;
 }
 
@@ -433,20 +491,25 @@ lbm_status lbm_step(lbm_ctx* c, int64_t nsteps) {
   const StepConfig& cfg = kStepConfigs[c->step_cfg];
   const StepConst sc = step_const(cfg, g, (float)c->kK, (float)c->km);
   const StepFn fn = cfg.fn[c->p.bc];
-  int64_t s = 0;
-  if (c->step2_cfg >= 0) {
-    // two time steps per launch
-    for (; s + 1 < nsteps; s += 2) {
-      launch_step2(c, c->step2_cfg, c->buf[c->cur], c->buf[c->cur ^ 1], wall_at(c, c->nstep + s),
-                   wall_at(c, c->nstep + s + 1));
+  // chunks of WALL_CHUNK steps: the chunk's wall velocities are summed first,
+  // then its steps run, two per launch with a two-step variant (the chunks
+  // are even, so only the last step of an odd total runs alone)
+  for (int64_t s0 = 0; s0 < nsteps; s0 += WALL_CHUNK) {
+    const int m = (int)(nsteps - s0 < WALL_CHUNK ? nsteps - s0 : WALL_CHUNK);
+    eval_walls(c, c->nstep + s0, m);
+    int k = 0;
+    if (c->step2_cfg >= 0) {
+      for (; k + 1 < m; k += 2) {
+        launch_step2(c, c->step2_cfg, c->buf[c->cur], c->buf[c->cur ^ 1], wall_at(c, k),
+                     wall_at(c, k + 1));
+        c->cur ^= 1;
+      }
+    }
+    for (; k < m; ++k) {
+      hipLaunchKernelGGL(fn, dim3(sc.ntiles), dim3(cfg.threads), 0, c->stream,
+                         (const float*)c->buf[c->cur], c->buf[c->cur ^ 1], g, sc, wall_at(c, k));
       c->cur ^= 1;
     }
-  }
-  for (; s < nsteps; ++s) {
-    const Wall w = wall_at(c, c->nstep + s);
-    hipLaunchKernelGGL(fn, dim3(sc.ntiles), dim3(cfg.threads), 0, c->stream,
-                       (const float*)c->buf[c->cur], c->buf[c->cur ^ 1], g, sc, w);
-    c->cur ^= 1;
   }
   c->nstep += nsteps;
   return launch_check("k_step launch");
@@ -568,11 +631,10 @@ lbm_status lbm_autotune(lbm_ctx* c, int32_t reps, int32_t use_cache, int32_t* h_
     hipEventDestroy(e0);
     return s;
   }
-  Wall w;
-  w.rank = 0;
-  w.W = nullptr;
-  w.Trow = nullptr;
-  w.L = 2 * (c->g.nx + c->g.ny);
+  // timed with this context's walls at the current step when it has them
+  const bool tw = timing_walls(c);
+  const Wall w = tw ? wall_at(c, 0) : zero_wall(c);
+  const Wall w1 = tw ? wall_at(c, 1) : zero_wall(c);
   int best = -1;
   double best_ms = 1e300;
   for (int i = 0; i < kNumStepConfigs && s == LBM_OK; ++i) {
@@ -599,7 +661,7 @@ lbm_status lbm_autotune(lbm_ctx* c, int32_t reps, int32_t use_cache, int32_t* h_
   for (int i = 0; i < kNumStep2Configs && s == LBM_OK && step2_fits(c->g); ++i) {
     for (int r = 0; r < reps + 2; ++r) {
       if (r == 2) hipEventRecord(e0, c->stream);
-      launch_step2(c, i, c->buf[c->cur], c->buf[c->cur ^ 1], w, w);
+      launch_step2(c, i, c->buf[c->cur], c->buf[c->cur ^ 1], w, w1);
     }
     hipEventRecord(e1, c->stream);
     s = hip_check(hipEventSynchronize(e1), "autotune sync");
@@ -668,14 +730,13 @@ lbm_status lbm_time_step2_config(lbm_ctx* c, int32_t index, int32_t reps, double
     hipEventDestroy(e0);
     return s;
   }
-  Wall w;
-  w.rank = 0;
-  w.W = nullptr;
-  w.Trow = nullptr;
-  w.L = 2 * (c->g.nx + c->g.ny);
+  // timed with this context's walls at the current step when it has them
+  const bool tw = timing_walls(c);
+  const Wall w = tw ? wall_at(c, 0) : zero_wall(c);
+  const Wall w1 = tw ? wall_at(c, 1) : zero_wall(c);
   for (int r = 0; r < reps + 2; ++r) {
     if (r == 2) hipEventRecord(e0, c->stream);
-    launch_step2(c, index, c->buf[c->cur], c->buf[c->cur ^ 1], w, w);
+    launch_step2(c, index, c->buf[c->cur], c->buf[c->cur ^ 1], w, w1);
   }
   hipEventRecord(e1, c->stream);
   s = hip_check(hipEventSynchronize(e1), "timing sync");
@@ -701,11 +762,9 @@ lbm_status lbm_time_step_config(lbm_ctx* c, int32_t index, int32_t reps, double*
     hipEventDestroy(e0);
     return s;
   }
-  Wall w;
-  w.rank = 0;
-  w.W = nullptr;
-  w.Trow = nullptr;
-  w.L = 2 * (c->g.nx + c->g.ny);
+  // timed with this context's walls at the current step when it has them
+  const bool tw = timing_walls(c);
+  const Wall w = tw ? wall_at(c, 0) : zero_wall(c);
   const StepConfig& cfg = kStepConfigs[index];
   const StepConst sc = step_const(cfg, c->g, (float)c->kK, (float)c->km);
   for (int r = 0; r < reps + 2; ++r) {

@@ -33,10 +33,14 @@ struct Wall {
   const float* Trow;  // [rank] time functions of this step
   int rank;
   int L;              // 2 (nx + ny)
+  // [L][2] velocities of this step already summed over the rank (nullptr: sum
+  // W and Trow here); the sum is wall_series below in both cases
+  const float* V = nullptr;
 };
 
-// Wall velocity du_D/dt at link `link` (Eq. bc_ansatz data), separable form.
-__device__ inline void wall_velocity(const Wall& w, int link, float& a, float& b) {
+// Wall velocity du_D/dt at link `link` (Eq. bc_ansatz data), separable form
+// sum_r W[r][link] T[r], accumulated in rank order with FMA.
+__device__ inline void wall_series(const Wall& w, int link, float& a, float& b) {
   a = 0.f;
   b = 0.f;
   for (int r = 0; r < w.rank; ++r) {
@@ -45,6 +49,15 @@ __device__ inline void wall_velocity(const Wall& w, int link, float& a, float& b
     a = fmaf(p[0], t, a);
     b = fmaf(p[1], t, b);
   }
+}
+
+__device__ inline void wall_velocity(const Wall& w, int link, float& a, float& b) {
+  if (w.V) {
+    a = w.V[2 * link];
+    b = w.V[2 * link + 1];
+    return;
+  }
+  wall_series(w, link, a, b);
 }
 
 // Dirichlet rule for a missing population q (direction (i,j)):
