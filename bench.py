@@ -45,8 +45,9 @@ def parse():
     ap.add_argument("--step-configs", default="",
                     help="force single-step launch configurations 'P,D' (periodic, Dirichlet) "
                          "instead of autotuning, e.g. to profile what a timed run chose")
-    ap.add_argument("--step2-configs", default="",
-                    help="with --step-configs: two-step variants 'P,D' (-1 = single steps only)")
+    ap.add_argument("--tblock-configs", default="",
+                    help="with --step-configs: temporally blocked variants 'P,D' (-1 = single "
+                         "steps only)")
     return ap.parse_args()
 
 
@@ -97,20 +98,20 @@ def main():
     cfgs = step_configs()
     tuned = []
     forced = [int(v) for v in args.step_configs.split(",")] if args.step_configs else None
-    forced2 = [int(v) for v in args.step2_configs.split(",")] if args.step2_configs else None
+    forced2 = [int(v) for v in args.tblock_configs.split(",")] if args.tblock_configs else None
     for li, lat in enumerate(lats):
         if forced:
             lat.step_config = forced[li]
-            lat.step2_config = forced2[li] if forced2 else -1
+            lat.tblock_config = forced2[li] if forced2 else -1
         else:
             lat.autotune(reps=10, use_cache=True)
-        idx, idx2 = lat.step_config, lat.step2_config
+        idx, idx2 = lat.step_config, lat.tblock_config
         c = cfgs[idx]
         t = {"lattice": "%dx%d" % (lat.nx, lat.ny), "config": idx, "vec": c["vec"],
              "threads": c["threads"], "nontemporal": c["nontemporal"], "shuffle": c["shuffle"],
-             "step2_config": idx2}
+             "tblock_config": idx2}
         if idx2 >= 0:
-            t["step2"] = lat.step2_configs()[idx2]
+            t["tblock"] = lat.tblock_configs()[idx2]
         tuned.append(t)
     log("autotuned: %s" % tuned)
     for lat in lats:
@@ -139,26 +140,30 @@ def main():
     # Its average launch duration comes from the periodic part of the timed
     # region (HIP events on the stream the kernels run on).  Algorithmic bytes
     # per launch: every node's 20 FP32 populations read once and written once
-    # (160 B per node), for one time step (k_step) or two (k_step2).
+    # (160 B per node), for one time step (k_step) or T (k_tblock).
     per_lat = lats[0]
-    two = tuned[0]["step2_config"] >= 0
+    blocked = tuned[0]["tblock_config"] >= 0
+    T = tuned[0]["tblock"]["steps"] if blocked else 1
     per_ms = ev[0].elapsed_time(ev[1])
-    launches = K // 2 + K % 2 if two else K
-    kern_ms = per_ms / (K / 2.0 if two else K)   # an odd trailing single step counts half
+    # lbm_step runs chunks of 420 steps, T per launch; leftover steps one at a time
+    launches = (K // 420) * (420 // T) + (K % 420) // T if blocked else K
+    single_left = K - launches * T if blocked else 0
+    kern_ms = per_ms / (launches + single_left / T)   # a single step counts 1/T of a launch
     alg_bytes = BYTES_PER_LUP * per.nx * per.ny
     achieved = alg_bytes / (kern_ms * 1e-3) / 1e9
-    kname = "k_step2" if two else "k_step"
+    kname = "k_tblock" if blocked else "k_step"
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": measured_traffic(kname),
                 "kernel": "%s (periodic 4096x4096, %s)" % (
-                    kname, ("two-step variant %d" % tuned[0]["step2_config"]) if two
+                    kname, ("blocked variant %d, %d steps per launch"
+                            % (tuned[0]["tblock_config"], T)) if blocked
                     else ("config %d" % tuned[0]["config"])),
                 "kernel_ms": round(kern_ms, 5), "launches": launches,
-                "steps_per_launch": 2 if two else 1,
-                "kernel_glups": round((2 if two else 1) * per.nx * per.ny / kern_ms / 1e6, 2),
+                "steps_per_launch": T,
+                "kernel_glups": round(T * per.nx * per.ny / kern_ms / 1e6, 2),
                 "algorithmic_bytes_per_launch": alg_bytes}
-    if two:
+    if blocked:
         # the best single-step kernel on the same lattice, for comparison: its
         # bandwidth fraction is the kernel-quality figure of the one-step form
         ms1 = per_lat.time_step_config(tuned[0]["config"], reps=50)

@@ -115,7 +115,7 @@ lbm_status lbm_set_populations(lbm_ctx* ctx, const float* d_f);
  * Steps beyond nsteps are rejected by lbm_step.  The source rows 3-5 use
  * c_K/c and c_mu/c (the leading-order bounce-back balance, Eq. bb0, carries
  * the 1/c of the equilibrium; the printed speeds coincide only for c = 1).
- * lbm_step sums the series for chunks of up to 64 steps into a table inside
+ * lbm_step sums the series for chunks of up to 420 steps into a table inside
  * the workspace (one small launch per chunk, FMA in rank order), so the step
  * kernels read one velocity per wall link.  Pointers are kept (not copied)
  * and must stay valid while stepping. */
@@ -180,27 +180,32 @@ lbm_status lbm_set_step_config(lbm_ctx* ctx, int32_t index);
 lbm_status lbm_autotune(lbm_ctx* ctx, int32_t reps, int32_t use_cache, int32_t* h_index,
                         double* h_ms);
 
-/* ---- two time steps per launch (temporal blocking) --------------------------
- * A wave owns a strip of 64 columns and sweeps a segment of rows, forming the
- * intermediate time level in registers, so a pair of steps reads and writes
- * the populations once (80 B + 80 B per node for two updates).  Bitwise
- * identical to two single steps.  Variants differ in rows per segment and
- * store type and rows prefetched ahead (h_prefetch); h_seg_rows 0 means the
- * segment length is chosen at launch so that one wave per resident slot
- * covers the grid.  index -1 disables it;
- * lbm_autotune selects it when it is faster per step than the best
- * single-step configuration.  With it enabled lbm_step(n) runs n/2 two-step
- * launches and, for odd n, one single step.  Grids whose row byte offsets
- * ((19 planes + one row) * 4 B) reach 2^31 cannot use it: setting or timing a
- * variant then fails with LBM_E_ARG and the autotuner skips it.  Any output
- * pointer may be NULL. */
-int32_t lbm_step2_config_count(void);
-lbm_status lbm_step2_config_info(int32_t index, int32_t* h_seg_rows, int32_t* h_nontemporal,
-                                 int32_t* h_prefetch);
-lbm_status lbm_get_step2_config(const lbm_ctx* ctx, int32_t* h_index);
-lbm_status lbm_set_step2_config(lbm_ctx* ctx, int32_t index);
-/* Average duration (ms) of one two-step launch (state-preserving, synchronises). */
-lbm_status lbm_time_step2_config(lbm_ctx* ctx, int32_t index, int32_t reps, double* h_ms);
+/* ---- several time steps per launch (temporal blocking) ----------------------
+ * The scheme's update of a node needs only its four neighbours (pull
+ * streaming, Eq. streaming, then the local collision, Eq. collision), so T
+ * consecutive steps of a row need rows within distance T of the previous
+ * state.  A wave owns a strip of 64 columns and sweeps a segment of rows,
+ * forming the T - 1 intermediate time levels in registers, so T steps read and
+ * write the populations once (80 B + 80 B per node for T updates).  Bitwise
+ * identical to T single steps.  Variants (h_steps = T in 2..7) differ in rows
+ * per segment, store type and rows prefetched ahead (h_prefetch); h_seg_rows
+ * 0 means the segment length is chosen at launch so that one wave per
+ * resident slot covers the grid.  index -1 disables blocking; lbm_autotune
+ * selects a variant when it is faster per step than the best single-step
+ * configuration.  With a variant of T steps enabled, lbm_step(n) runs the
+ * steps in chunks of 420 (a multiple of every T offered), T per launch, and
+ * only the last (n mod 420) mod T steps one at a time.  Grids whose row byte
+ * offsets ((19 planes + one row) * 4 B) reach 2^31 cannot use it: setting or
+ * timing a variant then fails with LBM_E_ARG and the autotuner skips it.  Any
+ * output pointer may be NULL. */
+int32_t lbm_tblock_config_count(void);
+lbm_status lbm_tblock_config_info(int32_t index, int32_t* h_steps, int32_t* h_seg_rows,
+                                  int32_t* h_nontemporal, int32_t* h_prefetch);
+lbm_status lbm_get_tblock_config(const lbm_ctx* ctx, int32_t* h_index);
+lbm_status lbm_set_tblock_config(lbm_ctx* ctx, int32_t index);
+/* Average duration (ms) of one launch of blocked variant `index` (T steps;
+ * state-preserving, synchronises). */
+lbm_status lbm_time_tblock_config(lbm_ctx* ctx, int32_t index, int32_t reps, double* h_ms);
 
 /* Average duration (ms) of one step launch of configuration `index` on this
  * context (same state-preserving scheme as lbm_autotune).  Synchronises. */

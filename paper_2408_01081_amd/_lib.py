@@ -53,12 +53,13 @@ SIGNATURES = [
     ("lbm_autotune", ctypes.c_int, [_VP, _I32, _I32, ctypes.POINTER(_I32), _PD]),
     ("lbm_time_step_config", ctypes.c_int, [_VP, _I32, _I32, _PD]),
     ("lbm_copy_f32", ctypes.c_int, [_VP, _VP, _I64, _VP]),
-    ("lbm_step2_config_count", _I32, []),
-    ("lbm_step2_config_info", ctypes.c_int,
-     [_I32, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
-    ("lbm_get_step2_config", ctypes.c_int, [_VP, ctypes.POINTER(_I32)]),
-    ("lbm_set_step2_config", ctypes.c_int, [_VP, _I32]),
-    ("lbm_time_step2_config", ctypes.c_int, [_VP, _I32, _I32, _PD]),
+    ("lbm_tblock_config_count", _I32, []),
+    ("lbm_tblock_config_info", ctypes.c_int,
+     [_I32, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32),
+      ctypes.POINTER(_I32)]),
+    ("lbm_get_tblock_config", ctypes.c_int, [_VP, ctypes.POINTER(_I32)]),
+    ("lbm_set_tblock_config", ctypes.c_int, [_VP, _I32]),
+    ("lbm_time_tblock_config", ctypes.c_int, [_VP, _I32, _I32, _PD]),
     ("lbm_batch_workspace_bytes", ctypes.c_size_t, [_I32, _VP]),
     ("lbm_batch_create", ctypes.c_int, [_I32, _VP, _VP, ctypes.c_size_t, _VP,
                                         ctypes.POINTER(_VP)]),

@@ -25,7 +25,7 @@
 #include "lbm.h"
 #include "lbm_kernels.hpp"
 #include "lbm_step.hpp"
-#include "lbm_step2.hpp"
+#include "lbm_tblock.hpp"
 #include "lbm_init.hpp"
 #include "lbm_host.hpp"
 
@@ -220,24 +220,26 @@ struct lbm_ctx {
   int64_t wall_nsteps;
   int device;
   int step_cfg;   // index into kStepConfigs
-  int step2_cfg;  // index into kStep2Configs, or -1 (single steps only)
-  int step2_slots[32];  // resident waves of a two-step variant on this device (0: not known)
+  int tb_cfg;         // index into kTBConfigs, or -1 (single steps only)
+  int tb_slots[64];   // resident waves of a blocked variant on this device (0: not known)
   float* wall_v;        // [WALL_CHUNK][2 (nx + ny)][2] wall velocities of upcoming steps
 };
 
 namespace {
 
-// steps whose wall velocities are summed ahead in one launch (even, so that
-// two-step launches pair steps inside a chunk)
-constexpr int WALL_CHUNK = 64;
+// steps whose wall velocities are summed ahead in one launch (a multiple of
+// every blocked variant's step count, so blocked launches fill a chunk)
+constexpr int WALL_CHUNK = 420;
 
-size_t wall_table_bytes(const Grid& g) {
+// the wall-velocity table exists for Dirichlet lattices only
+size_t wall_table_bytes(const Grid& g, int bc) {
+  if (bc != LBM_DIRICHLET) return 0;
   return (size_t)round_up((int64_t)WALL_CHUNK * 2 * (g.nx + g.ny) * 2 * 4, 256);
 }
 
-size_t ws_bytes(const Grid& g) {
+size_t ws_bytes(const Grid& g, int bc) {
   return 2 * state_bytes(g) + (size_t)round_up((2 * RED_BLOCKS + 2) * 8, 256) +
-         wall_table_bytes(g);
+         wall_table_bytes(g, bc);
 }
 
 // V[s][link][2] = wall velocity of step `step0 + s` at every link
@@ -286,7 +288,7 @@ const char* lbm_last_error(void) { return g_err.c_str(); }
 size_t lbm_workspace_bytes(const lbm_params* p) {
   Derived d;
   if (derive(p, &d) != LBM_OK) return 0;
-  return ws_bytes(make_grid(p));
+  return ws_bytes(make_grid(p), p->bc);
 }
 
 lbm_status lbm_create(const lbm_params* p, void* d_ws, size_t ws_size, void* hip_stream,
@@ -298,7 +300,7 @@ lbm_status lbm_create(const lbm_params* p, void* d_ws, size_t ws_size, void* hip
   if (!d_ws) return fail(LBM_E_ARG, "null workspace");
   if (((uintptr_t)d_ws & 255) != 0) return fail(LBM_E_ARG, "workspace not 256-byte aligned");
   const Grid g = make_grid(p);
-  if (ws_size < ws_bytes(g)) return fail(LBM_E_SPACE, "workspace too small");
+  if (ws_size < ws_bytes(g, p->bc)) return fail(LBM_E_SPACE, "workspace too small");
   NormConst nc;
   if (!norm_weights(d.kK, d.km, nc.k)) return fail(LBM_E_CFL, "g_ij not positive definite");
   lbm_ctx* c = new (std::nothrow) lbm_ctx();
@@ -309,8 +311,10 @@ lbm_status lbm_create(const lbm_params* p, void* d_ws, size_t ws_size, void* hip
   c->buf[0] = (float*)d_ws;
   c->buf[1] = (float*)((char*)d_ws + state_bytes(g));
   c->partial = (double*)((char*)d_ws + 2 * state_bytes(g));
-  c->wall_v = (float*)((char*)d_ws + 2 * state_bytes(g) +
-                       (size_t)round_up((2 * RED_BLOCKS + 2) * 8, 256));
+  c->wall_v = p->bc == LBM_DIRICHLET
+                  ? (float*)((char*)d_ws + 2 * state_bytes(g) +
+                             (size_t)round_up((2 * RED_BLOCKS + 2) * 8, 256))
+                  : nullptr;
   c->cur = 0;
   c->initialised = false;
   c->nstep = 0;
@@ -325,7 +329,7 @@ lbm_status lbm_create(const lbm_params* p, void* d_ws, size_t ws_size, void* hip
   c->wall_nsteps = 0;
   hipGetDevice(&c->device);
   c->step_cfg = default_step_config(g.nx);
-  c->step2_cfg = -1;
+  c->tb_cfg = -1;
   *out = c;
   g_err.clear();
   return LBM_OK;
@@ -389,22 +393,26 @@ int64_t lbm_step_count(const lbm_ctx* c) { return c ? c->nstep : -1; }
 
 namespace {
 
-typedef void (*Step2Fn)(const float*, float*, Grid, Step2Const, Wall, Wall);
-// seg_rows 0: as many rows per segment as fill the device with one wave per
-// resident slot (one round of waves, no tail), rounded up to the ring length
-struct Step2Config {
-  int seg_rows, nt, pf;
-  Step2Fn fn[2];
+typedef void (*TBFn)(const float*, float*, Grid, TBConst, WallSeq);
+// Temporally blocked variants: T steps per launch, output rows per segment
+// (0: as many as fill the device with one wave per resident slot, rounded up
+// to the ring length), nontemporal stores, rows prefetched ahead.
+struct TBConfig {
+  int steps, seg_rows, nt, pf;
+  TBFn fn[2];
 };
-#define LBM_CFG2(S, N, F) \
-  {S, N, F, {&k_step2<LBM_PERIODIC, N, F>, &k_step2<LBM_DIRICHLET, N, F>}}
-const Step2Config kStep2Configs[] = {
-    LBM_CFG2(4, 0, 1),  LBM_CFG2(5, 0, 2),  LBM_CFG2(6, 0, 3),  LBM_CFG2(3, 0, 1),
-    LBM_CFG2(8, 0, 1),  LBM_CFG2(12, 0, 1), LBM_CFG2(16, 0, 1), LBM_CFG2(32, 0, 1),
-    LBM_CFG2(0, 0, 1),  LBM_CFG2(4, 1, 1),  LBM_CFG2(8, 1, 1),  LBM_CFG2(64, 1, 1)};
-#undef LBM_CFG2
-constexpr int kNumStep2Configs = (int)(sizeof(kStep2Configs) / sizeof(kStep2Configs[0]));
-static_assert(kNumStep2Configs <= 32, "step2_slots size");
+#define LBM_TB(T, S, N, F) \
+  {T, S, N, F, {&k_tblock<LBM_PERIODIC, N, F, T>, &k_tblock<LBM_DIRICHLET, N, F, T>}}
+const TBConfig kTBConfigs[] = {
+    LBM_TB(2, 4, 0, 1),  LBM_TB(2, 4, 1, 1),  LBM_TB(2, 8, 0, 1),  LBM_TB(2, 0, 0, 1),
+    LBM_TB(3, 4, 0, 1),  LBM_TB(3, 5, 0, 2),  LBM_TB(3, 4, 1, 1),  LBM_TB(3, 8, 1, 1),
+    LBM_TB(4, 4, 0, 1),  LBM_TB(4, 8, 0, 1),  LBM_TB(4, 4, 1, 1),  LBM_TB(4, 8, 1, 1),
+    LBM_TB(4, 12, 1, 1), LBM_TB(5, 16, 0, 1), LBM_TB(5, 32, 0, 1), LBM_TB(5, 16, 1, 1),
+    LBM_TB(6, 16, 0, 1), LBM_TB(6, 32, 0, 1), LBM_TB(6, 48, 0, 1), LBM_TB(6, 16, 1, 1),
+    LBM_TB(7, 32, 0, 1), LBM_TB(7, 48, 0, 1), LBM_TB(7, 64, 0, 1), LBM_TB(7, 32, 1, 1)};
+#undef LBM_TB
+constexpr int kNumTBConfigs = (int)(sizeof(kTBConfigs) / sizeof(kTBConfigs[0]));
+static_assert(kNumTBConfigs <= 64, "tb_slots size");
 
 // Sum the wall velocities of steps step0 .. step0 + n - 1 (n <= WALL_CHUNK)
 // into the context's table; no-op without wall data.
@@ -425,11 +433,11 @@ Wall zero_wall(const lbm_ctx* c) {
   return w;
 }
 
-// For timing launches: sum the walls of the current and the next step into
-// the table when the context has wall data for them.
-bool timing_walls(lbm_ctx* c) {
-  if (c->wall_rank == 0 || c->nstep + 2 > c->wall_nsteps) return false;
-  eval_walls(c, c->nstep, 2);
+// For timing launches: sum the walls of the next `n` steps into the table
+// when the context has wall data for them.
+bool timing_walls(lbm_ctx* c, int n = 4) {
+  if (c->wall_rank == 0 || c->nstep + n > c->wall_nsteps) return false;
+  eval_walls(c, c->nstep, n);
   return true;
 }
 
@@ -444,10 +452,17 @@ Wall wall_at(const lbm_ctx* c, int s) {
   return w;
 }
 
-int step2_seg_rows(lbm_ctx* c, int index) {
-  const Step2Config& k = kStep2Configs[index];
+WallSeq walls_from(const lbm_ctx* c, int s, bool with_walls) {
+  WallSeq ws;
+  ws.L = 2 * (c->g.nx + c->g.ny);
+  ws.V = with_walls && c->wall_rank ? c->wall_v + (int64_t)s * ws.L * 2 : nullptr;
+  return ws;
+}
+
+int tb_seg_rows(lbm_ctx* c, int index) {
+  const TBConfig& k = kTBConfigs[index];
   if (k.seg_rows > 0) return k.seg_rows;
-  int& slots = c->step2_slots[index];
+  int& slots = c->tb_slots[index];
   if (slots == 0) {
     int per_cu = 0, cus = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k.fn[c->p.bc], 256,
@@ -462,7 +477,8 @@ int step2_seg_rows(lbm_ctx* c, int index) {
     slots = per_cu * 4 * cus;
   }
   const int ring = 3 + k.pf;
-  const int nstrips = (c->g.nx + S2_VALID - 1) / S2_VALID;
+  const int valid = TB_LANES - 2 * k.steps;
+  const int nstrips = (c->g.nx + valid - 1) / valid;
   int nseg = slots / nstrips;
   if (nseg < 1) nseg = 1;
   int rows = (c->g.ny + nseg - 1) / nseg;
@@ -470,13 +486,14 @@ int step2_seg_rows(lbm_ctx* c, int index) {
   return rows;
 }
 
-void launch_step2(lbm_ctx* c, int index, const float* src, float* dst, const Wall& w0,
-                  const Wall& w1) {
-  const Step2Config& k = kStep2Configs[index];
-  const Step2Const sc = step2_const(c->g, (float)c->kK, (float)c->km, step2_seg_rows(c, index));
+// one launch of variant `index`: kTBConfigs[index].steps steps, level l with
+// the walls of table entry s0 + l - 1
+void launch_tb(lbm_ctx* c, int index, const float* src, float* dst, const WallSeq& ws) {
+  const TBConfig& k = kTBConfigs[index];
+  const TBConst sc = tblock_const(c->g, (float)c->kK, (float)c->km, tb_seg_rows(c, index), k.steps);
   const int ntiles = sc.nstrips * sc.nseg;
   hipLaunchKernelGGL(k.fn[c->p.bc], dim3((unsigned)((ntiles + 3) / 4)), dim3(256), 0, c->stream,
-                     src, dst, c->g, sc, w0, w1);
+                     src, dst, c->g, sc, ws);
 }
 
 }  // namespace
@@ -492,16 +509,17 @@ lbm_status lbm_step(lbm_ctx* c, int64_t nsteps) {
   const StepConst sc = step_const(cfg, g, (float)c->kK, (float)c->km);
   const StepFn fn = cfg.fn[c->p.bc];
   // chunks of WALL_CHUNK steps: the chunk's wall velocities are summed first,
-  // then its steps run, two per launch with a two-step variant (the chunks
-  // are even, so only the last step of an odd total runs alone)
+  // then its steps run, T per launch with a blocked variant (WALL_CHUNK is a
+  // multiple of every T in the table, so only the last T-1 steps or fewer of
+  // a total run one at a time)
+  const int T = c->tb_cfg >= 0 ? kTBConfigs[c->tb_cfg].steps : 1;
   for (int64_t s0 = 0; s0 < nsteps; s0 += WALL_CHUNK) {
     const int m = (int)(nsteps - s0 < WALL_CHUNK ? nsteps - s0 : WALL_CHUNK);
     eval_walls(c, c->nstep + s0, m);
     int k = 0;
-    if (c->step2_cfg >= 0) {
-      for (; k + 1 < m; k += 2) {
-        launch_step2(c, c->step2_cfg, c->buf[c->cur], c->buf[c->cur ^ 1], wall_at(c, k),
-                     wall_at(c, k + 1));
+    if (T > 1) {
+      for (; k + T <= m; k += T) {
+        launch_tb(c, c->tb_cfg, c->buf[c->cur], c->buf[c->cur ^ 1], walls_from(c, k, true));
         c->cur ^= 1;
       }
     }
@@ -542,7 +560,7 @@ int find_config(int vec, int threads, int nt, int xmode) {
 }
 
 // Cache file (path in LBM_AUTOTUNE_CACHE): one line per tuned shape,
-// "nx ny bc vec threads nt xmode step2 ms" (step2 = two-step variant or -1).
+// "nx ny bc vec threads nt xmode tb ms" (tb = blocked variant or -1).
 // Caller holds g_tune_mu.
 void load_tune_file() {
   if (g_tune_file_loaded) return;
@@ -556,7 +574,7 @@ void load_tune_file() {
   while (fscanf(f, "%d %d %d %d %d %d %d %d %lf", &nx, &ny, &bc, &vec, &th, &nt, &xm, &s2,
                 &ms) == 9) {
     const int i = find_config(vec, th, nt, xm);
-    if (i >= 0 && step_config_valid(i, nx) && s2 >= -1 && s2 < 64)
+    if (i >= 0 && step_config_valid(i, nx) && s2 >= -1 && s2 < kNumTBConfigs)
       g_tune_cache[TuneKey{nx, ny, bc}] = TuneVal{i, s2};
   }
   fclose(f);
@@ -614,8 +632,7 @@ lbm_status lbm_autotune(lbm_ctx* c, int32_t reps, int32_t use_cache, int32_t* h_
     auto it = g_tune_cache.find(key);
     if (it != g_tune_cache.end()) {
       c->step_cfg = it->second.cfg;
-      c->step2_cfg =
-          it->second.cfg2 < kNumStep2Configs && step2_fits(c->g) ? it->second.cfg2 : -1;
+      c->tb_cfg = it->second.cfg2 < kNumTBConfigs && tblock_fits(c->g) ? it->second.cfg2 : -1;
       if (h_index) *h_index = it->second.cfg;
       if (h_ms) *h_ms = -1.0;
       return LBM_OK;
@@ -634,7 +651,7 @@ lbm_status lbm_autotune(lbm_ctx* c, int32_t reps, int32_t use_cache, int32_t* h_
   // timed with this context's walls at the current step when it has them
   const bool tw = timing_walls(c);
   const Wall w = tw ? wall_at(c, 0) : zero_wall(c);
-  const Wall w1 = tw ? wall_at(c, 1) : zero_wall(c);
+  const WallSeq ws = walls_from(c, 0, tw);
   int best = -1;
   double best_ms = 1e300;
   for (int i = 0; i < kNumStepConfigs && s == LBM_OK; ++i) {
@@ -655,20 +672,21 @@ lbm_status lbm_autotune(lbm_ctx* c, int32_t reps, int32_t use_cache, int32_t* h_
       best = i;
     }
   }
-  // two-step variants: time per step = time per launch / 2
+  // blocked variants: time per step = time per launch / steps per launch
   int best2 = -1;
   double best2_ms = 1e300;
-  for (int i = 0; i < kNumStep2Configs && s == LBM_OK && step2_fits(c->g); ++i) {
+  for (int i = 0; i < kNumTBConfigs && s == LBM_OK && tblock_fits(c->g); ++i) {
     for (int r = 0; r < reps + 2; ++r) {
       if (r == 2) hipEventRecord(e0, c->stream);
-      launch_step2(c, i, c->buf[c->cur], c->buf[c->cur ^ 1], w, w1);
+      launch_tb(c, i, c->buf[c->cur], c->buf[c->cur ^ 1], ws);
     }
     hipEventRecord(e1, c->stream);
     s = hip_check(hipEventSynchronize(e1), "autotune sync");
     float ms = 0.f;
     if (s == LBM_OK) s = hip_check(hipEventElapsedTime(&ms, e0, e1), "autotune timing");
-    if (s == LBM_OK && ms / reps / 2 < best2_ms) {
-      best2_ms = ms / reps / 2;
+    const double per = (double)ms / reps / kTBConfigs[i].steps;
+    if (s == LBM_OK && per < best2_ms) {
+      best2_ms = per;
       best2 = i;
     }
   }
@@ -677,50 +695,53 @@ lbm_status lbm_autotune(lbm_ctx* c, int32_t reps, int32_t use_cache, int32_t* h_
   if (s) return s;
   if (best < 0) return fail(LBM_E_ARG, "no valid launch configuration");
   c->step_cfg = best;
-  c->step2_cfg = best2_ms < best_ms ? best2 : -1;
+  c->tb_cfg = best2_ms < best_ms ? best2 : -1;
   const double per_step = best2_ms < best_ms ? best2_ms : best_ms;
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     load_tune_file();
-    g_tune_cache[key] = TuneVal{best, c->step2_cfg};
-    append_tune_file(key, TuneVal{best, c->step2_cfg}, per_step);
+    g_tune_cache[key] = TuneVal{best, c->tb_cfg};
+    append_tune_file(key, TuneVal{best, c->tb_cfg}, per_step);
   }
   if (h_index) *h_index = best;
   if (h_ms) *h_ms = per_step;
   return LBM_OK;
 }
 
-int32_t lbm_step2_config_count(void) { return kNumStep2Configs; }
+int32_t lbm_tblock_config_count(void) { return kNumTBConfigs; }
 
-lbm_status lbm_step2_config_info(int32_t index, int32_t* seg_rows, int32_t* nt, int32_t* pf) {
-  if (index < 0 || index >= kNumStep2Configs) return fail(LBM_E_ARG, "config index out of range");
-  if (seg_rows) *seg_rows = kStep2Configs[index].seg_rows;
-  if (nt) *nt = kStep2Configs[index].nt;
-  if (pf) *pf = kStep2Configs[index].pf;
+lbm_status lbm_tblock_config_info(int32_t index, int32_t* steps, int32_t* seg_rows, int32_t* nt,
+                                  int32_t* pf) {
+  if (index < 0 || index >= kNumTBConfigs) return fail(LBM_E_ARG, "config index out of range");
+  const TBConfig& k = kTBConfigs[index];
+  if (steps) *steps = k.steps;
+  if (seg_rows) *seg_rows = k.seg_rows;
+  if (nt) *nt = k.nt;
+  if (pf) *pf = k.pf;
   return LBM_OK;
 }
 
-lbm_status lbm_get_step2_config(const lbm_ctx* c, int32_t* index) {
+lbm_status lbm_get_tblock_config(const lbm_ctx* c, int32_t* index) {
   if (!c || !index) return fail(LBM_E_ARG, "null argument");
-  *index = c->step2_cfg;
+  *index = c->tb_cfg;
   return LBM_OK;
 }
 
-lbm_status lbm_set_step2_config(lbm_ctx* c, int32_t index) {
+lbm_status lbm_set_tblock_config(lbm_ctx* c, int32_t index) {
   if (!c) return fail(LBM_E_ARG, "null ctx");
-  if (index < -1 || index >= kNumStep2Configs) return fail(LBM_E_ARG, "config index out of range");
-  if (index >= 0 && !step2_fits(c->g))
-    return fail(LBM_E_ARG, "grid too wide for the two-step kernel (row offsets exceed 2^31 B)");
-  c->step2_cfg = index;
+  if (index < -1 || index >= kNumTBConfigs) return fail(LBM_E_ARG, "config index out of range");
+  if (index >= 0 && !tblock_fits(c->g))
+    return fail(LBM_E_ARG, "grid too wide for the blocked kernel (row offsets exceed 2^31 B)");
+  c->tb_cfg = index;
   return LBM_OK;
 }
 
-lbm_status lbm_time_step2_config(lbm_ctx* c, int32_t index, int32_t reps, double* h_ms) {
+lbm_status lbm_time_tblock_config(lbm_ctx* c, int32_t index, int32_t reps, double* h_ms) {
   if (!c || !h_ms) return fail(LBM_E_ARG, "null argument");
   if (!c->initialised) return fail(LBM_E_STATE, "not initialised");
-  if (index < 0 || index >= kNumStep2Configs) return fail(LBM_E_ARG, "invalid configuration");
-  if (!step2_fits(c->g))
-    return fail(LBM_E_ARG, "grid too wide for the two-step kernel (row offsets exceed 2^31 B)");
+  if (index < 0 || index >= kNumTBConfigs) return fail(LBM_E_ARG, "invalid configuration");
+  if (!tblock_fits(c->g))
+    return fail(LBM_E_ARG, "grid too wide for the blocked kernel (row offsets exceed 2^31 B)");
   if (reps < 1) return fail(LBM_E_ARG, "reps must be >= 1");
   hipEvent_t e0, e1;
   lbm_status s = hip_check(hipEventCreate(&e0), "event");
@@ -731,12 +752,10 @@ lbm_status lbm_time_step2_config(lbm_ctx* c, int32_t index, int32_t reps, double
     return s;
   }
   // timed with this context's walls at the current step when it has them
-  const bool tw = timing_walls(c);
-  const Wall w = tw ? wall_at(c, 0) : zero_wall(c);
-  const Wall w1 = tw ? wall_at(c, 1) : zero_wall(c);
+  const WallSeq ws = walls_from(c, 0, timing_walls(c));
   for (int r = 0; r < reps + 2; ++r) {
     if (r == 2) hipEventRecord(e0, c->stream);
-    launch_step2(c, index, c->buf[c->cur], c->buf[c->cur ^ 1], w, w1);
+    launch_tb(c, index, c->buf[c->cur], c->buf[c->cur ^ 1], ws);
   }
   hipEventRecord(e1, c->stream);
   s = hip_check(hipEventSynchronize(e1), "timing sync");

@@ -1,0 +1,286 @@
+// T time steps per pass over HBM (temporal blocking in registers).
+//
+// One wave owns a strip of 64 consecutive columns and sweeps a segment of
+// output rows.  Level 0 is the post-collision state f*(t_n) read from memory;
+// level l (1 <= l <= T) is f*(t_{n+l}).  At sub-iteration i of the sweep
+// (output row y0 + i) the wave
+//   loads   level 0 row y0 + i + T + PF      (PF rows ahead of its use),
+//   forms   level l row y0 + i + T - l       (l = 1 .. T) from level l-1 rows
+//           y0 + i + T - l - 1 .. y0 + i + T - l + 1,
+//   stores  level T row y0 + i.
+// Only level T goes back to memory: 80 B read + 80 B written per node for T
+// node updates.
+//   x neighbours: one-lane DPP wave shifts; lane edges lose one exact column
+//     per level, so level T is exact on lanes T .. 63-T: strips overlap by 2T
+//     columns and store 64 - 2T columns;
+//   y neighbours: rows kept in registers.  Level l needs rows from
+//     sub-iterations i-2 .. i of level l-1, so every level is a ring of
+//     3 + PF slots holding the row of sub-iteration i in slot i mod (3 + PF);
+//     the sweep is unrolled by the ring length, so slots rotate by renaming
+//     and a row is never copied between registers (the wait for a prefetched
+//     row sits at its first use).  Before the first output row, 2T
+//     sub-iterations fill the pipeline, each computing only the levels whose
+//     rows the segment needs.
+// Rows are addressed with buffer instructions: a wave-uniform resource per row
+// (scalar registers), the plane offset as scalar offset and the column as
+// 32-bit lane offset.  Lanes that must not store give an offset beyond the
+// resource's range, which the hardware drops: stores need no branch, so the
+// wait counts stay exact.
+// Walls (Dirichlet) are applied at every level with the velocities of that
+// level's step.  Every node update is collide() on the same inputs as the
+// single-step kernel, so the result is bitwise identical to T launches of it.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lbm.h"
+#include "lbm_kernels.hpp"
+#include "lbm_step.hpp"
+
+namespace lbmk {
+
+constexpr int TB_LANES = 64;
+
+struct TBConst {
+  float kK, km;
+  int nstrips;   // strips across a row
+  int seg_rows;  // output rows per segment
+  int nseg;      // segments along y
+  int plane4;    // bytes between planes
+  int extent;    // bytes one row's resource covers: (NP - 1) planes + one row
+};
+
+// Wall velocities of the launch's steps: level l uses table V + (l-1) * 2L
+// (nullptr: walls at rest).
+struct WallSeq {
+  const float* V;
+  int L;  // 2 (nx + ny)
+};
+
+constexpr int TB_RSRC_WORD3 = 0x00020000;  // raw 32-bit buffer access (gfx9 family)
+constexpr int TB_DROP = (int)0x80000000u;  // lane offset beyond every row's range
+
+__device__ inline int wrap_mod(int x, int n) {
+  int r = x % n;
+  return r < 0 ? r + n : r;
+}
+
+// row actually read for sweep row y (uniform): periodic wrap or wall clamp
+template <int BC>
+__device__ inline int row_index(int y, int ny) {
+  if (BC == LBM_PERIODIC) {
+    while (y < 0) y += ny;
+    while (y >= ny) y -= ny;
+    return y;
+  }
+  return y < 0 ? 0 : (y >= ny ? ny - 1 : y);
+}
+
+// value held by lane - 1 (wave_shr:1) and by lane + 1 (wave_shl:1); the
+// lane without a source reads 0 (bound control), and its result is never
+// stored
+__device__ inline float from_lane_below(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x138, 0xf, 0xf, true));
+}
+__device__ inline float from_lane_above(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x130, 0xf, 0xf, true));
+}
+
+// one level-update of row y at this lane's column x from the rows below,
+// at and above (post-collision values of the previous level)
+template <int BC>
+__device__ inline void level_update(const float below[NP], const float at[NP],
+                                    const float above[NP], int x, int y, int nx, int ny,
+                                    float kK, float km, const Wall& w, float out[NP]) {
+  float f[NQ][NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    f[0][c] = from_lane_below(at[0 * NC + c]);  // f*_0 from x - 1
+    f[1][c] = below[1 * NC + c];
+    f[2][c] = from_lane_above(at[2 * NC + c]);  // f*_2 from x + 1
+    f[3][c] = above[3 * NC + c];
+  }
+  if (BC == LBM_DIRICHLET) {
+    float fb[NC], va, vb;
+    if (x == 0) {
+      for (int c = 0; c < NC; ++c) fb[c] = at[2 * NC + c];
+      wall_velocity(w, y, va, vb);
+      wall_rule(1, 0, kK, km, va, vb, fb, f[0]);
+    }
+    if (x == nx - 1) {
+      for (int c = 0; c < NC; ++c) fb[c] = at[0 * NC + c];
+      wall_velocity(w, ny + y, va, vb);
+      wall_rule(-1, 0, kK, km, va, vb, fb, f[2]);
+    }
+    if (y == 0) {
+      for (int c = 0; c < NC; ++c) fb[c] = at[3 * NC + c];
+      wall_velocity(w, 2 * ny + x, va, vb);
+      wall_rule(0, 1, kK, km, va, vb, fb, f[1]);
+    }
+    if (y == ny - 1) {
+      for (int c = 0; c < NC; ++c) fb[c] = at[1 * NC + c];
+      wall_velocity(w, 2 * ny + nx + x, va, vb);
+      wall_rule(0, -1, kK, km, va, vb, fb, f[3]);
+    }
+  }
+  collide(kK, km, f);
+#pragma unroll
+  for (int q = 0; q < NQ; ++q)
+#pragma unroll
+    for (int c = 0; c < NC; ++c) out[q * NC + c] = f[q][c];
+}
+
+// Per-lane constants of one wave's strip.
+struct Strip {
+  int xw;   // column for the wall tests (-2 for lanes outside the grid)
+  int xr4;  // byte offset of the column this lane reads
+  int xs4;  // byte offset of the column this lane stores, or TB_DROP
+};
+
+template <int BC>
+__device__ inline void load_row(const float* __restrict__ src, const Grid& g, const TBConst& sc,
+                                const Strip& st, int y, float v[NP]) {
+  const float* rp = src + (int64_t)row_index<BC>(y, g.ny) * g.pitch;
+  const __amdgpu_buffer_rsrc_t rs =
+      __builtin_amdgcn_make_buffer_rsrc((void*)rp, (short)0, sc.extent, TB_RSRC_WORD3);
+#pragma unroll
+  for (int k = 0; k < NP; ++k)
+    v[k] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, st.xr4, k * sc.plane4, 0));
+}
+
+// update of row y of level l from the rows below, at and above it; rows off
+// the grid (computed only to be dropped or replaced by a wall) use any valid
+// row for their wall lookups
+template <int BC>
+__device__ inline void row_update(const float below[NP], const float at[NP],
+                                  const float above[NP], int xw, int y, int level, const Grid& g,
+                                  const TBConst& sc, const WallSeq& ws, float out[NP]) {
+  const int yc = y < 0 ? 0 : (y >= g.ny ? g.ny - 1 : y);
+  Wall w;
+  w.W = nullptr;
+  w.Trow = nullptr;
+  w.rank = 0;
+  w.L = ws.L;
+  w.V = ws.V ? ws.V + (int64_t)(level - 1) * 2 * ws.L : nullptr;
+  level_update<BC>(below, at, above, xw, yc, g.nx, g.ny, sc.kK, sc.km, w, out);
+}
+
+// One sub-iteration i of the sweep (PRE: a pipeline-filling sub-iteration
+// before the first output row, I = i then; slot = i mod NB, known at compile
+// time in both cases).
+template <int BC, int NT, int PF, int T, bool PRE>
+__device__ inline void sub_iteration(const float* __restrict__ src, float* __restrict__ dst,
+                                     const Grid& g, const TBConst& sc, const Strip& st,
+                                     const WallSeq& ws, int y0, int y1, int i, int I, int slot,
+                                     float (&lv0)[3 + PF][NP], float (&lv)[T - 1][3 + PF][NP]) {
+  constexpr int NB = 3 + PF;
+  const int s = slot, s1 = (slot + NB - 1) % NB, s2 = (slot + NB - 2) % NB;
+  const int last_in = y1 - 1 + T;  // last level-0 row the segment needs
+  // prefetch level-0 row y0 + i + T + PF into slot (i + PF) mod NB, which held
+  // the row of sub-iteration i + PF - NB = i - 3 (no longer read).  Past the
+  // last needed row it re-reads that row (a cache hit).
+  {
+    const int yl = y0 + i + T + PF < last_in ? y0 + i + T + PF : last_in;
+    load_row<BC>(src, g, sc, st, yl, lv0[(slot + PF) % NB]);
+  }
+  // keep the prefetch at the head of the sub-iteration: the scheduler would
+  // sink it towards its first use and shorten the distance it hides
+  __builtin_amdgcn_sched_barrier(0);
+  // level 1 .. T-1: level l row y0 + i + T - l; during the pipeline fill only
+  // the levels whose rows the segment needs (I >= -2 (T - l))
+  if (!PRE || I >= -2 * (T - 1))
+    row_update<BC>(lv0[s2], lv0[s1], lv0[s], st.xw, y0 + i + T - 1, 1, g, sc, ws, lv[0][s]);
+#pragma unroll
+  for (int l = 2; l < T; ++l) {
+    if (PRE && I < -2 * (T - l)) continue;
+    row_update<BC>(lv[l - 2][s2], lv[l - 2][s1], lv[l - 2][s], st.xw, y0 + i + T - l, l, g, sc,
+                   ws, lv[l - 1][s]);
+  }
+  if (!PRE) {
+    // level T, output row y0 + i
+    float o[NP];
+    const int rr = y0 + i;
+    row_update<BC>(lv[T - 2][s2], lv[T - 2][s1], lv[T - 2][s], st.xw, rr, T, g, sc, ws, o);
+    const int off = rr < y1 ? st.xs4 : TB_DROP;
+    const int yo = rr < g.ny ? rr : g.ny - 1;
+    float* rp = dst + (int64_t)yo * g.pitch;
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc((void*)rp, (short)0, sc.extent, TB_RSRC_WORD3);
+#pragma unroll
+    for (int k = 0; k < NP; ++k)  // aux 2: nontemporal
+      __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(o[k]), rs, off, k * sc.plane4,
+                                            NT ? 2 : 0);
+  }
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+template <int BC, int NT, int PF, int T>
+__global__ __launch_bounds__(256) void k_tblock(const float* __restrict__ src,
+                                                float* __restrict__ dst, Grid g, TBConst sc,
+                                                WallSeq ws) {
+  static_assert(T >= 2 && T <= 7, "2 to 7 time levels per launch");
+  constexpr int NB = 3 + PF;
+  constexpr int VALID = TB_LANES - 2 * T;  // stored columns per strip
+  const int lane = threadIdx.x & 63;
+  const int ntiles = sc.nstrips * sc.nseg;
+  const int nwg = (ntiles + 3) / 4;
+  // wave index: uniform by construction, stated to the compiler
+  const int wid = xcd_tile(blockIdx.x, nwg) * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (wid >= ntiles) return;  // whole waves exit together
+  const int strip = wid % sc.nstrips, seg = wid / sc.nstrips;
+  const int nx = g.nx, ny = g.ny;
+  const int x = strip * VALID - T + lane;  // unwrapped column of this lane
+  const int xc = BC == LBM_PERIODIC ? wrap_mod(x, nx) : (x < 0 ? 0 : (x >= nx ? nx - 1 : x));
+  const bool store = lane >= T && lane < TB_LANES - T && x >= 0 && x < nx;
+  Strip st;
+  st.xw = (x >= 0 && x < nx) ? x : -2;
+  st.xr4 = (int)((uint32_t)xc * 4u);
+  st.xs4 = store ? (int)((uint32_t)x * 4u) : TB_DROP;
+  const int y0 = seg * sc.seg_rows;
+  const int y1 = y0 + sc.seg_rows < ny ? y0 + sc.seg_rows : ny;
+
+  float lv0[NB][NP];     // level 0: row of sub-iteration i is y0 + i + T
+  float lv[T - 1][NB][NP];  // level l: row of sub-iteration i is y0 + i + T - l
+  // level-0 rows of the first PF sub-iterations of the pipeline fill
+#pragma unroll
+  for (int k = 0; k < PF; ++k) {
+    constexpr int first = -2 * T;
+    load_row<BC>(src, g, sc, st, y0 + first + k + T, lv0[((first + k) % NB + NB) % NB]);
+  }
+  // pipeline fill: sub-iterations -2T .. -1
+#pragma unroll
+  for (int p = 0; p < 2 * T; ++p) {
+    const int I = p - 2 * T;
+    sub_iteration<BC, NT, PF, T, true>(src, dst, g, sc, st, ws, y0, y1, I, I, (I % NB + NB) % NB,
+                                       lv0, lv);
+  }
+  // The sweep runs in whole rings of NB rows; rows past the segment end are
+  // computed from valid (wrapped or clamped) rows and their stores dropped.
+  // No early exit inside a ring: a conditional exit would let the compiler
+  // sink each prefetch past it, next to its first use.
+  for (int i0 = 0; i0 < y1 - y0; i0 += NB) {
+#pragma unroll
+    for (int j = 0; j < NB; ++j)
+      sub_iteration<BC, NT, PF, T, false>(src, dst, g, sc, st, ws, y0, y1, i0 + j, 0, j, lv0, lv);
+  }
+}
+
+inline TBConst tblock_const(const Grid& g, float kK, float km, int seg_rows, int T) {
+  TBConst sc;
+  sc.kK = kK;
+  sc.km = km;
+  sc.nstrips = (g.nx + (TB_LANES - 2 * T) - 1) / (TB_LANES - 2 * T);
+  sc.seg_rows = seg_rows;
+  sc.nseg = (g.ny + seg_rows - 1) / seg_rows;
+  sc.plane4 = (int)(g.plane * 4);
+  sc.extent = (int)(((NP - 1) * g.plane + g.nx) * 4);
+  return sc;
+}
+
+// the byte offsets of a row's resource must stay below 2^31
+inline bool tblock_fits(const Grid& g) {
+  return ((NP - 1) * g.plane + g.pitch) * 4 < ((int64_t)1 << 31);
+}
+
+}  // namespace lbmk

@@ -160,28 +160,30 @@ class Lattice:
         check(self.L.lbm_set_step_config(self.ctx, int(index)))
 
     @property
-    def step2_config(self):
+    def tblock_config(self):
+        """Temporally blocked variant in use (T steps per launch), -1 = none."""
         i = ctypes.c_int32()
-        check(self.L.lbm_get_step2_config(self.ctx, ctypes.byref(i)))
+        check(self.L.lbm_get_tblock_config(self.ctx, ctypes.byref(i)))
         return i.value
 
-    @step2_config.setter
-    def step2_config(self, index):
-        check(self.L.lbm_set_step2_config(self.ctx, int(index)))
+    @tblock_config.setter
+    def tblock_config(self, index):
+        check(self.L.lbm_set_tblock_config(self.ctx, int(index)))
 
-    def step2_configs(self):
+    def tblock_configs(self):
         out = []
-        for i in range(self.L.lbm_step2_config_count()):
-            sr, nt, pf = (ctypes.c_int32() for _ in range(3))
-            check(self.L.lbm_step2_config_info(i, ctypes.byref(sr), ctypes.byref(nt),
-                                               ctypes.byref(pf)))
-            out.append({"index": i, "seg_rows": sr.value, "nontemporal": nt.value,
-                        "prefetch": pf.value})
+        for i in range(self.L.lbm_tblock_config_count()):
+            t, sr, nt, pf = (ctypes.c_int32() for _ in range(4))
+            check(self.L.lbm_tblock_config_info(i, ctypes.byref(t), ctypes.byref(sr),
+                                                ctypes.byref(nt), ctypes.byref(pf)))
+            out.append({"index": i, "steps": t.value, "seg_rows": sr.value,
+                        "nontemporal": nt.value, "prefetch": pf.value})
         return out
 
-    def time_step2_config(self, index, reps=20):
+    def time_tblock_config(self, index, reps=20):
+        """Average ms of one launch (T steps) of blocked variant `index`."""
         ms = ctypes.c_double()
-        check(self.L.lbm_time_step2_config(self.ctx, int(index), int(reps), ctypes.byref(ms)))
+        check(self.L.lbm_time_tblock_config(self.ctx, int(index), int(reps), ctypes.byref(ms)))
         return ms.value
 
     def valid_step_configs(self):

@@ -78,7 +78,7 @@ def test_copy_kernel():
 @pytest.mark.parametrize("bc", [synth.PERIODIC, synth.DIRICHLET])
 @pytest.mark.parametrize("nx,ny", [(512, 96), (300, 70), (64, 64), (61, 7), (1, 5), (130, 1),
                                    (2, 2), (1024, 33)])
-def test_two_step_kernel_bitwise_equals_single_steps(bc, nx, ny):
+def test_blocked_kernels_bitwise_equal_single_steps(bc, nx, ny):
     # temporal blocking changes where values live, not the arithmetic
     torch = _torch()
     from paper_2408_01081_amd.lbm import Lattice
@@ -88,11 +88,11 @@ def test_two_step_kernel_bitwise_equals_single_steps(bc, nx, ny):
     W, T = prob.wall_table(nsteps)
     ref = None
     lat = Lattice(prob.nx, prob.ny, prob.dx, prob.dt, prob.lam, prob.mu, prob.rho, prob.bc)
-    for cfg2 in [-1] + [c["index"] for c in lat.step2_configs()]:
+    for cfg2 in [-1] + [c["index"] for c in lat.tblock_configs()]:
         lat.init(torch.from_numpy(v0), torch.from_numpy(sb0))
         if bc == synth.DIRICHLET:
             lat.set_wall_velocity(torch.from_numpy(W), torch.from_numpy(T))
-        lat.step2_config = cfg2
+        lat.tblock_config = cfg2
         lat.step(5).step(nsteps - 5)
         f = lat.populations().cpu().numpy()
         if ref is None:
@@ -102,7 +102,7 @@ def test_two_step_kernel_bitwise_equals_single_steps(bc, nx, ny):
 
 
 @gpu
-def test_two_step_kernel_matches_oracle_dirichlet_walls():
+def test_blocked_kernels_match_oracle_dirichlet_walls():
     torch = _torch()
     import oracle
     from paper_2408_01081_amd.lbm import Lattice
@@ -115,10 +115,10 @@ def test_two_step_kernel_matches_oracle_dirichlet_walls():
     sim.advance(n)
     ref = sim.U()
     lat = Lattice(prob.nx, prob.ny, prob.dx, prob.dt, prob.lam, prob.mu, prob.rho, prob.bc)
-    for c in lat.step2_configs():
+    for c in lat.tblock_configs():
         lat.init(torch.from_numpy(v0), torch.from_numpy(sb0))
         lat.set_wall_velocity(torch.from_numpy(W), torch.from_numpy(T))
-        lat.step2_config = c["index"]
+        lat.tblock_config = c["index"]
         lat.step(n)
         U = lat.moments_U().double().cpu().numpy()
         assert oracle.rel_l2(U, ref) < 1e-5, c
