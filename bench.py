@@ -154,7 +154,9 @@ def main():
     kname = "k_tblock" if blocked else "k_step"
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": measured_traffic(kname),
+                "traffic": measured_traffic(
+                    kname, ("tblock_config=%d" % tuned[0]["tblock_config"]) if blocked
+                    else ("step_config=%d" % tuned[0]["config"])),
                 "kernel": "%s (periodic 4096x4096, %s)" % (
                     kname, ("blocked variant %d, %d steps per launch"
                             % (tuned[0]["tblock_config"], T)) if blocked
@@ -244,16 +246,17 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def measured_traffic(kname):
+def measured_traffic(kname, launch):
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3
-    counter summary, if it was taken on the current kernel source."""
+    counter summary, if it was taken on the current kernel source and on the
+    launch configuration this run uses."""
     path = os.path.join(ROOT, "profiles", "%s_periodic_4096_traffic.json" % kname)
     if not os.path.exists(path):
         return None
     try:
         d = json.load(open(path))
         from paper_2408_01081_amd import build as B
-        if d.get("source_sha256") != B.source_hash():
+        if d.get("source_sha256") != B.source_hash() or d.get("launch") != launch:
             return None
         return d.get("bytes_per_launch")
     except Exception:

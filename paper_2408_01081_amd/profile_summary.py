@@ -7,9 +7,9 @@
   stats:   the per-kernel table of a --kernel-trace --stats run.
 
     python -m paper_2408_01081_amd.profile_summary traffic \\
-        --fetch DIR --write DIR --match 'k_step2<0,' --copy-bytes 2684354560 \\
-        --algorithmic-bytes 2684354560 --kernel 'description' --command CMD --command CMD \\
-        --out profiles/NAME.json
+        --fetch DIR --write DIR --match 'k_tblock<0, 0, 1, 7>' --copy-bytes 2684354560 \\
+        --algorithmic-bytes 2684354560 --kernel 'description' --launch tblock_config=21 \\
+        --command CMD --command CMD --out profiles/NAME.json
     python -m paper_2408_01081_amd.profile_summary stats --dir DIR --title T \\
         --command CMD --note LINE --out profiles/NAME.md
 """
@@ -57,7 +57,8 @@ def traffic(a):
     fs, ws = half / avg(cf), half / avg(cw)
     rd, wr = avg(f) * fs * 1024, avg(w) * ws * 1024
     out = {
-        "kernel": a.kernel, "match": a.match, "source_sha256": B.source_hash(),
+        "kernel": a.kernel, "match": a.match, "launch": a.launch,
+        "source_sha256": B.source_hash(),
         "commands": a.command,
         "fetch_kib_per_dispatch": round(avg(f), 2), "write_kib_per_dispatch": round(avg(w), 2),
         "dispatches": [len(f), len(w)],
@@ -106,6 +107,8 @@ def main():
     t.add_argument("--copy-bytes", type=int, required=True)
     t.add_argument("--algorithmic-bytes", type=int, required=True)
     t.add_argument("--kernel", required=True)
+    t.add_argument("--launch", default="",
+                   help="launch configuration the counters belong to, e.g. tblock_config=21")
     t.add_argument("--command", action="append", default=[])
     t.add_argument("--out", required=True)
     s = sub.add_parser("stats")
