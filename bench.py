@@ -296,6 +296,7 @@ def batched_leg(n, nsteps):
                for p in probs])
     b.init(b.pack([p.v0 for p in probs]), b.pack([p.sb0 for p in probs]))
     E0 = b.energy()
+    tb, tb_ms = b.autotune(reps=5)   # single steps or a temporally blocked variant
     b.step(nsteps)            # builds (and caches) the graph, warms up
     torch.cuda.synchronize()
     log("batched setup + first graph %.1fs" % (time.time() - t0))
@@ -315,8 +316,14 @@ def batched_leg(n, nsteps):
                         (n, sum(p.bc for p in probs)),
             "nodes": nodes, "steps": nsteps, "graph_launches": 1, "ms": round(ms, 3),
             "GLUPS": round(nodes * nsteps / (ms * 1e-3) / 1e9, 3),
-            "GB/s": round(160 * nodes * nsteps / (ms * 1e-3) / 1e9, 1),
+            "tblock": b.tblock_configs()[tb] if tb >= 0 else None,
+            "algorithmic_GB/s": round(160 * nodes * nsteps / steps_per_launch(b, tb)
+                                      / (ms * 1e-3) / 1e9, 1),
             "max_rel_energy_drift": drift}
+
+
+def steps_per_launch(b, tb):
+    return b.tblock_configs()[tb]["steps"] if tb >= 0 else 1
 
 
 BF16_PEAK_TFLOPS = 2500.0

@@ -218,7 +218,7 @@ lbm_status lbm_copy_f32(float* d_dst, const float* d_src, int64_t n, void* hip_s
 /* ---- batched lattices --------------------------------------------------------
  * n independent instances, each with its own lbm_params (size, boundary,
  * material, dx, dt; flags must be 0), advanced together: one launch per time
- * step covers every row segment of every instance, with the same per-node
+ * step (or per T steps, below) covers every instance, with the same per-node
  * arithmetic as lbm_step (results are bitwise identical to stepping each
  * instance alone).  lbm_batch_step(n) executes the n launches as one hipGraph
  * (built node by node and cached per step count while no instance has wall
@@ -251,11 +251,30 @@ lbm_status lbm_batch_init_fields_f32(lbm_batch* b, const float* d_fields);
 lbm_status lbm_batch_set_wall_velocity(lbm_batch* b, int32_t i, int32_t rank, const float* d_W,
                                        const float* d_T, int64_t nsteps);
 
-/* Advance every instance n steps: one hipGraph launch of n step kernels. */
+/* Advance every instance n steps: one hipGraph launch of the step kernels
+ * (one step per kernel, or T per kernel with a blocked variant selected). */
 lbm_status lbm_batch_step(lbm_batch* b, int64_t n);
 
 /* Same steps launched one kernel at a time (no graph). */
 lbm_status lbm_batch_step_eager(lbm_batch* b, int64_t n);
+
+/* Temporally blocked batched steps: the blocked sweep of lbm_tblock_config_*
+ * applied to every instance in one launch per T steps (a table maps each wave
+ * to its instance, strip and segment); bitwise identical to single steps.
+ * The blocked kernel handles walls at rest only: while any instance has wall
+ * data (lbm_batch_set_wall_velocity with rank > 0) lbm_batch_step and
+ * lbm_batch_step_eager run single steps whatever variant is selected.  Index
+ * -1 = single steps.  Selecting a variant synchronises the batch's stream and
+ * uploads its wave table into the workspace.  lbm_batch_autotune times the
+ * single-step kernel and every usable variant on the live state without
+ * changing it (reps launches each, HIP events), selects the fastest per step
+ * and returns its index and ms per step; it synchronises. */
+int32_t lbm_batch_tblock_config_count(void);
+lbm_status lbm_batch_tblock_config_info(int32_t index, int32_t* h_steps, int32_t* h_seg_rows,
+                                        int32_t* h_nontemporal, int32_t* h_prefetch);
+lbm_status lbm_batch_get_tblock_config(const lbm_batch* b, int32_t* h_index);
+lbm_status lbm_batch_set_tblock_config(lbm_batch* b, int32_t index);
+lbm_status lbm_batch_autotune(lbm_batch* b, int32_t reps, int32_t* h_index, double* h_ms);
 
 /* Packed FP32 moments: (v, sigma_bar) or the system variables U, [..][5][ny][nx]. */
 lbm_status lbm_batch_moments(lbm_batch* b, float* d_out);

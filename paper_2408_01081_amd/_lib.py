@@ -70,6 +70,13 @@ SIGNATURES = [
     ("lbm_batch_set_wall_velocity", ctypes.c_int, [_VP, _I32, _I32, _VP, _VP, _I64]),
     ("lbm_batch_step", ctypes.c_int, [_VP, _I64]),
     ("lbm_batch_step_eager", ctypes.c_int, [_VP, _I64]),
+    ("lbm_batch_tblock_config_count", _I32, []),
+    ("lbm_batch_tblock_config_info", ctypes.c_int,
+     [_I32, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32),
+      ctypes.POINTER(_I32)]),
+    ("lbm_batch_get_tblock_config", ctypes.c_int, [_VP, ctypes.POINTER(_I32)]),
+    ("lbm_batch_set_tblock_config", ctypes.c_int, [_VP, _I32]),
+    ("lbm_batch_autotune", ctypes.c_int, [_VP, _I32, ctypes.POINTER(_I32), _PD]),
     ("lbm_batch_moments", ctypes.c_int, [_VP, _VP]),
     ("lbm_batch_moments_U", ctypes.c_int, [_VP, _VP]),
     ("lbm_batch_energy", ctypes.c_int, [_VP, _PD]),

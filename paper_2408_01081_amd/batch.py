@@ -109,6 +109,34 @@ class Batch:
         return self
 
     @property
+    def tblock_config(self):
+        """Temporally blocked variant in use (T steps per launch), -1 = none."""
+        i = ctypes.c_int32()
+        check(self.L.lbm_batch_get_tblock_config(self.ctx, ctypes.byref(i)))
+        return i.value
+
+    @tblock_config.setter
+    def tblock_config(self, index):
+        check(self.L.lbm_batch_set_tblock_config(self.ctx, int(index)))
+
+    def tblock_configs(self):
+        out = []
+        for i in range(self.L.lbm_batch_tblock_config_count()):
+            t, sr, nt, pf = (ctypes.c_int32() for _ in range(4))
+            check(self.L.lbm_batch_tblock_config_info(i, ctypes.byref(t), ctypes.byref(sr),
+                                                      ctypes.byref(nt), ctypes.byref(pf)))
+            out.append({"index": i, "steps": t.value, "seg_rows": sr.value,
+                        "nontemporal": nt.value, "prefetch": pf.value})
+        return out
+
+    def autotune(self, reps=5):
+        """Select the fastest of single steps and the blocked variants (state
+        unchanged); returns (index, ms per step)."""
+        i, ms = ctypes.c_int32(), ctypes.c_double()
+        check(self.L.lbm_batch_autotune(self.ctx, int(reps), ctypes.byref(i), ctypes.byref(ms)))
+        return i.value, ms.value
+
+    @property
     def steps(self):
         return int(self.L.lbm_batch_step_count(self.ctx))
 

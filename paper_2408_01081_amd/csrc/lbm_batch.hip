@@ -7,7 +7,10 @@
 // index to (instance, row, segment), so one launch advances every instance by
 // one step with the same per-node arithmetic as the single-lattice kernel
 // (bitwise-identical results).  lbm_batch_step(n) runs n such launches as one
-// hipGraph built node by node (no stream capture, no memset nodes).
+// hipGraph built node by node (no stream capture, no memset nodes).  With a
+// temporally blocked variant selected, a node advances every instance by T
+// steps: a second table maps each wave to (instance, strip, segment) and the
+// wave runs the single-lattice blocked sweep on its instance.
 //
 // Packed field arrays (inputs and outputs of the batch) store instance i's
 // fields contiguously, [component][ny_i][nx_i], starting at component count
@@ -20,6 +23,7 @@
 
 #include <map>
 #include <new>
+#include <tuple>
 #include <utility>
 #include <vector>
 
@@ -28,6 +32,7 @@
 #include "lbm_init.hpp"
 #include "lbm_kernels.hpp"
 #include "lbm_step.hpp"
+#include "lbm_tblock.hpp"
 
 using namespace lbmk;
 using namespace lbmh;
@@ -86,6 +91,57 @@ __global__ __launch_bounds__(THREADS) void k_batch_step(const float* __restrict_
   else
     step_segment<LBM_DIRICHLET, 1, THREADS, 1, 0>(src, dst, d.g, d.kK, d.km, w, y, tx);
 }
+
+// T steps of every instance per launch (walls at rest); wave w works on
+// instance waves[w].x, strip / segment index waves[w].y of that instance.
+template <int NT, int PF, int T>
+__global__ __launch_bounds__(256) void k_batch_tblock(const float* __restrict__ pool_src,
+                                                      float* __restrict__ pool_dst,
+                                                      const InstDesc* __restrict__ descs,
+                                                      const int2* __restrict__ waves, int nwaves,
+                                                      int seg_rows, int64_t step) {
+  constexpr int VALID = TB_LANES - 2 * T;
+  const int nwg = (nwaves + 3) / 4;
+  const int wid = xcd_tile(blockIdx.x, nwg) * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (wid >= nwaves) return;  // whole waves exit together
+  const int2 wv = waves[wid];
+  const int inst = __builtin_amdgcn_readfirstlane(wv.x);
+  const int local = __builtin_amdgcn_readfirstlane(wv.y);
+  const InstDesc& d = descs[inst];
+  TBConst sc;
+  sc.kK = d.kK;
+  sc.km = d.km;
+  sc.nstrips = (d.g.nx + VALID - 1) / VALID;
+  sc.seg_rows = seg_rows;
+  sc.nseg = (d.g.ny + seg_rows - 1) / seg_rows;
+  sc.plane4 = (int)(d.g.plane * 4);
+  sc.extent = (int)(((NP - 1) * d.g.plane + d.g.nx) * 4);
+  // walls at rest: blocked launches run only while no instance has wall data
+  WallSeq ws;
+  ws.V = nullptr;
+  ws.L = 2 * (d.g.nx + d.g.ny);
+  const float* src = pool_src + d.off;
+  float* dst = pool_dst + d.off;
+  const int strip = local % sc.nstrips, seg = local / sc.nstrips;
+  if (d.bc == LBM_PERIODIC)
+    tblock_wave<LBM_PERIODIC, NT, PF, T>(src, dst, d.g, sc, ws, strip, seg);
+  else
+    tblock_wave<LBM_DIRICHLET, NT, PF, T>(src, dst, d.g, sc, ws, strip, seg);
+}
+
+typedef void (*BatchTBFn)(const float*, float*, const InstDesc*, const int2*, int, int, int64_t);
+struct BatchTBConfig {
+  int steps, seg_rows, nt, pf;
+  BatchTBFn fn;
+};
+#define LBM_BTB(T, S, N, F) {T, S, N, F, &k_batch_tblock<N, F, T>}
+const BatchTBConfig kBatchTB[] = {
+    LBM_BTB(2, 4, 0, 1), LBM_BTB(2, 8, 1, 1),  LBM_BTB(3, 4, 0, 1),  LBM_BTB(3, 8, 0, 1),
+    LBM_BTB(4, 4, 0, 1), LBM_BTB(4, 8, 0, 1),  LBM_BTB(4, 4, 1, 1),  LBM_BTB(4, 16, 0, 1),
+    LBM_BTB(5, 8, 0, 1), LBM_BTB(5, 16, 0, 1), LBM_BTB(6, 16, 0, 1), LBM_BTB(7, 16, 0, 1),
+    LBM_BTB(7, 32, 0, 1)};
+#undef LBM_BTB
+constexpr int kNumBatchTB = (int)(sizeof(kBatchTB) / sizeof(kBatchTB[0]));
 
 // packed = 0: v0 [..][2][ny][nx] and s0 [..][3][ny][nx] separate arrays;
 // packed = 1: one array [..][5][ny][nx] = (v, sigma_bar) in s0's place (v0 unused).
@@ -220,8 +276,24 @@ struct Layout {
   std::vector<int> tile_inst, tile_count;
   int64_t pool_floats = 0, total_nodes = 0;
   int ntiles = 0;
-  size_t off_pool[2], off_desc, off_tiles, off_count, off_partial, off_out, bytes;
+  int tb_waves[kNumBatchTB];  // waves of each blocked variant
+  int tb_max_waves = 0;
+  bool tb_ok = true;          // every instance fits the blocked kernel
+  size_t off_pool[2], off_desc, off_tiles, off_count, off_partial, off_out, off_waves, bytes;
 };
+
+// wave table of blocked variant `v`: (instance, strip + nstrips * segment)
+std::vector<int2> wave_table(const Layout& L, int v) {
+  const BatchTBConfig& k = kBatchTB[v];
+  const int valid = TB_LANES - 2 * k.steps;
+  std::vector<int2> t;
+  for (int i = 0; i < (int)L.desc.size(); ++i) {
+    const Grid& g = L.desc[i].g;
+    const int n = ((g.nx + valid - 1) / valid) * ((g.ny + k.seg_rows - 1) / k.seg_rows);
+    for (int j = 0; j < n; ++j) t.push_back(make_int2(i, j));
+  }
+  return t;
+}
 
 lbm_status plan(int32_t n, const lbm_params* params, Layout* L) {
   if (n < 1 || !params) return fail(LBM_E_ARG, "batch needs n >= 1 and parameters");
@@ -254,6 +326,19 @@ lbm_status plan(int32_t n, const lbm_params* params, Layout* L) {
     d.ic = InitConst{dv.kK, dv.km, dv.cK, dv.cmu, params[i].rho, params[i].dx, params[i].bc};
     if (!norm_weights(dv.kK, dv.km, d.kw)) return fail(LBM_E_CFL, "g_ij not positive definite");
   }
+  for (int v = 0; v < kNumBatchTB; ++v) {
+    const int valid = TB_LANES - 2 * kBatchTB[v].steps;
+    int64_t w = 0;
+    for (int i = 0; i < n; ++i) {
+      const Grid& g = L->desc[i].g;
+      w += (int64_t)((g.nx + valid - 1) / valid) *
+           ((g.ny + kBatchTB[v].seg_rows - 1) / kBatchTB[v].seg_rows);
+    }
+    if (w > 0x7fffffff) return fail(LBM_E_ARG, "batch too large");
+    L->tb_waves[v] = (int)w;
+    if (w > L->tb_max_waves) L->tb_max_waves = (int)w;
+  }
+  for (int i = 0; i < n; ++i) L->tb_ok = L->tb_ok && tblock_fits(L->desc[i].g);
   L->tile_inst.resize(L->ntiles);
   for (int i = 0; i < n; ++i)
     for (int t = 0; t < L->tile_count[i]; ++t) L->tile_inst[L->desc[i].tile0 + t] = i;
@@ -270,6 +355,7 @@ lbm_status plan(int32_t n, const lbm_params* params, Layout* L) {
   L->off_count = take(sizeof(int) * n);
   L->off_partial = take(sizeof(double) * 2 * (size_t)L->ntiles);
   L->off_out = take(sizeof(double) * 2 * n);
+  L->off_waves = take(sizeof(int2) * (size_t)L->tb_max_waves);
   L->bytes = o;
   return LBM_OK;
 }
@@ -287,12 +373,15 @@ struct lbm_batch {
   int* d_count;
   double* d_partial;
   double* d_out;
+  int2* d_waves;  // wave table of the selected blocked variant
   int cur;
   bool initialised;
   int64_t nstep;
   std::vector<int64_t> wall_nsteps;
   bool any_wall;
-  std::map<std::pair<int64_t, int>, hipGraphExec_t> graphs;  // (steps, parity), wall-free
+  int tb_cfg;  // selected blocked variant, -1: one step per launch
+  // (steps, parity, blocked variant) -> graph, built while no instance has walls
+  std::map<std::tuple<int64_t, int, int>, hipGraphExec_t> graphs;
 };
 
 namespace {
@@ -308,40 +397,99 @@ lbm_status upload_descs(lbm_batch* b) {
                    "descriptor upload");
 }
 
-// Build a graph of `steps` step launches starting from buffer `cur` at step
-// index `step0` (the step index matters only for wall tables).
+// Steps per launch for `steps` steps: T per launch with a blocked variant,
+// the remainder (fewer than T) one at a time.  The blocked kernel handles
+// walls at rest only, so any instance with wall data means single steps.
+std::vector<int> launch_plan(const lbm_batch* b, int64_t steps) {
+  std::vector<int> p;
+  const int T = b->tb_cfg >= 0 && !b->any_wall ? kBatchTB[b->tb_cfg].steps : 1;
+  int64_t k = 0;
+  for (; T > 1 && k + T <= steps; k += T) p.push_back(T);
+  for (; k < steps; ++k) p.push_back(1);
+  return p;
+}
+
+// Launch parameters of one launch advancing `t` steps from step index `step`
+// (the step index matters only for wall tables).
+struct LaunchArgs {
+  const float* src;
+  float* dst;
+  const InstDesc* descs;
+  const int* tiles;
+  const int2* waves;
+  int ntiles, nwaves, seg_rows;
+  int64_t step;
+  void* args[7];
+  hipKernelNodeParams kp;
+};
+
+void make_launch(const lbm_batch* b, int t, int parity, int64_t step, LaunchArgs* a) {
+  a->src = b->pool[parity];
+  a->dst = b->pool[parity ^ 1];
+  a->descs = b->d_desc;
+  a->tiles = b->d_tiles;
+  a->waves = b->d_waves;
+  a->ntiles = b->L.ntiles;
+  a->step = step;
+  memset(&a->kp, 0, sizeof a->kp);
+  a->kp.blockDim = dim3(BT);
+  if (t == 1) {
+    a->args[0] = (void*)&a->src;
+    a->args[1] = (void*)&a->dst;
+    a->args[2] = (void*)&a->descs;
+    a->args[3] = (void*)&a->tiles;
+    a->args[4] = (void*)&a->ntiles;
+    a->args[5] = (void*)&a->step;
+    a->kp.func = reinterpret_cast<void*>(&k_batch_step<BT>);
+    a->kp.gridDim = dim3((unsigned)a->ntiles);
+  } else {
+    const BatchTBConfig& k = kBatchTB[b->tb_cfg];
+    a->nwaves = b->L.tb_waves[b->tb_cfg];
+    a->seg_rows = k.seg_rows;
+    a->args[0] = (void*)&a->src;
+    a->args[1] = (void*)&a->dst;
+    a->args[2] = (void*)&a->descs;
+    a->args[3] = (void*)&a->waves;
+    a->args[4] = (void*)&a->nwaves;
+    a->args[5] = (void*)&a->seg_rows;
+    a->args[6] = (void*)&a->step;
+    a->kp.func = reinterpret_cast<void*>(k.fn);
+    a->kp.gridDim = dim3((unsigned)((a->nwaves + 3) / 4));
+  }
+  a->kp.kernelParams = a->args;
+}
+
+// Build a graph of the launches for `steps` steps starting from buffer `cur`
+// at step index `step0`.
 lbm_status build_graph(lbm_batch* b, int64_t steps, int cur, int64_t step0,
                        hipGraphExec_t* exec) {
   hipGraph_t graph;
   lbm_status s = hip_check(hipGraphCreate(&graph, 0), "graph create");
   if (s) return s;
   hipGraphNode_t prev = nullptr;
-  for (int64_t k = 0; k < steps && s == LBM_OK; ++k) {
-    const float* src = b->pool[(cur + k) & 1];
-    float* dst = b->pool[(cur + k + 1) & 1];
-    const InstDesc* descs = b->d_desc;
-    const int* tiles = b->d_tiles;
-    int ntiles = b->L.ntiles;
-    int64_t step = step0 + k;
-    void* args[] = {(void*)&src, (void*)&dst, (void*)&descs, (void*)&tiles, (void*)&ntiles,
-                    (void*)&step};
-    hipKernelNodeParams kp;
-    memset(&kp, 0, sizeof kp);
-    kp.func = reinterpret_cast<void*>(&k_batch_step<BT>);
-    kp.gridDim = dim3((unsigned)ntiles);
-    kp.blockDim = dim3(BT);
-    kp.sharedMemBytes = 0;
-    kp.kernelParams = args;
-    kp.extra = nullptr;
+  int parity = cur;
+  int64_t step = step0;
+  for (int t : launch_plan(b, steps)) {
+    LaunchArgs a;
+    make_launch(b, t, parity, step, &a);
     hipGraphNode_t node;
-    s = hip_check(hipGraphAddKernelNode(&node, graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp),
+    s = hip_check(hipGraphAddKernelNode(&node, graph, prev ? &prev : nullptr, prev ? 1 : 0, &a.kp),
                   "graph add kernel node");
+    if (s) break;
     prev = node;
+    parity ^= 1;
+    step += t;
   }
   if (s == LBM_OK) s = hip_check(hipGraphInstantiate(exec, graph, nullptr, nullptr, 0),
                                  "graph instantiate");
   hipGraphDestroy(graph);
   return s;
+}
+
+void launch_direct(lbm_batch* b, int t, int parity, int64_t step) {
+  LaunchArgs a;
+  make_launch(b, t, parity, step, &a);
+  hipLaunchKernel(a.kp.func, a.kp.gridDim, a.kp.blockDim, a.kp.kernelParams, 0, b->stream);
 }
 
 lbm_status batch_reduce(lbm_batch* b, int mode, const float* ref, double* h_out2) {
@@ -392,6 +540,8 @@ lbm_status lbm_batch_create(int32_t n, const lbm_params* params, void* d_ws, siz
   b->d_count = (int*)(b->ws + b->L.off_count);
   b->d_partial = (double*)(b->ws + b->L.off_partial);
   b->d_out = (double*)(b->ws + b->L.off_out);
+  b->d_waves = (int2*)(b->ws + b->L.off_waves);
+  b->tb_cfg = -1;
   b->cur = 0;
   b->initialised = false;
   b->nstep = 0;
@@ -487,7 +637,7 @@ lbm_status lbm_batch_step(lbm_batch* b, int64_t nsteps) {
       return fail(LBM_E_ARG, "wall table too short for the requested steps");
   lbm_status s;
   if (!b->any_wall) {
-    auto key = std::make_pair(nsteps, b->cur);
+    auto key = std::make_tuple(nsteps, b->cur, b->tb_cfg);
     auto it = b->graphs.find(key);
     if (it == b->graphs.end()) {
       hipGraphExec_t exec;
@@ -504,7 +654,7 @@ lbm_status lbm_batch_step(lbm_batch* b, int64_t nsteps) {
     hipGraphExecDestroy(exec);
   }
   if (s) return s;
-  b->cur = (int)((b->cur + nsteps) & 1);
+  b->cur ^= (int)(launch_plan(b, nsteps).size() & 1);
   b->nstep += nsteps;
   return LBM_OK;
 }
@@ -516,15 +666,104 @@ lbm_status lbm_batch_step_eager(lbm_batch* b, int64_t nsteps) {
   for (int i = 0; i < b->n; ++i)
     if (b->L.desc[i].rank > 0 && b->nstep + nsteps > b->wall_nsteps[i])
       return fail(LBM_E_ARG, "wall table too short for the requested steps");
-  for (int64_t k = 0; k < nsteps; ++k) {
-    hipLaunchKernelGGL(k_batch_step<BT>, dim3((unsigned)b->L.ntiles), dim3(BT), 0, b->stream,
-                       (const float*)b->pool[b->cur], b->pool[b->cur ^ 1],
-                       (const InstDesc*)b->d_desc, (const int*)b->d_tiles, b->L.ntiles,
-                       b->nstep + k);
+  for (int t : launch_plan(b, nsteps)) {
+    launch_direct(b, t, b->cur, b->nstep);
     b->cur ^= 1;
+    b->nstep += t;
   }
-  b->nstep += nsteps;
   return launch_check("batch step launch");
+}
+
+int32_t lbm_batch_tblock_config_count(void) { return kNumBatchTB; }
+
+lbm_status lbm_batch_tblock_config_info(int32_t index, int32_t* steps, int32_t* seg_rows,
+                                        int32_t* nt, int32_t* pf) {
+  if (index < 0 || index >= kNumBatchTB) return fail(LBM_E_ARG, "config index out of range");
+  const BatchTBConfig& k = kBatchTB[index];
+  if (steps) *steps = k.steps;
+  if (seg_rows) *seg_rows = k.seg_rows;
+  if (nt) *nt = k.nt;
+  if (pf) *pf = k.pf;
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_get_tblock_config(const lbm_batch* b, int32_t* index) {
+  if (!b || !index) return fail(LBM_E_ARG, "null argument");
+  *index = b->tb_cfg;
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_set_tblock_config(lbm_batch* b, int32_t index) {
+  if (!b) return fail(LBM_E_ARG, "null batch");
+  if (index < -1 || index >= kNumBatchTB) return fail(LBM_E_ARG, "config index out of range");
+  if (index == b->tb_cfg) return LBM_OK;
+  if (index >= 0 && !b->L.tb_ok)
+    return fail(LBM_E_ARG, "an instance is too wide for the blocked kernel");
+  // the wave table is shared by every blocked variant: wait for queued work
+  // that may read it, then replace it
+  lbm_status s = hip_check(hipStreamSynchronize(b->stream), "batch sync");
+  if (s) return s;
+  drop_graphs(b);
+  if (index >= 0) {
+    const std::vector<int2> t = wave_table(b->L, index);
+    s = hip_check(hipMemcpy(b->d_waves, t.data(), sizeof(int2) * t.size(), hipMemcpyHostToDevice),
+                  "wave table upload");
+    if (s) return s;
+  }
+  b->tb_cfg = index;
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_autotune(lbm_batch* b, int32_t reps, int32_t* h_index, double* h_ms) {
+  if (!b) return fail(LBM_E_ARG, "null batch");
+  if (!b->initialised) return fail(LBM_E_STATE, "autotune needs an initialised batch");
+  if (reps < 1) return fail(LBM_E_ARG, "reps must be >= 1");
+  hipEvent_t e0, e1;
+  lbm_status s = hip_check(hipEventCreate(&e0), "event");
+  if (s) return s;
+  s = hip_check(hipEventCreate(&e1), "event");
+  if (s) {
+    hipEventDestroy(e0);
+    return s;
+  }
+  int64_t wall_left = INT64_MAX;  // steps of wall data left for timed launches
+  for (int i = 0; i < b->n; ++i)
+    if (b->L.desc[i].rank > 0 && b->wall_nsteps[i] - b->nstep < wall_left)
+      wall_left = b->wall_nsteps[i] - b->nstep;
+  // blocked variants are skipped while an instance has wall data (they would
+  // not be used by lbm_batch_step then)
+  int best = -1;
+  double best_ms = 1e300;
+  // timed launches read the current pool and write the spare one: the state
+  // is not changed
+  for (int v = -1; v < kNumBatchTB && s == LBM_OK; ++v) {
+    if (v >= 0 && (!b->L.tb_ok || b->any_wall)) continue;
+    if (v < 0 && wall_left < 1) continue;
+    s = lbm_batch_set_tblock_config(b, v);
+    if (s) break;
+    const int t = v >= 0 ? kBatchTB[v].steps : 1;
+    for (int r = 0; r < reps + 2; ++r) {
+      if (r == 2) hipEventRecord(e0, b->stream);
+      launch_direct(b, t, b->cur, b->nstep);
+    }
+    hipEventRecord(e1, b->stream);
+    s = hip_check(hipEventSynchronize(e1), "autotune sync");
+    float ms = 0.f;
+    if (s == LBM_OK) s = hip_check(hipEventElapsedTime(&ms, e0, e1), "autotune timing");
+    const double per = (double)ms / reps / t;
+    if (s == LBM_OK && per < best_ms) {
+      best_ms = per;
+      best = v;
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (s) return s;
+  s = lbm_batch_set_tblock_config(b, best);
+  if (s) return s;
+  if (h_index) *h_index = best;
+  if (h_ms) *h_ms = best_ms;
+  return LBM_OK;
 }
 
 static lbm_status batch_moments(lbm_batch* b, float* out, int mode) {

@@ -51,8 +51,8 @@ struct TBConst {
   int extent;    // bytes one row's resource covers: (NP - 1) planes + one row
 };
 
-// Wall velocities of the launch's steps: level l uses table V + (l-1) * 2L
-// (nullptr: walls at rest).
+// Wall velocities of the launch's steps: level l (step n + l - 1) reads the
+// summed table V + (l-1) 2L (nullptr: walls at rest).
 struct WallSeq {
   const float* V;
   int L;  // 2 (nx + ny)
@@ -90,7 +90,7 @@ __device__ inline float from_lane_above(float v) {
 // one level-update of row y at this lane's column x from the rows below,
 // at and above (post-collision values of the previous level)
 template <int BC>
-__device__ inline void level_update(const float below[NP], const float at[NP],
+__device__ __forceinline__ void level_update(const float below[NP], const float at[NP],
                                     const float above[NP], int x, int y, int nx, int ny,
                                     float kK, float km, const Wall& w, float out[NP]) {
   float f[NQ][NC];
@@ -139,7 +139,7 @@ struct Strip {
 };
 
 template <int BC>
-__device__ inline void load_row(const float* __restrict__ src, const Grid& g, const TBConst& sc,
+__device__ __forceinline__ void load_row(const float* __restrict__ src, const Grid& g, const TBConst& sc,
                                 const Strip& st, int y, float v[NP]) {
   const float* rp = src + (int64_t)row_index<BC>(y, g.ny) * g.pitch;
   const __amdgpu_buffer_rsrc_t rs =
@@ -153,16 +153,17 @@ __device__ inline void load_row(const float* __restrict__ src, const Grid& g, co
 // the grid (computed only to be dropped or replaced by a wall) use any valid
 // row for their wall lookups
 template <int BC>
-__device__ inline void row_update(const float below[NP], const float at[NP],
-                                  const float above[NP], int xw, int y, int level, const Grid& g,
-                                  const TBConst& sc, const WallSeq& ws, float out[NP]) {
+__device__ __forceinline__ void row_update(const float below[NP], const float at[NP],
+                                           const float above[NP], int xw, int y, int level,
+                                           const Grid& g, const TBConst& sc, const WallSeq& ws,
+                                           float out[NP]) {
   const int yc = y < 0 ? 0 : (y >= g.ny ? g.ny - 1 : y);
   Wall w;
-  w.W = nullptr;
-  w.Trow = nullptr;
-  w.rank = 0;
   w.L = ws.L;
   w.V = ws.V ? ws.V + (int64_t)(level - 1) * 2 * ws.L : nullptr;
+  w.W = nullptr;
+  w.rank = 0;
+  w.Trow = nullptr;
   level_update<BC>(below, at, above, xw, yc, g.nx, g.ny, sc.kK, sc.km, w, out);
 }
 
@@ -170,7 +171,7 @@ __device__ inline void row_update(const float below[NP], const float at[NP],
 // before the first output row, I = i then; slot = i mod NB, known at compile
 // time in both cases).
 template <int BC, int NT, int PF, int T, bool PRE>
-__device__ inline void sub_iteration(const float* __restrict__ src, float* __restrict__ dst,
+__device__ __forceinline__ void sub_iteration(const float* __restrict__ src, float* __restrict__ dst,
                                      const Grid& g, const TBConst& sc, const Strip& st,
                                      const WallSeq& ws, int y0, int y1, int i, int I, int slot,
                                      float (&lv0)[3 + PF][NP], float (&lv)[T - 1][3 + PF][NP]) {
@@ -215,20 +216,15 @@ __device__ inline void sub_iteration(const float* __restrict__ src, float* __res
   __builtin_amdgcn_sched_barrier(0);
 }
 
+// One wave's work: strip `strip`, output rows of segment `seg`.
 template <int BC, int NT, int PF, int T>
-__global__ __launch_bounds__(256) void k_tblock(const float* __restrict__ src,
-                                                float* __restrict__ dst, Grid g, TBConst sc,
-                                                WallSeq ws) {
+__device__ __forceinline__ void tblock_wave(const float* __restrict__ src, float* __restrict__ dst,
+                                   const Grid& g, const TBConst& sc, const WallSeq& ws,
+                                   int strip, int seg) {
   static_assert(T >= 2 && T <= 7, "2 to 7 time levels per launch");
   constexpr int NB = 3 + PF;
   constexpr int VALID = TB_LANES - 2 * T;  // stored columns per strip
   const int lane = threadIdx.x & 63;
-  const int ntiles = sc.nstrips * sc.nseg;
-  const int nwg = (ntiles + 3) / 4;
-  // wave index: uniform by construction, stated to the compiler
-  const int wid = xcd_tile(blockIdx.x, nwg) * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  if (wid >= ntiles) return;  // whole waves exit together
-  const int strip = wid % sc.nstrips, seg = wid / sc.nstrips;
   const int nx = g.nx, ny = g.ny;
   const int x = strip * VALID - T + lane;  // unwrapped column of this lane
   const int xc = BC == LBM_PERIODIC ? wrap_mod(x, nx) : (x < 0 ? 0 : (x >= nx ? nx - 1 : x));
@@ -240,7 +236,7 @@ __global__ __launch_bounds__(256) void k_tblock(const float* __restrict__ src,
   const int y0 = seg * sc.seg_rows;
   const int y1 = y0 + sc.seg_rows < ny ? y0 + sc.seg_rows : ny;
 
-  float lv0[NB][NP];     // level 0: row of sub-iteration i is y0 + i + T
+  float lv0[NB][NP];        // level 0: row of sub-iteration i is y0 + i + T
   float lv[T - 1][NB][NP];  // level l: row of sub-iteration i is y0 + i + T - l
   // level-0 rows of the first PF sub-iterations of the pipeline fill
 #pragma unroll
@@ -264,6 +260,18 @@ __global__ __launch_bounds__(256) void k_tblock(const float* __restrict__ src,
     for (int j = 0; j < NB; ++j)
       sub_iteration<BC, NT, PF, T, false>(src, dst, g, sc, st, ws, y0, y1, i0 + j, 0, j, lv0, lv);
   }
+}
+
+template <int BC, int NT, int PF, int T>
+__global__ __launch_bounds__(256) void k_tblock(const float* __restrict__ src,
+                                                float* __restrict__ dst, Grid g, TBConst sc,
+                                                WallSeq ws) {
+  const int ntiles = sc.nstrips * sc.nseg;
+  const int nwg = (ntiles + 3) / 4;
+  // wave index: uniform by construction, stated to the compiler
+  const int wid = xcd_tile(blockIdx.x, nwg) * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (wid >= ntiles) return;  // whole waves exit together
+  tblock_wave<BC, NT, PF, T>(src, dst, g, sc, ws, wid % sc.nstrips, wid / sc.nstrips);
 }
 
 inline TBConst tblock_const(const Grid& g, float kK, float km, int seg_rows, int T) {

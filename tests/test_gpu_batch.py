@@ -130,3 +130,63 @@ def test_batch_reinit_from_fp32_fields():
     m1 = b1.moments().double().cpu().numpy()
     m2 = b2.moments().double().cpu().numpy()
     assert oracle.rel_l2(m2, m1) < 1e-6
+
+
+@gpu
+def test_batch_blocked_variants_bitwise_equal_single_steps():
+    # every temporally blocked variant, graph and eager, with step counts that
+    # leave a remainder of single steps; walls at rest
+    torch = _torch()
+    from paper_2408_01081_amd.batch import Batch
+    probs = _problems()
+    fields = [p.initial_fields() for p in probs]
+    b = Batch([_params(p) for p in probs])
+    v0, s0 = b.pack([f[0] for f in fields]), b.pack([f[1] for f in fields])
+    b.init(v0, s0).step(23, graph=False)
+    ref = b.moments(system=True).cpu().numpy()
+    for c in b.tblock_configs():
+        b.tblock_config = c["index"]
+        for graph in (True, False):
+            b.init(v0, s0)
+            b.step(9, graph=graph).step(14, graph=graph)
+            got = b.moments(system=True).cpu().numpy()
+            assert b.steps == 23
+            assert np.array_equal(got.view(np.uint32), ref.view(np.uint32)), (c, graph)
+
+
+@gpu
+def test_batch_blocked_variant_with_walls_runs_single_steps():
+    # wall data switch the batch to single steps, so a selected blocked
+    # variant must still give the single-lattice result with moving walls
+    torch = _torch()
+    from paper_2408_01081_amd.batch import Batch
+    from paper_2408_01081_amd.lbm import Lattice
+    p = synth.plane_wave_problem(300, 129, synth.DIRICHLET, seed=2, kmax=4)
+    v0, s0 = p.initial_fields()
+    W, T = p.wall_table(17)
+    b = Batch([_params(p)])
+    b.tblock_config = 4
+    b.set_wall_velocity(0, torch.from_numpy(W), torch.from_numpy(T))
+    b.init(b.pack([v0]), b.pack([s0])).step(17)
+    lat = Lattice(p.nx, p.ny, p.dx, p.dt, p.lam, p.mu, p.rho, p.bc)
+    lat.init(torch.from_numpy(v0), torch.from_numpy(s0))
+    lat.set_wall_velocity(torch.from_numpy(W), torch.from_numpy(T))
+    lat.step(17)
+    got = b.moments(system=True).cpu().numpy()
+    want = lat.moments_U().cpu().numpy().reshape(-1)
+    assert np.array_equal(got.view(np.uint32), want.view(np.uint32))
+
+
+@gpu
+def test_batch_autotune_keeps_state():
+    torch = _torch()
+    from paper_2408_01081_amd.batch import Batch
+    probs = _problems()
+    fields = [p.initial_fields() for p in probs]
+    b = Batch([_params(p) for p in probs])
+    b.init(b.pack([f[0] for f in fields]), b.pack([f[1] for f in fields])).step(3)
+    before = b.moments(system=True).cpu().numpy()
+    idx, ms = b.autotune(reps=3)
+    assert -1 <= idx < len(b.tblock_configs()) and ms > 0
+    assert b.tblock_config == idx and b.steps == 3
+    assert np.array_equal(b.moments(system=True).cpu().numpy(), before)
