@@ -90,15 +90,19 @@ __device__ inline double wg_sum(double v, double* sh) {
   return r;
 }
 
-// one workgroup per sample: s_b, Chebyshev values T[b][m]
-__global__ __launch_bounds__(RT) void k_stats(const float* __restrict__ in, int HW,
-                                              float* __restrict__ sv,
-                                              float* __restrict__ T) {
+// Per-sample statistics in two passes: SB workgroups per sample sum |U|^2,
+// c_K and c_mu over their pixels (FP64), then one workgroup per sample adds
+// the SB partial sums in a fixed order and forms s_b and the Chebyshev values
+// T[b][m].
+constexpr int SB = 64;  // workgroups per sample in the first pass
+
+__global__ __launch_bounds__(RT) void k_stats_partial(const float* __restrict__ in, int HW,
+                                                      double* __restrict__ part) {
   __shared__ double sh[RT];
-  const int b = blockIdx.x;
+  const int b = blockIdx.y;
   const float* f = in + (int64_t)b * 8 * HW;
   double u2 = 0.0, ck = 0.0, cm = 0.0;
-  for (int p = threadIdx.x; p < HW; p += RT) {
+  for (int p = blockIdx.x * RT + threadIdx.x; p < HW; p += SB * RT) {
     const Mat m = material(f, HW, p);
     float U[5];
     phys_to_U(f, HW, p, m, U);
@@ -109,6 +113,23 @@ __global__ __launch_bounds__(RT) void k_stats(const float* __restrict__ in, int 
   u2 = wg_sum(u2, sh);
   ck = wg_sum(ck, sh);
   cm = wg_sum(cm, sh);
+  if (threadIdx.x == 0) {
+    double* o = part + ((int64_t)b * SB + blockIdx.x) * 3;
+    o[0] = u2;
+    o[1] = ck;
+    o[2] = cm;
+  }
+}
+
+__global__ __launch_bounds__(RT) void k_stats(const double* __restrict__ part, int HW,
+                                              float* __restrict__ sv, float* __restrict__ T) {
+  __shared__ double sh[RT];
+  const int b = blockIdx.x;
+  const double* q = part + (int64_t)b * SB * 3;
+  const bool mine = (int)threadIdx.x < SB;
+  const double u2 = wg_sum(mine ? q[3 * threadIdx.x] : 0.0, sh);
+  const double ck = wg_sum(mine ? q[3 * threadIdx.x + 1] : 0.0, sh);
+  const double cm = wg_sum(mine ? q[3 * threadIdx.x + 2] : 0.0, sh);
   if (threadIdx.x == 0) {
     const double s = sqrt(u2 / (5.0 * HW));
     sv[b] = (float)(s > 0 ? s : 1.0);
@@ -281,7 +302,7 @@ struct Plan {
   size_t bytes = 0;
   // workspace offsets
   size_t o_param, o_grad, o_m, o_v, o_wfh, o_wfl, o_wbh, o_wbl, o_s, o_T, o_gam, o_dgam,
-      o_part, o_loss, o_x0, o_z[NL], o_pool[3], o_up[3], o_g[NL], o_gpool[3], o_gup[3],
+      o_part, o_spart, o_loss, o_x0, o_z[NL], o_pool[3], o_up[3], o_g[NL], o_gpool[3], o_gup[3],
       o_gtmp[2], o_wpart;
   int64_t wpart_floats = 0;
 };
@@ -329,6 +350,7 @@ lbm_status make_plan(const sg_config* cfg, Plan* P) {
   P->o_T = take(B * NBASIS * 4);
   P->o_gam = take((size_t)NL * B * 128 * 4);
   P->o_part = take(((size_t)B * P->H * P->W / RT + 1) * 8);
+  P->o_spart = take((size_t)B * SB * 3 * 8);
   P->o_loss = take(8);
   P->o_x0 = take(act(0, CP));
   for (int l = 0; l < NL; ++l) P->o_z[l] = take(act(kLayers[l].level, kLayers[l].cout));
@@ -374,6 +396,7 @@ struct sg_net {
   float* gam[NL];
   float* dgam;
   double* part;
+  double* spart;  // per-sample statistics partials [B][SB][3]
   double* loss;
   float* x0;
   Tensor z[NL], pool[3], up[3], g[NL], gpool[3], gup[3], gtmp[2];
@@ -389,13 +412,54 @@ namespace {
 
 inline unsigned grid1(int64_t n) { return (unsigned)((n + RT - 1) / RT); }
 
-template <int SPLIT, int NB, int PB>
+template <int SPLIT, int NB, int PB, int KS>
 void launch_conv(sg_net* n, const Tensor& x, const float* xscale, const unsigned short* wh,
                  const unsigned short* wl, Tensor& z, int cin, int cout, int accumulate) {
   const int64_t pixels = (int64_t)n->B * x.H * x.W;
-  dim3 grid((unsigned)(pixels / (64 * PB)), (unsigned)(cout / (16 * NB)));
-  hipLaunchKernelGGL((k_conv<SPLIT, NB, PB>), grid, dim3(256), 0, n->stream, x.p, xscale, wh, wl,
-                     z.p, x.H, x.W, cin, cout, n->circular, accumulate);
+  dim3 grid((unsigned)(pixels / (16 * PB * (4 / KS))), (unsigned)(cout / (16 * NB)));
+  hipLaunchKernelGGL((k_conv<SPLIT, NB, PB, KS>), grid, dim3(256), 0, n->stream, x.p, xscale, wh,
+                     wl, z.p, x.H, x.W, cin, cout, n->circular, accumulate);
+}
+
+// Tile shapes of the convolution, most work per wave first: (NB, PB, KS).
+// The first one that gives at least kConvMinWG workgroups is used (else the
+// one with the most workgroups), so small late layers still fill the chip.
+struct ConvShape {
+  int nb, pb, ks;
+};
+const ConvShape kConvShapes[] = {{4, 2, 1}, {4, 1, 1}, {2, 2, 1}, {2, 1, 1}, {4, 1, 2},
+                                 {2, 1, 2}, {1, 1, 2}, {2, 1, 4}, {1, 1, 4}};
+constexpr int64_t kConvMinWG = 1024;
+
+int conv_shape(int64_t pixels, int cin, int cout) {
+  int best = -1;
+  int64_t best_wg = -1;
+  for (int k = 0; k < (int)(sizeof(kConvShapes) / sizeof(kConvShapes[0])); ++k) {
+    const ConvShape& c = kConvShapes[k];
+    const int64_t px = 16 * c.pb * (4 / c.ks);
+    if (cout % (16 * c.nb) || pixels % px || cin / 32 < c.ks) continue;
+    const int64_t wg = pixels / px * (cout / (16 * c.nb));
+    if (wg >= kConvMinWG) return k;
+    if (wg > best_wg) best_wg = wg, best = k;
+  }
+  return best >= 0 ? best : 3;
+}
+
+template <int SPLIT>
+void launch_conv_shape(int k, sg_net* n, const Tensor& x, const float* xscale,
+                       const unsigned short* wh, const unsigned short* wl, Tensor& z, int cin,
+                       int cout, int accumulate) {
+  switch (k) {
+    case 0: return launch_conv<SPLIT, 4, 2, 1>(n, x, xscale, wh, wl, z, cin, cout, accumulate);
+    case 1: return launch_conv<SPLIT, 4, 1, 1>(n, x, xscale, wh, wl, z, cin, cout, accumulate);
+    case 2: return launch_conv<SPLIT, 2, 2, 1>(n, x, xscale, wh, wl, z, cin, cout, accumulate);
+    case 3: return launch_conv<SPLIT, 2, 1, 1>(n, x, xscale, wh, wl, z, cin, cout, accumulate);
+    case 4: return launch_conv<SPLIT, 4, 1, 2>(n, x, xscale, wh, wl, z, cin, cout, accumulate);
+    case 5: return launch_conv<SPLIT, 2, 1, 2>(n, x, xscale, wh, wl, z, cin, cout, accumulate);
+    case 6: return launch_conv<SPLIT, 1, 1, 2>(n, x, xscale, wh, wl, z, cin, cout, accumulate);
+    case 7: return launch_conv<SPLIT, 2, 1, 4>(n, x, xscale, wh, wl, z, cin, cout, accumulate);
+    default: return launch_conv<SPLIT, 1, 1, 4>(n, x, xscale, wh, wl, z, cin, cout, accumulate);
+  }
 }
 
 void conv(sg_net* n, const Tensor& x, const float* xscale, int l, Tensor& z, bool backward,
@@ -405,23 +469,11 @@ void conv(sg_net* n, const Tensor& x, const float* xscale, int l, Tensor& z, boo
   const unsigned short* wh = (backward ? n->wbh : n->wfh) + n->P.wq_off[l];
   const unsigned short* wl = (backward ? n->wbl : n->wfl) + n->P.wq_off[l];
   const int64_t pixels = (int64_t)n->B * x.H * x.W;
-  // two pixel blocks per wave where the grid stays large enough
-  const bool pb2 = pixels % 128 == 0 && pixels / 128 * (cout / 64 > 0 ? cout / 64 : 1) >= 512;
-  if (n->P.split == 3) {
-    if (cout >= 64)
-      pb2 ? launch_conv<3, 4, 2>(n, x, xscale, wh, wl, z, cin, cout, accumulate)
-          : launch_conv<3, 4, 1>(n, x, xscale, wh, wl, z, cin, cout, accumulate);
-    else
-      pb2 ? launch_conv<3, 2, 2>(n, x, xscale, wh, wl, z, cin, cout, accumulate)
-          : launch_conv<3, 2, 1>(n, x, xscale, wh, wl, z, cin, cout, accumulate);
-  } else {
-    if (cout >= 64)
-      pb2 ? launch_conv<1, 4, 2>(n, x, xscale, wh, wl, z, cin, cout, accumulate)
-          : launch_conv<1, 4, 1>(n, x, xscale, wh, wl, z, cin, cout, accumulate);
-    else
-      pb2 ? launch_conv<1, 2, 2>(n, x, xscale, wh, wl, z, cin, cout, accumulate)
-          : launch_conv<1, 2, 1>(n, x, xscale, wh, wl, z, cin, cout, accumulate);
-  }
+  const int k = conv_shape(pixels, cin, cout);
+  if (n->P.split == 3)
+    launch_conv_shape<3>(k, n, x, xscale, wh, wl, z, cin, cout, accumulate);
+  else
+    launch_conv_shape<1>(k, n, x, xscale, wh, wl, z, cin, cout, accumulate);
 }
 
 void pool(sg_net* n, const Tensor& in, const float* scale, Tensor& out) {
@@ -455,7 +507,9 @@ lbm_status forward(sg_net* n, const float* in, int B, int circular) {
   n->in = in;
   if (!n->weights_ready) prep_weights(n);
   const int HW = P.H * P.W;
-  hipLaunchKernelGGL(k_stats, dim3(B), dim3(RT), 0, n->stream, in, HW, n->s, n->T);
+  hipLaunchKernelGGL(k_stats_partial, dim3(SB, B), dim3(RT), 0, n->stream, in, HW, n->spart);
+  hipLaunchKernelGGL(k_stats, dim3(B), dim3(RT), 0, n->stream, (const double*)n->spart, HW, n->s,
+                     n->T);
   hipLaunchKernelGGL(k_pre, dim3(grid1((int64_t)B * HW)), dim3(RT), 0, n->stream, in, B, HW,
                      n->s, n->x0);
   GammaArgs ga;
@@ -627,6 +681,7 @@ lbm_status sg_create(const sg_config* cfg, void* d_ws, size_t ws_bytes, void* hi
   n->T = (float*)(w + P.o_T);
   for (int l = 0; l < NL; ++l) n->gam[l] = (float*)(w + P.o_gam) + (size_t)l * P.B * 128;
   n->part = (double*)(w + P.o_part);
+  n->spart = (double*)(w + P.o_spart);
   n->loss = (double*)(w + P.o_loss);
   n->x0 = (float*)(w + P.o_x0);
   for (int l = 0; l < NL; ++l) {

@@ -46,21 +46,25 @@ __device__ inline bf16 as_bf16(unsigned short b) {
 // in-bounds probe): lane l holds A[l%16][8(l/16)+j], B[8(l/16)+j][l%16] for
 // j = 0..7, and D[4(l/16)+j][l%16] for j = 0..3.
 // One wave computes PB blocks of 16 pixels (each one row piece, W % 16 == 0)
-// x 16*NB output channels, so every weight fragment feeds PB products; a
-// workgroup is 4 waves (64 PB pixels).  Cin % 32 == 0.
+// x 16*NB output channels, so every weight fragment feeds PB products.  The
+// 4 waves of a workgroup are 4/KS pixel groups x KS slices of the reduction
+// (input-channel chunks of 32 taken round robin); the KS partial sums are
+// added in LDS in slice order, so the result does not depend on timing.  A
+// workgroup covers 16 * PB * 4/KS pixels.  Cin % 32 == 0.
 // Used for the forward pass (Wt = [9][Cout][Cin]) and, with the flipped and
 // transposed weights, for the data gradient.
 // ---------------------------------------------------------------------------
-template <int SPLIT, int NB, int PB>
+template <int SPLIT, int NB, int PB, int KS>
 __global__ __launch_bounds__(256) void k_conv(const float* __restrict__ X,
                                               const float* __restrict__ xscale,
                                               const unsigned short* __restrict__ Whi,
                                               const unsigned short* __restrict__ Wlo,
                                               float* __restrict__ Z, int H, int W, int Cin,
                                               int Cout, int circular, int accumulate) {
-  // PB blocks of 16 consecutive pixels per wave (each inside one image row);
-  // a workgroup covers 4 * 16 * PB pixels
+  static_assert(KS == 1 || KS == 2 || KS == 4, "reduction slices per workgroup");
+  constexpr int PG = 4 / KS;  // pixel groups per workgroup
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int pg = wave / KS, ks = wave % KS;
   const int64_t HW = (int64_t)H * W;
   const int m = lane & 15, kq = lane >> 4;
   const int co0 = blockIdx.y * 16 * NB;
@@ -68,7 +72,7 @@ __global__ __launch_bounds__(256) void k_conv(const float* __restrict__ X,
   int bb[PB], yy[PB], xx[PB];
 #pragma unroll
   for (int pb = 0; pb < PB; ++pb) {
-    pix0[pb] = ((int64_t)blockIdx.x * 4 * PB + wave * PB + pb) * 16;
+    pix0[pb] = ((int64_t)blockIdx.x * PG * PB + pg * PB + pb) * 16;
     bb[pb] = (int)(pix0[pb] / HW);
     const int rem = (int)(pix0[pb] - (int64_t)bb[pb] * HW);
     yy[pb] = rem / W;
@@ -80,7 +84,7 @@ __global__ __launch_bounds__(256) void k_conv(const float* __restrict__ X,
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) acc[pb][nb] = (f32x4){0.f, 0.f, 0.f, 0.f};
 
-  for (int c0 = 0; c0 < Cin; c0 += 32) {
+  for (int c0 = 32 * ks; c0 < Cin; c0 += 32 * KS) {
 #pragma unroll
     for (int t = 0; t < 9; ++t) {
       const int dy = t / 3 - 1, dx = t % 3 - 1;
@@ -129,6 +133,28 @@ __global__ __launch_bounds__(256) void k_conv(const float* __restrict__ X,
         }
       }
     }
+  }
+  if (KS > 1) {
+    // slices 1..KS-1 hand their sums to slice 0 of the same pixel group
+    __shared__ f32x4 red[KS > 1 ? 4 : 1][PB * NB][64];
+    if (ks > 0) {
+#pragma unroll
+      for (int pb = 0; pb < PB; ++pb)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) red[wave][pb * NB + nb][lane] = acc[pb][nb];
+    }
+    __syncthreads();
+    if (ks > 0) return;
+#pragma unroll
+    for (int k = 1; k < KS; ++k)
+#pragma unroll
+      for (int pb = 0; pb < PB; ++pb)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+          const f32x4 r = red[wave + k][pb * NB + nb][lane];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[pb][nb][j] += r[j];
+        }
   }
 #pragma unroll
   for (int pb = 0; pb < PB; ++pb)
