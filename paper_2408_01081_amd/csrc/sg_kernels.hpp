@@ -54,9 +54,41 @@ __device__ inline bf16 as_bf16(unsigned short b) {
 // Used for the forward pass (Wt = [9][Cout][Cin]) and, with the flipped and
 // transposed weights, for the data gradient.
 // ---------------------------------------------------------------------------
+// Input split once per layer: Xh / Xl = BF16 hi / lo parts of X * s (s the
+// per-sample, per-channel gain, or 1), NHWC like X; 4 elements per thread.
+__global__ __launch_bounds__(256) void k_split_bf16(const float* __restrict__ X,
+                                                    const float* __restrict__ xscale,
+                                                    int64_t n4, int64_t HWC, int C,
+                                                    unsigned short* __restrict__ Xh,
+                                                    unsigned short* __restrict__ Xl) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n4) return;
+  const int64_t e = 4 * i;
+  const float4 v = *reinterpret_cast<const float4*>(X + e);
+  float a[4] = {v.x, v.y, v.z, v.w};
+  if (xscale) {
+    const int64_t b = e / HWC;
+    const int c = (int)(e % C);
+    const float* sc = xscale + b * C + c;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) a[j] *= sc[j];
+  }
+  ushort4 h, l;
+  unsigned short hb[4], lb[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    hb[j] = bf16_bits(a[j]);
+    lb[j] = bf16_bits(a[j] - bf16_value(hb[j]));
+  }
+  h.x = hb[0]; h.y = hb[1]; h.z = hb[2]; h.w = hb[3];
+  l.x = lb[0]; l.y = lb[1]; l.z = lb[2]; l.w = lb[3];
+  *reinterpret_cast<ushort4*>(Xh + e) = h;
+  *reinterpret_cast<ushort4*>(Xl + e) = l;
+}
+
 template <int SPLIT, int NB, int PB, int KS>
-__global__ __launch_bounds__(256) void k_conv(const float* __restrict__ X,
-                                              const float* __restrict__ xscale,
+__global__ __launch_bounds__(256) void k_conv(const unsigned short* __restrict__ Xh,
+                                              const unsigned short* __restrict__ Xl,
                                               const unsigned short* __restrict__ Whi,
                                               const unsigned short* __restrict__ Wlo,
                                               float* __restrict__ Z, int H, int W, int Cin,
@@ -101,21 +133,10 @@ __global__ __launch_bounds__(256) void k_conv(const float* __restrict__ X,
           ys = ys < 0 ? 0 : (ys >= H ? H - 1 : ys);
           xs = xs < 0 ? 0 : (xs >= W ? W - 1 : xs);
         }
-        const float* xp = X + (((int64_t)bb[pb] * H + ys) * W + xs) * Cin + 8 * kq + c0;
-        float a[8];
-        const float4 v0 = *reinterpret_cast<const float4*>(xp);
-        const float4 v1 = *reinterpret_cast<const float4*>(xp + 4);
-        a[0] = v0.x; a[1] = v0.y; a[2] = v0.z; a[3] = v0.w;
-        a[4] = v1.x; a[5] = v1.y; a[6] = v1.z; a[7] = v1.w;
-        const float* sc = xscale ? xscale + (int64_t)bb[pb] * Cin + c0 + 8 * kq : nullptr;
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          a[j] = valid ? a[j] : 0.f;
-          if (sc) a[j] *= sc[j];
-          const unsigned short h = bf16_bits(a[j]);
-          ahi[pb][j] = as_bf16(h);
-          alo[pb][j] = as_bf16(bf16_bits(a[j] - bf16_value(h)));
-        }
+        const int64_t xo = (((int64_t)bb[pb] * H + ys) * W + xs) * Cin + 8 * kq + c0;
+        const bf16x8 zero = {};
+        ahi[pb] = valid ? *reinterpret_cast<const bf16x8*>(Xh + xo) : zero;
+        if (SPLIT == 3) alo[pb] = valid ? *reinterpret_cast<const bf16x8*>(Xl + xo) : zero;
       }
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
