@@ -248,19 +248,20 @@ def main():
 
 def measured_traffic(kname, launch):
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3
-    counter summary, if it was taken on the current kernel source and on the
-    launch configuration this run uses."""
+    counter summary, if one was taken on the current lattice-kernel sources
+    and on the launch configuration this run uses."""
     path = os.path.join(ROOT, "profiles", "%s_periodic_4096_traffic.json" % kname)
     if not os.path.exists(path):
         return None
     try:
-        d = json.load(open(path))
         from paper_2408_01081_amd import build as B
-        if d.get("source_sha256") != B.source_hash() or d.get("launch") != launch:
-            return None
-        return d.get("bytes_per_launch")
+        h = B.source_hash("lbm")
+        for e in json.load(open(path)).get("entries", []):
+            if e.get("source_sha256") == h and e.get("launch") == launch:
+                return e.get("bytes_per_launch")
     except Exception:
         return None
+    return None
 
 
 def periodic_parity(prob, lat, nsample=4096):

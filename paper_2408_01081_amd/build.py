@@ -45,13 +45,21 @@ def build(verbose: bool = False) -> str:
     return out
 
 
-def source_hash() -> str:
-    """SHA-256 over the HIP sources and the build flags (identifies a kernel
-    build for stored profiling results)."""
+def source_hash(prefix: str = "") -> str:
+    """SHA-256 over the HIP sources whose names start with `prefix` (all by
+    default; "lbm" for the lattice kernels), the public headers and the build
+    flags: identifies a kernel build for stored profiling results."""
     import hashlib
     h = hashlib.sha256()
     for s in sorted(os.listdir(CSRC)):
+        if not s.startswith(prefix):
+            continue
         with open(os.path.join(CSRC, s), "rb") as fh:
+            h.update(s.encode() + b"\0" + fh.read())
+    for s in sorted(os.listdir(INCLUDE)):
+        if not s.startswith(prefix):
+            continue
+        with open(os.path.join(INCLUDE, s), "rb") as fh:
             h.update(s.encode() + b"\0" + fh.read())
     h.update(" ".join(HIPCC_FLAGS).encode())
     return h.hexdigest()

@@ -3,7 +3,7 @@
   traffic: HBM bytes per launch of one kernel from two counter runs
       (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled by what the
       same counter reads for the plain copy kernel k_copy of known size in the
-      same run;
+      same run; one entry per launch configuration in the output file;
   stats:   the per-kernel table of a --kernel-trace --stats run.
 
     python -m paper_2408_01081_amd.profile_summary traffic \\
@@ -58,7 +58,7 @@ def traffic(a):
     rd, wr = avg(f) * fs * 1024, avg(w) * ws * 1024
     out = {
         "kernel": a.kernel, "match": a.match, "launch": a.launch,
-        "source_sha256": B.source_hash(),
+        "source_sha256": B.source_hash("lbm"),
         "commands": a.command,
         "fetch_kib_per_dispatch": round(avg(f), 2), "write_kib_per_dispatch": round(avg(w), 2),
         "dispatches": [len(f), len(w)],
@@ -73,7 +73,14 @@ def traffic(a):
         "read_over_algorithmic": round(rd / (a.algorithmic_bytes / 2), 5),
         "write_over_algorithmic": round(wr / (a.algorithmic_bytes / 2), 5),
     }
-    json.dump(out, open(a.out, "w"), indent=1)
+    # one file holds the entries of several launch configurations of the
+    # same kernel and workload; an entry for the same launch is replaced
+    doc = {"entries": []}
+    if os.path.exists(a.out):
+        old = json.load(open(a.out))
+        doc["entries"] = [e for e in old.get("entries", []) if e.get("launch") != a.launch]
+    doc["entries"].append(out)
+    json.dump(doc, open(a.out, "w"), indent=1)
     print(json.dumps(out, indent=1))
 
 
