@@ -78,14 +78,19 @@ def main():
     t0 = time.time()
     per = synth.plane_wave_problem(4096, 4096, synth.PERIODIC, seed=2)
     dir_ = synth.plane_wave_problem(2048, 1024, synth.DIRICHLET, seed=2, dx=1.0 / 1024)
+    # each lattice on its own HIP stream (default priority): the two lattices
+    # are independent, so the GPU may run their launches side by side
+    streams = [torch.cuda.Stream(device=dev), torch.cuda.Stream(device=dev)]
     lats = []
-    for prob in (per, dir_):
+    for prob, st in zip((per, dir_), streams):
         v0, sb0 = prob.initial_fields()
-        lat = Lattice(prob.nx, prob.ny, prob.dx, prob.dt, prob.lam, prob.mu, prob.rho, prob.bc)
-        lat.init(torch.from_numpy(v0).to(dev), torch.from_numpy(sb0).to(dev))
-        if prob.bc == synth.DIRICHLET:
-            Wt, Tt = prob.wall_table(total)
-            lat.set_wall_velocity(torch.from_numpy(Wt).to(dev), torch.from_numpy(Tt).to(dev))
+        with torch.cuda.stream(st):
+            lat = Lattice(prob.nx, prob.ny, prob.dx, prob.dt, prob.lam, prob.mu, prob.rho,
+                          prob.bc)
+            lat.init(torch.from_numpy(v0).to(dev), torch.from_numpy(sb0).to(dev))
+            if prob.bc == synth.DIRICHLET:
+                Wt, Tt = prob.wall_table(total)
+                lat.set_wall_velocity(torch.from_numpy(Wt).to(dev), torch.from_numpy(Tt).to(dev))
         lats.append(lat)
         del v0, sb0
     torch.cuda.synchronize()
@@ -119,32 +124,39 @@ def main():
     torch.cuda.synchronize()
 
     # ---- timed region ----------------------------------------------------------
-    # events: start, after the periodic lattice's K steps, after the Dirichlet's
+    # start / end on the main stream; each lattice's K steps bracketed by
+    # events on its own stream
     stream = torch.cuda.current_stream(dev)
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    E = lambda: torch.cuda.Event(enable_timing=True)
+    start, end = E(), E()
+    ev = [[E(), E()], [E(), E()]]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ev[0].record(stream)
-    lats[0].step(K)
-    ev[1].record(stream)
-    lats[1].step(K)
-    ev[2].record(stream)
+    start.record(stream)
+    for li, (lat, st) in enumerate(zip(lats, streams)):
+        st.wait_event(start)
+        ev[li][0].record(st)
+        lat.step(K)
+        ev[li][1].record(st)
+        stream.wait_event(ev[li][1])
+    end.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    ms_total = ev[0].elapsed_time(ev[2])
+    ms_total = start.elapsed_time(end)
     ms_per_step = ms_total / K
     glups = nodes * K / (ms_total * 1e-3) / 1e9
     log("timed: %d steps in %.3f s (events %.3f s)" % (K, wall, ms_total * 1e-3))
 
     # ---- dominant kernel: the 4096^2 periodic lattice's kernel -----------------
-    # Its average launch duration comes from the periodic part of the timed
-    # region (HIP events on the stream the kernels run on).  Algorithmic bytes
+    # Its average launch duration comes from the periodic lattice's part of the
+    # timed region (HIP events on the stream its kernels run on; the Dirichlet
+    # lattice's launches may share the GPU meanwhile).  Algorithmic bytes
     # per launch: every node's 20 FP32 populations read once and written once
     # (160 B per node), for one time step (k_step) or T (k_tblock).
     per_lat = lats[0]
     blocked = tuned[0]["tblock_config"] >= 0
     T = tuned[0]["tblock"]["steps"] if blocked else 1
-    per_ms = ev[0].elapsed_time(ev[1])
+    per_ms = ev[0][0].elapsed_time(ev[0][1])
     # lbm_step runs chunks of 420 steps, T per launch; leftover steps one at a time
     launches = (K // 420) * (420 // T) + (K % 420) // T if blocked else K
     single_left = K - launches * T if blocked else 0
@@ -154,9 +166,7 @@ def main():
     kname = "k_tblock" if blocked else "k_step"
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": measured_traffic(
-                    kname, ("tblock_config=%d" % tuned[0]["tblock_config"]) if blocked
-                    else ("step_config=%d" % tuned[0]["config"])),
+                "traffic": measured_traffic(kname, launch_key(tuned[0])),
                 "kernel": "%s (periodic 4096x4096, %s)" % (
                     kname, ("blocked variant %d, %d steps per launch"
                             % (tuned[0]["tblock_config"], T)) if blocked
@@ -231,8 +241,8 @@ def main():
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": "plain LBM FP32: periodic 4096x4096 + Dirichlet 2048x1024 "
                                "(time-dependent manufactured walls), plane-wave data, "
-                               "nu seeded (%.4f / %.4f), rho = 1, half CFL limit"
-                               % (per.meta["nu"], dir_.meta["nu"]),
+                               "nu seeded (%.4f / %.4f), rho = 1, half CFL limit; the two "
+                               "lattices on two HIP streams" % (per.meta["nu"], dir_.meta["nu"]),
                    "nodes_per_step": nodes, "precision": "FP32 populations, FP64 init",
                    "step_configs": tuned},
         "hbm_frac": roofline["frac"],
@@ -246,16 +256,26 @@ def main():
     print(json.dumps(out), flush=True)
 
 
+def launch_key(t):
+    """Launch properties the stored counter results are keyed on."""
+    if t["tblock_config"] >= 0:
+        b = t["tblock"]
+        return "T=%d seg=%d nt=%d pf=%d" % (b["steps"], b["seg_rows"], b["nontemporal"],
+                                           b["prefetch"])
+    return "vec=%d threads=%d nt=%d shuffle=%d" % (t["vec"], t["threads"], t["nontemporal"],
+                                                   t["shuffle"])
+
+
 def measured_traffic(kname, launch):
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3
-    counter summary, if one was taken on the current lattice-kernel sources
-    and on the launch configuration this run uses."""
+    counter summary, if one was taken on the current device code of that
+    kernel and on the launch configuration this run uses."""
     path = os.path.join(ROOT, "profiles", "%s_periodic_4096_traffic.json" % kname)
     if not os.path.exists(path):
         return None
     try:
         from paper_2408_01081_amd import build as B
-        h = B.source_hash("lbm")
+        h = B.kernel_hash(kname)
         for e in json.load(open(path)).get("entries", []):
             if e.get("source_sha256") == h and e.get("launch") == launch:
                 return e.get("bytes_per_launch")

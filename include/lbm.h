@@ -169,14 +169,17 @@ lbm_status lbm_set_step_config(lbm_ctx* ctx, int32_t index);
 
 /* Time every valid configuration on this context's grid (reps launches each
  * after two warm-up launches, HIP events on the context's stream), including
- * the two-step variants (per step), and select the fastest.  Launches are
+ * the temporally blocked variants below (compared per step), and select the
+ * fastest single-step configuration (*h_index) and, when it is faster per
+ * step, a blocked variant (read it with lbm_get_tblock_config).  Launches are
  * timed with the context's wall data at the current step when it has data for
- * two more steps, else with resting walls.  The lattice state is not
+ * seven more steps, else with resting walls.  The lattice state is not
  * modified: timed launches read the current state and write the spare buffer.
- * With use_cache != 0 a previous
- * result for the same (nx, ny, bc) in this process, or in the file named by
- * the environment variable LBM_AUTOTUNE_CACHE, is reused without timing
- * (*h_ms = -1 then).  New results are appended to that file.  Synchronises. */
+ * With use_cache != 0 a previous result for the same (nx, ny, bc) in this
+ * process, or in the file named by the environment variable
+ * LBM_AUTOTUNE_CACHE, is reused without timing (*h_ms = -1 then).  New
+ * results are appended to that file.  *h_ms = best time per step.
+ * Synchronises. */
 lbm_status lbm_autotune(lbm_ctx* ctx, int32_t reps, int32_t use_cache, int32_t* h_index,
                         double* h_ms);
 
@@ -220,10 +223,10 @@ lbm_status lbm_copy_f32(float* d_dst, const float* d_src, int64_t n, void* hip_s
  * material, dx, dt; flags must be 0), advanced together: one launch per time
  * step (or per T steps, below) covers every instance, with the same per-node
  * arithmetic as lbm_step (results are bitwise identical to stepping each
- * instance alone).  lbm_batch_step(n) executes the n launches as one hipGraph
- * (built node by node and cached per step count while no instance has wall
- * data).  The caller owns the workspace; the library never allocates device
- * memory.
+ * instance alone).  lbm_batch_step(n) executes the launches as one hipGraph
+ * (built node by node and cached per step count, buffer parity and blocked
+ * variant while no instance has wall data).  The caller owns the workspace;
+ * the library never allocates device memory.
  *
  * Packed field arrays hold instance i's fields contiguously as
  * [component][ny_i][nx_i], starting at (component count) x

@@ -45,6 +45,25 @@ def build(verbose: bool = False) -> str:
     return out
 
 
+# the files that define each profiled kernel's device code
+KERNEL_SOURCES = {
+    "k_tblock": ["lbm_tblock.hpp", "lbm_kernels.hpp", "lbm_step.hpp"],
+    "k_step": ["lbm_step.hpp", "lbm_kernels.hpp"],
+}
+
+
+def kernel_hash(kname: str) -> str:
+    """SHA-256 over the device sources of kernel `kname` and the build flags:
+    identifies the kernel code that stored counter results belong to."""
+    import hashlib
+    h = hashlib.sha256()
+    for s in KERNEL_SOURCES[kname]:
+        with open(os.path.join(CSRC, s), "rb") as fh:
+            h.update(s.encode() + b"\0" + fh.read())
+    h.update(" ".join(HIPCC_FLAGS).encode())
+    return h.hexdigest()
+
+
 def source_hash(prefix: str = "") -> str:
     """SHA-256 over the HIP sources whose names start with `prefix` (all by
     default; "lbm" for the lattice kernels), the public headers and the build

@@ -433,9 +433,10 @@ Wall zero_wall(const lbm_ctx* c) {
   return w;
 }
 
-// For timing launches: sum the walls of the next `n` steps into the table
-// when the context has wall data for them.
-bool timing_walls(lbm_ctx* c, int n = 4) {
+// For timing launches: sum the walls of the next `n` steps (the most steps a
+// blocked launch takes) into the table when the context has wall data for
+// them.
+bool timing_walls(lbm_ctx* c, int n = 7) {
   if (c->wall_rank == 0 || c->nstep + n > c->wall_nsteps) return false;
   eval_walls(c, c->nstep, n);
   return true;

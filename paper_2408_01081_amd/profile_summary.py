@@ -8,7 +8,8 @@
 
     python -m paper_2408_01081_amd.profile_summary traffic \\
         --fetch DIR --write DIR --match 'k_tblock<0, 0, 1, 7>' --copy-bytes 2684354560 \\
-        --algorithmic-bytes 2684354560 --kernel 'description' --launch tblock_config=21 \\
+        --algorithmic-bytes 2684354560 --kernel 'description' --kname k_tblock \\
+        --launch 'T=7 seg=48 nt=0 pf=1' \\
         --command CMD --command CMD --out profiles/NAME.json
     python -m paper_2408_01081_amd.profile_summary stats --dir DIR --title T \\
         --command CMD --note LINE --out profiles/NAME.md
@@ -58,7 +59,7 @@ def traffic(a):
     rd, wr = avg(f) * fs * 1024, avg(w) * ws * 1024
     out = {
         "kernel": a.kernel, "match": a.match, "launch": a.launch,
-        "source_sha256": B.source_hash("lbm"),
+        "source_sha256": B.kernel_hash(a.kname),
         "commands": a.command,
         "fetch_kib_per_dispatch": round(avg(f), 2), "write_kib_per_dispatch": round(avg(w), 2),
         "dispatches": [len(f), len(w)],
@@ -114,8 +115,10 @@ def main():
     t.add_argument("--copy-bytes", type=int, required=True)
     t.add_argument("--algorithmic-bytes", type=int, required=True)
     t.add_argument("--kernel", required=True)
+    t.add_argument("--kname", required=True, choices=["k_tblock", "k_step"])
     t.add_argument("--launch", default="",
-                   help="launch configuration the counters belong to, e.g. tblock_config=21")
+                   help="launch configuration the counters belong to, e.g. "
+                        "'T=7 seg=48 nt=0 pf=1'")
     t.add_argument("--command", action="append", default=[])
     t.add_argument("--out", required=True)
     s = sub.add_parser("stats")

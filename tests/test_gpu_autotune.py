@@ -76,10 +76,13 @@ def test_copy_kernel():
 
 @gpu
 @pytest.mark.parametrize("bc", [synth.PERIODIC, synth.DIRICHLET])
-@pytest.mark.parametrize("nx,ny", [(512, 96), (300, 70), (64, 64), (61, 7), (1, 5), (130, 1),
-                                   (2, 2), (1024, 33)])
-def test_blocked_kernels_bitwise_equal_single_steps(bc, nx, ny):
-    # temporal blocking changes where values live, not the arithmetic
+@pytest.mark.parametrize("nx,ny,plane", [(512, 96, False), (300, 70, False), (64, 64, False),
+                                         (61, 7, False), (1, 5, False), (130, 1, False),
+                                         (2, 2, False), (1024, 33, False), (300, 70, True),
+                                         (61, 7, True)])
+def test_blocked_kernels_bitwise_equal_single_steps(bc, nx, ny, plane):
+    # temporal blocking changes where values live, not the arithmetic (both
+    # population layouts)
     torch = _torch()
     from paper_2408_01081_amd.lbm import Lattice
     prob = synth.plane_wave_problem(nx, ny, bc, seed=13, kmax=2)
@@ -87,7 +90,8 @@ def test_blocked_kernels_bitwise_equal_single_steps(bc, nx, ny):
     nsteps = 23                       # odd: the last step is a single step
     W, T = prob.wall_table(nsteps)
     ref = None
-    lat = Lattice(prob.nx, prob.ny, prob.dx, prob.dt, prob.lam, prob.mu, prob.rho, prob.bc)
+    lat = Lattice(prob.nx, prob.ny, prob.dx, prob.dt, prob.lam, prob.mu, prob.rho, prob.bc,
+                  plane_layout=plane)
     for cfg2 in [-1] + [c["index"] for c in lat.tblock_configs()]:
         lat.init(torch.from_numpy(v0), torch.from_numpy(sb0))
         if bc == synth.DIRICHLET:
@@ -99,6 +103,35 @@ def test_blocked_kernels_bitwise_equal_single_steps(bc, nx, ny):
             ref = f
         else:
             assert np.array_equal(f.view(np.uint32), ref.view(np.uint32)), cfg2
+
+
+@gpu
+def test_blocked_kernels_across_wall_table_chunks():
+    # lbm_step sums wall velocities in chunks of 420 steps: runs longer than a
+    # chunk, split at odd places, stay bitwise equal to single steps
+    torch = _torch()
+    from paper_2408_01081_amd.lbm import Lattice
+    prob = synth.plane_wave_problem(70, 45, synth.DIRICHLET, seed=17, kmax=3)
+    v0, sb0 = prob.initial_fields()
+    nsteps = 431 + 419
+    W, T = prob.wall_table(nsteps)
+    lat = Lattice(prob.nx, prob.ny, prob.dx, prob.dt, prob.lam, prob.mu, prob.rho, prob.bc)
+    ref = None
+    seen = set()
+    for c in [{"index": -1, "steps": 1}] + lat.tblock_configs():
+        if c["steps"] in seen:
+            continue
+        seen.add(c["steps"])
+        lat.init(torch.from_numpy(v0), torch.from_numpy(sb0))
+        lat.set_wall_velocity(torch.from_numpy(W), torch.from_numpy(T))
+        lat.tblock_config = c["index"]
+        lat.step(431).step(419)
+        assert lat.steps == nsteps
+        f = lat.populations().cpu().numpy()
+        if ref is None:
+            ref = f
+        else:
+            assert np.array_equal(f.view(np.uint32), ref.view(np.uint32)), c
 
 
 @gpu
