@@ -360,16 +360,25 @@ int orc_norm_weights(double kK, double km, double* out) {
 double orc_energy(int nx, int ny, double kK, double km, const double* f) {
   double kw[NQ * NC * NC];
   if (orc_norm_weights(kK, km, kw)) return -1.0;
-  double total = 0.0;
-#pragma omp parallel for reduction(+ : total) schedule(static)
-  for (int l = 0; l < ny; ++l)
+  /* one partial sum per row, then the rows in order: the value does not
+     depend on the number of threads */
+  double* rows = (double*)malloc(sizeof(double) * (size_t)ny);
+  if (!rows) return -1.0;
+#pragma omp parallel for schedule(static)
+  for (int l = 0; l < ny; ++l) {
+    double row = 0.0;
     for (int k = 0; k < nx; ++k)
       for (int q = 0; q < NQ; ++q) {
         double v[NC];
         for (int c = 0; c < NC; ++c) v[c] = f[atq(q, c, l, k, nx, ny)];
         for (int r = 0; r < NC; ++r)
-          for (int c = 0; c < NC; ++c) total += v[r] * kw[(q * NC + r) * NC + c] * v[c];
+          for (int c = 0; c < NC; ++c) row += v[r] * kw[(q * NC + r) * NC + c] * v[c];
       }
+    rows[l] = row;
+  }
+  double total = 0.0;
+  for (int l = 0; l < ny; ++l) total += rows[l];
+  free(rows);
   return total;
 }
 
