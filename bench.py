@@ -40,6 +40,7 @@ def parse():
     ap.add_argument("--batch-instances", type=int, default=512)
     ap.add_argument("--batch-steps", type=int, default=2000)
     ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--no-load-leg", action="store_true")
     ap.add_argument("--surrogate-weights", default=os.path.join(
         ROOT, "paper_2408_01081_amd", "weights", "surrogate.npy"))
     ap.add_argument("--step-configs", default="",
@@ -78,19 +79,17 @@ def main():
     t0 = time.time()
     per = synth.plane_wave_problem(4096, 4096, synth.PERIODIC, seed=2)
     dir_ = synth.plane_wave_problem(2048, 1024, synth.DIRICHLET, seed=2, dx=1.0 / 1024)
-    # each lattice on its own HIP stream (default priority): the two lattices
-    # are independent, so the GPU may run their launches side by side
-    streams = [torch.cuda.Stream(device=dev), torch.cuda.Stream(device=dev)]
+    # both lattices on the current stream, one after the other: each kernel's
+    # launch duration is then its own (two streams overlapped the lattices'
+    # launches by about 2% of the step time and blurred the per-kernel times)
     lats = []
-    for prob, st in zip((per, dir_), streams):
+    for prob in (per, dir_):
         v0, sb0 = prob.initial_fields()
-        with torch.cuda.stream(st):
-            lat = Lattice(prob.nx, prob.ny, prob.dx, prob.dt, prob.lam, prob.mu, prob.rho,
-                          prob.bc)
-            lat.init(torch.from_numpy(v0).to(dev), torch.from_numpy(sb0).to(dev))
-            if prob.bc == synth.DIRICHLET:
-                Wt, Tt = prob.wall_table(total)
-                lat.set_wall_velocity(torch.from_numpy(Wt).to(dev), torch.from_numpy(Tt).to(dev))
+        lat = Lattice(prob.nx, prob.ny, prob.dx, prob.dt, prob.lam, prob.mu, prob.rho, prob.bc)
+        lat.init(torch.from_numpy(v0).to(dev), torch.from_numpy(sb0).to(dev))
+        if prob.bc == synth.DIRICHLET:
+            Wt, Tt = prob.wall_table(total)
+            lat.set_wall_velocity(torch.from_numpy(Wt).to(dev), torch.from_numpy(Tt).to(dev))
         lats.append(lat)
         del v0, sb0
     torch.cuda.synchronize()
@@ -124,8 +123,8 @@ def main():
     torch.cuda.synchronize()
 
     # ---- timed region ----------------------------------------------------------
-    # start / end on the main stream; each lattice's K steps bracketed by
-    # events on its own stream
+    # each lattice's K steps bracketed by events on the stream its kernels
+    # run on
     stream = torch.cuda.current_stream(dev)
     E = lambda: torch.cuda.Event(enable_timing=True)
     start, end = E(), E()
@@ -133,12 +132,10 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     start.record(stream)
-    for li, (lat, st) in enumerate(zip(lats, streams)):
-        st.wait_event(start)
-        ev[li][0].record(st)
+    for li, lat in enumerate(lats):
+        ev[li][0].record(stream)
         lat.step(K)
-        ev[li][1].record(st)
-        stream.wait_event(ev[li][1])
+        ev[li][1].record(stream)
     end.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -149,8 +146,7 @@ def main():
 
     # ---- dominant kernel: the 4096^2 periodic lattice's kernel -----------------
     # Its average launch duration comes from the periodic lattice's part of the
-    # timed region (HIP events on the stream its kernels run on; the Dirichlet
-    # lattice's launches may share the GPU meanwhile).  Algorithmic bytes
+    # timed region (HIP events on the stream its kernels run on).  Algorithmic bytes
     # per launch: every node's 20 FP32 populations read once and written once
     # (160 B per node), for one time step (k_step) or T (k_tblock).
     per_lat = lats[0]
@@ -216,6 +212,14 @@ def main():
     del lats, per_lat
     torch.cuda.empty_cache()
 
+    # ---- the step with a body load and the displacement output ----------------
+    with_load = None
+    if not args.no_load_leg:
+        try:
+            with_load = load_leg()
+        except Exception as ex:  # reported, never hidden
+            with_load = {"error": repr(ex)}
+
     # ---- batched instances: one hipGraph launch of many steps ------------------
     batched = None
     if args.batch_instances > 0 and args.batch_steps > 0:
@@ -241,14 +245,15 @@ def main():
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": "plain LBM FP32: periodic 4096x4096 + Dirichlet 2048x1024 "
                                "(time-dependent manufactured walls), plane-wave data, "
-                               "nu seeded (%.4f / %.4f), rho = 1, half CFL limit; the two "
-                               "lattices on two HIP streams" % (per.meta["nu"], dir_.meta["nu"]),
+                               "nu seeded (%.4f / %.4f), rho = 1, half CFL limit" %
+                               (per.meta["nu"], dir_.meta["nu"]),
                    "nodes_per_step": nodes, "precision": "FP32 populations, FP64 init",
                    "step_configs": tuned},
         "hbm_frac": roofline["frac"],
         "roofline": roofline,
         "cpu_baseline": cpu,
         "parity": parity,
+        "with_load_and_displacement": with_load,
         "batched": batched,
         "surrogate": surrogate,
         "wall_s": round(wall, 3),
@@ -341,6 +346,51 @@ def batched_leg(n, nsteps):
             "algorithmic_GB/s": round(160 * nodes * nsteps / steps_per_launch(b, tb)
                                       / (ms * 1e-3) / 1e9, 1),
             "max_rel_energy_drift": drift}
+
+
+def load_leg(nsteps=200):
+    """The 4096^2 periodic lattice stepped with a body load (the standing
+    manufactured solution's, separable, rank 16) and the FP64 displacement
+    state: the optional outputs' cost, reported beside the plain step."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2408_01081_amd.lbm import Lattice
+    N = 4096
+    mat = synth.Material.from_lame(1.0, 0.5, 1.0)
+    e = synth.Elastodynamics(*synth.standing_mms_solution(), mat)
+    dx = 1.0 / N
+    prob = synth.Problem(N, N, dx, synth.dt_at_cfl_fraction(dx, mat, 0.5), 1.0, 0.5, 1.0,
+                         synth.PERIODIC, sol=e)
+    dev = torch.device("cuda:0")
+    lat = Lattice(N, N, prob.dx, prob.dt, prob.lam, prob.mu, prob.rho, synth.PERIODIC,
+                  displacement=True)
+    BX, BY, BT = prob.body_table(2 * nsteps + 10)
+    lat.set_body_force(*(torch.from_numpy(a).to(dev) for a in (BX, BY, BT)))
+    v0, sb0 = prob.initial_fields()
+    lat.init(torch.from_numpy(v0).to(dev), torch.from_numpy(sb0).to(dev))
+    X, Y = synth.node_coords(N, N, dx)
+    lat.init_displacement(torch.from_numpy(np.stack([e.ux(X, Y, 0.0), e.uy(X, Y, 0.0)])).to(dev))
+    lat.step(10)
+    stream = torch.cuda.current_stream(dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    lat.step(nsteps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / nsteps
+    alg = (BYTES_PER_LUP + 32) * N * N
+    out = {"workload": "periodic 4096x4096, body load of rank %d (standing manufactured "
+                       "solution) + FP64 displacement state, one launch per step" % BX.shape[0],
+           "kernel": "k_step_ext", "steps": nsteps, "ms_per_step": round(ms, 5),
+           "GLUPS": round(N * N / ms / 1e6, 2),
+           "algorithmic_bytes_per_node": BYTES_PER_LUP + 32,
+           "algorithmic_GB/s": round(alg / (ms * 1e-3) / 1e9, 1),
+           "frac": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    del lat
+    torch.cuda.empty_cache()
+    return out
 
 
 def steps_per_launch(b, tb):

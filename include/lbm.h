@@ -64,7 +64,7 @@ typedef struct {
   double rho;          /* density > 0                                            */
   int32_t bc;          /* lbm_bc                                                 */
   int32_t model;       /* lbm_model                                              */
-  uint32_t flags;      /* 0 or LBM_F_PLANE_LAYOUT                                 */
+  uint32_t flags;      /* 0 or LBM_F_PLANE_LAYOUT | LBM_F_DISPLACEMENT | ...      */
 } lbm_params;
 
 /* Population layout in the workspace (both: 20 FP32 planes, x fastest, rows
@@ -72,6 +72,19 @@ typedef struct {
  * of one lattice row contiguous.  LBM_F_PLANE_LAYOUT: plane-major
  * [plane][y][x].  Results are bitwise identical; only speed differs. */
 #define LBM_F_PLANE_LAYOUT 1u
+
+/* LBM_F_DISPLACEMENT: the workspace also holds a displacement state
+ * [2][ny][nx] FP32, integrated by the trapezoidal rule (Section 3.5) inside
+ * every step (16 B per node); see lbm_init_displacement.  Single lattices
+ * only. */
+#define LBM_F_DISPLACEMENT 2u
+
+/* LBM_F_ALLOW_UNSTABLE: accept parameters that violate the CFL-like
+ * condition Eq. stab_cond, to reproduce the divergence of the unstable pair
+ * of Section 6.2.  Above the limit some g_ij is not positive definite and the
+ * weighted norm does not exist: lbm_energy then returns the plain sum of
+ * squares of the populations.  Single lattices only. */
+#define LBM_F_ALLOW_UNSTABLE 4u
 
 /* Device bytes the workspace must provide for these parameters (0 if the
  * parameters are invalid). */
@@ -101,7 +114,9 @@ lbm_status lbm_init(lbm_ctx* ctx, const double* d_v0, const double* d_sigma0,
 
 /* Load FP32 populations directly ([4][5][ny][nx], pre-collision, directions
  * in the paper's order (1,0),(0,1),(-1,0),(0,-1), components of U) at step
- * counter 0, with zero body load.  For checkpoints and parity tests. */
+ * counter 0, collided with the body load of t_0 (if one is set; Eq. cond_eq).
+ * For checkpoints and parity tests;
+ * a context with LBM_F_DISPLACEMENT still needs lbm_init_displacement. */
 lbm_status lbm_set_populations(lbm_ctx* ctx, const float* d_f);
 
 /* Time-dependent Dirichlet data (Eq. bc_ansatz with source Eq. bc_s) in
@@ -121,6 +136,64 @@ lbm_status lbm_set_populations(lbm_ctx* ctx, const float* d_f);
  * and must stay valid while stepping. */
 lbm_status lbm_set_wall_velocity(lbm_ctx* ctx, int32_t rank, const float* d_W,
                                  const float* d_T, int64_t nsteps);
+
+/* Body load b_bar = rho b (Eq. cond_eq: B_hat = dt b_bar / rho) in separable
+ * form: at node (k, l) and time level t_n
+ *   b_bar_a(x_k, y_l, t_n) = sum_r d_X[r][a][k] * d_Y[r][l] * d_T[n][r],
+ * a = x, y component (a product of a function of x, a function of y and a
+ * function of t per term, e.g. the expansion of sin(a x + b y + w t)).
+ *   rank   R in 0..4096 (0 = no load; pointers may then be NULL)
+ *   d_X    [R][2][nx] FP32,  d_Y  [R][ny] FP32,
+ *   d_T    [nsteps + 1][R] FP32, row n = time functions at t_n
+ * The load enters the initialisation (Eq. ic_second), the collision
+ * (U_num = sum f + B_hat / 2 at every collision) and every output at the
+ * current level.  Steps beyond nsteps are rejected by lbm_step; steps with a
+ * load run one launch per step of the one-node-per-thread kernel (no
+ * temporal blocking).  Set it before lbm_init to include B_hat(0) in the
+ * initialisation.  Pointers are kept (not copied) and must stay valid while
+ * stepping. */
+lbm_status lbm_set_body_force(lbm_ctx* ctx, int32_t rank, const float* d_X, const float* d_Y,
+                              const float* d_T, int64_t nsteps);
+
+/* Start the displacement output (Section 3.5, Eq. trapezoidal: u(t_{n+1}) =
+ * u(t_n) + dt/2 (v(t_n) + v(t_{n+1}))) from u0 = d_u0 [2][ny][nx] FP64, right
+ * after lbm_init (step counter 0).  The workspace keeps D = u + dt/2 v_num
+ * in FP64 (a running sum: FP32 would round the whole displacement at every
+ * half step); each step adds dt/2 v_num twice.  Requires LBM_F_DISPLACEMENT;
+ * lbm_step rejects a context with the flag until this has been called.
+ * Steps of such a context run one launch per step (no temporal blocking). */
+lbm_status lbm_init_displacement(lbm_ctx* ctx, const double* d_u0);
+
+/* Displacement u(t_n) = D - dt/2 v_num(t_n) at the current step, [2][ny][nx]
+ * FP32 (x then y component). */
+lbm_status lbm_displacement(lbm_ctx* ctx, float* d_u);
+
+/* ---- error norms against an exact solution (Section 6.1) ------------------
+ * The exact outputs in separable form, FP64: at node (k, l) and level t_n
+ *   phi_c(x_k, y_l, t_n) = sum_r d_X[r][c][k] * d_Y[r][l] * d_T[n][r],
+ * c = u_x, u_y, v_x, v_y, sigma_xx, sigma_yy, sigma_xy (Cauchy stress).
+ *   rank   R in 0..4096 (0 removes the reference and stops tracking)
+ *   d_X    [R][7][nx],  d_Y  [R][ny],  d_T  [nsteps + 1][R]
+ * Pointers are kept (not copied) and must stay valid while tracking. */
+lbm_status lbm_set_reference(lbm_ctx* ctx, int32_t rank, const double* d_X, const double* d_Y,
+                             const double* d_T, int64_t nsteps);
+
+/* on != 0: zero the running sums, add the current level, and from then on
+ * add every level lbm_step forms (steps then run one launch per step);
+ * on == 0: stop adding.  lbm_init and lbm_set_populations stop tracking.
+ * Per level and node the numerical outputs are formed as lbm_moments and
+ * lbm_displacement form them (the displacement group needs
+ * LBM_F_DISPLACEMENT and lbm_init_displacement, else it stays zero) and the
+ * differences to phi are summed in FP64 with fixed-order reductions. */
+lbm_status lbm_error_track(lbm_ctx* ctx, int32_t on);
+
+/* Running sums since tracking started, h_out[10] FP64: for the groups
+ * u (u_x, u_y), v (v_x, v_y) and sigma (3 components), in that order,
+ * sum over levels and nodes of |e|^2, of |phi|^2 and the maximum of
+ * |e|_inf; then the number of levels added.  The norms of Section 6.1
+ * follow as L2(e) = (dx^2 dt sum |e|^2)^(1/2), L2rel = (sum |e|^2 /
+ * sum |phi|^2)^(1/2), Linfrel = max |e|_inf / L2(phi).  Synchronises. */
+lbm_status lbm_error_sums(lbm_ctx* ctx, double* h_out);
 
 /* Advance n >= 0 time steps (Section 3.6: collision with omega = 2, then
  * streaming with periodic wrap or the Dirichlet rule), asynchronously. */
@@ -193,7 +266,7 @@ lbm_status lbm_autotune(lbm_ctx* ctx, int32_t reps, int32_t use_cache, int32_t* 
  * identical to T single steps.  Variants (h_steps = T in 2..7) differ in rows
  * per segment, store type and rows prefetched ahead (h_prefetch); h_seg_rows
  * 0 means the segment length is chosen at launch so that one wave per
- * resident slot covers the grid.  index -1 disables blocking; lbm_autotune
+ * resident slot covers the grid, -k that k waves per slot do.  index -1 disables blocking; lbm_autotune
  * selects a variant when it is faster per step than the best single-step
  * configuration.  With a variant of T steps enabled, lbm_step(n) runs the
  * steps in chunks of 420 (a multiple of every T offered), T per launch, and

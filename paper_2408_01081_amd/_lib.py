@@ -37,6 +37,12 @@ SIGNATURES = [
     ("lbm_init", ctypes.c_int, [_VP, _VP, _VP, _VP]),
     ("lbm_set_populations", ctypes.c_int, [_VP, _VP]),
     ("lbm_set_wall_velocity", ctypes.c_int, [_VP, _I32, _VP, _VP, _I64]),
+    ("lbm_set_body_force", ctypes.c_int, [_VP, _I32, _VP, _VP, _VP, _I64]),
+    ("lbm_init_displacement", ctypes.c_int, [_VP, _VP]),
+    ("lbm_displacement", ctypes.c_int, [_VP, _VP]),
+    ("lbm_set_reference", ctypes.c_int, [_VP, _I32, _VP, _VP, _VP, _I64]),
+    ("lbm_error_track", ctypes.c_int, [_VP, _I32]),
+    ("lbm_error_sums", ctypes.c_int, [_VP, _PD]),
     ("lbm_step", ctypes.c_int, [_VP, _I64]),
     ("lbm_step_count", _I64, [_VP]),
     ("lbm_moments", ctypes.c_int, [_VP, _VP]),

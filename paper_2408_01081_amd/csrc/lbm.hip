@@ -7,7 +7,7 @@
 //                collision, rounded once to FP32 (one pass, 40 B in/80 B out).
 //   k_step       fused pull-stream + collide, FP32, memory bound
 //                (80 B read + 80 B written per node and step).
-//   k_moments    U(t_n) = sum_q f*_q  and the outputs of Section 3.5.
+//   k_moments    U(t_n) = sum_q f*_q - B_hat(t_n)/2 and the outputs of Section 3.5.
 //   k_reduce_*   FP64 block reductions (energy, rel-L2), deterministic order.
 #include <hip/hip_runtime.h>
 
@@ -48,18 +48,64 @@ constexpr int RED_THREADS = 256;
 __global__ __launch_bounds__(256) void k_init(const double* __restrict__ v0,
                                               const double* __restrict__ s0,
                                               const double* __restrict__ grad,
-                                              float* __restrict__ dst, Grid g, InitConst k) {
+                                              float* __restrict__ dst, Grid g, InitConst k,
+                                              Force F) {
   const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t n = (int64_t)g.nx * g.ny;
   if (id >= n) return;
   const int y = (int)(id / g.nx), x = (int)(id - (int64_t)y * g.nx);
-  init_node<double>(v0, s0, grad, dst, g, k, x, y);
+  init_node<double>(v0, s0, grad, dst, g, k, x, y, F);
+}
+
+// U_num(t_n) of a node from its stored post-collision populations:
+// sum_q f*_q = U_num + B_hat / 2, so U_num = sum_q f*_q - B_hat / 2
+__device__ inline void node_moment(const float f[NQ][NC], const Force& F, int x, int y,
+                                   float U[NC]) {
+  moment0(f, U);
+  if (F.rank > 0) {
+    float bx, by;
+    body_hat(F, x, y, bx, by);
+    U[0] -= 0.5f * bx;
+    U[1] -= 0.5f * by;
+  }
+}
+
+// Displacement state after initialisation: D = u0 + dt/2 v_num(t_0)
+__global__ __launch_bounds__(256) void k_init_disp(const float* __restrict__ src,
+                                                   const double* __restrict__ u0,
+                                                   double* __restrict__ D, Grid g, Force F,
+                                                   double half_dt) {
+  const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n = (int64_t)g.nx * g.ny;
+  if (id >= n) return;
+  const int y = (int)(id / g.nx), x = (int)(id - (int64_t)y * g.nx);
+  float f[NQ][NC], U[NC];
+  for (int q = 0; q < NQ; ++q)
+    for (int c = 0; c < NC; ++c) f[q][c] = src[pidx(g, q * NC + c, y, x)];
+  node_moment(f, F, x, y, U);
+  for (int d = 0; d < 2; ++d) D[d * n + id] = u0[d * n + id] + half_dt * (double)U[d];
+}
+
+// Displacement output u(t_n) = D - dt/2 v_num(t_n) (D holds u(t_n) + dt/2 v_num(t_n))
+__global__ __launch_bounds__(256) void k_displacement(const float* __restrict__ src,
+                                                      const double* __restrict__ D,
+                                                      float* __restrict__ out, Grid g, Force F,
+                                                      double half_dt) {
+  const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n = (int64_t)g.nx * g.ny;
+  if (id >= n) return;
+  const int y = (int)(id / g.nx), x = (int)(id - (int64_t)y * g.nx);
+  float f[NQ][NC], U[NC];
+  for (int q = 0; q < NQ; ++q)
+    for (int c = 0; c < NC; ++c) f[q][c] = src[pidx(g, q * NC + c, y, x)];
+  node_moment(f, F, x, y, U);
+  for (int d = 0; d < 2; ++d) out[d * n + id] = (float)(D[d * n + id] - half_dt * (double)U[d]);
 }
 
 // load pre-collision FP32 populations [4][5][ny][nx] and collide (FP32)
 __global__ __launch_bounds__(256) void k_set_populations(const float* __restrict__ fin,
                                                          float* __restrict__ dst, Grid g,
-                                                         float kK, float km) {
+                                                         float kK, float km, Force F) {
   const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t n = (int64_t)g.nx * g.ny;
   if (id >= n) return;
@@ -67,7 +113,17 @@ __global__ __launch_bounds__(256) void k_set_populations(const float* __restrict
   float f[NQ][NC];
   for (int q = 0; q < NQ; ++q)
     for (int c = 0; c < NC; ++c) f[q][c] = fin[(q * NC + c) * n + id];
-  collide(kK, km, f);
+  if (F.rank > 0) {
+    float U[NC];
+    moment0(f, U);
+    float bx, by;
+    body_hat(F, x, y, bx, by);
+    U[0] += 0.5f * bx;
+    U[1] += 0.5f * by;
+    collide_with(kK, km, U, f);
+  } else {
+    collide(kK, km, f);
+  }
   for (int q = 0; q < NQ; ++q)
     for (int c = 0; c < NC; ++c) dst[pidx(g, q * NC + c, y, x)] = f[q][c];
 }
@@ -79,7 +135,8 @@ struct MomConst {
 };
 
 __global__ __launch_bounds__(256) void k_moments(const float* __restrict__ src,
-                                                 float* __restrict__ out, Grid g, MomConst m) {
+                                                 float* __restrict__ out, Grid g, MomConst m,
+                                                 Force F) {
   const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t n = (int64_t)g.nx * g.ny;
   if (id >= n) return;
@@ -88,13 +145,20 @@ __global__ __launch_bounds__(256) void k_moments(const float* __restrict__ src,
   for (int q = 0; q < NQ; ++q)
     for (int c = 0; c < NC; ++c) f[q][c] = src[pidx(g, q * NC + c, y, x)];
   if (m.mode == 2) {
-    collide(m.kK, m.km, f);  // the omega = 2 collision is an involution
+    // f = 2 f_eq(U_num) - f*: without a load the collision is an involution
+    if (F.rank > 0) {
+      float U[NC];
+      node_moment(f, F, x, y, U);
+      collide_with(m.kK, m.km, U, f);
+    } else {
+      collide(m.kK, m.km, f);
+    }
     for (int q = 0; q < NQ; ++q)
       for (int c = 0; c < NC; ++c) out[(q * NC + c) * n + id] = f[q][c];
     return;
   }
   float U[NC];
-  for (int c = 0; c < NC; ++c) U[c] = (f[0][c] + f[1][c]) + (f[2][c] + f[3][c]);
+  node_moment(f, F, x, y, U);
   if (m.mode == 1) {
     for (int c = 0; c < NC; ++c) out[c * n + id] = U[c];
     return;
@@ -122,11 +186,14 @@ __device__ inline double block_sum(double v, double* sh) {
   return r;
 }
 
-// mode 0: energy sum_q f*^T k_q f* ; mode 1: rel-L2 partial sums vs ref
+// mode 0: energy sum_q f^T k_q f of the pre-collision populations (without
+// a load the collision is an isometry of this norm, so f* serves); mode 1:
+// rel-L2 partial sums of U_num vs ref
 __global__ __launch_bounds__(RED_THREADS) void k_reduce(const float* __restrict__ src,
                                                         const double* __restrict__ ref, Grid g,
                                                         NormConst nc, int mode,
-                                                        double* __restrict__ partial) {
+                                                        double* __restrict__ partial, Force F,
+                                                        float kK, float km) {
   __shared__ double sh[RED_THREADS];
   const int64_t n = (int64_t)g.nx * g.ny;
   double a = 0.0, b = 0.0;
@@ -134,8 +201,16 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce(const float* __restrict_
        id += (int64_t)gridDim.x * RED_THREADS) {
     const int y = (int)(id / g.nx), x = (int)(id - (int64_t)y * g.nx);
     double f[NQ][NC];
+    float fs[NQ][NC];
     for (int q = 0; q < NQ; ++q)
-      for (int c = 0; c < NC; ++c) f[q][c] = (double)src[pidx(g, q * NC + c, y, x)];
+      for (int c = 0; c < NC; ++c) fs[q][c] = src[pidx(g, q * NC + c, y, x)];
+    if (F.rank > 0 && mode == 0) {
+      float U[NC];
+      node_moment(fs, F, x, y, U);
+      collide_with(kK, km, U, fs);
+    }
+    for (int q = 0; q < NQ; ++q)
+      for (int c = 0; c < NC; ++c) f[q][c] = (double)fs[q][c];
     if (mode == 0) {
       for (int q = 0; q < NQ; ++q)
         for (int r = 0; r < NC; ++r) {
@@ -144,11 +219,12 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce(const float* __restrict_
           a += f[q][r] * t;
         }
     } else {
+      // U from the stored post-collision state, in FP32 like the moments
+      // kernel, then widened
+      float U[NC];
+      node_moment(fs, F, x, y, U);
       for (int c = 0; c < NC; ++c) {
-        // U from the stored post-collision state, summed in FP32 like the
-        // moments kernel, then widened
-        const float u32 = ((float)f[0][c] + (float)f[1][c]) + ((float)f[2][c] + (float)f[3][c]);
-        const double d = (double)u32 - ref[c * n + id];
+        const double d = (double)U[c] - ref[c * n + id];
         a += d * d;
         b += ref[c * n + id] * ref[c * n + id];
       }
@@ -177,6 +253,106 @@ __global__ __launch_bounds__(RED_THREADS) void k_reduce_final(const double* __re
     out[0] = sa;
     out[1] = sb;
   }
+}
+
+// ---- space-time error norms against an exact solution (Section 6.1) -------
+// Exact fields of the outputs in separable form, FP64:
+//   phi_c(x_k, y_l, t_n) = sum_r X[r][c][k] Y[r][l] T[n][r],
+// c = u_x, u_y, v_x, v_y, sigma_bar_xx, sigma_bar_yy, sigma_bar_xy.
+struct RefTable {
+  const double* X;     // [rank][ERR_C][nx]
+  const double* Y;     // [rank][ny]
+  const double* Trow;  // [rank] of this time level
+  int rank, nx, ny;
+};
+constexpr int ERR_C = 7;
+// per group (0: u, 1: v, 2: sigma_bar): sum |e|^2, sum |exact|^2, max |e|_inf
+constexpr int ERR_VALS = 9;
+constexpr int ERR_ACC = ERR_VALS + 1;  // + number of levels added
+
+__device__ inline double block_max(double v, double* sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = RED_THREADS / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + s]);
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+// Per-block error sums of one time level: numerical outputs formed exactly as
+// the moments and displacement kernels form them (U in FP32, u in FP64),
+// compared in FP64 with the exact fields.
+__global__ __launch_bounds__(RED_THREADS) void k_err_partial(const float* __restrict__ src,
+                                                             const double* __restrict__ D,
+                                                             Grid g, Force F, RefTable R,
+                                                             MomConst m, double half_dt,
+                                                             double* __restrict__ partial) {
+  __shared__ double sh[RED_THREADS];
+  const int64_t n = (int64_t)g.nx * g.ny;
+  double e2[3] = {0, 0, 0}, x2[3] = {0, 0, 0}, em[3] = {0, 0, 0};
+  for (int64_t id = (int64_t)blockIdx.x * RED_THREADS + threadIdx.x; id < n;
+       id += (int64_t)gridDim.x * RED_THREADS) {
+    const int y = (int)(id / g.nx), x = (int)(id - (int64_t)y * g.nx);
+    float f[NQ][NC], U[NC];
+    for (int q = 0; q < NQ; ++q)
+      for (int c = 0; c < NC; ++c) f[q][c] = src[pidx(g, q * NC + c, y, x)];
+    node_moment(f, F, x, y, U);
+    double num[ERR_C];
+    num[0] = D ? D[id] - half_dt * (double)U[0] : 0.0;
+    num[1] = D ? D[n + id] - half_dt * (double)U[1] : 0.0;
+    num[2] = U[0];
+    num[3] = U[1];
+    num[4] = -m.rho * (m.cK * U[2] + m.cmu * U[3]);
+    num[5] = -m.rho * (m.cK * U[2] - m.cmu * U[3]);
+    num[6] = -m.rho * (m.cmu * U[4]);
+    double ex[ERR_C] = {0, 0, 0, 0, 0, 0, 0};
+    for (int r = 0; r < R.rank; ++r) {
+      const double yt = R.Y[(int64_t)r * R.ny + y] * R.Trow[r];
+      const double* X = R.X + (int64_t)r * ERR_C * R.nx + x;
+      for (int c = 0; c < ERR_C; ++c) ex[c] = fma(X[(int64_t)c * R.nx], yt, ex[c]);
+    }
+    for (int c = D ? 0 : 2; c < ERR_C; ++c) {
+      const int grp = c < 2 ? 0 : (c < 4 ? 1 : 2);
+      const double d = num[c] - ex[c];
+      e2[grp] += d * d;
+      x2[grp] += ex[c] * ex[c];
+      em[grp] = fmax(em[grp], fabs(d));
+    }
+  }
+  for (int k = 0; k < 3; ++k) {
+    const double a = block_sum(e2[k], sh);
+    const double b = block_sum(x2[k], sh);
+    const double c = block_max(em[k], sh);
+    if (threadIdx.x == 0) {
+      partial[ERR_VALS * blockIdx.x + 3 * k] = a;
+      partial[ERR_VALS * blockIdx.x + 3 * k + 1] = b;
+      partial[ERR_VALS * blockIdx.x + 3 * k + 2] = c;
+    }
+  }
+}
+
+// Adds one level's block partials (fixed order) to the running sums.
+__global__ __launch_bounds__(RED_THREADS) void k_err_final(const double* __restrict__ partial,
+                                                           int nblocks, double* __restrict__ acc) {
+  __shared__ double sh[RED_THREADS];
+  for (int k = 0; k < ERR_VALS; ++k) {
+    const bool is_max = k % 3 == 2;
+    double v = 0.0;
+    for (int i = threadIdx.x; i < nblocks; i += RED_THREADS) {
+      const double p = partial[ERR_VALS * i + k];
+      v = is_max ? fmax(v, p) : v + p;
+    }
+    const double r = is_max ? block_max(v, sh) : block_sum(v, sh);
+    if (threadIdx.x == 0) acc[k] = is_max ? fmax(acc[k], r) : acc[k] + r;
+  }
+  if (threadIdx.x == 0) acc[ERR_VALS] += 1.0;
+}
+
+__global__ void k_err_zero(double* acc) {
+  if (threadIdx.x < ERR_ACC) acc[threadIdx.x] = 0.0;
 }
 
 // plain streaming copy, 16 bytes per lane and access, nontemporal stores
@@ -223,6 +399,23 @@ struct lbm_ctx {
   int tb_cfg;         // index into kTBConfigs, or -1 (single steps only)
   int tb_slots[64];   // resident waves of a blocked variant on this device (0: not known)
   float* wall_v;        // [WALL_CHUNK][2 (nx + ny)][2] wall velocities of upcoming steps
+  // separable body load (rank 0: none); row n of force_T belongs to t_n
+  const float* force_X;
+  const float* force_Y;
+  const float* force_T;
+  int force_rank;
+  int64_t force_nsteps;
+  double* disp;  // [2][ny][nx] FP64 displacement state D, or null (LBM_F_DISPLACEMENT)
+  bool disp_ready;
+  // exact solution for the error norms (rank 0: none)
+  const double* ref_X;
+  const double* ref_Y;
+  const double* ref_T;
+  int ref_rank;
+  int64_t ref_nsteps;
+  bool err_on;
+  double* err_part;  // [RED_BLOCKS][ERR_VALS] block partials
+  double* err_acc;   // [ERR_ACC] running sums
 };
 
 namespace {
@@ -237,9 +430,56 @@ size_t wall_table_bytes(const Grid& g, int bc) {
   return (size_t)round_up((int64_t)WALL_CHUNK * 2 * (g.nx + g.ny) * 2 * 4, 256);
 }
 
-size_t ws_bytes(const Grid& g, int bc) {
+size_t disp_bytes(const Grid& g, uint32_t flags) {
+  if (!(flags & LBM_F_DISPLACEMENT)) return 0;
+  return (size_t)round_up((int64_t)2 * g.nx * g.ny * 8, 256);
+}
+
+constexpr size_t ERR_BYTES = (size_t)(RED_BLOCKS * ERR_VALS + 16) * 8;
+
+size_t ws_bytes(const Grid& g, int bc, uint32_t flags) {
   return 2 * state_bytes(g) + (size_t)round_up((2 * RED_BLOCKS + 2) * 8, 256) +
-         wall_table_bytes(g, bc);
+         wall_table_bytes(g, bc) + disp_bytes(g, flags) + ERR_BYTES;
+}
+
+RefTable ref_at(const lbm_ctx* c, int64_t n) {
+  RefTable R;
+  R.X = c->ref_X;
+  R.Y = c->ref_Y;
+  R.Trow = c->ref_T + n * c->ref_rank;
+  R.rank = c->ref_rank;
+  R.nx = c->g.nx;
+  R.ny = c->g.ny;
+  return R;
+}
+
+
+// body load of time level n (rank 0 without load data)
+Force force_at(const lbm_ctx* c, int64_t n) {
+  Force F;
+  F.rank = c->force_rank;
+  F.X = c->force_X;
+  F.Y = c->force_Y;
+  F.Trow = c->force_rank ? c->force_T + n * c->force_rank : nullptr;
+  F.nx = c->g.nx;
+  F.ny = c->g.ny;
+  F.scale = (float)(c->p.dt / c->p.rho);
+  return F;
+}
+
+// add the errors of the state in the current buffer (time level `level`)
+// to the running sums
+void err_accumulate(lbm_ctx* c, int64_t level) {
+  const int64_t n = (int64_t)c->g.nx * c->g.ny;
+  int nb = (int)((n + RED_THREADS - 1) / RED_THREADS);
+  nb = nb > RED_BLOCKS ? RED_BLOCKS : nb;
+  MomConst m{(float)c->cK, (float)c->cmu, (float)c->p.rho, (float)c->kK, (float)c->km, 0};
+  hipLaunchKernelGGL(k_err_partial, dim3(nb), dim3(RED_THREADS), 0, c->stream,
+                     (const float*)c->buf[c->cur], (const double*)(c->disp_ready ? c->disp : nullptr),
+                     c->g, force_at(c, level), ref_at(c, level), m, 0.5 * c->p.dt,
+                     c->err_part);
+  hipLaunchKernelGGL(k_err_final, dim3(1), dim3(RED_THREADS), 0, c->stream,
+                     (const double*)c->err_part, nb, c->err_acc);
 }
 
 // V[s][link][2] = wall velocity of step `step0 + s` at every link
@@ -264,7 +504,8 @@ lbm_status reduce(lbm_ctx* c, int mode, const double* ref, double out[2]) {
   int nb = (int)((n + RED_THREADS - 1) / RED_THREADS);
   nb = nb > RED_BLOCKS ? RED_BLOCKS : nb;
   hipLaunchKernelGGL(k_reduce, dim3(nb), dim3(RED_THREADS), 0, c->stream, c->buf[c->cur], ref,
-                     c->g, c->norm, mode, c->partial);
+                     c->g, c->norm, mode, c->partial, force_at(c, c->nstep), (float)c->kK,
+                     (float)c->km);
   hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(RED_THREADS), 0, c->stream, c->partial, nb,
                      c->partial + 2 * RED_BLOCKS);
   lbm_status s = launch_check("reduce launch");
@@ -288,7 +529,7 @@ const char* lbm_last_error(void) { return g_err.c_str(); }
 size_t lbm_workspace_bytes(const lbm_params* p) {
   Derived d;
   if (derive(p, &d) != LBM_OK) return 0;
-  return ws_bytes(make_grid(p), p->bc);
+  return ws_bytes(make_grid(p), p->bc, p->flags);
 }
 
 lbm_status lbm_create(const lbm_params* p, void* d_ws, size_t ws_size, void* hip_stream,
@@ -300,9 +541,15 @@ lbm_status lbm_create(const lbm_params* p, void* d_ws, size_t ws_size, void* hip
   if (!d_ws) return fail(LBM_E_ARG, "null workspace");
   if (((uintptr_t)d_ws & 255) != 0) return fail(LBM_E_ARG, "workspace not 256-byte aligned");
   const Grid g = make_grid(p);
-  if (ws_size < ws_bytes(g, p->bc)) return fail(LBM_E_SPACE, "workspace too small");
+  if (ws_size < ws_bytes(g, p->bc, p->flags)) return fail(LBM_E_SPACE, "workspace too small");
   NormConst nc;
-  if (!norm_weights(d.kK, d.km, nc.k)) return fail(LBM_E_CFL, "g_ij not positive definite");
+  if (!norm_weights(d.kK, d.km, nc.k)) {
+    if (!(p->flags & LBM_F_ALLOW_UNSTABLE)) return fail(LBM_E_CFL, "g_ij not positive definite");
+    // above the limit the weighted norm does not exist: plain sum of squares
+    for (int q = 0; q < NQ; ++q)
+      for (int a = 0; a < NC; ++a)
+        for (int b = 0; b < NC; ++b) nc.k[q][a][b] = a == b ? 1.0 : 0.0;
+  }
   lbm_ctx* c = new (std::nothrow) lbm_ctx();
   if (!c) return fail(LBM_E_ARG, "out of host memory");
   c->p = *p;
@@ -315,6 +562,23 @@ lbm_status lbm_create(const lbm_params* p, void* d_ws, size_t ws_size, void* hip
                   ? (float*)((char*)d_ws + 2 * state_bytes(g) +
                              (size_t)round_up((2 * RED_BLOCKS + 2) * 8, 256))
                   : nullptr;
+  c->disp = (p->flags & LBM_F_DISPLACEMENT)
+                ? (double*)((char*)d_ws + 2 * state_bytes(g) +
+                           (size_t)round_up((2 * RED_BLOCKS + 2) * 8, 256) +
+                           wall_table_bytes(g, p->bc))
+                : nullptr;
+  c->disp_ready = false;
+  c->err_part = (double*)((char*)d_ws + 2 * state_bytes(g) +
+                          (size_t)round_up((2 * RED_BLOCKS + 2) * 8, 256) +
+                          wall_table_bytes(g, p->bc) + disp_bytes(g, p->flags));
+  c->err_acc = c->err_part + (size_t)RED_BLOCKS * ERR_VALS;
+  c->err_on = false;
+  c->ref_X = c->ref_Y = c->ref_T = nullptr;
+  c->ref_rank = 0;
+  c->ref_nsteps = 0;
+  c->force_X = c->force_Y = c->force_T = nullptr;
+  c->force_rank = 0;
+  c->force_nsteps = 0;
   c->cur = 0;
   c->initialised = false;
   c->nstep = 0;
@@ -353,25 +617,110 @@ lbm_status lbm_init(lbm_ctx* c, const double* d_v0, const double* d_sigma0, cons
   const int64_t n = (int64_t)c->g.nx * c->g.ny;
   InitConst k{c->kK, c->km, c->cK, c->cmu, c->p.rho, c->p.dx, c->p.bc};
   hipLaunchKernelGGL(k_init, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, d_v0,
-                     d_sigma0, d_grad, c->buf[0], c->g, k);
+                     d_sigma0, d_grad, c->buf[0], c->g, k, force_at(c, 0));
   lbm_status s = launch_check("k_init launch");
   if (s) return s;
   c->cur = 0;
   c->nstep = 0;
   c->initialised = true;
+  c->disp_ready = false;
+  c->err_on = false;
   return LBM_OK;
+}
+
+lbm_status lbm_set_body_force(lbm_ctx* c, int32_t rank, const float* d_X, const float* d_Y,
+                              const float* d_T, int64_t nsteps) {
+  if (!c) return fail(LBM_E_ARG, "null ctx");
+  if (rank < 0 || rank > 4096) return fail(LBM_E_ARG, "rank out of range");
+  if (rank > 0 && (!d_X || !d_Y || !d_T || nsteps < 0)) return fail(LBM_E_ARG, "null load table");
+  c->force_rank = rank;
+  c->force_X = rank ? d_X : nullptr;
+  c->force_Y = rank ? d_Y : nullptr;
+  c->force_T = rank ? d_T : nullptr;
+  c->force_nsteps = rank ? nsteps : 0;
+  return LBM_OK;
+}
+
+lbm_status lbm_init_displacement(lbm_ctx* c, const double* d_u0) {
+  if (!c || !d_u0) return fail(LBM_E_ARG, "null argument");
+  if (!c->disp) return fail(LBM_E_STATE, "context created without LBM_F_DISPLACEMENT");
+  if (!c->initialised || c->nstep != 0)
+    return fail(LBM_E_STATE, "lbm_init_displacement needs a freshly initialised lattice");
+  const int64_t n = (int64_t)c->g.nx * c->g.ny;
+  hipLaunchKernelGGL(k_init_disp, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream,
+                     (const float*)c->buf[c->cur], d_u0, c->disp, c->g, force_at(c, 0),
+                     0.5 * c->p.dt);
+  lbm_status s = launch_check("k_init_disp launch");
+  if (s) return s;
+  c->disp_ready = true;
+  return LBM_OK;
+}
+
+lbm_status lbm_displacement(lbm_ctx* c, float* d_u) {
+  if (!c || !d_u) return fail(LBM_E_ARG, "null argument");
+  if (!c->disp || !c->disp_ready)
+    return fail(LBM_E_STATE, "no displacement: LBM_F_DISPLACEMENT and lbm_init_displacement");
+  const int64_t n = (int64_t)c->g.nx * c->g.ny;
+  hipLaunchKernelGGL(k_displacement, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream,
+                     (const float*)c->buf[c->cur], (const double*)c->disp, d_u, c->g,
+                     force_at(c, c->nstep), 0.5 * c->p.dt);
+  return launch_check("k_displacement launch");
+}
+
+lbm_status lbm_set_reference(lbm_ctx* c, int32_t rank, const double* d_X, const double* d_Y,
+                             const double* d_T, int64_t nsteps) {
+  if (!c) return fail(LBM_E_ARG, "null ctx");
+  if (rank < 0 || rank > 4096) return fail(LBM_E_ARG, "rank out of range");
+  if (rank > 0 && (!d_X || !d_Y || !d_T || nsteps < 0))
+    return fail(LBM_E_ARG, "null reference table");
+  c->ref_rank = rank;
+  c->ref_X = rank ? d_X : nullptr;
+  c->ref_Y = rank ? d_Y : nullptr;
+  c->ref_T = rank ? d_T : nullptr;
+  c->ref_nsteps = rank ? nsteps : 0;
+  if (!rank) c->err_on = false;
+  return LBM_OK;
+}
+
+lbm_status lbm_error_track(lbm_ctx* c, int32_t on) {
+  if (!c) return fail(LBM_E_ARG, "null ctx");
+  if (!on) {
+    c->err_on = false;
+    return LBM_OK;
+  }
+  if (c->ref_rank == 0) return fail(LBM_E_STATE, "no reference solution (lbm_set_reference)");
+  if (!c->initialised) return fail(LBM_E_STATE, "not initialised");
+  if (c->nstep > c->ref_nsteps) return fail(LBM_E_ARG, "reference table too short");
+  hipLaunchKernelGGL(k_err_zero, dim3(1), dim3(64), 0, c->stream, c->err_acc);
+  err_accumulate(c, c->nstep);
+  lbm_status s = launch_check("error accumulation launch");
+  if (s) return s;
+  c->err_on = true;
+  return LBM_OK;
+}
+
+lbm_status lbm_error_sums(lbm_ctx* c, double* h_out) {
+  if (!c || !h_out) return fail(LBM_E_ARG, "null argument");
+  lbm_status s = hip_check(hipMemcpyAsync(h_out, c->err_acc, ERR_ACC * sizeof(double),
+                                          hipMemcpyDeviceToHost, c->stream),
+                           "error sums copy");
+  if (s) return s;
+  return hip_check(hipStreamSynchronize(c->stream), "error sums sync");
 }
 
 lbm_status lbm_set_populations(lbm_ctx* c, const float* d_f) {
   if (!c || !d_f) return fail(LBM_E_ARG, "null argument");
   const int64_t n = (int64_t)c->g.nx * c->g.ny;
   hipLaunchKernelGGL(k_set_populations, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
-                     c->stream, d_f, c->buf[0], c->g, (float)c->kK, (float)c->km);
+                     c->stream, d_f, c->buf[0], c->g, (float)c->kK, (float)c->km,
+                     force_at(c, 0));
   lbm_status s = launch_check("k_set_populations launch");
   if (s) return s;
   c->cur = 0;
   c->nstep = 0;
   c->initialised = true;
+  c->disp_ready = false;
+  c->err_on = false;
   return LBM_OK;
 }
 
@@ -409,7 +758,8 @@ const TBConfig kTBConfigs[] = {
     LBM_TB(4, 4, 0, 1),  LBM_TB(4, 8, 0, 1),  LBM_TB(4, 4, 1, 1),  LBM_TB(4, 8, 1, 1),
     LBM_TB(4, 12, 1, 1), LBM_TB(5, 16, 0, 1), LBM_TB(5, 32, 0, 1), LBM_TB(5, 16, 1, 1),
     LBM_TB(6, 16, 0, 1), LBM_TB(6, 32, 0, 1), LBM_TB(6, 48, 0, 1), LBM_TB(6, 16, 1, 1),
-    LBM_TB(7, 32, 0, 1), LBM_TB(7, 48, 0, 1), LBM_TB(7, 64, 0, 1), LBM_TB(7, 32, 1, 1)};
+    LBM_TB(7, 32, 0, 1), LBM_TB(7, 48, 0, 1), LBM_TB(7, 64, 0, 1), LBM_TB(7, 32, 1, 1),
+    LBM_TB(7, 0, 0, 1),  LBM_TB(7, -2, 0, 1), LBM_TB(6, 0, 0, 1),  LBM_TB(5, 0, 0, 1)};
 #undef LBM_TB
 constexpr int kNumTBConfigs = (int)(sizeof(kTBConfigs) / sizeof(kTBConfigs[0]));
 static_assert(kNumTBConfigs <= 64, "tb_slots size");
@@ -480,7 +830,8 @@ int tb_seg_rows(lbm_ctx* c, int index) {
   const int ring = 3 + k.pf;
   const int valid = TB_LANES - 2 * k.steps;
   const int nstrips = (c->g.nx + valid - 1) / valid;
-  int nseg = slots / nstrips;
+  const int rounds = k.seg_rows < 0 ? -k.seg_rows : 1;
+  int nseg = slots * rounds / nstrips;
   if (nseg < 1) nseg = 1;
   int rows = (c->g.ny + nseg - 1) / nseg;
   rows = (rows + ring - 1) / ring * ring;
@@ -499,12 +850,58 @@ void launch_tb(lbm_ctx* c, int index, const float* src, float* dst, const WallSe
 
 }  // namespace
 
+// Steps with a body load and/or the displacement state: one step per launch
+// of the one-node-per-thread kernel.  Step n -> n+1 collides at t_{n+1} with
+// the load row of that level.
+static lbm_status step_ext(lbm_ctx* c, int64_t nsteps) {
+  typedef void (*ExtFn)(const float*, float*, Grid, StepConst, Wall, StepExtra);
+  static const ExtFn fns[2][2][2] = {
+      {{&k_step_ext<LBM_PERIODIC, false, false>, &k_step_ext<LBM_PERIODIC, false, true>},
+       {&k_step_ext<LBM_PERIODIC, true, false>, &k_step_ext<LBM_PERIODIC, true, true>}},
+      {{&k_step_ext<LBM_DIRICHLET, false, false>, &k_step_ext<LBM_DIRICHLET, false, true>},
+       {&k_step_ext<LBM_DIRICHLET, true, false>, &k_step_ext<LBM_DIRICHLET, true, true>}}};
+  const Grid& g = c->g;
+  const bool force = c->force_rank > 0, disp = c->disp != nullptr;
+  const ExtFn fn = fns[c->p.bc][force][disp];
+  StepConst sc;
+  sc.kK = (float)c->kK;
+  sc.km = (float)c->km;
+  sc.tiles_x = (g.nx + 255) / 256;
+  sc.ntiles = sc.tiles_x * g.ny;
+  StepExtra ex;
+  ex.D = c->disp;
+  ex.half_dt = 0.5 * c->p.dt;
+  const int64_t base = c->nstep;
+  for (int64_t s0 = 0; s0 < nsteps; s0 += WALL_CHUNK) {
+    const int m = (int)(nsteps - s0 < WALL_CHUNK ? nsteps - s0 : WALL_CHUNK);
+    eval_walls(c, base + s0, m);
+    for (int k = 0; k < m; ++k) {
+      const int64_t level = base + s0 + k + 1;  // the level this step forms
+      ex.F = force_at(c, level);
+      hipLaunchKernelGGL(fn, dim3(sc.ntiles), dim3(256), 0, c->stream,
+                         (const float*)c->buf[c->cur], c->buf[c->cur ^ 1], g, sc, wall_at(c, k),
+                         ex);
+      c->cur ^= 1;
+      if (c->err_on) err_accumulate(c, level);
+    }
+  }
+  c->nstep = base + nsteps;
+  return launch_check("k_step_ext launch");
+}
+
 lbm_status lbm_step(lbm_ctx* c, int64_t nsteps) {
   if (!c) return fail(LBM_E_ARG, "null ctx");
   if (!c->initialised) return fail(LBM_E_STATE, "lbm_step before lbm_init");
   if (nsteps < 0) return fail(LBM_E_ARG, "negative step count");
   if (c->wall_rank > 0 && c->nstep + nsteps > c->wall_nsteps)
     return fail(LBM_E_ARG, "wall table too short for the requested steps");
+  if (c->force_rank > 0 && c->nstep + nsteps > c->force_nsteps)
+    return fail(LBM_E_ARG, "body load table too short for the requested steps");
+  if (c->disp && !c->disp_ready)
+    return fail(LBM_E_STATE, "LBM_F_DISPLACEMENT: lbm_init_displacement before lbm_step");
+  if (c->err_on && c->nstep + nsteps > c->ref_nsteps)
+    return fail(LBM_E_ARG, "reference table too short for the requested steps");
+  if (c->force_rank > 0 || c->disp || c->err_on) return step_ext(c, nsteps);
   const Grid& g = c->g;
   const StepConfig& cfg = kStepConfigs[c->step_cfg];
   const StepConst sc = step_const(cfg, g, (float)c->kK, (float)c->km);
@@ -809,7 +1206,7 @@ static lbm_status moments_mode(lbm_ctx* c, float* out, int mode) {
   const int64_t n = (int64_t)c->g.nx * c->g.ny;
   MomConst m{(float)c->cK, (float)c->cmu, (float)c->p.rho, (float)c->kK, (float)c->km, mode};
   hipLaunchKernelGGL(k_moments, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream,
-                     c->buf[c->cur], out, c->g, m);
+                     c->buf[c->cur], out, c->g, m, force_at(c, c->nstep));
   return launch_check("k_moments launch");
 }
 

@@ -303,7 +303,8 @@ lbm_status plan(int32_t n, const lbm_params* params, Layout* L) {
     Derived dv;
     lbm_status s = derive(&params[i], &dv);
     if (s) return fail(s, "instance " + std::to_string(i) + ": " + g_err);
-    if (params[i].flags != 0) return fail(LBM_E_ARG, "batched instances use the row layout");
+    if (params[i].flags != 0)
+      return fail(LBM_E_ARG, "batched instances take no flags (row layout, no displacement, CFL enforced)");
     InstDesc& d = L->desc[i];
     memset(&d, 0, sizeof d);
     d.g = make_grid(&params[i]);

@@ -81,7 +81,8 @@ inline lbm_status derive(const lbm_params* p, Derived* d) {
   if ((int64_t)p->nx * p->ny > (int64_t)1 << 31) return fail(LBM_E_ARG, "grid too large");
   if (!(p->dx > 0) || !(p->dt > 0) || !(p->rho > 0) || !(p->mu > 0))
     return fail(LBM_E_ARG, "dx, dt, rho, mu must be positive");
-  if (p->flags & ~(uint32_t)LBM_F_PLANE_LAYOUT) return fail(LBM_E_ARG, "unknown flags");
+  if (p->flags & ~(uint32_t)(LBM_F_PLANE_LAYOUT | LBM_F_DISPLACEMENT | LBM_F_ALLOW_UNSTABLE))
+    return fail(LBM_E_ARG, "unknown flags");
   double lam = p->lambda;
   if (p->model == LBM_PLANE_STRESS) {
     if (!(lam + 2.0 * p->mu > 0)) return fail(LBM_E_ARG, "lambda + 2 mu must be positive");
@@ -97,7 +98,7 @@ inline lbm_status derive(const lbm_params* p, Derived* d) {
   d->kK = d->cK / d->c;
   d->km = d->cmu / d->c;
   const double ratio = 2.0 * sqrt(d->kK * d->kK + d->km * d->km);
-  if (!(ratio < 1.0)) {
+  if (!(ratio < 1.0) && !(p->flags & LBM_F_ALLOW_UNSTABLE)) {
     char b[160];
     snprintf(b, sizeof b, "CFL-like condition violated: 2 sqrt(cK^2+cmu^2)/c = %.6f >= 1", ratio);
     return fail(LBM_E_CFL, b);

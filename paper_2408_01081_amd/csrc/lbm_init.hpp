@@ -85,14 +85,30 @@ __device__ inline void lattice_grad(const InitConst& k, const T* v0, const T* s0
   for (int c = 0; c < NC; ++c) G[c] = s * 0.5 * (-3.0 * A[c] + 4.0 * B[c] - C[c]);
 }
 
+// B_hat(x, y, t_0) = (dt / rho) b_bar in FP64 from the separable tables (zero
+// without a load)
+__device__ inline void body_hat0(const Force& F, int x, int y, double& bx, double& by) {
+  double a = 0.0, b = 0.0;
+  for (int r = 0; r < F.rank; ++r) {
+    const double yt = (double)F.Y[(int64_t)r * F.ny + y] * (double)F.Trow[r];
+    const float* X = F.X + (int64_t)r * 2 * F.nx;
+    a += (double)X[x] * yt;
+    b += (double)X[F.nx + x] * yt;
+  }
+  bx = (double)F.scale * a;
+  by = (double)F.scale * b;
+}
+
 // Populations f*(0) of one node (x, y): Eq. ic_second in FP64 followed by the
 // first omega = 2 collision, rounded once to FP32.  v0 [2][ny][nx], s0
 // [3][ny][nx] are the instance's fields (double or float); grad is nullable
-// [2][5][ny][nx] FP64 physical derivatives of (v, sigma_bar).
+// [2][5][ny][nx] FP64 physical derivatives of (v, sigma_bar); F the body
+// load at t_0 (rank 0: none).
 template <typename T>
 __device__ inline void init_node(const T* __restrict__ v0, const T* __restrict__ s0,
                                  const double* __restrict__ grad, float* __restrict__ dst,
-                                 const Grid& g, const InitConst& k, int x, int y) {
+                                 const Grid& g, const InitConst& k, int x, int y,
+                                 const Force& F = Force{}) {
   const int64_t n = (int64_t)g.nx * g.ny;
   const int64_t id = (int64_t)y * g.nx + x;
   double U[NC], UX[NC], UY[NC];
@@ -114,7 +130,12 @@ __device__ inline void init_node(const T* __restrict__ v0, const T* __restrict__
 
   // Eq. ic_second in lattice units (c dt = dx absorbed into UX, UY):
   // f_q = 1/4 [U + 2 C_q U]
-  //   - 1/8 { i UX + (2i^2-1) X(UX) - 2 C_q X(UX) + j UY + (2j^2-1) Y(UY) - 2 C_q Y(UY) }
+  //   - 1/8 { B + 2 C_q B + i UX + (2i^2-1) X(UX) - 2 C_q X(UX)
+  //           + j UY + (2j^2-1) Y(UY) - 2 C_q Y(UY) },  B = (B_hat_x, B_hat_y, 0, 0, 0)
+  double Bh[NC] = {0.0, 0.0, 0.0, 0.0, 0.0}, XB[NC], YB[NC];
+  if (F.rank > 0) body_hat0(F, x, y, Bh[0], Bh[1]);
+  flux_x(k, Bh, XB);
+  flux_y(k, Bh, YB);
   double XU[NC], YU[NC], XUX[NC], YUY[NC], XXUX[NC], YXUX[NC], XYUY[NC], YYUY[NC];
   flux_x(k, U, XU);
   flux_y(k, U, YU);
@@ -130,14 +151,15 @@ __device__ inline void init_node(const T* __restrict__ v0, const T* __restrict__
     const double i = I[q], j = J[q];
     for (int c = 0; c < NC; ++c) {
       const double eq = 0.25 * (U[c] + 2.0 * (i * XU[c] + j * YU[c]));
+      const double cb = Bh[c] + 2.0 * (i * XB[c] + j * YB[c]);
       const double cx = i * UX[c] + (2.0 * i * i - 1.0) * XUX[c] - 2.0 * (i * XXUX[c] + j * YXUX[c]);
       const double cy = j * UY[c] + (2.0 * j * j - 1.0) * YUY[c] - 2.0 * (i * XYUY[c] + j * YYUY[c]);
-      f[q][c] = eq - 0.125 * (cx + cy);
+      f[q][c] = eq - 0.125 * (cb + cx + cy);
     }
   }
   // first collision in FP64 (omega = 2): f* = 2 f_eq(U_num) - f, U_num = sum f
   double Un[NC], Xn[NC], Yn[NC];
-  for (int c = 0; c < NC; ++c) Un[c] = (f[0][c] + f[1][c]) + (f[2][c] + f[3][c]);
+  for (int c = 0; c < NC; ++c) Un[c] = (f[0][c] + f[1][c]) + (f[2][c] + f[3][c]) + 0.5 * Bh[c];
   flux_x(k, Un, Xn);
   flux_y(k, Un, Yn);
   for (int q = 0; q < NQ; ++q) {

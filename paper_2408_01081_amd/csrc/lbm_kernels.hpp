@@ -73,12 +73,16 @@ __device__ inline void wall_rule(int i, int j, float kK, float km, float a, floa
   out[4] = fb[4] + km * (float)(j) * a + km * (float)(i) * b;
 }
 
-// omega = 2 collision of one node: f*_q = h + s_q C U - f_q with h = U/2.
-// Written once so every kernel variant rounds identically.
-__device__ inline void collide(float kK, float km, float f[NQ][NC]) {
-  float U[NC];
+// Zeroth moment sum_q f_q of one node (the scheme's U without the load term).
+__device__ inline void moment0(const float f[NQ][NC], float U[NC]) {
 #pragma unroll
   for (int c = 0; c < NC; ++c) U[c] = (f[0][c] + f[1][c]) + (f[2][c] + f[3][c]);
+}
+
+// omega = 2 collision of one node for a given moment U:
+// f*_q = 2 f_eq,q(U) - f_q = h + s_q C U - f_q with h = U/2 (Eq. feq).
+// Written once so every kernel variant rounds identically.
+__device__ inline void collide_with(float kK, float km, const float U[NC], float f[NQ][NC]) {
   // X = Phi_x(U)/c, Y = Phi_y(U)/c
   const float X0 = fmaf(kK, U[2], km * U[3]);
   const float X1 = km * U[4];
@@ -100,6 +104,36 @@ __device__ inline void collide(float kK, float km, float f[NQ][NC]) {
     f[2][c] = (h - X[c]) - f[2][c];
     f[3][c] = (h - Y[c]) - f[3][c];
   }
+}
+
+// Collision without body load (U = sum_q f_q).
+__device__ inline void collide(float kK, float km, float f[NQ][NC]) {
+  float U[NC];
+  moment0(f, U);
+  collide_with(kK, km, U, f);
+}
+
+// Separable physical body load b_bar_c(x_k, y_l, t) = sum_r X[r][c][k] Y[r][l] T_r(t)
+// of one time level; the scheme uses B_hat = dt b = (dt / rho) b_bar on the
+// velocity components (Eq. cond_eq: U_num = sum_q f_q + B_hat / 2).
+struct Force {
+  const float* X;     // [rank][2][nx]
+  const float* Y;     // [rank][ny]
+  const float* Trow;  // [rank] time functions of this time level
+  int rank, nx, ny;
+  float scale;        // dt / rho
+};
+
+__device__ inline void body_hat(const Force& F, int x, int y, float& bx, float& by) {
+  float a = 0.f, b = 0.f;
+  for (int r = 0; r < F.rank; ++r) {
+    const float yt = F.Y[(int64_t)r * F.ny + y] * F.Trow[r];
+    const float* X = F.X + (int64_t)r * 2 * F.nx;
+    a = fmaf(X[x], yt, a);
+    b = fmaf(X[F.nx + x], yt, b);
+  }
+  bx = F.scale * a;
+  by = F.scale * b;
 }
 
 }  // namespace lbmk

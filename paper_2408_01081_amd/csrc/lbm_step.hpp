@@ -84,12 +84,22 @@ __device__ inline void vstore(float* p, const float in[VEC]) {
     *reinterpret_cast<T*>(p) = v;
 }
 
+// Optional per-node work of a step: body load of the new time level and the
+// trapezoidal displacement update (Section 3.5): with v = v_num of the new
+// level, u = D + dt/2 v is the displacement at that level and D <- u + dt/2 v
+// is kept for the next (D [2][ny][nx], updated in place).
+struct StepExtra {
+  Force F;
+  double* D;       // displacement state u + dt/2 v, FP64 [2][ny][nx]
+  double half_dt;
+};
+
 // One row segment (row y, segment tx) of one lattice: the body shared by the
 // single-lattice and the batched step kernels.
-template <int BC, int VEC, int THREADS, int NT, int XMODE>
+template <int BC, int VEC, int THREADS, int NT, int XMODE, bool FORCE = false, bool DISP = false>
 __device__ inline void step_segment(const float* __restrict__ src, float* __restrict__ dst,
                                     const Grid& g, float kK, float km, const Wall& w, int y,
-                                    int tx) {
+                                    int tx, const StepExtra& ex = StepExtra{}) {
   StepConst sc;
   sc.kK = kK;
   sc.km = km;
@@ -179,7 +189,32 @@ __device__ inline void step_segment(const float* __restrict__ src, float* __rest
   }
 
 #pragma unroll
-  for (int k = 0; k < VEC; ++k) collide(sc.kK, sc.km, f[k]);
+  for (int k = 0; k < VEC; ++k) {
+    if constexpr (FORCE || DISP) {
+      // U_num = sum_q f_q + B_hat / 2 (Eq. cond_eq)
+      float U[NC];
+      moment0(f[k], U);
+      if constexpr (FORCE) {
+        float bx, by;
+        body_hat(ex.F, x0 + k, y, bx, by);
+        U[0] += 0.5f * bx;
+        U[1] += 0.5f * by;
+      }
+      if constexpr (DISP) {
+#pragma unroll
+        for (int d = 0; d < 2; ++d) {
+          // FP64 running sum: FP32 would add a rounding of the full
+          // displacement at every half step
+          double* p = ex.D + ((int64_t)d * ny + y) * nx + x0 + k;
+          const double u = *p + ex.half_dt * (double)U[d];
+          *p = u + ex.half_dt * (double)U[d];
+        }
+      }
+      collide_with(sc.kK, sc.km, U, f[k]);
+    } else {
+      collide(sc.kK, sc.km, f[k]);
+    }
+  }
 
 #pragma unroll
   for (int q = 0; q < NQ; ++q)
@@ -200,6 +235,18 @@ __global__ __launch_bounds__(THREADS) void k_step(const float* __restrict__ src,
   const int y = tile / sc.tiles_x;
   const int tx = tile - y * sc.tiles_x;
   step_segment<BC, VEC, THREADS, NT, XMODE>(src, dst, g, sc.kK, sc.km, w, y, tx);
+}
+
+// Steps with a body load and/or displacement output: one node per thread,
+// 256 threads, plain loads and stores.
+template <int BC, bool FORCE, bool DISP>
+__global__ __launch_bounds__(256) void k_step_ext(const float* __restrict__ src,
+                                                  float* __restrict__ dst, Grid g, StepConst sc,
+                                                  Wall w, StepExtra ex) {
+  const int tile = xcd_tile(blockIdx.x, sc.ntiles);
+  const int y = tile / sc.tiles_x;
+  const int tx = tile - y * sc.tiles_x;
+  step_segment<BC, 1, 256, 0, 0, FORCE, DISP>(src, dst, g, sc.kK, sc.km, w, y, tx, ex);
 }
 
 // ---------------------------------------------------------------------------

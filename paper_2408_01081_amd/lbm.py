@@ -13,7 +13,7 @@ from ._lib import LbmParams, check
 
 PERIODIC, DIRICHLET = 0, 1
 PLANE_STRAIN, PLANE_STRESS, CONTINUUM_2D = 0, 1, 2
-PLANE_LAYOUT = 1
+PLANE_LAYOUT, DISPLACEMENT, ALLOW_UNSTABLE = 1, 2, 4
 
 
 def _ptr(t):
@@ -35,15 +35,19 @@ class Lattice:
 
     Parameters follow ``lbm_params``: nodes ``nx`` x ``ny``, spacing ``dx``,
     time step ``dt``, Lame constants ``lam`` and ``mu``, density ``rho``,
-    boundary ``bc`` (PERIODIC or DIRICHLET) and material ``model``."""
+    boundary ``bc`` (PERIODIC or DIRICHLET) and material ``model``;
+    ``displacement`` reserves the displacement state (``init_displacement``);
+    ``allow_unstable`` accepts parameters beyond the CFL-like limit."""
 
     def __init__(self, nx, ny, dx, dt, lam, mu, rho, bc=PERIODIC, model=PLANE_STRAIN,
-                 device="cuda:0", plane_layout=False):
+                 device="cuda:0", plane_layout=False, displacement=False, allow_unstable=False):
         self.L = _lib.load()
         self.device = torch.device(device)
         self.nx, self.ny, self.bc = int(nx), int(ny), int(bc)
+        flags = ((PLANE_LAYOUT if plane_layout else 0) | (DISPLACEMENT if displacement else 0)
+                 | (ALLOW_UNSTABLE if allow_unstable else 0))
         self.params = LbmParams(int(nx), int(ny), float(dx), float(dt), float(lam), float(mu),
-                                float(rho), int(bc), int(model), PLANE_LAYOUT if plane_layout else 0)
+                                float(rho), int(bc), int(model), flags)
         nbytes = self.L.lbm_workspace_bytes(ctypes.byref(self.params))
         if nbytes == 0:
             # re-run create to get the precise validation error
@@ -110,6 +114,71 @@ class Lattice:
         check(self.L.lbm_set_wall_velocity(self.ctx, R, _ptr(W), _ptr(T), T.shape[0]))
         self._wall = (W, T)
         return self
+
+    def set_body_force(self, X, Y, T):
+        """Separable body load b_bar = rho b: X [R][2][nx], Y [R][ny],
+        T [nsteps+1][R] (float32); R = 0 or X None removes it."""
+        if X is None or X.shape[0] == 0:
+            check(self.L.lbm_set_body_force(self.ctx, 0, None, None, None, 0))
+            self._force = None
+            return self
+        X, Y, T = (t.to(self.device, torch.float32).contiguous() for t in (X, Y, T))
+        R = X.shape[0]
+        if (X.shape != (R, 2, self.nx) or Y.shape != (R, self.ny) or T.dim() != 2
+                or T.shape[1] != R or T.shape[0] < 1):
+            raise ValueError("bad body load table shapes")
+        check(self.L.lbm_set_body_force(self.ctx, R, _ptr(X), _ptr(Y), _ptr(T), T.shape[0] - 1))
+        self._force = (X, Y, T)
+        return self
+
+    def init_displacement(self, u0):
+        """Start the trapezoidal displacement output from u0 [2][ny][nx]."""
+        t = u0.to(self.device, torch.float64).contiguous()
+        self._check_shape(t, (2, self.ny, self.nx))
+        check(self.L.lbm_init_displacement(self.ctx, _ptr(t)))
+        self._keep = list(self._keep) + [t]
+        return self
+
+    def displacement(self, out=None):
+        """u(t_n) float32 [2][ny][nx]."""
+        out = self._out(out, (2, self.ny, self.nx))
+        check(self.L.lbm_displacement(self.ctx, _ptr(out)))
+        return out
+
+    def set_reference(self, X, Y, T):
+        """Exact outputs for the error norms: X [R][7][nx], Y [R][ny],
+        T [nsteps+1][R] (float64); components u_x, u_y, v_x, v_y,
+        sigma_xx, sigma_yy, sigma_xy."""
+        if X is None or X.shape[0] == 0:
+            check(self.L.lbm_set_reference(self.ctx, 0, None, None, None, 0))
+            self._ref = None
+            return self
+        X, Y, T = (t.to(self.device, torch.float64).contiguous() for t in (X, Y, T))
+        R = X.shape[0]
+        if (X.shape != (R, 7, self.nx) or Y.shape != (R, self.ny) or T.dim() != 2
+                or T.shape[1] != R or T.shape[0] < 1):
+            raise ValueError("bad reference table shapes")
+        check(self.L.lbm_set_reference(self.ctx, R, _ptr(X), _ptr(Y), _ptr(T), T.shape[0] - 1))
+        self._ref = (X, Y, T)
+        return self
+
+    def track_errors(self, on=True):
+        check(self.L.lbm_error_track(self.ctx, int(bool(on))))
+        return self
+
+    def error_norms(self):
+        """Space-time norms of Section 6.1 over the tracked levels, per group
+        ('u', 'v', 's' for Cauchy stress): L2, L2rel, Linf, Linfrel."""
+        import math
+        buf = (ctypes.c_double * 10)()
+        check(self.L.lbm_error_sums(self.ctx, buf))
+        w = self.params.dx ** 2 * self.params.dt
+        out = {"levels": int(buf[9])}
+        for gi, name in enumerate(("u", "v", "s")):
+            e2, x2, einf = buf[3 * gi], buf[3 * gi + 1], buf[3 * gi + 2]
+            out[name] = {"L2": math.sqrt(w * e2), "L2rel": math.sqrt(e2 / x2) if x2 else None,
+                         "Linf": einf, "Linfrel": einf / math.sqrt(w * x2) if x2 else None}
+        return out
 
     # -- stepping and output ---------------------------------------------------
     def step(self, n=1):

@@ -94,6 +94,15 @@ class Problem:
         xb, yb = wall_points(self.nx, self.ny, self.dx)
         return np.stack([self.sol.vx(xb, yb, t), self.sol.vy(xb, yb, t)], axis=1)
 
+    def body_table(self, nsteps: int):
+        """Body load table of the solution's manufactured load; see
+        separable_body_table.  R = 0 when the solution needs no load."""
+        return separable_body_table(self.sol, self.nx, self.ny, self.dx, self.dt, nsteps)
+
+    def reference_table(self, nsteps: int):
+        """Exact outputs for the error norms; see separable_reference_table."""
+        return separable_reference_table(self.sol, self.nx, self.ny, self.dx, self.dt, nsteps)
+
     def wall_table(self, nsteps: int, step0: int = 0):
         """Separable wall velocity du_D/dt(x_b, t_n + dt/2) = sum_r W[r] T[n][r].
 
@@ -117,6 +126,57 @@ class Problem:
                     Ws.append(Wr)
                     Ts.append(fn(w[k] * tn))
         return np.stack(Ws), np.stack(Ts, axis=1)
+
+
+def separable_table(comps, nx: int, ny: int, dx: float, dt: float, nsteps: int):
+    """Fields given as SinSums, comps = [(SinSum, scale), ...] (component c is
+    scale_c * comps[c][0]), at the nodes and levels t_n = n dt, n = 0..nsteps,
+    as a sum of products of a function of x, of y and of t:
+      field_c(x_k, y_l, t_n) = sum_r X[r][c][k] Y[r][l] T[n][r].
+
+    Each term A sin(al + be + ga) (al = a x + p, be = b y, ga = w t) splits into
+    four products by the addition theorem:
+      sin al cos be cos ga + cos al sin be cos ga
+      + cos al cos be sin ga - sin al sin be sin ga.
+    Returns float64 (X [R][C][nx], Y [R][ny], T [nsteps+1][R])."""
+    C = len(comps)
+    xs = (np.arange(nx) + 0.5) * dx
+    ys = (np.arange(ny) + 0.5) * dx
+    tn = np.arange(nsteps + 1) * dt
+    Xs, Ys, Ts = [], [], []
+    for comp, (s, scale) in enumerate(comps):
+        for A, a, b, w, p in s.terms:
+            al, be, ga = a * xs + p, b * ys, w * tn
+            for fx, fy, ft, sign in ((np.sin, np.cos, np.cos, 1.0), (np.cos, np.sin, np.cos, 1.0),
+                                     (np.cos, np.cos, np.sin, 1.0), (np.sin, np.sin, np.sin, -1.0)):
+                Xr = np.zeros((C, nx))
+                Xr[comp] = sign * scale * A * fx(al)
+                Xs.append(Xr)
+                Ys.append(fy(be))
+                Ts.append(ft(ga))
+    if not Xs:
+        return np.zeros((0, C, nx)), np.zeros((0, ny)), np.zeros((nsteps + 1, 0))
+    return np.stack(Xs), np.stack(Ys), np.stack(Ts, axis=1)
+
+
+def separable_body_table(sol: Elastodynamics | None, nx: int, ny: int, dx: float, dt: float,
+                         nsteps: int):
+    """The physical body load b_bar = rho b of ``sol`` in the form of
+    separable_table (two components); R = 0 without a load."""
+    if sol is None or not sol.has_body_force():
+        return np.zeros((0, 2, nx)), np.zeros((0, ny)), np.zeros((nsteps + 1, 0))
+    r = sol.mat.rho
+    return separable_table([(sol.bx, r), (sol.by, r)], nx, ny, dx, dt, nsteps)
+
+
+def separable_reference_table(sol: Elastodynamics, nx: int, ny: int, dx: float, dt: float,
+                              nsteps: int):
+    """The exact outputs of ``sol`` (u_x, u_y, v_x, v_y and the Cauchy stress
+    sigma_bar = rho sigma: xx, yy, xy) in the form of separable_table."""
+    r = sol.mat.rho
+    comps = [(sol.ux, 1.0), (sol.uy, 1.0), (sol.vx, 1.0), (sol.vy, 1.0),
+             (sol.sxx, r), (sol.syy, r), (sol.sxy, r)]
+    return separable_table(comps, nx, ny, dx, dt, nsteps)
 
 
 def plane_wave_superposition(seed: int, mat: Material, nwaves: int = 8, kmax: int = 16,

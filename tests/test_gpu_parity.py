@@ -236,3 +236,24 @@ def test_full_size_dirichlet_2048x1024_windowed_oracle():
     err = oracle.rel_l2(np.array(got), np.array(want))
     print("2048x1024 Dirichlet, %d steps, sampled rel-L2 vs oracle: %.3e" % (n, err))
     assert err < 1e-5
+
+
+@gpu
+@pytest.mark.parametrize("model,name", [(0, "plane_strain"), (1, "plane_stress"),
+                                        (2, "continuum_2d")])
+@pytest.mark.parametrize("bc", [synth.PERIODIC, synth.DIRICHLET])
+def test_material_models_match_oracle(model, name, bc):
+    # Section 2 material laws: the model only changes c_K (Lame's lambda is
+    # replaced by 2 lambda mu / (lambda + 2 mu) for plane stress)
+    torch = _torch()
+    from paper_2408_01081_amd.lbm import Lattice
+    nx, ny, lam, mu, rho, dx, dt = 70, 45, 1.3, 0.7, 1.9, 0.01, 0.002
+    lat = Lattice(nx, ny, dx, dt, lam, mu, rho, bc, model=model)
+    s = oracle.Setup(nx, ny, dx, dt, lam, mu, rho, bc, model=name)
+    assert abs(lat.kK - s.kK) <= 1e-15 * s.kK and abs(lat.km - s.km) <= 1e-15 * s.km
+    f0 = synth.random_populations(17 + model, nx, ny).astype(np.float32)
+    lat.set_populations(torch.from_numpy(f0))
+    lat.step(300)
+    want = oracle.run_free(s, f0.astype(np.float64), 300)
+    got = lat.populations().double().cpu().numpy()
+    assert oracle.rel_l2(got, want) < 1e-5
