@@ -87,12 +87,97 @@ __device__ inline float from_lane_above(float v) {
   return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x130, 0xf, 0xf, true));
 }
 
+// Shifted operands folded into the add / subtract that consumes them
+// (DPP source operand): r_c = a_c(lane - 1) + b_c and s_c = c_c(lane + 1)
+// + d_c, five components each, with the same bound control as the shifts
+// above.  The compiler folds a separate shift only when all its uses follow
+// within a few instructions, which the blocked kernel's long sub-iterations
+// defeat.  A VALU write of a register needs two wait states before a DPP
+// read of it; the assembler block starts with them (s_nop 1) because the
+// hazard check does not look inside it, and its results are early-clobber
+// so no input is overwritten before the block has read it.
+__device__ __forceinline__ void add_shifted(const float a[NC], const float b[NC],
+                                            const float c[NC], const float d[NC],
+                                            float r[NC], float s[NC]) {
+  asm volatile(
+      "s_nop 1\n\t"
+      "v_add_f32_dpp %0, %10, %15 wave_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_add_f32_dpp %1, %11, %16 wave_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_add_f32_dpp %2, %12, %17 wave_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_add_f32_dpp %3, %13, %18 wave_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_add_f32_dpp %4, %14, %19 wave_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_add_f32_dpp %5, %20, %25 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_add_f32_dpp %6, %21, %26 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_add_f32_dpp %7, %22, %27 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_add_f32_dpp %8, %23, %28 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_add_f32_dpp %9, %24, %29 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1"
+      : "=&v"(r[0]), "=&v"(r[1]), "=&v"(r[2]), "=&v"(r[3]), "=&v"(r[4]), "=&v"(s[0]),
+        "=&v"(s[1]), "=&v"(s[2]), "=&v"(s[3]), "=&v"(s[4])
+      : "v"(a[0]), "v"(a[1]), "v"(a[2]), "v"(a[3]), "v"(a[4]), "v"(b[0]), "v"(b[1]),
+        "v"(b[2]), "v"(b[3]), "v"(b[4]), "v"(c[0]), "v"(c[1]), "v"(c[2]), "v"(c[3]),
+        "v"(c[4]), "v"(d[0]), "v"(d[1]), "v"(d[2]), "v"(d[3]), "v"(d[4]));
+}
+
+// r_c = b_c - a_c(lane - 1) and s_c = d_c - c_c(lane + 1) (see add_shifted)
+__device__ __forceinline__ void sub_shifted(const float a[NC], const float b[NC],
+                                            const float c[NC], const float d[NC],
+                                            float r[NC], float s[NC]) {
+  asm volatile(
+      "s_nop 1\n\t"
+      "v_subrev_f32_dpp %0, %10, %15 wave_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_subrev_f32_dpp %1, %11, %16 wave_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_subrev_f32_dpp %2, %12, %17 wave_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_subrev_f32_dpp %3, %13, %18 wave_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_subrev_f32_dpp %4, %14, %19 wave_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_subrev_f32_dpp %5, %20, %25 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_subrev_f32_dpp %6, %21, %26 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_subrev_f32_dpp %7, %22, %27 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_subrev_f32_dpp %8, %23, %28 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_subrev_f32_dpp %9, %24, %29 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1"
+      : "=&v"(r[0]), "=&v"(r[1]), "=&v"(r[2]), "=&v"(r[3]), "=&v"(r[4]), "=&v"(s[0]),
+        "=&v"(s[1]), "=&v"(s[2]), "=&v"(s[3]), "=&v"(s[4])
+      : "v"(a[0]), "v"(a[1]), "v"(a[2]), "v"(a[3]), "v"(a[4]), "v"(b[0]), "v"(b[1]),
+        "v"(b[2]), "v"(b[3]), "v"(b[4]), "v"(c[0]), "v"(c[1]), "v"(c[2]), "v"(c[3]),
+        "v"(c[4]), "v"(d[0]), "v"(d[1]), "v"(d[2]), "v"(d[3]), "v"(d[4]));
+}
+
 // one level-update of row y at this lane's column x from the rows below,
 // at and above (post-collision values of the previous level)
 template <int BC>
 __device__ __forceinline__ void level_update(const float below[NP], const float at[NP],
                                     const float above[NP], int x, int y, int nx, int ny,
                                     float kK, float km, const Wall& w, float out[NP]) {
+  if constexpr (BC == LBM_PERIODIC) {
+    // collide() on f_0 = f*_0(x - 1), f_1 = f*_1(y - 1), f_2 = f*_2(x + 1),
+    // f_3 = f*_3(y + 1) with the same operations in the same order:
+    // U = (f_0 + f_1) + (f_2 + f_3), then f*_q = (h +- X or Y) - f_q
+    float p01[NC], p23[NC], U[NC];
+    add_shifted(at + 0 * NC, below + 1 * NC, at + 2 * NC, above + 3 * NC, p01, p23);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) U[c] = p01[c] + p23[c];
+    float X[NC], Y[NC];
+    X[0] = fmaf(kK, U[2], km * U[3]);
+    X[1] = km * U[4];
+    X[2] = kK * U[0];
+    X[3] = km * U[0];
+    X[4] = km * U[1];
+    Y[0] = km * U[4];
+    Y[1] = fmaf(kK, U[2], -(km * U[3]));
+    Y[2] = kK * U[1];
+    Y[3] = -(km * U[1]);
+    Y[4] = km * U[0];
+    float t0[NC], t2[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const float h = 0.5f * U[c];
+      t0[c] = h + X[c];
+      t2[c] = h - X[c];
+      out[1 * NC + c] = (h + Y[c]) - below[1 * NC + c];
+      out[3 * NC + c] = (h - Y[c]) - above[3 * NC + c];
+    }
+    sub_shifted(at + 0 * NC, t0, at + 2 * NC, t2, out + 0 * NC, out + 2 * NC);
+    return;
+  }
   float f[NQ][NC];
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
