@@ -759,7 +759,9 @@ const TBConfig kTBConfigs[] = {
     LBM_TB(4, 12, 1, 1), LBM_TB(5, 16, 0, 1), LBM_TB(5, 32, 0, 1), LBM_TB(5, 16, 1, 1),
     LBM_TB(6, 16, 0, 1), LBM_TB(6, 32, 0, 1), LBM_TB(6, 48, 0, 1), LBM_TB(6, 16, 1, 1),
     LBM_TB(7, 32, 0, 1), LBM_TB(7, 48, 0, 1), LBM_TB(7, 64, 0, 1), LBM_TB(7, 32, 1, 1),
-    LBM_TB(7, 0, 0, 1),  LBM_TB(7, -2, 0, 1), LBM_TB(6, 0, 0, 1),  LBM_TB(5, 0, 0, 1)};
+    LBM_TB(7, 0, 0, 1),  LBM_TB(7, -2, 0, 1), LBM_TB(6, 0, 0, 1),  LBM_TB(5, 0, 0, 1),
+    LBM_TB(7, 16, 0, 1), LBM_TB(7, 24, 0, 1), LBM_TB(7, 20, 0, 2), LBM_TB(7, 30, 0, 2),
+    LBM_TB(6, 8, 0, 1),  LBM_TB(6, 12, 0, 1), LBM_TB(6, 20, 0, 2), LBM_TB(6, 30, 0, 2)};
 #undef LBM_TB
 constexpr int kNumTBConfigs = (int)(sizeof(kTBConfigs) / sizeof(kTBConfigs[0]));
 static_assert(kNumTBConfigs <= 64, "tb_slots size");
