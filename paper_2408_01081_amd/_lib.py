@@ -92,6 +92,7 @@ SIGNATURES = [
     ("sg_param_count", _I64, []),
     ("sg_create", ctypes.c_int, [_VP, _VP, ctypes.c_size_t, _VP, ctypes.POINTER(_VP)]),
     ("sg_destroy", ctypes.c_int, [_VP]),
+    ("sg_set_conv_mode", ctypes.c_int, [_VP, _I32]),
     ("sg_set_params", ctypes.c_int, [_VP, _VP]),
     ("sg_get_params", ctypes.c_int, [_VP, _VP]),
     ("sg_get_grads", ctypes.c_int, [_VP, _VP]),

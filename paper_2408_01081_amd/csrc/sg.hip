@@ -419,6 +419,7 @@ struct sg_net {
   const float* in;
   int64_t adam_step;
   bool weights_ready;
+  int conv_mode;  // 0: LDS-tiled kernel where it applies; 1: direct kernel only
 };
 
 namespace {
@@ -477,6 +478,32 @@ void launch_conv_shape(int k, sg_net* n, const Tensor& x, const float* xscale,
   }
 }
 
+template <int SPLIT, int PB, int NB>
+void launch_convt(sg_net* n, const Tensor& x, const float* xscale, const unsigned short* wh,
+                  const unsigned short* wl, Tensor& z, int cin, int cout, int accumulate) {
+  constexpr int CT = (4 / (64 / (16 * PB))) * 16 * NB;
+  dim3 grid((unsigned)((int64_t)n->B * x.H * (x.W / 64)), (unsigned)(cout / CT));
+  hipLaunchKernelGGL((k_convt<SPLIT, PB, NB>), grid, dim3(256), 0, n->stream,
+                     (const float*)x.p, xscale, wh, wl, z.p, x.H, x.W, cin, cout, n->circular,
+                     accumulate);
+}
+
+// The LDS-tiled kernel where the row is a multiple of 64 pixels: 64 output
+// channels per workgroup (2 x 2 waves of 32 x 32) when that still gives 512
+// workgroups, else 32 (4 waves of 16 pixels x 32 channels).  Returns false
+// where it does not apply.
+template <int SPLIT>
+bool conv_tiled(sg_net* n, const Tensor& x, const float* xscale, const unsigned short* wh,
+                const unsigned short* wl, Tensor& z, int cin, int cout, int accumulate) {
+  if (n->conv_mode == 1 || x.W % 64 || cin % 32 || cout % 32) return false;
+  const int64_t tiles = (int64_t)n->B * x.H * (x.W / 64);
+  if (cout % 64 == 0 && tiles * (cout / 64) >= 512)
+    launch_convt<SPLIT, 2, 2>(n, x, xscale, wh, wl, z, cin, cout, accumulate);
+  else
+    launch_convt<SPLIT, 1, 2>(n, x, xscale, wh, wl, z, cin, cout, accumulate);
+  return true;
+}
+
 void conv(sg_net* n, const Tensor& x, const float* xscale, int l, Tensor& z, bool backward,
           int accumulate) {
   const LayerSpec& L = kLayers[l];
@@ -484,6 +511,10 @@ void conv(sg_net* n, const Tensor& x, const float* xscale, int l, Tensor& z, boo
   const unsigned short* wh = (backward ? n->wbh : n->wfh) + n->P.wq_off[l];
   const unsigned short* wl = (backward ? n->wbl : n->wfl) + n->P.wq_off[l];
   const int64_t pixels = (int64_t)n->B * x.H * x.W;
+  // the LDS-tiled kernel splits its input tiles itself
+  if (n->P.split == 3 ? conv_tiled<3>(n, x, xscale, wh, wl, z, cin, cout, accumulate)
+                      : conv_tiled<1>(n, x, xscale, wh, wl, z, cin, cout, accumulate))
+    return;
   // the input's BF16 hi/lo parts (with its gain), once for all taps and
   // output-channel blocks
   const int64_t n4 = pixels * cin / 4;
@@ -733,6 +764,13 @@ lbm_status sg_create(const sg_config* cfg, void* d_ws, size_t ws_bytes, void* hi
   n->adam_step = 0;
   n->weights_ready = false;
   *out = n;
+  return LBM_OK;
+}
+
+lbm_status sg_set_conv_mode(sg_net* n, int32_t mode) {
+  if (!n) return fail(LBM_E_ARG, "null net");
+  if (mode != 0 && mode != 1) return fail(LBM_E_ARG, "conv mode must be 0 or 1");
+  n->conv_mode = mode;
   return LBM_OK;
 }
 

@@ -189,6 +189,135 @@ __global__ __launch_bounds__(256) void k_conv(const unsigned short* __restrict__
 }
 
 // ---------------------------------------------------------------------------
+// The same convolution with the input tile staged in LDS.  A workgroup computes
+// 64 consecutive pixels of one image row (W % 64 == 0) x CT output channels;
+// for every 32-channel chunk of the input the 3 x 66 pixel neighbourhood of
+// those pixels is read from the FP32 activations, multiplied by the gain and
+// split into BF16 hi and lo parts exactly as k_split_bf16 does, and stored in
+// LDS (20 dwords per pixel: 16 data + 4 padding, so the 16 lanes of an
+// A-fragment read hit distinct banks), where all 9 taps and all waves read it.  Wave w owns 16 PB pixels (w mod WPX) x
+// 16 NB output channels (w / WPX).  The products are accumulated in the same
+// order as k_conv<SPLIT, NB, PB, 1> (chunks, taps, channel blocks, pixel
+// blocks), so the two give bitwise identical results.  Cin % 32 == 0,
+// Cout % CT == 0.
+// ---------------------------------------------------------------------------
+template <int SPLIT, int PB, int NB>
+__global__ __launch_bounds__(256) void k_convt(const float* __restrict__ X,
+                                               const float* __restrict__ xscale,
+                                               const unsigned short* __restrict__ Whi,
+                                               const unsigned short* __restrict__ Wlo,
+                                               float* __restrict__ Z, int H, int W, int Cin,
+                                               int Cout, int circular, int accumulate) {
+  constexpr int WPX = 64 / (16 * PB);  // waves along the pixels
+  constexpr int WCO = 4 / WPX;         // waves along the output channels
+  static_assert(WPX * WCO == 4, "four waves per workgroup");
+  constexpr int CT = WCO * 16 * NB;    // output channels per workgroup
+  constexpr int TW = 66;               // tile columns: 64 pixels + one each side
+  constexpr int PS = 20;               // dwords per tile pixel
+  constexpr int NH = SPLIT == 3 ? 2 : 1;
+  __shared__ uint4 tile4[NH * 3 * TW * PS / 4];
+  uint32_t* tile = reinterpret_cast<uint32_t*>(tile4);
+
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int m = lane & 15, kq = lane >> 4;
+  const int wp = wave % WPX, wc = wave / WPX;
+  const int tiles_x = W / 64;
+  const int xt = (int)(blockIdx.x % (unsigned)tiles_x);
+  const int rest = (int)(blockIdx.x / (unsigned)tiles_x);
+  const int y = rest % H, b = rest / H;
+  const int x0 = 64 * xt;
+  const int co0 = blockIdx.y * CT + 16 * NB * wc;
+  const int px0 = 16 * PB * wp;
+
+  f32x4 acc[PB][NB];
+#pragma unroll
+  for (int pb = 0; pb < PB; ++pb)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) acc[pb][nb] = (f32x4){0.f, 0.f, 0.f, 0.f};
+
+  for (int c0 = 0; c0 < Cin; c0 += 32) {
+    if (c0) __syncthreads();  // every wave is done with the previous chunk
+    // 3 rows x 66 columns x 4 pieces of 8 channels, hi (and lo)
+    for (int i = threadIdx.x; i < 3 * TW * 4; i += 256) {
+      const int q = i & 3, col = (i >> 2) % TW, row = (i >> 2) / TW;
+      int ys = y + row - 1, xs = x0 + col - 1;
+      bool valid = true;
+      if (circular) {
+        ys = ys < 0 ? ys + H : (ys >= H ? ys - H : ys);
+        xs = xs < 0 ? xs + W : (xs >= W ? xs - W : xs);
+      } else {
+        valid = ys >= 0 && ys < H && xs >= 0 && xs < W;
+      }
+      uint4 vh = {0u, 0u, 0u, 0u}, vl = {0u, 0u, 0u, 0u};
+      if (valid) {
+        const int64_t xo = (((int64_t)b * H + ys) * W + xs) * Cin + c0 + 8 * q;
+        const float4 u0 = *reinterpret_cast<const float4*>(X + xo);
+        const float4 u1 = *reinterpret_cast<const float4*>(X + xo + 4);
+        float a[8] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w};
+        if (xscale) {
+          const float* sc = xscale + (int64_t)b * Cin + c0 + 8 * q;
+#pragma unroll
+          for (int j = 0; j < 8; ++j) a[j] *= sc[j];
+        }
+        uint32_t h[4], l[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const unsigned short h0 = bf16_bits(a[2 * j]), h1 = bf16_bits(a[2 * j + 1]);
+          h[j] = (uint32_t)h0 | ((uint32_t)h1 << 16);
+          if (SPLIT == 3) {
+            const unsigned short l0 = bf16_bits(a[2 * j] - bf16_value(h0));
+            const unsigned short l1 = bf16_bits(a[2 * j + 1] - bf16_value(h1));
+            l[j] = (uint32_t)l0 | ((uint32_t)l1 << 16);
+          }
+        }
+        vh = (uint4){h[0], h[1], h[2], h[3]};
+        if (SPLIT == 3) vl = (uint4){l[0], l[1], l[2], l[3]};
+      }
+      const int d = (row * TW + col) * PS + 4 * q;
+      *reinterpret_cast<uint4*>(tile + d) = vh;
+      if (SPLIT == 3) *reinterpret_cast<uint4*>(tile + 3 * TW * PS + d) = vl;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+      const int dy = t / 3 - 1, dx = t % 3 - 1;
+      bf16x8 ahi[PB], alo[PB];
+#pragma unroll
+      for (int pb = 0; pb < PB; ++pb) {
+        const int d = ((dy + 1) * TW + px0 + 16 * pb + m + dx + 1) * PS + 4 * kq;
+        ahi[pb] = *reinterpret_cast<const bf16x8*>(tile + d);
+        if (SPLIT == 3) alo[pb] = *reinterpret_cast<const bf16x8*>(tile + 3 * TW * PS + d);
+      }
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const int64_t wo = ((int64_t)t * Cout + co0 + 16 * nb + m) * Cin + 8 * kq + c0;
+        const bf16x8 bhi = *reinterpret_cast<const bf16x8*>(Whi + wo);
+        bf16x8 blo;
+        if (SPLIT == 3) blo = *reinterpret_cast<const bf16x8*>(Wlo + wo);
+#pragma unroll
+        for (int pb = 0; pb < PB; ++pb) {
+          acc[pb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[pb], bhi, acc[pb][nb], 0, 0, 0);
+          if (SPLIT == 3) {
+            acc[pb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo[pb], bhi, acc[pb][nb], 0, 0, 0);
+            acc[pb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[pb], blo, acc[pb][nb], 0, 0, 0);
+          }
+        }
+      }
+    }
+  }
+  const int64_t pix = ((int64_t)b * H + y) * W + x0 + px0;
+#pragma unroll
+  for (int pb = 0; pb < PB; ++pb)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        float* zp = Z + (pix + 16 * pb + 4 * kq + j) * Cout + co0 + 16 * nb + m;
+        *zp = accumulate ? *zp + acc[pb][nb][j] : acc[pb][nb][j];
+      }
+}
+
+// ---------------------------------------------------------------------------
 // Weight gradient.  dW[t][o][i] = sum_{b,p} G[b,p,o] * s_o[b,o] * X[b,p+off_t,i] * s_i[b,i]
 // As a GEMM: D (16 o x 16 i) += A (16 o x 32 pixels) B (32 pixels x 16 i).
 // grid: x = tap (9) * (Cout/16) * (Cin/(16 NI)), y = pixel split; each of the

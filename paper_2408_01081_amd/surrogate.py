@@ -98,6 +98,11 @@ class Surrogate:
             self.L.sg_destroy(ctx)
             self.ctx = None
 
+    def set_conv_mode(self, mode):
+        """0: LDS-tiled convolutions where they apply (default); 1: direct only."""
+        check(self.L.sg_set_conv_mode(self.ctx, int(mode)))
+        return self
+
     def set_params(self, v):
         t = torch.as_tensor(np.asarray(v, dtype=np.float32) if not torch.is_tensor(v) else v)
         t = t.to(self.device, torch.float32).contiguous()

@@ -124,3 +124,29 @@ def test_adam_step_matches_reference_and_loss_decreases():
     assert np.max(np.abs(v1 - want)) < 1e-6 + 1e-5 * lr
     losses = [net.train_step(x, t, circular=True, lr=lr) for _ in range(30)]
     assert losses[-1] < 0.5 * losses[0], losses
+
+
+@gpu
+@pytest.mark.parametrize("split,circular,B,H,W", [(3, True, 1, 256, 256), (3, False, 2, 128, 256),
+                                                  (1, False, 1, 64, 128)])
+def test_tiled_and_direct_convolutions_agree(split, circular, B, H, W):
+    # the LDS-tiled convolution (rows that are multiples of 64 pixels) and the
+    # direct one compute the same products; only the FP32 summation order of
+    # the reduction slices may differ (with plain BF16 operands such a
+    # difference can flip the rounding of the next layer's operand, so the
+    # bound is that of the split-1 reference comparison)
+    torch = _torch()
+    from paper_2408_01081_amd import surrogate as S
+    inp, _ = _inputs(5, B, H, W)
+    P = _params(6)
+    x = torch.from_numpy(inp.astype(np.float32)).cuda()
+    outs = []
+    for mode in (0, 1):
+        net = S.Surrogate(B, H, W, split=split)
+        net.set_params(S.pack_params(P))
+        net.set_conv_mode(mode)
+        outs.append(net.forward(x, circular=circular).double().cpu().numpy())
+        del net
+    err = _rel(outs[0] - inp[:, :5], outs[1] - inp[:, :5])
+    print("tiled vs direct, split %d: rel diff of the correction %.2e" % (split, err))
+    assert err < (1e-5 if split == 3 else 3e-2)
