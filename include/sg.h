@@ -56,10 +56,12 @@ lbm_status sg_create(const sg_config* cfg, void* d_ws, size_t ws_bytes, void* hi
 lbm_status sg_destroy(sg_net* net);
 
 /* Convolution kernel family: 0 (default) stages each input tile in LDS where
- * the row length at a layer is a multiple of 64 pixels and uses the direct
+ * the row length at a layer is a multiple of 64 pixels or 32 or 16 pixels,
+ * with the weights in LDS too for 32-channel output tiles, and uses the direct
  * kernel elsewhere; 1 uses the direct kernel (operands read from global
- * memory) for every layer.  Both compute the same products and sums (FP32
- * accumulation order may differ); for comparisons and timing. */
+ * memory) for every layer; 2 is 0 with the weights always read from global
+ * memory.  All compute the same products and sums (FP32 accumulation order
+ * may differ); for comparisons and timing. */
 lbm_status sg_set_conv_mode(sg_net* net, int32_t mode);
 
 /* Copy the parameter vector in (resets the Adam state) or out, device to

@@ -419,7 +419,8 @@ struct sg_net {
   const float* in;
   int64_t adam_step;
   bool weights_ready;
-  int conv_mode;  // 0: LDS-tiled kernel where it applies; 1: direct kernel only
+  int conv_mode;  // 0: LDS-tiled kernel where it applies; 1: direct kernel only;
+                  // 2: tiled, weights from global memory
 };
 
 namespace {
@@ -478,29 +479,48 @@ void launch_conv_shape(int k, sg_net* n, const Tensor& x, const float* xscale,
   }
 }
 
-template <int SPLIT, int PB, int NB>
+template <int SPLIT, int PB, int NB, bool WL, int WT>
 void launch_convt(sg_net* n, const Tensor& x, const float* xscale, const unsigned short* wh,
                   const unsigned short* wl, Tensor& z, int cin, int cout, int accumulate) {
   constexpr int CT = (4 / (64 / (16 * PB))) * 16 * NB;
-  dim3 grid((unsigned)((int64_t)n->B * x.H * (x.W / 64)), (unsigned)(cout / CT));
-  hipLaunchKernelGGL((k_convt<SPLIT, PB, NB>), grid, dim3(256), 0, n->stream,
+  dim3 grid((unsigned)((int64_t)n->B * x.H * x.W / 64), (unsigned)(cout / CT));
+  hipLaunchKernelGGL((k_convt<SPLIT, PB, NB, WL, WT>), grid, dim3(256), 0, n->stream,
                      (const float*)x.p, xscale, wh, wl, z.p, x.H, x.W, cin, cout, n->circular,
                      accumulate);
 }
 
-// The LDS-tiled kernel where the row is a multiple of 64 pixels: 64 output
-// channels per workgroup (2 x 2 waves of 32 x 32) when that still gives 512
-// workgroups, else 32 (4 waves of 16 pixels x 32 channels).  Returns false
-// where it does not apply.
+// The LDS-tiled kernel where the row is a multiple of 64 pixels or 32 or 16
+// pixels long and it gives at least 256 workgroups: 64 output channels per
+// workgroup (2 x 2 waves of 32 x 32) when that still gives 512 workgroups,
+// else 32 (4 waves of 16 pixels x 32 channels, weights staged in LDS too).
+// Returns false where it does not apply.
+template <int SPLIT, int WT>
+void conv_tiled_w(sg_net* n, const Tensor& x, const float* xscale, const unsigned short* wh,
+                  const unsigned short* wl, Tensor& z, int cin, int cout, int accumulate) {
+  const int64_t tiles = (int64_t)n->B * x.H * x.W / 64;
+  if (cout % 64 == 0 && tiles * (cout / 64) >= 512)
+    launch_convt<SPLIT, 2, 2, false, WT>(n, x, xscale, wh, wl, z, cin, cout, accumulate);
+  else if (n->conv_mode == 2)
+    launch_convt<SPLIT, 1, 2, false, WT>(n, x, xscale, wh, wl, z, cin, cout, accumulate);
+  else
+    launch_convt<SPLIT, 1, 2, true, WT>(n, x, xscale, wh, wl, z, cin, cout, accumulate);
+}
+
 template <int SPLIT>
 bool conv_tiled(sg_net* n, const Tensor& x, const float* xscale, const unsigned short* wh,
                 const unsigned short* wl, Tensor& z, int cin, int cout, int accumulate) {
-  if (n->conv_mode == 1 || x.W % 64 || cin % 32 || cout % 32) return false;
-  const int64_t tiles = (int64_t)n->B * x.H * (x.W / 64);
-  if (cout % 64 == 0 && tiles * (cout / 64) >= 512)
-    launch_convt<SPLIT, 2, 2>(n, x, xscale, wh, wl, z, cin, cout, accumulate);
+  if (n->conv_mode == 1 || cin % 32 || cout % 32 || ((int64_t)x.H * x.W) % 64) return false;
+  // too few workgroups to fill the chip: the direct kernel splits the
+  // reduction over waves instead
+  if ((int64_t)n->B * x.H * x.W / 64 * (cout / 32) < 256) return false;
+  if (x.W % 64 == 0)
+    conv_tiled_w<SPLIT, 64>(n, x, xscale, wh, wl, z, cin, cout, accumulate);
+  else if (x.W == 32)
+    conv_tiled_w<SPLIT, 32>(n, x, xscale, wh, wl, z, cin, cout, accumulate);
+  else if (x.W == 16)
+    conv_tiled_w<SPLIT, 16>(n, x, xscale, wh, wl, z, cin, cout, accumulate);
   else
-    launch_convt<SPLIT, 1, 2>(n, x, xscale, wh, wl, z, cin, cout, accumulate);
+    return false;
   return true;
 }
 
@@ -769,7 +789,7 @@ lbm_status sg_create(const sg_config* cfg, void* d_ws, size_t ws_bytes, void* hi
 
 lbm_status sg_set_conv_mode(sg_net* n, int32_t mode) {
   if (!n) return fail(LBM_E_ARG, "null net");
-  if (mode != 0 && mode != 1) return fail(LBM_E_ARG, "conv mode must be 0 or 1");
+  if (mode < 0 || mode > 2) return fail(LBM_E_ARG, "conv mode must be 0, 1 or 2");
   n->conv_mode = mode;
   return LBM_OK;
 }

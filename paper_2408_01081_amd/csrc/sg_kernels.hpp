@@ -190,9 +190,10 @@ __global__ __launch_bounds__(256) void k_conv(const unsigned short* __restrict__
 
 // ---------------------------------------------------------------------------
 // The same convolution with the input tile staged in LDS.  A workgroup computes
-// 64 consecutive pixels of one image row (W % 64 == 0) x CT output channels;
-// for every 32-channel chunk of the input the 3 x 66 pixel neighbourhood of
-// those pixels is read from the FP32 activations, multiplied by the gain and
+// 64 consecutive pixels of one image (a row piece when W >= 64, W % 64 == 0;
+// 64 / W whole rows when W = 32 or 16) x CT output channels; for every
+// 32-channel chunk of the input the neighbourhood of those pixels (one pixel
+// more on every side) is read from the FP32 activations, multiplied by the gain and
 // split into BF16 hi and lo parts exactly as k_split_bf16 does, and stored in
 // LDS (20 dwords per pixel: 16 data + 4 padding, so the 16 lanes of an
 // A-fragment read hit distinct banks), where all 9 taps and all waves read it.  Wave w owns 16 PB pixels (w mod WPX) x
@@ -201,7 +202,7 @@ __global__ __launch_bounds__(256) void k_conv(const unsigned short* __restrict__
 // blocks), so the two give bitwise identical results.  Cin % 32 == 0,
 // Cout % CT == 0.
 // ---------------------------------------------------------------------------
-template <int SPLIT, int PB, int NB>
+template <int SPLIT, int PB, int NB, bool WL = false, int WT = 64>
 __global__ __launch_bounds__(256) void k_convt(const float* __restrict__ X,
                                                const float* __restrict__ xscale,
                                                const unsigned short* __restrict__ Whi,
@@ -212,21 +213,29 @@ __global__ __launch_bounds__(256) void k_convt(const float* __restrict__ X,
   constexpr int WCO = 4 / WPX;         // waves along the output channels
   static_assert(WPX * WCO == 4, "four waves per workgroup");
   constexpr int CT = WCO * 16 * NB;    // output channels per workgroup
-  constexpr int TW = 66;               // tile columns: 64 pixels + one each side
+  // the 64 pixels are 64 / WT rows of WT pixels (WT = 64 for W >= 64, else W)
+  constexpr int TR = 64 / WT + 2;      // tile rows: those rows + one each side
+  constexpr int TW = WT + 2;           // tile columns: WT pixels + one each side
   constexpr int PS = 20;               // dwords per tile pixel
   constexpr int NH = SPLIT == 3 ? 2 : 1;
-  __shared__ uint4 tile4[NH * 3 * TW * PS / 4];
+  // WL: the chunk's weights of the workgroup's CT channels for all 9 taps
+  // are staged in LDS as well ([hi/lo][tap][channel], PS dwords per channel)
+  constexpr int WS = WL ? 9 * CT * PS : 0;
+  __shared__ uint4 tile4[NH * (TR * TW * PS + WS) / 4];
   uint32_t* tile = reinterpret_cast<uint32_t*>(tile4);
+  uint32_t* wtile = tile + NH * TR * TW * PS;
 
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int m = lane & 15, kq = lane >> 4;
   const int wp = wave % WPX, wc = wave / WPX;
-  const int tiles_x = W / 64;
-  const int xt = (int)(blockIdx.x % (unsigned)tiles_x);
-  const int rest = (int)(blockIdx.x / (unsigned)tiles_x);
-  const int y = rest % H, b = rest / H;
-  const int x0 = 64 * xt;
-  const int co0 = blockIdx.y * CT + 16 * NB * wc;
+  // the workgroup's 64 consecutive pixels (row-major within one image)
+  const int64_t p0 = (int64_t)blockIdx.x * 64;
+  const int64_t HW = (int64_t)H * W;
+  const int b = (int)(p0 / HW);
+  const int rem = (int)(p0 - (int64_t)b * HW);
+  const int y = rem / W, x0 = rem - (rem / W) * W;
+  const int cw = 16 * NB * wc;  // the wave's channels within the workgroup's CT
+  const int co0 = blockIdx.y * CT + cw;
   const int px0 = 16 * PB * wp;
 
   f32x4 acc[PB][NB];
@@ -237,8 +246,8 @@ __global__ __launch_bounds__(256) void k_convt(const float* __restrict__ X,
 
   for (int c0 = 0; c0 < Cin; c0 += 32) {
     if (c0) __syncthreads();  // every wave is done with the previous chunk
-    // 3 rows x 66 columns x 4 pieces of 8 channels, hi (and lo)
-    for (int i = threadIdx.x; i < 3 * TW * 4; i += 256) {
+    // TR rows x TW columns x 4 pieces of 8 channels, hi (and lo)
+    for (int i = threadIdx.x; i < TR * TW * 4; i += 256) {
       const int q = i & 3, col = (i >> 2) % TW, row = (i >> 2) / TW;
       int ys = y + row - 1, xs = x0 + col - 1;
       bool valid = true;
@@ -275,7 +284,18 @@ __global__ __launch_bounds__(256) void k_convt(const float* __restrict__ X,
       }
       const int d = (row * TW + col) * PS + 4 * q;
       *reinterpret_cast<uint4*>(tile + d) = vh;
-      if (SPLIT == 3) *reinterpret_cast<uint4*>(tile + 3 * TW * PS + d) = vl;
+      if (SPLIT == 3) *reinterpret_cast<uint4*>(tile + TR * TW * PS + d) = vl;
+    }
+    if (WL) {
+      // 9 taps x CT channels x 4 pieces of 8 input channels
+      for (int i = threadIdx.x; i < 9 * CT * 4; i += 256) {
+        const int q = i & 3, co = (i >> 2) % CT, t = (i >> 2) / CT;
+        const int64_t wo = ((int64_t)t * Cout + blockIdx.y * CT + co) * Cin + c0 + 8 * q;
+        const int d = (t * CT + co) * PS + 4 * q;
+        *reinterpret_cast<uint4*>(wtile + d) = *reinterpret_cast<const uint4*>(Whi + wo);
+        if (SPLIT == 3)
+          *reinterpret_cast<uint4*>(wtile + WS + d) = *reinterpret_cast<const uint4*>(Wlo + wo);
+      }
     }
     __syncthreads();
 #pragma unroll
@@ -284,16 +304,23 @@ __global__ __launch_bounds__(256) void k_convt(const float* __restrict__ X,
       bf16x8 ahi[PB], alo[PB];
 #pragma unroll
       for (int pb = 0; pb < PB; ++pb) {
-        const int d = ((dy + 1) * TW + px0 + 16 * pb + m + dx + 1) * PS + 4 * kq;
+        const int p = px0 + 16 * pb + m, r = p / WT, xp = p - r * WT;
+        const int d = ((r + dy + 1) * TW + xp + dx + 1) * PS + 4 * kq;
         ahi[pb] = *reinterpret_cast<const bf16x8*>(tile + d);
-        if (SPLIT == 3) alo[pb] = *reinterpret_cast<const bf16x8*>(tile + 3 * TW * PS + d);
+        if (SPLIT == 3) alo[pb] = *reinterpret_cast<const bf16x8*>(tile + TR * TW * PS + d);
       }
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
-        const int64_t wo = ((int64_t)t * Cout + co0 + 16 * nb + m) * Cin + 8 * kq + c0;
-        const bf16x8 bhi = *reinterpret_cast<const bf16x8*>(Whi + wo);
-        bf16x8 blo;
-        if (SPLIT == 3) blo = *reinterpret_cast<const bf16x8*>(Wlo + wo);
+        bf16x8 bhi, blo;
+        if (WL) {
+          const int d = (t * CT + cw + 16 * nb + m) * PS + 4 * kq;
+          bhi = *reinterpret_cast<const bf16x8*>(wtile + d);
+          if (SPLIT == 3) blo = *reinterpret_cast<const bf16x8*>(wtile + WS + d);
+        } else {
+          const int64_t wo = ((int64_t)t * Cout + co0 + 16 * nb + m) * Cin + 8 * kq + c0;
+          bhi = *reinterpret_cast<const bf16x8*>(Whi + wo);
+          if (SPLIT == 3) blo = *reinterpret_cast<const bf16x8*>(Wlo + wo);
+        }
 #pragma unroll
         for (int pb = 0; pb < PB; ++pb) {
           acc[pb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[pb], bhi, acc[pb][nb], 0, 0, 0);
@@ -305,7 +332,7 @@ __global__ __launch_bounds__(256) void k_convt(const float* __restrict__ X,
       }
     }
   }
-  const int64_t pix = ((int64_t)b * H + y) * W + x0 + px0;
+  const int64_t pix = p0 + px0;
 #pragma unroll
   for (int pb = 0; pb < PB; ++pb)
 #pragma unroll

@@ -146,3 +146,48 @@ class Surrogate:
                                    int(bool(circular)), ctypes.c_float(lr),
                                    ctypes.byref(loss) if want_loss else None))
         return loss.value if want_loss else None
+
+
+LEVELS = [0, 0, 0, 1, 1, 2, 2, 3, 3, 2, 2, 1, 1, 0, 0, 0]  # resolution level of each layer
+
+
+def forward_flops(B, H, W):
+    """Multiply-add FLOPs of one forward (the 3x3 convolutions)."""
+    return B * sum(2 * 9 * ci * co * (H >> lv) * (W >> lv)
+                   for (_, ci, co), lv in zip(LAYERS, LEVELS))
+
+
+def main():
+    """Time the forward pass: python -m paper_2408_01081_amd.surrogate B H W
+    [conv_mode] [weights.npy] (median of 20 calls after 3 warm-up calls)."""
+    import os
+    import sys
+    B, H, W = (int(a) for a in sys.argv[1:4])
+    mode = int(sys.argv[4]) if len(sys.argv) > 4 else 0
+    path = sys.argv[5] if len(sys.argv) > 5 else os.path.join(
+        os.path.dirname(os.path.abspath(__file__)), "weights", "surrogate.npy")
+    net = Surrogate(B, H, W, split=3)
+    net.set_params(np.load(path, allow_pickle=False))
+    net.set_conv_mode(mode)
+    x = torch.randn(B, 8, H, W, device=net.device)
+    x[:, 5], x[:, 6], x[:, 7] = 0.5, 1.0, 1.0
+    for _ in range(3):
+        net.forward(x)
+    times = []
+    for _ in range(20):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        net.forward(x)
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    ms = float(np.median(times))
+    fl = forward_flops(B, H, W)
+    print("forward B=%d %dx%d conv_mode %d: %.4f ms, %.1f TFLOP/s (%.1f on the matrix cores "
+          "with the hi/lo split, %.1f%% of the 2.5 PFLOP/s BF16 peak)"
+          % (B, H, W, mode, ms, fl / ms / 1e9, 3 * fl / ms / 1e9, 3 * fl / ms / 1e9 / 25.0),
+          flush=True)
+
+
+if __name__ == "__main__":
+    main()
