@@ -443,6 +443,29 @@ def surrogate_leg(weights_path):
             "mfma_TFLOP/s": round(split * fl / ms / 1e9, 2),
             "frac_of_bf16_peak": round(split * fl / ms / 1e9 / BF16_PEAK_TFLOPS, 4)}
         del net
+    # training step (forward, loss, backward, Adam) at the training shape
+    B, H = 32, 128
+    net = Surrogate(B, H, H, split=3, train=True)
+    net.set_params(params)
+    x = torch.randn(B, 8, H, H, device="cuda")
+    x[:, 5], x[:, 6], x[:, 7] = 0.5, 1.0, 1.0
+    tgt = x[:, :5].contiguous()
+    for _ in range(3):
+        net.train_step(x, tgt, lr=0.0, want_loss=False)
+    e0.record()
+    for _ in range(10):
+        net.train_step(x, tgt, lr=0.0, want_loss=False)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 10
+    fl = 3 * unet_flops(H, H, B)  # forward + data gradients + weight gradients
+    out["train_step_b%d_%d" % (B, H)] = {
+        "ms": round(ms, 4), "GFLOP": round(fl / 1e9, 2), "TFLOP/s": round(fl / ms / 1e9, 2),
+        "mfma_TFLOP/s": round(3 * fl / ms / 1e9, 2),
+        "frac_of_bf16_peak": round(3 * fl / ms / 1e9 / BF16_PEAK_TFLOPS, 4),
+        "note": "forward + backward (data and weight gradients of every convolution) + Adam; "
+                "FLOP counted as three forward passes"}
+    del net
     # serving comparison (C5 shape): seeded material and GRF data
     prob = synth.grf_problem(256, 256, synth.DIRICHLET, seed=5)
     plain_ms, variant, plain_final, variants = serve.plain_time_to_solution(prob, 4096, reps=3)

@@ -479,12 +479,12 @@ void launch_conv_shape(int k, sg_net* n, const Tensor& x, const float* xscale,
   }
 }
 
-template <int SPLIT, int PB, int NB, bool WL, int WT>
+template <int SPLIT, int PB, int NB, bool WL, int WT, int RW = 64 / WT>
 void launch_convt(sg_net* n, const Tensor& x, const float* xscale, const unsigned short* wh,
                   const unsigned short* wl, Tensor& z, int cin, int cout, int accumulate) {
-  constexpr int CT = (4 / (64 / (16 * PB))) * 16 * NB;
-  dim3 grid((unsigned)((int64_t)n->B * x.H * x.W / 64), (unsigned)(cout / CT));
-  hipLaunchKernelGGL((k_convt<SPLIT, PB, NB, WL, WT>), grid, dim3(256), 0, n->stream,
+  constexpr int CT = (4 / (RW * WT / (16 * PB))) * 16 * NB;
+  dim3 grid((unsigned)((int64_t)n->B * x.H * x.W / (RW * WT)), (unsigned)(cout / CT));
+  hipLaunchKernelGGL((k_convt<SPLIT, PB, NB, WL, WT, RW>), grid, dim3(256), 0, n->stream,
                      (const float*)x.p, xscale, wh, wl, z.p, x.H, x.W, cin, cout, n->circular,
                      accumulate);
 }
@@ -498,6 +498,13 @@ template <int SPLIT, int WT>
 void conv_tiled_w(sg_net* n, const Tensor& x, const float* xscale, const unsigned short* wh,
                   const unsigned short* wl, Tensor& z, int cin, int cout, int accumulate) {
   const int64_t tiles = (int64_t)n->B * x.H * x.W / 64;
+  // blocks of 4 rows x 64 pixels (one wave per row, 32 output channels,
+  // weights in LDS) where they still give 256 workgroups: the weights and
+  // the halo rows are staged once for 4x as many pixels
+  if (WT == 64 && n->conv_mode != 2 && x.H % 4 == 0 && tiles / 4 * (cout / 32) >= 256) {
+    launch_convt<SPLIT, 4, 2, true, 64, 4>(n, x, xscale, wh, wl, z, cin, cout, accumulate);
+    return;
+  }
   if (cout % 64 == 0 && tiles * (cout / 64) >= 512)
     launch_convt<SPLIT, 2, 2, false, WT>(n, x, xscale, wh, wl, z, cin, cout, accumulate);
   else if (n->conv_mode == 2)

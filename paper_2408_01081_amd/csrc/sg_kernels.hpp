@@ -190,8 +190,8 @@ __global__ __launch_bounds__(256) void k_conv(const unsigned short* __restrict__
 
 // ---------------------------------------------------------------------------
 // The same convolution with the input tile staged in LDS.  A workgroup computes
-// 64 consecutive pixels of one image (a row piece when W >= 64, W % 64 == 0;
-// 64 / W whole rows when W = 32 or 16) x CT output channels; for every
+// a block of RW rows x WT pixels of one image (WT = 64 with W % 64 == 0, or
+// WT = W = 32 or 16; RW * WT = 64 or 256) x CT output channels; for every
 // 32-channel chunk of the input the neighbourhood of those pixels (one pixel
 // more on every side) is read from the FP32 activations, multiplied by the gain and
 // split into BF16 hi and lo parts exactly as k_split_bf16 does, and stored in
@@ -202,19 +202,20 @@ __global__ __launch_bounds__(256) void k_conv(const unsigned short* __restrict__
 // blocks), so the two give bitwise identical results.  Cin % 32 == 0,
 // Cout % CT == 0.
 // ---------------------------------------------------------------------------
-template <int SPLIT, int PB, int NB, bool WL = false, int WT = 64>
+template <int SPLIT, int PB, int NB, bool WL = false, int WT = 64, int RW = 64 / WT>
 __global__ __launch_bounds__(256) void k_convt(const float* __restrict__ X,
                                                const float* __restrict__ xscale,
                                                const unsigned short* __restrict__ Whi,
                                                const unsigned short* __restrict__ Wlo,
                                                float* __restrict__ Z, int H, int W, int Cin,
                                                int Cout, int circular, int accumulate) {
-  constexpr int WPX = 64 / (16 * PB);  // waves along the pixels
-  constexpr int WCO = 4 / WPX;         // waves along the output channels
-  static_assert(WPX * WCO == 4, "four waves per workgroup");
-  constexpr int CT = WCO * 16 * NB;    // output channels per workgroup
-  // the 64 pixels are 64 / WT rows of WT pixels (WT = 64 for W >= 64, else W)
-  constexpr int TR = 64 / WT + 2;      // tile rows: those rows + one each side
+  // the workgroup's pixels: RW rows of WT pixels (WT = 64 for W >= 64, else W)
+  constexpr int NPX = RW * WT;
+  constexpr int WPX = NPX / (16 * PB);  // waves along the pixels
+  constexpr int WCO = 4 / WPX;          // waves along the output channels
+  static_assert(WPX * WCO == 4 && NPX % (16 * PB) == 0, "four waves per workgroup");
+  constexpr int CT = WCO * 16 * NB;     // output channels per workgroup
+  constexpr int TR = RW + 2;           // tile rows: those rows + one each side
   constexpr int TW = WT + 2;           // tile columns: WT pixels + one each side
   constexpr int PS = 20;               // dwords per tile pixel
   constexpr int NH = SPLIT == 3 ? 2 : 1;
@@ -228,12 +229,11 @@ __global__ __launch_bounds__(256) void k_convt(const float* __restrict__ X,
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int m = lane & 15, kq = lane >> 4;
   const int wp = wave % WPX, wc = wave / WPX;
-  // the workgroup's 64 consecutive pixels (row-major within one image)
-  const int64_t p0 = (int64_t)blockIdx.x * 64;
-  const int64_t HW = (int64_t)H * W;
-  const int b = (int)(p0 / HW);
-  const int rem = (int)(p0 - (int64_t)b * HW);
-  const int y = rem / W, x0 = rem - (rem / W) * W;
+  // the workgroup's block: rows y .. y + RW - 1, columns x0 .. x0 + WT - 1
+  const int tx = W / WT, tiles = (H / RW) * tx;
+  const int b = (int)(blockIdx.x / (unsigned)tiles);
+  const int rem = (int)(blockIdx.x - (unsigned)b * (unsigned)tiles);
+  const int y = (rem / tx) * RW, x0 = (rem - (rem / tx) * tx) * WT;
   const int cw = 16 * NB * wc;  // the wave's channels within the workgroup's CT
   const int co0 = blockIdx.y * CT + cw;
   const int px0 = 16 * PB * wp;
@@ -332,14 +332,15 @@ __global__ __launch_bounds__(256) void k_convt(const float* __restrict__ X,
       }
     }
   }
-  const int64_t pix = p0 + px0;
 #pragma unroll
   for (int pb = 0; pb < PB; ++pb)
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        float* zp = Z + (pix + 16 * pb + 4 * kq + j) * Cout + co0 + 16 * nb + m;
+        const int p = px0 + 16 * pb + 4 * kq + j, r = p / WT, xp = p - r * WT;
+        const int64_t pix = ((int64_t)b * H + y + r) * W + x0 + xp;
+        float* zp = Z + pix * Cout + co0 + 16 * nb + m;
         *zp = accumulate ? *zp + acc[pb][nb][j] : acc[pb][nb][j];
       }
 }

@@ -128,10 +128,10 @@ def test_adam_step_matches_reference_and_loss_decreases():
 
 @gpu
 @pytest.mark.parametrize("split,circular,B,H,W", [(3, True, 1, 256, 256), (3, False, 2, 128, 256),
-                                                  (1, False, 1, 64, 128)])
+                                                  (3, True, 32, 64, 128), (1, False, 4, 64, 128)])
 def test_tiled_and_direct_convolutions_agree(split, circular, B, H, W):
-    # the LDS-tiled convolution (rows that are multiples of 64 pixels) and the
-    # direct one compute the same products; only the FP32 summation order of
+    # the LDS-tiled convolution (blocks of 4 x 64, 1 x 64, 2 x 32 and 4 x 16
+    # pixels across these shapes) and the direct one compute the same products; only the FP32 summation order of
     # the reduction slices may differ (with plain BF16 operands such a
     # difference can flip the rounding of the next layer's operand, so the
     # bound is that of the split-1 reference comparison)
