@@ -247,18 +247,40 @@ __global__ __launch_bounds__(RT) void k_sum_partials(const double* __restrict__ 
   if (threadIdx.x == 0) *out = s;
 }
 
-// dgamma[b][c] = sum_p g[b,p,c] z[b,p,c]: one workgroup per (b, c), fixed-order tree
-__global__ __launch_bounds__(RT) void k_film_grad(const float* __restrict__ g,
-                                                  const float* __restrict__ z, int HW, int C,
-                                                  float* __restrict__ dgam) {
+// dgamma[b][c] = sum_p g[b,p,c] z[b,p,c] (FiLM gain gradient).
+// Two passes with coalesced reads: workgroup (b, s) takes
+// pixel chunk s of sample b for all C channels (thread t: channel t mod C,
+// every (RT / C)-th pixel), FP64 partial sums per channel added in a fixed
+// order; then dgam[b][c] = sum over the S chunks in order.
+__global__ __launch_bounds__(RT) void k_film_grad_part(const float* __restrict__ g,
+                                                       const float* __restrict__ z, int HW, int C,
+                                                       int S, double* __restrict__ part) {
   __shared__ double sh[RT];
-  const int b = blockIdx.x / C, c = blockIdx.x - (blockIdx.x / C) * C;
+  const int b = blockIdx.x / S, sidx = blockIdx.x - (blockIdx.x / S) * S;
+  const int G = RT / C, c = threadIdx.x % C, grp = threadIdx.x / C;
+  const int64_t p0 = (int64_t)HW * sidx / S, p1 = (int64_t)HW * (sidx + 1) / S;
   const float* gp = g + (int64_t)b * HW * C + c;
   const float* zp = z + (int64_t)b * HW * C + c;
-  double s = 0.0;
-  for (int p = threadIdx.x; p < HW; p += RT) s += (double)gp[(int64_t)p * C] * zp[(int64_t)p * C];
-  s = wg_sum(s, sh);
-  if (threadIdx.x == 0) dgam[blockIdx.x] = (float)s;
+  double acc = 0.0;
+  if (grp < G)
+    for (int64_t p = p0 + grp; p < p1; p += G) acc += (double)gp[p * C] * zp[p * C];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  if ((int)threadIdx.x < C) {
+    double t = 0.0;
+    for (int k = 0; k < G; ++k) t += sh[k * C + threadIdx.x];
+    part[(int64_t)blockIdx.x * C + threadIdx.x] = t;
+  }
+}
+
+__global__ __launch_bounds__(RT) void k_film_grad_sum(const double* __restrict__ part, int B,
+                                                      int C, int S, float* __restrict__ dgam) {
+  const int e = blockIdx.x * RT + threadIdx.x;
+  if (e >= B * C) return;
+  const int b = e / C, c = e - b * C;
+  double t = 0.0;
+  for (int k = 0; k < S; ++k) t += part[((int64_t)b * S + k) * C + c];
+  dgam[e] = (float)t;
 }
 
 // da[c][m] = sum_b T[b][m] dgam[b][c]
@@ -634,14 +656,43 @@ void conv_back(sg_net* n, int l, const Tensor& gy, const Tensor& xin, const floa
   const LayerSpec& L = kLayers[l];
   const Tensor& zl = n->z[l];
   const int HW = zl.H * zl.W;
-  // FiLM coefficients
-  hipLaunchKernelGGL(k_film_grad, dim3(n->B * L.cout), dim3(RT), 0, n->stream, gy.p, zl.p, HW,
-                     L.cout, n->dgam);
+  // FiLM coefficients (the weight-gradient partials' buffer holds the
+  // per-chunk sums; it is rewritten only after they have been added)
+  int S = 16;
+  while (S > 1 && ((int64_t)n->B * S * L.cout * 2 > n->P.wpart_floats || HW / S < 64)) S /= 2;
+  hipLaunchKernelGGL(k_film_grad_part, dim3(n->B * S), dim3(RT), 0, n->stream, gy.p, zl.p, HW,
+                     L.cout, S, (double*)n->wpart);
+  hipLaunchKernelGGL(k_film_grad_sum, dim3(grid1((int64_t)n->B * L.cout)), dim3(RT), 0,
+                     n->stream, (const double*)n->wpart, n->B, L.cout, S, n->dgam);
   hipLaunchKernelGGL(k_film_coef_grad, dim3(grid1(L.cout * NBASIS)), dim3(RT), 0, n->stream,
                      (const float*)n->dgam, (const float*)n->T, n->B, L.cout,
                      n->grad + P.aoff[l]);
   // weights: dW = sum (gamma * gy) (x) (xscale * x)
   const int64_t pixels = (int64_t)n->B * HW;
+  if (n->conv_mode != 1 && zl.W % 64 == 0 && L.cin % 32 == 0 && L.cout % 32 == 0) {
+    // LDS-staged kernel: ~256 workgroups (one per CU: 92 KB of LDS), as many
+    // pixel-block groups as the partials' buffer holds
+    const int64_t nblocks = pixels / 64;
+    const int tiles = (L.cout / 32) * (L.cin / 32);
+    int64_t ng = 256 / tiles;
+    const int64_t cap = n->P.wpart_floats / ((int64_t)9 * L.cout * L.cin);
+    ng = ng > cap ? cap : ng;
+    ng = ng > nblocks ? nblocks : ng;
+    ng = ng < 1 ? 1 : ng;
+    if (P.split == 3)
+      hipLaunchKernelGGL((k_wgradt<3>), dim3((unsigned)ng, (unsigned)tiles), dim3(256), 0,
+                         n->stream, gy.p, (const float*)n->gam[l], xin.p, xscale, n->wpart, n->B,
+                         zl.H, zl.W, L.cin, L.cout, n->circular);
+    else
+      hipLaunchKernelGGL((k_wgradt<1>), dim3((unsigned)ng, (unsigned)tiles), dim3(256), 0,
+                         n->stream, gy.p, (const float*)n->gam[l], xin.p, xscale, n->wpart, n->B,
+                         zl.H, zl.W, L.cin, L.cout, n->circular);
+    const int64_t nw = (int64_t)9 * L.cout * L.cin;
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3((unsigned)((nw + 63) / 64)), dim3(RT), 0, n->stream,
+                       (const float*)n->wpart, (int)ng, L.cin, L.cout, n->grad + P.woff[l]);
+    if (gin.p) conv(n, gy, n->gam[l], l, gin, true, accumulate);
+    return;
+  }
   int nsplit = 1;
   while (nsplit < 64 && pixels / (nsplit * 2) >= 2048 && (pixels % (nsplit * 2 * 128)) == 0)
     nsplit *= 2;
@@ -668,7 +719,7 @@ void conv_back(sg_net* n, int l, const Tensor& gy, const Tensor& xin, const floa
                          L.cin, L.cout, n->circular, pps);
   }
   const int64_t nw = (int64_t)9 * L.cout * L.cin;
-  hipLaunchKernelGGL(k_wgrad_reduce, dim3(grid1(nw)), dim3(RT), 0, n->stream,
+  hipLaunchKernelGGL(k_wgrad_reduce, dim3((unsigned)((nw + 63) / 64)), dim3(RT), 0, n->stream,
                      (const float*)n->wpart, nsplit, L.cin, L.cout, n->grad + P.woff[l]);
   // data gradient: conv with flipped, transposed weights of (gamma * gy)
   if (gin.p) conv(n, gy, n->gam[l], l, gin, true, accumulate);

@@ -441,17 +441,161 @@ __global__ __launch_bounds__(256) void k_wgrad(const float* __restrict__ G,
 }
 
 // sum the pixel splits in a fixed order: grad[o][i][t] (master layout)
+// The weight gradient with both operands staged in LDS, channel-major (the
+// matrix core's reduction runs over pixels, which must be contiguous per
+// channel): a workgroup owns a 32 x 32 (output, input channel) tile of all 9
+// taps and sweeps blocks of 64 pixels of one image row (W % 64 == 0), blocks
+// blockIdx.x, blockIdx.x + gridDim.x, ...  Per block it stages
+//   gT[h][o][p]      gamma-scaled gradient, split into hi/lo, 72 bf16 per row;
+//   xT[h][d][i][r][c] the gain-scaled input of rows y-1..y+1 at columns
+//                    x0 - 1 + d + c (three copies d = 0, 1, 2 so that every
+//                    tap reads 8 pixels at an aligned offset), 72 per row;
+// (row strides of 36 and 108 dwords keep the 16 lanes of a fragment read on
+// distinct banks).  Wave w computes the 16 x 16 sub-tile (w / 2, w mod 2) for
+// all taps and writes partial[blockIdx.x][t][o][i] for k_wgrad_reduce.
+template <int SPLIT>
+__global__ __launch_bounds__(256) void k_wgradt(const float* __restrict__ G,
+                                                const float* __restrict__ gscale,
+                                                const float* __restrict__ X,
+                                                const float* __restrict__ xscale,
+                                                float* __restrict__ partial, int B, int H, int W,
+                                                int Cin, int Cout, int circular) {
+  constexpr int NH = SPLIT == 3 ? 2 : 1;
+  constexpr int RS = 72;                      // bf16 per staged row (64 + 8 padding)
+  constexpr int GT = 32 * RS;                 // gT elements per hi/lo part
+  constexpr int XT = 3 * 32 * 3 * RS;         // xT elements per hi/lo part
+  __shared__ uint4 lds4[NH * (GT + XT) * 2 / 16];
+  unsigned short* gT = reinterpret_cast<unsigned short*>(lds4);
+  unsigned short* xT = gT + NH * GT;
+
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int m = lane & 15, kq = lane >> 4;
+  const int nit = Cin / 32;
+  const int o0 = (int)(blockIdx.y / (unsigned)nit) * 32, i0 = (int)(blockIdx.y % (unsigned)nit) * 32;
+  const int ow = 16 * (wave >> 1), iw = 16 * (wave & 1);
+  const int tx = W / 64;
+  const int64_t nblocks = (int64_t)B * H * tx;
+
+  f32x4 acc[9];
+#pragma unroll
+  for (int t = 0; t < 9; ++t) acc[t] = (f32x4){0.f, 0.f, 0.f, 0.f};
+
+  for (int64_t blk = blockIdx.x; blk < nblocks; blk += gridDim.x) {
+    const int b = (int)(blk / ((int64_t)H * tx));
+    const int rem = (int)(blk - (int64_t)b * H * tx);
+    const int y = rem / tx, x0 = (rem - (rem / tx) * tx) * 64;
+    __syncthreads();  // the previous block's fragments have been read
+    {
+      // gradient: thread t -> pixel t / 4, output channels 8 (t mod 4) ...
+      const int p = threadIdx.x >> 2, q = threadIdx.x & 3;
+      const int64_t go = (((int64_t)b * H + y) * W + x0 + p) * Cout + o0 + 8 * q;
+      const float4 u0 = *reinterpret_cast<const float4*>(G + go);
+      const float4 u1 = *reinterpret_cast<const float4*>(G + go + 4);
+      float a[8] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w};
+      if (gscale) {
+        const float* sc = gscale + (int64_t)b * Cout + o0 + 8 * q;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) a[j] *= sc[j];
+      }
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const unsigned short h = bf16_bits(a[j]);
+        gT[(8 * q + j) * RS + p] = h;
+        if (SPLIT == 3) gT[GT + (8 * q + j) * RS + p] = bf16_bits(a[j] - bf16_value(h));
+      }
+    }
+    // input: rows y-1..y+1, halo columns 0..65 (image x0 - 1 + hc), 4 x 8 channels
+    for (int it = threadIdx.x; it < 3 * 66 * 4; it += 256) {
+      const int q = it & 3, hc = (it >> 2) % 66, r = (it >> 2) / 66;
+      int ys = y + r - 1, xs = x0 + hc - 1;
+      bool valid = true;
+      if (circular) {
+        ys = ys < 0 ? ys + H : (ys >= H ? ys - H : ys);
+        xs = xs < 0 ? xs + W : (xs >= W ? xs - W : xs);
+      } else {
+        valid = ys >= 0 && ys < H && xs >= 0 && xs < W;
+      }
+      float a[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+      if (valid) {
+        const int64_t xo = (((int64_t)b * H + ys) * W + xs) * Cin + i0 + 8 * q;
+        const float4 u0 = *reinterpret_cast<const float4*>(X + xo);
+        const float4 u1 = *reinterpret_cast<const float4*>(X + xo + 4);
+        a[0] = u0.x; a[1] = u0.y; a[2] = u0.z; a[3] = u0.w;
+        a[4] = u1.x; a[5] = u1.y; a[6] = u1.z; a[7] = u1.w;
+        if (xscale) {
+          const float* sc = xscale + (int64_t)b * Cin + i0 + 8 * q;
+#pragma unroll
+          for (int j = 0; j < 8; ++j) a[j] *= sc[j];
+        }
+      }
+      unsigned short hb[8], lb[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        hb[j] = bf16_bits(a[j]);
+        lb[j] = bf16_bits(a[j] - bf16_value(hb[j]));
+      }
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const int c = hc - d;
+        if (c < 0 || c >= 64) continue;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int e = ((d * 32 + 8 * q + j) * 3 + r) * RS + c;
+          xT[e] = hb[j];
+          if (SPLIT == 3) xT[XT + e] = lb[j];
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks) {
+      const int pk = 32 * ks + 8 * kq;
+      const int ga = (ow + m) * RS + pk;
+      const bf16x8 ahi = *reinterpret_cast<const bf16x8*>(gT + ga);
+      bf16x8 alo;
+      if (SPLIT == 3) alo = *reinterpret_cast<const bf16x8*>(gT + GT + ga);
+#pragma unroll
+      for (int t = 0; t < 9; ++t) {
+        const int r = t / 3, d = t % 3;  // dy + 1, dx + 1
+        const int xb = ((d * 32 + iw + m) * 3 + r) * RS + pk;
+        const bf16x8 bhi = *reinterpret_cast<const bf16x8*>(xT + xb);
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, bhi, acc[t], 0, 0, 0);
+        if (SPLIT == 3) {
+          const bf16x8 blo = *reinterpret_cast<const bf16x8*>(xT + XT + xb);
+          acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo, bhi, acc[t], 0, 0, 0);
+          acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, blo, acc[t], 0, 0, 0);
+        }
+      }
+    }
+  }
+  // D[row = o (4 kq + j)][col = i (m)]
+#pragma unroll
+  for (int t = 0; t < 9; ++t)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      partial[(((int64_t)blockIdx.x * 9 + t) * Cout + o0 + ow + 4 * kq + j) * Cin + i0 + iw + m] =
+          acc[t][j];
+}
+
 __global__ __launch_bounds__(256) void k_wgrad_reduce(const float* __restrict__ partial,
                                                       int nsplit, int Cin, int Cout,
                                                       float* __restrict__ grad) {
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  // 64 weights per workgroup, 4 groups of threads summing every 4th split,
+  // the 4 group sums added in order
+  __shared__ float sh[4][64];
+  const int el = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int64_t e = (int64_t)blockIdx.x * 64 + el;
   const int64_t n = (int64_t)9 * Cout * Cin;
-  if (e >= n) return;
+  float s = 0.f;
+  if (e < n)
+    for (int k = g; k < nsplit; k += 4) s += partial[(int64_t)k * n + e];
+  sh[g][el] = s;
+  __syncthreads();
+  if (g || e >= n) return;
+  s = ((sh[0][el] + sh[1][el]) + sh[2][el]) + sh[3][el];
   const int t = (int)(e / ((int64_t)Cout * Cin));
   const int64_t oi = e - (int64_t)t * Cout * Cin;
   const int o = (int)(oi / Cin), i = (int)(oi - (int64_t)o * Cin);
-  float s = 0.f;
-  for (int k = 0; k < nsplit; ++k) s += partial[(int64_t)k * n + e];
   grad[((int64_t)o * Cin + i) * 9 + t] = s;
 }
 
