@@ -115,7 +115,7 @@ def main():
              "threads": c["threads"], "nontemporal": c["nontemporal"], "shuffle": c["shuffle"],
              "tblock_config": idx2}
         if idx2 >= 0:
-            t["tblock"] = lat.tblock_configs()[idx2]
+            t["tblock"] = next(k for k in lat.tblock_configs() if k["index"] == idx2)
         tuned.append(t)
     log("autotuned: %s" % tuned)
     for lat in lats:
@@ -153,8 +153,10 @@ def main():
     blocked = tuned[0]["tblock_config"] >= 0
     T = tuned[0]["tblock"]["steps"] if blocked else 1
     per_ms = ev[0][0].elapsed_time(ev[0][1])
-    # lbm_step runs chunks of 420 steps, T per launch; leftover steps one at a time
-    launches = (K // 420) * (420 // T) + (K % 420) // T if blocked else K
+    # lbm_step runs chunks of floor(420 / T) T steps, T per launch; leftover
+    # steps one at a time
+    chunk = 420 // T * T
+    launches = (K // chunk) * (chunk // T) + (K % chunk) // T if blocked else K
     single_left = K - launches * T if blocked else 0
     kern_ms = per_ms / (launches + single_left / T)   # a single step counts 1/T of a launch
     alg_bytes = BYTES_PER_LUP * per.nx * per.ny

@@ -263,14 +263,14 @@ lbm_status lbm_autotune(lbm_ctx* ctx, int32_t reps, int32_t use_cache, int32_t* 
  * state.  A wave owns a strip of 64 columns and sweeps a segment of rows,
  * forming the T - 1 intermediate time levels in registers, so T steps read and
  * write the populations once (80 B + 80 B per node for T updates).  Bitwise
- * identical to T single steps.  Variants (h_steps = T in 2..7) differ in rows
+ * identical to T single steps.  Variants (h_steps = T in 2..8) differ in rows
  * per segment, store type and rows prefetched ahead (h_prefetch); h_seg_rows
  * 0 means the segment length is chosen at launch so that one wave per
  * resident slot covers the grid, -k that k waves per slot do.  index -1 disables blocking; lbm_autotune
  * selects a variant when it is faster per step than the best single-step
  * configuration.  With a variant of T steps enabled, lbm_step(n) runs the
- * steps in chunks of 420 (a multiple of every T offered), T per launch, and
- * only the last (n mod 420) mod T steps one at a time.  Grids whose row byte
+ * steps in chunks of floor(420 / T) T steps, T per launch, and only the
+ * last (n mod chunk) mod T steps one at a time.  Grids whose row byte
  * offsets ((19 planes + one row) * 4 B) reach 2^31 cannot use it: setting or
  * timing a variant then fails with LBM_E_ARG and the autotuner skips it.  Any
  * output pointer may be NULL. */

@@ -420,8 +420,9 @@ struct lbm_ctx {
 
 namespace {
 
-// steps whose wall velocities are summed ahead in one launch (a multiple of
-// every blocked variant's step count, so blocked launches fill a chunk)
+// most steps whose wall velocities are summed ahead in one launch; a lattice
+// stepping T per blocked launch uses chunks of floor(WALL_CHUNK / T) T steps
+// so that blocked launches fill every chunk
 constexpr int WALL_CHUNK = 420;
 
 // the wall-velocity table exists for Dirichlet lattices only
@@ -761,10 +762,13 @@ const TBConfig kTBConfigs[] = {
     LBM_TB(7, 32, 0, 1), LBM_TB(7, 48, 0, 1), LBM_TB(7, 64, 0, 1), LBM_TB(7, 32, 1, 1),
     LBM_TB(7, 0, 0, 1),  LBM_TB(7, -2, 0, 1), LBM_TB(6, 0, 0, 1),  LBM_TB(5, 0, 0, 1),
     LBM_TB(7, 16, 0, 1), LBM_TB(7, 24, 0, 1), LBM_TB(7, 20, 0, 2), LBM_TB(7, 30, 0, 2),
-    LBM_TB(6, 8, 0, 1),  LBM_TB(6, 12, 0, 1), LBM_TB(6, 20, 0, 2), LBM_TB(6, 30, 0, 2)};
+    LBM_TB(6, 8, 0, 1),  LBM_TB(6, 12, 0, 1), LBM_TB(6, 20, 0, 2), LBM_TB(6, 30, 0, 2),
+    LBM_TB(8, 20, 0, 2), LBM_TB(8, 30, 0, 2), LBM_TB(8, 24, 0, 1), LBM_TB(8, 32, 0, 1),
+    LBM_TB(8, 0, 0, 2),  LBM_TB(8, -2, 0, 2), LBM_TB(8, 0, 0, 1),  LBM_TB(7, 0, 0, 2)};
 #undef LBM_TB
 constexpr int kNumTBConfigs = (int)(sizeof(kTBConfigs) / sizeof(kTBConfigs[0]));
 static_assert(kNumTBConfigs <= 64, "tb_slots size");
+
 
 // Sum the wall velocities of steps step0 .. step0 + n - 1 (n <= WALL_CHUNK)
 // into the context's table; no-op without wall data.
@@ -788,7 +792,7 @@ Wall zero_wall(const lbm_ctx* c) {
 // For timing launches: sum the walls of the next `n` steps (the most steps a
 // blocked launch takes) into the table when the context has wall data for
 // them.
-bool timing_walls(lbm_ctx* c, int n = 7) {
+bool timing_walls(lbm_ctx* c, int n = 8) {
   if (c->wall_rank == 0 || c->nstep + n > c->wall_nsteps) return false;
   eval_walls(c, c->nstep, n);
   return true;
@@ -812,6 +816,9 @@ WallSeq walls_from(const lbm_ctx* c, int s, bool with_walls) {
   return ws;
 }
 
+// Rows per segment of variant `index`: its seg_rows, or for seg_rows <= 0 as
+// many as give one wave per resident slot (times -seg_rows) across the grid,
+// rounded up to the ring length.
 int tb_seg_rows(lbm_ctx* c, int index) {
   const TBConfig& k = kTBConfigs[index];
   if (k.seg_rows > 0) return k.seg_rows;
@@ -908,13 +915,14 @@ lbm_status lbm_step(lbm_ctx* c, int64_t nsteps) {
   const StepConfig& cfg = kStepConfigs[c->step_cfg];
   const StepConst sc = step_const(cfg, g, (float)c->kK, (float)c->km);
   const StepFn fn = cfg.fn[c->p.bc];
-  // chunks of WALL_CHUNK steps: the chunk's wall velocities are summed first,
-  // then its steps run, T per launch with a blocked variant (WALL_CHUNK is a
-  // multiple of every T in the table, so only the last T-1 steps or fewer of
-  // a total run one at a time)
+  // chunks of a multiple of T steps (at most WALL_CHUNK): the chunk's wall
+  // velocities are summed first, then its steps run, T per launch with a
+  // blocked variant, so only the last T-1 steps or fewer of a total run one
+  // at a time
   const int T = c->tb_cfg >= 0 ? kTBConfigs[c->tb_cfg].steps : 1;
-  for (int64_t s0 = 0; s0 < nsteps; s0 += WALL_CHUNK) {
-    const int m = (int)(nsteps - s0 < WALL_CHUNK ? nsteps - s0 : WALL_CHUNK);
+  const int chunk = WALL_CHUNK / T * T;
+  for (int64_t s0 = 0; s0 < nsteps; s0 += chunk) {
+    const int m = (int)(nsteps - s0 < chunk ? nsteps - s0 : chunk);
     eval_walls(c, c->nstep + s0, m);
     int k = 0;
     if (T > 1) {

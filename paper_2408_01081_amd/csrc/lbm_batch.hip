@@ -174,10 +174,10 @@ __global__ __launch_bounds__(BT) void k_batch_moments(const float* __restrict__ 
   const int64_t ni = (int64_t)d.g.nx * d.g.ny;
   const int y = (int)(loc / d.g.nx), x = (int)(loc - (int64_t)y * d.g.nx);
   const float* src = pool + d.off;
-  float U[NC];
-  for (int c = 0; c < NC; ++c)
-    U[c] = (src[pidx(d.g, 0 * NC + c, y, x)] + src[pidx(d.g, 1 * NC + c, y, x)]) +
-           (src[pidx(d.g, 2 * NC + c, y, x)] + src[pidx(d.g, 3 * NC + c, y, x)]);
+  float f[NQ][NC], U[NC];
+  for (int q = 0; q < NQ; ++q)
+    for (int c = 0; c < NC; ++c) f[q][c] = src[pidx(d.g, q * NC + c, y, x)];
+  moment0(f, U);  // the single lattice's summation order
   float* o = out + 5 * d.node0 + loc;
   if (mode == 1) {
     for (int c = 0; c < NC; ++c) o[c * ni] = U[c];
@@ -235,7 +235,8 @@ __global__ __launch_bounds__(BT) void k_batch_reduce(const float* __restrict__ p
       double Ur[NC];
       to_U(d.ic, rr[0], rr[ni], rr[2 * ni], rr[3 * ni], rr[4 * ni], Ur);
       for (int c = 0; c < NC; ++c) {
-        const float u32 = ((float)f[0][c] + (float)f[1][c]) + ((float)f[2][c] + (float)f[3][c]);
+        // U in FP32 as the lattice forms it (moment0's order)
+        const float u32 = (float)f[2][c] + ((float)f[0][c] + ((float)f[1][c] + (float)f[3][c]));
         const double u = (double)u32, e = u - Ur[c];
         a += e * e;
         b += u * u;

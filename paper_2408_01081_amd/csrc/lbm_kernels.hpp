@@ -73,15 +73,20 @@ __device__ inline void wall_rule(int i, int j, float kK, float km, float a, floa
   out[4] = fb[4] + km * (float)(j) * a + km * (float)(i) * b;
 }
 
-// Zeroth moment sum_q f_q of one node (the scheme's U without the load term).
+// Zeroth moment sum_q f_q of one node (the scheme's U without the load term),
+// summed as f_2 + (f_0 + (f_1 + f_3)): the y neighbours first, then one x
+// neighbour at a time, the order in which the blocked kernel's cross-lane
+// adds can consume them.
 __device__ inline void moment0(const float f[NQ][NC], float U[NC]) {
 #pragma unroll
-  for (int c = 0; c < NC; ++c) U[c] = (f[0][c] + f[1][c]) + (f[2][c] + f[3][c]);
+  for (int c = 0; c < NC; ++c) U[c] = f[2][c] + (f[0][c] + (f[1][c] + f[3][c]));
 }
 
 // omega = 2 collision of one node for a given moment U:
-// f*_q = 2 f_eq,q(U) - f_q = h + s_q C U - f_q with h = U/2 (Eq. feq).
-// Written once so every kernel variant rounds identically.
+// f*_q = 2 f_eq,q(U) - f_q = (U/2 + s_q C U) - f_q (Eq. feq), the first
+// bracket as one fused multiply-add (U/2 is exact, so this rounds as the sum
+// of h = U/2 and s_q C U would).  Written once so every kernel variant
+// rounds identically.
 __device__ inline void collide_with(float kK, float km, const float U[NC], float f[NQ][NC]) {
   // X = Phi_x(U)/c, Y = Phi_y(U)/c
   const float X0 = fmaf(kK, U[2], km * U[3]);
@@ -98,11 +103,10 @@ __device__ inline void collide_with(float kK, float km, const float U[NC], float
   const float Y[NC] = {Y0, Y1, Y2, Y3, Y4};
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
-    const float h = 0.5f * U[c];
-    f[0][c] = (h + X[c]) - f[0][c];
-    f[1][c] = (h + Y[c]) - f[1][c];
-    f[2][c] = (h - X[c]) - f[2][c];
-    f[3][c] = (h - Y[c]) - f[3][c];
+    f[0][c] = fmaf(0.5f, U[c], X[c]) - f[0][c];
+    f[1][c] = fmaf(0.5f, U[c], Y[c]) - f[1][c];
+    f[2][c] = fmaf(0.5f, U[c], -X[c]) - f[2][c];
+    f[3][c] = fmaf(0.5f, U[c], -Y[c]) - f[3][c];
   }
 }
 

@@ -87,58 +87,79 @@ __device__ inline float from_lane_above(float v) {
   return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x130, 0xf, 0xf, true));
 }
 
-// Shifted operands folded into the add / subtract that consumes them
-// (DPP source operand): r_c = a_c(lane - 1) + b_c and s_c = c_c(lane + 1)
-// + d_c, five components each, with the same bound control as the shifts
-// above.  The compiler folds a separate shift only when all its uses follow
-// within a few instructions, which the blocked kernel's long sub-iterations
-// defeat.  A VALU write of a register needs two wait states before a DPP
-// read of it; the assembler block starts with them (s_nop 1) because the
-// hazard check does not look inside it, and its results are early-clobber
-// so no input is overwritten before the block has read it.
-__device__ __forceinline__ void add_shifted(const float a[NC], const float b[NC],
-                                            const float c[NC], const float d[NC],
-                                            float r[NC], float s[NC]) {
+// Shifted operands folded into the add / subtract that consumes them (DPP
+// source operand, wave_shr:1 reads lane - 1, wave_shl:1 lane + 1, bound
+// control as in the shifts above).  The compiler folds a separate shift only
+// when all its uses follow within a few instructions, which the blocked
+// kernel's long sub-iterations defeat, so the two blocks below are assembler.
+// A DPP instruction must not read a register that one of the two VALU
+// instructions before it wrote; the compiler's hazard check does not look
+// inside an assembler block, so each block opens with five or more plain VALU
+// instructions that write none of the registers its DPP instructions read
+// from outside, and every in-block value is read three or more instructions
+// after it is written.  Outputs are early-clobber: no input register is
+// overwritten before the block has read it.
+
+// U_c = f2_c(lane + 1) + (f0_c(lane - 1) + (f1_c + f3_c)), c = 0 .. 4 (the
+// association of moment0); s is scratch.
+__device__ __forceinline__ void moment_shifted(const float f0[NC], const float f1[NC],
+                                               const float f2[NC], const float f3[NC],
+                                               float U[NC]) {
+  float s[NC];
   asm volatile(
-      "s_nop 1\n\t"
-      "v_add_f32_dpp %0, %10, %15 wave_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
-      "v_add_f32_dpp %1, %11, %16 wave_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
-      "v_add_f32_dpp %2, %12, %17 wave_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
-      "v_add_f32_dpp %3, %13, %18 wave_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
-      "v_add_f32_dpp %4, %14, %19 wave_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
-      "v_add_f32_dpp %5, %20, %25 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
-      "v_add_f32_dpp %6, %21, %26 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
-      "v_add_f32_dpp %7, %22, %27 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
-      "v_add_f32_dpp %8, %23, %28 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
-      "v_add_f32_dpp %9, %24, %29 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1"
-      : "=&v"(r[0]), "=&v"(r[1]), "=&v"(r[2]), "=&v"(r[3]), "=&v"(r[4]), "=&v"(s[0]),
+      "v_add_f32 %5, %15, %25\n\t"
+      "v_add_f32 %6, %16, %26\n\t"
+      "v_add_f32 %7, %17, %27\n\t"
+      "v_add_f32 %8, %18, %28\n\t"
+      "v_add_f32 %9, %19, %29\n\t"
+      "v_add_f32_dpp %5, %10, %5 wave_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_add_f32_dpp %6, %11, %6 wave_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_add_f32_dpp %7, %12, %7 wave_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_add_f32_dpp %8, %13, %8 wave_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_add_f32_dpp %9, %14, %9 wave_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_add_f32_dpp %0, %20, %5 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_add_f32_dpp %1, %21, %6 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_add_f32_dpp %2, %22, %7 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_add_f32_dpp %3, %23, %8 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_add_f32_dpp %4, %24, %9 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1"
+      : "=&v"(U[0]), "=&v"(U[1]), "=&v"(U[2]), "=&v"(U[3]), "=&v"(U[4]), "=&v"(s[0]),
         "=&v"(s[1]), "=&v"(s[2]), "=&v"(s[3]), "=&v"(s[4])
-      : "v"(a[0]), "v"(a[1]), "v"(a[2]), "v"(a[3]), "v"(a[4]), "v"(b[0]), "v"(b[1]),
-        "v"(b[2]), "v"(b[3]), "v"(b[4]), "v"(c[0]), "v"(c[1]), "v"(c[2]), "v"(c[3]),
-        "v"(c[4]), "v"(d[0]), "v"(d[1]), "v"(d[2]), "v"(d[3]), "v"(d[4]));
+      : "v"(f0[0]), "v"(f0[1]), "v"(f0[2]), "v"(f0[3]), "v"(f0[4]), "v"(f1[0]), "v"(f1[1]),
+        "v"(f1[2]), "v"(f1[3]), "v"(f1[4]), "v"(f2[0]), "v"(f2[1]), "v"(f2[2]), "v"(f2[3]),
+        "v"(f2[4]), "v"(f3[0]), "v"(f3[1]), "v"(f3[2]), "v"(f3[3]), "v"(f3[4]));
 }
 
-// r_c = b_c - a_c(lane - 1) and s_c = d_c - c_c(lane + 1) (see add_shifted)
-__device__ __forceinline__ void sub_shifted(const float a[NC], const float b[NC],
-                                            const float c[NC], const float d[NC],
-                                            float r[NC], float s[NC]) {
+// o0_c = fma(U_c, 1/2, X_c) - f0_c(lane - 1) and o2_c = fma(U_c, 1/2, -X_c)
+// - f2_c(lane + 1): the collision of populations 0 and 2 (collide_with).
+__device__ __forceinline__ void collide_shifted(const float U[NC], const float X[NC],
+                                                const float f0[NC], const float f2[NC],
+                                                float o0[NC], float o2[NC]) {
   asm volatile(
-      "s_nop 1\n\t"
-      "v_subrev_f32_dpp %0, %10, %15 wave_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
-      "v_subrev_f32_dpp %1, %11, %16 wave_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
-      "v_subrev_f32_dpp %2, %12, %17 wave_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
-      "v_subrev_f32_dpp %3, %13, %18 wave_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
-      "v_subrev_f32_dpp %4, %14, %19 wave_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
-      "v_subrev_f32_dpp %5, %20, %25 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
-      "v_subrev_f32_dpp %6, %21, %26 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
-      "v_subrev_f32_dpp %7, %22, %27 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
-      "v_subrev_f32_dpp %8, %23, %28 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
-      "v_subrev_f32_dpp %9, %24, %29 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1"
-      : "=&v"(r[0]), "=&v"(r[1]), "=&v"(r[2]), "=&v"(r[3]), "=&v"(r[4]), "=&v"(s[0]),
-        "=&v"(s[1]), "=&v"(s[2]), "=&v"(s[3]), "=&v"(s[4])
-      : "v"(a[0]), "v"(a[1]), "v"(a[2]), "v"(a[3]), "v"(a[4]), "v"(b[0]), "v"(b[1]),
-        "v"(b[2]), "v"(b[3]), "v"(b[4]), "v"(c[0]), "v"(c[1]), "v"(c[2]), "v"(c[3]),
-        "v"(c[4]), "v"(d[0]), "v"(d[1]), "v"(d[2]), "v"(d[3]), "v"(d[4]));
+      "v_fma_f32 %0, %10, 0.5, %15\n\t"
+      "v_fma_f32 %1, %11, 0.5, %16\n\t"
+      "v_fma_f32 %2, %12, 0.5, %17\n\t"
+      "v_fma_f32 %3, %13, 0.5, %18\n\t"
+      "v_fma_f32 %4, %14, 0.5, %19\n\t"
+      "v_fma_f32 %5, %10, 0.5, -%15\n\t"
+      "v_fma_f32 %6, %11, 0.5, -%16\n\t"
+      "v_fma_f32 %7, %12, 0.5, -%17\n\t"
+      "v_fma_f32 %8, %13, 0.5, -%18\n\t"
+      "v_fma_f32 %9, %14, 0.5, -%19\n\t"
+      "v_subrev_f32_dpp %0, %20, %0 wave_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_subrev_f32_dpp %1, %21, %1 wave_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_subrev_f32_dpp %2, %22, %2 wave_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_subrev_f32_dpp %3, %23, %3 wave_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_subrev_f32_dpp %4, %24, %4 wave_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_subrev_f32_dpp %5, %25, %5 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_subrev_f32_dpp %6, %26, %6 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_subrev_f32_dpp %7, %27, %7 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_subrev_f32_dpp %8, %28, %8 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_subrev_f32_dpp %9, %29, %9 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1"
+      : "=&v"(o0[0]), "=&v"(o0[1]), "=&v"(o0[2]), "=&v"(o0[3]), "=&v"(o0[4]), "=&v"(o2[0]),
+        "=&v"(o2[1]), "=&v"(o2[2]), "=&v"(o2[3]), "=&v"(o2[4])
+      : "v"(U[0]), "v"(U[1]), "v"(U[2]), "v"(U[3]), "v"(U[4]), "v"(X[0]), "v"(X[1]),
+        "v"(X[2]), "v"(X[3]), "v"(X[4]), "v"(f0[0]), "v"(f0[1]), "v"(f0[2]), "v"(f0[3]),
+        "v"(f0[4]), "v"(f2[0]), "v"(f2[1]), "v"(f2[2]), "v"(f2[3]), "v"(f2[4]));
 }
 
 // one level-update of row y at this lane's column x from the rows below,
@@ -149,12 +170,9 @@ __device__ __forceinline__ void level_update(const float below[NP], const float 
                                     float kK, float km, const Wall& w, float out[NP]) {
   if constexpr (BC == LBM_PERIODIC) {
     // collide() on f_0 = f*_0(x - 1), f_1 = f*_1(y - 1), f_2 = f*_2(x + 1),
-    // f_3 = f*_3(y + 1) with the same operations in the same order:
-    // U = (f_0 + f_1) + (f_2 + f_3), then f*_q = (h +- X or Y) - f_q
-    float p01[NC], p23[NC], U[NC];
-    add_shifted(at + 0 * NC, below + 1 * NC, at + 2 * NC, above + 3 * NC, p01, p23);
-#pragma unroll
-    for (int c = 0; c < NC; ++c) U[c] = p01[c] + p23[c];
+    // f_3 = f*_3(y + 1) with the same operations in the same order
+    float U[NC];
+    moment_shifted(at + 0 * NC, below + 1 * NC, at + 2 * NC, above + 3 * NC, U);
     float X[NC], Y[NC];
     X[0] = fmaf(kK, U[2], km * U[3]);
     X[1] = km * U[4];
@@ -166,16 +184,12 @@ __device__ __forceinline__ void level_update(const float below[NP], const float 
     Y[2] = kK * U[1];
     Y[3] = -(km * U[1]);
     Y[4] = km * U[0];
-    float t0[NC], t2[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-      const float h = 0.5f * U[c];
-      t0[c] = h + X[c];
-      t2[c] = h - X[c];
-      out[1 * NC + c] = (h + Y[c]) - below[1 * NC + c];
-      out[3 * NC + c] = (h - Y[c]) - above[3 * NC + c];
+      out[1 * NC + c] = fmaf(0.5f, U[c], Y[c]) - below[1 * NC + c];
+      out[3 * NC + c] = fmaf(0.5f, U[c], -Y[c]) - above[3 * NC + c];
     }
-    sub_shifted(at + 0 * NC, t0, at + 2 * NC, t2, out + 0 * NC, out + 2 * NC);
+    collide_shifted(U, X, at + 0 * NC, at + 2 * NC, out + 0 * NC, out + 2 * NC);
     return;
   }
   float f[NQ][NC];
@@ -223,10 +237,32 @@ struct Strip {
   int xs4;  // byte offset of the column this lane stores, or TB_DROP
 };
 
+// Level-0 rows are read in sweep order y0 - T, y0 - T + 1, ... up to the last
+// row the segment needs and then that row again; the cursor holds the sweep
+// row and the row it reads (periodic wrap or wall clamp) and advances by one
+// compare and add instead of a wrap per row.  Row byte offsets fit in 32 bits
+// (tblock_fits).
+struct RowCursor {
+  int y;     // sweep row of the next load
+  int r;     // row it reads
+  int last;  // last level-0 row the segment needs
+};
+
 template <int BC>
-__device__ __forceinline__ void load_row(const float* __restrict__ src, const Grid& g, const TBConst& sc,
-                                const Strip& st, int y, float v[NP]) {
-  const float* rp = src + (int64_t)row_index<BC>(y, g.ny) * g.pitch;
+__device__ __forceinline__ void cursor_advance(RowCursor& c, int ny) {
+  if (c.y < c.last) {
+    ++c.y;
+    if (BC == LBM_PERIODIC) {
+      c.r = c.r + 1 == ny ? 0 : c.r + 1;
+    } else {
+      c.r = c.y < 0 ? 0 : (c.y >= ny ? ny - 1 : c.y);
+    }
+  }
+}
+
+__device__ __forceinline__ void load_row(const float* __restrict__ src, int pitch4,
+                                         const TBConst& sc, const Strip& st, int r, float v[NP]) {
+  const char* rp = (const char*)src + (uint32_t)(r * pitch4);
   const __amdgpu_buffer_rsrc_t rs =
       __builtin_amdgcn_make_buffer_rsrc((void*)rp, (short)0, sc.extent, TB_RSRC_WORD3);
 #pragma unroll
@@ -258,18 +294,17 @@ __device__ __forceinline__ void row_update(const float below[NP], const float at
 template <int BC, int NT, int PF, int T, bool PRE>
 __device__ __forceinline__ void sub_iteration(const float* __restrict__ src, float* __restrict__ dst,
                                      const Grid& g, const TBConst& sc, const Strip& st,
-                                     const WallSeq& ws, int y0, int y1, int i, int I, int slot,
-                                     float (&lv0)[3 + PF][NP], float (&lv)[T - 1][3 + PF][NP]) {
+                                     const WallSeq& ws, int pitch4, RowCursor& cur, int y0,
+                                     int y1, int i, int I, int slot, float (&lv0)[3 + PF][NP],
+                                     float (&lv)[T - 1][3 + PF][NP]) {
   constexpr int NB = 3 + PF;
   const int s = slot, s1 = (slot + NB - 1) % NB, s2 = (slot + NB - 2) % NB;
-  const int last_in = y1 - 1 + T;  // last level-0 row the segment needs
-  // prefetch level-0 row y0 + i + T + PF into slot (i + PF) mod NB, which held
-  // the row of sub-iteration i + PF - NB = i - 3 (no longer read).  Past the
-  // last needed row it re-reads that row (a cache hit).
-  {
-    const int yl = y0 + i + T + PF < last_in ? y0 + i + T + PF : last_in;
-    load_row<BC>(src, g, sc, st, yl, lv0[(slot + PF) % NB]);
-  }
+  // prefetch level-0 row y0 + i + T + PF (the cursor's row) into slot
+  // (i + PF) mod NB, which held the row of sub-iteration i + PF - NB = i - 3
+  // (no longer read).  Past the last needed row it re-reads that row (a
+  // cache hit).
+  load_row(src, pitch4, sc, st, cur.r, lv0[(slot + PF) % NB]);
+  cursor_advance<BC>(cur, g.ny);
   // keep the prefetch at the head of the sub-iteration: the scheduler would
   // sink it towards its first use and shorten the distance it hides
   __builtin_amdgcn_sched_barrier(0);
@@ -290,7 +325,7 @@ __device__ __forceinline__ void sub_iteration(const float* __restrict__ src, flo
     row_update<BC>(lv[T - 2][s2], lv[T - 2][s1], lv[T - 2][s], st.xw, rr, T, g, sc, ws, o);
     const int off = rr < y1 ? st.xs4 : TB_DROP;
     const int yo = rr < g.ny ? rr : g.ny - 1;
-    float* rp = dst + (int64_t)yo * g.pitch;
+    char* rp = (char*)dst + (uint32_t)(yo * pitch4);
     const __amdgpu_buffer_rsrc_t rs =
         __builtin_amdgcn_make_buffer_rsrc((void*)rp, (short)0, sc.extent, TB_RSRC_WORD3);
 #pragma unroll
@@ -306,7 +341,7 @@ template <int BC, int NT, int PF, int T>
 __device__ __forceinline__ void tblock_wave(const float* __restrict__ src, float* __restrict__ dst,
                                    const Grid& g, const TBConst& sc, const WallSeq& ws,
                                    int strip, int seg) {
-  static_assert(T >= 2 && T <= 7, "2 to 7 time levels per launch");
+  static_assert(T >= 2 && T <= 8, "2 to 8 time levels per launch");
   constexpr int NB = 3 + PF;
   constexpr int VALID = TB_LANES - 2 * T;  // stored columns per strip
   const int lane = threadIdx.x & 63;
@@ -320,6 +355,11 @@ __device__ __forceinline__ void tblock_wave(const float* __restrict__ src, float
   st.xs4 = store ? (int)((uint32_t)x * 4u) : TB_DROP;
   const int y0 = seg * sc.seg_rows;
   const int y1 = y0 + sc.seg_rows < ny ? y0 + sc.seg_rows : ny;
+  const int pitch4 = (int)(g.pitch * 4);
+  RowCursor cur;
+  cur.y = y0 - T;
+  cur.r = row_index<BC>(cur.y, ny);
+  cur.last = y1 - 1 + T;
 
   float lv0[NB][NP];        // level 0: row of sub-iteration i is y0 + i + T
   float lv[T - 1][NB][NP];  // level l: row of sub-iteration i is y0 + i + T - l
@@ -327,14 +367,15 @@ __device__ __forceinline__ void tblock_wave(const float* __restrict__ src, float
 #pragma unroll
   for (int k = 0; k < PF; ++k) {
     constexpr int first = -2 * T;
-    load_row<BC>(src, g, sc, st, y0 + first + k + T, lv0[((first + k) % NB + NB) % NB]);
+    load_row(src, pitch4, sc, st, cur.r, lv0[((first + k) % NB + NB) % NB]);
+    cursor_advance<BC>(cur, ny);
   }
   // pipeline fill: sub-iterations -2T .. -1
 #pragma unroll
   for (int p = 0; p < 2 * T; ++p) {
     const int I = p - 2 * T;
-    sub_iteration<BC, NT, PF, T, true>(src, dst, g, sc, st, ws, y0, y1, I, I, (I % NB + NB) % NB,
-                                       lv0, lv);
+    sub_iteration<BC, NT, PF, T, true>(src, dst, g, sc, st, ws, pitch4, cur, y0, y1, I, I,
+                                       (I % NB + NB) % NB, lv0, lv);
   }
   // The sweep runs in whole rings of NB rows; rows past the segment end are
   // computed from valid (wrapped or clamped) rows and their stores dropped.
@@ -343,7 +384,8 @@ __device__ __forceinline__ void tblock_wave(const float* __restrict__ src, float
   for (int i0 = 0; i0 < y1 - y0; i0 += NB) {
 #pragma unroll
     for (int j = 0; j < NB; ++j)
-      sub_iteration<BC, NT, PF, T, false>(src, dst, g, sc, st, ws, y0, y1, i0 + j, 0, j, lv0, lv);
+      sub_iteration<BC, NT, PF, T, false>(src, dst, g, sc, st, ws, pitch4, cur, y0, y1, i0 + j, 0,
+                                          j, lv0, lv);
   }
 }
 

@@ -106,8 +106,39 @@ def test_blocked_kernels_bitwise_equal_single_steps(bc, nx, ny, plane):
 
 
 @gpu
+@pytest.mark.parametrize("bc,nx,ny", [(synth.PERIODIC, 4096, 4096), (synth.PERIODIC, 4096, 2000),
+                                      (synth.DIRICHLET, 4096, 2000)])
+def test_whole_device_blocked_variants_bitwise_equal_single_steps(bc, nx, ny):
+    # variants sized to the resident wave slots, on the full-size grid and on
+    # one whose last segment is short
+    torch = _torch()
+    from paper_2408_01081_amd.lbm import Lattice
+    prob = synth.plane_wave_problem(nx, ny, bc, seed=19, kmax=3)
+    v0, sb0 = prob.initial_fields()
+    nsteps = 17
+    W, T = prob.wall_table(nsteps)
+    lat = Lattice(prob.nx, prob.ny, prob.dx, prob.dt, prob.lam, prob.mu, prob.rho, prob.bc)
+    ref = None
+    cfgs = [c["index"] for c in lat.tblock_configs() if c["seg_rows"] <= 0]
+    assert cfgs
+    for cfg2 in [-1] + cfgs:
+        lat.init(torch.from_numpy(v0), torch.from_numpy(sb0))
+        if bc == synth.DIRICHLET:
+            lat.set_wall_velocity(torch.from_numpy(W), torch.from_numpy(T))
+        lat.tblock_config = cfg2
+        lat.step(nsteps)
+        f = lat.populations()
+        if ref is None:
+            ref = f
+        else:
+            assert torch.equal(f.view(torch.int32), ref.view(torch.int32)), cfg2
+    del ref, f, lat
+    torch.cuda.empty_cache()
+
+
+@gpu
 def test_blocked_kernels_across_wall_table_chunks():
-    # lbm_step sums wall velocities in chunks of 420 steps: runs longer than a
+    # lbm_step sums wall velocities in chunks of up to 420 steps: runs longer than a
     # chunk, split at odd places, stay bitwise equal to single steps
     torch = _torch()
     from paper_2408_01081_amd.lbm import Lattice
