@@ -82,16 +82,17 @@ def main():
     # both lattices on the current stream, one after the other: each kernel's
     # launch duration is then its own (two streams overlapped the lattices'
     # launches by about 2% of the step time and blurred the per-kernel times)
-    lats = []
+    lats, fields = [], []
     for prob in (per, dir_):
         v0, sb0 = prob.initial_fields()
+        v0, sb0 = torch.from_numpy(v0).to(dev), torch.from_numpy(sb0).to(dev)
         lat = Lattice(prob.nx, prob.ny, prob.dx, prob.dt, prob.lam, prob.mu, prob.rho, prob.bc)
-        lat.init(torch.from_numpy(v0).to(dev), torch.from_numpy(sb0).to(dev))
+        lat.init(v0, sb0)
         if prob.bc == synth.DIRICHLET:
-            Wt, Tt = prob.wall_table(total)
+            Wt, Tt = prob.wall_table(max(total, RERANK_STEPS + 64))
             lat.set_wall_velocity(torch.from_numpy(Wt).to(dev), torch.from_numpy(Tt).to(dev))
         lats.append(lat)
-        del v0, sb0
+        fields.append((v0, sb0))
     torch.cuda.synchronize()
     log("setup %.1fs" % (time.time() - t0))
 
@@ -109,6 +110,7 @@ def main():
             lat.tblock_config = forced2[li] if forced2 else -1
         else:
             lat.autotune(reps=10, use_cache=True)
+            rerank(lat, fields[li])
         idx, idx2 = lat.step_config, lat.tblock_config
         c = cfgs[idx]
         t = {"lattice": "%dx%d" % (lat.nx, lat.ny), "config": idx, "vec": c["vec"],
@@ -117,6 +119,7 @@ def main():
         if idx2 >= 0:
             t["tblock"] = next(k for k in lat.tblock_configs() if k["index"] == idx2)
         tuned.append(t)
+    fields = None  # the initial fields were kept for the re-rank only
     log("autotuned: %s" % tuned)
     for lat in lats:
         lat.step(W)
@@ -271,6 +274,38 @@ def launch_key(t):
                                            b["prefetch"])
     return "vec=%d threads=%d nt=%d shuffle=%d" % (t["vec"], t["threads"], t["nontemporal"],
                                                    t["shuffle"])
+
+
+RERANK_STEPS = 840  # a multiple of every steps-per-launch
+
+
+def rerank(lat, fields, top=4):
+    """The autotuner times repeated launches from one buffer, which on grids
+    smaller than the device's last-level cache stays resident there; real
+    stepping alternates two buffers.  Time the autotuner's choice and the
+    blocked variants its launch timing ranks best by stepping RERANK_STEPS
+    steps each, keep the fastest, and re-initialise the lattice (state and
+    step count as before)."""
+    import torch
+    per_step = sorted((lat.time_tblock_config(c["index"], 5) / c["steps"], c["index"])
+                      for c in lat.tblock_configs())
+    cands = [lat.tblock_config] + [i for _, i in per_step[:top] if i != lat.tblock_config]
+    best = None
+    for idx in cands:
+        lat.init(*fields)
+        lat.tblock_config = idx
+        lat.step(64)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        lat.step(RERANK_STEPS)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        if best is None or ms < best[0]:
+            best = (ms, idx)
+    lat.init(*fields)
+    lat.tblock_config = best[1]
+    torch.cuda.synchronize()
 
 
 def measured_traffic(kname, launch):

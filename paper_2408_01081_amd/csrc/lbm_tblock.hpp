@@ -163,16 +163,38 @@ __device__ __forceinline__ void collide_shifted(const float U[NC], const float X
 }
 
 // one level-update of row y at this lane's column x from the rows below,
-// at and above (post-collision values of the previous level)
-template <int BC>
+// at and above (post-collision values of the previous level).  EDGE: the
+// wave's columns include a Dirichlet wall column (x = 0 or nx - 1), whose
+// lanes replace a shifted population by the wall rule; other waves of a
+// Dirichlet lattice meet walls only in rows 0 and ny - 1, a branch uniform
+// across the wave.
+template <int BC, bool EDGE>
 __device__ __forceinline__ void level_update(const float below[NP], const float at[NP],
                                     const float above[NP], int x, int y, int nx, int ny,
                                     float kK, float km, const Wall& w, float out[NP]) {
-  if constexpr (BC == LBM_PERIODIC) {
+  if constexpr (BC == LBM_PERIODIC || !EDGE) {
     // collide() on f_0 = f*_0(x - 1), f_1 = f*_1(y - 1), f_2 = f*_2(x + 1),
-    // f_3 = f*_3(y + 1) with the same operations in the same order
+    // f_3 = f*_3(y + 1) (or the wall rule in the rows next to a wall) with
+    // the same operations in the same order
+    float f1[NC], f3[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      f1[c] = below[1 * NC + c];
+      f3[c] = above[3 * NC + c];
+    }
+    if constexpr (BC == LBM_DIRICHLET) {
+      float va, vb;
+      if (y == 0) {
+        wall_velocity(w, 2 * ny + x, va, vb);
+        wall_rule(0, 1, kK, km, va, vb, at + 3 * NC, f1);
+      }
+      if (y == ny - 1) {
+        wall_velocity(w, 2 * ny + nx + x, va, vb);
+        wall_rule(0, -1, kK, km, va, vb, at + 1 * NC, f3);
+      }
+    }
     float U[NC];
-    moment_shifted(at + 0 * NC, below + 1 * NC, at + 2 * NC, above + 3 * NC, U);
+    moment_shifted(at + 0 * NC, f1, at + 2 * NC, f3, U);
     float X[NC], Y[NC];
     X[0] = fmaf(kK, U[2], km * U[3]);
     X[1] = km * U[4];
@@ -186,8 +208,8 @@ __device__ __forceinline__ void level_update(const float below[NP], const float 
     Y[4] = km * U[0];
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-      out[1 * NC + c] = fmaf(0.5f, U[c], Y[c]) - below[1 * NC + c];
-      out[3 * NC + c] = fmaf(0.5f, U[c], -Y[c]) - above[3 * NC + c];
+      out[1 * NC + c] = fmaf(0.5f, U[c], Y[c]) - f1[c];
+      out[3 * NC + c] = fmaf(0.5f, U[c], -Y[c]) - f3[c];
     }
     collide_shifted(U, X, at + 0 * NC, at + 2 * NC, out + 0 * NC, out + 2 * NC);
     return;
@@ -273,7 +295,7 @@ __device__ __forceinline__ void load_row(const float* __restrict__ src, int pitc
 // update of row y of level l from the rows below, at and above it; rows off
 // the grid (computed only to be dropped or replaced by a wall) use any valid
 // row for their wall lookups
-template <int BC>
+template <int BC, bool EDGE>
 __device__ __forceinline__ void row_update(const float below[NP], const float at[NP],
                                            const float above[NP], int xw, int y, int level,
                                            const Grid& g, const TBConst& sc, const WallSeq& ws,
@@ -285,13 +307,13 @@ __device__ __forceinline__ void row_update(const float below[NP], const float at
   w.W = nullptr;
   w.rank = 0;
   w.Trow = nullptr;
-  level_update<BC>(below, at, above, xw, yc, g.nx, g.ny, sc.kK, sc.km, w, out);
+  level_update<BC, EDGE>(below, at, above, xw, yc, g.nx, g.ny, sc.kK, sc.km, w, out);
 }
 
 // One sub-iteration i of the sweep (PRE: a pipeline-filling sub-iteration
 // before the first output row, I = i then; slot = i mod NB, known at compile
 // time in both cases).
-template <int BC, int NT, int PF, int T, bool PRE>
+template <int BC, int NT, int PF, int T, bool EDGE, bool PRE>
 __device__ __forceinline__ void sub_iteration(const float* __restrict__ src, float* __restrict__ dst,
                                      const Grid& g, const TBConst& sc, const Strip& st,
                                      const WallSeq& ws, int pitch4, RowCursor& cur, int y0,
@@ -311,18 +333,19 @@ __device__ __forceinline__ void sub_iteration(const float* __restrict__ src, flo
   // level 1 .. T-1: level l row y0 + i + T - l; during the pipeline fill only
   // the levels whose rows the segment needs (I >= -2 (T - l))
   if (!PRE || I >= -2 * (T - 1))
-    row_update<BC>(lv0[s2], lv0[s1], lv0[s], st.xw, y0 + i + T - 1, 1, g, sc, ws, lv[0][s]);
+    row_update<BC, EDGE>(lv0[s2], lv0[s1], lv0[s], st.xw, y0 + i + T - 1, 1, g, sc, ws,
+                         lv[0][s]);
 #pragma unroll
   for (int l = 2; l < T; ++l) {
     if (PRE && I < -2 * (T - l)) continue;
-    row_update<BC>(lv[l - 2][s2], lv[l - 2][s1], lv[l - 2][s], st.xw, y0 + i + T - l, l, g, sc,
-                   ws, lv[l - 1][s]);
+    row_update<BC, EDGE>(lv[l - 2][s2], lv[l - 2][s1], lv[l - 2][s], st.xw, y0 + i + T - l, l, g,
+                         sc, ws, lv[l - 1][s]);
   }
   if (!PRE) {
     // level T, output row y0 + i
     float o[NP];
     const int rr = y0 + i;
-    row_update<BC>(lv[T - 2][s2], lv[T - 2][s1], lv[T - 2][s], st.xw, rr, T, g, sc, ws, o);
+    row_update<BC, EDGE>(lv[T - 2][s2], lv[T - 2][s1], lv[T - 2][s], st.xw, rr, T, g, sc, ws, o);
     const int off = rr < y1 ? st.xs4 : TB_DROP;
     const int yo = rr < g.ny ? rr : g.ny - 1;
     char* rp = (char*)dst + (uint32_t)(yo * pitch4);
@@ -336,13 +359,49 @@ __device__ __forceinline__ void sub_iteration(const float* __restrict__ src, flo
   __builtin_amdgcn_sched_barrier(0);
 }
 
+// The sweep of one wave over output rows y0 .. y1 - 1 (EDGE: see level_update).
+template <int BC, int NT, int PF, int T, bool EDGE>
+__device__ __forceinline__ void tblock_sweep(const float* __restrict__ src,
+                                             float* __restrict__ dst, const Grid& g,
+                                             const TBConst& sc, const Strip& st,
+                                             const WallSeq& ws, int pitch4, RowCursor& cur,
+                                             int y0, int y1) {
+  constexpr int NB = 3 + PF;
+  const int ny = g.ny;
+  float lv0[NB][NP];        // level 0: row of sub-iteration i is y0 + i + T
+  float lv[T - 1][NB][NP];  // level l: row of sub-iteration i is y0 + i + T - l
+  // level-0 rows of the first PF sub-iterations of the pipeline fill
+#pragma unroll
+  for (int k = 0; k < PF; ++k) {
+    constexpr int first = -2 * T;
+    load_row(src, pitch4, sc, st, cur.r, lv0[((first + k) % NB + NB) % NB]);
+    cursor_advance<BC>(cur, ny);
+  }
+  // pipeline fill: sub-iterations -2T .. -1
+#pragma unroll
+  for (int p = 0; p < 2 * T; ++p) {
+    const int I = p - 2 * T;
+    sub_iteration<BC, NT, PF, T, EDGE, true>(src, dst, g, sc, st, ws, pitch4, cur, y0, y1, I, I,
+                                             (I % NB + NB) % NB, lv0, lv);
+  }
+  // The sweep runs in whole rings of NB rows; rows past the segment end are
+  // computed from valid (wrapped or clamped) rows and their stores dropped.
+  // No early exit inside a ring: a conditional exit would let the compiler
+  // sink each prefetch past it, next to its first use.
+  for (int i0 = 0; i0 < y1 - y0; i0 += NB) {
+#pragma unroll
+    for (int j = 0; j < NB; ++j)
+      sub_iteration<BC, NT, PF, T, EDGE, false>(src, dst, g, sc, st, ws, pitch4, cur, y0, y1,
+                                                i0 + j, 0, j, lv0, lv);
+  }
+}
+
 // One wave's work: strip `strip`, output rows of segment `seg`.
 template <int BC, int NT, int PF, int T>
 __device__ __forceinline__ void tblock_wave(const float* __restrict__ src, float* __restrict__ dst,
                                    const Grid& g, const TBConst& sc, const WallSeq& ws,
                                    int strip, int seg) {
   static_assert(T >= 2 && T <= 8, "2 to 8 time levels per launch");
-  constexpr int NB = 3 + PF;
   constexpr int VALID = TB_LANES - 2 * T;  // stored columns per strip
   const int lane = threadIdx.x & 63;
   const int nx = g.nx, ny = g.ny;
@@ -360,33 +419,15 @@ __device__ __forceinline__ void tblock_wave(const float* __restrict__ src, float
   cur.y = y0 - T;
   cur.r = row_index<BC>(cur.y, ny);
   cur.last = y1 - 1 + T;
-
-  float lv0[NB][NP];        // level 0: row of sub-iteration i is y0 + i + T
-  float lv[T - 1][NB][NP];  // level l: row of sub-iteration i is y0 + i + T - l
-  // level-0 rows of the first PF sub-iterations of the pipeline fill
-#pragma unroll
-  for (int k = 0; k < PF; ++k) {
-    constexpr int first = -2 * T;
-    load_row(src, pitch4, sc, st, cur.r, lv0[((first + k) % NB + NB) % NB]);
-    cursor_advance<BC>(cur, ny);
+  if constexpr (BC == LBM_DIRICHLET) {
+    // a Dirichlet wave meets the side walls only if its columns include one
+    const int x_first = strip * VALID - T;
+    if (x_first <= 0 || x_first + TB_LANES - 1 >= nx - 1) {
+      tblock_sweep<BC, NT, PF, T, true>(src, dst, g, sc, st, ws, pitch4, cur, y0, y1);
+      return;
+    }
   }
-  // pipeline fill: sub-iterations -2T .. -1
-#pragma unroll
-  for (int p = 0; p < 2 * T; ++p) {
-    const int I = p - 2 * T;
-    sub_iteration<BC, NT, PF, T, true>(src, dst, g, sc, st, ws, pitch4, cur, y0, y1, I, I,
-                                       (I % NB + NB) % NB, lv0, lv);
-  }
-  // The sweep runs in whole rings of NB rows; rows past the segment end are
-  // computed from valid (wrapped or clamped) rows and their stores dropped.
-  // No early exit inside a ring: a conditional exit would let the compiler
-  // sink each prefetch past it, next to its first use.
-  for (int i0 = 0; i0 < y1 - y0; i0 += NB) {
-#pragma unroll
-    for (int j = 0; j < NB; ++j)
-      sub_iteration<BC, NT, PF, T, false>(src, dst, g, sc, st, ws, pitch4, cur, y0, y1, i0 + j, 0,
-                                          j, lv0, lv);
-  }
+  tblock_sweep<BC, NT, PF, T, false>(src, dst, g, sc, st, ws, pitch4, cur, y0, y1);
 }
 
 template <int BC, int NT, int PF, int T>
