@@ -669,7 +669,8 @@ void conv_back(sg_net* n, int l, const Tensor& gy, const Tensor& xin, const floa
                      n->grad + P.aoff[l]);
   // weights: dW = sum (gamma * gy) (x) (xscale * x)
   const int64_t pixels = (int64_t)n->B * HW;
-  if (n->conv_mode != 1 && zl.W % 64 == 0 && L.cin % 32 == 0 && L.cout % 32 == 0) {
+  const bool rows_fit = zl.W % 64 == 0 || (64 % zl.W == 0 && zl.H % (64 / zl.W) == 0);
+  if (n->conv_mode != 1 && rows_fit && L.cin % 32 == 0 && L.cout % 32 == 0) {
     // LDS-staged kernel: ~256 workgroups (one per CU: 92 KB of LDS), as many
     // pixel-block groups as the partials' buffer holds
     const int64_t nblocks = pixels / 64;

@@ -444,12 +444,14 @@ __global__ __launch_bounds__(256) void k_wgrad(const float* __restrict__ G,
 // The weight gradient with both operands staged in LDS, channel-major (the
 // matrix core's reduction runs over pixels, which must be contiguous per
 // channel): a workgroup owns a 32 x 32 (output, input channel) tile of all 9
-// taps and sweeps blocks of 64 pixels of one image row (W % 64 == 0), blocks
-// blockIdx.x, blockIdx.x + gridDim.x, ...  Per block it stages
-//   gT[h][o][p]      gamma-scaled gradient, split into hi/lo, 72 bf16 per row;
-//   xT[h][d][i][r][c] the gain-scaled input of rows y-1..y+1 at columns
-//                    x0 - 1 + d + c (three copies d = 0, 1, 2 so that every
-//                    tap reads 8 pixels at an aligned offset), 72 per row;
+// taps and sweeps blocks of 64 pixels, blocks blockIdx.x, blockIdx.x +
+// gridDim.x, ...  A block is 64 pixels of one image row (W % 64 == 0) or
+// RB = 64 / W whole rows (W = 16, 32; H % RB == 0), pixel p at row
+// y + p / PW, column x0 + p % PW (PW = min(W, 64)).  Per block it stages
+//   gT[h][o][p]       gamma-scaled gradient, split into hi/lo, 72 bf16 per row;
+//   xT[h][d][i][r][p] the gain-scaled input at tap (r - 1, d - 1) of pixel p
+//                     (three copies d = 0, 1, 2 so that every tap reads 8
+//                     pixels at an aligned offset), 72 per row;
 // (row strides of 36 and 108 dwords keep the 16 lanes of a fragment read on
 // distinct banks).  Wave w computes the 16 x 16 sub-tile (w / 2, w mod 2) for
 // all taps and writes partial[blockIdx.x][t][o][i] for k_wgrad_reduce.
@@ -473,22 +475,25 @@ __global__ __launch_bounds__(256) void k_wgradt(const float* __restrict__ G,
   const int nit = Cin / 32;
   const int o0 = (int)(blockIdx.y / (unsigned)nit) * 32, i0 = (int)(blockIdx.y % (unsigned)nit) * 32;
   const int ow = 16 * (wave >> 1), iw = 16 * (wave & 1);
-  const int tx = W / 64;
-  const int64_t nblocks = (int64_t)B * H * tx;
+  const int PW = W < 64 ? W : 64;   // pixels of a block per image row
+  const int RB = 64 / PW;           // image rows per block
+  const int tx = W / PW;            // blocks across a row
+  const int HB = H / RB;            // block rows per image
+  const int64_t nblocks = (int64_t)B * HB * tx;
 
   f32x4 acc[9];
 #pragma unroll
   for (int t = 0; t < 9; ++t) acc[t] = (f32x4){0.f, 0.f, 0.f, 0.f};
 
   for (int64_t blk = blockIdx.x; blk < nblocks; blk += gridDim.x) {
-    const int b = (int)(blk / ((int64_t)H * tx));
-    const int rem = (int)(blk - (int64_t)b * H * tx);
-    const int y = rem / tx, x0 = (rem - (rem / tx) * tx) * 64;
+    const int b = (int)(blk / ((int64_t)HB * tx));
+    const int rem = (int)(blk - (int64_t)b * HB * tx);
+    const int y = (rem / tx) * RB, x0 = (rem - (rem / tx) * tx) * 64;
     __syncthreads();  // the previous block's fragments have been read
     {
       // gradient: thread t -> pixel t / 4, output channels 8 (t mod 4) ...
       const int p = threadIdx.x >> 2, q = threadIdx.x & 3;
-      const int64_t go = (((int64_t)b * H + y) * W + x0 + p) * Cout + o0 + 8 * q;
+      const int64_t go = (((int64_t)b * H + y + p / PW) * W + x0 + p % PW) * Cout + o0 + 8 * q;
       const float4 u0 = *reinterpret_cast<const float4*>(G + go);
       const float4 u1 = *reinterpret_cast<const float4*>(G + go + 4);
       float a[8] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w};
@@ -504,10 +509,13 @@ __global__ __launch_bounds__(256) void k_wgradt(const float* __restrict__ G,
         if (SPLIT == 3) gT[GT + (8 * q + j) * RS + p] = bf16_bits(a[j] - bf16_value(h));
       }
     }
-    // input: rows y-1..y+1, halo columns 0..65 (image x0 - 1 + hc), 4 x 8 channels
-    for (int it = threadIdx.x; it < 3 * 66 * 4; it += 256) {
-      const int q = it & 3, hc = (it >> 2) % 66, r = (it >> 2) / 66;
-      int ys = y + r - 1, xs = x0 + hc - 1;
+    // input: halo rows hr = 0 .. RB + 1 (image y - 1 + hr), halo columns
+    // hc = 0 .. PW + 1 (image x0 - 1 + hc), 4 x 8 channels; each element is
+    // tap (r - 1, d - 1) of the pixels at row hr - r, column hc - d
+    const int HC = PW + 2;
+    for (int it = threadIdx.x; it < (RB + 2) * HC * 4; it += 256) {
+      const int q = it & 3, hc = (it >> 2) % HC, hr = (it >> 2) / HC;
+      int ys = y + hr - 1, xs = x0 + hc - 1;
       bool valid = true;
       if (circular) {
         ys = ys < 0 ? ys + H : (ys >= H ? ys - H : ys);
@@ -535,14 +543,20 @@ __global__ __launch_bounds__(256) void k_wgradt(const float* __restrict__ G,
         lb[j] = bf16_bits(a[j] - bf16_value(hb[j]));
       }
 #pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        const int c = hc - d;
-        if (c < 0 || c >= 64) continue;
+      for (int r = 0; r < 3; ++r) {
+        const int pr = hr - r;
+        if (pr < 0 || pr >= RB) continue;
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          const int e = ((d * 32 + 8 * q + j) * 3 + r) * RS + c;
-          xT[e] = hb[j];
-          if (SPLIT == 3) xT[XT + e] = lb[j];
+        for (int d = 0; d < 3; ++d) {
+          const int c = hc - d;
+          if (c < 0 || c >= PW) continue;
+          const int pp = pr * PW + c;
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            const int e = ((d * 32 + 8 * q + j) * 3 + r) * RS + pp;
+            xT[e] = hb[j];
+            if (SPLIT == 3) xT[XT + e] = lb[j];
+          }
         }
       }
     }

@@ -150,3 +150,29 @@ def test_tiled_and_direct_convolutions_agree(split, circular, B, H, W):
     err = _rel(outs[0] - inp[:, :5], outs[1] - inp[:, :5])
     print("tiled vs direct, split %d: rel diff of the correction %.2e" % (split, err))
     assert err < (1e-5 if split == 3 else 3e-2)
+
+
+@gpu
+@pytest.mark.parametrize("circular", [True, False])
+def test_tiled_and_direct_weight_gradients_agree(circular):
+    # the LDS-staged weight gradient (blocks of 64 pixels: one row segment at
+    # the 128- and 64-wide levels, 2 and 4 whole rows at the 32- and 16-wide
+    # ones) and the direct kernel sum the same products in another order
+    torch = _torch()
+    from paper_2408_01081_amd import surrogate as S
+    B, H, W = 8, 128, 128
+    inp, tgt = _inputs(7, B, H, W)
+    P = _params(8)
+    x = torch.from_numpy(inp.astype(np.float32)).cuda()
+    t = torch.from_numpy(tgt.astype(np.float32)).cuda()
+    grads = []
+    for mode in (0, 1):
+        net = S.Surrogate(B, H, W, split=3, train=True)
+        net.set_params(S.pack_params(P))
+        net.set_conv_mode(mode)
+        net.train_step(x, t, circular=circular, lr=0.0)
+        grads.append(S.unpack_params(net.get_grads().double().cpu().numpy()))
+        del net
+    worst = max(_rel(grads[0][k], grads[1][k]) for k in grads[0])
+    print("tiled vs direct weight gradients: worst block rel diff %.2e" % worst)
+    assert worst < 1e-4
