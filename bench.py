@@ -218,12 +218,18 @@ def main():
     torch.cuda.empty_cache()
 
     # ---- the step with a body load and the displacement output ----------------
-    with_load = None
+    with_load = with_load_blocked = None
     if not args.no_load_leg:
         try:
             with_load = load_leg()
         except Exception as ex:  # reported, never hidden
             with_load = {"error": repr(ex)}
+        if tuned[0]["tblock_config"] >= 0:
+            try:
+                with_load_blocked = load_leg(nsteps=400, disp=False,
+                                             tblock=tuned[0]["tblock_config"])
+            except Exception as ex:  # reported, never hidden
+                with_load_blocked = {"error": repr(ex)}
 
     # ---- batched instances: one hipGraph launch of many steps ------------------
     batched = None
@@ -259,6 +265,7 @@ def main():
         "cpu_baseline": cpu,
         "parity": parity,
         "with_load_and_displacement": with_load,
+        "with_load": with_load_blocked,
         "batched": batched,
         "surrogate": surrogate,
         "wall_s": round(wall, 3),
@@ -385,10 +392,12 @@ def batched_leg(n, nsteps):
             "max_rel_energy_drift": drift}
 
 
-def load_leg(nsteps=200):
+def load_leg(nsteps=200, disp=True, tblock=None):
     """The 4096^2 periodic lattice stepped with a body load (the standing
-    manufactured solution's, separable, rank 16) and the FP64 displacement
-    state: the optional outputs' cost, reported beside the plain step."""
+    manufactured solution's, separable, rank 16), with the FP64 displacement
+    state (one launch per step) or without it (blocked variant `tblock`, T
+    steps per launch): the optional outputs' cost, reported beside the plain
+    step."""
     import numpy as np
     import torch
 
@@ -402,13 +411,17 @@ def load_leg(nsteps=200):
                          synth.PERIODIC, sol=e)
     dev = torch.device("cuda:0")
     lat = Lattice(N, N, prob.dx, prob.dt, prob.lam, prob.mu, prob.rho, synth.PERIODIC,
-                  displacement=True)
+                  displacement=disp)
+    if tblock is not None:
+        lat.tblock_config = tblock
     BX, BY, BT = prob.body_table(2 * nsteps + 10)
     lat.set_body_force(*(torch.from_numpy(a).to(dev) for a in (BX, BY, BT)))
     v0, sb0 = prob.initial_fields()
     lat.init(torch.from_numpy(v0).to(dev), torch.from_numpy(sb0).to(dev))
-    X, Y = synth.node_coords(N, N, dx)
-    lat.init_displacement(torch.from_numpy(np.stack([e.ux(X, Y, 0.0), e.uy(X, Y, 0.0)])).to(dev))
+    if disp:
+        X, Y = synth.node_coords(N, N, dx)
+        lat.init_displacement(torch.from_numpy(np.stack([e.ux(X, Y, 0.0),
+                                                         e.uy(X, Y, 0.0)])).to(dev))
     lat.step(10)
     stream = torch.cuda.current_stream(dev)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -417,14 +430,24 @@ def load_leg(nsteps=200):
     e1.record(stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / nsteps
-    alg = (BYTES_PER_LUP + 32) * N * N
-    out = {"workload": "periodic 4096x4096, body load of rank %d (standing manufactured "
-                       "solution) + FP64 displacement state, one launch per step" % BX.shape[0],
-           "kernel": "k_step_ext", "steps": nsteps, "ms_per_step": round(ms, 5),
-           "GLUPS": round(N * N / ms / 1e6, 2),
-           "algorithmic_bytes_per_node": BYTES_PER_LUP + 32,
-           "algorithmic_GB/s": round(alg / (ms * 1e-3) / 1e9, 1),
-           "frac": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    if disp:
+        alg = (BYTES_PER_LUP + 32) * N * N
+        out = {"workload": "periodic 4096x4096, body load of rank %d (standing manufactured "
+                           "solution) + FP64 displacement state, one launch per step"
+                           % BX.shape[0],
+               "kernel": "k_step_ext", "steps": nsteps, "ms_per_step": round(ms, 5),
+               "GLUPS": round(N * N / ms / 1e6, 2),
+               "algorithmic_bytes_per_node": BYTES_PER_LUP + 32,
+               "algorithmic_GB/s": round(alg / (ms * 1e-3) / 1e9, 1),
+               "frac": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    else:
+        T = next(k for k in lat.tblock_configs() if k["index"] == lat.tblock_config)["steps"]
+        out = {"workload": "periodic 4096x4096, body load of rank %d (standing manufactured "
+                           "solution), %d steps per launch" % (BX.shape[0], T),
+               "kernel": "k_tblock with load (variant %d)" % lat.tblock_config,
+               "steps": nsteps, "ms_per_step": round(ms, 5),
+               "GLUPS": round(N * N / ms / 1e6, 2),
+               "algorithmic_bytes_per_node_update": round(BYTES_PER_LUP / T, 2)}
     del lat
     torch.cuda.empty_cache()
     return out

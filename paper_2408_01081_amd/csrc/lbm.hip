@@ -398,6 +398,7 @@ struct lbm_ctx {
   int step_cfg;   // index into kStepConfigs
   int tb_cfg;         // index into kTBConfigs, or -1 (single steps only)
   int tb_slots[64];   // resident waves of a blocked variant on this device (0: not known)
+  int tbf_slots[8];   // the same for the variants with a body load
   float* wall_v;        // [WALL_CHUNK][2 (nx + ny)][2] wall velocities of upcoming steps
   // separable body load (rank 0: none); row n of force_T belongs to t_n
   const float* force_X;
@@ -405,6 +406,7 @@ struct lbm_ctx {
   const float* force_T;
   int force_rank;
   int64_t force_nsteps;
+  float* force_rows;  // [8][ny][TB_MAXR] row factors of a blocked launch with a load
   double* disp;  // [2][ny][nx] FP64 displacement state D, or null (LBM_F_DISPLACEMENT)
   bool disp_ready;
   // exact solution for the error norms (rank 0: none)
@@ -438,9 +440,14 @@ size_t disp_bytes(const Grid& g, uint32_t flags) {
 
 constexpr size_t ERR_BYTES = (size_t)(RED_BLOCKS * ERR_VALS + 16) * 8;
 
+size_t force_rows_bytes(const Grid& g) {
+  return (size_t)round_up((int64_t)8 * g.ny * TB_MAXR * 4, 256);
+}
+
 size_t ws_bytes(const Grid& g, int bc, uint32_t flags) {
   return 2 * state_bytes(g) + (size_t)round_up((2 * RED_BLOCKS + 2) * 8, 256) +
-         wall_table_bytes(g, bc) + disp_bytes(g, flags) + ERR_BYTES;
+         wall_table_bytes(g, bc) + disp_bytes(g, flags) + round_up(ERR_BYTES, 256) +
+         force_rows_bytes(g);
 }
 
 RefTable ref_at(const lbm_ctx* c, int64_t n) {
@@ -573,6 +580,7 @@ lbm_status lbm_create(const lbm_params* p, void* d_ws, size_t ws_size, void* hip
                           (size_t)round_up((2 * RED_BLOCKS + 2) * 8, 256) +
                           wall_table_bytes(g, p->bc) + disp_bytes(g, p->flags));
   c->err_acc = c->err_part + (size_t)RED_BLOCKS * ERR_VALS;
+  c->force_rows = (float*)((char*)c->err_part + round_up(ERR_BYTES, 256));
   c->err_on = false;
   c->ref_X = c->ref_Y = c->ref_T = nullptr;
   c->ref_rank = 0;
@@ -743,7 +751,7 @@ int64_t lbm_step_count(const lbm_ctx* c) { return c ? c->nstep : -1; }
 
 namespace {
 
-typedef void (*TBFn)(const float*, float*, Grid, TBConst, WallSeq);
+typedef void (*TBFn)(const float*, float*, Grid, TBConst, WallSeq, TBForce);
 // Temporally blocked variants: T steps per launch, output rows per segment
 // (0: as many as fill the device with one wave per resident slot, rounded up
 // to the ring length), nontemporal stores, rows prefetched ahead.
@@ -753,6 +761,12 @@ struct TBConfig {
 };
 #define LBM_TB(T, S, N, F) \
   {T, S, N, F, {&k_tblock<LBM_PERIODIC, N, F, T>, &k_tblock<LBM_DIRICHLET, N, F, T>}}
+// variants with a body load: the best variants of the load-free table's grids
+// (the Dirichlet kernel holding both wall paths and the load does not fit in
+// registers at T = 8)
+#define LBM_TBF(T, S, N, F) \
+  {T, S, N, F, {&k_tblock<LBM_PERIODIC, N, F, T, true>, &k_tblock<LBM_DIRICHLET, N, F, T, true>}}
+#define LBM_TBF_P(T, S, N, F) {T, S, N, F, {&k_tblock<LBM_PERIODIC, N, F, T, true>, nullptr}}
 const TBConfig kTBConfigs[] = {
     LBM_TB(2, 4, 0, 1),  LBM_TB(2, 4, 1, 1),  LBM_TB(2, 8, 0, 1),  LBM_TB(2, 0, 0, 1),
     LBM_TB(3, 4, 0, 1),  LBM_TB(3, 5, 0, 2),  LBM_TB(3, 4, 1, 1),  LBM_TB(3, 8, 1, 1),
@@ -765,9 +779,15 @@ const TBConfig kTBConfigs[] = {
     LBM_TB(6, 8, 0, 1),  LBM_TB(6, 12, 0, 1), LBM_TB(6, 20, 0, 2), LBM_TB(6, 30, 0, 2),
     LBM_TB(8, 20, 0, 2), LBM_TB(8, 30, 0, 2), LBM_TB(8, 24, 0, 1), LBM_TB(8, 32, 0, 1),
     LBM_TB(8, 0, 0, 2),  LBM_TB(8, -2, 0, 2), LBM_TB(8, 0, 0, 1),  LBM_TB(7, 0, 0, 2)};
+const TBConfig kTBForceConfigs[] = {LBM_TBF_P(8, 0, 0, 2), LBM_TBF_P(8, 30, 0, 2),
+                                     LBM_TBF(6, 16, 1, 1), LBM_TBF(4, 4, 1, 1)};
 #undef LBM_TB
+#undef LBM_TBF
+#undef LBM_TBF_P
+constexpr int kNumTBForceConfigs = (int)(sizeof(kTBForceConfigs) / sizeof(kTBForceConfigs[0]));
 constexpr int kNumTBConfigs = (int)(sizeof(kTBConfigs) / sizeof(kTBConfigs[0]));
 static_assert(kNumTBConfigs <= 64, "tb_slots size");
+static_assert(kNumTBForceConfigs <= 8, "tbf_slots size");
 
 
 // Sum the wall velocities of steps step0 .. step0 + n - 1 (n <= WALL_CHUNK)
@@ -816,14 +836,12 @@ WallSeq walls_from(const lbm_ctx* c, int s, bool with_walls) {
   return ws;
 }
 
-// Rows per segment of variant `index`: its seg_rows, or for seg_rows <= 0 as
+// Rows per segment of blocked variant k: its seg_rows, or for seg_rows <= 0 as
 // many as give one wave per resident slot (times -seg_rows) across the grid,
-// rounded up to the ring length.
-int tb_seg_rows(lbm_ctx* c, int index) {
-  const TBConfig& k = kTBConfigs[index];
+// rounded up to the ring length (*slots caches the device's resident waves).
+int seg_rows_of(lbm_ctx* c, const TBConfig& k, int* slots) {
   if (k.seg_rows > 0) return k.seg_rows;
-  int& slots = c->tb_slots[index];
-  if (slots == 0) {
+  if (*slots == 0) {
     int per_cu = 0, cus = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k.fn[c->p.bc], 256,
                                                      0) != hipSuccess ||
@@ -834,17 +852,21 @@ int tb_seg_rows(lbm_ctx* c, int index) {
       per_cu = 2;
       cus = 256;
     }
-    slots = per_cu * 4 * cus;
+    *slots = per_cu * 4 * cus;
   }
   const int ring = 3 + k.pf;
   const int valid = TB_LANES - 2 * k.steps;
   const int nstrips = (c->g.nx + valid - 1) / valid;
   const int rounds = k.seg_rows < 0 ? -k.seg_rows : 1;
-  int nseg = slots * rounds / nstrips;
+  int nseg = *slots * rounds / nstrips;
   if (nseg < 1) nseg = 1;
   int rows = (c->g.ny + nseg - 1) / nseg;
   rows = (rows + ring - 1) / ring * ring;
   return rows;
+}
+
+int tb_seg_rows(lbm_ctx* c, int index) {
+  return seg_rows_of(c, kTBConfigs[index], &c->tb_slots[index]);
 }
 
 // one launch of variant `index`: kTBConfigs[index].steps steps, level l with
@@ -854,7 +876,37 @@ void launch_tb(lbm_ctx* c, int index, const float* src, float* dst, const WallSe
   const TBConst sc = tblock_const(c->g, (float)c->kK, (float)c->km, tb_seg_rows(c, index), k.steps);
   const int ntiles = sc.nstrips * sc.nseg;
   hipLaunchKernelGGL(k.fn[c->p.bc], dim3((unsigned)((ntiles + 3) / 4)), dim3(256), 0, c->stream,
-                     src, dst, c->g, sc, ws);
+                     src, dst, c->g, sc, ws, TBForce{nullptr, nullptr, 0, 0.f});
+}
+
+// rows[l][y][r] = Y[r][y] T_{n1 + l}[r] for r < R, -0 beyond (the factors of
+// body_hat, one per level of a blocked launch whose first level is n1)
+__global__ void k_force_rows(const float* __restrict__ Y, const float* __restrict__ T1, int R,
+                             int ny, int T, float* __restrict__ rows) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)T * ny * TB_MAXR) return;
+  const int r = (int)(i % TB_MAXR);
+  const int64_t ly = i / TB_MAXR;
+  const int y = (int)(ly % ny), l = (int)(ly / ny);
+  rows[i] = r < R ? Y[(int64_t)r * ny + y] * T1[(int64_t)l * R + r] : -0.f;
+}
+
+// the load variant for a lattice whose blocked variant is tb_cfg: the same
+// launch shape if there is one, else the same T, else the first for its
+// boundary type; -1 if none applies
+int force_variant(const lbm_ctx* c) {
+  if (c->tb_cfg < 0 || c->force_rank > TB_MAXR || !tblock_fits(c->g)) return -1;
+  const TBConfig& t = kTBConfigs[c->tb_cfg];
+  int same_t = -1, first = -1;
+  for (int i = 0; i < kNumTBForceConfigs; ++i) {
+    const TBConfig& k = kTBForceConfigs[i];
+    if (!k.fn[c->p.bc]) continue;
+    if (c->g.ny < k.steps + 3 + k.pf) continue;  // the kernel wraps a load row once
+    if (k.steps == t.steps && k.seg_rows == t.seg_rows && k.nt == t.nt && k.pf == t.pf) return i;
+    if (k.steps == t.steps && same_t < 0) same_t = i;
+    if (first < 0) first = i;
+  }
+  return same_t >= 0 ? same_t : first;
 }
 
 }  // namespace
@@ -898,6 +950,38 @@ static lbm_status step_ext(lbm_ctx* c, int64_t nsteps) {
   return launch_check("k_step_ext launch");
 }
 
+// Steps with a body load (no displacement state, no error norms), T per
+// launch with load variant fi: before each launch the row factors of its T
+// levels are formed; the last nsteps mod T steps run one per launch.
+static lbm_status step_force_blocked(lbm_ctx* c, int64_t nsteps, int fi) {
+  const TBConfig& k = kTBForceConfigs[fi];
+  const int T = k.steps, R = c->force_rank;
+  const int chunk = WALL_CHUNK / T * T;
+  const TBConst sc =
+      tblock_const(c->g, (float)c->kK, (float)c->km, seg_rows_of(c, k, &c->tbf_slots[fi]), T);
+  const int ntiles = sc.nstrips * sc.nseg;
+  const TBForce F{c->force_X, c->force_rows, R, (float)(c->p.dt / c->p.rho)};
+  const int64_t nrows = (int64_t)T * c->g.ny * TB_MAXR;
+  const int64_t nb = nsteps / T * T;
+  for (int64_t done = 0; done < nb;) {
+    const int m = (int)(nb - done < chunk ? nb - done : chunk);
+    eval_walls(c, c->nstep, m);
+    for (int j = 0; j < m; j += T) {
+      hipLaunchKernelGGL(k_force_rows, dim3((unsigned)((nrows + 255) / 256)), dim3(256), 0,
+                         c->stream, c->force_Y, c->force_T + (c->nstep + 1) * R, R, c->g.ny, T,
+                         c->force_rows);
+      hipLaunchKernelGGL(k.fn[c->p.bc], dim3((unsigned)((ntiles + 3) / 4)), dim3(256), 0,
+                         c->stream, (const float*)c->buf[c->cur], c->buf[c->cur ^ 1], c->g, sc,
+                         walls_from(c, j, true), F);
+      c->cur ^= 1;
+      c->nstep += T;
+    }
+    done += m;
+  }
+  if (nsteps > nb) return step_ext(c, nsteps - nb);
+  return launch_check("k_tblock launch (body load)");
+}
+
 lbm_status lbm_step(lbm_ctx* c, int64_t nsteps) {
   if (!c) return fail(LBM_E_ARG, "null ctx");
   if (!c->initialised) return fail(LBM_E_STATE, "lbm_step before lbm_init");
@@ -910,6 +994,10 @@ lbm_status lbm_step(lbm_ctx* c, int64_t nsteps) {
     return fail(LBM_E_STATE, "LBM_F_DISPLACEMENT: lbm_init_displacement before lbm_step");
   if (c->err_on && c->nstep + nsteps > c->ref_nsteps)
     return fail(LBM_E_ARG, "reference table too short for the requested steps");
+  if (c->force_rank > 0 && !c->disp && !c->err_on) {
+    const int fi = force_variant(c);
+    if (fi >= 0) return step_force_blocked(c, nsteps, fi);
+  }
   if (c->force_rank > 0 || c->disp || c->err_on) return step_ext(c, nsteps);
   const Grid& g = c->g;
   const StepConfig& cfg = kStepConfigs[c->step_cfg];

@@ -58,6 +58,38 @@ struct WallSeq {
   int L;  // 2 (nx + ny)
 };
 
+// Body load of a blocked launch (Eq. cond_eq: U_num = sum f + B_hat / 2),
+// the separable sum of the single-step kernel's body_hat: each lane keeps its
+// column's coefficients X[r][c][x] (ranks >= rank padded with +0) and the
+// launch's row factors rows[l][y][r] = Y[r][y] T_{n+l+1}[r] (padded with -0)
+// are read through the scalar cache.  A padded term adds +0 * -0 = -0, which
+// leaves every sum unchanged in round-to-nearest, so the result is bitwise
+// the single-step kernel's.
+constexpr int TB_MAXR = 16;  // largest rank the blocked kernel takes
+struct TBForce {
+  const float* X;     // [rank][2][nx]
+  const float* rows;  // [T][ny][TB_MAXR], written before the launch
+  int rank;
+  float scale;        // dt / rho
+};
+struct LaneLoad {
+  float x[2][TB_MAXR];
+};
+typedef const __attribute__((address_space(4))) float* ConstRow;
+
+// B_hat (c = 0, 1) of this lane's node from the row factors yt
+__device__ __forceinline__ void load_terms(const LaneLoad& ll, const float (&yt)[TB_MAXR],
+                                           float scale, float& bx, float& by) {
+  float a = 0.f, b = 0.f;
+#pragma unroll
+  for (int r = 0; r < TB_MAXR; ++r) {
+    a = fmaf(ll.x[0][r], yt[r], a);
+    b = fmaf(ll.x[1][r], yt[r], b);
+  }
+  bx = scale * a;
+  by = scale * b;
+}
+
 constexpr int TB_RSRC_WORD3 = 0x00020000;  // raw 32-bit buffer access (gfx9 family)
 constexpr int TB_DROP = (int)0x80000000u;  // lane offset beyond every row's range
 
@@ -168,10 +200,14 @@ __device__ __forceinline__ void collide_shifted(const float U[NC], const float X
 // lanes replace a shifted population by the wall rule; other waves of a
 // Dirichlet lattice meet walls only in rows 0 and ny - 1, a branch uniform
 // across the wave.
-template <int BC, bool EDGE>
+template <int BC, bool EDGE, bool FORCE>
 __device__ __forceinline__ void level_update(const float below[NP], const float at[NP],
                                     const float above[NP], int x, int y, int nx, int ny,
-                                    float kK, float km, const Wall& w, float out[NP]) {
+                                    float kK, float km, const Wall& w, const LaneLoad& ll,
+                                    const float (&yt)[TB_MAXR], float scale, float out[NP]) {
+  // the load terms first: they do not depend on the populations
+  float bx = 0.f, by = 0.f;
+  if constexpr (FORCE) load_terms(ll, yt, scale, bx, by);
   if constexpr (BC == LBM_PERIODIC || !EDGE) {
     // collide() on f_0 = f*_0(x - 1), f_1 = f*_1(y - 1), f_2 = f*_2(x + 1),
     // f_3 = f*_3(y + 1) (or the wall rule in the rows next to a wall) with
@@ -195,6 +231,10 @@ __device__ __forceinline__ void level_update(const float below[NP], const float 
     }
     float U[NC];
     moment_shifted(at + 0 * NC, f1, at + 2 * NC, f3, U);
+    if constexpr (FORCE) {
+      U[0] += 0.5f * bx;
+      U[1] += 0.5f * by;
+    }
     float X[NC], Y[NC];
     X[0] = fmaf(kK, U[2], km * U[3]);
     X[1] = km * U[4];
@@ -245,7 +285,13 @@ __device__ __forceinline__ void level_update(const float below[NP], const float 
       wall_rule(0, -1, kK, km, va, vb, fb, f[3]);
     }
   }
-  collide(kK, km, f);
+  float U[NC];
+  moment0(f, U);
+  if constexpr (FORCE) {
+    U[0] += 0.5f * bx;
+    U[1] += 0.5f * by;
+  }
+  collide_with(kK, km, U, f);
 #pragma unroll
   for (int q = 0; q < NQ; ++q)
 #pragma unroll
@@ -295,11 +341,12 @@ __device__ __forceinline__ void load_row(const float* __restrict__ src, int pitc
 // update of row y of level l from the rows below, at and above it; rows off
 // the grid (computed only to be dropped or replaced by a wall) use any valid
 // row for their wall lookups
-template <int BC, bool EDGE>
+template <int BC, bool EDGE, bool FORCE>
 __device__ __forceinline__ void row_update(const float below[NP], const float at[NP],
                                            const float above[NP], int xw, int y, int level,
                                            const Grid& g, const TBConst& sc, const WallSeq& ws,
-                                           float out[NP]) {
+                                           const TBForce& F, const LaneLoad& ll,
+                                           const float (&yt)[TB_MAXR], float out[NP]) {
   const int yc = y < 0 ? 0 : (y >= g.ny ? g.ny - 1 : y);
   Wall w;
   w.L = ws.L;
@@ -307,16 +354,32 @@ __device__ __forceinline__ void row_update(const float below[NP], const float at
   w.W = nullptr;
   w.rank = 0;
   w.Trow = nullptr;
-  level_update<BC, EDGE>(below, at, above, xw, yc, g.nx, g.ny, sc.kK, sc.km, w, out);
+  level_update<BC, EDGE, FORCE>(below, at, above, xw, yc, g.nx, g.ny, sc.kK, sc.km, w, ll, yt,
+                                F.scale, out);
+}
+
+// Row factors of level `level`, row y (scalar loads).  The node a row stands
+// for: on a periodic lattice the rows beyond the grid are the wrapped rows
+// (one wrap suffices: the host takes this path only for ny >= T + ring
+// length); on a Dirichlet lattice they are never used (clamped).
+template <int BC>
+__device__ __forceinline__ void load_factors(const TBForce& F, const Grid& g, int level, int y,
+                                             float (&yt)[TB_MAXR]) {
+  int yl = y < 0 ? 0 : (y >= g.ny ? g.ny - 1 : y);
+  if (BC == LBM_PERIODIC) yl = y < 0 ? y + g.ny : (y >= g.ny ? y - g.ny : y);
+  const ConstRow yr = (ConstRow)(F.rows + ((int64_t)(level - 1) * g.ny + yl) * TB_MAXR);
+#pragma unroll
+  for (int r = 0; r < TB_MAXR; ++r) yt[r] = yr[r];
 }
 
 // One sub-iteration i of the sweep (PRE: a pipeline-filling sub-iteration
 // before the first output row, I = i then; slot = i mod NB, known at compile
 // time in both cases).
-template <int BC, int NT, int PF, int T, bool EDGE, bool PRE>
+template <int BC, int NT, int PF, int T, bool EDGE, bool FORCE, bool PRE>
 __device__ __forceinline__ void sub_iteration(const float* __restrict__ src, float* __restrict__ dst,
                                      const Grid& g, const TBConst& sc, const Strip& st,
-                                     const WallSeq& ws, int pitch4, RowCursor& cur, int y0,
+                                     const WallSeq& ws, const TBForce& F, const LaneLoad& ll,
+                                     int pitch4, RowCursor& cur, int y0,
                                      int y1, int i, int I, int slot, float (&lv0)[3 + PF][NP],
                                      float (&lv)[T - 1][3 + PF][NP]) {
   constexpr int NB = 3 + PF;
@@ -331,21 +394,30 @@ __device__ __forceinline__ void sub_iteration(const float* __restrict__ src, flo
   // sink it towards its first use and shorten the distance it hides
   __builtin_amdgcn_sched_barrier(0);
   // level 1 .. T-1: level l row y0 + i + T - l; during the pipeline fill only
-  // the levels whose rows the segment needs (I >= -2 (T - l))
+  // the levels whose rows the segment needs (I >= -2 (T - l)).  With a load
+  // the row factors of level l + 1 are requested before level l is formed
+  // (yt[l mod 2] holds level l's), so their latency hides behind it.
+  float yt[2][TB_MAXR];
+  if constexpr (FORCE) {
+    load_factors<BC>(F, g, 1, y0 + i + T - 1, yt[1]);
+    load_factors<BC>(F, g, 2, y0 + i + T - 2, yt[0]);
+  }
   if (!PRE || I >= -2 * (T - 1))
-    row_update<BC, EDGE>(lv0[s2], lv0[s1], lv0[s], st.xw, y0 + i + T - 1, 1, g, sc, ws,
-                         lv[0][s]);
+    row_update<BC, EDGE, FORCE>(lv0[s2], lv0[s1], lv0[s], st.xw, y0 + i + T - 1, 1, g, sc, ws, F,
+                                ll, yt[1], lv[0][s]);
 #pragma unroll
   for (int l = 2; l < T; ++l) {
+    if constexpr (FORCE) load_factors<BC>(F, g, l + 1, y0 + i + T - l - 1, yt[(l + 1) & 1]);
     if (PRE && I < -2 * (T - l)) continue;
-    row_update<BC, EDGE>(lv[l - 2][s2], lv[l - 2][s1], lv[l - 2][s], st.xw, y0 + i + T - l, l, g,
-                         sc, ws, lv[l - 1][s]);
+    row_update<BC, EDGE, FORCE>(lv[l - 2][s2], lv[l - 2][s1], lv[l - 2][s], st.xw,
+                                y0 + i + T - l, l, g, sc, ws, F, ll, yt[l & 1], lv[l - 1][s]);
   }
   if (!PRE) {
     // level T, output row y0 + i
     float o[NP];
     const int rr = y0 + i;
-    row_update<BC, EDGE>(lv[T - 2][s2], lv[T - 2][s1], lv[T - 2][s], st.xw, rr, T, g, sc, ws, o);
+    row_update<BC, EDGE, FORCE>(lv[T - 2][s2], lv[T - 2][s1], lv[T - 2][s], st.xw, rr, T, g, sc,
+                                ws, F, ll, yt[T & 1], o);
     const int off = rr < y1 ? st.xs4 : TB_DROP;
     const int yo = rr < g.ny ? rr : g.ny - 1;
     char* rp = (char*)dst + (uint32_t)(yo * pitch4);
@@ -360,11 +432,12 @@ __device__ __forceinline__ void sub_iteration(const float* __restrict__ src, flo
 }
 
 // The sweep of one wave over output rows y0 .. y1 - 1 (EDGE: see level_update).
-template <int BC, int NT, int PF, int T, bool EDGE>
+template <int BC, int NT, int PF, int T, bool EDGE, bool FORCE>
 __device__ __forceinline__ void tblock_sweep(const float* __restrict__ src,
                                              float* __restrict__ dst, const Grid& g,
                                              const TBConst& sc, const Strip& st,
-                                             const WallSeq& ws, int pitch4, RowCursor& cur,
+                                             const WallSeq& ws, const TBForce& F,
+                                             const LaneLoad& ll, int pitch4, RowCursor& cur,
                                              int y0, int y1) {
   constexpr int NB = 3 + PF;
   const int ny = g.ny;
@@ -381,8 +454,8 @@ __device__ __forceinline__ void tblock_sweep(const float* __restrict__ src,
 #pragma unroll
   for (int p = 0; p < 2 * T; ++p) {
     const int I = p - 2 * T;
-    sub_iteration<BC, NT, PF, T, EDGE, true>(src, dst, g, sc, st, ws, pitch4, cur, y0, y1, I, I,
-                                             (I % NB + NB) % NB, lv0, lv);
+    sub_iteration<BC, NT, PF, T, EDGE, FORCE, true>(src, dst, g, sc, st, ws, F, ll, pitch4, cur,
+                                                    y0, y1, I, I, (I % NB + NB) % NB, lv0, lv);
   }
   // The sweep runs in whole rings of NB rows; rows past the segment end are
   // computed from valid (wrapped or clamped) rows and their stores dropped.
@@ -391,16 +464,16 @@ __device__ __forceinline__ void tblock_sweep(const float* __restrict__ src,
   for (int i0 = 0; i0 < y1 - y0; i0 += NB) {
 #pragma unroll
     for (int j = 0; j < NB; ++j)
-      sub_iteration<BC, NT, PF, T, EDGE, false>(src, dst, g, sc, st, ws, pitch4, cur, y0, y1,
-                                                i0 + j, 0, j, lv0, lv);
+      sub_iteration<BC, NT, PF, T, EDGE, FORCE, false>(src, dst, g, sc, st, ws, F, ll, pitch4,
+                                                       cur, y0, y1, i0 + j, 0, j, lv0, lv);
   }
 }
 
 // One wave's work: strip `strip`, output rows of segment `seg`.
-template <int BC, int NT, int PF, int T>
+template <int BC, int NT, int PF, int T, bool FORCE = false>
 __device__ __forceinline__ void tblock_wave(const float* __restrict__ src, float* __restrict__ dst,
                                    const Grid& g, const TBConst& sc, const WallSeq& ws,
-                                   int strip, int seg) {
+                                   int strip, int seg, const TBForce& F = TBForce{}) {
   static_assert(T >= 2 && T <= 8, "2 to 8 time levels per launch");
   constexpr int VALID = TB_LANES - 2 * T;  // stored columns per strip
   const int lane = threadIdx.x & 63;
@@ -419,27 +492,37 @@ __device__ __forceinline__ void tblock_wave(const float* __restrict__ src, float
   cur.y = y0 - T;
   cur.r = row_index<BC>(cur.y, ny);
   cur.last = y1 - 1 + T;
+  // this lane's load coefficients (the column it reads)
+  LaneLoad ll;
+  if constexpr (FORCE) {
+#pragma unroll
+    for (int r = 0; r < TB_MAXR; ++r)
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+        ll.x[c][r] = r < F.rank ? F.X[((int64_t)r * 2 + c) * nx + xc] : 0.f;
+  }
   if constexpr (BC == LBM_DIRICHLET) {
     // a Dirichlet wave meets the side walls only if its columns include one
     const int x_first = strip * VALID - T;
     if (x_first <= 0 || x_first + TB_LANES - 1 >= nx - 1) {
-      tblock_sweep<BC, NT, PF, T, true>(src, dst, g, sc, st, ws, pitch4, cur, y0, y1);
+      tblock_sweep<BC, NT, PF, T, true, FORCE>(src, dst, g, sc, st, ws, F, ll, pitch4, cur, y0,
+                                               y1);
       return;
     }
   }
-  tblock_sweep<BC, NT, PF, T, false>(src, dst, g, sc, st, ws, pitch4, cur, y0, y1);
+  tblock_sweep<BC, NT, PF, T, false, FORCE>(src, dst, g, sc, st, ws, F, ll, pitch4, cur, y0, y1);
 }
 
-template <int BC, int NT, int PF, int T>
+template <int BC, int NT, int PF, int T, bool FORCE = false>
 __global__ __launch_bounds__(256) void k_tblock(const float* __restrict__ src,
                                                 float* __restrict__ dst, Grid g, TBConst sc,
-                                                WallSeq ws) {
+                                                WallSeq ws, TBForce F) {
   const int ntiles = sc.nstrips * sc.nseg;
   const int nwg = (ntiles + 3) / 4;
   // wave index: uniform by construction, stated to the compiler
   const int wid = xcd_tile(blockIdx.x, nwg) * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (wid >= ntiles) return;  // whole waves exit together
-  tblock_wave<BC, NT, PF, T>(src, dst, g, sc, ws, wid % sc.nstrips, wid / sc.nstrips);
+  tblock_wave<BC, NT, PF, T, FORCE>(src, dst, g, sc, ws, wid % sc.nstrips, wid / sc.nstrips, F);
 }
 
 inline TBConst tblock_const(const Grid& g, float kK, float km, int seg_rows, int T) {

@@ -180,3 +180,61 @@ def test_load_and_displacement_errors():
     # removing the load returns to the plain path
     lat.set_body_force(None, None, None)
     lat.step(3)
+
+
+def _random_load(g, R, nx, ny, nsteps):
+    """A seeded separable load table of rank R (arbitrary, not a solution's)."""
+    return (0.5 * g.standard_normal((R, 2, nx)), g.standard_normal((R, ny)),
+            g.standard_normal((nsteps + 1, R)))
+
+
+@gpu
+@pytest.mark.parametrize("bc,N,ny", [(synth.PERIODIC, 130, 64), (synth.PERIODIC, 70, 45),
+                                     (synth.DIRICHLET, 300, 70), (synth.DIRICHLET, 61, 37)])
+@pytest.mark.parametrize("R", [1, 5, 16, 17])
+def test_blocked_steps_with_load_bitwise_equal_single_steps(bc, N, ny, R):
+    # with a load of rank <= 16 and no displacement state the blocked kernel
+    # steps T per launch (the ranks below 16 padded with terms that add
+    # exactly nothing); rank 17 runs one step per launch; every launch
+    # variant, through each load variant, gives the single-step state bit for
+    # bit (Dirichlet with moving walls)
+    torch = _torch()
+    from paper_2408_01081_amd.lbm import Lattice
+    prob = synth.plane_wave_problem(N, ny, bc, seed=23, kmax=3)
+    v0, sb0 = prob.initial_fields()
+    nsteps = 37
+    g = np.random.default_rng(R)
+    BX, BY, BT = (torch.from_numpy(a) for a in _random_load(g, R, N, ny, nsteps))
+    W, T = prob.wall_table(nsteps)
+    lat = Lattice(prob.nx, prob.ny, prob.dx, prob.dt, prob.lam, prob.mu, prob.rho, prob.bc)
+    lat.set_body_force(BX, BY, BT)
+    ref = None
+    for cfg in [-1] + [c["index"] for c in lat.tblock_configs()]:
+        lat.init(torch.from_numpy(v0), torch.from_numpy(sb0))
+        if bc == synth.DIRICHLET:
+            lat.set_wall_velocity(torch.from_numpy(W), torch.from_numpy(T))
+        lat.tblock_config = cfg
+        lat.step(11).step(nsteps - 11)
+        f = lat.populations()
+        if ref is None:
+            ref = f
+            assert torch.isfinite(f).all()
+        else:
+            assert torch.equal(f.view(torch.int32), ref.view(torch.int32)), cfg
+
+
+@gpu
+@pytest.mark.parametrize("bc", [synth.PERIODIC, synth.DIRICHLET])
+def test_blocked_steps_with_load_match_oracle(bc):
+    # the standing solution's load has rank 16 for these Lame parameters, so
+    # the blocked kernel takes it (no displacement state)
+    mat = synth.Material.from_lame(1.0, 0.5, 1.0)
+    prob = _mms(64, bc, synth.standing_mms_solution, mat,
+                lambda dx: synth.dt_at_cfl_fraction(dx, mat, 0.5), ny=48)
+    assert prob.body_table(1)[0].shape[0] == 16
+    lat, sim, s = _run(prob, 300, tblock=40 if bc == synth.PERIODIC else 19, with_disp=False)
+    lat.step(296).step(4)
+    sim.advance(300)
+    err = oracle.rel_l2(lat.moments_U().double().cpu().numpy(), sim.U())
+    print("blocked with load, bc=%d: rel-L2 %.3e" % (bc, err))
+    assert err < 1e-5
