@@ -147,11 +147,13 @@ lbm_status lbm_set_wall_velocity(lbm_ctx* ctx, int32_t rank, const float* d_W,
  *   d_T    [nsteps + 1][R] FP32, row n = time functions at t_n
  * The load enters the initialisation (Eq. ic_second), the collision
  * (U_num = sum f + B_hat / 2 at every collision) and every output at the
- * current level.  Steps beyond nsteps are rejected by lbm_step; steps with a
- * load run one launch per step of the one-node-per-thread kernel (no
- * temporal blocking).  Set it before lbm_init to include B_hat(0) in the
- * initialisation.  Pointers are kept (not copied) and must stay valid while
- * stepping. */
+ * current level.  Steps beyond nsteps are rejected by lbm_step.  With a
+ * blocked variant selected (lbm_set_tblock_config / lbm_autotune), R <= 16,
+ * no displacement state, no error tracking and ny >= T + 5, steps run T per
+ * launch of a blocked kernel with the load (bitwise the same results);
+ * otherwise one launch per step of the one-node-per-thread kernel.  Set it
+ * before lbm_init to include B_hat(0) in the initialisation.  Pointers are
+ * kept (not copied) and must stay valid while stepping. */
 lbm_status lbm_set_body_force(lbm_ctx* ctx, int32_t rank, const float* d_X, const float* d_Y,
                               const float* d_T, int64_t nsteps);
 
