@@ -62,7 +62,7 @@ struct WallSeq {
 // the separable sum of the single-step kernel's body_hat: each lane keeps its
 // column's coefficients X[r][c][x] (ranks >= rank padded with +0) and the
 // launch's row factors rows[l][y][r] = Y[r][y] T_{n+l+1}[r] (padded with -0)
-// are read through the scalar cache.  A padded term adds +0 * -0 = -0, which
+// are staged through LDS (fac_request, fac_stage, fac_read below).  A padded term adds +0 * -0 = -0, which
 // leaves every sum unchanged in round-to-nearest, so the result is bitwise
 // the single-step kernel's.
 constexpr int TB_MAXR = 16;  // largest rank the blocked kernel takes
@@ -75,7 +75,6 @@ struct TBForce {
 struct LaneLoad {
   float x[2][TB_MAXR];
 };
-typedef const __attribute__((address_space(4))) float* ConstRow;
 
 // B_hat (c = 0, 1) of this lane's node from the row factors yt
 __device__ __forceinline__ void load_terms(const LaneLoad& ll, const float (&yt)[TB_MAXR],
@@ -358,18 +357,55 @@ __device__ __forceinline__ void row_update(const float below[NP], const float at
                                 F.scale, out);
 }
 
-// Row factors of level `level`, row y (scalar loads).  The node a row stands
-// for: on a periodic lattice the rows beyond the grid are the wrapped rows
-// (one wrap suffices: the host takes this path only for ny >= T + ring
-// length); on a Dirichlet lattice they are never used (clamped).
-template <int BC>
-__device__ __forceinline__ void load_factors(const TBForce& F, const Grid& g, int level, int y,
-                                             float (&yt)[TB_MAXR]) {
-  int yl = y < 0 ? 0 : (y >= g.ny ? g.ny - 1 : y);
-  if (BC == LBM_PERIODIC) yl = y < 0 ? y + g.ny : (y >= g.ny ? y - g.ny : y);
-  const ConstRow yr = (ConstRow)(F.rows + ((int64_t)(level - 1) * g.ny + yl) * TB_MAXR);
+// Row factors through LDS.  A sub-iteration j needs the factors of its T
+// level rows, the table f[e], e = 16 (l - 1) + r (level l, rank r): lane k
+// holds elements k and k + 64.  At sub-iteration i the wave requests them for
+// sub-iteration i + 2 (vector loads, before the population prefetch), writes
+// those of i + 1 (requested at i - 1) into that sub-iteration's LDS slot, and
+// its level updates read their 16 factors from slot i (the same address in
+// every lane: broadcast reads).  The node a row stands for: on a periodic
+// lattice the rows beyond the grid are the wrapped rows (one wrap suffices:
+// the host takes this path only for ny >= T + ring length); on a Dirichlet
+// lattice their loads are never used (clamped).
+template <int BC, int T>
+__device__ __forceinline__ void fac_request(const TBForce& F, const Grid& g, int y0, int j,
+                                            float (&v)[2]) {
+  const int lane = threadIdx.x & 63;
 #pragma unroll
-  for (int r = 0; r < TB_MAXR; ++r) yt[r] = yr[r];
+  for (int k = 0; k < 2; ++k) {
+    const int e = lane + 64 * k;
+    v[k] = 0.f;
+    if (e < TB_MAXR * T) {
+      const int l = e / TB_MAXR + 1, r = e % TB_MAXR;
+      const int y = y0 + j + T - l;
+      int yl = y < 0 ? 0 : (y >= g.ny ? g.ny - 1 : y);
+      if (BC == LBM_PERIODIC) yl = y < 0 ? y + g.ny : (y >= g.ny ? y - g.ny : y);
+      v[k] = F.rows[((int64_t)(l - 1) * g.ny + yl) * TB_MAXR + r];
+    }
+  }
+}
+
+template <int T>
+__device__ __forceinline__ void fac_stage(float* slot, const float (&v)[2]) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int k = 0; k < 2; ++k)
+    if (lane + 64 * k < TB_MAXR * T) slot[lane + 64 * k] = v[k];
+  // the wave's later reads of the slot see these writes (LDS operations of
+  // a wave complete in order); keep the compiler from moving them
+  __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ void fac_read(const float* slot, int level, float (&yt)[TB_MAXR]) {
+  const float4* p = reinterpret_cast<const float4*>(slot + (level - 1) * TB_MAXR);
+#pragma unroll
+  for (int q = 0; q < TB_MAXR / 4; ++q) {
+    const float4 v = p[q];
+    yt[4 * q] = v.x;
+    yt[4 * q + 1] = v.y;
+    yt[4 * q + 2] = v.z;
+    yt[4 * q + 3] = v.w;
+  }
 }
 
 // One sub-iteration i of the sweep (PRE: a pipeline-filling sub-iteration
@@ -379,11 +415,14 @@ template <int BC, int NT, int PF, int T, bool EDGE, bool FORCE, bool PRE>
 __device__ __forceinline__ void sub_iteration(const float* __restrict__ src, float* __restrict__ dst,
                                      const Grid& g, const TBConst& sc, const Strip& st,
                                      const WallSeq& ws, const TBForce& F, const LaneLoad& ll,
+                                     float* fac, float (&fv)[3 + PF][2],
                                      int pitch4, RowCursor& cur, int y0,
                                      int y1, int i, int I, int slot, float (&lv0)[3 + PF][NP],
                                      float (&lv)[T - 1][3 + PF][NP]) {
   constexpr int NB = 3 + PF;
+  constexpr int FS = TB_MAXR * T;  // floats of one LDS factor slot
   const int s = slot, s1 = (slot + NB - 1) % NB, s2 = (slot + NB - 2) % NB;
+  if constexpr (FORCE) fac_request<BC, T>(F, g, y0, i + 2, fv[(s + 2) % NB]);
   // prefetch level-0 row y0 + i + T + PF (the cursor's row) into slot
   // (i + PF) mod NB, which held the row of sub-iteration i + PF - NB = i - 3
   // (no longer read).  Past the last needed row it re-reads that row (a
@@ -395,19 +434,20 @@ __device__ __forceinline__ void sub_iteration(const float* __restrict__ src, flo
   __builtin_amdgcn_sched_barrier(0);
   // level 1 .. T-1: level l row y0 + i + T - l; during the pipeline fill only
   // the levels whose rows the segment needs (I >= -2 (T - l)).  With a load
-  // the row factors of level l + 1 are requested before level l is formed
-  // (yt[l mod 2] holds level l's), so their latency hides behind it.
+  // the factors of level l + 1 are read from LDS before level l is formed
+  // (yt[l mod 2] holds level l's).
   float yt[2][TB_MAXR];
   if constexpr (FORCE) {
-    load_factors<BC>(F, g, 1, y0 + i + T - 1, yt[1]);
-    load_factors<BC>(F, g, 2, y0 + i + T - 2, yt[0]);
+    fac_stage<T>(fac + ((s + 1) % NB) * FS, fv[(s + 1) % NB]);
+    fac_read(fac + s * FS, 1, yt[1]);
+    fac_read(fac + s * FS, 2, yt[0]);
   }
   if (!PRE || I >= -2 * (T - 1))
     row_update<BC, EDGE, FORCE>(lv0[s2], lv0[s1], lv0[s], st.xw, y0 + i + T - 1, 1, g, sc, ws, F,
                                 ll, yt[1], lv[0][s]);
 #pragma unroll
   for (int l = 2; l < T; ++l) {
-    if constexpr (FORCE) load_factors<BC>(F, g, l + 1, y0 + i + T - l - 1, yt[(l + 1) & 1]);
+    if constexpr (FORCE) fac_read(fac + s * FS, l + 1, yt[(l + 1) & 1]);
     if (PRE && I < -2 * (T - l)) continue;
     row_update<BC, EDGE, FORCE>(lv[l - 2][s2], lv[l - 2][s1], lv[l - 2][s], st.xw,
                                 y0 + i + T - l, l, g, sc, ws, F, ll, yt[l & 1], lv[l - 1][s]);
@@ -437,10 +477,19 @@ __device__ __forceinline__ void tblock_sweep(const float* __restrict__ src,
                                              float* __restrict__ dst, const Grid& g,
                                              const TBConst& sc, const Strip& st,
                                              const WallSeq& ws, const TBForce& F,
-                                             const LaneLoad& ll, int pitch4, RowCursor& cur,
-                                             int y0, int y1) {
+                                             const LaneLoad& ll, float* fac, int pitch4,
+                                             RowCursor& cur, int y0, int y1) {
   constexpr int NB = 3 + PF;
   const int ny = g.ny;
+  // load factors: requested two sub-iterations ahead (fv), staged in LDS one
+  // ahead; the first sub-iteration's are staged here
+  float fv[NB][2];
+  if constexpr (FORCE) {
+    constexpr int first = -2 * T;
+    fac_request<BC, T>(F, g, y0, first, fv[((first % NB) + NB) % NB]);
+    fac_request<BC, T>(F, g, y0, first + 1, fv[(((first + 1) % NB) + NB) % NB]);
+    fac_stage<T>(fac + (((first % NB) + NB) % NB) * TB_MAXR * T, fv[((first % NB) + NB) % NB]);
+  }
   float lv0[NB][NP];        // level 0: row of sub-iteration i is y0 + i + T
   float lv[T - 1][NB][NP];  // level l: row of sub-iteration i is y0 + i + T - l
   // level-0 rows of the first PF sub-iterations of the pipeline fill
@@ -454,8 +503,9 @@ __device__ __forceinline__ void tblock_sweep(const float* __restrict__ src,
 #pragma unroll
   for (int p = 0; p < 2 * T; ++p) {
     const int I = p - 2 * T;
-    sub_iteration<BC, NT, PF, T, EDGE, FORCE, true>(src, dst, g, sc, st, ws, F, ll, pitch4, cur,
-                                                    y0, y1, I, I, (I % NB + NB) % NB, lv0, lv);
+    sub_iteration<BC, NT, PF, T, EDGE, FORCE, true>(src, dst, g, sc, st, ws, F, ll, fac, fv,
+                                                    pitch4, cur, y0, y1, I, I, (I % NB + NB) % NB,
+                                                    lv0, lv);
   }
   // The sweep runs in whole rings of NB rows; rows past the segment end are
   // computed from valid (wrapped or clamped) rows and their stores dropped.
@@ -464,8 +514,9 @@ __device__ __forceinline__ void tblock_sweep(const float* __restrict__ src,
   for (int i0 = 0; i0 < y1 - y0; i0 += NB) {
 #pragma unroll
     for (int j = 0; j < NB; ++j)
-      sub_iteration<BC, NT, PF, T, EDGE, FORCE, false>(src, dst, g, sc, st, ws, F, ll, pitch4,
-                                                       cur, y0, y1, i0 + j, 0, j, lv0, lv);
+      sub_iteration<BC, NT, PF, T, EDGE, FORCE, false>(src, dst, g, sc, st, ws, F, ll, fac, fv,
+                                                       pitch4, cur, y0, y1, i0 + j, 0, j, lv0,
+                                                       lv);
   }
 }
 
@@ -473,7 +524,8 @@ __device__ __forceinline__ void tblock_sweep(const float* __restrict__ src,
 template <int BC, int NT, int PF, int T, bool FORCE = false>
 __device__ __forceinline__ void tblock_wave(const float* __restrict__ src, float* __restrict__ dst,
                                    const Grid& g, const TBConst& sc, const WallSeq& ws,
-                                   int strip, int seg, const TBForce& F = TBForce{}) {
+                                   int strip, int seg, const TBForce& F = TBForce{},
+                                   float* fac = nullptr) {
   static_assert(T >= 2 && T <= 8, "2 to 8 time levels per launch");
   constexpr int VALID = TB_LANES - 2 * T;  // stored columns per strip
   const int lane = threadIdx.x & 63;
@@ -505,12 +557,13 @@ __device__ __forceinline__ void tblock_wave(const float* __restrict__ src, float
     // a Dirichlet wave meets the side walls only if its columns include one
     const int x_first = strip * VALID - T;
     if (x_first <= 0 || x_first + TB_LANES - 1 >= nx - 1) {
-      tblock_sweep<BC, NT, PF, T, true, FORCE>(src, dst, g, sc, st, ws, F, ll, pitch4, cur, y0,
-                                               y1);
+      tblock_sweep<BC, NT, PF, T, true, FORCE>(src, dst, g, sc, st, ws, F, ll, fac, pitch4, cur,
+                                               y0, y1);
       return;
     }
   }
-  tblock_sweep<BC, NT, PF, T, false, FORCE>(src, dst, g, sc, st, ws, F, ll, pitch4, cur, y0, y1);
+  tblock_sweep<BC, NT, PF, T, false, FORCE>(src, dst, g, sc, st, ws, F, ll, fac, pitch4, cur, y0,
+                                            y1);
 }
 
 template <int BC, int NT, int PF, int T, bool FORCE = false>
@@ -522,7 +575,11 @@ __global__ __launch_bounds__(256) void k_tblock(const float* __restrict__ src,
   // wave index: uniform by construction, stated to the compiler
   const int wid = xcd_tile(blockIdx.x, nwg) * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (wid >= ntiles) return;  // whole waves exit together
-  tblock_wave<BC, NT, PF, T, FORCE>(src, dst, g, sc, ws, wid % sc.nstrips, wid / sc.nstrips, F);
+  // per wave: one slot of load factors per ring row (unused without a load)
+  __shared__ __attribute__((aligned(16))) float fac[FORCE ? 4 * (3 + PF) * TB_MAXR * T : 4];
+  float* mine = FORCE ? fac + (threadIdx.x >> 6) * (3 + PF) * TB_MAXR * T : nullptr;
+  tblock_wave<BC, NT, PF, T, FORCE>(src, dst, g, sc, ws, wid % sc.nstrips, wid / sc.nstrips, F,
+                                    mine);
 }
 
 inline TBConst tblock_const(const Grid& g, float kK, float km, int seg_rows, int T) {
