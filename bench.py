@@ -218,18 +218,18 @@ def main():
     torch.cuda.empty_cache()
 
     # ---- the step with a body load and the displacement output ----------------
-    with_load = with_load_blocked = None
+    with_load = with_load_blocked = with_load_single = None
     if not args.no_load_leg:
-        try:
-            with_load = load_leg()
-        except Exception as ex:  # reported, never hidden
-            with_load = {"error": repr(ex)}
-        if tuned[0]["tblock_config"] >= 0:
+        tb = tuned[0]["tblock_config"]
+        legs = {}
+        for key, kw in (("disp", dict(nsteps=400, disp=True, tblock=tb)),
+                        ("load", dict(nsteps=400, disp=False, tblock=tb)),
+                        ("single", dict(nsteps=200, disp=True, tblock=-1))):
             try:
-                with_load_blocked = load_leg(nsteps=400, disp=False,
-                                             tblock=tuned[0]["tblock_config"])
+                legs[key] = load_leg(**kw)
             except Exception as ex:  # reported, never hidden
-                with_load_blocked = {"error": repr(ex)}
+                legs[key] = {"error": repr(ex)}
+        with_load, with_load_blocked, with_load_single = legs["disp"], legs["load"], legs["single"]
 
     # ---- batched instances: one hipGraph launch of many steps ------------------
     batched = None
@@ -266,6 +266,7 @@ def main():
         "parity": parity,
         "with_load_and_displacement": with_load,
         "with_load": with_load_blocked,
+        "with_load_and_displacement_one_launch_per_step": with_load_single,
         "batched": batched,
         "surrogate": surrogate,
         "wall_s": round(wall, 3),
@@ -394,10 +395,9 @@ def batched_leg(n, nsteps):
 
 def load_leg(nsteps=200, disp=True, tblock=None):
     """The 4096^2 periodic lattice stepped with a body load (the standing
-    manufactured solution's, separable, rank 16), with the FP64 displacement
-    state (one launch per step) or without it (blocked variant `tblock`, T
-    steps per launch): the optional outputs' cost, reported beside the plain
-    step."""
+    manufactured solution's, separable, rank 16), with or without the FP64
+    displacement state, blocked variant `tblock` selected (-1: one launch per
+    step): the optional outputs' cost, reported beside the plain step."""
     import numpy as np
     import torch
 
@@ -430,24 +430,20 @@ def load_leg(nsteps=200, disp=True, tblock=None):
     e1.record(stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / nsteps
-    if disp:
-        alg = (BYTES_PER_LUP + 32) * N * N
-        out = {"workload": "periodic 4096x4096, body load of rank %d (standing manufactured "
-                           "solution) + FP64 displacement state, one launch per step"
-                           % BX.shape[0],
-               "kernel": "k_step_ext", "steps": nsteps, "ms_per_step": round(ms, 5),
-               "GLUPS": round(N * N / ms / 1e6, 2),
-               "algorithmic_bytes_per_node": BYTES_PER_LUP + 32,
-               "algorithmic_GB/s": round(alg / (ms * 1e-3) / 1e9, 1),
-               "frac": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
-    else:
-        T = next(k for k in lat.tblock_configs() if k["index"] == lat.tblock_config)["steps"]
-        out = {"workload": "periodic 4096x4096, body load of rank %d (standing manufactured "
-                           "solution), %d steps per launch" % (BX.shape[0], T),
-               "kernel": "k_tblock with load (variant %d)" % lat.tblock_config,
-               "steps": nsteps, "ms_per_step": round(ms, 5),
-               "GLUPS": round(N * N / ms / 1e6, 2),
-               "algorithmic_bytes_per_node_update": round(BYTES_PER_LUP / T, 2)}
+    T = lat.steps_per_launch
+    extra = " + FP64 displacement state" if disp else ""
+    per_launch = BYTES_PER_LUP + (32 if disp else 0)  # B per node and launch
+    out = {"workload": "periodic 4096x4096, body load of rank %d (standing manufactured "
+                       "solution)%s, %d step(s) per launch" % (BX.shape[0], extra, T),
+           "kernel": ("k_tblock with load%s" % (" and displacement" if disp else "")) if T > 1
+           else "k_step_ext",
+           "steps": nsteps, "ms_per_step": round(ms, 5), "GLUPS": round(N * N / ms / 1e6, 2),
+           "steps_per_launch": T,
+           "algorithmic_bytes_per_node_update": round(per_launch / T, 2)}
+    if T == 1:
+        alg = per_launch * N * N
+        out["algorithmic_GB/s"] = round(alg / (ms * 1e-3) / 1e9, 1)
+        out["frac"] = round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
     del lat
     torch.cuda.empty_cache()
     return out

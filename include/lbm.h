@@ -149,9 +149,10 @@ lbm_status lbm_set_wall_velocity(lbm_ctx* ctx, int32_t rank, const float* d_W,
  * (U_num = sum f + B_hat / 2 at every collision) and every output at the
  * current level.  Steps beyond nsteps are rejected by lbm_step.  With a
  * blocked variant selected (lbm_set_tblock_config / lbm_autotune), R <= 16,
- * no displacement state, no error tracking and ny >= T + 5, steps run T per
- * launch of a blocked kernel with the load (bitwise the same results);
- * otherwise one launch per step of the one-node-per-thread kernel.  Set it
+ * no error tracking and ny >= T + 5, steps run T per launch of a blocked
+ * kernel with the load (and the displacement state if the context keeps
+ * it), bitwise the same results; otherwise one launch per step of the
+ * one-node-per-thread kernel (lbm_steps_per_launch tells which).  Set it
  * before lbm_init to include B_hat(0) in the initialisation.  Pointers are
  * kept (not copied) and must stay valid while stepping. */
 lbm_status lbm_set_body_force(lbm_ctx* ctx, int32_t rank, const float* d_X, const float* d_Y,
@@ -163,7 +164,10 @@ lbm_status lbm_set_body_force(lbm_ctx* ctx, int32_t rank, const float* d_X, cons
  * in FP64 (a running sum: FP32 would round the whole displacement at every
  * half step); each step adds dt/2 v_num twice.  Requires LBM_F_DISPLACEMENT;
  * lbm_step rejects a context with the flag until this has been called.
- * Steps of such a context run one launch per step (no temporal blocking). */
+ * With a blocked variant selected (and a body load of rank <= 16 or none,
+ * no error tracking) steps run several per launch, the rows in flight kept
+ * in LDS and updated in the same order (bitwise the same D); otherwise one
+ * launch per step. */
 lbm_status lbm_init_displacement(lbm_ctx* ctx, const double* d_u0);
 
 /* Displacement u(t_n) = D - dt/2 v_num(t_n) at the current step, [2][ny][nx]
@@ -279,6 +283,12 @@ lbm_status lbm_autotune(lbm_ctx* ctx, int32_t reps, int32_t use_cache, int32_t* 
 int32_t lbm_tblock_config_count(void);
 lbm_status lbm_tblock_config_info(int32_t index, int32_t* h_steps, int32_t* h_seg_rows,
                                   int32_t* h_nontemporal, int32_t* h_prefetch);
+/* Time steps per launch that lbm_step uses for this context as configured
+ * now: T of the selected blocked variant (with a body load and/or the
+ * displacement state: of the variant with those extras that lbm_step picks
+ * for it), 1 for single steps or while error norms are tracked; -1 for a
+ * NULL context. */
+int32_t lbm_steps_per_launch(const lbm_ctx* ctx);
 lbm_status lbm_get_tblock_config(const lbm_ctx* ctx, int32_t* h_index);
 lbm_status lbm_set_tblock_config(lbm_ctx* ctx, int32_t index);
 /* Average duration (ms) of one launch of blocked variant `index` (T steps;

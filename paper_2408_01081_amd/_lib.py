@@ -63,6 +63,7 @@ SIGNATURES = [
     ("lbm_tblock_config_info", ctypes.c_int,
      [_I32, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32),
       ctypes.POINTER(_I32)]),
+    ("lbm_steps_per_launch", _I32, [_VP]),
     ("lbm_get_tblock_config", ctypes.c_int, [_VP, ctypes.POINTER(_I32)]),
     ("lbm_set_tblock_config", ctypes.c_int, [_VP, _I32]),
     ("lbm_time_tblock_config", ctypes.c_int, [_VP, _I32, _I32, _PD]),

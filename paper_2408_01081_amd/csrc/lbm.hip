@@ -398,7 +398,7 @@ struct lbm_ctx {
   int step_cfg;   // index into kStepConfigs
   int tb_cfg;         // index into kTBConfigs, or -1 (single steps only)
   int tb_slots[64];   // resident waves of a blocked variant on this device (0: not known)
-  int tbf_slots[8];   // the same for the variants with a body load
+  int tbf_slots[24];  // the same for the variants with a load / displacement (3 per variant)
   float* wall_v;        // [WALL_CHUNK][2 (nx + ny)][2] wall velocities of upcoming steps
   // separable body load (rank 0: none); row n of force_T belongs to t_n
   const float* force_X;
@@ -751,7 +751,7 @@ int64_t lbm_step_count(const lbm_ctx* c) { return c ? c->nstep : -1; }
 
 namespace {
 
-typedef void (*TBFn)(const float*, float*, Grid, TBConst, WallSeq, TBForce);
+typedef void (*TBFn)(const float*, float*, Grid, TBConst, WallSeq, TBExtra);
 // Temporally blocked variants: T steps per launch, output rows per segment
 // (0: as many as fill the device with one wave per resident slot, rounded up
 // to the ring length), nontemporal stores, rows prefetched ahead.
@@ -761,12 +761,26 @@ struct TBConfig {
 };
 #define LBM_TB(T, S, N, F) \
   {T, S, N, F, {&k_tblock<LBM_PERIODIC, N, F, T>, &k_tblock<LBM_DIRICHLET, N, F, T>}}
-// variants with a body load: the best variants of the load-free table's grids
-// (the Dirichlet kernel holding both wall paths and the load does not fit in
-// registers at T = 8)
-#define LBM_TBF(T, S, N, F) \
-  {T, S, N, F, {&k_tblock<LBM_PERIODIC, N, F, T, true>, &k_tblock<LBM_DIRICHLET, N, F, T, true>}}
-#define LBM_TBF_P(T, S, N, F) {T, S, N, F, {&k_tblock<LBM_PERIODIC, N, F, T, true>, nullptr}}
+// Variants with a body load and/or the displacement state, the best variants
+// of the load-free table's grids; fn[m][bc], m = 0: load, 1: displacement,
+// 2: both (at T = 8 only the periodic kernel with a load fits in registers)
+struct TBExtConfig {
+  int steps, seg_rows, nt, pf;
+  TBFn fn[3][2];
+};
+#define LBM_TBX_K(B, T, N, F, L, D) &k_tblock<B, N, F, T, L, D>
+#define LBM_TBX(T, S, N, F)                                                                       \
+  {T, S, N, F,                                                                                    \
+   {{LBM_TBX_K(LBM_PERIODIC, T, N, F, true, false), LBM_TBX_K(LBM_DIRICHLET, T, N, F, true, false)}, \
+    {LBM_TBX_K(LBM_PERIODIC, T, N, F, false, true), LBM_TBX_K(LBM_DIRICHLET, T, N, F, false, true)}, \
+    {LBM_TBX_K(LBM_PERIODIC, T, N, F, true, true), LBM_TBX_K(LBM_DIRICHLET, T, N, F, true, true)}}}
+#define LBM_TBX_PD(T, S, N, F)                                                      \
+  {T, S, N, F,                                                                     \
+   {{nullptr, nullptr},                                                            \
+    {LBM_TBX_K(LBM_PERIODIC, T, N, F, false, true), nullptr},                      \
+    {LBM_TBX_K(LBM_PERIODIC, T, N, F, true, true), nullptr}}}
+#define LBM_TBX_P(T, S, N, F) \
+  {T, S, N, F, {{LBM_TBX_K(LBM_PERIODIC, T, N, F, true, false), nullptr}, {nullptr, nullptr}, {nullptr, nullptr}}}
 const TBConfig kTBConfigs[] = {
     LBM_TB(2, 4, 0, 1),  LBM_TB(2, 4, 1, 1),  LBM_TB(2, 8, 0, 1),  LBM_TB(2, 0, 0, 1),
     LBM_TB(3, 4, 0, 1),  LBM_TB(3, 5, 0, 2),  LBM_TB(3, 4, 1, 1),  LBM_TB(3, 8, 1, 1),
@@ -779,15 +793,17 @@ const TBConfig kTBConfigs[] = {
     LBM_TB(6, 8, 0, 1),  LBM_TB(6, 12, 0, 1), LBM_TB(6, 20, 0, 2), LBM_TB(6, 30, 0, 2),
     LBM_TB(8, 20, 0, 2), LBM_TB(8, 30, 0, 2), LBM_TB(8, 24, 0, 1), LBM_TB(8, 32, 0, 1),
     LBM_TB(8, 0, 0, 2),  LBM_TB(8, -2, 0, 2), LBM_TB(8, 0, 0, 1),  LBM_TB(7, 0, 0, 2)};
-const TBConfig kTBForceConfigs[] = {LBM_TBF_P(8, 0, 0, 2), LBM_TBF_P(8, 30, 0, 2),
-                                     LBM_TBF(6, 16, 1, 1), LBM_TBF(4, 4, 1, 1)};
+const TBExtConfig kTBExtraConfigs[] = {LBM_TBX_P(8, 0, 0, 2), LBM_TBX_PD(6, 0, 0, 2),
+                                       LBM_TBX(6, 16, 1, 1)};
 #undef LBM_TB
-#undef LBM_TBF
-#undef LBM_TBF_P
-constexpr int kNumTBForceConfigs = (int)(sizeof(kTBForceConfigs) / sizeof(kTBForceConfigs[0]));
+#undef LBM_TBX_K
+#undef LBM_TBX
+#undef LBM_TBX_P
+#undef LBM_TBX_PD
+constexpr int kNumTBExtraConfigs = (int)(sizeof(kTBExtraConfigs) / sizeof(kTBExtraConfigs[0]));
 constexpr int kNumTBConfigs = (int)(sizeof(kTBConfigs) / sizeof(kTBConfigs[0]));
 static_assert(kNumTBConfigs <= 64, "tb_slots size");
-static_assert(kNumTBForceConfigs <= 8, "tbf_slots size");
+static_assert(kNumTBExtraConfigs * 3 <= 24, "tbf_slots size");
 
 
 // Sum the wall velocities of steps step0 .. step0 + n - 1 (n <= WALL_CHUNK)
@@ -839,12 +855,12 @@ WallSeq walls_from(const lbm_ctx* c, int s, bool with_walls) {
 // Rows per segment of blocked variant k: its seg_rows, or for seg_rows <= 0 as
 // many as give one wave per resident slot (times -seg_rows) across the grid,
 // rounded up to the ring length (*slots caches the device's resident waves).
-int seg_rows_of(lbm_ctx* c, const TBConfig& k, int* slots) {
-  if (k.seg_rows > 0) return k.seg_rows;
+int seg_rows_of(lbm_ctx* c, int steps, int seg_rows, int pf, TBFn fn, int* slots) {
+  if (seg_rows > 0) return seg_rows;
   if (*slots == 0) {
     int per_cu = 0, cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k.fn[c->p.bc], 256,
-                                                     0) != hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)fn, 256, 0) !=
+            hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) !=
             hipSuccess ||
         per_cu < 1 || cus < 1) {
@@ -854,10 +870,10 @@ int seg_rows_of(lbm_ctx* c, const TBConfig& k, int* slots) {
     }
     *slots = per_cu * 4 * cus;
   }
-  const int ring = 3 + k.pf;
-  const int valid = TB_LANES - 2 * k.steps;
+  const int ring = 3 + pf;
+  const int valid = TB_LANES - 2 * steps;
   const int nstrips = (c->g.nx + valid - 1) / valid;
-  const int rounds = k.seg_rows < 0 ? -k.seg_rows : 1;
+  const int rounds = seg_rows < 0 ? -seg_rows : 1;
   int nseg = *slots * rounds / nstrips;
   if (nseg < 1) nseg = 1;
   int rows = (c->g.ny + nseg - 1) / nseg;
@@ -866,7 +882,8 @@ int seg_rows_of(lbm_ctx* c, const TBConfig& k, int* slots) {
 }
 
 int tb_seg_rows(lbm_ctx* c, int index) {
-  return seg_rows_of(c, kTBConfigs[index], &c->tb_slots[index]);
+  const TBConfig& k = kTBConfigs[index];
+  return seg_rows_of(c, k.steps, k.seg_rows, k.pf, k.fn[c->p.bc], &c->tb_slots[index]);
 }
 
 // one launch of variant `index`: kTBConfigs[index].steps steps, level l with
@@ -876,7 +893,7 @@ void launch_tb(lbm_ctx* c, int index, const float* src, float* dst, const WallSe
   const TBConst sc = tblock_const(c->g, (float)c->kK, (float)c->km, tb_seg_rows(c, index), k.steps);
   const int ntiles = sc.nstrips * sc.nseg;
   hipLaunchKernelGGL(k.fn[c->p.bc], dim3((unsigned)((ntiles + 3) / 4)), dim3(256), 0, c->stream,
-                     src, dst, c->g, sc, ws, TBForce{nullptr, nullptr, 0, 0.f});
+                     src, dst, c->g, sc, ws, TBExtra{nullptr, nullptr, 0, 0.f, nullptr, 0.0});
 }
 
 // rows[l][y][r] = Y[r][y] T_{n1 + l}[r] for r < R, -0 beyond (the factors of
@@ -891,16 +908,16 @@ __global__ void k_force_rows(const float* __restrict__ Y, const float* __restric
   rows[i] = r < R ? Y[(int64_t)r * ny + y] * T1[(int64_t)l * R + r] : -0.f;
 }
 
-// the load variant for a lattice whose blocked variant is tb_cfg: the same
-// launch shape if there is one, else the same T, else the first for its
-// boundary type; -1 if none applies
-int force_variant(const lbm_ctx* c) {
+// the variant with extras m (0 load, 1 displacement, 2 both) for a lattice
+// whose blocked variant is tb_cfg: the same launch shape if there is one,
+// else the same T, else the first for its boundary type; -1 if none applies
+int extra_variant(const lbm_ctx* c, int m) {
   if (c->tb_cfg < 0 || c->force_rank > TB_MAXR || !tblock_fits(c->g)) return -1;
   const TBConfig& t = kTBConfigs[c->tb_cfg];
   int same_t = -1, first = -1;
-  for (int i = 0; i < kNumTBForceConfigs; ++i) {
-    const TBConfig& k = kTBForceConfigs[i];
-    if (!k.fn[c->p.bc]) continue;
+  for (int i = 0; i < kNumTBExtraConfigs; ++i) {
+    const TBExtConfig& k = kTBExtraConfigs[i];
+    if (!k.fn[m][c->p.bc]) continue;
     if (c->g.ny < k.steps + 3 + k.pf) continue;  // the kernel wraps a load row once
     if (k.steps == t.steps && k.seg_rows == t.seg_rows && k.nt == t.nt && k.pf == t.pf) return i;
     if (k.steps == t.steps && same_t < 0) same_t = i;
@@ -950,36 +967,41 @@ static lbm_status step_ext(lbm_ctx* c, int64_t nsteps) {
   return launch_check("k_step_ext launch");
 }
 
-// Steps with a body load (no displacement state, no error norms), T per
-// launch with load variant fi: before each launch the row factors of its T
-// levels are formed; the last nsteps mod T steps run one per launch.
-static lbm_status step_force_blocked(lbm_ctx* c, int64_t nsteps, int fi) {
-  const TBConfig& k = kTBForceConfigs[fi];
+// Steps with a body load and/or the displacement state (no error norms), T
+// per launch with variant vi, extras m: before each launch with a load the
+// row factors of its T levels are formed; the last nsteps mod T steps run
+// one per launch.
+static lbm_status step_extra_blocked(lbm_ctx* c, int64_t nsteps, int vi, int m) {
+  const TBExtConfig& k = kTBExtraConfigs[vi];
+  const TBFn fn = k.fn[m][c->p.bc];
   const int T = k.steps, R = c->force_rank;
   const int chunk = WALL_CHUNK / T * T;
-  const TBConst sc =
-      tblock_const(c->g, (float)c->kK, (float)c->km, seg_rows_of(c, k, &c->tbf_slots[fi]), T);
+  const TBConst sc = tblock_const(c->g, (float)c->kK, (float)c->km,
+                                  seg_rows_of(c, T, k.seg_rows, k.pf, fn, &c->tbf_slots[vi * 3 + m]),
+                                  T);
   const int ntiles = sc.nstrips * sc.nseg;
-  const TBForce F{c->force_X, c->force_rows, R, (float)(c->p.dt / c->p.rho)};
+  const TBExtra F{c->force_X, c->force_rows, R, (float)(c->p.dt / c->p.rho), c->disp,
+                  0.5 * c->p.dt};
   const int64_t nrows = (int64_t)T * c->g.ny * TB_MAXR;
   const int64_t nb = nsteps / T * T;
   for (int64_t done = 0; done < nb;) {
-    const int m = (int)(nb - done < chunk ? nb - done : chunk);
-    eval_walls(c, c->nstep, m);
-    for (int j = 0; j < m; j += T) {
-      hipLaunchKernelGGL(k_force_rows, dim3((unsigned)((nrows + 255) / 256)), dim3(256), 0,
-                         c->stream, c->force_Y, c->force_T + (c->nstep + 1) * R, R, c->g.ny, T,
-                         c->force_rows);
-      hipLaunchKernelGGL(k.fn[c->p.bc], dim3((unsigned)((ntiles + 3) / 4)), dim3(256), 0,
-                         c->stream, (const float*)c->buf[c->cur], c->buf[c->cur ^ 1], c->g, sc,
+    const int n = (int)(nb - done < chunk ? nb - done : chunk);
+    eval_walls(c, c->nstep, n);
+    for (int j = 0; j < n; j += T) {
+      if (R > 0)
+        hipLaunchKernelGGL(k_force_rows, dim3((unsigned)((nrows + 255) / 256)), dim3(256), 0,
+                           c->stream, c->force_Y, c->force_T + (c->nstep + 1) * R, R, c->g.ny, T,
+                           c->force_rows);
+      hipLaunchKernelGGL(fn, dim3((unsigned)((ntiles + 3) / 4)), dim3(256), 0, c->stream,
+                         (const float*)c->buf[c->cur], c->buf[c->cur ^ 1], c->g, sc,
                          walls_from(c, j, true), F);
       c->cur ^= 1;
       c->nstep += T;
     }
-    done += m;
+    done += n;
   }
   if (nsteps > nb) return step_ext(c, nsteps - nb);
-  return launch_check("k_tblock launch (body load)");
+  return launch_check("k_tblock launch (load / displacement)");
 }
 
 lbm_status lbm_step(lbm_ctx* c, int64_t nsteps) {
@@ -994,9 +1016,10 @@ lbm_status lbm_step(lbm_ctx* c, int64_t nsteps) {
     return fail(LBM_E_STATE, "LBM_F_DISPLACEMENT: lbm_init_displacement before lbm_step");
   if (c->err_on && c->nstep + nsteps > c->ref_nsteps)
     return fail(LBM_E_ARG, "reference table too short for the requested steps");
-  if (c->force_rank > 0 && !c->disp && !c->err_on) {
-    const int fi = force_variant(c);
-    if (fi >= 0) return step_force_blocked(c, nsteps, fi);
+  if ((c->force_rank > 0 || c->disp) && !c->err_on) {
+    const int m = c->force_rank > 0 ? (c->disp ? 2 : 0) : 1;
+    const int vi = extra_variant(c, m);
+    if (vi >= 0) return step_extra_blocked(c, nsteps, vi, m);
   }
   if (c->force_rank > 0 || c->disp || c->err_on) return step_ext(c, nsteps);
   const Grid& g = c->g;
@@ -1215,6 +1238,17 @@ lbm_status lbm_tblock_config_info(int32_t index, int32_t* steps, int32_t* seg_ro
   if (nt) *nt = k.nt;
   if (pf) *pf = k.pf;
   return LBM_OK;
+}
+
+int32_t lbm_steps_per_launch(const lbm_ctx* c) {
+  if (!c) return -1;
+  if (c->err_on) return 1;
+  if (c->force_rank > 0 || c->disp) {
+    const int m = c->force_rank > 0 ? (c->disp ? 2 : 0) : 1;
+    const int vi = extra_variant(c, m);
+    return vi >= 0 ? kTBExtraConfigs[vi].steps : 1;
+  }
+  return c->tb_cfg >= 0 && tblock_fits(c->g) ? kTBConfigs[c->tb_cfg].steps : 1;
 }
 
 lbm_status lbm_get_tblock_config(const lbm_ctx* c, int32_t* index) {

@@ -66,12 +66,22 @@ struct WallSeq {
 // leaves every sum unchanged in round-to-nearest, so the result is bitwise
 // the single-step kernel's.
 constexpr int TB_MAXR = 16;  // largest rank the blocked kernel takes
-struct TBForce {
+struct TBExtra {
   const float* X;     // [rank][2][nx]
   const float* rows;  // [T][ny][TB_MAXR], written before the launch
   int rank;
   float scale;        // dt / rho
+  double* D;          // [2][ny][nx] FP64 displacement state (launches that keep it)
+  double half_dt;     // dt / 2
 };
+
+// FP64 displacement state D = u + dt/2 v_num of a blocked launch: every step
+// adds dt/2 v_num twice, u = D + dt/2 U, D = u + dt/2 U (the single-step
+// kernel's operations), so each row is updated at its T levels in order.  A
+// wave keeps the rows it owns in an LDS ring of TB_DSLOTS rows (16 B per
+// lane: both components), requested two sub-iterations before their first
+// level, staged one before, and written back after their last level.
+constexpr int TB_DSLOTS = 16;
 struct LaneLoad {
   float x[2][TB_MAXR];
 };
@@ -203,7 +213,8 @@ template <int BC, bool EDGE, bool FORCE>
 __device__ __forceinline__ void level_update(const float below[NP], const float at[NP],
                                     const float above[NP], int x, int y, int nx, int ny,
                                     float kK, float km, const Wall& w, const LaneLoad& ll,
-                                    const float (&yt)[TB_MAXR], float scale, float out[NP]) {
+                                    const float (&yt)[TB_MAXR], float scale, float out[NP],
+                                    float (&Uo)[2]) {
   // the load terms first: they do not depend on the populations
   float bx = 0.f, by = 0.f;
   if constexpr (FORCE) load_terms(ll, yt, scale, bx, by);
@@ -234,6 +245,8 @@ __device__ __forceinline__ void level_update(const float below[NP], const float 
       U[0] += 0.5f * bx;
       U[1] += 0.5f * by;
     }
+    Uo[0] = U[0];
+    Uo[1] = U[1];
     float X[NC], Y[NC];
     X[0] = fmaf(kK, U[2], km * U[3]);
     X[1] = km * U[4];
@@ -290,6 +303,8 @@ __device__ __forceinline__ void level_update(const float below[NP], const float 
     U[0] += 0.5f * bx;
     U[1] += 0.5f * by;
   }
+  Uo[0] = U[0];
+  Uo[1] = U[1];
   collide_with(kK, km, U, f);
 #pragma unroll
   for (int q = 0; q < NQ; ++q)
@@ -344,8 +359,9 @@ template <int BC, bool EDGE, bool FORCE>
 __device__ __forceinline__ void row_update(const float below[NP], const float at[NP],
                                            const float above[NP], int xw, int y, int level,
                                            const Grid& g, const TBConst& sc, const WallSeq& ws,
-                                           const TBForce& F, const LaneLoad& ll,
-                                           const float (&yt)[TB_MAXR], float out[NP]) {
+                                           const TBExtra& F, const LaneLoad& ll,
+                                           const float (&yt)[TB_MAXR], float out[NP],
+                                           float (&Uo)[2]) {
   const int yc = y < 0 ? 0 : (y >= g.ny ? g.ny - 1 : y);
   Wall w;
   w.L = ws.L;
@@ -354,7 +370,7 @@ __device__ __forceinline__ void row_update(const float below[NP], const float at
   w.rank = 0;
   w.Trow = nullptr;
   level_update<BC, EDGE, FORCE>(below, at, above, xw, yc, g.nx, g.ny, sc.kK, sc.km, w, ll, yt,
-                                F.scale, out);
+                                F.scale, out, Uo);
 }
 
 // Row factors through LDS.  A sub-iteration j needs the factors of its T
@@ -368,7 +384,7 @@ __device__ __forceinline__ void row_update(const float below[NP], const float at
 // the host takes this path only for ny >= T + ring length); on a Dirichlet
 // lattice their loads are never used (clamped).
 template <int BC, int T>
-__device__ __forceinline__ void fac_request(const TBForce& F, const Grid& g, int y0, int j,
+__device__ __forceinline__ void fac_request(const TBExtra& F, const Grid& g, int y0, int j,
                                             float (&v)[2]) {
   const int lane = threadIdx.x & 63;
 #pragma unroll
@@ -408,14 +424,82 @@ __device__ __forceinline__ void fac_read(const float* slot, int level, float (&y
   }
 }
 
+// displacement rows: request (global loads of this lane's read column),
+// stage into the LDS ring, update at one level, write back (lanes that own
+// their column; the others get an offset beyond the row's range)
+__device__ __forceinline__ void d_request(const TBExtra& F, const Grid& g, const Strip& st, int y,
+                                          double (&v)[2]) {
+  const int xc = st.xr4 >> 2;
+#pragma unroll
+  for (int c = 0; c < 2; ++c) v[c] = F.D[((int64_t)c * g.ny + y) * g.nx + xc];
+}
+
+__device__ __forceinline__ double* d_slot(double* dring, int y) {
+  return dring + ((y & (TB_DSLOTS - 1)) * TB_LANES + (threadIdx.x & 63)) * 2;
+}
+
+__device__ __forceinline__ void d_stage(double* dring, int y, const double (&v)[2]) {
+  double* p = d_slot(dring, y);
+  p[0] = v[0];
+  p[1] = v[1];
+  __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ void d_update(double (&d)[2], const float (&U)[2], double h) {
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    const double u = d[c] + h * (double)U[c];
+    d[c] = u + h * (double)U[c];
+  }
+}
+
+__device__ __forceinline__ void d_store(const TBExtra& F, const Grid& g, int doff, int y,
+                                        const double (&d)[2]) {
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    double* rp = F.D + ((int64_t)c * g.ny + y) * g.nx;
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)rp, (short)0, (int)(g.nx * 8), TB_RSRC_WORD3);
+    const uint64_t bits = (uint64_t)__double_as_longlong(d[c]);
+    __builtin_amdgcn_raw_buffer_store_b32((uint32_t)bits, rs, doff, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b32((uint32_t)(bits >> 32), rs, doff, 4, 0);
+  }
+}
+
+// One level update of a row inside a sub-iteration, with the displacement
+// rows when the launch keeps them (rows the wave owns: y0 <= y < y1)
+template <int BC, bool EDGE, bool FORCE, bool DISP>
+__device__ __forceinline__ void level_step(const float below[NP], const float at[NP],
+                                           const float above[NP], int xw, int y, int level,
+                                           const Grid& g, const TBConst& sc, const WallSeq& ws,
+                                           const TBExtra& F, const LaneLoad& ll,
+                                           const float (&yt)[TB_MAXR], float out[NP],
+                                           double* dring, int y0, int y1, int doff, bool last) {
+  float Uo[2];
+  if constexpr (DISP) {
+    if (y >= y0 && y < y1) {
+      double* p = d_slot(dring, y);
+      double d[2] = {p[0], p[1]};
+      row_update<BC, EDGE, FORCE>(below, at, above, xw, y, level, g, sc, ws, F, ll, yt, out, Uo);
+      d_update(d, Uo, F.half_dt);
+      p[0] = d[0];
+      p[1] = d[1];
+      if (last) d_store(F, g, doff, y, d);
+      return;
+    }
+  }
+  row_update<BC, EDGE, FORCE>(below, at, above, xw, y, level, g, sc, ws, F, ll, yt, out, Uo);
+}
+
 // One sub-iteration i of the sweep (PRE: a pipeline-filling sub-iteration
 // before the first output row, I = i then; slot = i mod NB, known at compile
 // time in both cases).
-template <int BC, int NT, int PF, int T, bool EDGE, bool FORCE, bool PRE>
+template <int BC, int NT, int PF, int T, bool EDGE, bool FORCE, bool DISP, bool PRE>
 __device__ __forceinline__ void sub_iteration(const float* __restrict__ src, float* __restrict__ dst,
                                      const Grid& g, const TBConst& sc, const Strip& st,
-                                     const WallSeq& ws, const TBForce& F, const LaneLoad& ll,
-                                     float* fac, float (&fv)[3 + PF][2],
+                                     const WallSeq& ws, const TBExtra& F, const LaneLoad& ll,
+                                     float* fac, float (&fv)[3 + PF][2], double* dring,
+                                     double (&dv)[3 + PF][2], int doff,
                                      int pitch4, RowCursor& cur, int y0,
                                      int y1, int i, int I, int slot, float (&lv0)[3 + PF][NP],
                                      float (&lv)[T - 1][3 + PF][NP]) {
@@ -423,6 +507,11 @@ __device__ __forceinline__ void sub_iteration(const float* __restrict__ src, flo
   constexpr int FS = TB_MAXR * T;  // floats of one LDS factor slot
   const int s = slot, s1 = (slot + NB - 1) % NB, s2 = (slot + NB - 2) % NB;
   if constexpr (FORCE) fac_request<BC, T>(F, g, y0, i + 2, fv[(s + 2) % NB]);
+  // displacement row whose first level comes two sub-iterations on
+  if constexpr (DISP) {
+    const int yq = y0 + i + 2 + T - 1;
+    if (yq >= y0 && yq < y1) d_request(F, g, st, yq, dv[(s + 2) % NB]);
+  }
   // prefetch level-0 row y0 + i + T + PF (the cursor's row) into slot
   // (i + PF) mod NB, which held the row of sub-iteration i + PF - NB = i - 3
   // (no longer read).  Past the last needed row it re-reads that row (a
@@ -442,22 +531,27 @@ __device__ __forceinline__ void sub_iteration(const float* __restrict__ src, flo
     fac_read(fac + s * FS, 1, yt[1]);
     fac_read(fac + s * FS, 2, yt[0]);
   }
+  if constexpr (DISP) {
+    const int yq = y0 + i + 1 + T - 1;
+    if (yq >= y0 && yq < y1) d_stage(dring, yq, dv[(s + 1) % NB]);
+  }
   if (!PRE || I >= -2 * (T - 1))
-    row_update<BC, EDGE, FORCE>(lv0[s2], lv0[s1], lv0[s], st.xw, y0 + i + T - 1, 1, g, sc, ws, F,
-                                ll, yt[1], lv[0][s]);
+    level_step<BC, EDGE, FORCE, DISP>(lv0[s2], lv0[s1], lv0[s], st.xw, y0 + i + T - 1, 1, g, sc,
+                                      ws, F, ll, yt[1], lv[0][s], dring, y0, y1, doff, false);
 #pragma unroll
   for (int l = 2; l < T; ++l) {
     if constexpr (FORCE) fac_read(fac + s * FS, l + 1, yt[(l + 1) & 1]);
     if (PRE && I < -2 * (T - l)) continue;
-    row_update<BC, EDGE, FORCE>(lv[l - 2][s2], lv[l - 2][s1], lv[l - 2][s], st.xw,
-                                y0 + i + T - l, l, g, sc, ws, F, ll, yt[l & 1], lv[l - 1][s]);
+    level_step<BC, EDGE, FORCE, DISP>(lv[l - 2][s2], lv[l - 2][s1], lv[l - 2][s], st.xw,
+                                      y0 + i + T - l, l, g, sc, ws, F, ll, yt[l & 1],
+                                      lv[l - 1][s], dring, y0, y1, doff, false);
   }
   if (!PRE) {
     // level T, output row y0 + i
     float o[NP];
     const int rr = y0 + i;
-    row_update<BC, EDGE, FORCE>(lv[T - 2][s2], lv[T - 2][s1], lv[T - 2][s], st.xw, rr, T, g, sc,
-                                ws, F, ll, yt[T & 1], o);
+    level_step<BC, EDGE, FORCE, DISP>(lv[T - 2][s2], lv[T - 2][s1], lv[T - 2][s], st.xw, rr, T,
+                                      g, sc, ws, F, ll, yt[T & 1], o, dring, y0, y1, doff, true);
     const int off = rr < y1 ? st.xs4 : TB_DROP;
     const int yo = rr < g.ny ? rr : g.ny - 1;
     char* rp = (char*)dst + (uint32_t)(yo * pitch4);
@@ -472,15 +566,20 @@ __device__ __forceinline__ void sub_iteration(const float* __restrict__ src, flo
 }
 
 // The sweep of one wave over output rows y0 .. y1 - 1 (EDGE: see level_update).
-template <int BC, int NT, int PF, int T, bool EDGE, bool FORCE>
+template <int BC, int NT, int PF, int T, bool EDGE, bool FORCE, bool DISP>
 __device__ __forceinline__ void tblock_sweep(const float* __restrict__ src,
                                              float* __restrict__ dst, const Grid& g,
                                              const TBConst& sc, const Strip& st,
-                                             const WallSeq& ws, const TBForce& F,
-                                             const LaneLoad& ll, float* fac, int pitch4,
-                                             RowCursor& cur, int y0, int y1) {
+                                             const WallSeq& ws, const TBExtra& F,
+                                             const LaneLoad& ll, float* fac, double* dring,
+                                             int doff, int pitch4, RowCursor& cur, int y0,
+                                             int y1) {
   constexpr int NB = 3 + PF;
   const int ny = g.ny;
+  // displacement rows requested two sub-iterations ahead (dv), staged one
+  // ahead; the first row with a level in the pipeline fill is y0 at
+  // sub-iteration 1 - T, requested in the fill itself
+  double dv[NB][2];
   // load factors: requested two sub-iterations ahead (fv), staged in LDS one
   // ahead; the first sub-iteration's are staged here
   float fv[NB][2];
@@ -503,9 +602,9 @@ __device__ __forceinline__ void tblock_sweep(const float* __restrict__ src,
 #pragma unroll
   for (int p = 0; p < 2 * T; ++p) {
     const int I = p - 2 * T;
-    sub_iteration<BC, NT, PF, T, EDGE, FORCE, true>(src, dst, g, sc, st, ws, F, ll, fac, fv,
-                                                    pitch4, cur, y0, y1, I, I, (I % NB + NB) % NB,
-                                                    lv0, lv);
+    sub_iteration<BC, NT, PF, T, EDGE, FORCE, DISP, true>(src, dst, g, sc, st, ws, F, ll, fac, fv,
+                                                          dring, dv, doff, pitch4, cur, y0, y1, I,
+                                                          I, (I % NB + NB) % NB, lv0, lv);
   }
   // The sweep runs in whole rings of NB rows; rows past the segment end are
   // computed from valid (wrapped or clamped) rows and their stores dropped.
@@ -514,18 +613,18 @@ __device__ __forceinline__ void tblock_sweep(const float* __restrict__ src,
   for (int i0 = 0; i0 < y1 - y0; i0 += NB) {
 #pragma unroll
     for (int j = 0; j < NB; ++j)
-      sub_iteration<BC, NT, PF, T, EDGE, FORCE, false>(src, dst, g, sc, st, ws, F, ll, fac, fv,
-                                                       pitch4, cur, y0, y1, i0 + j, 0, j, lv0,
-                                                       lv);
+      sub_iteration<BC, NT, PF, T, EDGE, FORCE, DISP, false>(src, dst, g, sc, st, ws, F, ll, fac,
+                                                             fv, dring, dv, doff, pitch4, cur, y0,
+                                                             y1, i0 + j, 0, j, lv0, lv);
   }
 }
 
 // One wave's work: strip `strip`, output rows of segment `seg`.
-template <int BC, int NT, int PF, int T, bool FORCE = false>
+template <int BC, int NT, int PF, int T, bool FORCE = false, bool DISP = false>
 __device__ __forceinline__ void tblock_wave(const float* __restrict__ src, float* __restrict__ dst,
                                    const Grid& g, const TBConst& sc, const WallSeq& ws,
-                                   int strip, int seg, const TBForce& F = TBForce{},
-                                   float* fac = nullptr) {
+                                   int strip, int seg, const TBExtra& F = TBExtra{},
+                                   float* fac = nullptr, double* dring = nullptr) {
   static_assert(T >= 2 && T <= 8, "2 to 8 time levels per launch");
   constexpr int VALID = TB_LANES - 2 * T;  // stored columns per strip
   const int lane = threadIdx.x & 63;
@@ -544,6 +643,9 @@ __device__ __forceinline__ void tblock_wave(const float* __restrict__ src, float
   cur.y = y0 - T;
   cur.r = row_index<BC>(cur.y, ny);
   cur.last = y1 - 1 + T;
+  // byte offset of this lane's column in a displacement row (doubles), or
+  // beyond the row for lanes that do not own their column
+  const int doff = store ? (int)((uint32_t)x * 8u) : TB_DROP;
   // this lane's load coefficients (the column it reads)
   LaneLoad ll;
   if constexpr (FORCE) {
@@ -557,19 +659,19 @@ __device__ __forceinline__ void tblock_wave(const float* __restrict__ src, float
     // a Dirichlet wave meets the side walls only if its columns include one
     const int x_first = strip * VALID - T;
     if (x_first <= 0 || x_first + TB_LANES - 1 >= nx - 1) {
-      tblock_sweep<BC, NT, PF, T, true, FORCE>(src, dst, g, sc, st, ws, F, ll, fac, pitch4, cur,
-                                               y0, y1);
+      tblock_sweep<BC, NT, PF, T, true, FORCE, DISP>(src, dst, g, sc, st, ws, F, ll, fac, dring,
+                                                     doff, pitch4, cur, y0, y1);
       return;
     }
   }
-  tblock_sweep<BC, NT, PF, T, false, FORCE>(src, dst, g, sc, st, ws, F, ll, fac, pitch4, cur, y0,
-                                            y1);
+  tblock_sweep<BC, NT, PF, T, false, FORCE, DISP>(src, dst, g, sc, st, ws, F, ll, fac, dring, doff,
+                                                  pitch4, cur, y0, y1);
 }
 
-template <int BC, int NT, int PF, int T, bool FORCE = false>
+template <int BC, int NT, int PF, int T, bool FORCE = false, bool DISP = false>
 __global__ __launch_bounds__(256) void k_tblock(const float* __restrict__ src,
                                                 float* __restrict__ dst, Grid g, TBConst sc,
-                                                WallSeq ws, TBForce F) {
+                                                WallSeq ws, TBExtra F) {
   const int ntiles = sc.nstrips * sc.nseg;
   const int nwg = (ntiles + 3) / 4;
   // wave index: uniform by construction, stated to the compiler
@@ -578,8 +680,11 @@ __global__ __launch_bounds__(256) void k_tblock(const float* __restrict__ src,
   // per wave: one slot of load factors per ring row (unused without a load)
   __shared__ __attribute__((aligned(16))) float fac[FORCE ? 4 * (3 + PF) * TB_MAXR * T : 4];
   float* mine = FORCE ? fac + (threadIdx.x >> 6) * (3 + PF) * TB_MAXR * T : nullptr;
-  tblock_wave<BC, NT, PF, T, FORCE>(src, dst, g, sc, ws, wid % sc.nstrips, wid / sc.nstrips, F,
-                                    mine);
+  // per wave: the displacement rows in flight (unused without them)
+  __shared__ __attribute__((aligned(16))) double dring[DISP ? 4 * TB_DSLOTS * TB_LANES * 2 : 2];
+  double* dmine = DISP ? dring + (threadIdx.x >> 6) * TB_DSLOTS * TB_LANES * 2 : nullptr;
+  tblock_wave<BC, NT, PF, T, FORCE, DISP>(src, dst, g, sc, ws, wid % sc.nstrips,
+                                          wid / sc.nstrips, F, mine, dmine);
 }
 
 inline TBConst tblock_const(const Grid& g, float kK, float km, int seg_rows, int T) {

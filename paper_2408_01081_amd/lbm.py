@@ -239,6 +239,11 @@ class Lattice:
     def tblock_config(self, index):
         check(self.L.lbm_set_tblock_config(self.ctx, int(index)))
 
+    @property
+    def steps_per_launch(self):
+        """Time steps per launch lbm_step uses for this lattice as configured."""
+        return int(self.L.lbm_steps_per_launch(self.ctx))
+
     def tblock_configs(self):
         out = []
         for i in range(self.L.lbm_tblock_config_count()):

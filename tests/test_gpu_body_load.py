@@ -238,3 +238,56 @@ def test_blocked_steps_with_load_match_oracle(bc):
     err = oracle.rel_l2(lat.moments_U().double().cpu().numpy(), sim.U())
     print("blocked with load, bc=%d: rel-L2 %.3e" % (bc, err))
     assert err < 1e-5
+
+
+@gpu
+@pytest.mark.parametrize("bc,N,ny", [(synth.PERIODIC, 130, 64), (synth.DIRICHLET, 300, 70),
+                                     (synth.DIRICHLET, 61, 37)])
+@pytest.mark.parametrize("R", [0, 5, 16])
+def test_blocked_steps_with_displacement_bitwise_equal_single_steps(bc, N, ny, R):
+    # with the FP64 displacement state (and a load of rank <= 16, or none)
+    # the blocked kernel keeps the rows a wave owns in LDS and adds dt/2 v
+    # twice per level in the single-step order: populations and displacement
+    # bit for bit those of one launch per step, for every launch variant
+    torch = _torch()
+    from paper_2408_01081_amd.lbm import Lattice
+    prob = synth.plane_wave_problem(N, ny, bc, seed=29, kmax=3)
+    v0, sb0 = prob.initial_fields()
+    nsteps = 37
+    g = np.random.default_rng(100 + R)
+    u0 = torch.from_numpy(g.standard_normal((2, ny, N)))
+    W, T = prob.wall_table(nsteps)
+    lat = Lattice(prob.nx, prob.ny, prob.dx, prob.dt, prob.lam, prob.mu, prob.rho, prob.bc,
+                  displacement=True)
+    if R:
+        lat.set_body_force(*(torch.from_numpy(a) for a in _random_load(g, R, N, ny, nsteps)))
+    ref = None
+    for cfg in [-1] + [c["index"] for c in lat.tblock_configs()]:
+        lat.init(torch.from_numpy(v0), torch.from_numpy(sb0))
+        lat.init_displacement(u0)
+        if bc == synth.DIRICHLET:
+            lat.set_wall_velocity(torch.from_numpy(W), torch.from_numpy(T))
+        lat.tblock_config = cfg
+        lat.step(11).step(nsteps - 11)
+        got = (lat.populations(), lat.displacement())
+        if ref is None:
+            ref = got
+            assert all(torch.isfinite(t).all() for t in got)
+        else:
+            for a, b in zip(got, ref):
+                assert torch.equal(a.view(torch.int32), b.view(torch.int32)), cfg
+
+
+@gpu
+@pytest.mark.parametrize("bc", [synth.PERIODIC, synth.DIRICHLET])
+def test_blocked_steps_with_load_and_displacement_match_oracle(bc):
+    mat = synth.Material.from_lame(1.0, 0.5, 1.0)
+    prob = _mms(64, bc, synth.standing_mms_solution, mat,
+                lambda dx: synth.dt_at_cfl_fraction(dx, mat, 0.5), ny=48)
+    lat, sim, s = _run(prob, 300, tblock=40 if bc == synth.PERIODIC else 19)
+    lat.step(296).step(4)
+    sim.advance(300)
+    err = oracle.rel_l2(lat.moments_U().double().cpu().numpy(), sim.U())
+    uerr = oracle.rel_l2(lat.displacement().double().cpu().numpy(), sim.displacement())
+    print("blocked with load and displacement, bc=%d: rel-L2 U %.3e u %.3e" % (bc, err, uerr))
+    assert err < 1e-5 and uerr < 1e-5
