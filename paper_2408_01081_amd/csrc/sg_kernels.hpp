@@ -485,35 +485,42 @@ __global__ __launch_bounds__(256) void k_wgradt(const float* __restrict__ G,
 #pragma unroll
   for (int t = 0; t < 9; ++t) acc[t] = (f32x4){0.f, 0.f, 0.f, 0.f};
 
-  for (int64_t blk = blockIdx.x; blk < nblocks; blk += gridDim.x) {
+  // A block's operands pass through registers: the next block's loads are
+  // issued before this block's matrix-core phase and written to LDS after
+  // it, so their latency hides behind the products (one workgroup per CU).
+  // Input: halo rows hr = 0 .. RB + 1 (image y - 1 + hr), halo columns
+  // hc = 0 .. PW + 1 (image x0 - 1 + hc), 4 x 8 channels per element, at
+  // most 4 elements per thread ((RB + 2) (PW + 2) 4 <= 1024 for 64 % W == 0
+  // or W % 64 == 0); each element is tap (r - 1, d - 1) of the pixels at row
+  // hr - r, column hc - d.
+  const int HC = PW + 2;
+  const int NIT = (RB + 2) * HC * 4;
+  constexpr int MAXIT = 4;
+  float gr[8], xr[MAXIT][8];
+  auto fetch = [&](int64_t blk) {
     const int b = (int)(blk / ((int64_t)HB * tx));
     const int rem = (int)(blk - (int64_t)b * HB * tx);
     const int y = (rem / tx) * RB, x0 = (rem - (rem / tx) * tx) * 64;
-    __syncthreads();  // the previous block's fragments have been read
     {
       // gradient: thread t -> pixel t / 4, output channels 8 (t mod 4) ...
       const int p = threadIdx.x >> 2, q = threadIdx.x & 3;
       const int64_t go = (((int64_t)b * H + y + p / PW) * W + x0 + p % PW) * Cout + o0 + 8 * q;
       const float4 u0 = *reinterpret_cast<const float4*>(G + go);
       const float4 u1 = *reinterpret_cast<const float4*>(G + go + 4);
-      float a[8] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w};
+      gr[0] = u0.x; gr[1] = u0.y; gr[2] = u0.z; gr[3] = u0.w;
+      gr[4] = u1.x; gr[5] = u1.y; gr[6] = u1.z; gr[7] = u1.w;
       if (gscale) {
         const float* sc = gscale + (int64_t)b * Cout + o0 + 8 * q;
 #pragma unroll
-        for (int j = 0; j < 8; ++j) a[j] *= sc[j];
-      }
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const unsigned short h = bf16_bits(a[j]);
-        gT[(8 * q + j) * RS + p] = h;
-        if (SPLIT == 3) gT[GT + (8 * q + j) * RS + p] = bf16_bits(a[j] - bf16_value(h));
+        for (int j = 0; j < 8; ++j) gr[j] *= sc[j];
       }
     }
-    // input: halo rows hr = 0 .. RB + 1 (image y - 1 + hr), halo columns
-    // hc = 0 .. PW + 1 (image x0 - 1 + hc), 4 x 8 channels; each element is
-    // tap (r - 1, d - 1) of the pixels at row hr - r, column hc - d
-    const int HC = PW + 2;
-    for (int it = threadIdx.x; it < (RB + 2) * HC * 4; it += 256) {
+#pragma unroll
+    for (int k = 0; k < MAXIT; ++k) {
+      const int it = threadIdx.x + 256 * k;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) xr[k][j] = 0.f;
+      if (it >= NIT) continue;
       const int q = it & 3, hc = (it >> 2) % HC, hr = (it >> 2) / HC;
       int ys = y + hr - 1, xs = x0 + hc - 1;
       bool valid = true;
@@ -523,24 +530,40 @@ __global__ __launch_bounds__(256) void k_wgradt(const float* __restrict__ G,
       } else {
         valid = ys >= 0 && ys < H && xs >= 0 && xs < W;
       }
-      float a[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
       if (valid) {
         const int64_t xo = (((int64_t)b * H + ys) * W + xs) * Cin + i0 + 8 * q;
         const float4 u0 = *reinterpret_cast<const float4*>(X + xo);
         const float4 u1 = *reinterpret_cast<const float4*>(X + xo + 4);
-        a[0] = u0.x; a[1] = u0.y; a[2] = u0.z; a[3] = u0.w;
-        a[4] = u1.x; a[5] = u1.y; a[6] = u1.z; a[7] = u1.w;
+        xr[k][0] = u0.x; xr[k][1] = u0.y; xr[k][2] = u0.z; xr[k][3] = u0.w;
+        xr[k][4] = u1.x; xr[k][5] = u1.y; xr[k][6] = u1.z; xr[k][7] = u1.w;
         if (xscale) {
           const float* sc = xscale + (int64_t)b * Cin + i0 + 8 * q;
 #pragma unroll
-          for (int j = 0; j < 8; ++j) a[j] *= sc[j];
+          for (int j = 0; j < 8; ++j) xr[k][j] *= sc[j];
         }
       }
+    }
+  };
+  auto stage = [&]() {
+    {
+      const int p = threadIdx.x >> 2, q = threadIdx.x & 3;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const unsigned short h = bf16_bits(gr[j]);
+        gT[(8 * q + j) * RS + p] = h;
+        if (SPLIT == 3) gT[GT + (8 * q + j) * RS + p] = bf16_bits(gr[j] - bf16_value(h));
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < MAXIT; ++k) {
+      const int it = threadIdx.x + 256 * k;
+      if (it >= NIT) continue;
+      const int q = it & 3, hc = (it >> 2) % HC, hr = (it >> 2) / HC;
       unsigned short hb[8], lb[8];
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
-        hb[j] = bf16_bits(a[j]);
-        lb[j] = bf16_bits(a[j] - bf16_value(hb[j]));
+        hb[j] = bf16_bits(xr[k][j]);
+        lb[j] = bf16_bits(xr[k][j] - bf16_value(hb[j]));
       }
 #pragma unroll
       for (int r = 0; r < 3; ++r) {
@@ -560,6 +583,13 @@ __global__ __launch_bounds__(256) void k_wgradt(const float* __restrict__ G,
         }
       }
     }
+  };
+
+  if ((int64_t)blockIdx.x < nblocks) fetch(blockIdx.x);
+  for (int64_t blk = blockIdx.x; blk < nblocks; blk += gridDim.x) {
+    __syncthreads();  // the previous block's fragments have been read
+    stage();
+    if (blk + gridDim.x < nblocks) fetch(blk + gridDim.x);
     __syncthreads();
 #pragma unroll
     for (int ks = 0; ks < 2; ++ks) {
