@@ -27,8 +27,11 @@
 // resource's range, which the hardware drops: stores need no branch, so the
 // wait counts stay exact.
 // Walls (Dirichlet) are applied at every level with the velocities of that
-// level's step.  Every node update is collide() on the same inputs as the
-// single-step kernel, so the result is bitwise identical to T launches of it.
+// level's step.  Every node update is the single-step kernel's moment and
+// collision on the same inputs, so the result is bitwise identical to T
+// launches of it.  Optional extras per launch: a separable body load (row
+// factors staged through LDS) and the FP64 displacement state (the rows a
+// wave owns kept in LDS), each added in the single-step kernel's order.
 #pragma once
 
 #include <hip/hip_runtime.h>
