@@ -502,8 +502,10 @@ __global__ __launch_bounds__(256) void k_wgradt(const float* __restrict__ G,
     const int rem = (int)(blk - (int64_t)b * HB * tx);
     const int y = (rem / tx) * RB, x0 = (rem - (rem / tx) * tx) * 64;
     {
-      // gradient: thread t -> pixel t / 4, output channels 8 (t mod 4) ...
-      const int p = threadIdx.x >> 2, q = threadIdx.x & 3;
+      // gradient: thread t -> pixel t mod 64, output channels 8 (t / 64) ...
+      // (a wave writes one channel row at 64 consecutive pixels: no two
+      // lanes on one LDS bank but the two halves of a dword)
+      const int p = threadIdx.x & 63, q = threadIdx.x >> 6;
       const int64_t go = (((int64_t)b * H + y + p / PW) * W + x0 + p % PW) * Cout + o0 + 8 * q;
       const float4 u0 = *reinterpret_cast<const float4*>(G + go);
       const float4 u1 = *reinterpret_cast<const float4*>(G + go + 4);
@@ -521,7 +523,8 @@ __global__ __launch_bounds__(256) void k_wgradt(const float* __restrict__ G,
 #pragma unroll
       for (int j = 0; j < 8; ++j) xr[k][j] = 0.f;
       if (it >= NIT) continue;
-      const int q = it & 3, hc = (it >> 2) % HC, hr = (it >> 2) / HC;
+      // consecutive lanes take consecutive halo columns (see the gradient)
+      const int hc = it % HC, hr = (it / HC) % (RB + 2), q = it / (HC * (RB + 2));
       int ys = y + hr - 1, xs = x0 + hc - 1;
       bool valid = true;
       if (circular) {
@@ -546,7 +549,7 @@ __global__ __launch_bounds__(256) void k_wgradt(const float* __restrict__ G,
   };
   auto stage = [&]() {
     {
-      const int p = threadIdx.x >> 2, q = threadIdx.x & 3;
+      const int p = threadIdx.x & 63, q = threadIdx.x >> 6;
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
         const unsigned short h = bf16_bits(gr[j]);
@@ -558,7 +561,7 @@ __global__ __launch_bounds__(256) void k_wgradt(const float* __restrict__ G,
     for (int k = 0; k < MAXIT; ++k) {
       const int it = threadIdx.x + 256 * k;
       if (it >= NIT) continue;
-      const int q = it & 3, hc = (it >> 2) % HC, hr = (it >> 2) / HC;
+      const int hc = it % HC, hr = (it / HC) % (RB + 2), q = it / (HC * (RB + 2));
       unsigned short hb[8], lb[8];
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
