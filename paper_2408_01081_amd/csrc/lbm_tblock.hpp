@@ -279,15 +279,25 @@ __device__ __forceinline__ void level_update(const float below[NP], const float 
   }
   if (BC == LBM_DIRICHLET) {
     float fb[NC], va, vb;
+    // the side walls' velocities of this row are the same in every lane:
+    // read them through the scalar cache before the lanes diverge (a vector
+    // load inside the branch would wait for every prefetched row as well)
+    float la = 0.f, lb = 0.f, ra = 0.f, rb = 0.f;
+    if (w.V) {
+      typedef const __attribute__((address_space(4))) float* ConstV;
+      const ConstV v = (ConstV)w.V;
+      la = v[2 * y];
+      lb = v[2 * y + 1];
+      ra = v[2 * (ny + y)];
+      rb = v[2 * (ny + y) + 1];
+    }
     if (x == 0) {
       for (int c = 0; c < NC; ++c) fb[c] = at[2 * NC + c];
-      wall_velocity(w, y, va, vb);
-      wall_rule(1, 0, kK, km, va, vb, fb, f[0]);
+      wall_rule(1, 0, kK, km, la, lb, fb, f[0]);
     }
     if (x == nx - 1) {
       for (int c = 0; c < NC; ++c) fb[c] = at[0 * NC + c];
-      wall_velocity(w, ny + y, va, vb);
-      wall_rule(-1, 0, kK, km, va, vb, fb, f[2]);
+      wall_rule(-1, 0, kK, km, ra, rb, fb, f[2]);
     }
     if (y == 0) {
       for (int c = 0; c < NC; ++c) fb[c] = at[3 * NC + c];
