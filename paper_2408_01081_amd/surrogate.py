@@ -159,9 +159,35 @@ def forward_flops(B, H, W):
 
 def main():
     """Time the forward pass: python -m paper_2408_01081_amd.surrogate B H W
-    [conv_mode] [weights.npy] (median of 20 calls after 3 warm-up calls)."""
+    [conv_mode] [weights.npy] (median of 20 calls after 3 warm-up calls), or
+    a training step (forward + backward + Adam, learning rate 1e-6):
+    python -m paper_2408_01081_amd.surrogate train B H W (mean of 10 steps
+    after 3 warm-up steps)."""
     import os
     import sys
+    if sys.argv[1] == "train":
+        B, H, W = (int(a) for a in sys.argv[2:5])
+        net = Surrogate(B, H, W, split=3, train=True)
+        net.set_params(np.load(os.path.join(os.path.dirname(os.path.abspath(__file__)),
+                                            "weights", "surrogate.npy"), allow_pickle=False))
+        g = torch.Generator(device=net.device).manual_seed(0)
+        x = torch.randn(B, 8, H, W, device=net.device, generator=g)
+        x[:, 5], x[:, 6], x[:, 7] = 0.5, 1.0, 1.0
+        y = x[:, :5] + 0.01 * torch.randn(B, 5, H, W, device=net.device, generator=g)
+        for _ in range(3):
+            net.train_step(x, y, lr=1e-6, want_loss=False)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(10):
+            net.train_step(x, y, lr=1e-6, want_loss=False)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 10
+        fl = 3 * forward_flops(B, H, W)
+        print("train step B=%d %dx%d: %.4f ms, %.1f TFLOP/s counted as 3 forward passes "
+              "(%.1f%% of the 2.5 PFLOP/s BF16 peak with the hi/lo split)"
+              % (B, H, W, ms, fl / ms / 1e9, 3 * fl / ms / 1e9 / 25.0), flush=True)
+        return
     B, H, W = (int(a) for a in sys.argv[1:4])
     mode = int(sys.argv[4]) if len(sys.argv) > 4 else 0
     path = sys.argv[5] if len(sys.argv) > 5 else os.path.join(

@@ -291,3 +291,27 @@ def test_blocked_steps_with_load_and_displacement_match_oracle(bc):
     uerr = oracle.rel_l2(lat.displacement().double().cpu().numpy(), sim.displacement())
     print("blocked with load and displacement, bc=%d: rel-L2 U %.3e u %.3e" % (bc, err, uerr))
     assert err < 1e-5 and uerr < 1e-5
+
+
+@gpu
+def test_steps_per_launch_reports_the_path():
+    torch = _torch()
+    from paper_2408_01081_amd.lbm import Lattice
+    prob = synth.plane_wave_problem(256, 128, synth.PERIODIC, seed=31, kmax=2)
+    g = np.random.default_rng(5)
+    lat = Lattice(prob.nx, prob.ny, prob.dx, prob.dt, prob.lam, prob.mu, prob.rho, prob.bc,
+                  displacement=True)
+    idx = {(c["steps"], c["seg_rows"], c["nontemporal"], c["prefetch"]): c["index"]
+           for c in lat.tblock_configs()}
+    assert lat.steps_per_launch == 1                    # no blocked variant selected
+    lat.tblock_config = idx[(8, 0, 0, 2)]
+    assert lat.steps_per_launch == 6                    # displacement state: the T = 6 kernels
+    lat.set_body_force(*(torch.from_numpy(a) for a in _random_load(g, 16, 256, 128, 10)))
+    assert lat.steps_per_launch == 6
+    lat.set_body_force(*(torch.from_numpy(a) for a in _random_load(g, 17, 256, 128, 10)))
+    assert lat.steps_per_launch == 1                    # rank above 16: one launch per step
+    lat2 = Lattice(prob.nx, prob.ny, prob.dx, prob.dt, prob.lam, prob.mu, prob.rho, prob.bc)
+    lat2.tblock_config = idx[(8, 0, 0, 2)]
+    assert lat2.steps_per_launch == 8
+    lat2.set_body_force(*(torch.from_numpy(a) for a in _random_load(g, 16, 256, 128, 10)))
+    assert lat2.steps_per_launch == 8                   # the load-only kernel has T = 8
