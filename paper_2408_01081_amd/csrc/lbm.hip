@@ -763,7 +763,8 @@ struct TBConfig {
   {T, S, N, F, {&k_tblock<LBM_PERIODIC, N, F, T>, &k_tblock<LBM_DIRICHLET, N, F, T>}}
 // Variants with a body load and/or the displacement state, the best variants
 // of the load-free table's grids; fn[m][bc], m = 0: load, 1: displacement,
-// 2: both (at T = 8 only the periodic kernel with a load fits in registers)
+// 2: both (at T = 8 only the periodic kernel with a load fits in registers,
+// at T = 7 the periodic kernel with the displacement state alone)
 struct TBExtConfig {
   int steps, seg_rows, nt, pf;
   TBFn fn[3][2];
@@ -779,6 +780,8 @@ struct TBExtConfig {
    {{nullptr, nullptr},                                                            \
     {LBM_TBX_K(LBM_PERIODIC, T, N, F, false, true), nullptr},                      \
     {LBM_TBX_K(LBM_PERIODIC, T, N, F, true, true), nullptr}}}
+#define LBM_TBX_D(T, S, N, F) \
+  {T, S, N, F, {{nullptr, nullptr}, {LBM_TBX_K(LBM_PERIODIC, T, N, F, false, true), nullptr}, {nullptr, nullptr}}}
 #define LBM_TBX_P(T, S, N, F) \
   {T, S, N, F, {{LBM_TBX_K(LBM_PERIODIC, T, N, F, true, false), nullptr}, {nullptr, nullptr}, {nullptr, nullptr}}}
 const TBConfig kTBConfigs[] = {
@@ -793,13 +796,14 @@ const TBConfig kTBConfigs[] = {
     LBM_TB(6, 8, 0, 1),  LBM_TB(6, 12, 0, 1), LBM_TB(6, 20, 0, 2), LBM_TB(6, 30, 0, 2),
     LBM_TB(8, 20, 0, 2), LBM_TB(8, 30, 0, 2), LBM_TB(8, 24, 0, 1), LBM_TB(8, 32, 0, 1),
     LBM_TB(8, 0, 0, 2),  LBM_TB(8, -2, 0, 2), LBM_TB(8, 0, 0, 1),  LBM_TB(7, 0, 0, 2)};
-const TBExtConfig kTBExtraConfigs[] = {LBM_TBX_P(8, 0, 0, 2), LBM_TBX_PD(6, 0, 0, 2),
-                                       LBM_TBX(6, 16, 1, 1)};
+const TBExtConfig kTBExtraConfigs[] = {LBM_TBX_P(8, 0, 0, 2), LBM_TBX_D(7, 0, 0, 2),
+                                       LBM_TBX_PD(6, 0, 0, 2), LBM_TBX(6, 16, 1, 1)};
 #undef LBM_TB
 #undef LBM_TBX_K
 #undef LBM_TBX
 #undef LBM_TBX_P
 #undef LBM_TBX_PD
+#undef LBM_TBX_D
 constexpr int kNumTBExtraConfigs = (int)(sizeof(kTBExtraConfigs) / sizeof(kTBExtraConfigs[0]));
 constexpr int kNumTBConfigs = (int)(sizeof(kTBConfigs) / sizeof(kTBConfigs[0]));
 static_assert(kNumTBConfigs <= 64, "tb_slots size");

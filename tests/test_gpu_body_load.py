@@ -305,9 +305,9 @@ def test_steps_per_launch_reports_the_path():
            for c in lat.tblock_configs()}
     assert lat.steps_per_launch == 1                    # no blocked variant selected
     lat.tblock_config = idx[(8, 0, 0, 2)]
-    assert lat.steps_per_launch == 6                    # displacement state: the T = 6 kernels
+    assert lat.steps_per_launch == 7                    # displacement state alone: T = 7
     lat.set_body_force(*(torch.from_numpy(a) for a in _random_load(g, 16, 256, 128, 10)))
-    assert lat.steps_per_launch == 6
+    assert lat.steps_per_launch == 6                    # load and displacement: T = 6
     lat.set_body_force(*(torch.from_numpy(a) for a in _random_load(g, 17, 256, 128, 10)))
     assert lat.steps_per_launch == 1                    # rank above 16: one launch per step
     lat2 = Lattice(prob.nx, prob.ny, prob.dx, prob.dt, prob.lam, prob.mu, prob.rho, prob.bc)
