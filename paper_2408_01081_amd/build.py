@@ -30,18 +30,41 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def build(verbose: bool = False) -> str:
-    out = os.path.join(HERE, LIBNAME)
-    tmp = out + ".tmp%d" % os.getpid()
-    cmd = [hipcc()] + HIPCC_FLAGS + ["-I", INCLUDE, "-I", CSRC, "-o", tmp] + \
-        [os.path.join(CSRC, s) for s in SOURCES]
+def _run(cmd, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
-        raise RuntimeError("hipcc failed (%d)" % r.returncode)
-    os.replace(tmp, out)
+        raise RuntimeError("hipcc failed (%d): %s" % (r.returncode, " ".join(cmd)))
+
+
+def build(verbose: bool = False) -> str:
+    """Compile every source to an object (in parallel), then link the
+    shared library; the library is replaced only when all steps succeed."""
+    from concurrent.futures import ThreadPoolExecutor
+    out = os.path.join(HERE, LIBNAME)
+    tag = "%d" % os.getpid()
+    objdir = os.path.join(HERE, "_build")
+    os.makedirs(objdir, exist_ok=True)
+    compile_flags = [f for f in HIPCC_FLAGS if f != "-shared"]
+    objs, cmds = [], []
+    for src in SOURCES:
+        obj = os.path.join(objdir, "%s.%s.o" % (src, tag))
+        objs.append(obj)
+        cmds.append([hipcc()] + compile_flags + ["-I", INCLUDE, "-I", CSRC, "-c", "-o", obj,
+                                                 os.path.join(CSRC, src)])
+    try:
+        with ThreadPoolExecutor(max_workers=len(cmds)) as ex:
+            for f in [ex.submit(_run, c, verbose) for c in cmds]:
+                f.result()
+        tmp = out + ".tmp" + tag
+        _run([hipcc(), "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs, verbose)
+        os.replace(tmp, out)
+    finally:
+        for o in objs:
+            if os.path.exists(o):
+                os.remove(o)
     return out
 
 
