@@ -148,7 +148,7 @@ lbm_status lbm_set_wall_velocity(lbm_ctx* ctx, int32_t rank, const float* d_W,
  * The load enters the initialisation (Eq. ic_second), the collision
  * (U_num = sum f + B_hat / 2 at every collision) and every output at the
  * current level.  Steps beyond nsteps are rejected by lbm_step.  With a
- * blocked variant selected (lbm_set_tblock_config / lbm_autotune), R <= 16,
+ * blocked variant selected (lbm_set_tblock_config / lbm_autotune), R <= 32,
  * no error tracking and ny >= T + 5, steps run T per launch of a blocked
  * kernel with the load (and the displacement state if the context keeps
  * it), bitwise the same results; otherwise one launch per step of the
@@ -164,7 +164,7 @@ lbm_status lbm_set_body_force(lbm_ctx* ctx, int32_t rank, const float* d_X, cons
  * in FP64 (a running sum: FP32 would round the whole displacement at every
  * half step); each step adds dt/2 v_num twice.  Requires LBM_F_DISPLACEMENT;
  * lbm_step rejects a context with the flag until this has been called.
- * With a blocked variant selected (and a body load of rank <= 16 or none,
+ * With a blocked variant selected (and a body load of rank <= 32 or none,
  * no error tracking) steps run several per launch, the rows in flight kept
  * in LDS and updated in the same order (bitwise the same D); otherwise one
  * launch per step. */

@@ -764,26 +764,37 @@ struct TBConfig {
 // Variants with a body load and/or the displacement state, the best variants
 // of the load-free table's grids; fn[m][bc], m = 0: load, 1: displacement,
 // 2: both (at T = 8 only the periodic kernel with a load fits in registers,
-// at T = 7 the periodic kernel with the displacement state alone)
+// at T = 7 the periodic kernel with the displacement state alone; with 32
+// load ranks the one-wave-per-slot periodic kernel takes the load alone)
 struct TBExtConfig {
   int steps, seg_rows, nt, pf;
+  int mr;  // load ranks the kernels take (16 or 32)
   TBFn fn[3][2];
 };
-#define LBM_TBX_K(B, T, N, F, L, D) &k_tblock<B, N, F, T, L, D>
+#define LBM_TBX_K(B, T, N, F, L, D) &k_tblock<B, N, F, T, L, D, 16>
+#define LBM_TBX_K32(B, T, N, F, L, D) &k_tblock<B, N, F, T, L, D, 32>
 #define LBM_TBX(T, S, N, F)                                                                       \
-  {T, S, N, F,                                                                                    \
+  {T, S, N, F, 16,                                                                                \
    {{LBM_TBX_K(LBM_PERIODIC, T, N, F, true, false), LBM_TBX_K(LBM_DIRICHLET, T, N, F, true, false)}, \
     {LBM_TBX_K(LBM_PERIODIC, T, N, F, false, true), LBM_TBX_K(LBM_DIRICHLET, T, N, F, false, true)}, \
     {LBM_TBX_K(LBM_PERIODIC, T, N, F, true, true), LBM_TBX_K(LBM_DIRICHLET, T, N, F, true, true)}}}
 #define LBM_TBX_PD(T, S, N, F)                                                      \
-  {T, S, N, F,                                                                     \
+  {T, S, N, F, 16,                                                                 \
    {{nullptr, nullptr},                                                            \
     {LBM_TBX_K(LBM_PERIODIC, T, N, F, false, true), nullptr},                      \
     {LBM_TBX_K(LBM_PERIODIC, T, N, F, true, true), nullptr}}}
 #define LBM_TBX_D(T, S, N, F) \
-  {T, S, N, F, {{nullptr, nullptr}, {LBM_TBX_K(LBM_PERIODIC, T, N, F, false, true), nullptr}, {nullptr, nullptr}}}
+  {T, S, N, F, 16, {{nullptr, nullptr}, {LBM_TBX_K(LBM_PERIODIC, T, N, F, false, true), nullptr}, {nullptr, nullptr}}}
 #define LBM_TBX_P(T, S, N, F) \
-  {T, S, N, F, {{LBM_TBX_K(LBM_PERIODIC, T, N, F, true, false), nullptr}, {nullptr, nullptr}, {nullptr, nullptr}}}
+  {T, S, N, F, 16, {{LBM_TBX_K(LBM_PERIODIC, T, N, F, true, false), nullptr}, {nullptr, nullptr}, {nullptr, nullptr}}}
+// ranks 17 .. 32 (load, load and displacement)
+#define LBM_TBX32(T, S, N, F)                                                                    \
+  {T, S, N, F, 32,                                                                               \
+   {{LBM_TBX_K32(LBM_PERIODIC, T, N, F, true, false), LBM_TBX_K32(LBM_DIRICHLET, T, N, F, true, false)}, \
+    {nullptr, nullptr},                                                                          \
+    {LBM_TBX_K32(LBM_PERIODIC, T, N, F, true, true), LBM_TBX_K32(LBM_DIRICHLET, T, N, F, true, true)}}}
+#define LBM_TBX32_P(T, S, N, F) \
+  {T, S, N, F, 32, {{LBM_TBX_K32(LBM_PERIODIC, T, N, F, true, false), nullptr}, {nullptr, nullptr}, {nullptr, nullptr}}}
 const TBConfig kTBConfigs[] = {
     LBM_TB(2, 4, 0, 1),  LBM_TB(2, 4, 1, 1),  LBM_TB(2, 8, 0, 1),  LBM_TB(2, 0, 0, 1),
     LBM_TB(3, 4, 0, 1),  LBM_TB(3, 5, 0, 2),  LBM_TB(3, 4, 1, 1),  LBM_TB(3, 8, 1, 1),
@@ -796,10 +807,14 @@ const TBConfig kTBConfigs[] = {
     LBM_TB(6, 8, 0, 1),  LBM_TB(6, 12, 0, 1), LBM_TB(6, 20, 0, 2), LBM_TB(6, 30, 0, 2),
     LBM_TB(8, 20, 0, 2), LBM_TB(8, 30, 0, 2), LBM_TB(8, 24, 0, 1), LBM_TB(8, 32, 0, 1),
     LBM_TB(8, 0, 0, 2),  LBM_TB(8, -2, 0, 2), LBM_TB(8, 0, 0, 1),  LBM_TB(7, 0, 0, 2)};
-const TBExtConfig kTBExtraConfigs[] = {LBM_TBX_P(8, 0, 0, 2), LBM_TBX_D(7, 0, 0, 2),
-                                       LBM_TBX_PD(6, 0, 0, 2), LBM_TBX(6, 16, 1, 1)};
+const TBExtConfig kTBExtraConfigs[] = {LBM_TBX_P(8, 0, 0, 2),  LBM_TBX_D(7, 0, 0, 2),
+                                       LBM_TBX_PD(6, 0, 0, 2), LBM_TBX(6, 16, 1, 1),
+                                       LBM_TBX32_P(6, 0, 0, 2), LBM_TBX32(6, 16, 1, 1)};
 #undef LBM_TB
 #undef LBM_TBX_K
+#undef LBM_TBX_K32
+#undef LBM_TBX32
+#undef LBM_TBX32_P
 #undef LBM_TBX
 #undef LBM_TBX_P
 #undef LBM_TBX_PD
@@ -900,14 +915,15 @@ void launch_tb(lbm_ctx* c, int index, const float* src, float* dst, const WallSe
                      src, dst, c->g, sc, ws, TBExtra{nullptr, nullptr, 0, 0.f, nullptr, 0.0});
 }
 
-// rows[l][y][r] = Y[r][y] T_{n1 + l}[r] for r < R, -0 beyond (the factors of
-// body_hat, one per level of a blocked launch whose first level is n1)
+// rows[l][y][r] = Y[r][y] T_{n1 + l}[r] for r < R, -0 for R <= r < MR (the
+// factors of body_hat, one per level of a blocked launch whose first level
+// is n1)
 __global__ void k_force_rows(const float* __restrict__ Y, const float* __restrict__ T1, int R,
-                             int ny, int T, float* __restrict__ rows) {
+                             int ny, int T, int MR, float* __restrict__ rows) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (int64_t)T * ny * TB_MAXR) return;
-  const int r = (int)(i % TB_MAXR);
-  const int64_t ly = i / TB_MAXR;
+  if (i >= (int64_t)T * ny * MR) return;
+  const int r = (int)(i % MR);
+  const int64_t ly = i / MR;
   const int y = (int)(ly % ny), l = (int)(ly / ny);
   rows[i] = r < R ? Y[(int64_t)r * ny + y] * T1[(int64_t)l * R + r] : -0.f;
 }
@@ -918,10 +934,13 @@ __global__ void k_force_rows(const float* __restrict__ Y, const float* __restric
 int extra_variant(const lbm_ctx* c, int m) {
   if (c->tb_cfg < 0 || c->force_rank > TB_MAXR || !tblock_fits(c->g)) return -1;
   const TBConfig& t = kTBConfigs[c->tb_cfg];
+  // the narrowest rank width that holds the load (16 or 32)
+  const int mr = c->force_rank > 16 ? 32 : 16;
   int same_t = -1, first = -1;
   for (int i = 0; i < kNumTBExtraConfigs; ++i) {
     const TBExtConfig& k = kTBExtraConfigs[i];
     if (!k.fn[m][c->p.bc]) continue;
+    if (m != 1 && k.mr != mr) continue;
     if (c->g.ny < k.steps + 3 + k.pf) continue;  // the kernel wraps a load row once
     if (k.steps == t.steps && k.seg_rows == t.seg_rows && k.nt == t.nt && k.pf == t.pf) return i;
     if (k.steps == t.steps && same_t < 0) same_t = i;
@@ -986,7 +1005,7 @@ static lbm_status step_extra_blocked(lbm_ctx* c, int64_t nsteps, int vi, int m) 
   const int ntiles = sc.nstrips * sc.nseg;
   const TBExtra F{c->force_X, c->force_rows, R, (float)(c->p.dt / c->p.rho), c->disp,
                   0.5 * c->p.dt};
-  const int64_t nrows = (int64_t)T * c->g.ny * TB_MAXR;
+  const int64_t nrows = (int64_t)T * c->g.ny * k.mr;
   const int64_t nb = nsteps / T * T;
   for (int64_t done = 0; done < nb;) {
     const int n = (int)(nb - done < chunk ? nb - done : chunk);
@@ -995,7 +1014,7 @@ static lbm_status step_extra_blocked(lbm_ctx* c, int64_t nsteps, int vi, int m) 
       if (R > 0)
         hipLaunchKernelGGL(k_force_rows, dim3((unsigned)((nrows + 255) / 256)), dim3(256), 0,
                            c->stream, c->force_Y, c->force_T + (c->nstep + 1) * R, R, c->g.ny, T,
-                           c->force_rows);
+                           k.mr, c->force_rows);
       hipLaunchKernelGGL(fn, dim3((unsigned)((ntiles + 3) / 4)), dim3(256), 0, c->stream,
                          (const float*)c->buf[c->cur], c->buf[c->cur ^ 1], c->g, sc,
                          walls_from(c, j, true), F);

@@ -68,10 +68,10 @@ struct WallSeq {
 // are staged through LDS (fac_request, fac_stage, fac_read below).  A padded term adds +0 * -0 = -0, which
 // leaves every sum unchanged in round-to-nearest, so the result is bitwise
 // the single-step kernel's.
-constexpr int TB_MAXR = 16;  // largest rank the blocked kernel takes
+constexpr int TB_MAXR = 32;  // largest rank the blocked kernel takes (variants of 16 and 32)
 struct TBExtra {
   const float* X;     // [rank][2][nx]
-  const float* rows;  // [T][ny][TB_MAXR], written before the launch
+  const float* rows;  // [T][ny][MR], written before the launch (MR: the variant's ranks)
   int rank;
   float scale;        // dt / rho
   double* D;          // [2][ny][nx] FP64 displacement state (launches that keep it)
@@ -85,16 +85,18 @@ struct TBExtra {
 // lane: both components), requested two sub-iterations before their first
 // level, staged one before, and written back after their last level.
 constexpr int TB_DSLOTS = 16;
+template <int MR>
 struct LaneLoad {
-  float x[2][TB_MAXR];
+  float x[2][MR];
 };
 
 // B_hat (c = 0, 1) of this lane's node from the row factors yt
-__device__ __forceinline__ void load_terms(const LaneLoad& ll, const float (&yt)[TB_MAXR],
+template <int MR>
+__device__ __forceinline__ void load_terms(const LaneLoad<MR>& ll, const float (&yt)[MR],
                                            float scale, float& bx, float& by) {
   float a = 0.f, b = 0.f;
 #pragma unroll
-  for (int r = 0; r < TB_MAXR; ++r) {
+  for (int r = 0; r < MR; ++r) {
     a = fmaf(ll.x[0][r], yt[r], a);
     b = fmaf(ll.x[1][r], yt[r], b);
   }
@@ -212,11 +214,11 @@ __device__ __forceinline__ void collide_shifted(const float U[NC], const float X
 // lanes replace a shifted population by the wall rule; other waves of a
 // Dirichlet lattice meet walls only in rows 0 and ny - 1, a branch uniform
 // across the wave.
-template <int BC, bool EDGE, bool FORCE>
+template <int BC, bool EDGE, bool FORCE, int MR>
 __device__ __forceinline__ void level_update(const float below[NP], const float at[NP],
                                     const float above[NP], int x, int y, int nx, int ny,
-                                    float kK, float km, const Wall& w, const LaneLoad& ll,
-                                    const float (&yt)[TB_MAXR], float scale, float out[NP],
+                                    float kK, float km, const Wall& w, const LaneLoad<MR>& ll,
+                                    const float (&yt)[MR], float scale, float out[NP],
                                     float (&Uo)[2]) {
   // the load terms first: they do not depend on the populations
   float bx = 0.f, by = 0.f;
@@ -368,12 +370,12 @@ __device__ __forceinline__ void load_row(const float* __restrict__ src, int pitc
 // update of row y of level l from the rows below, at and above it; rows off
 // the grid (computed only to be dropped or replaced by a wall) use any valid
 // row for their wall lookups
-template <int BC, bool EDGE, bool FORCE>
+template <int BC, bool EDGE, bool FORCE, int MR>
 __device__ __forceinline__ void row_update(const float below[NP], const float at[NP],
                                            const float above[NP], int xw, int y, int level,
                                            const Grid& g, const TBConst& sc, const WallSeq& ws,
-                                           const TBExtra& F, const LaneLoad& ll,
-                                           const float (&yt)[TB_MAXR], float out[NP],
+                                           const TBExtra& F, const LaneLoad<MR>& ll,
+                                           const float (&yt)[MR], float out[NP],
                                            float (&Uo)[2]) {
   const int yc = y < 0 ? 0 : (y >= g.ny ? g.ny - 1 : y);
   Wall w;
@@ -382,8 +384,8 @@ __device__ __forceinline__ void row_update(const float below[NP], const float at
   w.W = nullptr;
   w.rank = 0;
   w.Trow = nullptr;
-  level_update<BC, EDGE, FORCE>(below, at, above, xw, yc, g.nx, g.ny, sc.kK, sc.km, w, ll, yt,
-                                F.scale, out, Uo);
+  level_update<BC, EDGE, FORCE, MR>(below, at, above, xw, yc, g.nx, g.ny, sc.kK, sc.km, w, ll,
+                                    yt, F.scale, out, Uo);
 }
 
 // Row factors through LDS.  A sub-iteration j needs the factors of its T
@@ -396,39 +398,42 @@ __device__ __forceinline__ void row_update(const float below[NP], const float at
 // lattice the rows beyond the grid are the wrapped rows (one wrap suffices:
 // the host takes this path only for ny >= T + ring length); on a Dirichlet
 // lattice their loads are never used (clamped).
-template <int BC, int T>
+template <int BC, int T, int MR>
 __device__ __forceinline__ void fac_request(const TBExtra& F, const Grid& g, int y0, int j,
-                                            float (&v)[2]) {
+                                            float (&v)[(MR * T + 63) / 64]) {
+  constexpr int FE = (MR * T + 63) / 64;  // factors per lane
   const int lane = threadIdx.x & 63;
 #pragma unroll
-  for (int k = 0; k < 2; ++k) {
+  for (int k = 0; k < FE; ++k) {
     const int e = lane + 64 * k;
     v[k] = 0.f;
-    if (e < TB_MAXR * T) {
-      const int l = e / TB_MAXR + 1, r = e % TB_MAXR;
+    if (e < MR * T) {
+      const int l = e / MR + 1, r = e % MR;
       const int y = y0 + j + T - l;
       int yl = y < 0 ? 0 : (y >= g.ny ? g.ny - 1 : y);
       if (BC == LBM_PERIODIC) yl = y < 0 ? y + g.ny : (y >= g.ny ? y - g.ny : y);
-      v[k] = F.rows[((int64_t)(l - 1) * g.ny + yl) * TB_MAXR + r];
+      v[k] = F.rows[((int64_t)(l - 1) * g.ny + yl) * MR + r];
     }
   }
 }
 
-template <int T>
-__device__ __forceinline__ void fac_stage(float* slot, const float (&v)[2]) {
+template <int T, int MR>
+__device__ __forceinline__ void fac_stage(float* slot, const float (&v)[(MR * T + 63) / 64]) {
+  constexpr int FE = (MR * T + 63) / 64;
   const int lane = threadIdx.x & 63;
 #pragma unroll
-  for (int k = 0; k < 2; ++k)
-    if (lane + 64 * k < TB_MAXR * T) slot[lane + 64 * k] = v[k];
+  for (int k = 0; k < FE; ++k)
+    if (lane + 64 * k < MR * T) slot[lane + 64 * k] = v[k];
   // the wave's later reads of the slot see these writes (LDS operations of
   // a wave complete in order); keep the compiler from moving them
   __builtin_amdgcn_wave_barrier();
 }
 
-__device__ __forceinline__ void fac_read(const float* slot, int level, float (&yt)[TB_MAXR]) {
-  const float4* p = reinterpret_cast<const float4*>(slot + (level - 1) * TB_MAXR);
+template <int MR>
+__device__ __forceinline__ void fac_read(const float* slot, int level, float (&yt)[MR]) {
+  const float4* p = reinterpret_cast<const float4*>(slot + (level - 1) * MR);
 #pragma unroll
-  for (int q = 0; q < TB_MAXR / 4; ++q) {
+  for (int q = 0; q < MR / 4; ++q) {
     const float4 v = p[q];
     yt[4 * q] = v.x;
     yt[4 * q + 1] = v.y;
@@ -481,19 +486,20 @@ __device__ __forceinline__ void d_store(const TBExtra& F, const Grid& g, int dof
 
 // One level update of a row inside a sub-iteration, with the displacement
 // rows when the launch keeps them (rows the wave owns: y0 <= y < y1)
-template <int BC, bool EDGE, bool FORCE, bool DISP>
+template <int BC, bool EDGE, bool FORCE, bool DISP, int MR>
 __device__ __forceinline__ void level_step(const float below[NP], const float at[NP],
                                            const float above[NP], int xw, int y, int level,
                                            const Grid& g, const TBConst& sc, const WallSeq& ws,
-                                           const TBExtra& F, const LaneLoad& ll,
-                                           const float (&yt)[TB_MAXR], float out[NP],
+                                           const TBExtra& F, const LaneLoad<MR>& ll,
+                                           const float (&yt)[MR], float out[NP],
                                            double* dring, int y0, int y1, int doff, bool last) {
   float Uo[2];
   if constexpr (DISP) {
     if (y >= y0 && y < y1) {
       double* p = d_slot(dring, y);
       double d[2] = {p[0], p[1]};
-      row_update<BC, EDGE, FORCE>(below, at, above, xw, y, level, g, sc, ws, F, ll, yt, out, Uo);
+      row_update<BC, EDGE, FORCE, MR>(below, at, above, xw, y, level, g, sc, ws, F, ll, yt, out,
+                                      Uo);
       d_update(d, Uo, F.half_dt);
       p[0] = d[0];
       p[1] = d[1];
@@ -501,25 +507,26 @@ __device__ __forceinline__ void level_step(const float below[NP], const float at
       return;
     }
   }
-  row_update<BC, EDGE, FORCE>(below, at, above, xw, y, level, g, sc, ws, F, ll, yt, out, Uo);
+  row_update<BC, EDGE, FORCE, MR>(below, at, above, xw, y, level, g, sc, ws, F, ll, yt, out, Uo);
 }
 
 // One sub-iteration i of the sweep (PRE: a pipeline-filling sub-iteration
 // before the first output row, I = i then; slot = i mod NB, known at compile
 // time in both cases).
-template <int BC, int NT, int PF, int T, bool EDGE, bool FORCE, bool DISP, bool PRE>
+template <int BC, int NT, int PF, int T, bool EDGE, bool FORCE, bool DISP, int MR, bool PRE>
 __device__ __forceinline__ void sub_iteration(const float* __restrict__ src, float* __restrict__ dst,
                                      const Grid& g, const TBConst& sc, const Strip& st,
-                                     const WallSeq& ws, const TBExtra& F, const LaneLoad& ll,
-                                     float* fac, float (&fv)[3 + PF][2], double* dring,
+                                     const WallSeq& ws, const TBExtra& F, const LaneLoad<MR>& ll,
+                                     float* fac, float (&fv)[3 + PF][(MR * T + 63) / 64],
+                                     double* dring,
                                      double (&dv)[3 + PF][2], int doff,
                                      int pitch4, RowCursor& cur, int y0,
                                      int y1, int i, int I, int slot, float (&lv0)[3 + PF][NP],
                                      float (&lv)[T - 1][3 + PF][NP]) {
   constexpr int NB = 3 + PF;
-  constexpr int FS = TB_MAXR * T;  // floats of one LDS factor slot
+  constexpr int FS = MR * T;  // floats of one LDS factor slot
   const int s = slot, s1 = (slot + NB - 1) % NB, s2 = (slot + NB - 2) % NB;
-  if constexpr (FORCE) fac_request<BC, T>(F, g, y0, i + 2, fv[(s + 2) % NB]);
+  if constexpr (FORCE) fac_request<BC, T, MR>(F, g, y0, i + 2, fv[(s + 2) % NB]);
   // displacement row whose first level comes two sub-iterations on
   if constexpr (DISP) {
     const int yq = y0 + i + 2 + T - 1;
@@ -538,9 +545,9 @@ __device__ __forceinline__ void sub_iteration(const float* __restrict__ src, flo
   // the levels whose rows the segment needs (I >= -2 (T - l)).  With a load
   // the factors of level l + 1 are read from LDS before level l is formed
   // (yt[l mod 2] holds level l's).
-  float yt[2][TB_MAXR];
+  float yt[2][MR];
   if constexpr (FORCE) {
-    fac_stage<T>(fac + ((s + 1) % NB) * FS, fv[(s + 1) % NB]);
+    fac_stage<T, MR>(fac + ((s + 1) % NB) * FS, fv[(s + 1) % NB]);
     fac_read(fac + s * FS, 1, yt[1]);
     fac_read(fac + s * FS, 2, yt[0]);
   }
@@ -549,13 +556,13 @@ __device__ __forceinline__ void sub_iteration(const float* __restrict__ src, flo
     if (yq >= y0 && yq < y1) d_stage(dring, yq, dv[(s + 1) % NB]);
   }
   if (!PRE || I >= -2 * (T - 1))
-    level_step<BC, EDGE, FORCE, DISP>(lv0[s2], lv0[s1], lv0[s], st.xw, y0 + i + T - 1, 1, g, sc,
+    level_step<BC, EDGE, FORCE, DISP, MR>(lv0[s2], lv0[s1], lv0[s], st.xw, y0 + i + T - 1, 1, g, sc,
                                       ws, F, ll, yt[1], lv[0][s], dring, y0, y1, doff, false);
 #pragma unroll
   for (int l = 2; l < T; ++l) {
     if constexpr (FORCE) fac_read(fac + s * FS, l + 1, yt[(l + 1) & 1]);
     if (PRE && I < -2 * (T - l)) continue;
-    level_step<BC, EDGE, FORCE, DISP>(lv[l - 2][s2], lv[l - 2][s1], lv[l - 2][s], st.xw,
+    level_step<BC, EDGE, FORCE, DISP, MR>(lv[l - 2][s2], lv[l - 2][s1], lv[l - 2][s], st.xw,
                                       y0 + i + T - l, l, g, sc, ws, F, ll, yt[l & 1],
                                       lv[l - 1][s], dring, y0, y1, doff, false);
   }
@@ -563,7 +570,7 @@ __device__ __forceinline__ void sub_iteration(const float* __restrict__ src, flo
     // level T, output row y0 + i
     float o[NP];
     const int rr = y0 + i;
-    level_step<BC, EDGE, FORCE, DISP>(lv[T - 2][s2], lv[T - 2][s1], lv[T - 2][s], st.xw, rr, T,
+    level_step<BC, EDGE, FORCE, DISP, MR>(lv[T - 2][s2], lv[T - 2][s1], lv[T - 2][s], st.xw, rr, T,
                                       g, sc, ws, F, ll, yt[T & 1], o, dring, y0, y1, doff, true);
     const int off = rr < y1 ? st.xs4 : TB_DROP;
     const int yo = rr < g.ny ? rr : g.ny - 1;
@@ -579,12 +586,12 @@ __device__ __forceinline__ void sub_iteration(const float* __restrict__ src, flo
 }
 
 // The sweep of one wave over output rows y0 .. y1 - 1 (EDGE: see level_update).
-template <int BC, int NT, int PF, int T, bool EDGE, bool FORCE, bool DISP>
+template <int BC, int NT, int PF, int T, bool EDGE, bool FORCE, bool DISP, int MR>
 __device__ __forceinline__ void tblock_sweep(const float* __restrict__ src,
                                              float* __restrict__ dst, const Grid& g,
                                              const TBConst& sc, const Strip& st,
                                              const WallSeq& ws, const TBExtra& F,
-                                             const LaneLoad& ll, float* fac, double* dring,
+                                             const LaneLoad<MR>& ll, float* fac, double* dring,
                                              int doff, int pitch4, RowCursor& cur, int y0,
                                              int y1) {
   constexpr int NB = 3 + PF;
@@ -595,12 +602,12 @@ __device__ __forceinline__ void tblock_sweep(const float* __restrict__ src,
   double dv[NB][2];
   // load factors: requested two sub-iterations ahead (fv), staged in LDS one
   // ahead; the first sub-iteration's are staged here
-  float fv[NB][2];
+  float fv[NB][(MR * T + 63) / 64];
   if constexpr (FORCE) {
     constexpr int first = -2 * T;
-    fac_request<BC, T>(F, g, y0, first, fv[((first % NB) + NB) % NB]);
-    fac_request<BC, T>(F, g, y0, first + 1, fv[(((first + 1) % NB) + NB) % NB]);
-    fac_stage<T>(fac + (((first % NB) + NB) % NB) * TB_MAXR * T, fv[((first % NB) + NB) % NB]);
+    fac_request<BC, T, MR>(F, g, y0, first, fv[((first % NB) + NB) % NB]);
+    fac_request<BC, T, MR>(F, g, y0, first + 1, fv[(((first + 1) % NB) + NB) % NB]);
+    fac_stage<T, MR>(fac + (((first % NB) + NB) % NB) * MR * T, fv[((first % NB) + NB) % NB]);
   }
   float lv0[NB][NP];        // level 0: row of sub-iteration i is y0 + i + T
   float lv[T - 1][NB][NP];  // level l: row of sub-iteration i is y0 + i + T - l
@@ -615,7 +622,7 @@ __device__ __forceinline__ void tblock_sweep(const float* __restrict__ src,
 #pragma unroll
   for (int p = 0; p < 2 * T; ++p) {
     const int I = p - 2 * T;
-    sub_iteration<BC, NT, PF, T, EDGE, FORCE, DISP, true>(src, dst, g, sc, st, ws, F, ll, fac, fv,
+    sub_iteration<BC, NT, PF, T, EDGE, FORCE, DISP, MR, true>(src, dst, g, sc, st, ws, F, ll, fac, fv,
                                                           dring, dv, doff, pitch4, cur, y0, y1, I,
                                                           I, (I % NB + NB) % NB, lv0, lv);
   }
@@ -626,14 +633,14 @@ __device__ __forceinline__ void tblock_sweep(const float* __restrict__ src,
   for (int i0 = 0; i0 < y1 - y0; i0 += NB) {
 #pragma unroll
     for (int j = 0; j < NB; ++j)
-      sub_iteration<BC, NT, PF, T, EDGE, FORCE, DISP, false>(src, dst, g, sc, st, ws, F, ll, fac,
+      sub_iteration<BC, NT, PF, T, EDGE, FORCE, DISP, MR, false>(src, dst, g, sc, st, ws, F, ll, fac,
                                                              fv, dring, dv, doff, pitch4, cur, y0,
                                                              y1, i0 + j, 0, j, lv0, lv);
   }
 }
 
 // One wave's work: strip `strip`, output rows of segment `seg`.
-template <int BC, int NT, int PF, int T, bool FORCE = false, bool DISP = false>
+template <int BC, int NT, int PF, int T, bool FORCE = false, bool DISP = false, int MR = 16>
 __device__ __forceinline__ void tblock_wave(const float* __restrict__ src, float* __restrict__ dst,
                                    const Grid& g, const TBConst& sc, const WallSeq& ws,
                                    int strip, int seg, const TBExtra& F = TBExtra{},
@@ -660,10 +667,10 @@ __device__ __forceinline__ void tblock_wave(const float* __restrict__ src, float
   // beyond the row for lanes that do not own their column
   const int doff = store ? (int)((uint32_t)x * 8u) : TB_DROP;
   // this lane's load coefficients (the column it reads)
-  LaneLoad ll;
+  LaneLoad<MR> ll;
   if constexpr (FORCE) {
 #pragma unroll
-    for (int r = 0; r < TB_MAXR; ++r)
+    for (int r = 0; r < MR; ++r)
 #pragma unroll
       for (int c = 0; c < 2; ++c)
         ll.x[c][r] = r < F.rank ? F.X[((int64_t)r * 2 + c) * nx + xc] : 0.f;
@@ -672,16 +679,16 @@ __device__ __forceinline__ void tblock_wave(const float* __restrict__ src, float
     // a Dirichlet wave meets the side walls only if its columns include one
     const int x_first = strip * VALID - T;
     if (x_first <= 0 || x_first + TB_LANES - 1 >= nx - 1) {
-      tblock_sweep<BC, NT, PF, T, true, FORCE, DISP>(src, dst, g, sc, st, ws, F, ll, fac, dring,
+      tblock_sweep<BC, NT, PF, T, true, FORCE, DISP, MR>(src, dst, g, sc, st, ws, F, ll, fac, dring,
                                                      doff, pitch4, cur, y0, y1);
       return;
     }
   }
-  tblock_sweep<BC, NT, PF, T, false, FORCE, DISP>(src, dst, g, sc, st, ws, F, ll, fac, dring, doff,
+  tblock_sweep<BC, NT, PF, T, false, FORCE, DISP, MR>(src, dst, g, sc, st, ws, F, ll, fac, dring, doff,
                                                   pitch4, cur, y0, y1);
 }
 
-template <int BC, int NT, int PF, int T, bool FORCE = false, bool DISP = false>
+template <int BC, int NT, int PF, int T, bool FORCE = false, bool DISP = false, int MR = 16>
 __global__ __launch_bounds__(256) void k_tblock(const float* __restrict__ src,
                                                 float* __restrict__ dst, Grid g, TBConst sc,
                                                 WallSeq ws, TBExtra F) {
@@ -691,12 +698,12 @@ __global__ __launch_bounds__(256) void k_tblock(const float* __restrict__ src,
   const int wid = xcd_tile(blockIdx.x, nwg) * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (wid >= ntiles) return;  // whole waves exit together
   // per wave: one slot of load factors per ring row (unused without a load)
-  __shared__ __attribute__((aligned(16))) float fac[FORCE ? 4 * (3 + PF) * TB_MAXR * T : 4];
-  float* mine = FORCE ? fac + (threadIdx.x >> 6) * (3 + PF) * TB_MAXR * T : nullptr;
+  __shared__ __attribute__((aligned(16))) float fac[FORCE ? 4 * (3 + PF) * MR * T : 4];
+  float* mine = FORCE ? fac + (threadIdx.x >> 6) * (3 + PF) * MR * T : nullptr;
   // per wave: the displacement rows in flight (unused without them)
   __shared__ __attribute__((aligned(16))) double dring[DISP ? 4 * TB_DSLOTS * TB_LANES * 2 : 2];
   double* dmine = DISP ? dring + (threadIdx.x >> 6) * TB_DSLOTS * TB_LANES * 2 : nullptr;
-  tblock_wave<BC, NT, PF, T, FORCE, DISP>(src, dst, g, sc, ws, wid % sc.nstrips,
+  tblock_wave<BC, NT, PF, T, FORCE, DISP, MR>(src, dst, g, sc, ws, wid % sc.nstrips,
                                           wid / sc.nstrips, F, mine, dmine);
 }
 

@@ -191,13 +191,13 @@ def _random_load(g, R, nx, ny, nsteps):
 @gpu
 @pytest.mark.parametrize("bc,N,ny", [(synth.PERIODIC, 130, 64), (synth.PERIODIC, 70, 45),
                                      (synth.DIRICHLET, 300, 70), (synth.DIRICHLET, 61, 37)])
-@pytest.mark.parametrize("R", [1, 5, 16, 17])
+@pytest.mark.parametrize("R", [1, 5, 16, 17, 32, 33])
 def test_blocked_steps_with_load_bitwise_equal_single_steps(bc, N, ny, R):
-    # with a load of rank <= 16 and no displacement state the blocked kernel
-    # steps T per launch (the ranks below 16 padded with terms that add
-    # exactly nothing); rank 17 runs one step per launch; every launch
-    # variant, through each load variant, gives the single-step state bit for
-    # bit (Dirichlet with moving walls)
+    # with a load of rank <= 32 and no displacement state the blocked kernel
+    # steps T per launch (kernels for 16 and 32 ranks, the ranks below padded
+    # with terms that add exactly nothing); rank 33 runs one step per launch;
+    # every launch variant, through each load variant, gives the single-step
+    # state bit for bit (Dirichlet with moving walls)
     torch = _torch()
     from paper_2408_01081_amd.lbm import Lattice
     prob = synth.plane_wave_problem(N, ny, bc, seed=23, kmax=3)
@@ -243,7 +243,7 @@ def test_blocked_steps_with_load_match_oracle(bc):
 @gpu
 @pytest.mark.parametrize("bc,N,ny", [(synth.PERIODIC, 130, 64), (synth.DIRICHLET, 300, 70),
                                      (synth.DIRICHLET, 61, 37)])
-@pytest.mark.parametrize("R", [0, 5, 16])
+@pytest.mark.parametrize("R", [0, 5, 16, 24])
 def test_blocked_steps_with_displacement_bitwise_equal_single_steps(bc, N, ny, R):
     # with the FP64 displacement state (and a load of rank <= 16, or none)
     # the blocked kernel keeps the rows a wave owns in LDS and adds dt/2 v
@@ -309,7 +309,9 @@ def test_steps_per_launch_reports_the_path():
     lat.set_body_force(*(torch.from_numpy(a) for a in _random_load(g, 16, 256, 128, 10)))
     assert lat.steps_per_launch == 6                    # load and displacement: T = 6
     lat.set_body_force(*(torch.from_numpy(a) for a in _random_load(g, 17, 256, 128, 10)))
-    assert lat.steps_per_launch == 1                    # rank above 16: one launch per step
+    assert lat.steps_per_launch == 6                    # ranks 17 .. 32: the T = 6 kernels
+    lat.set_body_force(*(torch.from_numpy(a) for a in _random_load(g, 33, 256, 128, 10)))
+    assert lat.steps_per_launch == 1                    # rank above 32: one launch per step
     lat2 = Lattice(prob.nx, prob.ny, prob.dx, prob.dt, prob.lam, prob.mu, prob.rho, prob.bc)
     lat2.tblock_config = idx[(8, 0, 0, 2)]
     assert lat2.steps_per_launch == 8
