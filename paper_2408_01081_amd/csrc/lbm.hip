@@ -788,6 +788,8 @@ struct TBExtConfig {
 #define LBM_TBX_P(T, S, N, F) \
   {T, S, N, F, 16, {{LBM_TBX_K(LBM_PERIODIC, T, N, F, true, false), nullptr}, {nullptr, nullptr}, {nullptr, nullptr}}}
 // ranks 17 .. 32 (load, load and displacement)
+#define LBM_TBX32_PB(T, S, N, F) \
+  {T, S, N, F, 32, {{nullptr, nullptr}, {nullptr, nullptr}, {LBM_TBX_K32(LBM_PERIODIC, T, N, F, true, true), nullptr}}}
 #define LBM_TBX32(T, S, N, F)                                                                    \
   {T, S, N, F, 32,                                                                               \
    {{LBM_TBX_K32(LBM_PERIODIC, T, N, F, true, false), LBM_TBX_K32(LBM_DIRICHLET, T, N, F, true, false)}, \
@@ -809,12 +811,14 @@ const TBConfig kTBConfigs[] = {
     LBM_TB(8, 0, 0, 2),  LBM_TB(8, -2, 0, 2), LBM_TB(8, 0, 0, 1),  LBM_TB(7, 0, 0, 2)};
 const TBExtConfig kTBExtraConfigs[] = {LBM_TBX_P(8, 0, 0, 2),  LBM_TBX_D(7, 0, 0, 2),
                                        LBM_TBX_PD(6, 0, 0, 2), LBM_TBX(6, 16, 1, 1),
-                                       LBM_TBX32_P(6, 0, 0, 2), LBM_TBX32(6, 16, 1, 1)};
+                                       LBM_TBX32_P(6, 0, 0, 2), LBM_TBX32_PB(6, 0, 0, 1),
+                                       LBM_TBX32(6, 16, 1, 1)};
 #undef LBM_TB
 #undef LBM_TBX_K
 #undef LBM_TBX_K32
 #undef LBM_TBX32
 #undef LBM_TBX32_P
+#undef LBM_TBX32_PB
 #undef LBM_TBX
 #undef LBM_TBX_P
 #undef LBM_TBX_PD
