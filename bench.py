@@ -126,19 +126,25 @@ def main():
     torch.cuda.synchronize()
 
     # ---- timed region ----------------------------------------------------------
-    # each lattice's K steps bracketed by events on the stream its kernels
-    # run on
+    # each lattice's K steps, as lbm_step runs them: full launches of T steps,
+    # then one launch for the K mod T steps left; events on the stream the
+    # kernels run on mark the full launches apart from the rest, so the
+    # dominant kernel's average launch time comes from its own launches
     stream = torch.cuda.current_stream(dev)
     E = lambda: torch.cuda.Event(enable_timing=True)
     start, end = E(), E()
-    ev = [[E(), E()], [E(), E()]]
+    ev = [[E(), E(), E()], [E(), E(), E()]]
+    Ts = [lat.steps_per_launch for lat in lats]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     start.record(stream)
     for li, lat in enumerate(lats):
+        full = K // Ts[li] * Ts[li]
         ev[li][0].record(stream)
-        lat.step(K)
+        lat.step(full)
         ev[li][1].record(stream)
+        lat.step(K - full)
+        ev[li][2].record(stream)
     end.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -154,14 +160,17 @@ def main():
     # (160 B per node), for one time step (k_step) or T (k_tblock).
     per_lat = lats[0]
     blocked = tuned[0]["tblock_config"] >= 0
-    T = tuned[0]["tblock"]["steps"] if blocked else 1
-    per_ms = ev[0][0].elapsed_time(ev[0][1])
-    # lbm_step runs chunks of floor(420 / T) T steps, T per launch; leftover
-    # steps one at a time
-    chunk = 420 // T * T
-    launches = (K // chunk) * (chunk // T) + (K % chunk) // T if blocked else K
-    single_left = K - launches * T if blocked else 0
-    kern_ms = per_ms / (launches + single_left / T)   # a single step counts 1/T of a launch
+    T = Ts[0]
+    assert T == (tuned[0]["tblock"]["steps"] if blocked else 1)
+    launches = K // T
+    if launches > 0:
+        kern_ms = ev[0][0].elapsed_time(ev[0][1]) / launches
+        kern_src = "HIP events around the %d full launches of the timed region" % launches
+    else:  # fewer timed steps than one launch takes: time the launch apart
+        kern_ms = (per_lat.time_tblock_config(tuned[0]["tblock_config"], 20) if blocked
+                   else per_lat.time_step_config(tuned[0]["config"], 20))
+        kern_src = "20 launches timed apart (the timed region has no full launch)"
+    rest = K - launches * T
     alg_bytes = BYTES_PER_LUP * per.nx * per.ny
     achieved = alg_bytes / (kern_ms * 1e-3) / 1e9
     kname = "k_tblock" if blocked else "k_step"
@@ -172,8 +181,12 @@ def main():
                     kname, ("blocked variant %d, %d steps per launch"
                             % (tuned[0]["tblock_config"], T)) if blocked
                     else ("config %d" % tuned[0]["config"])),
-                "kernel_ms": round(kern_ms, 5), "launches": launches,
-                "steps_per_launch": T,
+                "kernel_ms": round(kern_ms, 5), "kernel_ms_from": kern_src,
+                "launches": launches, "steps_per_launch": T,
+                "steps_after_full_launches": {
+                    "steps": rest, "ms": round(ev[0][1].elapsed_time(ev[0][2]), 5),
+                    "launch": ("none" if rest == 0 else "single-step kernel" if rest == 1
+                               else "one %d-step blocked launch" % rest)},
                 "kernel_glups": round(T * per.nx * per.ny / kern_ms / 1e6, 2),
                 "algorithmic_bytes_per_launch": alg_bytes}
     if blocked:
@@ -543,27 +556,63 @@ def surrogate_leg(weights_path):
     return out
 
 
-def cpu_baseline(per, dir_, nsteps):
+def _omp_threads(n):
+    """Set the OpenMP thread count of the oracle's runtime (the system
+    libgomp the C oracle links); returns the previous count."""
+    import ctypes
+    g = ctypes.CDLL("libgomp.so.1")
+    old = g.omp_get_max_threads()
+    g.omp_set_num_threads(int(n))
+    return old
+
+
+def cpu_baseline(per, dir_, nsteps, single_steps=4):
     """Time the FP64 oracle (as it stands) on a bounded sample of the same
-    workload: nsteps steps of each lattice from its initial state."""
+    workload: nsteps steps of each lattice from its initial state on all of
+    the host's cores, then single_steps steps of each on one core.  The
+    periodic lattice runs the oracle's C step loop; the Dirichlet lattice
+    steps through the oracle's per-step driver with the benchmark's
+    time-dependent wall velocities (summed from the closed form every step)."""
     import oracle
-    t_total, lups = 0.0, 0
-    for prob in (per, dir_):
-        s = oracle.Setup(prob.nx, prob.ny, prob.dx, prob.dt, prob.lam, prob.mu, prob.rho,
-                         prob.bc)
-        v0, sb0 = prob.initial_fields()
-        f = oracle.init_populations(s, s.U_from_fields(v0, sb0))
-        del v0, sb0
-        t0 = time.perf_counter()
-        oracle.run_free(s, f, nsteps)
-        t_total += time.perf_counter() - t0
-        lups += prob.nx * prob.ny * nsteps
-        del f
-    return {"value": round(lups / t_total / 1e9, 5), "unit": "GLUPS",
-            "cores": int(oracle.lib().orc_threads()), "kind": "oracle",
-            "sample": "%d steps of each lattice (4096x4096 periodic, 2048x1024 Dirichlet with "
-                      "homogeneous walls), FP64, step loop only" % nsteps,
-            "seconds": round(t_total, 2)}
+
+    def sample(n):
+        t_total, lups = 0.0, 0
+        for prob in (per, dir_):
+            s = oracle.Setup(prob.nx, prob.ny, prob.dx, prob.dt, prob.lam, prob.mu, prob.rho,
+                             prob.bc)
+            v0, sb0 = prob.initial_fields()
+            if prob.bc == oracle.DIRICHLET:
+                sim = oracle.Simulation(s, v0, sb0, wall=prob.wall_velocity)
+                del v0, sb0
+                t0 = time.perf_counter()
+                sim.advance(n)
+                t_total += time.perf_counter() - t0
+                del sim
+            else:
+                f = oracle.init_populations(s, s.U_from_fields(v0, sb0))
+                del v0, sb0
+                t0 = time.perf_counter()
+                oracle.run_free(s, f, n)
+                t_total += time.perf_counter() - t0
+                del f
+            lups += prob.nx * prob.ny * n
+        return lups / t_total / 1e9, t_total
+
+    cores = int(oracle.lib().orc_threads())
+    all_glups, all_s = sample(nsteps)
+    old = _omp_threads(1)
+    try:
+        one_glups, one_s = sample(single_steps)
+    finally:
+        _omp_threads(old)
+    return {"value": round(all_glups, 5), "unit": "GLUPS", "cores": cores, "kind": "oracle",
+            "sample": "%d steps of each lattice (4096x4096 periodic; 2048x1024 Dirichlet with "
+                      "the benchmark's rank-30 time-dependent walls), FP64, step loop only"
+                      % nsteps,
+            "seconds": round(all_s, 2),
+            "single_core": {"value": round(one_glups, 6), "unit": "GLUPS", "cores": 1,
+                            "sample": "%d steps of each lattice, same data" % single_steps,
+                            "seconds": round(one_s, 2)}}
 
 
 if __name__ == "__main__":

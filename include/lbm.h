@@ -60,7 +60,8 @@ typedef enum { LBM_PLANE_STRAIN = 0, LBM_PLANE_STRESS = 1, LBM_CONTINUUM_2D = 2 
 typedef struct {
   int32_t nx, ny;      /* nodes per side, >= 1, nx * ny <= 2^31                   */
   double dx, dt;       /* lattice spacing and time step; c = dx/dt               */
-  double lambda, mu;   /* Lame constants; mu > 0, lambda + mu > 0                 */
+  double lambda, mu;   /* Lame constants; mu >= 0, lambda + mu > 0 (mu = 0: see
+                          lbm_init_from_gradient; batched instances need mu > 0) */
   double rho;          /* density > 0                                            */
   int32_t bc;          /* lbm_bc                                                 */
   int32_t model;       /* lbm_model                                              */
@@ -112,6 +113,24 @@ lbm_status lbm_create(const lbm_params* p, void* d_ws, size_t ws_bytes, void* hi
 lbm_status lbm_init(lbm_ctx* ctx, const double* d_v0, const double* d_sigma0,
                     const double* d_grad);
 
+/* The same initialisation (Eq. ic_second) from the initial velocity and the
+ * gradient of the initial displacement, through Eq. ic_vector:
+ *   U0 = (v0x, v0y, -c_K (du_x/dx + du_y/dy), -c_mu (du_x/dx - du_y/dy),
+ *         -c_mu (du_y/dx + du_x/dy)),
+ * which involves no division by c_mu: the entry point for mu = 0 (c_mu = 0,
+ * the (c_K^2, c_mu^2) = (1.5, 0) material of Section 6.1), where lbm_init
+ * fails with LBM_E_ARG.
+ *   d_v0      [2][ny][nx] FP64  initial velocity
+ *   d_gradu0  [4][ny][nx] FP64  du_x/dx, du_x/dy, du_y/dx, du_y/dy of u0
+ *   d_grad    nullable [2][6][ny][nx] FP64: d/dx then d/dy of the six input
+ *             fields (v_x, v_y, du_x/dx, du_x/dy, du_y/dx, du_y/dy), physical
+ *             units; when NULL the library takes second-order central
+ *             differences of U0 (periodic wrap; one-sided second order at
+ *             Dirichlet walls).
+ * Computed in FP64, rounded once to FP32; resets the step counter to 0. */
+lbm_status lbm_init_from_gradient(lbm_ctx* ctx, const double* d_v0, const double* d_gradu0,
+                                  const double* d_grad);
+
 /* Load FP32 populations directly ([4][5][ny][nx], pre-collision, directions
  * in the paper's order (1,0),(0,1),(-1,0),(0,-1), components of U) at step
  * counter 0, collided with the body load of t_0 (if one is set; Eq. cond_eq).
@@ -151,8 +170,10 @@ lbm_status lbm_set_wall_velocity(lbm_ctx* ctx, int32_t rank, const float* d_W,
  * blocked variant selected (lbm_set_tblock_config / lbm_autotune), R <= 32,
  * no error tracking and ny >= T + 5, steps run T per launch of a blocked
  * kernel with the load (and the displacement state if the context keeps
- * it), bitwise the same results; otherwise one launch per step of the
- * one-node-per-thread kernel (lbm_steps_per_launch tells which).  Set it
+ * it), bitwise the same results, and the steps after the last full launch
+ * in as few launches of shorter blocked variants as exist (a last single
+ * step in the one-node-per-thread kernel); otherwise one launch per step of
+ * the one-node-per-thread kernel (lbm_steps_per_launch tells which).  Set it
  * before lbm_init to include B_hat(0) in the initialisation.  Pointers are
  * kept (not copied) and must stay valid while stepping. */
 lbm_status lbm_set_body_force(lbm_ctx* ctx, int32_t rank, const float* d_X, const float* d_Y,
@@ -275,11 +296,15 @@ lbm_status lbm_autotune(lbm_ctx* ctx, int32_t reps, int32_t use_cache, int32_t* 
  * resident slot covers the grid, -k that k waves per slot do.  index -1 disables blocking; lbm_autotune
  * selects a variant when it is faster per step than the best single-step
  * configuration.  With a variant of T steps enabled, lbm_step(n) runs the
- * steps in chunks of floor(420 / T) T steps, T per launch, and only the
- * last (n mod chunk) mod T steps one at a time.  Grids whose row byte
- * offsets ((19 planes + one row) * 4 B) reach 2^31 cannot use it: setting or
- * timing a variant then fails with LBM_E_ARG and the autotuner skips it.  Any
- * output pointer may be NULL. */
+ * steps in chunks of floor(420 / T) T steps, T per launch; the r = n mod T
+ * steps after the last full launch take one launch of an r-step variant
+ * (the fastest one lbm_autotune timed, else the r-step variant of the
+ * nearest launch shape), or of the single-step kernel for r = 1.  Row base
+ * addresses are 64-bit; only the byte offsets inside one row's 20 planes
+ * ((19 plane strides + one row) * 4 B) must stay below 2^31, which fails
+ * for the plane-major layout beyond about 28 M nodes and for rows of more
+ * than about 13 M nodes: setting or timing a variant then fails with
+ * LBM_E_ARG and the autotuner skips it.  Any output pointer may be NULL. */
 int32_t lbm_tblock_config_count(void);
 lbm_status lbm_tblock_config_info(int32_t index, int32_t* h_steps, int32_t* h_seg_rows,
                                   int32_t* h_nontemporal, int32_t* h_prefetch);
@@ -375,6 +400,15 @@ lbm_status lbm_batch_energy(lbm_batch* b, double* h_out);
  * FP32 physical fields [..][5][ny][nx] (v, sigma_bar), measured on the system
  * variables U: ||U - U(fields)|| / ||U|| (FP64) into h_out[n].  Synchronises. */
 lbm_status lbm_batch_rel_l2_fields(lbm_batch* b, const float* d_fields, double* h_out);
+
+/* Per-instance relative L2 difference between two packed FP32 physical field
+ * arrays d_a, d_b [..][5][ny][nx] (v, sigma_bar), measured on the system
+ * variables U of each instance's material (inverse of Eq. sigma_num, FP64):
+ * ||U(a) - U(b)|| / ||U(b)|| into h_out[n].  Uses the batch's layout and
+ * materials only (no lattice state; callable before any initialisation).
+ * Synchronises. */
+lbm_status lbm_batch_rel_l2_pair(lbm_batch* b, const float* d_a, const float* d_b,
+                                 double* h_out);
 
 lbm_status lbm_batch_destroy(lbm_batch* b);
 

@@ -222,6 +222,11 @@ class Simulation:
     v0, sb0       physical initial velocity [2] and Cauchy stress [3] fields
     dfields       optional exact spatial derivatives [2][5] of (v, sigma_bar)
                   (physical); otherwise central differences are used
+    gradu0        optional displacement gradient [2][2] (d u_a / d x_b) of u0:
+                  U0 then follows Eq. ic_vector from (v0, gradu0) and sb0 is
+                  not used (needed for c_mu = 0, where the stress does not
+                  determine j_d, j_xy); dfields then holds the exact
+                  derivatives [2] of (v0, gradu0) in the same nesting
     u0            optional initial displacement; enables the trapezoidal
                   displacement output (Eq. trapezoidal) with u*(0) = u0 - dt/2 v(0)
     body(t)       optional physical body load b_bar(t) on the nodes, [2][ny][nx]
@@ -229,14 +234,21 @@ class Simulation:
     """
 
     def __init__(self, s: Setup, v0, sb0, dfields=None, u0=None, body=None, wall=None,
-                 init_correction=True):
+                 init_correction=True, gradu0=None):
         self.s, self.body, self.wall = s, body, wall
         self.n = 0
-        U0 = s.U_from_fields(v0, sb0)
         UX = UY = None
-        if dfields is not None:
-            UX = s.U_from_fields(dfields[0][:2], dfields[0][2:]) * s.dx
-            UY = s.U_from_fields(dfields[1][:2], dfields[1][2:]) * s.dx
+        if gradu0 is not None:
+            # Eq. ic_vector (linear: derivatives map the same way)
+            U0 = s.U_from_displacement_gradient(v0, gradu0)
+            if dfields is not None:
+                UX = s.U_from_displacement_gradient(*dfields[0]) * s.dx
+                UY = s.U_from_displacement_gradient(*dfields[1]) * s.dx
+        else:
+            U0 = s.U_from_fields(v0, sb0)
+            if dfields is not None:
+                UX = s.U_from_fields(dfields[0][:2], dfields[0][2:]) * s.dx
+                UY = s.U_from_fields(dfields[1][:2], dfields[1][2:]) * s.dx
         B0 = self.bhat(0.0)
         if init_correction:
             self.f = init_populations(s, U0, UX, UY, B0)

@@ -35,6 +35,7 @@ SIGNATURES = [
     ("lbm_create", ctypes.c_int, [ctypes.POINTER(LbmParams), _VP, ctypes.c_size_t, _VP,
                                   ctypes.POINTER(_VP)]),
     ("lbm_init", ctypes.c_int, [_VP, _VP, _VP, _VP]),
+    ("lbm_init_from_gradient", ctypes.c_int, [_VP, _VP, _VP, _VP]),
     ("lbm_set_populations", ctypes.c_int, [_VP, _VP]),
     ("lbm_set_wall_velocity", ctypes.c_int, [_VP, _I32, _VP, _VP, _I64]),
     ("lbm_set_body_force", ctypes.c_int, [_VP, _I32, _VP, _VP, _VP, _I64]),
@@ -88,6 +89,7 @@ SIGNATURES = [
     ("lbm_batch_moments_U", ctypes.c_int, [_VP, _VP]),
     ("lbm_batch_energy", ctypes.c_int, [_VP, _PD]),
     ("lbm_batch_rel_l2_fields", ctypes.c_int, [_VP, _VP, _PD]),
+    ("lbm_batch_rel_l2_pair", ctypes.c_int, [_VP, _VP, _VP, _PD]),
     ("lbm_batch_destroy", ctypes.c_int, [_VP]),
     ("sg_workspace_bytes", ctypes.c_size_t, [_VP]),
     ("sg_param_count", _I64, []),

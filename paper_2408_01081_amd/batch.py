@@ -161,3 +161,14 @@ class Batch:
         out = (ctypes.c_double * self.n)()
         check(self.L.lbm_batch_rel_l2_fields(self.ctx, _ptr(f), out))
         return np.array(out[:])
+
+    def rel_l2_pair(self, a, b):
+        """Per-instance ||U(a) - U(b)|| / ||U(b)|| of two packed FP32 field
+        arrays (v, sigma_bar), U from each instance's material; no state."""
+        fa = a.to(self.device, torch.float32).contiguous()
+        fb = b.to(self.device, torch.float32).contiguous()
+        if fa.numel() != 5 * self.total_nodes or fb.numel() != 5 * self.total_nodes:
+            raise ValueError("packed field sizes do not match the batch")
+        out = (ctypes.c_double * self.n)()
+        check(self.L.lbm_batch_rel_l2_pair(self.ctx, _ptr(fa), _ptr(fb), out))
+        return np.array(out[:])

@@ -10,7 +10,8 @@ ROOT = os.path.dirname(HERE)
 INCLUDE = os.path.join(ROOT, "include")
 CSRC = os.path.join(HERE, "csrc")
 LIBNAME = "liblbm_hip.so"
-SOURCES = ["lbm.hip", "lbm_batch.hip", "sg.hip"]
+SOURCES = ["lbm.hip", "lbm_tb_pa.hip", "lbm_tb_pb.hip", "lbm_tb_da.hip", "lbm_tb_db.hip",
+           "lbm_tb_xa.hip", "lbm_tb_xb.hip", "lbm_batch.hip", "sg.hip"]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [
@@ -55,7 +56,7 @@ def build(verbose: bool = False) -> str:
         cmds.append([hipcc()] + compile_flags + ["-I", INCLUDE, "-I", CSRC, "-c", "-o", obj,
                                                  os.path.join(CSRC, src)])
     try:
-        with ThreadPoolExecutor(max_workers=len(cmds)) as ex:
+        with ThreadPoolExecutor(max_workers=min(len(cmds), os.cpu_count() or 4)) as ex:
             for f in [ex.submit(_run, c, verbose) for c in cmds]:
                 f.result()
         tmp = out + ".tmp" + tag

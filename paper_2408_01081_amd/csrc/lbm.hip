@@ -26,6 +26,7 @@
 #include "lbm_kernels.hpp"
 #include "lbm_step.hpp"
 #include "lbm_tblock.hpp"
+#include "lbm_tb_tables.hpp"
 #include "lbm_init.hpp"
 #include "lbm_host.hpp"
 
@@ -396,9 +397,10 @@ struct lbm_ctx {
   int64_t wall_nsteps;
   int device;
   int step_cfg;   // index into kStepConfigs
-  int tb_cfg;         // index into kTBConfigs, or -1 (single steps only)
+  int tb_cfg;         // index into kTBVariants, or -1 (single steps only)
   int tb_slots[64];   // resident waves of a blocked variant on this device (0: not known)
-  int tbf_slots[24];  // the same for the variants with a load / displacement (3 per variant)
+  int tbf_slots[48];  // the same for the variants with a load / displacement (3 per variant)
+  int tb_rem[9];      // variant for the last r = 2 .. 8 steps of a run (-1: nearest shape)
   float* wall_v;        // [WALL_CHUNK][2 (nx + ny)][2] wall velocities of upcoming steps
   // separable body load (rank 0: none); row n of force_T belongs to t_n
   const float* force_X;
@@ -603,6 +605,7 @@ lbm_status lbm_create(const lbm_params* p, void* d_ws, size_t ws_size, void* hip
   hipGetDevice(&c->device);
   c->step_cfg = default_step_config(g.nx);
   c->tb_cfg = -1;
+  for (int r = 0; r < 9; ++r) c->tb_rem[r] = -1;
   *out = c;
   g_err.clear();
   return LBM_OK;
@@ -621,12 +624,12 @@ lbm_status lbm_lattice_constants(const lbm_ctx* c, double* kK, double* km, doubl
   return LBM_OK;
 }
 
-lbm_status lbm_init(lbm_ctx* c, const double* d_v0, const double* d_sigma0, const double* d_grad) {
-  if (!c || !d_v0 || !d_sigma0) return fail(LBM_E_ARG, "null argument");
+static lbm_status init_from(lbm_ctx* c, const double* d_v0, const double* d_s0,
+                            const double* d_grad, int src) {
   const int64_t n = (int64_t)c->g.nx * c->g.ny;
-  InitConst k{c->kK, c->km, c->cK, c->cmu, c->p.rho, c->p.dx, c->p.bc};
+  InitConst k{c->kK, c->km, c->cK, c->cmu, c->p.rho, c->p.dx, c->p.bc, src};
   hipLaunchKernelGGL(k_init, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, d_v0,
-                     d_sigma0, d_grad, c->buf[0], c->g, k, force_at(c, 0));
+                     d_s0, d_grad, c->buf[0], c->g, k, force_at(c, 0));
   lbm_status s = launch_check("k_init launch");
   if (s) return s;
   c->cur = 0;
@@ -635,6 +638,20 @@ lbm_status lbm_init(lbm_ctx* c, const double* d_v0, const double* d_sigma0, cons
   c->disp_ready = false;
   c->err_on = false;
   return LBM_OK;
+}
+
+lbm_status lbm_init(lbm_ctx* c, const double* d_v0, const double* d_sigma0, const double* d_grad) {
+  if (!c || !d_v0 || !d_sigma0) return fail(LBM_E_ARG, "null argument");
+  if (!(c->cmu > 0))
+    return fail(LBM_E_ARG,
+                "mu = 0: the stress does not determine j_d, j_xy; use lbm_init_from_gradient");
+  return init_from(c, d_v0, d_sigma0, d_grad, INIT_FROM_STRESS);
+}
+
+lbm_status lbm_init_from_gradient(lbm_ctx* c, const double* d_v0, const double* d_gradu0,
+                                  const double* d_grad) {
+  if (!c || !d_v0 || !d_gradu0) return fail(LBM_E_ARG, "null argument");
+  return init_from(c, d_v0, d_gradu0, d_grad, INIT_FROM_GRADIENT);
 }
 
 lbm_status lbm_set_body_force(lbm_ctx* c, int32_t rank, const float* d_X, const float* d_Y,
@@ -751,82 +768,34 @@ int64_t lbm_step_count(const lbm_ctx* c) { return c ? c->nstep : -1; }
 
 namespace {
 
-typedef void (*TBFn)(const float*, float*, Grid, TBConst, WallSeq, TBExtra);
-// Temporally blocked variants: T steps per launch, output rows per segment
-// (0: as many as fill the device with one wave per resident slot, rounded up
-// to the ring length), nontemporal stores, rows prefetched ahead.
-struct TBConfig {
-  int steps, seg_rows, nt, pf;
-  TBFn fn[2];
+// Kernel handles of the blocked variants (lbm_tb_tables.hpp), filled once
+// from the translation units that instantiate them.
+struct TBTables {
+  TBFn fn[kNumTBVariants][2];       // load-free, [variant][bc]
+  TBExtFns xfn[kNumTBExtVariants];  // with extras, [variant][extras][bc]
 };
-#define LBM_TB(T, S, N, F) \
-  {T, S, N, F, {&k_tblock<LBM_PERIODIC, N, F, T>, &k_tblock<LBM_DIRICHLET, N, F, T>}}
-// Variants with a body load and/or the displacement state, the best variants
-// of the load-free table's grids; fn[m][bc], m = 0: load, 1: displacement,
-// 2: both (at T = 8 only the periodic kernel with a load fits in registers,
-// at T = 7 the periodic kernel with the displacement state alone; with 32
-// load ranks the one-wave-per-slot periodic kernel takes the load alone)
-struct TBExtConfig {
-  int steps, seg_rows, nt, pf;
-  int mr;  // load ranks the kernels take (16 or 32)
-  TBFn fn[3][2];
-};
-#define LBM_TBX_K(B, T, N, F, L, D) &k_tblock<B, N, F, T, L, D, 16>
-#define LBM_TBX_K32(B, T, N, F, L, D) &k_tblock<B, N, F, T, L, D, 32>
-#define LBM_TBX(T, S, N, F)                                                                       \
-  {T, S, N, F, 16,                                                                                \
-   {{LBM_TBX_K(LBM_PERIODIC, T, N, F, true, false), LBM_TBX_K(LBM_DIRICHLET, T, N, F, true, false)}, \
-    {LBM_TBX_K(LBM_PERIODIC, T, N, F, false, true), LBM_TBX_K(LBM_DIRICHLET, T, N, F, false, true)}, \
-    {LBM_TBX_K(LBM_PERIODIC, T, N, F, true, true), LBM_TBX_K(LBM_DIRICHLET, T, N, F, true, true)}}}
-#define LBM_TBX_PD(T, S, N, F)                                                      \
-  {T, S, N, F, 16,                                                                 \
-   {{nullptr, nullptr},                                                            \
-    {LBM_TBX_K(LBM_PERIODIC, T, N, F, false, true), nullptr},                      \
-    {LBM_TBX_K(LBM_PERIODIC, T, N, F, true, true), nullptr}}}
-#define LBM_TBX_D(T, S, N, F) \
-  {T, S, N, F, 16, {{nullptr, nullptr}, {LBM_TBX_K(LBM_PERIODIC, T, N, F, false, true), nullptr}, {nullptr, nullptr}}}
-#define LBM_TBX_P(T, S, N, F) \
-  {T, S, N, F, 16, {{LBM_TBX_K(LBM_PERIODIC, T, N, F, true, false), nullptr}, {nullptr, nullptr}, {nullptr, nullptr}}}
-// ranks 17 .. 32 (load, load and displacement)
-#define LBM_TBX32_PB(T, S, N, F) \
-  {T, S, N, F, 32, {{nullptr, nullptr}, {nullptr, nullptr}, {LBM_TBX_K32(LBM_PERIODIC, T, N, F, true, true), nullptr}}}
-#define LBM_TBX32(T, S, N, F)                                                                    \
-  {T, S, N, F, 32,                                                                               \
-   {{LBM_TBX_K32(LBM_PERIODIC, T, N, F, true, false), LBM_TBX_K32(LBM_DIRICHLET, T, N, F, true, false)}, \
-    {nullptr, nullptr},                                                                          \
-    {LBM_TBX_K32(LBM_PERIODIC, T, N, F, true, true), LBM_TBX_K32(LBM_DIRICHLET, T, N, F, true, true)}}}
-#define LBM_TBX32_P(T, S, N, F) \
-  {T, S, N, F, 32, {{LBM_TBX_K32(LBM_PERIODIC, T, N, F, true, false), nullptr}, {nullptr, nullptr}, {nullptr, nullptr}}}
-const TBConfig kTBConfigs[] = {
-    LBM_TB(2, 4, 0, 1),  LBM_TB(2, 4, 1, 1),  LBM_TB(2, 8, 0, 1),  LBM_TB(2, 0, 0, 1),
-    LBM_TB(3, 4, 0, 1),  LBM_TB(3, 5, 0, 2),  LBM_TB(3, 4, 1, 1),  LBM_TB(3, 8, 1, 1),
-    LBM_TB(4, 4, 0, 1),  LBM_TB(4, 8, 0, 1),  LBM_TB(4, 4, 1, 1),  LBM_TB(4, 8, 1, 1),
-    LBM_TB(4, 12, 1, 1), LBM_TB(5, 16, 0, 1), LBM_TB(5, 32, 0, 1), LBM_TB(5, 16, 1, 1),
-    LBM_TB(6, 16, 0, 1), LBM_TB(6, 32, 0, 1), LBM_TB(6, 48, 0, 1), LBM_TB(6, 16, 1, 1),
-    LBM_TB(7, 32, 0, 1), LBM_TB(7, 48, 0, 1), LBM_TB(7, 64, 0, 1), LBM_TB(7, 32, 1, 1),
-    LBM_TB(7, 0, 0, 1),  LBM_TB(7, -2, 0, 1), LBM_TB(6, 0, 0, 1),  LBM_TB(5, 0, 0, 1),
-    LBM_TB(7, 16, 0, 1), LBM_TB(7, 24, 0, 1), LBM_TB(7, 20, 0, 2), LBM_TB(7, 30, 0, 2),
-    LBM_TB(6, 8, 0, 1),  LBM_TB(6, 12, 0, 1), LBM_TB(6, 20, 0, 2), LBM_TB(6, 30, 0, 2),
-    LBM_TB(8, 20, 0, 2), LBM_TB(8, 30, 0, 2), LBM_TB(8, 24, 0, 1), LBM_TB(8, 32, 0, 1),
-    LBM_TB(8, 0, 0, 2),  LBM_TB(8, -2, 0, 2), LBM_TB(8, 0, 0, 1),  LBM_TB(7, 0, 0, 2)};
-const TBExtConfig kTBExtraConfigs[] = {LBM_TBX_P(8, 0, 0, 2),  LBM_TBX_D(7, 0, 0, 2),
-                                       LBM_TBX_PD(6, 0, 0, 2), LBM_TBX(6, 16, 1, 1),
-                                       LBM_TBX32_P(6, 0, 0, 2), LBM_TBX32_PB(6, 0, 0, 1),
-                                       LBM_TBX32(6, 16, 1, 1)};
-#undef LBM_TB
-#undef LBM_TBX_K
-#undef LBM_TBX_K32
-#undef LBM_TBX32
-#undef LBM_TBX32_P
-#undef LBM_TBX32_PB
-#undef LBM_TBX
-#undef LBM_TBX_P
-#undef LBM_TBX_PD
-#undef LBM_TBX_D
-constexpr int kNumTBExtraConfigs = (int)(sizeof(kTBExtraConfigs) / sizeof(kTBExtraConfigs[0]));
-constexpr int kNumTBConfigs = (int)(sizeof(kTBConfigs) / sizeof(kTBConfigs[0]));
-static_assert(kNumTBConfigs <= 64, "tb_slots size");
-static_assert(kNumTBExtraConfigs * 3 <= 24, "tbf_slots size");
+
+const TBTables& tb_tables() {
+  static const TBTables t = [] {
+    TBTables r;
+    TBFn p[kNumTBVariants], d[kNumTBVariants];
+    tb_fill_periodic_a(p);
+    tb_fill_periodic_b(p);
+    tb_fill_dirichlet_a(d);
+    tb_fill_dirichlet_b(d);
+    for (int i = 0; i < kNumTBVariants; ++i) {
+      r.fn[i][LBM_PERIODIC] = p[i];
+      r.fn[i][LBM_DIRICHLET] = d[i];
+    }
+    tb_fill_extra_a(r.xfn);
+    tb_fill_extra_b(r.xfn);
+    return r;
+  }();
+  return t;
+}
+
+static_assert(kNumTBVariants <= 64, "tb_slots size");
+static_assert(kNumTBExtVariants * 3 <= 48, "tbf_slots size");
 
 
 // Sum the wall velocities of steps step0 .. step0 + n - 1 (n <= WALL_CHUNK)
@@ -905,18 +874,43 @@ int seg_rows_of(lbm_ctx* c, int steps, int seg_rows, int pf, TBFn fn, int* slots
 }
 
 int tb_seg_rows(lbm_ctx* c, int index) {
-  const TBConfig& k = kTBConfigs[index];
-  return seg_rows_of(c, k.steps, k.seg_rows, k.pf, k.fn[c->p.bc], &c->tb_slots[index]);
+  const TBVariant& k = kTBVariants[index];
+  return seg_rows_of(c, k.steps, k.seg_rows, k.pf, tb_tables().fn[index][c->p.bc],
+                     &c->tb_slots[index]);
 }
 
-// one launch of variant `index`: kTBConfigs[index].steps steps, level l with
+// one launch of variant `index`: kTBVariants[index].steps steps, level l with
 // the walls of table entry s0 + l - 1
 void launch_tb(lbm_ctx* c, int index, const float* src, float* dst, const WallSeq& ws) {
-  const TBConfig& k = kTBConfigs[index];
+  const TBVariant& k = kTBVariants[index];
   const TBConst sc = tblock_const(c->g, (float)c->kK, (float)c->km, tb_seg_rows(c, index), k.steps);
   const int ntiles = sc.nstrips * sc.nseg;
-  hipLaunchKernelGGL(k.fn[c->p.bc], dim3((unsigned)((ntiles + 3) / 4)), dim3(256), 0, c->stream,
-                     src, dst, c->g, sc, ws, TBExtra{nullptr, nullptr, 0, 0.f, nullptr, 0.0});
+  hipLaunchKernelGGL(tb_tables().fn[index][c->p.bc], dim3((unsigned)((ntiles + 3) / 4)),
+                     dim3(256), 0, c->stream, src, dst, c->g, sc, ws,
+                     TBExtra{nullptr, nullptr, 0, 0.f, nullptr, 0.0});
+}
+
+// The variant that takes the last r (2 <= r < T) steps of a run in one
+// launch: the autotuner's fastest r-step variant when it has timed them, else
+// the r-step variant nearest to the selected one's shape (same rows per
+// segment, store type and prefetch, then the same rows per segment and
+// prefetch, then the same rows per segment, then the first); -1 if none.
+int remainder_variant(const lbm_ctx* c, int r) {
+  if (r < 2 || r > 8) return -1;
+  if (c->tb_rem[r] >= 0) return c->tb_rem[r];
+  const TBVariant& t = kTBVariants[c->tb_cfg];
+  int best = -1, best_score = -1;
+  for (int i = 0; i < kNumTBVariants; ++i) {
+    const TBVariant& k = kTBVariants[i];
+    if (k.steps != r) continue;
+    const int score = (k.seg_rows == t.seg_rows ? 4 : 0) + (k.pf == t.pf ? 2 : 0) +
+                      (k.nt == t.nt ? 1 : 0);
+    if (score > best_score) {
+      best_score = score;
+      best = i;
+    }
+  }
+  return best;
 }
 
 // rows[l][y][r] = Y[r][y] T_{n1 + l}[r] for r < R, -0 for R <= r < MR (the
@@ -932,25 +926,44 @@ __global__ void k_force_rows(const float* __restrict__ Y, const float* __restric
   rows[i] = r < R ? Y[(int64_t)r * ny + y] * T1[(int64_t)l * R + r] : -0.f;
 }
 
-// the variant with extras m (0 load, 1 displacement, 2 both) for a lattice
-// whose blocked variant is tb_cfg: the same launch shape if there is one,
-// else the same T, else the first for its boundary type; -1 if none applies
+// whether extras variant i has the kernel for extras m on this lattice (load
+// ranks, and one wrap of a load row at most)
+bool extra_usable(const lbm_ctx* c, int i, int m) {
+  const TBExtVariant& k = kTBExtVariants[i];
+  if (!tb_tables().xfn[i][m][c->p.bc]) return false;
+  const int mr = c->force_rank > 16 ? 32 : 16;  // the narrowest rank width that holds the load
+  if (m != 1 && k.mr != mr) return false;
+  return c->g.ny >= k.steps + 3 + k.pf;
+}
+
+// the whole-run variant with extras m (0 load, 1 displacement, 2 both) for a
+// lattice whose blocked variant is tb_cfg: the same launch shape if there is
+// one, else the same T, else the first for its boundary type; -1 if none
+// applies
 int extra_variant(const lbm_ctx* c, int m) {
   if (c->tb_cfg < 0 || c->force_rank > TB_MAXR || !tblock_fits(c->g)) return -1;
-  const TBConfig& t = kTBConfigs[c->tb_cfg];
-  // the narrowest rank width that holds the load (16 or 32)
-  const int mr = c->force_rank > 16 ? 32 : 16;
+  const TBVariant& t = kTBVariants[c->tb_cfg];
   int same_t = -1, first = -1;
-  for (int i = 0; i < kNumTBExtraConfigs; ++i) {
-    const TBExtConfig& k = kTBExtraConfigs[i];
-    if (!k.fn[m][c->p.bc]) continue;
-    if (m != 1 && k.mr != mr) continue;
-    if (c->g.ny < k.steps + 3 + k.pf) continue;  // the kernel wraps a load row once
+  for (int i = 0; i < kNumTBExtVariants; ++i) {
+    const TBExtVariant& k = kTBExtVariants[i];
+    if (!k.main || !extra_usable(c, i, m)) continue;
     if (k.steps == t.steps && k.seg_rows == t.seg_rows && k.nt == t.nt && k.pf == t.pf) return i;
     if (k.steps == t.steps && same_t < 0) same_t = i;
     if (first < 0) first = i;
   }
   return same_t >= 0 ? same_t : first;
+}
+
+// the variant with extras m for the last steps of a run: the one with the
+// most steps, at most r, for this lattice (-1: none, r < 2)
+int extra_remainder_variant(const lbm_ctx* c, int m, int r) {
+  int best = -1;
+  for (int i = 0; i < kNumTBExtVariants; ++i) {
+    const TBExtVariant& k = kTBExtVariants[i];
+    if (k.steps > r || k.steps < 2 || !extra_usable(c, i, m)) continue;
+    if (best < 0 || k.steps > kTBExtVariants[best].steps) best = i;
+  }
+  return best;
 }
 
 }  // namespace
@@ -994,15 +1007,13 @@ static lbm_status step_ext(lbm_ctx* c, int64_t nsteps) {
   return launch_check("k_step_ext launch");
 }
 
-// Steps with a body load and/or the displacement state (no error norms), T
-// per launch with variant vi, extras m: before each launch with a load the
-// row factors of its T levels are formed; the last nsteps mod T steps run
-// one per launch.
-static lbm_status step_extra_blocked(lbm_ctx* c, int64_t nsteps, int vi, int m) {
-  const TBExtConfig& k = kTBExtraConfigs[vi];
-  const TBFn fn = k.fn[m][c->p.bc];
+// One launch of extras variant vi (extras m): kTBExtVariants[vi].steps steps
+// from the current step, walls from table entry s; with a load the row
+// factors of its levels are formed first.
+static void launch_tbx(lbm_ctx* c, int vi, int m, int s) {
+  const TBExtVariant& k = kTBExtVariants[vi];
+  const TBFn fn = tb_tables().xfn[vi][m][c->p.bc];
   const int T = k.steps, R = c->force_rank;
-  const int chunk = WALL_CHUNK / T * T;
   const TBConst sc = tblock_const(c->g, (float)c->kK, (float)c->km,
                                   seg_rows_of(c, T, k.seg_rows, k.pf, fn, &c->tbf_slots[vi * 3 + m]),
                                   T);
@@ -1010,24 +1021,45 @@ static lbm_status step_extra_blocked(lbm_ctx* c, int64_t nsteps, int vi, int m) 
   const TBExtra F{c->force_X, c->force_rows, R, (float)(c->p.dt / c->p.rho), c->disp,
                   0.5 * c->p.dt};
   const int64_t nrows = (int64_t)T * c->g.ny * k.mr;
-  const int64_t nb = nsteps / T * T;
-  for (int64_t done = 0; done < nb;) {
-    const int n = (int)(nb - done < chunk ? nb - done : chunk);
+  if (R > 0)
+    hipLaunchKernelGGL(k_force_rows, dim3((unsigned)((nrows + 255) / 256)), dim3(256), 0,
+                       c->stream, c->force_Y, c->force_T + (c->nstep + 1) * R, R, c->g.ny, T,
+                       k.mr, c->force_rows);
+  hipLaunchKernelGGL(fn, dim3((unsigned)((ntiles + 3) / 4)), dim3(256), 0, c->stream,
+                     (const float*)c->buf[c->cur], c->buf[c->cur ^ 1], c->g, sc,
+                     walls_from(c, s, true), F);
+  c->cur ^= 1;
+  c->nstep += T;
+}
+
+// Steps with a body load and/or the displacement state (no error norms), T
+// per launch with variant vi, extras m.  The steps after the last full launch
+// run in as few launches of shorter variants as exist (the longest that fits
+// first); a single step left runs one launch of the one-step kernel.
+static lbm_status step_extra_blocked(lbm_ctx* c, int64_t nsteps, int vi, int m) {
+  const int T = kTBExtVariants[vi].steps;
+  const int chunk = WALL_CHUNK / T * T;
+  for (int64_t done = 0; done < nsteps;) {
+    const int n = (int)(nsteps - done < chunk ? nsteps - done : chunk);
     eval_walls(c, c->nstep, n);
-    for (int j = 0; j < n; j += T) {
-      if (R > 0)
-        hipLaunchKernelGGL(k_force_rows, dim3((unsigned)((nrows + 255) / 256)), dim3(256), 0,
-                           c->stream, c->force_Y, c->force_T + (c->nstep + 1) * R, R, c->g.ny, T,
-                           k.mr, c->force_rows);
-      hipLaunchKernelGGL(fn, dim3((unsigned)((ntiles + 3) / 4)), dim3(256), 0, c->stream,
-                         (const float*)c->buf[c->cur], c->buf[c->cur ^ 1], c->g, sc,
-                         walls_from(c, j, true), F);
-      c->cur ^= 1;
-      c->nstep += T;
+    int j = 0;
+    for (; j + T <= n; j += T) launch_tbx(c, vi, m, j);
+    for (int r = n - j; r >= 2; r = n - j) {
+      const int ri = extra_remainder_variant(c, m, r);
+      if (ri < 0) break;
+      launch_tbx(c, ri, m, j);
+      j += kTBExtVariants[ri].steps;
     }
-    done += n;
+    done += j;
+    if (j < n) {
+      // fewer than two steps left, or no shorter variant: one launch per step
+      lbm_status s = launch_check("k_tblock launch (load / displacement)");
+      if (s) return s;
+      s = step_ext(c, n - j);
+      if (s) return s;
+      done += n - j;
+    }
   }
-  if (nsteps > nb) return step_ext(c, nsteps - nb);
   return launch_check("k_tblock launch (load / displacement)");
 }
 
@@ -1055,9 +1087,9 @@ lbm_status lbm_step(lbm_ctx* c, int64_t nsteps) {
   const StepFn fn = cfg.fn[c->p.bc];
   // chunks of a multiple of T steps (at most WALL_CHUNK): the chunk's wall
   // velocities are summed first, then its steps run, T per launch with a
-  // blocked variant, so only the last T-1 steps or fewer of a total run one
-  // at a time
-  const int T = c->tb_cfg >= 0 ? kTBConfigs[c->tb_cfg].steps : 1;
+  // blocked variant; the r < T steps after the last full launch of a run take
+  // one launch of an r-step variant (r >= 2) or of the single-step kernel
+  const int T = c->tb_cfg >= 0 ? kTBVariants[c->tb_cfg].steps : 1;
   const int chunk = WALL_CHUNK / T * T;
   for (int64_t s0 = 0; s0 < nsteps; s0 += chunk) {
     const int m = (int)(nsteps - s0 < chunk ? nsteps - s0 : chunk);
@@ -1067,6 +1099,12 @@ lbm_status lbm_step(lbm_ctx* c, int64_t nsteps) {
       for (; k + T <= m; k += T) {
         launch_tb(c, c->tb_cfg, c->buf[c->cur], c->buf[c->cur ^ 1], walls_from(c, k, true));
         c->cur ^= 1;
+      }
+      const int ri = remainder_variant(c, m - k);
+      if (ri >= 0) {
+        launch_tb(c, ri, c->buf[c->cur], c->buf[c->cur ^ 1], walls_from(c, k, true));
+        c->cur ^= 1;
+        k = m;
       }
     }
     for (; k < m; ++k) {
@@ -1089,9 +1127,20 @@ struct TuneKey {
   }
 };
 
+// single-step configuration, blocked variant (-1: none) and the variants for
+// the last r steps of a run (-1: nearest shape; not kept in the cache file)
 struct TuneVal {
   int cfg, cfg2;
+  int rem[9];
 };
+
+TuneVal tune_val(int cfg, int cfg2, const int* rem) {
+  TuneVal v;
+  v.cfg = cfg;
+  v.cfg2 = cfg2;
+  for (int r = 0; r < 9; ++r) v.rem[r] = rem ? rem[r] : -1;
+  return v;
+}
 
 std::mutex g_tune_mu;
 std::map<TuneKey, TuneVal> g_tune_cache;
@@ -1120,8 +1169,8 @@ void load_tune_file() {
   while (fscanf(f, "%d %d %d %d %d %d %d %d %lf", &nx, &ny, &bc, &vec, &th, &nt, &xm, &s2,
                 &ms) == 9) {
     const int i = find_config(vec, th, nt, xm);
-    if (i >= 0 && step_config_valid(i, nx) && s2 >= -1 && s2 < kNumTBConfigs)
-      g_tune_cache[TuneKey{nx, ny, bc}] = TuneVal{i, s2};
+    if (i >= 0 && step_config_valid(i, nx) && s2 >= -1 && s2 < kNumTBVariants)
+      g_tune_cache[TuneKey{nx, ny, bc}] = tune_val(i, s2, nullptr);
   }
   fclose(f);
 }
@@ -1178,7 +1227,8 @@ lbm_status lbm_autotune(lbm_ctx* c, int32_t reps, int32_t use_cache, int32_t* h_
     auto it = g_tune_cache.find(key);
     if (it != g_tune_cache.end()) {
       c->step_cfg = it->second.cfg;
-      c->tb_cfg = it->second.cfg2 < kNumTBConfigs && tblock_fits(c->g) ? it->second.cfg2 : -1;
+      c->tb_cfg = it->second.cfg2 < kNumTBVariants && tblock_fits(c->g) ? it->second.cfg2 : -1;
+      for (int r = 0; r < 9; ++r) c->tb_rem[r] = c->tb_cfg >= 0 ? it->second.rem[r] : -1;
       if (h_index) *h_index = it->second.cfg;
       if (h_ms) *h_ms = -1.0;
       return LBM_OK;
@@ -1221,7 +1271,13 @@ lbm_status lbm_autotune(lbm_ctx* c, int32_t reps, int32_t use_cache, int32_t* h_
   // blocked variants: time per step = time per launch / steps per launch
   int best2 = -1;
   double best2_ms = 1e300;
-  for (int i = 0; i < kNumTBConfigs && s == LBM_OK && tblock_fits(c->g); ++i) {
+  int rem[9];
+  double rem_ms[9];
+  for (int r = 0; r < 9; ++r) {
+    rem[r] = -1;
+    rem_ms[r] = 1e300;
+  }
+  for (int i = 0; i < kNumTBVariants && s == LBM_OK && tblock_fits(c->g); ++i) {
     for (int r = 0; r < reps + 2; ++r) {
       if (r == 2) hipEventRecord(e0, c->stream);
       launch_tb(c, i, c->buf[c->cur], c->buf[c->cur ^ 1], ws);
@@ -1230,10 +1286,16 @@ lbm_status lbm_autotune(lbm_ctx* c, int32_t reps, int32_t use_cache, int32_t* h_
     s = hip_check(hipEventSynchronize(e1), "autotune sync");
     float ms = 0.f;
     if (s == LBM_OK) s = hip_check(hipEventElapsedTime(&ms, e0, e1), "autotune timing");
-    const double per = (double)ms / reps / kTBConfigs[i].steps;
+    const int steps = kTBVariants[i].steps;
+    const double per = (double)ms / reps / steps;
     if (s == LBM_OK && per < best2_ms) {
       best2_ms = per;
       best2 = i;
+    }
+    // the fastest launch of each step count, for the last steps of a run
+    if (s == LBM_OK && (double)ms / reps < rem_ms[steps]) {
+      rem_ms[steps] = (double)ms / reps;
+      rem[steps] = i;
     }
   }
   hipEventDestroy(e0);
@@ -1242,24 +1304,25 @@ lbm_status lbm_autotune(lbm_ctx* c, int32_t reps, int32_t use_cache, int32_t* h_
   if (best < 0) return fail(LBM_E_ARG, "no valid launch configuration");
   c->step_cfg = best;
   c->tb_cfg = best2_ms < best_ms ? best2 : -1;
+  for (int r = 0; r < 9; ++r) c->tb_rem[r] = rem[r];
   const double per_step = best2_ms < best_ms ? best2_ms : best_ms;
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     load_tune_file();
-    g_tune_cache[key] = TuneVal{best, c->tb_cfg};
-    append_tune_file(key, TuneVal{best, c->tb_cfg}, per_step);
+    g_tune_cache[key] = tune_val(best, c->tb_cfg, rem);
+    append_tune_file(key, g_tune_cache[key], per_step);
   }
   if (h_index) *h_index = best;
   if (h_ms) *h_ms = per_step;
   return LBM_OK;
 }
 
-int32_t lbm_tblock_config_count(void) { return kNumTBConfigs; }
+int32_t lbm_tblock_config_count(void) { return kNumTBVariants; }
 
 lbm_status lbm_tblock_config_info(int32_t index, int32_t* steps, int32_t* seg_rows, int32_t* nt,
                                   int32_t* pf) {
-  if (index < 0 || index >= kNumTBConfigs) return fail(LBM_E_ARG, "config index out of range");
-  const TBConfig& k = kTBConfigs[index];
+  if (index < 0 || index >= kNumTBVariants) return fail(LBM_E_ARG, "config index out of range");
+  const TBVariant& k = kTBVariants[index];
   if (steps) *steps = k.steps;
   if (seg_rows) *seg_rows = k.seg_rows;
   if (nt) *nt = k.nt;
@@ -1273,9 +1336,9 @@ int32_t lbm_steps_per_launch(const lbm_ctx* c) {
   if (c->force_rank > 0 || c->disp) {
     const int m = c->force_rank > 0 ? (c->disp ? 2 : 0) : 1;
     const int vi = extra_variant(c, m);
-    return vi >= 0 ? kTBExtraConfigs[vi].steps : 1;
+    return vi >= 0 ? kTBExtVariants[vi].steps : 1;
   }
-  return c->tb_cfg >= 0 && tblock_fits(c->g) ? kTBConfigs[c->tb_cfg].steps : 1;
+  return c->tb_cfg >= 0 && tblock_fits(c->g) ? kTBVariants[c->tb_cfg].steps : 1;
 }
 
 lbm_status lbm_get_tblock_config(const lbm_ctx* c, int32_t* index) {
@@ -1286,7 +1349,7 @@ lbm_status lbm_get_tblock_config(const lbm_ctx* c, int32_t* index) {
 
 lbm_status lbm_set_tblock_config(lbm_ctx* c, int32_t index) {
   if (!c) return fail(LBM_E_ARG, "null ctx");
-  if (index < -1 || index >= kNumTBConfigs) return fail(LBM_E_ARG, "config index out of range");
+  if (index < -1 || index >= kNumTBVariants) return fail(LBM_E_ARG, "config index out of range");
   if (index >= 0 && !tblock_fits(c->g))
     return fail(LBM_E_ARG, "grid too wide for the blocked kernel (row offsets exceed 2^31 B)");
   c->tb_cfg = index;
@@ -1296,7 +1359,7 @@ lbm_status lbm_set_tblock_config(lbm_ctx* c, int32_t index) {
 lbm_status lbm_time_tblock_config(lbm_ctx* c, int32_t index, int32_t reps, double* h_ms) {
   if (!c || !h_ms) return fail(LBM_E_ARG, "null argument");
   if (!c->initialised) return fail(LBM_E_STATE, "not initialised");
-  if (index < 0 || index >= kNumTBConfigs) return fail(LBM_E_ARG, "invalid configuration");
+  if (index < 0 || index >= kNumTBVariants) return fail(LBM_E_ARG, "invalid configuration");
   if (!tblock_fits(c->g))
     return fail(LBM_E_ARG, "grid too wide for the blocked kernel (row offsets exceed 2^31 B)");
   if (reps < 1) return fail(LBM_E_ARG, "reps must be >= 1");

@@ -204,9 +204,12 @@ __device__ inline double wg_sum(double v, double* sh) {
 
 // Per-tile partial sums in a fixed order.  mode 0: energy sum f*^T k f*;
 // mode 1: judge sums against packed physical fields ref (FP32):
-// a = sum |U - U(ref)|^2, b = sum |U|^2 over the U variables.
+// a = sum |U - U(ref)|^2, b = sum |U|^2 over the U variables;
+// mode 2: two packed field arrays, no lattice state:
+// a = sum |U(ref) - U(ref2)|^2, b = sum |U(ref2)|^2.
 __global__ __launch_bounds__(BT) void k_batch_reduce(const float* __restrict__ pool,
                                                      const float* __restrict__ ref,
+                                                     const float* __restrict__ ref2,
                                                      const InstDesc* __restrict__ descs,
                                                      const int* __restrict__ tile_inst,
                                                      int mode, double* __restrict__ partial) {
@@ -217,7 +220,18 @@ __global__ __launch_bounds__(BT) void k_batch_reduce(const float* __restrict__ p
   const int y = local / d.tiles_x;
   const int x = (local - y * d.tiles_x) * BT + (int)threadIdx.x;
   double a = 0.0, b = 0.0;
-  if (x < d.g.nx) {
+  if (x < d.g.nx && mode == 2) {
+    const int64_t ni = (int64_t)d.g.nx * d.g.ny;
+    const int64_t o = 5 * d.node0 + (int64_t)y * d.g.nx + x;
+    double Ua[NC], Ub[NC];
+    to_U(d.ic, ref[o], ref[o + ni], ref[o + 2 * ni], ref[o + 3 * ni], ref[o + 4 * ni], Ua);
+    to_U(d.ic, ref2[o], ref2[o + ni], ref2[o + 2 * ni], ref2[o + 3 * ni], ref2[o + 4 * ni], Ub);
+    for (int c = 0; c < NC; ++c) {
+      const double e = Ua[c] - Ub[c];
+      a += e * e;
+      b += Ub[c] * Ub[c];
+    }
+  } else if (x < d.g.nx) {
     const float* src = pool + d.off;
     double f[NQ][NC];
     for (int q = 0; q < NQ; ++q)
@@ -306,6 +320,10 @@ lbm_status plan(int32_t n, const lbm_params* params, Layout* L) {
     if (s) return fail(s, "instance " + std::to_string(i) + ": " + g_err);
     if (params[i].flags != 0)
       return fail(LBM_E_ARG, "batched instances take no flags (row layout, no displacement, CFL enforced)");
+    // batched instances are initialised from stress fields, whose inverse
+    // divides by c_mu
+    if (!(params[i].mu > 0))
+      return fail(LBM_E_ARG, "instance " + std::to_string(i) + ": batched instances need mu > 0");
     InstDesc& d = L->desc[i];
     memset(&d, 0, sizeof d);
     d.g = make_grid(&params[i]);
@@ -494,9 +512,10 @@ void launch_direct(lbm_batch* b, int t, int parity, int64_t step) {
   hipLaunchKernel(a.kp.func, a.kp.gridDim, a.kp.blockDim, a.kp.kernelParams, 0, b->stream);
 }
 
-lbm_status batch_reduce(lbm_batch* b, int mode, const float* ref, double* h_out2) {
+lbm_status batch_reduce(lbm_batch* b, int mode, const float* ref, double* h_out2,
+                        const float* ref2 = nullptr) {
   hipLaunchKernelGGL(k_batch_reduce, dim3((unsigned)b->L.ntiles), dim3(BT), 0, b->stream,
-                     (const float*)b->pool[b->cur], ref, (const InstDesc*)b->d_desc,
+                     (const float*)b->pool[b->cur], ref, ref2, (const InstDesc*)b->d_desc,
                      (const int*)b->d_tiles, mode, b->d_partial);
   hipLaunchKernelGGL(k_batch_reduce_final, dim3((unsigned)b->n), dim3(BT), 0, b->stream,
                      (const double*)b->d_partial, (const InstDesc*)b->d_desc,
@@ -796,6 +815,16 @@ lbm_status lbm_batch_rel_l2_fields(lbm_batch* b, const float* d_fields, double* 
   if (!b->initialised) return fail(LBM_E_STATE, "not initialised");
   std::vector<double> r(2 * b->n);
   lbm_status s = batch_reduce(b, 1, d_fields, r.data());
+  if (s) return s;
+  for (int i = 0; i < b->n; ++i) h_out[i] = r[2 * i + 1] > 0 ? sqrt(r[2 * i] / r[2 * i + 1]) : 0.0;
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_rel_l2_pair(lbm_batch* b, const float* d_a, const float* d_b,
+                                 double* h_out) {
+  if (!b || !d_a || !d_b || !h_out) return fail(LBM_E_ARG, "null argument");
+  std::vector<double> r(2 * b->n);
+  lbm_status s = batch_reduce(b, 2, d_a, r.data(), d_b);
   if (s) return s;
   for (int i = 0; i < b->n; ++i) h_out[i] = r[2 * i + 1] > 0 ? sqrt(r[2 * i] / r[2 * i + 1]) : 0.0;
   return LBM_OK;

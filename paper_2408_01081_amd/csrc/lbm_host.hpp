@@ -79,8 +79,11 @@ inline lbm_status derive(const lbm_params* p, Derived* d) {
   if (p->nx < 1 || p->ny < 1) return fail(LBM_E_ARG, "nx, ny must be >= 1");
   if (p->bc != LBM_PERIODIC && p->bc != LBM_DIRICHLET) return fail(LBM_E_ARG, "bad bc");
   if ((int64_t)p->nx * p->ny > (int64_t)1 << 31) return fail(LBM_E_ARG, "grid too large");
-  if (!(p->dx > 0) || !(p->dt > 0) || !(p->rho > 0) || !(p->mu > 0))
-    return fail(LBM_E_ARG, "dx, dt, rho, mu must be positive");
+  // mu = 0 (c_mu = 0, the limit of Section 6.1's material list) is admitted;
+  // such a lattice is initialised from the displacement gradient
+  // (lbm_init_from_gradient), since the stress form divides by c_mu
+  if (!(p->dx > 0) || !(p->dt > 0) || !(p->rho > 0) || !(p->mu >= 0))
+    return fail(LBM_E_ARG, "dx, dt, rho must be positive and mu non-negative");
   if (p->flags & ~(uint32_t)(LBM_F_PLANE_LAYOUT | LBM_F_DISPLACEMENT | LBM_F_ALLOW_UNSTABLE))
     return fail(LBM_E_ARG, "unknown flags");
   double lam = p->lambda;

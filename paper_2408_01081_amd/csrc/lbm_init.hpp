@@ -11,9 +11,15 @@
 
 namespace lbmk {
 
+// What the two field arrays of an initialisation hold: (v0, Cauchy stress)
+// or (v0, displacement gradient of u0)
+constexpr int INIT_FROM_STRESS = 0;
+constexpr int INIT_FROM_GRADIENT = 1;
+
 struct InitConst {
   double kK, km, cK, cmu, rho, dx;
   int bc;
+  int src = INIT_FROM_STRESS;
 };
 
 // Phi_x(V)/c and Phi_y(V)/c in double precision
@@ -43,9 +49,30 @@ __device__ inline void to_U(const InitConst& k, double vx, double vy, double sxx
   U[4] = -sxy * r / k.cmu;
 }
 
+// U0 at a node from the initial data: with INIT_FROM_STRESS s0 is the Cauchy
+// stress [3][ny][nx]; with INIT_FROM_GRADIENT it is the displacement
+// gradient [4][ny][nx] (du_x/dx, du_x/dy, du_y/dx, du_y/dy) and U0 follows
+// Eq. ic_vector directly, j = -c (derivatives of u0), with no division by
+// c_mu (so c_mu = 0 is allowed)
+// Eq. ic_vector: U from v and the displacement gradient (uxx = du_x/dx,
+// uxy = du_x/dy, uyx = du_y/dx, uyy = du_y/dy); linear, so it also maps
+// derivatives of these fields to derivatives of U
+__device__ inline void from_gradient(const InitConst& k, double vx, double vy, double uxx,
+                                     double uxy, double uyx, double uyy, double U[NC]) {
+  U[0] = vx;
+  U[1] = vy;
+  U[2] = -k.cK * (uxx + uyy);
+  U[3] = -k.cmu * (uxx - uyy);
+  U[4] = -k.cmu * (uyx + uxy);
+}
+
 template <typename T>
 __device__ inline void node_U(const InitConst& k, const T* v0, const T* s0, int64_t n, int64_t id,
                               double U[NC]) {
+  if (k.src == INIT_FROM_GRADIENT) {
+    from_gradient(k, v0[id], v0[n + id], s0[id], s0[n + id], s0[2 * n + id], s0[3 * n + id], U);
+    return;
+  }
   to_U(k, (double)v0[id], (double)v0[n + id], (double)s0[id], (double)s0[n + id],
        (double)s0[2 * n + id], U);
 }
@@ -100,10 +127,12 @@ __device__ inline void body_hat0(const Force& F, int x, int y, double& bx, doubl
 }
 
 // Populations f*(0) of one node (x, y): Eq. ic_second in FP64 followed by the
-// first omega = 2 collision, rounded once to FP32.  v0 [2][ny][nx], s0
-// [3][ny][nx] are the instance's fields (double or float); grad is nullable
-// [2][5][ny][nx] FP64 physical derivatives of (v, sigma_bar); F the body
-// load at t_0 (rank 0: none).
+// first omega = 2 collision, rounded once to FP32.  v0 [2][ny][nx] and s0
+// (Cauchy stress [3][ny][nx], or the displacement gradient [4][ny][nx] with
+// INIT_FROM_GRADIENT) are the instance's fields (double or float); grad is
+// nullable FP64 physical derivatives d/dx, d/dy of the input fields:
+// [2][5][ny][nx] of (v, sigma_bar), or [2][6][ny][nx] of (v, grad u0) with
+// INIT_FROM_GRADIENT; F the body load at t_0 (rank 0: none).
 template <typename T>
 __device__ inline void init_node(const T* __restrict__ v0, const T* __restrict__ s0,
                                  const double* __restrict__ grad, float* __restrict__ dst,
@@ -114,11 +143,20 @@ __device__ inline void init_node(const T* __restrict__ v0, const T* __restrict__
   double U[NC], UX[NC], UY[NC];
   node_U(k, v0, s0, n, id, U);
   if (grad) {
-    // physical derivatives of (v, sigma_bar) -> lattice derivatives of U
-    const double* gx = grad;
-    const double* gy = grad + 5 * n;
-    to_U(k, gx[id], gx[n + id], gx[2 * n + id], gx[3 * n + id], gx[4 * n + id], UX);
-    to_U(k, gy[id], gy[n + id], gy[2 * n + id], gy[3 * n + id], gy[4 * n + id], UY);
+    // physical derivatives of the input fields -> lattice derivatives of U
+    if (k.src == INIT_FROM_GRADIENT) {
+      const double* gx = grad;
+      const double* gy = grad + 6 * n;
+      from_gradient(k, gx[id], gx[n + id], gx[2 * n + id], gx[3 * n + id], gx[4 * n + id],
+                    gx[5 * n + id], UX);
+      from_gradient(k, gy[id], gy[n + id], gy[2 * n + id], gy[3 * n + id], gy[4 * n + id],
+                    gy[5 * n + id], UY);
+    } else {
+      const double* gx = grad;
+      const double* gy = grad + 5 * n;
+      to_U(k, gx[id], gx[n + id], gx[2 * n + id], gx[3 * n + id], gx[4 * n + id], UX);
+      to_U(k, gy[id], gy[n + id], gy[2 * n + id], gy[3 * n + id], gy[4 * n + id], UY);
+    }
     for (int c = 0; c < NC; ++c) {
       UX[c] *= k.dx;
       UY[c] *= k.dx;

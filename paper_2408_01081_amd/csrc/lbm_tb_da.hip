@@ -1,0 +1,12 @@
+// Instantiations of the load-free blocked kernels, Dirichlet lattices, first part of the variant table.
+#include <hip/hip_runtime.h>
+
+#include "lbm_tb_tables.hpp"
+
+namespace lbmk {
+
+void tb_fill_dirichlet_a(TBFn* out) {
+  tb_fill_range<LBM_DIRICHLET, 0>(out, std::make_integer_sequence<int, kTBSplit>{});
+}
+
+}  // namespace lbmk

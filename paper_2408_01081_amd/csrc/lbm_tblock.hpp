@@ -337,8 +337,10 @@ struct Strip {
 // Level-0 rows are read in sweep order y0 - T, y0 - T + 1, ... up to the last
 // row the segment needs and then that row again; the cursor holds the sweep
 // row and the row it reads (periodic wrap or wall clamp) and advances by one
-// compare and add instead of a wrap per row.  Row byte offsets fit in 32 bits
-// (tblock_fits).
+// compare and add instead of a wrap per row.  A row's base address is formed
+// in 64 bits (scalar), so lattices of any size the workspace holds are
+// addressed correctly; within a row the plane and column offsets fit in 32
+// bits (tblock_fits).
 struct RowCursor {
   int y;     // sweep row of the next load
   int r;     // row it reads
@@ -359,7 +361,7 @@ __device__ __forceinline__ void cursor_advance(RowCursor& c, int ny) {
 
 __device__ __forceinline__ void load_row(const float* __restrict__ src, int pitch4,
                                          const TBConst& sc, const Strip& st, int r, float v[NP]) {
-  const char* rp = (const char*)src + (uint32_t)(r * pitch4);
+  const char* rp = (const char*)src + (int64_t)r * pitch4;
   const __amdgpu_buffer_rsrc_t rs =
       __builtin_amdgcn_make_buffer_rsrc((void*)rp, (short)0, sc.extent, TB_RSRC_WORD3);
 #pragma unroll
@@ -574,7 +576,7 @@ __device__ __forceinline__ void sub_iteration(const float* __restrict__ src, flo
                                       g, sc, ws, F, ll, yt[T & 1], o, dring, y0, y1, doff, true);
     const int off = rr < y1 ? st.xs4 : TB_DROP;
     const int yo = rr < g.ny ? rr : g.ny - 1;
-    char* rp = (char*)dst + (uint32_t)(yo * pitch4);
+    char* rp = (char*)dst + (int64_t)yo * pitch4;
     const __amdgpu_buffer_rsrc_t rs =
         __builtin_amdgcn_make_buffer_rsrc((void*)rp, (short)0, sc.extent, TB_RSRC_WORD3);
 #pragma unroll
@@ -719,7 +721,8 @@ inline TBConst tblock_const(const Grid& g, float kK, float km, int seg_rows, int
   return sc;
 }
 
-// the byte offsets of a row's resource must stay below 2^31
+// the byte offsets inside one row's resource (19 plane strides + one row)
+// must stay below 2^31; row base addresses are 64-bit
 inline bool tblock_fits(const Grid& g) {
   return ((NP - 1) * g.plane + g.pitch) * 4 < ((int64_t)1 << 31);
 }

@@ -93,6 +93,22 @@ class Lattice:
         self._keep = ts
         return self
 
+    def init_from_gradient(self, v0, gradu0, grad=None):
+        """Second-order initialisation from the initial velocity [2][ny][nx]
+        and displacement gradient [4][ny][nx] (du_x/dx, du_x/dy, du_y/dx,
+        du_y/dy), optional exact d/dx, d/dy of these six fields
+        [2][6][ny][nx]; float64.  Needed for mu = 0, where the stress does
+        not determine U0."""
+        ts = [t.to(self.device, torch.float64).contiguous() if t is not None else None
+              for t in (v0, gradu0, grad)]
+        self._check_shape(ts[0], (2, self.ny, self.nx))
+        self._check_shape(ts[1], (4, self.ny, self.nx))
+        if ts[2] is not None:
+            self._check_shape(ts[2], (2, 6, self.ny, self.nx))
+        check(self.L.lbm_init_from_gradient(self.ctx, _ptr(ts[0]), _ptr(ts[1]), _ptr(ts[2])))
+        self._keep = ts
+        return self
+
     def set_populations(self, f):
         t = f.to(self.device, torch.float32).contiguous()
         self._check_shape(t, (4, 5, self.ny, self.nx))

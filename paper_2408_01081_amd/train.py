@@ -106,24 +106,26 @@ def window_errors(net, data, mat, circular, batch, max_pairs=4096, seed=0):
     return np.concatenate(errs)
 
 
-def rel_l2_U(a, b, material):
-    """||U(a) - U(b)|| / ||U(b)|| per sample, U = first-order system variables.
-    material: per sample [B][3] or per pixel [B][3][H][W] (lambda, mu, rho)."""
-    mt = material.double()
-    if mt.dim() == 2:
-        mt = mt[:, :, None, None]
-
-    def U(f):
-        lam, mu, rho = mt[:, 0:1], mt[:, 1:2], mt[:, 2:3]
-        cK = torch.sqrt((lam + mu) / rho)
-        cm = torch.sqrt(mu / rho)
-        f = f.double()
-        s = f[:, 2:] / rho
-        return torch.cat([f[:, :2], (-(s[:, 0:1] + s[:, 1:2]) / (2 * cK)),
-                          (-(s[:, 0:1] - s[:, 1:2]) / (2 * cm)), (-s[:, 2:3] / cm)], dim=1)
-    ua, ub = U(a), U(b)
-    d = (ua - ub).flatten(1).norm(dim=1)
-    return (d / ub.flatten(1).norm(dim=1)).cpu().numpy()
+def rel_l2_U(a, b, material, chunk=64):
+    """||U(a) - U(b)|| / ||U(b)|| per sample, U = first-order system variables
+    of each sample's material, computed by the library (lbm_batch_rel_l2_pair:
+    a batch of field-only instances, no lattice state).  a, b: [B][5][H][W]
+    fields (v, sigma_bar); material: per sample [B][3] or per pixel
+    [B][3][H][W] (lambda, mu, rho, constant over the window)."""
+    mt = material if material.dim() == 2 else material[:, :, 0, 0]
+    mt = mt.double().cpu().numpy()
+    Bn, _, H, W = a.shape
+    out = []
+    for k in range(0, Bn, chunk):
+        insts = []
+        for lam, mu, rho in mt[k:k + chunk]:
+            # any admissible time step: only the material enters U
+            cmax = math.sqrt((lam + 2.0 * mu) / rho)  # sqrt(c_K^2 + c_mu^2)
+            insts.append(dict(nx=W, ny=H, dx=1.0, dt=0.25 / cmax, lam=float(lam), mu=float(mu),
+                              rho=float(rho), bc=0))
+        batch = Batch(insts, device=a.device)
+        out.append(batch.rel_l2_pair(a[k:k + chunk].reshape(-1), b[k:k + chunk].reshape(-1)))
+    return np.concatenate(out)
 
 
 def train(net, sets, minutes, batch, lr0=1e-3, lr_end=2e-5, seed=0, log_every=100,

@@ -206,6 +206,18 @@ class Elastodynamics:
         comps = [self.vx, self.vy, self.sxx * r, self.syy * r, self.sxy * r]
         return np.stack([np.stack([c.d(a)(x, y, t) for c in comps]) for a in ("x", "y")])
 
+    def displacement_gradient(self, x, y, t):
+        """(du_x/dx, du_x/dy, du_y/dx, du_y/dy) at points, array [4][...]."""
+        return np.stack([self.ux.d("x")(x, y, t), self.ux.d("y")(x, y, t),
+                         self.uy.d("x")(x, y, t), self.uy.d("y")(x, y, t)])
+
+    def gradient_field_derivatives(self, x, y, t):
+        """d/dx and d/dy of (v_x, v_y, du_x/dx, du_x/dy, du_y/dx, du_y/dy):
+        array [2][6][...]."""
+        comps = [self.vx, self.vy, self.ux.d("x"), self.ux.d("y"), self.uy.d("x"),
+                 self.uy.d("y")]
+        return np.stack([np.stack([c.d(a)(x, y, t) for c in comps]) for a in ("x", "y")])
+
     def body_force(self, x, y, t):
         """Physical body load b_bar = rho * b, array [2][...]."""
         r = self.mat.rho

@@ -1,6 +1,7 @@
 """The C-ABI library loads without a GPU and exports every entry point that
 include/*.h declares; host-side validation works without device calls."""
 import ctypes
+import math
 import glob
 import os
 import re
@@ -58,3 +59,49 @@ def test_product_path_has_no_oracle_dependency():
         if path.endswith((".py", ".hip", ".hpp", ".cpp", ".h")):
             text = open(path).read()
             assert "oracle" not in text.replace("Oracle", ""), path
+
+
+def test_blocked_variants_take_large_row_major_grids():
+    # row base addresses of the blocked kernel are formed in 64 bits, so an
+    # 8192^2 row-major lattice (row offsets up to 5.4 GB) may use it; in the
+    # plane-major layout one row's 20 planes span more than 2^31 bytes at
+    # this size, beyond the 32-bit offsets inside a row, and it is refused
+    from paper_2408_01081_amd import _lib
+    L = _lib.load()
+    N = 8192
+    for flags, want in ((0, 0), (1, 1)):
+        p = _lib.LbmParams(N, N, 1.0 / N, 0.125 / N, 1.0, 1.0, 1.0, 0, 0, flags)
+        nb = L.lbm_workspace_bytes(ctypes.byref(p))
+        assert nb >= 2 * 80 * N * N
+        h = ctypes.c_void_p()
+        assert L.lbm_create(ctypes.byref(p), ctypes.c_void_p(256), nb, None, ctypes.byref(h)) == 0
+        try:
+            assert L.lbm_set_tblock_config(h, 40) == want, L.lbm_last_error()
+        finally:
+            L.lbm_destroy(h)
+
+
+def test_zero_shear_modulus_is_admitted_with_the_gradient_initialisation():
+    # mu = 0 (c_mu = 0) passes set-up; the stress initialisation, which
+    # divides by c_mu, refuses it before any device work; batched instances
+    # (initialised from stress) refuse it at planning
+    from paper_2408_01081_amd import _lib
+    L = _lib.load()
+    p = _lib.LbmParams(32, 32, 1.0 / 32, 0.4 / 32, 1.5, 0.0, 1.0, 0, 0, 0)
+    nb = L.lbm_workspace_bytes(ctypes.byref(p))
+    assert nb > 0
+    h = ctypes.c_void_p()
+    assert L.lbm_create(ctypes.byref(p), ctypes.c_void_p(256), nb, None, ctypes.byref(h)) == 0
+    try:
+        kK, km, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        assert L.lbm_lattice_constants(h, ctypes.byref(kK), ctypes.byref(km), ctypes.byref(c)) == 0
+        assert km.value == 0.0 and abs(kK.value - math.sqrt(1.5) * 0.4) < 1e-15
+        fake = ctypes.c_void_p(4096)
+        assert L.lbm_init(h, fake, fake, None) == 1
+        assert b"lbm_init_from_gradient" in L.lbm_last_error()
+    finally:
+        L.lbm_destroy(h)
+    arr = (_lib.LbmParams * 2)(_lib.LbmParams(32, 32, 1.0 / 32, 0.4 / 32, 1.0, 0.5, 1.0, 0, 0, 0), p)
+    assert L.lbm_batch_workspace_bytes(2, ctypes.cast(arr, ctypes.c_void_p)) == 0
+    neg = _lib.LbmParams(32, 32, 1.0 / 32, 0.4 / 32, 1.5, -0.1, 1.0, 0, 0, 0)
+    assert L.lbm_workspace_bytes(ctypes.byref(neg)) == 0

@@ -186,3 +186,65 @@ def test_blocked_kernels_match_oracle_dirichlet_walls():
         lat.step(n)
         U = lat.moments_U().double().cpu().numpy()
         assert oracle.rel_l2(U, ref) < 1e-5, c
+
+
+@gpu
+@pytest.mark.parametrize("bc", [synth.PERIODIC, synth.DIRICHLET])
+def test_every_remainder_bitwise_equal_single_steps(bc):
+    # lbm_step(n) with a T-step variant runs floor(n / T) full launches and
+    # the r = n mod T steps left in one launch of an r-step variant (r >= 2)
+    # or of the single-step kernel: for every T and every r, both launch
+    # shapes per T (fixed segments and one wave per resident slot), the state
+    # is the single-step state bit for bit (Dirichlet with moving walls)
+    torch = _torch()
+    from paper_2408_01081_amd.lbm import Lattice
+    prob = synth.plane_wave_problem(203, 71, bc, seed=37, kmax=3)
+    v0, sb0 = prob.initial_fields()
+    nmax = 3 * 8
+    W, T = prob.wall_table(nmax)
+    lat = Lattice(prob.nx, prob.ny, prob.dx, prob.dt, prob.lam, prob.mu, prob.rho, prob.bc)
+
+    def start(cfg):
+        lat.init(torch.from_numpy(v0), torch.from_numpy(sb0))
+        if bc == synth.DIRICHLET:
+            lat.set_wall_velocity(torch.from_numpy(W), torch.from_numpy(T))
+        lat.tblock_config = cfg
+
+    start(-1)
+    ref = {0: lat.populations()}
+    for n in range(1, nmax + 1):
+        lat.step(1)
+        ref[n] = lat.populations()
+    picks = {}
+    for c in lat.tblock_configs():
+        picks.setdefault((c["steps"], c["seg_rows"] <= 0), c["index"])
+    for (steps, _), cfg in sorted(picks.items()):
+        for n in range(steps, 2 * steps + 1) if steps < 8 else range(8, nmax + 1):
+            start(cfg)
+            lat.step(n)
+            got = lat.populations()
+            assert torch.equal(got.view(torch.int32), ref[n].view(torch.int32)), (cfg, steps, n)
+
+
+@gpu
+def test_blocked_kernel_on_lattice_beyond_32_bit_row_offsets():
+    # 8192^2 row-major: row byte offsets reach 5.4 GB, past 2^32; the blocked
+    # kernel forms row addresses in 64 bits and gives the single-step state
+    # bit for bit (8 + 8 steps and a 3-step launch for the rest)
+    torch = _torch()
+    from paper_2408_01081_amd.lbm import Lattice
+    N = 8192
+    prob = synth.plane_wave_problem(N, N, synth.PERIODIC, seed=41, kmax=4)
+    v0, sb0 = (torch.from_numpy(a).cuda() for a in prob.initial_fields())
+    lat = Lattice(prob.nx, prob.ny, prob.dx, prob.dt, prob.lam, prob.mu, prob.rho, prob.bc)
+    idx = {(c["steps"], c["seg_rows"], c["nontemporal"], c["prefetch"]): c["index"]
+           for c in lat.tblock_configs()}
+    out = []
+    for cfg in (-1, idx[(8, 0, 0, 2)]):
+        lat.init(v0, sb0)
+        lat.tblock_config = cfg
+        lat.step(19)
+        out.append(lat.moments_U())
+    del lat
+    assert torch.isfinite(out[0]).all()
+    assert torch.equal(out[0].view(torch.int32), out[1].view(torch.int32))

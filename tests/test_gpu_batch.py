@@ -190,3 +190,23 @@ def test_batch_autotune_keeps_state():
     assert -1 <= idx < len(b.tblock_configs()) and ms > 0
     assert b.tblock_config == idx and b.steps == 3
     assert np.array_equal(b.moments(system=True).cpu().numpy(), before)
+
+
+@gpu
+def test_batch_rel_l2_pair_of_field_arrays():
+    # per-instance ||U(a) - U(b)|| / ||U(b)|| with each instance's material
+    # (no lattice state involved), against the oracle's field conversion
+    torch = _torch()
+    from paper_2408_01081_amd.batch import Batch
+    probs = _problems()
+    b = Batch([_params(p) for p in probs])
+    g = np.random.default_rng(12)
+    fa = [g.standard_normal((5, p.ny, p.nx)) for p in probs]
+    fb = [f + 0.01 * (i + 1) * g.standard_normal(f.shape) for i, f in enumerate(fa)]
+    got = b.rel_l2_pair(b.pack(fa, torch.float32), b.pack(fb, torch.float32))
+    for i, p in enumerate(probs):
+        s = oracle.Setup(p.nx, p.ny, p.dx, p.dt, p.lam, p.mu, p.rho, p.bc)
+        a32, b32 = (np.asarray(x, dtype=np.float32).astype(np.float64) for x in (fa[i], fb[i]))
+        Ua, Ub = s.U_from_fields(a32[:2], a32[2:]), s.U_from_fields(b32[:2], b32[2:])
+        want = np.sqrt(np.sum((Ua - Ub) ** 2) / np.sum(Ub ** 2))
+        assert abs(got[i] - want) <= 1e-12 * want, (i, got[i], want)

@@ -317,3 +317,61 @@ def test_steps_per_launch_reports_the_path():
     assert lat2.steps_per_launch == 8
     lat2.set_body_force(*(torch.from_numpy(a) for a in _random_load(g, 16, 256, 128, 10)))
     assert lat2.steps_per_launch == 8                   # the load-only kernel has T = 8
+
+
+@gpu
+@pytest.mark.parametrize("bc", [synth.PERIODIC, synth.DIRICHLET])
+@pytest.mark.parametrize("extras", ["load", "disp", "both", "load32"])
+def test_blocked_extras_every_remainder_bitwise_equal_single_steps(bc, extras):
+    # with a load and/or the displacement state, lbm_step(n) runs full
+    # launches of the T-step kernel with those extras and the steps left in
+    # launches of shorter variants (the longest that fits first; a last
+    # single step in the one-step kernel): every remainder gives the state of
+    # one launch per step bit for bit
+    torch = _torch()
+    from paper_2408_01081_amd.lbm import Lattice
+    N, ny = 150, 40
+    prob = synth.plane_wave_problem(N, ny, bc, seed=43, kmax=3)
+    v0, sb0 = prob.initial_fields()
+    nmax = 2 * 8
+    g = np.random.default_rng(7)
+    R = {"load": 9, "disp": 0, "both": 12, "load32": 20}[extras]
+    disp = extras in ("disp", "both")
+    W, T = prob.wall_table(nmax)
+    u0 = torch.from_numpy(g.standard_normal((2, ny, N)))
+    load = [torch.from_numpy(a) for a in _random_load(g, R, N, ny, nmax)] if R else None
+    lat = Lattice(prob.nx, prob.ny, prob.dx, prob.dt, prob.lam, prob.mu, prob.rho, prob.bc,
+                  displacement=disp)
+    if load:
+        lat.set_body_force(*load)
+
+    def start(cfg):
+        lat.init(torch.from_numpy(v0), torch.from_numpy(sb0))
+        if disp:
+            lat.init_displacement(u0)
+        if bc == synth.DIRICHLET:
+            lat.set_wall_velocity(torch.from_numpy(W), torch.from_numpy(T))
+        lat.tblock_config = cfg
+
+    def state():
+        return [lat.populations()] + ([lat.displacement()] if disp else [])
+
+    start(-1)
+    ref = {}
+    for n in range(1, nmax + 1):
+        lat.step(1)
+        ref[n] = state()
+    seen = set()
+    for c in lat.tblock_configs():
+        start(c["index"])
+        T_run = lat.steps_per_launch
+        key = (T_run, c["seg_rows"] <= 0)
+        if T_run == 1 or key in seen:
+            continue
+        seen.add(key)
+        for n in range(T_run, min(2 * T_run, nmax) + 1):
+            start(c["index"])
+            lat.step(n)
+            for a, b in zip(state(), ref[n]):
+                assert torch.equal(a.view(torch.int32), b.view(torch.int32)), (c, T_run, n)
+    assert seen

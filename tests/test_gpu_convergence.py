@@ -39,7 +39,13 @@ def _gpu_norms(N, bc, cK2, cmu2, nsteps, c=2.5):
         lat.set_wall_velocity(*map(t, prob.wall_table(nsteps)))
     X, Y = synth.node_coords(N, N, dx)
     v0, sb0, u0 = e.fields(X, Y, 0.0)
-    lat.init(t(v0), t(sb0), t(e.field_gradients(X, Y, 0.0)))
+    if cmu2 > 0:
+        lat.init(t(v0), t(sb0), t(e.field_gradients(X, Y, 0.0)))
+    else:
+        # c_mu = 0: the stress does not determine j_d, j_xy; Eq. ic_vector
+        # from v0 and grad u0 (with the exact derivatives of both)
+        lat.init_from_gradient(t(v0), t(e.displacement_gradient(X, Y, 0.0)),
+                               t(e.gradient_field_derivatives(X, Y, 0.0)))
     lat.init_displacement(t(u0))
     lat.set_reference(*map(t, prob.reference_table(nsteps)))
     lat.track_errors(True)
@@ -49,19 +55,26 @@ def _gpu_norms(N, bc, cK2, cmu2, nsteps, c=2.5):
 
 @gpu
 @pytest.mark.parametrize("bc", [synth.PERIODIC, synth.DIRICHLET])
-def test_error_norms_match_oracle(bc):
+@pytest.mark.parametrize("cK2,cmu2", [(1.1, 0.4), (1.5, 0.0)])
+def test_error_norms_match_oracle(bc, cK2, cmu2):
     N, nsteps = 40, 100
-    got, prob = _gpu_norms(N, bc, 1.1, 0.4, nsteps)
+    got, prob = _gpu_norms(N, bc, cK2, cmu2, nsteps)
     assert got["levels"] == nsteps + 1
     e = prob.sol
     s = oracle.Setup(N, N, prob.dx, prob.dt, prob.lam, prob.mu, 1.0, bc)
     X, Y = s.nodes()
     xb, yb = s.wall_points()
     v0, sb0, u0 = e.fields(X, Y, 0.0)
-    sim = oracle.Simulation(s, v0, sb0, e.field_gradients(X, Y, 0.0), u0,
-                            body=lambda t: e.body_force(X, Y, t),
-                            wall=(lambda t: np.stack([e.vx(xb, yb, t), e.vy(xb, yb, t)], 1))
-                            if bc else None)
+    wall = (lambda t: np.stack([e.vx(xb, yb, t), e.vy(xb, yb, t)], 1)) if bc else None
+    body = lambda t: e.body_force(X, Y, t)
+    if cmu2 > 0:
+        sim = oracle.Simulation(s, v0, sb0, e.field_gradients(X, Y, 0.0), u0, body=body,
+                                wall=wall)
+    else:
+        d = e.gradient_field_derivatives(X, Y, 0.0)
+        sim = oracle.Simulation(s, v0, None, [(d[a][:2], d[a][2:].reshape(2, 2, N, N))
+                                              for a in range(2)], u0, body=body, wall=wall,
+                                gradu0=e.displacement_gradient(X, Y, 0.0).reshape(2, 2, N, N))
     nrm = oracle.SpaceTimeNorms(prob.dx, prob.dt)
 
     def rec(n, U, u):
@@ -88,7 +101,7 @@ def _orders(errs):
 
 @gpu
 @pytest.mark.parametrize("bc", [synth.PERIODIC, synth.DIRICHLET])
-@pytest.mark.parametrize("cK2,cmu2", [(1.4, 0.1), (1.1, 0.4)])
+@pytest.mark.parametrize("cK2,cmu2", [(1.5, 0.0), (1.4, 0.1), (1.1, 0.4)])
 def test_paper_convergence_study(bc, cK2, cmu2):
     res = {}
     for N in RESOLUTIONS:
@@ -105,12 +118,17 @@ def test_paper_convergence_study(bc, cK2, cmu2):
     # Section 6.1: second order for displacement and stress in both norms
     # with periodic boundaries; with Dirichlet walls second order in L2
     # (the stress Linf error drops to first order near the walls)
-    keys = ["u L2rel", "s L2rel"] + (["u Linfrel", "s Linfrel"] if bc == synth.PERIODIC
-                                     else ["u Linfrel"])
+    # With c_mu = 0 the oracle shows no drop of the Dirichlet stress Linf
+    # order up to dx = 1/320 (orders 2.01, 2.03, 2.04, 1.98 on the same
+    # run): the first-order boundary term, which the paper sees only on
+    # fine lattices for this material, stays below the second-order error
+    # at these resolutions, so it is held to second order here.
+    wall_first_order = bc == synth.DIRICHLET and cmu2 > 0
+    keys = ["u L2rel", "s L2rel", "u Linfrel"] + ([] if wall_first_order else ["s Linfrel"])
     for key in keys:
         orders = table[key][1]
         assert all(1.7 < o < 2.3 for o in orders), (key, orders)
-    if bc == synth.DIRICHLET:
+    if wall_first_order:
         # the wall rule's first-order stress error: the Linf order falls
         # towards 1 (for (1.4, 0.1) only on the finer lattices)
         orders = table["s Linfrel"][1]

@@ -239,6 +239,42 @@ def test_full_size_dirichlet_2048x1024_windowed_oracle():
 
 
 @gpu
+@pytest.mark.timeout(1500)
+def test_full_size_dirichlet_2048x1024_bench_configuration_all_nodes():
+    # the benchmark's Dirichlet lattice in the benchmark's launch
+    # configuration (autotuner, then the stepping re-rank of bench.py) with
+    # its rank-30 time-dependent walls: 1000 steps, every node against the
+    # full-grid FP64 C oracle at the spec bar
+    torch = _torch()
+    import bench
+    prob = synth.plane_wave_problem(2048, 1024, synth.DIRICHLET, seed=2, dx=1.0 / 1024)
+    n = 1000
+    v0, sb0 = prob.initial_fields()
+    fields = (torch.from_numpy(v0).cuda(), torch.from_numpy(sb0).cuda())
+    lat = _lattice(prob)
+    lat.init(*fields)
+    W, T = prob.wall_table(max(n, bench.RERANK_STEPS + 64))
+    lat.set_wall_velocity(torch.from_numpy(W).cuda(), torch.from_numpy(T).cuda())
+    lat.autotune(reps=10, use_cache=True)
+    bench.rerank(lat, fields)
+    cfg = lat.tblock_config
+    print("variant %d, %d steps per launch" % (cfg, lat.steps_per_launch), flush=True)
+    lat.step(n)
+    U = lat.moments_U().double().cpu().numpy()
+    s = oracle.Setup(prob.nx, prob.ny, prob.dx, prob.dt, prob.lam, prob.mu, prob.rho, prob.bc)
+    sim = oracle.Simulation(s, v0, sb0, wall=prob.wall_velocity)
+    for k in range(0, n, 100):   # the oracle takes minutes: report progress
+        sim.advance(min(100, n - k))
+        print("oracle at step %d" % sim.n, flush=True)
+    want = sim.U()
+    err = oracle.rel_l2(U, want)
+    worst = float(np.abs(U - want).max() / np.abs(want).max())
+    print("2048x1024 Dirichlet, variant %d, %d steps, all nodes: rel-L2 %.3e, max %.3e"
+          % (cfg, n, err, worst))
+    assert err < 1e-5
+
+
+@gpu
 @pytest.mark.parametrize("model,name", [(0, "plane_strain"), (1, "plane_stress"),
                                         (2, "continuum_2d")])
 @pytest.mark.parametrize("bc", [synth.PERIODIC, synth.DIRICHLET])

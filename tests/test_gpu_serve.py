@@ -83,12 +83,19 @@ def test_rollout_mixed_returns_valid_states():
     # the identity map: windows where the fields barely move are accepted
     net.set_params(pack_params(init_params(3, 0.0)).astype(np.float32))
     f0 = torch.cat([torch.from_numpy(prob.v0), torch.from_numpy(prob.sb0)]).float().cuda()
-    for tol in (0.05, 0.2, 0.6):
+    acc = []
+    for tol in (0.0, 0.05, 0.2, 0.6, 1e30):
         ro = Rollout(net, prob, chunk=4, tol=tol)
         out, st = ro.run(f0, 6)
-        assert st["accepted"] + st["fallbacks"] >= 6 - st["accepted"] or st["fallbacks"] == 0
+        # every window is either accepted or replaced by its replay
+        assert st["accepted"] + st["fallbacks"] == 6, st
+        # the judged errors include each rejected window's: the largest is
+        # above the tolerance exactly when some window fell back
+        assert (st["fallbacks"] == 0) == (st["window_err_max"] <= tol), (tol, st)
         assert torch.isfinite(out).all()
-        assert st["window_err_max"] is not None
+        acc.append(st["accepted"])
+    # nothing passes a zero tolerance, everything an infinite one
+    assert acc[0] == 0 and acc[-1] == 6, acc
 
 
 @gpu

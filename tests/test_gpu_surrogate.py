@@ -114,14 +114,16 @@ def test_adam_step_matches_reference_and_loss_decreases():
     x = torch.from_numpy(inp.astype(np.float32)).cuda()
     t = torch.from_numpy(tgt.astype(np.float32)).cuda()
     lr = 1e-3
-    net.train_step(x, t, circular=True, lr=lr)
-    g = net.get_grads().double().cpu().numpy()
-    v1 = net.get_params().double().cpu().numpy()
-    # reference Adam (first step) with the same gradient
-    m = 0.1 * g
-    vv = 0.001 * g * g
-    want = v0.astype(np.float64) - lr * (m / 0.1) / (np.sqrt(vv / 0.001) + 1e-8)
-    assert np.max(np.abs(v1 - want)) < 1e-6 + 1e-5 * lr
+    # the FP64 reference Adam (bias-corrected moments) fed the kernel's own
+    # gradient of each step, over several steps
+    Pr = {"v": v0.astype(np.float64)}
+    M, V = {"v": np.zeros_like(Pr["v"])}, {"v": np.zeros_like(Pr["v"])}
+    for step in range(1, 5):
+        net.train_step(x, t, circular=True, lr=lr)
+        g = net.get_grads().double().cpu().numpy()
+        R.adam_update(Pr, {"v": g}, M, V, step, lr)
+        v = net.get_params().double().cpu().numpy()
+        assert np.max(np.abs(v - Pr["v"])) < 1e-6 + 1e-5 * lr, step
     losses = [net.train_step(x, t, circular=True, lr=lr) for _ in range(30)]
     assert losses[-1] < 0.5 * losses[0], losses
 

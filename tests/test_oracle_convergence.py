@@ -12,7 +12,7 @@ from oracle import Setup, Simulation
 
 
 def run_mms(N, sol_fn, mat, bc, tf=None, nsteps=None, dt=None, init_correction=True,
-            printed=0.0, exact_grads=True):
+            printed=0.0, exact_grads=True, from_gradient=False):
     ux, uy = sol_fn(mat)
     e = synth.Elastodynamics(ux, uy, mat)
     dx = 1.0 / N
@@ -20,10 +20,21 @@ def run_mms(N, sol_fn, mat, bc, tf=None, nsteps=None, dt=None, init_correction=T
     X, Y = s.nodes()
     xb, yb = s.wall_points()
     v0, sb0, u0 = e.fields(X, Y, 0.0)
-    df = e.field_gradients(X, Y, 0.0) if exact_grads else None
     body = (lambda t: e.body_force(X, Y, t)) if e.has_body_force() else None
     wall = (lambda t: np.stack([e.vx(xb, yb, t), e.vy(xb, yb, t)], 1)) if bc else None
-    sim = Simulation(s, v0, sb0, df, u0, body=body, wall=wall, init_correction=init_correction)
+    if from_gradient:
+        # Eq. ic_vector from v0 and grad u0 (the c_mu = 0 material needs it)
+        gu = e.displacement_gradient(X, Y, 0.0).reshape(2, 2, N, N)
+        df = None
+        if exact_grads:
+            d = e.gradient_field_derivatives(X, Y, 0.0)
+            df = [(d[a][:2], d[a][2:].reshape(2, 2, N, N)) for a in range(2)]
+        sim = Simulation(s, v0, None, df, u0, body=body, wall=wall,
+                         init_correction=init_correction, gradu0=gu)
+    else:
+        df = e.field_gradients(X, Y, 0.0) if exact_grads else None
+        sim = Simulation(s, v0, sb0, df, u0, body=body, wall=wall,
+                         init_correction=init_correction)
     nrm = oracle.SpaceTimeNorms(dx, s.dt)
 
     def rec(n, U, u):
@@ -80,6 +91,42 @@ def test_periodic_moving_mms(cK2, cmu2):
                bc=oracle.PERIODIC, tf=0.5, dt=lambda dx: 0.4 * dx)
     for key in ("u", "s", "uinf"):
         assert all(3.7 < x < 4.3 for x in r[key]), (key, r[key])
+
+
+@pytest.mark.parametrize("bc", [oracle.PERIODIC, oracle.DIRICHLET])
+def test_zero_shear_speed_material(bc):
+    # (c_K^2, c_mu^2) = (1.5, 0.0) of Section 6.1's material list: j_d and
+    # j_xy carry no waves, the stress is isotropic, and the initial state
+    # comes from grad u0 (Eq. ic_vector); second order in L2 for u and
+    # sigma_bar with both boundary types (Dirichlet, as in the paper: second
+    # order in L2 at these resolutions)
+    mat = synth.Material(1.5, 0.0, 1.0)
+    r = ratios((20, 40, 80), sol_fn=lambda m: synth.periodic_moving_solution(), mat=mat, bc=bc,
+               tf=0.5, dt=lambda dx: 0.4 * dx, from_gradient=True)
+    lo, hi = (3.7, 4.3) if bc == oracle.PERIODIC else (3.2, 4.6)
+    for key in ("u", "s"):
+        assert all(lo < x < hi for x in r[key]), (key, r[key])
+
+
+def test_gradient_and_stress_initialisations_agree():
+    # for c_mu > 0 the two routes to U0 (Eq. ic_vector from grad u0, and the
+    # inverse of Eq. sigma_num from the Cauchy stress of the same u0) and to
+    # its derivatives give the same initial populations
+    mat = synth.Material(1.1, 0.4, 1.3)
+    e = synth.Elastodynamics(*synth.periodic_moving_solution(), mat)
+    N = 24
+    s = Setup(N, N, 1.0 / N, 0.4 / N, (mat.cK2 - mat.cmu2) * mat.rho, mat.cmu2 * mat.rho,
+              mat.rho, oracle.PERIODIC)
+    X, Y = s.nodes()
+    v0, sb0, u0 = e.fields(X, Y, 0.0)
+    gu = e.displacement_gradient(X, Y, 0.0).reshape(2, 2, N, N)
+    assert np.allclose(s.U_from_displacement_gradient(v0, gu), s.U_from_fields(v0, sb0),
+                       rtol=1e-12, atol=1e-12)
+    d = e.gradient_field_derivatives(X, Y, 0.0)
+    df = [(d[a][:2], d[a][2:].reshape(2, 2, N, N)) for a in range(2)]
+    a = Simulation(s, v0, None, df, gradu0=gu).f
+    b = Simulation(s, v0, sb0, e.field_gradients(X, Y, 0.0)).f
+    assert np.allclose(a, b, rtol=1e-12, atol=1e-12)
 
 
 def test_dirichlet_moving_mms():

@@ -103,3 +103,72 @@ def test_identity_network_reproduces_input():
     P["out.w"][:] = 0
     fw = S.Forward(P, inp, True)
     assert np.allclose(fw.out, inp[:, :5], atol=1e-12)
+
+
+def test_chebyshev_basis_is_cos_n_theta():
+    # T_n(cos theta) = cos(n theta): catches a wrong recurrence or order
+    theta = np.linspace(0.0, math.pi, 37)
+    T = S.chebyshev(np.cos(theta))
+    assert T.shape == (37, S.NBASIS)
+    for n in range(S.NBASIS):
+        assert np.allclose(T[:, n], np.cos(n * theta), atol=1e-14), n
+
+
+def _material_input(theta, rho=1.3):
+    # per-sample material with atan2(c_mu, c_K) = theta and c_K^2 + c_mu^2 = 2
+    cK, cm = math.sqrt(2) * math.cos(theta), math.sqrt(2) * math.sin(theta)
+    inp = np.zeros((1, 8, 4, 4))
+    inp[:, 6] = rho * cm * cm             # mu
+    inp[:, 5] = rho * cK * cK - inp[:, 6]  # lambda (c_K^2 = (lambda + mu) / rho)
+    inp[:, 7] = rho
+    return inp
+
+
+def test_conditioning_maps_the_angle_range_to_unit_interval():
+    # the end points of the angle range go to -1 and +1, its midpoint to 0,
+    # and the map is affine in theta in between
+    lo, hi = S.THETA_LO, S.THETA_HI
+    for theta, want in ((lo, -1.0), (hi, 1.0), (0.5 * (lo + hi), 0.0),
+                        (lo + 0.25 * (hi - lo), -0.5)):
+        assert abs(S.conditioning(_material_input(theta))[0] - want) < 1e-12, theta
+
+
+def test_pool_and_upsample_values():
+    # 2 x 2 means and nearest-neighbour copies, on a known array
+    x = np.arange(16.0).reshape(1, 4, 4, 1)
+    assert np.array_equal(S.pool2(x)[0, :, :, 0], [[2.5, 4.5], [10.5, 12.5]])
+    y = np.array([[1.0, 2.0], [3.0, 4.0]]).reshape(1, 2, 2, 1)
+    assert np.array_equal(S.up2(y)[0, :, :, 0], [[1, 1, 2, 2], [1, 1, 2, 2],
+                                                  [3, 3, 4, 4], [3, 3, 4, 4]])
+
+
+def test_fields_to_U_matches_oracle_conversion():
+    # the surrogate's pre-map and the lattice oracle's conversion (pinned by
+    # the oracle tests through Eq. sigma_num) agree for per-sample materials
+    import oracle
+    g = np.random.default_rng(8)
+    inp = _input(g, 3, 6, 5)
+    cK, cm, rho = S.material_speeds(inp)
+    U = S.fields_to_U(inp[:, :5], cK, cm, rho)
+    for b in range(3):
+        lam, mu, r = inp[b, 5, 0, 0], inp[b, 6, 0, 0], inp[b, 7, 0, 0]
+        s = oracle.Setup(5, 6, 1.0, 0.01, lam, mu, r, oracle.PERIODIC)
+        want = s.U_from_fields(inp[b, :2], inp[b, 2:5])
+        assert np.allclose(U[b], want, rtol=1e-13, atol=1e-13), b
+
+
+def test_adam_constant_gradient_moves_lr_per_step():
+    # with a constant gradient g the bias-corrected moments are exactly g and
+    # g^2 at every step, so each step moves by lr g / (|g| + eps): after n
+    # steps P = P0 - n lr g / (|g| + eps) (a missing or wrong bias correction
+    # makes the early steps shorter or longer)
+    g = np.random.default_rng(9)
+    grad = g.standard_normal((7, 3))
+    P = {"w": g.standard_normal((7, 3))}
+    P0 = P["w"].copy()
+    M, V = {"w": np.zeros((7, 3))}, {"w": np.zeros((7, 3))}
+    lr, eps = 1e-2, 1e-8
+    for n in range(1, 6):
+        S.adam_update(P, {"w": grad}, M, V, n, lr, eps=eps)
+        want = P0 - n * lr * grad / (np.abs(grad) + eps)
+        assert np.allclose(P["w"], want, rtol=0, atol=1e-13), n
