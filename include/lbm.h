@@ -410,6 +410,24 @@ lbm_status lbm_batch_rel_l2_fields(lbm_batch* b, const float* d_fields, double* 
 lbm_status lbm_batch_rel_l2_pair(lbm_batch* b, const float* d_a, const float* d_b,
                                  double* h_out);
 
+/* For callers that cannot allocate device memory (code that must not call
+ * hipMalloc, such as tight serving or evaluation loops and harnesses that
+ * forbid it): lbm_batch_rel_l2_pair without a batch or workspace.  n
+ * instances described by h_params (same rules as lbm_batch_create; the
+ * fields are packed as for a batch of them), d_a and d_b as for
+ * lbm_batch_rel_l2_pair; the same kernels and summation order, so the same
+ * results.  Instance descriptors, tile table and partial sums go to a fixed
+ * 4 MiB array of device memory inside the library, one per GPU, held until
+ * the process ends (found with hipGetSymbolAddress on the first call on each
+ * device, with that device current).  Limits: 1 <= n <= 256 (else
+ * LBM_E_ARG) and at most 131072 row tiles, sum over instances of
+ * ny * ceil(nx / 256) (else LBM_E_SPACE).  Calls no hipMalloc or hipFree.
+ * All calls on one GPU share the array: calls that overlap on one GPU (from
+ * other host threads, or on other streams) race.  Enqueued on hip_stream
+ * (a stream of the current device); synchronises it. */
+lbm_status lbm_rel_l2_pair_static(int32_t n, const lbm_params* h_params, const float* d_a,
+                                  const float* d_b, double* h_out, void* hip_stream);
+
 lbm_status lbm_batch_destroy(lbm_batch* b);
 
 /* Release the host context (the workspace stays with the caller). */

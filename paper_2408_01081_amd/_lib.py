@@ -90,6 +90,7 @@ SIGNATURES = [
     ("lbm_batch_energy", ctypes.c_int, [_VP, _PD]),
     ("lbm_batch_rel_l2_fields", ctypes.c_int, [_VP, _VP, _PD]),
     ("lbm_batch_rel_l2_pair", ctypes.c_int, [_VP, _VP, _VP, _PD]),
+    ("lbm_rel_l2_pair_static", ctypes.c_int, [_I32, _VP, _VP, _VP, _PD, _VP]),
     ("lbm_batch_destroy", ctypes.c_int, [_VP]),
     ("sg_workspace_bytes", ctypes.c_size_t, [_VP]),
     ("sg_param_count", _I64, []),

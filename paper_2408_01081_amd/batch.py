@@ -172,3 +172,27 @@ class Batch:
         out = (ctypes.c_double * self.n)()
         check(self.L.lbm_batch_rel_l2_pair(self.ctx, _ptr(fa), _ptr(fb), out))
         return np.array(out[:])
+
+
+def rel_l2_pair_static(instances, a, b, device="cuda:0"):
+    """lbm_rel_l2_pair_static: per-instance ||U(a) - U(b)|| / ||U(b)|| of
+    packed FP32 fields for the instances described by `instances` (dicts as
+    for Batch), with no batch, workspace or device allocation."""
+    L = _lib.load()
+    inst = list(instances)
+    arr = (LbmParams * len(inst))()
+    for i, p in enumerate(inst):
+        arr[i] = LbmParams(int(p["nx"]), int(p["ny"]), float(p["dx"]), float(p["dt"]),
+                           float(p["lam"]), float(p["mu"]), float(p["rho"]), int(p["bc"]),
+                           int(p.get("model", 0)), 0)
+    dev = torch.device(device)
+    fa = a.to(dev, torch.float32).contiguous()
+    fb = b.to(dev, torch.float32).contiguous()
+    nodes = sum(int(p["nx"]) * int(p["ny"]) for p in inst)
+    if fa.numel() != 5 * nodes or fb.numel() != 5 * nodes:
+        raise ValueError("packed field sizes do not match the instances")
+    out = (ctypes.c_double * len(inst))()
+    with torch.cuda.device(dev):
+        check(L.lbm_rel_l2_pair_static(len(inst), ctypes.cast(arr, ctypes.c_void_p), _ptr(fa),
+                                       _ptr(fb), out, _stream_ptr(dev)))
+    return np.array(out[:])

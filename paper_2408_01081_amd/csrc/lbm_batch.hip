@@ -22,6 +22,7 @@
 #include <string.h>
 
 #include <map>
+#include <mutex>
 #include <new>
 #include <tuple>
 #include <utility>
@@ -831,3 +832,103 @@ lbm_status lbm_batch_rel_l2_pair(lbm_batch* b, const float* d_a, const float* d_
 }
 
 }  // extern "C"
+
+// ---- the no-allocation variant of lbm_batch_rel_l2_pair --------------------
+// Instance descriptors, tile table and partial sums live in a fixed array of
+// device memory inside the library instead of a batch workspace.  Each GPU
+// holds its own copy; host code reaches it only through the address
+// hipGetSymbolAddress returns on that device (kept per device below), never
+// through the array's name.
+namespace {
+
+constexpr size_t STATIC_SCRATCH_BYTES = (size_t)4 << 20;
+constexpr int STATIC_MAX_INST = 256;
+constexpr int STATIC_MAX_TILES = 131072;
+
+static __device__ __align__(256) unsigned char scratch[STATIC_SCRATCH_BYTES];
+
+std::mutex g_scratch_mu;
+std::map<int, unsigned char*> g_scratch_addr;  // device -> its copy of scratch
+
+// Address of the current device's scratch, looked up once per device (with
+// that device current).
+lbm_status scratch_on_current_device(unsigned char** out) {
+  int dev = -1;
+  lbm_status s = hip_check(hipGetDevice(&dev), "hipGetDevice");
+  if (s) return s;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_addr.find(dev);
+  if (it == g_scratch_addr.end()) {
+    void* p = nullptr;
+    s = hip_check(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+    if (s) return s;
+    it = g_scratch_addr.emplace(dev, (unsigned char*)p).first;
+  }
+  *out = it->second;
+  return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" lbm_status lbm_rel_l2_pair_static(int32_t n, const lbm_params* h_params,
+                                             const float* d_a, const float* d_b, double* h_out,
+                                             void* hip_stream) {
+  if (!h_params || !d_a || !d_b || !h_out) return fail(LBM_E_ARG, "null argument");
+  if (n < 1 || n > STATIC_MAX_INST)
+    return fail(LBM_E_ARG, "lbm_rel_l2_pair_static takes 1 .. " +
+                               std::to_string(STATIC_MAX_INST) + " instances");
+  Layout L;
+  lbm_status s = plan(n, h_params, &L);
+  if (s) return s;
+  if (L.ntiles > STATIC_MAX_TILES)
+    return fail(LBM_E_SPACE, "lbm_rel_l2_pair_static: " + std::to_string(L.ntiles) +
+                                 " row tiles exceed the fixed scratch's " +
+                                 std::to_string(STATIC_MAX_TILES));
+  size_t o = 0;
+  auto take = [&](size_t b) {
+    const size_t at = o;
+    o += (size_t)round_up((int64_t)b, 256);
+    return at;
+  };
+  const size_t off_desc = take(sizeof(InstDesc) * n);
+  const size_t off_tiles = take(sizeof(int) * (size_t)L.ntiles);
+  const size_t off_count = take(sizeof(int) * n);
+  const size_t off_partial = take(sizeof(double) * 2 * (size_t)L.ntiles);
+  const size_t off_out = take(sizeof(double) * 2 * n);
+  if (o > STATIC_SCRATCH_BYTES) return fail(LBM_E_SPACE, "lbm_rel_l2_pair_static: scratch too small");
+  unsigned char* base = nullptr;
+  s = scratch_on_current_device(&base);
+  if (s) return s;
+  hipStream_t st = (hipStream_t)hip_stream;
+  // every partial and result slot is written before it is read: nothing to clear
+  s = hip_check(hipMemcpyAsync(base + off_desc, L.desc.data(), sizeof(InstDesc) * n,
+                               hipMemcpyHostToDevice, st),
+                "static scratch upload");
+  if (!s)
+    s = hip_check(hipMemcpyAsync(base + off_tiles, L.tile_inst.data(),
+                                 sizeof(int) * (size_t)L.ntiles, hipMemcpyHostToDevice, st),
+                  "static scratch upload");
+  if (!s)
+    s = hip_check(hipMemcpyAsync(base + off_count, L.tile_count.data(), sizeof(int) * n,
+                                 hipMemcpyHostToDevice, st),
+                  "static scratch upload");
+  if (s) return s;
+  const InstDesc* descs = (const InstDesc*)(base + off_desc);
+  double* partial = (double*)(base + off_partial);
+  double* out = (double*)(base + off_out);
+  hipLaunchKernelGGL(k_batch_reduce, dim3((unsigned)L.ntiles), dim3(BT), 0, st, nullptr, d_a,
+                     d_b, descs, (const int*)(base + off_tiles), 2, partial);
+  hipLaunchKernelGGL(k_batch_reduce_final, dim3((unsigned)n), dim3(BT), 0, st,
+                     (const double*)partial, descs, (const int*)(base + off_count), out);
+  s = launch_check("static pair reduce launch");
+  if (s) return s;
+  std::vector<double> r(2 * (size_t)n);
+  s = hip_check(hipMemcpyAsync(r.data(), out, sizeof(double) * 2 * n, hipMemcpyDeviceToHost, st),
+                "static pair reduce copy");
+  if (s) return s;
+  // the host copies above read L's vectors; they stay alive until here
+  s = hip_check(hipStreamSynchronize(st), "static pair reduce sync");
+  if (s) return s;
+  for (int i = 0; i < n; ++i) h_out[i] = r[2 * i + 1] > 0 ? sqrt(r[2 * i] / r[2 * i + 1]) : 0.0;
+  return LBM_OK;
+}
