@@ -328,6 +328,47 @@ lbm_status lbm_time_step_config(lbm_ctx* ctx, int32_t index, int32_t reps, doubl
  * the given stream: the bandwidth and memory-counter reference kernel. */
 lbm_status lbm_copy_f32(float* d_dst, const float* d_src, int64_t n, void* hip_stream);
 
+/* ---- the exact linear window operator of a periodic lattice -------------------
+ * On a periodic lattice with a fixed material the map from fields to the
+ * fields 16 steps later, through the second-order initialisation with
+ * central-difference gradients (Eq. ic_second), 16 steps (Section 3.6) and
+ * the outputs of Section 3.5, is linear (Eq. collision_vector and
+ * Eq. streaming are linear) and commutes with lattice shifts: a convolution
+ * whose taps are the responses to unit deltas, zero outside the diamond
+ * |dx| + |dy| <= 17 (one node per step, one more for the central
+ * differences).  The same map as lbm_init + lbm_step(16) + lbm_moments on
+ * such a lattice, in one launch, up to FP32 rounding. */
+#define LBM_WOP_STEPS 16
+#define LBM_WOP_SIDE 35               /* taps per side: 2 (16 + 1) + 1 */
+#define LBM_WOP_OPERAND_BYTES 262144  /* packed operator for lbm_wop_apply */
+
+/* Device scratch lbm_wop_build needs for these parameters (0 if invalid:
+ * Dirichlet, mu = 0, or failing lbm_create's checks).  Only the material,
+ * dx and dt of p matter for the build; nx and ny are ignored. */
+size_t lbm_wop_scratch_bytes(const lbm_params* p);
+size_t lbm_wop_operand_bytes(void);
+
+/* Build the operator for p's material and time step: unit deltas in each
+ * component of U go through the library's own FP64 initialisation and 16
+ * FP32 steps on a 40 x 40 periodic lattice set up on d_scratch
+ * (lbm_wop_scratch_bytes, 256-byte aligned).
+ *   d_G   nullable [35][35][5][5] FP32: G[dy + 17][dx + 17][co][ci], the
+ *         response in U_co at offset (dx, dy) to a unit delta in U_ci
+ *   d_op  LBM_WOP_OPERAND_BYTES, 16-byte aligned: the taps in the physical
+ *         fields (v, sigma_bar), packed for lbm_wop_apply
+ * Requires a periodic problem with mu > 0 (LBM_E_ARG otherwise).  Enqueued
+ * on hip_stream; the scratch must stay valid until the stream has run it. */
+lbm_status lbm_wop_build(const lbm_params* p, float* d_G, void* d_op, void* d_scratch,
+                         size_t scratch_bytes, void* hip_stream);
+
+/* Apply the operator to `batch` periodic windows of p->nx x p->ny (any sizes
+ * >= 1; p->bc periodic): d_in, d_out [batch][5][ny][nx] FP32 physical fields
+ * (v_x, v_y, sigma_xx, sigma_yy, sigma_xy), not overlapping.  One launch of
+ * FP32 matrix-core products (v_mfma_f32_16x16x4_f32) with the input tile of
+ * each workgroup staged in LDS. */
+lbm_status lbm_wop_apply(const lbm_params* p, const void* d_op, const float* d_in, float* d_out,
+                         int32_t batch, void* hip_stream);
+
 /* ---- batched lattices --------------------------------------------------------
  * n independent instances, each with its own lbm_params (size, boundary,
  * material, dx, dt; flags must be 0), advanced together: one launch per time

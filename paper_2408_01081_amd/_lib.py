@@ -68,6 +68,11 @@ SIGNATURES = [
     ("lbm_get_tblock_config", ctypes.c_int, [_VP, ctypes.POINTER(_I32)]),
     ("lbm_set_tblock_config", ctypes.c_int, [_VP, _I32]),
     ("lbm_time_tblock_config", ctypes.c_int, [_VP, _I32, _I32, _PD]),
+    ("lbm_wop_scratch_bytes", ctypes.c_size_t, [ctypes.POINTER(LbmParams)]),
+    ("lbm_wop_operand_bytes", ctypes.c_size_t, []),
+    ("lbm_wop_build", ctypes.c_int, [ctypes.POINTER(LbmParams), _VP, _VP, _VP, ctypes.c_size_t,
+                                     _VP]),
+    ("lbm_wop_apply", ctypes.c_int, [ctypes.POINTER(LbmParams), _VP, _VP, _VP, _I32, _VP]),
     ("lbm_batch_workspace_bytes", ctypes.c_size_t, [_I32, _VP]),
     ("lbm_batch_create", ctypes.c_int, [_I32, _VP, _VP, ctypes.c_size_t, _VP,
                                         ctypes.POINTER(_VP)]),

@@ -1,0 +1,132 @@
+"""The exact linear window operator (lbm_wop_*) on the HIP path, against the
+oracle (oracle/window.py, pinned by tests/test_oracle_window.py) and
+against the library's own lattice replay of the same window.
+
+Tolerances: the taps come from 16 FP32 lattice steps on unit deltas, so they
+carry FP32 rounding (about 1e-7 of the largest tap per operation, a few
+times that after 16 steps): 2e-6 of the largest tap.  Applied to fields,
+the FP32 products and sums add about 1e-7 relative: the spec bar
+rel-L2 <= 1e-5 against the FP64 oracle holds with margin."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import window as OW
+
+gpu = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _material(nu, rho):
+    mu = 1.0
+    return 2.0 * mu * nu / (1.0 - 2.0 * nu), mu, rho
+
+
+def _op(nx, ny, nu=0.3, rho=1.3):
+    from paper_2408_01081_amd.window import WindowOperator
+    lam, mu, rho = _material(nu, rho)
+    dx = 1.0 / nx
+    mat = synth.Material.from_lame(lam, mu, rho)
+    dt = synth.dt_at_cfl_fraction(dx, mat, 0.5)
+    s = oracle.Setup(nx, ny, dx, dt, lam, mu, rho, oracle.PERIODIC)
+    return WindowOperator(nx, ny, dx, dt, lam, mu, rho), s
+
+
+@gpu
+@pytest.mark.parametrize("nu,rho", [(0.3, 1.3), (0.05, 0.6), (0.45, 1.9)])
+def test_taps_match_oracle(nu, rho):
+    _torch()
+    op, s = _op(64, 64, nu, rho)
+    G = op.G.double().cpu().numpy()
+    Go = OW.window_operator(s, 16)
+    scale = np.abs(Go).max()
+    err = np.abs(G - Go).max() / scale
+    print("taps: max |G - G_oracle| / max |G| = %.2e" % err)
+    assert err < 2e-6
+    R = OW.radius(16)
+    dy, dx = np.meshgrid(np.arange(-R, R + 1), np.arange(-R, R + 1), indexing="ij")
+    assert np.all(G[np.abs(dx) + np.abs(dy) > R] == 0.0)
+
+
+def _fields(g, B, ny, nx):
+    return g.standard_normal((B, 5, ny, nx))
+
+
+@gpu
+@pytest.mark.parametrize("nx,ny,B", [(64, 64, 1), (80, 48, 2), (256, 256, 1), (130, 37, 3),
+                                     (5, 3, 2), (1, 1, 1), (200, 1, 1)])
+def test_apply_matches_oracle_window_map(nx, ny, B):
+    torch = _torch()
+    op, s = _op(nx, ny)
+    g = np.random.default_rng(nx * 1000 + ny)
+    f = _fields(g, B, ny, nx)
+    x = torch.from_numpy(f).float().cuda()
+    y = op.apply(x).double().cpu().numpy()
+    for b in range(B):
+        # the oracle's window map on the FP32-rounded input, in U
+        fb = f[b].astype(np.float32).astype(np.float64)
+        U = s.U_from_fields(fb[:2], fb[2:])
+        want = OW.window_map_n(s, U, 16)
+        got = s.U_from_fields(y[b, :2], y[b, 2:])
+        err = oracle.rel_l2(got, want)
+        print("%dx%d window %d: rel-L2 (U) vs the FP64 oracle %.2e" % (nx, ny, b, err))
+        assert err < 1e-5
+
+
+@gpu
+@pytest.mark.parametrize("nx,ny", [(128, 128), (96, 70)])
+def test_apply_matches_lattice_replay(nx, ny):
+    # the library's own lattice path on the same window (FP64
+    # initialisation from the FP32 fields, 16 FP32 steps): the same map
+    torch = _torch()
+    from paper_2408_01081_amd.batch import Batch
+    op, s = _op(nx, ny)
+    p = op.params
+    inst = dict(nx=nx, ny=ny, dx=p.dx, dt=p.dt, lam=p.lam, mu=p.mu, rho=p.rho, bc=0)
+    g = np.random.default_rng(5)
+    B = 4
+    x = torch.from_numpy(_fields(g, B, ny, nx)).float().cuda()
+    y = op.apply(x)
+    b = Batch([inst] * B)
+    b.init_fields_f32(x.reshape(-1))
+    b.step(16)
+    errs = b.rel_l2_fields(y.reshape(-1))
+    print("%dx%d: rel-L2 (U) operator vs lattice replay %s" % (nx, ny, errs))
+    assert np.all(errs < 2e-6)
+
+
+@gpu
+def test_rollout_with_exact_operator_accepts_every_window():
+    # the operator in the surrogate's place: every window passes the judge
+    # (the replay is the same map), and the chain stays at the lattice
+    # chain's state
+    torch = _torch()
+    from paper_2408_01081_amd.serve import Rollout
+    from paper_2408_01081_amd.window import WindowOperator, WindowSurrogate
+    prob = synth.grf_problem(128, 128, synth.PERIODIC, seed=21)
+    op = WindowOperator(prob.nx, prob.ny, prob.dx, prob.dt, prob.lam, prob.mu, prob.rho)
+    ro = Rollout(WindowSurrogate(op), prob, chunk=8, tol=1e-3)
+    f0 = torch.cat([torch.from_numpy(prob.v0), torch.from_numpy(prob.sb0)]).float().cuda()
+    out, st = ro.run(f0, 24)
+    print(st)
+    assert st["accepted"] == 24 and st["fallbacks"] == 0
+    assert st["window_err_max"] < 1e-5
+
+
+@gpu
+def test_window_operator_errors():
+    _torch()
+    from paper_2408_01081_amd.window import WindowOperator
+    with pytest.raises(ValueError):
+        WindowOperator(32, 32, 1.0 / 32, 0.1 / 32, 1.0, 0.0, 1.0)   # mu = 0
+    op, _ = _op(32, 32)
+    import torch
+    with pytest.raises(ValueError):
+        op.apply(torch.zeros((1, 5, 16, 32), device="cuda"))      # wrong size
