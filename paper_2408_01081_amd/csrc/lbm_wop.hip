@@ -167,7 +167,6 @@ __global__ __launch_bounds__(256) void k_wop_apply(const float* __restrict__ in,
                                                    const WopOperand* __restrict__ op, int nx,
                                                    int ny, int tiles_x) {
   __shared__ float tile[NC * WOP_PLANE];
-  __shared__ int colx[WOP_PITCH];
   __shared__ int rowy[WOP_RY];
   const int tid = threadIdx.x;
   const int tx = blockIdx.x % tiles_x, ty = blockIdx.x / tiles_x;
@@ -175,32 +174,61 @@ __global__ __launch_bounds__(256) void k_wop_apply(const float* __restrict__ in,
   const int64_t nn = (int64_t)nx * ny;
   const float* src = in + (int64_t)blockIdx.y * NC * nn;
   float* dst = out + (int64_t)blockIdx.y * NC * nn;
-  // periodic wrap of the tile's rows and columns (any lattice size)
-  for (int i = tid; i < WOP_PITCH; i += 256) colx[i] = wrap_index(X0 - WOP_R + i, nx);
+  // periodic wrap of the tile's rows (any lattice size)
   for (int i = tid; i < WOP_RY; i += 256) rowy[i] = wrap_index(Y0 - WOP_R + i, ny);
+  const int w = tid >> 6, lane = tid & 63, m = lane & 15, g = lane >> 4;
+  // the two columns of the tile this lane fills (the second for lanes < 37)
+  constexpr int C2 = WOP_PITCH - 64;
+  const int cx0 = wrap_index(X0 - WOP_R + lane, nx);
+  const int cx1 = lane < C2 ? wrap_index(X0 - WOP_R + 64 + lane, nx) : cx0;
   __syncthreads();
-  for (int i = tid; i < NC * WOP_PLANE; i += 256) {
-    const int c = i / WOP_PLANE;
-    const int rem = i - c * WOP_PLANE;
-    const int r = rem / WOP_PITCH, col = rem - r * WOP_PITCH;
-    tile[i] = src[c * nn + (int64_t)rowy[r] * nx + colx[col]];
+  // fill: wave w takes the (field, row) lines w, w + 4, w + 8, ..., four
+  // lines per round so that eight loads per lane are in flight
+  constexpr int LINES = NC * WOP_RY;
+  for (int l0 = w; l0 < LINES; l0 += 16) {  // lines l0, l0 + 4, l0 + 8, l0 + 12
+    float v0[4], v1[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int ln = l0 + 4 * k;
+      if (ln < LINES) {
+        const int c = ln / WOP_RY, r = ln - c * WOP_RY;
+        const float* rp = src + c * nn + (int64_t)rowy[r] * nx;
+        v0[k] = rp[cx0];
+        v1[k] = rp[cx1];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int ln = l0 + 4 * k;
+      if (ln < LINES) {
+        tile[ln * WOP_PITCH + lane] = v0[k];
+        if (lane < C2) tile[ln * WOP_PITCH + 64 + lane] = v1[k];
+      }
+    }
   }
   __syncthreads();
-  const int w = tid >> 6, lane = tid & 63, m = lane & 15, g = lane >> 4;
-  // this lane's A element of product s: tile[abase + aoff(s)]
+  // this lane's A element of product s: tile[abase + aoff(s)]; the next
+  // group's A and B are read while the current group's products run
   const float* abase = tile + 16 * w + m + g;
   const float4* bq = &op->b[0][lane];
   f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-  float4 bnext = bq[0];
+  float4 b = bq[0];
+  int4 ao = op->aoff[0];  // wave-uniform
+  float a0 = abase[ao.x], a1 = abase[ao.y], a2 = abase[ao.z], a3 = abase[ao.w];
   for (int q = 0; q < WOP_GROUPS; ++q) {
-    const float4 b = bnext;
-    if (q + 1 < WOP_GROUPS) bnext = bq[(q + 1) * 64];
-    const int4 ao = op->aoff[q];  // wave-uniform
-    const float a0 = abase[ao.x], a1 = abase[ao.y], a2 = abase[ao.z], a3 = abase[ao.w];
+    const int qn = q + 1 < WOP_GROUPS ? q + 1 : q;
+    const float4 bn = bq[qn * 64];
+    const int4 an = op->aoff[qn];
+    const float n0 = abase[an.x], n1 = abase[an.y], n2 = abase[an.z], n3 = abase[an.w];
     acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b.x, acc, 0, 0, 0);
     acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b.y, acc, 0, 0, 0);
     acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a2, b.z, acc, 0, 0, 0);
     acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a3, b.w, acc, 0, 0, 0);
+    b = bn;
+    a0 = n0;
+    a1 = n1;
+    a2 = n2;
+    a3 = n3;
   }
   // D[i][n]: lane holds n = lane % 16 = 5 t + co for pixels i = 4 g + v
   const int n = lane & 15;
