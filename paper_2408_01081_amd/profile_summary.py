@@ -4,7 +4,8 @@
       (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled by what the
       same counter reads for the plain copy kernel k_copy of known size in the
       same run; one entry per launch configuration in the output file;
-  stats:   the per-kernel table of a --kernel-trace --stats run.
+  stats:   the per-kernel table of a --kernel-trace --stats run (with
+      --by-grid, also per launch grid of the matching kernels).
 
     python -m paper_2408_01081_amd.profile_summary traffic \\
         --fetch DIR --write DIR --match 'k_tblock<0, 0, 1, 7>' --copy-bytes 2684354560 \\
@@ -85,6 +86,20 @@ def traffic(a):
     print(json.dumps(out, indent=1))
 
 
+def _by_grid(d: str, match: str):
+    """(kernel, grid) -> durations (ns) of the matching dispatches of a
+    --kernel-trace run; grid = workgroups (x, y, z)."""
+    out = {}
+    for r in csv.DictReader(open(_one(os.path.join(d, "*kernel_trace.csv")))):
+        if match not in r["Kernel_Name"]:
+            continue
+        wg = [int(r["Workgroup_Size_%s" % c]) for c in "XYZ"]
+        grid = tuple(int(r["Grid_Size_%s" % c]) // w for c, w in zip("XYZ", wg))
+        key = (_short(r["Kernel_Name"]), grid)
+        out.setdefault(key, []).append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    return out
+
+
 def stats(a):
     rows = list(csv.DictReader(open(_one(os.path.join(a.dir, "*kernel_stats.csv")))))
     lines = ["# " + a.title, "", "Command (repo root, one MI355X, ROCm 7.2):", ""]
@@ -98,6 +113,15 @@ def stats(a):
         lines.append("| %s | %s | %.1f | %.1f | %.1f | %.2f%% |" % (
             _short(r["Name"]), r["Calls"], float(r["AverageNs"]) / 1e3,
             float(r["MinNs"]) / 1e3, float(r["MaxNs"]) / 1e3, float(r["Percentage"])))
+    for m in a.by_grid:
+        g = _by_grid(a.dir, m)
+        lines += ["", "Dispatches of `%s` by launch grid (workgroups x, y, z):" % m, "",
+                  "| kernel | grid | calls | avg (us) | min (us) | max (us) |",
+                  "|---|---|---|---|---|---|"]
+        for (k, grid), v in sorted(g.items()):
+            lines.append("| %s | %s | %d | %.1f | %.1f | %.1f |" % (
+                k, "x".join(map(str, grid)), len(v), sum(v) / len(v) / 1e3, min(v) / 1e3,
+                max(v) / 1e3))
     if a.note:
         lines.append("")
         lines += ["* " + n for n in a.note]
@@ -126,6 +150,9 @@ def main():
     s.add_argument("--title", required=True)
     s.add_argument("--command", action="append", default=[])
     s.add_argument("--note", action="append", default=[])
+    s.add_argument("--by-grid", action="append", default=[],
+                   help="also list the dispatches of kernels matching this string per "
+                        "launch grid (from the kernel trace)")
     s.add_argument("--out", required=True)
     a = ap.parse_args()
     traffic(a) if a.what == "traffic" else stats(a)
