@@ -498,12 +498,17 @@ def window_op_flops(H, W, B):
     """(useful, issued) FLOPs of one application of the exact window
     operator: 2 x 5 x 5 per tap of the diamond |dx| + |dy| <= 17 (613 taps)
     per output node, and what the matrix-core kernel issues (16 x 16 x 4
-    products, 948 per tile of 16 columns x 3 rows, padding included)."""
+    products, 5 x 48 x 4 = 960 per tile of 16 columns x 3 rows, padding
+    included; workgroups of 128 columns, or of 64 where 128 would compute
+    over 15% more columns than needed or need more than 1024 workgroups)."""
     R = 17
     taps = 2 * R * R + 2 * R + 1
     useful = 2 * taps * 25 * H * W * B
-    tiles = ((W + 63) // 64) * 4 * ((H + 2) // 3) * B
-    issued = 2 * 16 * 16 * 4 * 948 * tiles
+    c1, c2 = (W + 63) // 64 * 64, (W + 127) // 128 * 128
+    wide = W > 64 and c2 * 100 <= c1 * 115 and c2 // 128 * ((H + 2) // 3) * B <= 1024
+    cols = c2 if wide else c1
+    tiles = (cols // 16) * ((H + 2) // 3) * B
+    issued = 2 * 16 * 16 * 4 * 960 * tiles
     return useful, issued
 
 

@@ -16,12 +16,15 @@
 //                   field conversions (fields -> U on input, U -> fields on
 //                   output) into them, packed as the matrix-core operand;
 //   k_wop_apply     the convolution as FP32 matrix-core products
-//                   (v_mfma_f32_16x16x4_f32): per wave a tile of 16 output
-//                   columns x 3 output rows, M = 16 pixels, N = 3 rows x 5
-//                   output fields (15 of 16), K = (input field, input row,
+//                   (v_mfma_f32_16x16x4_f32): per wave MT tiles of 16 output
+//                   columns x 3 output rows, each M = 16 pixels, N = 3 rows x
+//                   5 output fields (15 of 16), K = (input field, input row,
 //                   input column) over the union of the three rows' diamonds,
-//                   4 columns per product; the input tile of a workgroup
-//                   (4 waves side by side, periodic wrap) is staged in LDS.
+//                   4 columns per product, every B operand shared by the MT
+//                   tiles; the input tile of a workgroup (4 column tiles side
+//                   by side, periodic wrap) is staged in LDS, and 4 waves per
+//                   column tile take a quarter of the K range each (more
+//                   waves per SIMD to cover the operand's L2 latency).
 #include <hip/hip_runtime.h>
 
 #include <math.h>
@@ -42,9 +45,6 @@ constexpr int WOP_GEN = 2 * WOP_R + 6;              // side of the generating la
 constexpr int WOP_TR = 3;                           // output rows per wave tile
 constexpr int WOP_RY = WOP_TR + 2 * WOP_R;          // input rows of a tile
 constexpr int WOP_WAVES = 4;
-constexpr int WOP_COLS = 16 * WOP_WAVES;            // output columns per workgroup
-constexpr int WOP_PITCH = WOP_COLS + 2 * WOP_R + 3; // input columns X0 - R .. X0 + 63 + R + 3
-constexpr int WOP_PLANE = WOP_RY * WOP_PITCH;
 
 // input row ri of a tile (row Y0 - R + ri): half-width of the columns any of
 // the tile's output rows Y0 .. Y0 + 2 reaches there, and the 4-column
@@ -59,18 +59,32 @@ __host__ __device__ constexpr int wop_steps_per_field() {
   return s;
 }
 constexpr int WOP_STEPS_F = wop_steps_per_field();     // products per input field
-constexpr int WOP_STEPS = NC * WOP_STEPS_F;            // products per tile
-constexpr int WOP_GROUPS = (WOP_STEPS + 3) / 4;        // groups of 4 products
-static_assert(WOP_GROUPS * 4 * (64 * 4 + 4) <= LBM_WOP_OPERAND_BYTES, "operand size");
+constexpr int WOP_GF = (WOP_STEPS_F + 3) / 4;          // groups of 4 products per field
+constexpr int WOP_GROUPS = NC * WOP_GF;
+constexpr int WOP_BPF = 2;                             // B groups read ahead
+constexpr int WOP_KS = 4;                              // parts of the K range, one wave each
+constexpr int WOP_THREADS = 64 * WOP_WAVES * WOP_KS;
+
+// Offset of product sl of a field (sl < 4 WOP_GF) in a tile row of pitch P
+// relative to the field's plane: input row ri, first column R - half + 4 j
+// of the 4 the product covers (past the field's products: 0, with zero taps)
+template <int P>
+struct WopOffsets {
+  int o[4 * WOP_GF];
+  constexpr WopOffsets() : o() {
+    int sl = 0;
+    for (int ri = 0; ri < WOP_RY; ++ri)
+      for (int j = 0; j < wop_chunks(ri); ++j) o[sl++] = ri * P + (WOP_R - wop_half(ri) + 4 * j);
+  }
+};
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-// The packed operator: for product s (k = 4 input columns of one input row
-// and field), lane l holds B[k = 4 s + l / 16][n = l % 16] in group s / 4,
-// slot s % 4; then the wave-uniform LDS offset of each product's A operand.
+// The packed operator: for product s = 4 WOP_GF ci + sl (input field ci, sl
+// as above; k = 4 input columns of one input row), lane l holds
+// B[k = l / 16][n = l % 16] in group s / 4, slot s % 4.
 struct WopOperand {
   float4 b[WOP_GROUPS][64];
-  int4 aoff[WOP_GROUPS];
 };
 static_assert(sizeof(WopOperand) <= LBM_WOP_OPERAND_BYTES, "operand size");
 
@@ -114,14 +128,12 @@ __global__ void k_wop_pack(const float* __restrict__ G, WopOperand* __restrict__
   const int lane = i & 63;
   const int s = i >> 6;  // product
   const int g = lane >> 4, nn = lane & 15;
+  const int ci = s / (4 * WOP_GF), sl = s - ci * 4 * WOP_GF;
   float val = 0.f;
-  int aoff = 0;
-  if (s < WOP_STEPS) {
-    const int ci = s / WOP_STEPS_F;
-    int rem = s - ci * WOP_STEPS_F, ri = 0;
+  if (ci < NC && sl < WOP_STEPS_F) {
+    int rem = sl, ri = 0;
     while (rem >= wop_chunks(ri)) rem -= wop_chunks(ri++);
     const int j = rem, a = wop_half(ri);
-    aoff = ci * WOP_PLANE + ri * WOP_PITCH + (WOP_R - a + 4 * j);
     const int dx = -a + 4 * j + g;       // input column offset
     const int ry = ri - WOP_R;            // input row offset from the tile's first output row
     if (nn < NC * WOP_TR && dx <= a) {
@@ -153,7 +165,6 @@ __global__ void k_wop_pack(const float* __restrict__ G, WopOperand* __restrict__
     }
   }
   reinterpret_cast<float*>(&op->b[s >> 2][lane])[s & 3] = val;
-  if (lane == 0) reinterpret_cast<int*>(&op->aoff[s >> 2])[s & 3] = aoff;
 }
 
 __device__ inline int wrap_index(int v, int n) {
@@ -161,75 +172,156 @@ __device__ inline int wrap_index(int v, int n) {
   return r < 0 ? r + n : r;
 }
 
-// One workgroup: output columns X0 .. X0 + 63 of rows Y0 .. Y0 + 2 of window b.
-__global__ __launch_bounds__(256) void k_wop_apply(const float* __restrict__ in,
-                                                   float* __restrict__ out,
-                                                   const WopOperand* __restrict__ op, int nx,
-                                                   int ny, int tiles_x) {
-  __shared__ float tile[NC * WOP_PLANE];
+// Tile geometry of k_wop_apply with MT 16-column matrix tiles per wave: a
+// workgroup covers COLS output columns of three rows, and stages input
+// columns X0 - R .. X0 + COLS + R + 2 of every input row and field in LDS.
+template <int MT>
+struct WopTile {
+  static constexpr int COLS = 16 * MT * WOP_WAVES;
+  static constexpr int PITCH = COLS + 2 * WOP_R + 3;
+  static constexpr int PLANE = WOP_RY * PITCH;
+};
+
+// The products of groups Q0 .. Q0 + NQ - 1 of every input field into acc:
+// this lane's A element of product sl of field ci for tile t is
+// abase[ci PLANE + kOff.o[sl] + 16 t] (compile-time offsets once the group
+// loop is unrolled); A is read one group ahead and B WOP_BPF groups ahead
+// (in this wave's order: fields in turn, groups Q0 .. Q0 + NQ - 1 of each)
+// while the current group's products run.
+template <int MT, int Q0, int NQ>
+__device__ __forceinline__ void wop_products(const float* abase, const f32x4* bq,
+                                             f32x4 (&acc)[MT]) {
+  static_assert(WOP_BPF <= NQ, "read-ahead within one field's part");
+  constexpr int PITCH = WopTile<MT>::PITCH, PLANE = WopTile<MT>::PLANE;
+  constexpr WopOffsets<PITCH> kOff{};
+  float a[MT][4];
+#pragma unroll
+  for (int t = 0; t < MT; ++t)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) a[t][k] = abase[kOff.o[4 * Q0 + k] + 16 * t];
+  f32x4 b[WOP_BPF];
+#pragma unroll
+  for (int d = 0; d < WOP_BPF; ++d) b[d] = bq[64 * (Q0 + d)];
+  for (int ci = 0; ci < NC; ++ci) {
+    const float* af = abase + ci * PLANE;
+    const float* an = ci + 1 < NC ? af + PLANE : af;
+    // the read-ahead past the last field re-reads a group of it
+    const int gcur = ci * WOP_GF, gnext = (ci + 1 < NC ? ci + 1 : ci) * WOP_GF;
+#pragma unroll
+    for (int j = 0; j < NQ; ++j) {
+      const int jt = j + WOP_BPF;
+      const f32x4 bnew = jt < NQ ? bq[64 * (gcur + Q0 + jt)] : bq[64 * (gnext + Q0 + jt - NQ)];
+      const float* ap = j + 1 < NQ ? af : an;
+      const int qn = j + 1 < NQ ? Q0 + j + 1 : Q0;
+      float na[MT][4];
+#pragma unroll
+      for (int t = 0; t < MT; ++t)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) na[t][k] = ap[kOff.o[4 * qn + k] + 16 * t];
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int t = 0; t < MT; ++t)
+          acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t][k], b[0][k], acc[t], 0, 0, 0);
+#pragma unroll
+      for (int d = 0; d + 1 < WOP_BPF; ++d) b[d] = b[d + 1];
+      b[WOP_BPF - 1] = bnew;
+#pragma unroll
+      for (int t = 0; t < MT; ++t)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) a[t][k] = na[t][k];
+    }
+  }
+}
+
+// part kh of the K range: groups kh NQ .. (kh + 1) NQ - 1 of every field
+template <int MT, int K>
+__device__ __forceinline__ void wop_part(int kh, const float* abase, const f32x4* bq,
+                                         f32x4 (&acc)[MT]) {
+  constexpr int NQ = WOP_GF / WOP_KS;
+  if (kh == K)
+    wop_products<MT, K * NQ, NQ>(abase, bq, acc);
+  else if constexpr (K + 1 < WOP_KS)
+    wop_part<MT, K + 1>(kh, abase, bq, acc);
+}
+
+// One workgroup: output columns X0 .. X0 + COLS - 1 of rows Y0 .. Y0 + 2 of
+// window blockIdx.y.  Wave w computes columns X0 + 16 MT (w % 4) .. + 16 MT
+// - 1 as MT matrix tiles that share every B operand, over part w / 4 of the
+// K range; the parts' sums are added in order at the end.
+template <int MT>
+__global__ __launch_bounds__(WOP_THREADS) void k_wop_apply(const float* __restrict__ in,
+                                                           float* __restrict__ out,
+                                                           const WopOperand* __restrict__ op,
+                                                           int nx, int ny, int tiles_x) {
+  constexpr int PITCH = WopTile<MT>::PITCH, PLANE = WopTile<MT>::PLANE;
+  constexpr int NW = WOP_THREADS / 64;
+  static_assert(WOP_KS * WOP_WAVES * MT * 64 * 16 <= NC * PLANE * 4, "partial sums fit the tile");
+  __shared__ float tile[NC * PLANE];
   __shared__ int rowy[WOP_RY];
   const int tid = threadIdx.x;
   const int tx = blockIdx.x % tiles_x, ty = blockIdx.x / tiles_x;
-  const int X0 = tx * WOP_COLS, Y0 = ty * WOP_TR;
+  const int X0 = tx * WopTile<MT>::COLS, Y0 = ty * WOP_TR;
   const int64_t nn = (int64_t)nx * ny;
   const float* src = in + (int64_t)blockIdx.y * NC * nn;
   float* dst = out + (int64_t)blockIdx.y * NC * nn;
-  // periodic wrap of the tile's rows (any lattice size)
-  for (int i = tid; i < WOP_RY; i += 256) rowy[i] = wrap_index(Y0 - WOP_R + i, ny);
+  // periodic wrap of the tile's rows and of this lane's columns (any
+  // lattice size): lane fills tile columns lane + 64 c, c < CPL, the last
+  // one for lanes < CLAST only
+  for (int i = tid; i < WOP_RY; i += WOP_THREADS) rowy[i] = wrap_index(Y0 - WOP_R + i, ny);
   const int w = tid >> 6, lane = tid & 63, m = lane & 15, g = lane >> 4;
-  // the two columns of the tile this lane fills (the second for lanes < 37)
-  constexpr int C2 = WOP_PITCH - 64;
-  const int cx0 = wrap_index(X0 - WOP_R + lane, nx);
-  const int cx1 = lane < C2 ? wrap_index(X0 - WOP_R + 64 + lane, nx) : cx0;
+  const int wc = w % WOP_WAVES, kh = w / WOP_WAVES;
+  constexpr int CPL = (PITCH + 63) / 64;
+  constexpr int CLAST = PITCH - 64 * (CPL - 1);
+  int cx[CPL];
+#pragma unroll
+  for (int c = 0; c < CPL; ++c)
+    cx[c] = (c + 1 < CPL || lane < CLAST) ? wrap_index(X0 - WOP_R + 64 * c + lane, nx) : 0;
   __syncthreads();
-  // fill: wave w takes the (field, row) lines w, w + 4, w + 8, ..., four
-  // lines per round so that eight loads per lane are in flight
+  // fill: wave w takes the (field, row) lines w, w + NW, w + 2 NW, ..., four
+  // lines per round so that 4 CPL loads per lane are in flight
   constexpr int LINES = NC * WOP_RY;
-  for (int l0 = w; l0 < LINES; l0 += 16) {  // lines l0, l0 + 4, l0 + 8, l0 + 12
-    float v0[4], v1[4];
+  for (int l0 = w; l0 < LINES; l0 += 4 * NW) {
+    float v[4][CPL];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      const int ln = l0 + 4 * k;
+      const int ln = l0 + NW * k;
       if (ln < LINES) {
         const int c = ln / WOP_RY, r = ln - c * WOP_RY;
         const float* rp = src + c * nn + (int64_t)rowy[r] * nx;
-        v0[k] = rp[cx0];
-        v1[k] = rp[cx1];
+#pragma unroll
+        for (int cc = 0; cc < CPL; ++cc) v[k][cc] = rp[cx[cc]];
       }
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      const int ln = l0 + 4 * k;
+      const int ln = l0 + NW * k;
       if (ln < LINES) {
-        tile[ln * WOP_PITCH + lane] = v0[k];
-        if (lane < C2) tile[ln * WOP_PITCH + 64 + lane] = v1[k];
+#pragma unroll
+        for (int cc = 0; cc < CPL; ++cc)
+          if (cc + 1 < CPL || lane < CLAST) tile[ln * PITCH + 64 * cc + lane] = v[k][cc];
       }
     }
   }
   __syncthreads();
-  // this lane's A element of product s: tile[abase + aoff(s)]; the next
-  // group's A and B are read while the current group's products run
-  const float* abase = tile + 16 * w + m + g;
-  const float4* bq = &op->b[0][lane];
-  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-  float4 b = bq[0];
-  int4 ao = op->aoff[0];  // wave-uniform
-  float a0 = abase[ao.x], a1 = abase[ao.y], a2 = abase[ao.z], a3 = abase[ao.w];
-  for (int q = 0; q < WOP_GROUPS; ++q) {
-    const int qn = q + 1 < WOP_GROUPS ? q + 1 : q;
-    const float4 bn = bq[qn * 64];
-    const int4 an = op->aoff[qn];
-    const float n0 = abase[an.x], n1 = abase[an.y], n2 = abase[an.z], n3 = abase[an.w];
-    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b.x, acc, 0, 0, 0);
-    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b.y, acc, 0, 0, 0);
-    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a2, b.z, acc, 0, 0, 0);
-    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a3, b.w, acc, 0, 0, 0);
-    b = bn;
-    a0 = n0;
-    a1 = n1;
-    a2 = n2;
-    a3 = n3;
-  }
+  const float* abase = tile + 16 * MT * wc + m + g;
+  const f32x4* bq = reinterpret_cast<const f32x4*>(&op->b[0][lane]);
+  f32x4 acc[MT];
+#pragma unroll
+  for (int t = 0; t < MT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+  wop_part<MT, 0>(kh, abase, bq, acc);
+  // partial sums of parts 1 .. KS - 1 through LDS (the tile is no longer read)
+  __syncthreads();
+  f32x4* part = reinterpret_cast<f32x4*>(tile);
+  if (kh > 0)
+#pragma unroll
+    for (int t = 0; t < MT; ++t) part[(((kh - 1) * WOP_WAVES + wc) * MT + t) * 64 + lane] = acc[t];
+  __syncthreads();
+  if (kh > 0) return;
+#pragma unroll
+  for (int k = 1; k < WOP_KS; ++k)
+#pragma unroll
+    for (int t = 0; t < MT; ++t) acc[t] += part[(((k - 1) * WOP_WAVES + wc) * MT + t) * 64 + lane];
   // D[i][n]: lane holds n = lane % 16 = 5 t + co for pixels i = 4 g + v
   const int n = lane & 15;
   if (n >= NC * WOP_TR) return;
@@ -238,10 +330,12 @@ __global__ __launch_bounds__(256) void k_wop_apply(const float* __restrict__ in,
   if (y >= ny) return;
   float* row = dst + co * nn + (int64_t)y * nx;
 #pragma unroll
-  for (int v = 0; v < 4; ++v) {
-    const int x = X0 + 16 * w + 4 * g + v;
-    if (x < nx) row[x] = acc[v];
-  }
+  for (int tt = 0; tt < MT; ++tt)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int x = X0 + 16 * MT * wc + 16 * tt + 4 * g + v;
+      if (x < nx) row[x] = acc[tt][v];
+    }
 }
 
 // scratch of lbm_wop_build: the generating lattice's workspace, its initial
@@ -341,12 +435,23 @@ lbm_status lbm_wop_apply(const lbm_params* p, const void* d_op, const float* d_i
   const int64_t nb = (int64_t)NC * p->nx * p->ny * 4 * batch;
   const char *a = (const char*)d_in, *b = (const char*)d_out;
   if (a < b + nb && b < a + nb) return fail(LBM_E_ARG, "input and output overlap");
-  const int tiles_x = (p->nx + WOP_COLS - 1) / WOP_COLS;
-  const int tiles_y = (p->ny + WOP_TR - 1) / WOP_TR;
-  if ((int64_t)tiles_x * tiles_y > 0x7fffffff) return fail(LBM_E_ARG, "window too large");
-  hipLaunchKernelGGL(k_wop_apply, dim3((unsigned)(tiles_x * tiles_y), (unsigned)batch), dim3(256),
-                     0, (hipStream_t)hip_stream, d_in, d_out, (const WopOperand*)d_op, p->nx,
-                     p->ny, tiles_x);
+  // Two matrix tiles per wave (half the B traffic per product; one
+  // workgroup of 122 KB LDS per CU) for launches of at most 1024 such
+  // workgroups that compute at most 15% more columns than 64-column
+  // workgroups would; one tile per wave otherwise (two workgroups per CU)
+  const int64_t ty64 = (p->ny + WOP_TR - 1) / WOP_TR;
+  const int64_t c1 = ((int64_t)p->nx + 63) / 64 * 64, c2 = ((int64_t)p->nx + 127) / 128 * 128;
+  const bool wide = p->nx > 64 && c2 * 100 <= c1 * 115 && c2 / 128 * ty64 * batch <= 1024;
+  const int64_t cols = wide ? WopTile<2>::COLS : WopTile<1>::COLS;
+  const int64_t tiles_x = (p->nx + cols - 1) / cols;
+  if (tiles_x * ty64 > 0x7fffffff) return fail(LBM_E_ARG, "window too large");
+  const dim3 grid((unsigned)(tiles_x * ty64), (unsigned)batch);
+  if (wide)
+    hipLaunchKernelGGL(k_wop_apply<2>, grid, dim3(WOP_THREADS), 0, (hipStream_t)hip_stream, d_in,
+                       d_out, (const WopOperand*)d_op, p->nx, p->ny, (int)tiles_x);
+  else
+    hipLaunchKernelGGL(k_wop_apply<1>, grid, dim3(WOP_THREADS), 0, (hipStream_t)hip_stream, d_in,
+                       d_out, (const WopOperand*)d_op, p->nx, p->ny, (int)tiles_x);
   return launch_check("k_wop_apply launch");
 }
 
