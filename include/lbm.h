@@ -316,6 +316,24 @@ lbm_status lbm_tblock_config_info(int32_t index, int32_t* h_steps, int32_t* h_se
 int32_t lbm_steps_per_launch(const lbm_ctx* ctx);
 lbm_status lbm_get_tblock_config(const lbm_ctx* ctx, int32_t* h_index);
 lbm_status lbm_set_tblock_config(lbm_ctx* ctx, int32_t index);
+/* Split blocked launches of a Dirichlet lattice (Eq. bc_ansatz acts only at
+ * the walls and a step moves information one node, so after T steps the
+ * nodes at least T from every wall hold what periodic arithmetic on the same
+ * rows gives: bitwise the same operations).  A split launch sweeps the
+ * interior (the strips whose stored columns lie in [T, nx - T), rows
+ * 16 .. ny - 17) with the periodic kernel's code, which keeps the wall
+ * code's registers out of it, and the band along the walls with the
+ * Dirichlet rule as 16-row segments, in one grid; results are bitwise those
+ * of the unsplit launch.  Variants with T, store type and prefetch of a
+ * split kernel (T = 7, 6 with one or two rows prefetched, T = 5 with one;
+ * plain stores) can run split.  mode -1 (default): those
+ * with T >= 5 where the lattice allows; 0: never; 1: all of them where the
+ * lattice allows (at least one interior strip, and ny >= 33).  LBM_E_ARG
+ * for another mode.  The autotuner's choices are kept per mode. */
+lbm_status lbm_set_tblock_split(lbm_ctx* ctx, int32_t mode);
+/* 1 if launches of blocked variant `index` run split on this context as
+ * configured now, 0 if not, -1 for a NULL context or a bad index. */
+int32_t lbm_tblock_split_active(lbm_ctx* ctx, int32_t index);
 /* Average duration (ms) of one launch of blocked variant `index` (T steps;
  * state-preserving, synchronises). */
 lbm_status lbm_time_tblock_config(lbm_ctx* ctx, int32_t index, int32_t reps, double* h_ms);

@@ -11,7 +11,8 @@ INCLUDE = os.path.join(ROOT, "include")
 CSRC = os.path.join(HERE, "csrc")
 LIBNAME = "liblbm_hip.so"
 SOURCES = ["lbm.hip", "lbm_tb_pa.hip", "lbm_tb_pb.hip", "lbm_tb_da.hip", "lbm_tb_db.hip",
-           "lbm_tb_xa.hip", "lbm_tb_xb.hip", "lbm_batch.hip", "lbm_wop.hip", "sg.hip"]
+           "lbm_tb_xa.hip", "lbm_tb_xb.hip", "lbm_tb_sp.hip", "lbm_batch.hip", "lbm_wop.hip",
+           "sg.hip"]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [

@@ -401,6 +401,11 @@ struct lbm_ctx {
   int tb_slots[64];   // resident waves of a blocked variant on this device (0: not known)
   int tbf_slots[48];  // the same for the variants with a load / displacement (3 per variant)
   int tb_rem[9];      // variant for the last r = 2 .. 8 steps of a run (-1: nearest shape)
+  // split Dirichlet blocked launches (mode -1 automatic, 0 never, 1 wherever
+  // the lattice allows): the wall band with the Dirichlet rule and the
+  // interior with the periodic kernel's code, in one launch
+  int tb_split;
+  int tbs_slots[8];  // resident waves of a split kernel on this device (0: not known)
   float* wall_v;        // [WALL_CHUNK][2 (nx + ny)][2] wall velocities of upcoming steps
   // separable body load (rank 0: none); row n of force_T belongs to t_n
   const float* force_X;
@@ -606,6 +611,7 @@ lbm_status lbm_create(const lbm_params* p, void* d_ws, size_t ws_size, void* hip
   c->step_cfg = default_step_config(g.nx);
   c->tb_cfg = -1;
   for (int r = 0; r < 9; ++r) c->tb_rem[r] = -1;
+  c->tb_split = -1;
   *out = c;
   g_err.clear();
   return LBM_OK;
@@ -773,6 +779,7 @@ namespace {
 struct TBTables {
   TBFn fn[kNumTBVariants][2];       // load-free, [variant][bc]
   TBExtFns xfn[kNumTBExtVariants];  // with extras, [variant][extras][bc]
+  TBSplitFn sfn[kNumTBSplitVariants];  // split Dirichlet launches
 };
 
 const TBTables& tb_tables() {
@@ -789,6 +796,7 @@ const TBTables& tb_tables() {
     }
     tb_fill_extra_a(r.xfn);
     tb_fill_extra_b(r.xfn);
+    tb_fill_split(r.sfn);
     return r;
   }();
   return t;
@@ -796,6 +804,7 @@ const TBTables& tb_tables() {
 
 static_assert(kNumTBVariants <= 64, "tb_slots size");
 static_assert(kNumTBExtVariants * 3 <= 48, "tbf_slots size");
+static_assert(kNumTBSplitVariants <= 8, "tbs_slots size");
 
 
 // Sum the wall velocities of steps step0 .. step0 + n - 1 (n <= WALL_CHUNK)
@@ -879,10 +888,103 @@ int tb_seg_rows(lbm_ctx* c, int index) {
                      &c->tb_slots[index]);
 }
 
+// ---- split Dirichlet launches ---------------------------------------------
+// The Dirichlet rule changes a node's update only at the walls, and a change
+// travels one node per step, so after T steps every node at least T nodes
+// from each wall holds what periodic arithmetic on the same rows gives (the
+// same operations in the same order: bitwise equal).  A split launch
+// (k_tblock_split) sweeps the interior strips [lo, hi) (stores in
+// [T, nx - T)) over rows [SPLIT_ROWS, ny - SPLIT_ROWS) with the periodic
+// kernel's code, whose registers the wall code does not take, and the band
+// along the walls (the other strips, all rows; the first and last SPLIT_ROWS
+// rows of the interior strips) with the Dirichlet rule as short segments, in
+// one grid.  The interior's segments leave as many resident wave slots to
+// the band as it has tiles, so both run in one round.  16 rows for the band
+// at the top and bottom walls and per segment of the side-wall strips
+// (2048 x 1024, T = 7: 151 GLUPS; 8 or 24 rows: 142, 32: 106 to 147).
+constexpr int SPLIT_ROWS = 16;
+constexpr int SPLIT_AUTO_MIN_T = 5;  // automatic mode: where the Dirichlet kernel keeps spill registers
+
+struct SplitPlan {
+  int kernel;  // index into kTBSplitVariants
+  TBConst in, band;
+  int ntiles;
+};
+
+// the split kernel of load-free variant `index`, or -1
+int split_kernel(int index) {
+  const TBVariant& k = kTBVariants[index];
+  for (int i = 0; i < kNumTBSplitVariants; ++i) {
+    const TBSplitVariant& s = kTBSplitVariants[i];
+    if (s.steps == k.steps && s.nt == k.nt && s.pf == k.pf) return i;
+  }
+  return -1;
+}
+
+int split_slots(lbm_ctx* c, int kernel) {
+  int& slots = c->tbs_slots[kernel];
+  if (slots == 0) {
+    int per_cu = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, (const void*)tb_tables().sfn[kernel], 256, 0) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) !=
+            hipSuccess ||
+        per_cu < 1 || cus < 1) {
+      (void)hipGetLastError();
+      per_cu = 1;
+      cus = 256;
+    }
+    slots = per_cu * 4 * cus;
+  }
+  return slots;
+}
+
+bool split_plan(lbm_ctx* c, int index, SplitPlan& sp) {
+  if (c->p.bc != LBM_DIRICHLET || c->tb_split == 0) return false;
+  const TBVariant& k = kTBVariants[index];
+  const int T = k.steps;
+  if (c->tb_split < 0 && T < SPLIT_AUTO_MIN_T) return false;
+  sp.kernel = split_kernel(index);
+  if (sp.kernel < 0) return false;
+  const Grid& g = c->g;
+  const int valid = TB_LANES - 2 * T;
+  const int lo = 1, hi = (g.nx - T) / valid;
+  if (hi - lo < 1 || g.ny < 2 * SPLIT_ROWS + 1) return false;
+  sp.band = tblock_const(g, (float)c->kK, (float)c->km, SPLIT_ROWS, T);
+  sp.band.band_lo = lo;
+  sp.band.band_hi = hi;
+  sp.band.band_rows = SPLIT_ROWS;
+  const int nband = (sp.band.nstrips - (hi - lo)) * sp.band.nseg + 2 * (hi - lo);
+  const int rows = g.ny - 2 * SPLIT_ROWS;
+  int seg = k.seg_rows;
+  if (seg <= 0) {
+    const int rounds = seg < 0 ? -seg : 1;
+    int nseg = (split_slots(c, sp.kernel) * rounds - nband) / (hi - lo);
+    if (nseg < 1) nseg = 1;
+    const int ring = 3 + k.pf;
+    seg = (rows + nseg - 1) / nseg;
+    seg = (seg + ring - 1) / ring * ring;
+  }
+  sp.in = tblock_const(g, (float)c->kK, (float)c->km, seg, T);
+  sp.in.strip_first = lo;
+  sp.in.nstrips = hi - lo;
+  sp.in.y_first = SPLIT_ROWS;
+  sp.in.y_end = g.ny - SPLIT_ROWS;
+  sp.in.nseg = (rows + seg - 1) / seg;
+  sp.ntiles = nband + sp.in.nstrips * sp.in.nseg;
+  return true;
+}
+
 // one launch of variant `index`: kTBVariants[index].steps steps, level l with
 // the walls of table entry s0 + l - 1
 void launch_tb(lbm_ctx* c, int index, const float* src, float* dst, const WallSeq& ws) {
   const TBVariant& k = kTBVariants[index];
+  SplitPlan sp;
+  if (split_plan(c, index, sp)) {
+    hipLaunchKernelGGL(tb_tables().sfn[sp.kernel], dim3((unsigned)((sp.ntiles + 3) / 4)),
+                       dim3(256), 0, c->stream, src, dst, c->g, sp.band, sp.in, ws);
+    return;
+  }
   const TBConst sc = tblock_const(c->g, (float)c->kK, (float)c->km, tb_seg_rows(c, index), k.steps);
   const int ntiles = sc.nstrips * sc.nseg;
   hipLaunchKernelGGL(tb_tables().fn[index][c->p.bc], dim3((unsigned)((ntiles + 3) / 4)),
@@ -1122,8 +1224,9 @@ namespace {
 
 struct TuneKey {
   int nx, ny, bc;
+  int split;  // split mode of Dirichlet lattices (-1, the default, for periodic ones)
   bool operator<(const TuneKey& o) const {
-    return std::tie(nx, ny, bc) < std::tie(o.nx, o.ny, o.bc);
+    return std::tie(nx, ny, bc, split) < std::tie(o.nx, o.ny, o.bc, o.split);
   }
 };
 
@@ -1155,7 +1258,8 @@ int find_config(int vec, int threads, int nt, int xmode) {
 }
 
 // Cache file (path in LBM_AUTOTUNE_CACHE): one line per tuned shape,
-// "nx ny bc vec threads nt xmode tb ms" (tb = blocked variant or -1).
+// "nx ny bc vec threads nt xmode tb ms" (tb = blocked variant or -1), for the
+// default split mode only.
 // Caller holds g_tune_mu.
 void load_tune_file() {
   if (g_tune_file_loaded) return;
@@ -1170,14 +1274,14 @@ void load_tune_file() {
                 &ms) == 9) {
     const int i = find_config(vec, th, nt, xm);
     if (i >= 0 && step_config_valid(i, nx) && s2 >= -1 && s2 < kNumTBVariants)
-      g_tune_cache[TuneKey{nx, ny, bc}] = tune_val(i, s2, nullptr);
+      g_tune_cache[TuneKey{nx, ny, bc, -1}] = tune_val(i, s2, nullptr);
   }
   fclose(f);
 }
 
 void append_tune_file(const TuneKey& k, const TuneVal& v, double ms) {
   const char* path = getenv("LBM_AUTOTUNE_CACHE");
-  if (!path || !*path) return;
+  if (!path || !*path || k.split != -1) return;  // the file holds the default mode's choices
   FILE* f = fopen(path, "a");
   if (!f) return;
   const StepConfig& c = kStepConfigs[v.cfg];
@@ -1220,7 +1324,7 @@ lbm_status lbm_autotune(lbm_ctx* c, int32_t reps, int32_t use_cache, int32_t* h_
   if (!c) return fail(LBM_E_ARG, "null ctx");
   if (!c->initialised) return fail(LBM_E_STATE, "autotune needs an initialised lattice");
   if (reps < 1) return fail(LBM_E_ARG, "reps must be >= 1");
-  const TuneKey key{c->g.nx, c->g.ny, c->p.bc};
+  const TuneKey key{c->g.nx, c->g.ny, c->p.bc, c->p.bc == LBM_DIRICHLET ? c->tb_split : -1};
   if (use_cache) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     load_tune_file();
@@ -1354,6 +1458,19 @@ lbm_status lbm_set_tblock_config(lbm_ctx* c, int32_t index) {
     return fail(LBM_E_ARG, "grid too wide for the blocked kernel (row offsets exceed 2^31 B)");
   c->tb_cfg = index;
   return LBM_OK;
+}
+
+lbm_status lbm_set_tblock_split(lbm_ctx* c, int32_t mode) {
+  if (!c) return fail(LBM_E_ARG, "null ctx");
+  if (mode < -1 || mode > 1) return fail(LBM_E_ARG, "split mode must be -1, 0 or 1");
+  c->tb_split = mode;
+  return LBM_OK;
+}
+
+int32_t lbm_tblock_split_active(lbm_ctx* c, int32_t index) {
+  if (!c || index < 0 || index >= kNumTBVariants) return -1;
+  SplitPlan sp;
+  return split_plan(c, index, sp) ? 1 : 0;
 }
 
 lbm_status lbm_time_tblock_config(lbm_ctx* c, int32_t index, int32_t reps, double* h_ms) {

@@ -124,10 +124,11 @@ __global__ __launch_bounds__(256) void k_batch_tblock(const float* __restrict__ 
   const float* src = pool_src + d.off;
   float* dst = pool_dst + d.off;
   const int strip = local % sc.nstrips, seg = local / sc.nstrips;
+  const int y0 = seg * seg_rows, y1 = y0 + seg_rows < d.g.ny ? y0 + seg_rows : d.g.ny;
   if (d.bc == LBM_PERIODIC)
-    tblock_wave<LBM_PERIODIC, NT, PF, T>(src, dst, d.g, sc, ws, strip, seg);
+    tblock_wave<LBM_PERIODIC, NT, PF, T>(src, dst, d.g, sc, ws, strip, y0, y1);
   else
-    tblock_wave<LBM_DIRICHLET, NT, PF, T>(src, dst, d.g, sc, ws, strip, seg);
+    tblock_wave<LBM_DIRICHLET, NT, PF, T>(src, dst, d.g, sc, ws, strip, y0, y1);
 }
 
 typedef void (*BatchTBFn)(const float*, float*, const InstDesc*, const int2*, int, int, int64_t);

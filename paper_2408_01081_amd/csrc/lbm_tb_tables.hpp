@@ -95,6 +95,26 @@ void tbx_fill_range(TBExtFns* out, std::integer_sequence<int, K...>) {
   (tbx_put_all<LO + K>(out), ...);
 }
 
+// Kernels of split Dirichlet launches (k_tblock_split): T, nontemporal
+// stores, rows prefetched.  A load-free variant with the same three runs
+// split.  (At T = 8 the Dirichlet path keeps scratch spills, which make the
+// wall band slower than the unsplit launch.)
+struct TBSplitVariant {
+  int steps, nt, pf;
+};
+constexpr TBSplitVariant kTBSplitVariants[] = {{7, 0, 1}, {7, 0, 2}, {6, 0, 1},
+                                               {6, 0, 2}, {5, 0, 1}};
+constexpr int kNumTBSplitVariants =
+    (int)(sizeof(kTBSplitVariants) / sizeof(kTBSplitVariants[0]));
+typedef void (*TBSplitFn)(const float*, float*, Grid, TBConst, TBConst, WallSeq);
+
+template <int... K>
+void tbs_fill(TBSplitFn* out, std::integer_sequence<int, K...>) {
+  ((out[K] = &k_tblock_split<kTBSplitVariants[K].nt, kTBSplitVariants[K].pf,
+                             kTBSplitVariants[K].steps>),
+   ...);
+}
+
 // ---- the parts, one per translation unit ----------------------------------
 void tb_fill_periodic_a(TBFn* out);   // lbm_tb_pa.hip: periodic, [0, kTBSplit)
 void tb_fill_periodic_b(TBFn* out);   // lbm_tb_pb.hip: periodic, [kTBSplit, n)
@@ -102,5 +122,6 @@ void tb_fill_dirichlet_a(TBFn* out);  // lbm_tb_da.hip
 void tb_fill_dirichlet_b(TBFn* out);  // lbm_tb_db.hip
 void tb_fill_extra_a(TBExtFns* out);  // lbm_tb_xa.hip: [0, kTBExtSplit)
 void tb_fill_extra_b(TBExtFns* out);  // lbm_tb_xb.hip: [kTBExtSplit, n)
+void tb_fill_split(TBSplitFn* out);   // lbm_tb_sp.hip: the split kernels
 
 }  // namespace lbmk

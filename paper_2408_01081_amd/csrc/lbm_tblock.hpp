@@ -47,11 +47,19 @@ constexpr int TB_LANES = 64;
 
 struct TBConst {
   float kK, km;
-  int nstrips;   // strips across a row
+  int nstrips;   // strips across a row (of the launch)
   int seg_rows;  // output rows per segment
   int nseg;      // segments along y
   int plane4;    // bytes between planes
   int extent;    // bytes one row's resource covers: (NP - 1) planes + one row
+  // the launch's tiles: strips strip_first .. + nstrips - 1, segment k holds
+  // output rows y_first + k seg_rows .. (up to y_end - 1); or, when band_hi >
+  // band_lo (the wall band of a split Dirichlet step), every segment of the
+  // strips outside [band_lo, band_hi) and only the first and last seg_rows
+  // rows of the strips inside (see band_tile)
+  int strip_first, y_first, y_end;
+  int band_lo, band_hi;
+  int band_rows;  // wall band: rows at the top and at the bottom of the strips inside
 };
 
 // Wall velocities of the launch's steps: level l (step n + l - 1) reads the
@@ -641,11 +649,11 @@ __device__ __forceinline__ void tblock_sweep(const float* __restrict__ src,
   }
 }
 
-// One wave's work: strip `strip`, output rows of segment `seg`.
+// One wave's work: strip `strip`, output rows y0 .. y1 - 1.
 template <int BC, int NT, int PF, int T, bool FORCE = false, bool DISP = false, int MR = 16>
 __device__ __forceinline__ void tblock_wave(const float* __restrict__ src, float* __restrict__ dst,
                                    const Grid& g, const TBConst& sc, const WallSeq& ws,
-                                   int strip, int seg, const TBExtra& F = TBExtra{},
+                                   int strip, int y0, int y1, const TBExtra& F = TBExtra{},
                                    float* fac = nullptr, double* dring = nullptr) {
   static_assert(T >= 2 && T <= 8, "2 to 8 time levels per launch");
   constexpr int VALID = TB_LANES - 2 * T;  // stored columns per strip
@@ -658,8 +666,6 @@ __device__ __forceinline__ void tblock_wave(const float* __restrict__ src, float
   st.xw = (x >= 0 && x < nx) ? x : -2;
   st.xr4 = (int)((uint32_t)xc * 4u);
   st.xs4 = store ? (int)((uint32_t)x * 4u) : TB_DROP;
-  const int y0 = seg * sc.seg_rows;
-  const int y1 = y0 + sc.seg_rows < ny ? y0 + sc.seg_rows : ny;
   const int pitch4 = (int)(g.pitch * 4);
   RowCursor cur;
   cur.y = y0 - T;
@@ -690,11 +696,43 @@ __device__ __forceinline__ void tblock_wave(const float* __restrict__ src, float
                                                   pitch4, cur, y0, y1);
 }
 
+// Tiles of a launch (see TBConst): their number, and strip and output rows
+// of tile `wid`.  The wall band of a split Dirichlet step lists the
+// segments of the strips outside [band_lo, band_hi) first, then the top and
+// bottom band_rows rows of each strip inside.
+__device__ __forceinline__ int tile_count(const TBConst& sc) {
+  const int inner = sc.band_hi - sc.band_lo;
+  return inner > 0 ? (sc.nstrips - inner) * sc.nseg + 2 * inner : sc.nstrips * sc.nseg;
+}
+__device__ __forceinline__ void tile_of(const TBConst& sc, int ny, int wid, int& strip, int& y0,
+                                        int& y1) {
+  const int inner = sc.band_hi - sc.band_lo;
+  if (inner <= 0) {
+    const int seg = wid / sc.nstrips;
+    strip = sc.strip_first + (wid - seg * sc.nstrips);
+    y0 = sc.y_first + seg * sc.seg_rows;
+    y1 = y0 + sc.seg_rows < sc.y_end ? y0 + sc.seg_rows : sc.y_end;
+    return;
+  }
+  const int wside = (sc.nstrips - inner) * sc.nseg;
+  if (wid < wside) {
+    const int k = wid / sc.nseg, seg = wid - k * sc.nseg;
+    strip = k < sc.band_lo ? k : sc.band_hi + (k - sc.band_lo);
+    y0 = seg * sc.seg_rows;
+    y1 = y0 + sc.seg_rows < ny ? y0 + sc.seg_rows : ny;
+  } else {
+    const int k = wid - wside;
+    strip = sc.band_lo + (k >> 1);
+    y0 = (k & 1) ? ny - sc.band_rows : 0;
+    y1 = y0 + sc.band_rows;
+  }
+}
+
 template <int BC, int NT, int PF, int T, bool FORCE = false, bool DISP = false, int MR = 16>
 __global__ __launch_bounds__(256) void k_tblock(const float* __restrict__ src,
                                                 float* __restrict__ dst, Grid g, TBConst sc,
                                                 WallSeq ws, TBExtra F) {
-  const int ntiles = sc.nstrips * sc.nseg;
+  const int ntiles = tile_count(sc);
   const int nwg = (ntiles + 3) / 4;
   // wave index: uniform by construction, stated to the compiler
   const int wid = xcd_tile(blockIdx.x, nwg) * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -705,8 +743,33 @@ __global__ __launch_bounds__(256) void k_tblock(const float* __restrict__ src,
   // per wave: the displacement rows in flight (unused without them)
   __shared__ __attribute__((aligned(16))) double dring[DISP ? 4 * TB_DSLOTS * TB_LANES * 2 : 2];
   double* dmine = DISP ? dring + (threadIdx.x >> 6) * TB_DSLOTS * TB_LANES * 2 : nullptr;
-  tblock_wave<BC, NT, PF, T, FORCE, DISP, MR>(src, dst, g, sc, ws, wid % sc.nstrips,
-                                          wid / sc.nstrips, F, mine, dmine);
+  int strip, y0, y1;
+  tile_of(sc, g.ny, wid, strip, y0, y1);
+  tblock_wave<BC, NT, PF, T, FORCE, DISP, MR>(src, dst, g, sc, ws, strip, y0, y1, F, mine, dmine);
+}
+
+// A split Dirichlet launch in one grid: waves 0 .. (band tiles - 1) sweep the
+// wall band (`band`, a band launch's tiles) with the Dirichlet rule, the
+// others the interior (`in`) with the periodic kernel's code, which the
+// Dirichlet rule never reaches there (the branch is uniform per wave; each
+// path keeps its own register assignment).
+template <int NT, int PF, int T>
+__global__ __launch_bounds__(256) void k_tblock_split(const float* __restrict__ src,
+                                                      float* __restrict__ dst, Grid g,
+                                                      TBConst band, TBConst in, WallSeq ws) {
+  const int nb = tile_count(band);
+  const int ntiles = nb + tile_count(in);
+  const int nwg = (ntiles + 3) / 4;
+  const int wid = xcd_tile(blockIdx.x, nwg) * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (wid >= ntiles) return;
+  int strip, y0, y1;
+  if (wid < nb) {
+    tile_of(band, g.ny, wid, strip, y0, y1);
+    tblock_wave<LBM_DIRICHLET, NT, PF, T>(src, dst, g, band, ws, strip, y0, y1);
+  } else {
+    tile_of(in, g.ny, wid - nb, strip, y0, y1);
+    tblock_wave<LBM_PERIODIC, NT, PF, T>(src, dst, g, in, ws, strip, y0, y1);
+  }
 }
 
 inline TBConst tblock_const(const Grid& g, float kK, float km, int seg_rows, int T) {
@@ -718,6 +781,11 @@ inline TBConst tblock_const(const Grid& g, float kK, float km, int seg_rows, int
   sc.nseg = (g.ny + seg_rows - 1) / seg_rows;
   sc.plane4 = (int)(g.plane * 4);
   sc.extent = (int)(((NP - 1) * g.plane + g.nx) * 4);
+  sc.strip_first = 0;
+  sc.y_first = 0;
+  sc.y_end = g.ny;
+  sc.band_lo = sc.band_hi = 0;
+  sc.band_rows = 0;
   return sc;
 }
 

@@ -255,6 +255,17 @@ class Lattice:
     def tblock_config(self, index):
         check(self.L.lbm_set_tblock_config(self.ctx, int(index)))
 
+    def set_tblock_split(self, mode):
+        """Split blocked launches of a Dirichlet lattice (interior with the
+        periodic kernel's code, wall band with the Dirichlet rule, one
+        launch): -1 automatic (T >= 5), 0 never, 1 wherever the lattice
+        allows."""
+        check(self.L.lbm_set_tblock_split(self.ctx, int(mode)))
+
+    def tblock_split_active(self, index):
+        """Whether launches of blocked variant `index` run split now."""
+        return int(self.L.lbm_tblock_split_active(self.ctx, int(index))) == 1
+
     @property
     def steps_per_launch(self):
         """Time steps per launch lbm_step uses for this lattice as configured."""

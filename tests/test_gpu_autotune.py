@@ -105,6 +105,65 @@ def test_blocked_kernels_bitwise_equal_single_steps(bc, nx, ny, plane):
             assert np.array_equal(f.view(np.uint32), ref.view(np.uint32)), cfg2
 
 
+# (T, nontemporal, prefetch) of the variants that have a split kernel
+_SPLIT_KERNELS = {(7, 0, 1), (7, 0, 2), (6, 0, 1), (6, 0, 2), (5, 0, 1)}
+
+
+def _split_expected(nx, ny, c):
+    # a split kernel for the variant; the interior strips
+    # [1, (nx - T) // (64 - 2T)) one or more; 16 wall rows at the top and
+    # bottom leaving interior rows
+    T = c["steps"]
+    return ((T, c["nontemporal"], c["prefetch"]) in _SPLIT_KERNELS
+            and (nx - T) // (64 - 2 * T) > 1 and ny >= 33)
+
+
+@gpu
+@pytest.mark.parametrize("nx,ny,plane", [(512, 96, False), (200, 130, False), (130, 33, False),
+                                         (1030, 33, False), (300, 70, True), (120, 35, False),
+                                         (2048, 1024, False)])
+def test_split_dirichlet_launches_bitwise_equal(nx, ny, plane):
+    # a split launch (interior with the periodic kernel's code, wall band
+    # with the Dirichlet rule, in one grid) gives the unsplit launch's result
+    # bit for bit, with moving walls, for every variant
+    torch = _torch()
+    from paper_2408_01081_amd.lbm import Lattice
+    prob = synth.plane_wave_problem(nx, ny, synth.DIRICHLET, seed=29, kmax=2)
+    v0, sb0 = prob.initial_fields()
+    nsteps = 19
+    W, T = prob.wall_table(nsteps)
+    lat = Lattice(prob.nx, prob.ny, prob.dx, prob.dt, prob.lam, prob.mu, prob.rho, prob.bc,
+                  plane_layout=plane)
+
+    def run(cfg2, mode):
+        lat.set_tblock_split(mode)
+        lat.init(torch.from_numpy(v0), torch.from_numpy(sb0))
+        lat.set_wall_velocity(torch.from_numpy(W), torch.from_numpy(T))
+        lat.tblock_config = cfg2
+        lat.step(3).step(nsteps - 3)
+        return lat.populations().cpu().numpy().view(np.uint32)
+
+    ref = run(-1, 0)
+    split_seen = 0
+    for c in lat.tblock_configs():
+        i = c["index"]
+        lat.set_tblock_split(1)
+        active = lat.tblock_split_active(i)
+        assert active == _split_expected(nx, ny, c), (i, c["steps"])
+        split_seen += active
+        lat.set_tblock_split(0)
+        assert not lat.tblock_split_active(i)
+        lat.set_tblock_split(-1)
+        assert lat.tblock_split_active(i) == (active and c["steps"] >= 5)
+        for mode in (1, 0, -1):
+            f = run(i, mode)
+            assert np.array_equal(f, ref), (i, mode)
+    print("%dx%d: %d variants split" % (nx, ny, split_seen))
+    lat.set_tblock_split(-1)
+    with pytest.raises(RuntimeError):
+        lat.set_tblock_split(2)
+
+
 @gpu
 @pytest.mark.parametrize("bc,nx,ny", [(synth.PERIODIC, 4096, 4096), (synth.PERIODIC, 4096, 2000),
                                       (synth.DIRICHLET, 4096, 2000)])
