@@ -136,20 +136,29 @@ def main():
     # ---- timed region ----------------------------------------------------------
     # each lattice's K steps, as lbm_step runs them: full launches of T steps,
     # then one launch for the K mod T steps left; events on the stream the
-    # kernels run on mark the full launches apart from the rest, so the
-    # dominant kernel's average launch time comes from its own launches
+    # kernels run on mark the full launches apart from the rest, and each full
+    # launch of the periodic lattice on its own, so the dominant kernel's
+    # average launch time comes from its own launches (without the gaps
+    # between them)
     stream = torch.cuda.current_stream(dev)
     E = lambda: torch.cuda.Event(enable_timing=True)
     start, end = E(), E()
     ev = [[E(), E(), E()], [E(), E(), E()]]
     Ts = [lat.steps_per_launch for lat in lats]
+    lev = [(E(), E()) for _ in range(K // Ts[0])]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     start.record(stream)
     for li, lat in enumerate(lats):
         full = K // Ts[li] * Ts[li]
         ev[li][0].record(stream)
-        lat.step(full)
+        if li == 0:
+            for a0, a1 in lev:
+                a0.record(stream)
+                lat.step(Ts[0])
+                a1.record(stream)
+        else:
+            lat.step(full)
         ev[li][1].record(stream)
         lat.step(K - full)
         ev[li][2].record(stream)
@@ -172,8 +181,9 @@ def main():
     assert T == (tuned[0]["tblock"]["steps"] if blocked else 1)
     launches = K // T
     if launches > 0:
-        kern_ms = ev[0][0].elapsed_time(ev[0][1]) / launches
-        kern_src = "HIP events around the %d full launches of the timed region" % launches
+        kern_ms = sum(a0.elapsed_time(a1) for a0, a1 in lev) / launches
+        kern_src = ("HIP events around each of the %d full launches of the timed region "
+                    "(mean)" % launches)
     else:  # fewer timed steps than one launch takes: time the launch apart
         kern_ms = (per_lat.time_tblock_config(tuned[0]["tblock_config"], 20) if blocked
                    else per_lat.time_step_config(tuned[0]["config"], 20))
@@ -190,6 +200,8 @@ def main():
                             % (tuned[0]["tblock_config"], T)) if blocked
                     else ("config %d" % tuned[0]["config"])),
                 "kernel_ms": round(kern_ms, 5), "kernel_ms_from": kern_src,
+                "full_launches_ms_per_launch": (
+                    round(ev[0][0].elapsed_time(ev[0][1]) / launches, 5) if launches else None),
                 "launches": launches, "steps_per_launch": T,
                 "steps_after_full_launches": {
                     "steps": rest, "ms": round(ev[0][1].elapsed_time(ev[0][2]), 5),
