@@ -415,15 +415,44 @@ def batched_leg(n, nsteps):
     nodes = b.total_nodes
     import numpy as np
     drift = float(np.max(np.abs(E1 - E0) / E0))
-    return {"workload": "%d instances, sides U[64,512], %d Dirichlet (homogeneous walls), "
-                        "nu U[0,0.49], rho U[0.5,2], GRF data, FP32" %
-                        (n, sum(p.bc for p in probs)),
-            "nodes": nodes, "steps": nsteps, "graph_launches": 1, "ms": round(ms, 3),
-            "GLUPS": round(nodes * nsteps / (ms * 1e-3) / 1e9, 3),
-            "tblock": b.tblock_configs()[tb] if tb >= 0 else None,
-            "algorithmic_GB/s": round(160 * nodes * nsteps / steps_per_launch(b, tb)
-                                      / (ms * 1e-3) / 1e9, 1),
-            "max_rel_energy_drift": drift}
+    out = {"workload": "%d instances, sides U[64,512], %d Dirichlet (homogeneous walls), "
+                       "nu U[0,0.49], rho U[0.5,2], GRF data, FP32" %
+                       (n, sum(p.bc for p in probs)),
+           "nodes": nodes, "steps": nsteps, "graph_launches": 1, "ms": round(ms, 3),
+           "GLUPS": round(nodes * nsteps / (ms * 1e-3) / 1e9, 3),
+           "tblock": b.tblock_configs()[tb] if tb >= 0 else None,
+           "algorithmic_GB/s": round(160 * nodes * nsteps / steps_per_launch(b, tb)
+                                     / (ms * 1e-3) / 1e9, 1),
+           "max_rel_energy_drift": drift}
+    # the same instances with moving walls on every Dirichlet one (seeded
+    # rank-4 separable data): blocked launches read per-launch wall tables;
+    # the graph of each call is built inside the timed call
+    dev = torch.device("cuda")
+    for i, p in enumerate(probs):
+        if p.bc == synth.DIRICHLET:
+            W, T = synth.oscillating_walls(p.nx, p.ny, p.dt, 3 * nsteps + 64, rank=4,
+                                           seed=1000 + i)
+            b.set_wall_velocity(i, torch.from_numpy(W).float().to(dev),
+                                torch.from_numpy(T).float().to(dev))
+    mw = {}
+    for label, cfg in (("tuned", None), ("single_steps", -1)):
+        b.init(b.pack([p.v0 for p in probs]), b.pack([p.sb0 for p in probs]))
+        if cfg is None:
+            cfg, _ = b.autotune(reps=3)
+        else:
+            b.tblock_config = cfg
+        torch.cuda.synchronize()
+        e0.record(stream)
+        b.step(nsteps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        msw = e0.elapsed_time(e1)
+        mw[label] = {"ms": round(msw, 3), "GLUPS": round(nodes * nsteps / (msw * 1e-3) / 1e9, 3),
+                     "tblock": b.tblock_configs()[cfg] if cfg >= 0 else None}
+    out["moving_walls"] = {"walls": "rank-4 separable wall velocities on the %d Dirichlet "
+                                    "instances, %d steps" % (sum(p.bc for p in probs), nsteps),
+                           **mw}
+    return out
 
 
 def load_leg(nsteps=200, disp=True, tblock=None):

@@ -433,10 +433,11 @@ lbm_status lbm_batch_step_eager(lbm_batch* b, int64_t n);
 /* Temporally blocked batched steps: the blocked sweep of lbm_tblock_config_*
  * applied to every instance in one launch per T steps (a table maps each wave
  * to its instance, strip and segment); bitwise identical to single steps.
- * The blocked kernel handles walls at rest only: while any instance has wall
- * data (lbm_batch_set_wall_velocity with rank > 0) lbm_batch_step and
- * lbm_batch_step_eager run single steps whatever variant is selected.  Index
- * -1 = single steps.  Selecting a variant synchronises the batch's stream and
+ * Instances with wall data (lbm_batch_set_wall_velocity with rank > 0): a
+ * small launch before each blocked launch sums the wall velocities of its T
+ * steps into a per-instance table in the workspace (as lbm_set_wall_velocity
+ * data are summed for a single lattice), which the blocked kernel reads.
+ * Index -1 = single steps.  Selecting a variant synchronises the batch's stream and
  * uploads its wave table into the workspace.  lbm_batch_autotune times the
  * single-step kernel and every usable variant on the live state without
  * changing it (reps launches each, HIP events), selects the fastest per step

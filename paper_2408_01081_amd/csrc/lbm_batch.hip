@@ -55,6 +55,7 @@ struct InstDesc {
   const float* W;         // wall table or null
   const float* T;
   int rank;
+  float* V;  // Dirichlet instances: [8][2 (nx + ny)][2] wall velocities of a blocked launch's steps
 };
 
 __device__ inline int find_instance(const InstDesc* __restrict__ d, int n, int64_t node) {
@@ -93,8 +94,36 @@ __global__ __launch_bounds__(THREADS) void k_batch_step(const float* __restrict_
     step_segment<LBM_DIRICHLET, 1, THREADS, 1, 0>(src, dst, d.g, d.kK, d.km, w, y, tx);
 }
 
-// T steps of every instance per launch (walls at rest); wave w works on
-// instance waves[w].x, strip / segment index waves[w].y of that instance.
+// V[s][link][2] of every instance with wall data: the wall velocities of
+// steps step0 .. step0 + t - 1 (summed in rank order by wall_series, as the
+// single-step kernel forms them).  Workgroup blockIdx.x covers instance
+// blockIdx.x / per, its part blockIdx.x % per.
+__global__ void k_batch_wall_eval(const InstDesc* __restrict__ descs, int per, int64_t step0,
+                                  int t) {
+  const InstDesc& d = descs[blockIdx.x / per];
+  if (d.rank == 0) return;
+  const int L = 2 * (d.g.nx + d.g.ny);
+  const int64_t n = (int64_t)t * L;
+  for (int64_t i = (int64_t)(blockIdx.x % per) * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)per * blockDim.x) {
+    const int s = (int)(i / L), link = (int)(i - (int64_t)s * L);
+    Wall w;
+    w.W = d.W;
+    w.Trow = d.T + (step0 + s) * d.rank;
+    w.rank = d.rank;
+    w.L = L;
+    w.V = nullptr;
+    float a, b;
+    wall_series(w, link, a, b);
+    d.V[2 * i] = a;
+    d.V[2 * i + 1] = b;
+  }
+}
+
+// T steps of every instance per launch; wave w works on instance
+// waves[w].x, strip / segment index waves[w].y of that instance.  An
+// instance with wall data reads the velocities of the launch's steps from
+// its table V (k_batch_wall_eval before the launch).
 template <int NT, int PF, int T>
 __global__ __launch_bounds__(256) void k_batch_tblock(const float* __restrict__ pool_src,
                                                       float* __restrict__ pool_dst,
@@ -117,9 +146,8 @@ __global__ __launch_bounds__(256) void k_batch_tblock(const float* __restrict__ 
   sc.nseg = (d.g.ny + seg_rows - 1) / seg_rows;
   sc.plane4 = (int)(d.g.plane * 4);
   sc.extent = (int)(((NP - 1) * d.g.plane + d.g.nx) * 4);
-  // walls at rest: blocked launches run only while no instance has wall data
   WallSeq ws;
-  ws.V = nullptr;
+  ws.V = d.rank > 0 ? d.V : nullptr;
   ws.L = 2 * (d.g.nx + d.g.ny);
   const float* src = pool_src + d.off;
   float* dst = pool_dst + d.off;
@@ -296,8 +324,13 @@ struct Layout {
   int tb_waves[kNumBatchTB];  // waves of each blocked variant
   int tb_max_waves = 0;
   bool tb_ok = true;          // every instance fits the blocked kernel
-  size_t off_pool[2], off_desc, off_tiles, off_count, off_partial, off_out, off_waves, bytes;
+  size_t off_pool[2], off_desc, off_tiles, off_count, off_partial, off_out, off_waves, off_wallv,
+      bytes;
+  std::vector<int64_t> voff;  // float offset of each Dirichlet instance's wall table (-1: none)
+  int max_links = 0;          // largest 2 (nx + ny) of a Dirichlet instance
 };
+
+constexpr int BATCH_TB_MAXT = 8;  // most steps of a blocked launch: rows of a wall table
 
 // wave table of blocked variant `v`: (instance, strip + nstrips * segment)
 std::vector<int2> wave_table(const Layout& L, int v) {
@@ -316,6 +349,8 @@ lbm_status plan(int32_t n, const lbm_params* params, Layout* L) {
   if (n < 1 || !params) return fail(LBM_E_ARG, "batch needs n >= 1 and parameters");
   L->desc.resize(n);
   L->tile_count.resize(n);
+  L->voff.assign(n, -1);
+  int64_t wallv_floats = 0;
   for (int i = 0; i < n; ++i) {
     Derived dv;
     lbm_status s = derive(&params[i], &dv);
@@ -347,6 +382,12 @@ lbm_status plan(int32_t n, const lbm_params* params, Layout* L) {
     d.rho = (float)params[i].rho;
     d.ic = InitConst{dv.kK, dv.km, dv.cK, dv.cmu, params[i].rho, params[i].dx, params[i].bc};
     if (!norm_weights(dv.kK, dv.km, d.kw)) return fail(LBM_E_CFL, "g_ij not positive definite");
+    if (d.bc == LBM_DIRICHLET) {
+      const int links = 2 * (d.g.nx + d.g.ny);
+      L->voff[i] = wallv_floats;
+      wallv_floats += round_up((int64_t)BATCH_TB_MAXT * links * 2, 64);
+      if (links > L->max_links) L->max_links = links;
+    }
   }
   for (int v = 0; v < kNumBatchTB; ++v) {
     const int valid = TB_LANES - 2 * kBatchTB[v].steps;
@@ -378,6 +419,7 @@ lbm_status plan(int32_t n, const lbm_params* params, Layout* L) {
   L->off_partial = take(sizeof(double) * 2 * (size_t)L->ntiles);
   L->off_out = take(sizeof(double) * 2 * n);
   L->off_waves = take(sizeof(int2) * (size_t)L->tb_max_waves);
+  L->off_wallv = take(sizeof(float) * (size_t)wallv_floats);
   L->bytes = o;
   return LBM_OK;
 }
@@ -420,11 +462,10 @@ lbm_status upload_descs(lbm_batch* b) {
 }
 
 // Steps per launch for `steps` steps: T per launch with a blocked variant,
-// the remainder (fewer than T) one at a time.  The blocked kernel handles
-// walls at rest only, so any instance with wall data means single steps.
+// the remainder (fewer than T) one at a time.
 std::vector<int> launch_plan(const lbm_batch* b, int64_t steps) {
   std::vector<int> p;
-  const int T = b->tb_cfg >= 0 && !b->any_wall ? kBatchTB[b->tb_cfg].steps : 1;
+  const int T = b->tb_cfg >= 0 ? kBatchTB[b->tb_cfg].steps : 1;
   int64_t k = 0;
   for (; T > 1 && k + T <= steps; k += T) p.push_back(T);
   for (; k < steps; ++k) p.push_back(1);
@@ -481,6 +522,35 @@ void make_launch(const lbm_batch* b, int t, int parity, int64_t step, LaunchArgs
   a->kp.kernelParams = a->args;
 }
 
+// The wall-table launch before a blocked launch of t steps from step index
+// `step` (instances with wall data only).
+struct WallEvalArgs {
+  const InstDesc* descs;
+  int per, t;
+  int64_t step;
+  void* args[4];
+  hipKernelNodeParams kp;
+};
+
+void make_wall_eval(const lbm_batch* b, int t, int64_t step, WallEvalArgs* a) {
+  a->descs = b->d_desc;
+  a->t = t;
+  a->step = step;
+  const int64_t work = (int64_t)t * b->L.max_links;
+  a->per = (int)((work + BT - 1) / BT);
+  if (a->per > 16) a->per = 16;
+  if (a->per < 1) a->per = 1;
+  a->args[0] = (void*)&a->descs;
+  a->args[1] = (void*)&a->per;
+  a->args[2] = (void*)&a->step;
+  a->args[3] = (void*)&a->t;
+  memset(&a->kp, 0, sizeof a->kp);
+  a->kp.func = reinterpret_cast<void*>(&k_batch_wall_eval);
+  a->kp.gridDim = dim3((unsigned)(a->per * b->n));
+  a->kp.blockDim = dim3(BT);
+  a->kp.kernelParams = a->args;
+}
+
 // Build a graph of the launches for `steps` steps starting from buffer `cur`
 // at step index `step0`.
 lbm_status build_graph(lbm_batch* b, int64_t steps, int cur, int64_t step0,
@@ -492,9 +562,18 @@ lbm_status build_graph(lbm_batch* b, int64_t steps, int cur, int64_t step0,
   int parity = cur;
   int64_t step = step0;
   for (int t : launch_plan(b, steps)) {
+    hipGraphNode_t node;
+    if (t > 1 && b->any_wall) {
+      WallEvalArgs w;
+      make_wall_eval(b, t, step, &w);
+      s = hip_check(hipGraphAddKernelNode(&node, graph, prev ? &prev : nullptr, prev ? 1 : 0,
+                                          &w.kp),
+                    "graph add kernel node");
+      if (s) break;
+      prev = node;
+    }
     LaunchArgs a;
     make_launch(b, t, parity, step, &a);
-    hipGraphNode_t node;
     s = hip_check(hipGraphAddKernelNode(&node, graph, prev ? &prev : nullptr, prev ? 1 : 0, &a.kp),
                   "graph add kernel node");
     if (s) break;
@@ -509,6 +588,11 @@ lbm_status build_graph(lbm_batch* b, int64_t steps, int cur, int64_t step0,
 }
 
 void launch_direct(lbm_batch* b, int t, int parity, int64_t step) {
+  if (t > 1 && b->any_wall) {
+    WallEvalArgs w;
+    make_wall_eval(b, t, step, &w);
+    hipLaunchKernel(w.kp.func, w.kp.gridDim, w.kp.blockDim, w.kp.kernelParams, 0, b->stream);
+  }
   LaunchArgs a;
   make_launch(b, t, parity, step, &a);
   hipLaunchKernel(a.kp.func, a.kp.gridDim, a.kp.blockDim, a.kp.kernelParams, 0, b->stream);
@@ -564,6 +648,8 @@ lbm_status lbm_batch_create(int32_t n, const lbm_params* params, void* d_ws, siz
   b->d_partial = (double*)(b->ws + b->L.off_partial);
   b->d_out = (double*)(b->ws + b->L.off_out);
   b->d_waves = (int2*)(b->ws + b->L.off_waves);
+  for (int i = 0; i < n; ++i)
+    b->L.desc[i].V = b->L.voff[i] >= 0 ? (float*)(b->ws + b->L.off_wallv) + b->L.voff[i] : nullptr;
   b->tb_cfg = -1;
   b->cur = 0;
   b->initialised = false;
@@ -753,15 +839,13 @@ lbm_status lbm_batch_autotune(lbm_batch* b, int32_t reps, int32_t* h_index, doub
   for (int i = 0; i < b->n; ++i)
     if (b->L.desc[i].rank > 0 && b->wall_nsteps[i] - b->nstep < wall_left)
       wall_left = b->wall_nsteps[i] - b->nstep;
-  // blocked variants are skipped while an instance has wall data (they would
-  // not be used by lbm_batch_step then)
   int best = -1;
   double best_ms = 1e300;
   // timed launches read the current pool and write the spare one: the state
   // is not changed
   for (int v = -1; v < kNumBatchTB && s == LBM_OK; ++v) {
-    if (v >= 0 && (!b->L.tb_ok || b->any_wall)) continue;
-    if (v < 0 && wall_left < 1) continue;
+    if (v >= 0 && !b->L.tb_ok) continue;
+    if (wall_left < (v >= 0 ? kBatchTB[v].steps : 1)) continue;
     s = lbm_batch_set_tblock_config(b, v);
     if (s) break;
     const int t = v >= 0 ? kBatchTB[v].steps : 1;

@@ -5,5 +5,5 @@ from .workloads import (DIRICHLET, batched_instances, PERIODIC, Problem, dt_at_c
                         grf_problem, node_coords, plane_wave_problem, plane_wave_superposition,
                         poisson_lame, random_material, random_populations, rng,
                         separable_body_table, separable_reference_table,
-                        separable_table, wall_points,
+                        oscillating_walls, separable_table, wall_points,
                         wall_taper)

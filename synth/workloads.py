@@ -128,6 +128,31 @@ class Problem:
         return np.stack(Ws), np.stack(Ts, axis=1)
 
 
+def oscillating_walls(nx: int, ny: int, dt: float, nsteps: int, rank: int = 4,
+                      amp: float = 1e-2, seed: int = 0):
+    """Seeded separable wall velocities for a Dirichlet rectangle (driven
+    walls, no exact solution behind them): W [rank][L][2] with L = 2 (nx +
+    ny) links (left wall rows, right wall rows, bottom columns, top columns),
+    each component a short random Fourier series of the link position of
+    amplitude ~amp; T [nsteps][rank] = cos / sin (omega_r t_n), t_n = (n +
+    1/2) dt, omega_r / 2 pi uniform in [0.5, 4].  float64."""
+    rng = np.random.default_rng(seed)
+    L = 2 * (nx + ny)
+    s = np.arange(L) / L
+    W = np.zeros((rank, L, 2))
+    for r in range(rank):
+        for c in range(2):
+            k = rng.integers(1, 6, size=3)
+            ph = rng.uniform(0.0, 2 * np.pi, size=3)
+            a = rng.normal(size=3)
+            W[r, :, c] = amp * sum(a[j] * np.sin(2 * np.pi * k[j] * s + ph[j]) for j in range(3))
+    om = 2 * np.pi * rng.uniform(0.5, 4.0, size=rank)
+    tn = (np.arange(nsteps) + 0.5) * dt
+    T = np.stack([np.cos(om[r] * tn) if r % 2 == 0 else np.sin(om[r] * tn)
+                  for r in range(rank)], axis=1)
+    return W, T
+
+
 def separable_table(comps, nx: int, ny: int, dx: float, dt: float, nsteps: int):
     """Fields given as SinSums, comps = [(SinSum, scale), ...] (component c is
     scale_c * comps[c][0]), at the nodes and levels t_n = n dt, n = 0..nsteps,

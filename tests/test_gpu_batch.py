@@ -155,26 +155,46 @@ def test_batch_blocked_variants_bitwise_equal_single_steps():
 
 
 @gpu
-def test_batch_blocked_variant_with_walls_runs_single_steps():
-    # wall data switch the batch to single steps, so a selected blocked
-    # variant must still give the single-lattice result with moving walls
+def test_batch_blocked_variants_with_moving_walls_bitwise_equal_single_lattices():
+    # instances with moving walls (different ranks and sizes) beside periodic
+    # and resting-wall ones: every blocked variant, graph and eager, gives
+    # each single lattice's result with the same wall data bit for bit
     torch = _torch()
     from paper_2408_01081_amd.batch import Batch
     from paper_2408_01081_amd.lbm import Lattice
-    p = synth.plane_wave_problem(300, 129, synth.DIRICHLET, seed=2, kmax=4)
-    v0, s0 = p.initial_fields()
-    W, T = p.wall_table(17)
-    b = Batch([_params(p)])
-    b.tblock_config = 4
-    b.set_wall_velocity(0, torch.from_numpy(W), torch.from_numpy(T))
-    b.init(b.pack([v0]), b.pack([s0])).step(17)
-    lat = Lattice(p.nx, p.ny, p.dx, p.dt, p.lam, p.mu, p.rho, p.bc)
-    lat.init(torch.from_numpy(v0), torch.from_numpy(s0))
-    lat.set_wall_velocity(torch.from_numpy(W), torch.from_numpy(T))
-    lat.step(17)
-    got = b.moments(system=True).cpu().numpy()
-    want = lat.moments_U().cpu().numpy().reshape(-1)
-    assert np.array_equal(got.view(np.uint32), want.view(np.uint32))
+    probs = [synth.plane_wave_problem(300, 129, synth.DIRICHLET, seed=2, kmax=4),
+             synth.plane_wave_problem(64, 64, synth.PERIODIC, seed=3, kmax=2),
+             synth.plane_wave_problem(130, 71, synth.DIRICHLET, seed=5, kmax=3),
+             synth.plane_wave_problem(97, 40, synth.DIRICHLET, seed=7, kmax=2)]
+    nsteps = 23
+    walls = [p.wall_table(nsteps + 9) if i != 3 and p.bc == synth.DIRICHLET else None
+             for i, p in enumerate(probs)]
+    fields = [p.initial_fields() for p in probs]
+    want = []
+    for p, f, w in zip(probs, fields, walls):
+        lat = Lattice(p.nx, p.ny, p.dx, p.dt, p.lam, p.mu, p.rho, p.bc)
+        lat.init(torch.from_numpy(f[0]), torch.from_numpy(f[1]))
+        if w is not None:
+            lat.set_wall_velocity(torch.from_numpy(w[0]), torch.from_numpy(w[1]))
+        lat.step(nsteps)
+        want.append(lat.moments_U().cpu().numpy().reshape(-1))
+    want = np.concatenate(want)
+    b = Batch([_params(p) for p in probs])
+    v0, s0 = b.pack([f[0] for f in fields]), b.pack([f[1] for f in fields])
+    for i, w in enumerate(walls):
+        if w is not None:
+            b.set_wall_velocity(i, torch.from_numpy(w[0]).cuda(), torch.from_numpy(w[1]).cuda())
+    for idx in [-1] + [c["index"] for c in b.tblock_configs()]:
+        b.tblock_config = idx
+        for graph in (True, False):
+            b.init(v0, s0)
+            b.step(9, graph=graph).step(nsteps - 9, graph=graph)
+            got = b.moments(system=True).cpu().numpy()
+            assert np.array_equal(got.view(np.uint32), want.view(np.uint32)), (idx, graph)
+    # the autotuner times blocked variants with the walls too
+    b.init(v0, s0)
+    idx, ms = b.autotune(reps=2)
+    assert -1 <= idx < len(b.tblock_configs()) and ms > 0
 
 
 @gpu
