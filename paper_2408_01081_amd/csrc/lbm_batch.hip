@@ -121,10 +121,12 @@ __global__ void k_batch_wall_eval(const InstDesc* __restrict__ descs, int per, i
 }
 
 // T steps of every instance per launch; wave w works on instance
-// waves[w].x, strip / segment index waves[w].y of that instance.  An
+// waves[w].x, strip / segment index waves[w].y of that instance.  WALLS: an
 // instance with wall data reads the velocities of the launch's steps from
-// its table V (k_batch_wall_eval before the launch).
-template <int NT, int PF, int T>
+// its table V (k_batch_wall_eval before the launch); without, walls rest
+// (their velocities are the constant 0, which keeps the wall code's
+// registers out of the kernel that serves batches without wall data).
+template <int NT, int PF, int T, bool WALLS>
 __global__ __launch_bounds__(256) void k_batch_tblock(const float* __restrict__ pool_src,
                                                       float* __restrict__ pool_dst,
                                                       const InstDesc* __restrict__ descs,
@@ -147,7 +149,7 @@ __global__ __launch_bounds__(256) void k_batch_tblock(const float* __restrict__ 
   sc.plane4 = (int)(d.g.plane * 4);
   sc.extent = (int)(((NP - 1) * d.g.plane + d.g.nx) * 4);
   WallSeq ws;
-  ws.V = d.rank > 0 ? d.V : nullptr;
+  ws.V = WALLS && d.rank > 0 ? d.V : nullptr;
   ws.L = 2 * (d.g.nx + d.g.ny);
   const float* src = pool_src + d.off;
   float* dst = pool_dst + d.off;
@@ -162,9 +164,10 @@ __global__ __launch_bounds__(256) void k_batch_tblock(const float* __restrict__ 
 typedef void (*BatchTBFn)(const float*, float*, const InstDesc*, const int2*, int, int, int64_t);
 struct BatchTBConfig {
   int steps, seg_rows, nt, pf;
-  BatchTBFn fn;
+  BatchTBFn fn, fn_walls;  // walls at rest / wall tables
 };
-#define LBM_BTB(T, S, N, F) {T, S, N, F, &k_batch_tblock<N, F, T>}
+#define LBM_BTB(T, S, N, F) \
+  {T, S, N, F, &k_batch_tblock<N, F, T, false>, &k_batch_tblock<N, F, T, true>}
 const BatchTBConfig kBatchTB[] = {
     LBM_BTB(2, 4, 0, 1), LBM_BTB(2, 8, 1, 1),  LBM_BTB(3, 4, 0, 1),  LBM_BTB(3, 8, 0, 1),
     LBM_BTB(4, 4, 0, 1), LBM_BTB(4, 8, 0, 1),  LBM_BTB(4, 4, 1, 1),  LBM_BTB(4, 16, 0, 1),
@@ -516,7 +519,7 @@ void make_launch(const lbm_batch* b, int t, int parity, int64_t step, LaunchArgs
     a->args[4] = (void*)&a->nwaves;
     a->args[5] = (void*)&a->seg_rows;
     a->args[6] = (void*)&a->step;
-    a->kp.func = reinterpret_cast<void*>(k.fn);
+    a->kp.func = reinterpret_cast<void*>(b->any_wall ? k.fn_walls : k.fn);
     a->kp.gridDim = dim3((unsigned)((a->nwaves + 3) / 4));
   }
   a->kp.kernelParams = a->args;
