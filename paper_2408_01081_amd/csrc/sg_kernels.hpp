@@ -244,27 +244,52 @@ __global__ __launch_bounds__(256) void k_convt(const float* __restrict__ X,
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) acc[pb][nb] = (f32x4){0.f, 0.f, 0.f, 0.f};
 
+  // staging: thread t handles the items t, t + 256, ... of the tile (and of
+  // the weights); 256 is a multiple of 4, so its piece q of 8 channels is
+  // the same in every item.  All of a thread's loads of the input tile are
+  // issued before the first one is used, so their latencies overlap.
+  constexpr int NTILE = TR * TW * 4, PER = (NTILE + 255) / 256;
+  constexpr int NWT = WL ? 9 * CT * 4 : 1, PERW = (NWT + 255) / 256;
+  const int q = threadIdx.x & 3;
   for (int c0 = 0; c0 < Cin; c0 += 32) {
     if (c0) __syncthreads();  // every wave is done with the previous chunk
     // TR rows x TW columns x 4 pieces of 8 channels, hi (and lo)
-    for (int i = threadIdx.x; i < TR * TW * 4; i += 256) {
-      const int q = i & 3, col = (i >> 2) % TW, row = (i >> 2) / TW;
+    float4 u0[PER], u1[PER];
+    bool valid[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int i = threadIdx.x + 256 * k;
+      const int col = (i >> 2) % TW, row = (i >> 2) / TW;
       int ys = y + row - 1, xs = x0 + col - 1;
-      bool valid = true;
+      bool v = i < NTILE;
       if (circular) {
         ys = ys < 0 ? ys + H : (ys >= H ? ys - H : ys);
         xs = xs < 0 ? xs + W : (xs >= W ? xs - W : xs);
       } else {
-        valid = ys >= 0 && ys < H && xs >= 0 && xs < W;
+        v = v && ys >= 0 && ys < H && xs >= 0 && xs < W;
       }
-      uint4 vh = {0u, 0u, 0u, 0u}, vl = {0u, 0u, 0u, 0u};
-      if (valid) {
+      valid[k] = v;
+      if (v) {
         const int64_t xo = (((int64_t)b * H + ys) * W + xs) * Cin + c0 + 8 * q;
-        const float4 u0 = *reinterpret_cast<const float4*>(X + xo);
-        const float4 u1 = *reinterpret_cast<const float4*>(X + xo + 4);
-        float a[8] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w};
+        u0[k] = *reinterpret_cast<const float4*>(X + xo);
+        u1[k] = *reinterpret_cast<const float4*>(X + xo + 4);
+      }
+    }
+    float sc[8];
+    if (xscale) {
+      const float* sp = xscale + (int64_t)b * Cin + c0 + 8 * q;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) sc[j] = sp[j];
+    }
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int i = threadIdx.x + 256 * k;
+      if (k + 1 < PER || i < NTILE) {
+      const int col = (i >> 2) % TW, row = (i >> 2) / TW;
+      uint4 vh = {0u, 0u, 0u, 0u}, vl = {0u, 0u, 0u, 0u};
+      if (valid[k]) {
+        float a[8] = {u0[k].x, u0[k].y, u0[k].z, u0[k].w, u1[k].x, u1[k].y, u1[k].z, u1[k].w};
         if (xscale) {
-          const float* sc = xscale + (int64_t)b * Cin + c0 + 8 * q;
 #pragma unroll
           for (int j = 0; j < 8; ++j) a[j] *= sc[j];
         }
@@ -285,16 +310,22 @@ __global__ __launch_bounds__(256) void k_convt(const float* __restrict__ X,
       const int d = (row * TW + col) * PS + 4 * q;
       *reinterpret_cast<uint4*>(tile + d) = vh;
       if (SPLIT == 3) *reinterpret_cast<uint4*>(tile + TR * TW * PS + d) = vl;
+      }
     }
     if (WL) {
-      // 9 taps x CT channels x 4 pieces of 8 input channels
-      for (int i = threadIdx.x; i < 9 * CT * 4; i += 256) {
-        const int q = i & 3, co = (i >> 2) % CT, t = (i >> 2) / CT;
-        const int64_t wo = ((int64_t)t * Cout + blockIdx.y * CT + co) * Cin + c0 + 8 * q;
-        const int d = (t * CT + co) * PS + 4 * q;
-        *reinterpret_cast<uint4*>(wtile + d) = *reinterpret_cast<const uint4*>(Whi + wo);
-        if (SPLIT == 3)
-          *reinterpret_cast<uint4*>(wtile + WS + d) = *reinterpret_cast<const uint4*>(Wlo + wo);
+      // 9 taps x CT channels x 4 pieces of 8 input channels (from L2: every
+      // workgroup reads the same weights)
+#pragma unroll
+      for (int k = 0; k < PERW; ++k) {
+        const int i = threadIdx.x + 256 * k;
+        if (i < NWT) {
+          const int co = (i >> 2) % CT, t = (i >> 2) / CT;
+          const int64_t wo = ((int64_t)t * Cout + blockIdx.y * CT + co) * Cin + c0 + 8 * q;
+          const int d = (t * CT + co) * PS + 4 * q;
+          *reinterpret_cast<uint4*>(wtile + d) = *reinterpret_cast<const uint4*>(Whi + wo);
+          if (SPLIT == 3)
+            *reinterpret_cast<uint4*>(wtile + WS + d) = *reinterpret_cast<const uint4*>(Wlo + wo);
+        }
       }
     }
     __syncthreads();
