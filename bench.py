@@ -524,15 +524,8 @@ def unet_flops(H, W, B, padded=False):
     the network's own channels (5 real input fields into the first layer, 5
     real outputs of the last), or as the kernels run them (padded=True: 32
     channels there, one matrix-core pass)."""
-    from paper_2408_01081_amd.surrogate import LAYERS
-    levels = [0, 0, 0, 1, 1, 2, 2, 3, 3, 2, 2, 1, 1, 0, 0, 0]
-    tot = 0
-    for (name, ci, co), lv in zip(LAYERS, levels):
-        if not padded:
-            ci = 5 if name == "in" else ci
-            co = 5 if name == "out" else co
-        tot += 2 * 9 * ci * co * (H >> lv) * (W >> lv)
-    return tot * B
+    from paper_2408_01081_amd.surrogate import forward_flops
+    return forward_flops(B, H, W, padded=padded)
 
 
 def window_op_flops(H, W, B):
