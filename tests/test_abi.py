@@ -105,3 +105,39 @@ def test_zero_shear_modulus_is_admitted_with_the_gradient_initialisation():
     assert L.lbm_batch_workspace_bytes(2, ctypes.cast(arr, ctypes.c_void_p)) == 0
     neg = _lib.LbmParams(32, 32, 1.0 / 32, 0.4 / 32, 1.5, -0.1, 1.0, 0, 0, 0)
     assert L.lbm_workspace_bytes(ctypes.byref(neg)) == 0
+
+
+def test_split_dirichlet_launch_rule():
+    # which blocked launches of a Dirichlet lattice run split (interior with
+    # the periodic kernel's code, wall band with the Dirichlet rule): the
+    # variant has a split kernel (T, store type, prefetch), the interior
+    # strips [1, (nx - T) // (64 - 2T)) are one or more and ny >= 33; mode 1
+    # splits every such variant, -1 (the default) those with T >= 5, 0 none;
+    # periodic lattices never; host logic only (no device work)
+    from paper_2408_01081_amd import _lib
+    L = _lib.load()
+    kernels = {(7, 0, 1), (7, 0, 2), (6, 0, 1), (6, 0, 2), (5, 0, 1)}
+    info = []
+    for i in range(L.lbm_tblock_config_count()):
+        t, sr, nt, pf = (ctypes.c_int32() for _ in range(4))
+        assert L.lbm_tblock_config_info(i, ctypes.byref(t), ctypes.byref(sr), ctypes.byref(nt),
+                                        ctypes.byref(pf)) == 0
+        info.append((t.value, nt.value, pf.value))
+    for nx, ny, bc in ((2048, 1024, 1), (130, 33, 1), (130, 32, 1), (100, 40, 1), (64, 64, 1),
+                       (2048, 1024, 0)):
+        p = _lib.LbmParams(nx, ny, 1.0 / nx, 0.2 / nx, 1.0, 0.5, 1.0, bc, 0, 0)
+        nb = L.lbm_workspace_bytes(ctypes.byref(p))
+        h = ctypes.c_void_p()
+        assert L.lbm_create(ctypes.byref(p), ctypes.c_void_p(256), nb, None, ctypes.byref(h)) == 0
+        try:
+            for mode in (1, -1, 0):
+                assert L.lbm_set_tblock_split(h, mode) == 0
+                for i, (T, nt, pf) in enumerate(info):
+                    fits = (bc == 1 and (T, nt, pf) in kernels and (nx - T) // (64 - 2 * T) > 1
+                            and ny >= 33)
+                    want = fits and (mode == 1 or (mode == -1 and T >= 5))
+                    assert L.lbm_tblock_split_active(h, i) == int(want), (nx, ny, bc, mode, i)
+            assert L.lbm_set_tblock_split(h, 2) != 0
+            assert L.lbm_tblock_split_active(h, len(info)) == -1
+        finally:
+            L.lbm_destroy(h)
