@@ -326,10 +326,11 @@ lbm_status lbm_set_tblock_config(lbm_ctx* ctx, int32_t index);
  * Dirichlet rule as 16-row segments, in one grid; results are bitwise those
  * of the unsplit launch.  Variants with T, store type and prefetch of a
  * split kernel (T = 7, 6 with one or two rows prefetched, T = 5 with one;
- * plain stores) can run split.  mode -1 (default): those
- * with T >= 5 where the lattice allows; 0: never; 1: all of them where the
- * lattice allows (at least one interior strip, and ny >= 33).  LBM_E_ARG
- * for another mode.  The autotuner's choices are kept per mode. */
+ * plain stores; at T = 8 the Dirichlet code keeps scratch spills and no
+ * split kernel is built) run split where the lattice allows it (at least
+ * one interior strip, and ny >= 33).  mode -1 (default) or 1: split those;
+ * 0: never.  LBM_E_ARG for another mode.  The autotuner's choices are kept
+ * per mode. */
 lbm_status lbm_set_tblock_split(lbm_ctx* ctx, int32_t mode);
 /* 1 if launches of blocked variant `index` run split on this context as
  * configured now, 0 if not, -1 for a NULL context or a bad index. */

@@ -401,9 +401,10 @@ struct lbm_ctx {
   int tb_slots[64];   // resident waves of a blocked variant on this device (0: not known)
   int tbf_slots[48];  // the same for the variants with a load / displacement (3 per variant)
   int tb_rem[9];      // variant for the last r = 2 .. 8 steps of a run (-1: nearest shape)
-  // split Dirichlet blocked launches (mode -1 automatic, 0 never, 1 wherever
-  // the lattice allows): the wall band with the Dirichlet rule and the
-  // interior with the periodic kernel's code, in one launch
+  // split Dirichlet blocked launches (mode -1, the default, or 1: wherever a
+  // split kernel exists and the lattice allows; 0: never): the wall band
+  // with the Dirichlet rule and the interior with the periodic kernel's
+  // code, in one launch
   int tb_split;
   int tbs_slots[8];  // resident waves of a split kernel on this device (0: not known)
   float* wall_v;        // [WALL_CHUNK][2 (nx + ny)][2] wall velocities of upcoming steps
@@ -903,7 +904,6 @@ int tb_seg_rows(lbm_ctx* c, int index) {
 // at the top and bottom walls and per segment of the side-wall strips
 // (2048 x 1024, T = 7: 151 GLUPS; 8 or 24 rows: 142, 32: 106 to 147).
 constexpr int SPLIT_ROWS = 16;
-constexpr int SPLIT_AUTO_MIN_T = 5;  // automatic mode: where the Dirichlet kernel keeps spill registers
 
 struct SplitPlan {
   int kernel;  // index into kTBSplitVariants
@@ -943,7 +943,6 @@ bool split_plan(lbm_ctx* c, int index, SplitPlan& sp) {
   if (c->p.bc != LBM_DIRICHLET || c->tb_split == 0) return false;
   const TBVariant& k = kTBVariants[index];
   const int T = k.steps;
-  if (c->tb_split < 0 && T < SPLIT_AUTO_MIN_T) return false;
   sp.kernel = split_kernel(index);
   if (sp.kernel < 0) return false;
   const Grid& g = c->g;

@@ -258,8 +258,8 @@ class Lattice:
     def set_tblock_split(self, mode):
         """Split blocked launches of a Dirichlet lattice (interior with the
         periodic kernel's code, wall band with the Dirichlet rule, one
-        launch): -1 automatic (T >= 5), 0 never, 1 wherever the lattice
-        allows."""
+        launch): -1 (the default) or 1 wherever a split kernel exists and
+        the lattice allows, 0 never."""
         check(self.L.lbm_set_tblock_split(self.ctx, int(mode)))
 
     def tblock_split_active(self, index):

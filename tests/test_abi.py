@@ -111,9 +111,9 @@ def test_split_dirichlet_launch_rule():
     # which blocked launches of a Dirichlet lattice run split (interior with
     # the periodic kernel's code, wall band with the Dirichlet rule): the
     # variant has a split kernel (T, store type, prefetch), the interior
-    # strips [1, (nx - T) // (64 - 2T)) are one or more and ny >= 33; mode 1
-    # splits every such variant, -1 (the default) those with T >= 5, 0 none;
-    # periodic lattices never; host logic only (no device work)
+    # strips [1, (nx - T) // (64 - 2T)) are one or more and ny >= 33; modes
+    # -1 (the default) and 1 split every such variant, 0 none; periodic
+    # lattices never; host logic only (no device work)
     from paper_2408_01081_amd import _lib
     L = _lib.load()
     kernels = {(7, 0, 1), (7, 0, 2), (6, 0, 1), (6, 0, 2), (5, 0, 1)}
@@ -135,7 +135,7 @@ def test_split_dirichlet_launch_rule():
                 for i, (T, nt, pf) in enumerate(info):
                     fits = (bc == 1 and (T, nt, pf) in kernels and (nx - T) // (64 - 2 * T) > 1
                             and ny >= 33)
-                    want = fits and (mode == 1 or (mode == -1 and T >= 5))
+                    want = fits and mode != 0
                     assert L.lbm_tblock_split_active(h, i) == int(want), (nx, ny, bc, mode, i)
             assert L.lbm_set_tblock_split(h, 2) != 0
             assert L.lbm_tblock_split_active(h, len(info)) == -1
