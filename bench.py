@@ -528,20 +528,37 @@ def unet_flops(H, W, B, padded=False):
     return forward_flops(B, H, W, padded=padded)
 
 
+def window_op_tiles(H, W, B):
+    """(matrix tiles per wave, column tiles per workgroup) that lbm_wop_apply
+    picks for B windows of H x W: 2, 2 where that gives >= 512 workgroups,
+    else 2, 1 where that does, else 1, 2, else 1, 1, each only while it
+    computes at most 15% more columns than 16-column granularity."""
+    ty = (H + 2) // 3
+    c16 = (W + 15) // 16 * 16
+    def ok(cols, min_wgs):
+        n = (W + cols - 1) // cols
+        return n * cols * 100 <= c16 * 115 and n * ty * B >= min_wgs
+    if ok(64, 512):
+        return 2, 2
+    if ok(32, 512):
+        return 2, 1
+    if ok(32, 0):
+        return 1, 2
+    return 1, 1
+
+
 def window_op_flops(H, W, B):
     """(useful, issued) FLOPs of one application of the exact window
     operator: 2 x 5 x 5 per tap of the diamond |dx| + |dy| <= 17 (613 taps)
     per output node, and what the matrix-core kernel issues (16 x 16 x 4
     products, 5 x 48 x 4 = 960 per tile of 16 columns x 3 rows, padding
-    included; workgroups of 128 columns, or of 64 where 128 would compute
-    over 15% more columns than needed or need more than 1024 workgroups)."""
+    included, over the columns of the workgroups window_op_tiles gives)."""
     R = 17
     taps = 2 * R * R + 2 * R + 1
     useful = 2 * taps * 25 * H * W * B
-    c1, c2 = (W + 63) // 64 * 64, (W + 127) // 128 * 128
-    wide = W > 64 and c2 * 100 <= c1 * 115 and c2 // 128 * ((H + 2) // 3) * B <= 1024
-    cols = c2 if wide else c1
-    tiles = (cols // 16) * ((H + 2) // 3) * B
+    mt, nct = window_op_tiles(H, W, B)
+    cols = 16 * mt * nct
+    tiles = ((W + cols - 1) // cols) * mt * nct * ((H + 2) // 3) * B
     issued = 2 * 16 * 16 * 4 * 960 * tiles
     return useful, issued
 

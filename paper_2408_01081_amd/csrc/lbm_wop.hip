@@ -21,10 +21,10 @@
 //                   5 output fields (15 of 16), K = (input field, input row,
 //                   input column) over the union of the three rows' diamonds,
 //                   4 columns per product, every B operand shared by the MT
-//                   tiles; the input tile of a workgroup (4 column tiles side
-//                   by side, periodic wrap) is staged in LDS, and 4 waves per
-//                   column tile take a quarter of the K range each (more
-//                   waves per SIMD to cover the operand's L2 latency).
+//                   tiles; the input tile of a workgroup (NCT column tiles
+//                   side by side, periodic wrap) is staged in LDS, and 4
+//                   waves per column tile take a quarter of the K range each
+//                   (more waves per SIMD to cover the operand's L2 latency).
 #include <hip/hip_runtime.h>
 
 #include <math.h>
@@ -44,7 +44,6 @@ constexpr int WOP_SIDE = 2 * WOP_R + 1;             // taps per side
 constexpr int WOP_GEN = 2 * WOP_R + 6;              // side of the generating lattice
 constexpr int WOP_TR = 3;                           // output rows per wave tile
 constexpr int WOP_RY = WOP_TR + 2 * WOP_R;          // input rows of a tile
-constexpr int WOP_WAVES = 4;
 
 // input row ri of a tile (row Y0 - R + ri): half-width of the columns any of
 // the tile's output rows Y0 .. Y0 + 2 reaches there, and the 4-column
@@ -63,7 +62,7 @@ constexpr int WOP_GF = (WOP_STEPS_F + 3) / 4;          // groups of 4 products p
 constexpr int WOP_GROUPS = NC * WOP_GF;
 constexpr int WOP_BPF = 2;                             // B groups read ahead
 constexpr int WOP_KS = 4;                              // parts of the K range, one wave each
-constexpr int WOP_THREADS = 64 * WOP_WAVES * WOP_KS;
+
 
 // Offset of product sl of a field (sl < 4 WOP_GF) in a tile row of pitch P
 // relative to the field's plane: input row ri, first column R - half + 4 j
@@ -172,14 +171,17 @@ __device__ inline int wrap_index(int v, int n) {
   return r < 0 ? r + n : r;
 }
 
-// Tile geometry of k_wop_apply with MT 16-column matrix tiles per wave: a
-// workgroup covers COLS output columns of three rows, and stages input
-// columns X0 - R .. X0 + COLS + R + 2 of every input row and field in LDS.
-template <int MT>
+// Tile geometry of k_wop_apply with MT 16-column matrix tiles per wave and
+// NCT column tiles (of 16 MT columns) per workgroup: a workgroup covers COLS
+// output columns of three rows, and stages input columns X0 - R .. X0 + COLS
+// + R + 2 of every input row and field in LDS; WOP_KS waves per column tile.
+__host__ __device__ constexpr int wop_threads(int nct) { return 64 * nct * WOP_KS; }
+template <int MT, int NCT>
 struct WopTile {
-  static constexpr int COLS = 16 * MT * WOP_WAVES;
+  static constexpr int COLS = 16 * MT * NCT;
   static constexpr int PITCH = COLS + 2 * WOP_R + 3;
   static constexpr int PLANE = WOP_RY * PITCH;
+  static constexpr int THREADS = wop_threads(NCT);
 };
 
 // The products of groups Q0 .. Q0 + NQ - 1 of every input field into acc:
@@ -188,11 +190,10 @@ struct WopTile {
 // loop is unrolled); A is read one group ahead and B WOP_BPF groups ahead
 // (in this wave's order: fields in turn, groups Q0 .. Q0 + NQ - 1 of each)
 // while the current group's products run.
-template <int MT, int Q0, int NQ>
+template <int MT, int PITCH, int PLANE, int Q0, int NQ>
 __device__ __forceinline__ void wop_products(const float* abase, const f32x4* bq,
                                              f32x4 (&acc)[MT]) {
   static_assert(WOP_BPF <= NQ, "read-ahead within one field's part");
-  constexpr int PITCH = WopTile<MT>::PITCH, PLANE = WopTile<MT>::PLANE;
   constexpr WopOffsets<PITCH> kOff{};
   float a[MT][4];
 #pragma unroll
@@ -235,42 +236,42 @@ __device__ __forceinline__ void wop_products(const float* abase, const f32x4* bq
 }
 
 // part kh of the K range: groups kh NQ .. (kh + 1) NQ - 1 of every field
-template <int MT, int K>
+template <int MT, int PITCH, int PLANE, int K>
 __device__ __forceinline__ void wop_part(int kh, const float* abase, const f32x4* bq,
                                          f32x4 (&acc)[MT]) {
   constexpr int NQ = WOP_GF / WOP_KS;
   if (kh == K)
-    wop_products<MT, K * NQ, NQ>(abase, bq, acc);
+    wop_products<MT, PITCH, PLANE, K * NQ, NQ>(abase, bq, acc);
   else if constexpr (K + 1 < WOP_KS)
-    wop_part<MT, K + 1>(kh, abase, bq, acc);
+    wop_part<MT, PITCH, PLANE, K + 1>(kh, abase, bq, acc);
 }
 
 // One workgroup: output columns X0 .. X0 + COLS - 1 of rows Y0 .. Y0 + 2 of
-// window blockIdx.y.  Wave w computes columns X0 + 16 MT (w % 4) .. + 16 MT
-// - 1 as MT matrix tiles that share every B operand, over part w / 4 of the
-// K range; the parts' sums are added in order at the end.
-template <int MT>
-__global__ __launch_bounds__(WOP_THREADS) void k_wop_apply(const float* __restrict__ in,
-                                                           float* __restrict__ out,
-                                                           const WopOperand* __restrict__ op,
-                                                           int nx, int ny, int tiles_x) {
-  constexpr int PITCH = WopTile<MT>::PITCH, PLANE = WopTile<MT>::PLANE;
-  constexpr int NW = WOP_THREADS / 64;
-  static_assert(WOP_KS * WOP_WAVES * MT * 64 * 16 <= NC * PLANE * 4, "partial sums fit the tile");
+// window blockIdx.y.  Wave w computes columns X0 + 16 MT (w % NCT) .. + 16 MT
+// - 1 as MT matrix tiles that share every B operand, over part w / NCT of
+// the K range; the parts' sums are added in order at the end.
+template <int MT, int NCT>
+__global__ __launch_bounds__(wop_threads(NCT)) void k_wop_apply(
+    const float* __restrict__ in, float* __restrict__ out, const WopOperand* __restrict__ op,
+    int nx, int ny, int tiles_x) {
+  using TL = WopTile<MT, NCT>;
+  constexpr int PITCH = TL::PITCH, PLANE = TL::PLANE, NT = TL::THREADS;
+  constexpr int NW = NT / 64;
+  static_assert(WOP_KS * NCT * MT * 64 * 16 <= NC * PLANE * 4, "partial sums fit the tile");
   __shared__ float tile[NC * PLANE];
   __shared__ int rowy[WOP_RY];
   const int tid = threadIdx.x;
   const int tx = blockIdx.x % tiles_x, ty = blockIdx.x / tiles_x;
-  const int X0 = tx * WopTile<MT>::COLS, Y0 = ty * WOP_TR;
+  const int X0 = tx * TL::COLS, Y0 = ty * WOP_TR;
   const int64_t nn = (int64_t)nx * ny;
   const float* src = in + (int64_t)blockIdx.y * NC * nn;
   float* dst = out + (int64_t)blockIdx.y * NC * nn;
   // periodic wrap of the tile's rows and of this lane's columns (any
   // lattice size): lane fills tile columns lane + 64 c, c < CPL, the last
   // one for lanes < CLAST only
-  for (int i = tid; i < WOP_RY; i += WOP_THREADS) rowy[i] = wrap_index(Y0 - WOP_R + i, ny);
+  for (int i = tid; i < WOP_RY; i += NT) rowy[i] = wrap_index(Y0 - WOP_R + i, ny);
   const int w = tid >> 6, lane = tid & 63, m = lane & 15, g = lane >> 4;
-  const int wc = w % WOP_WAVES, kh = w / WOP_WAVES;
+  const int wc = w % NCT, kh = w / NCT;
   constexpr int CPL = (PITCH + 63) / 64;
   constexpr int CLAST = PITCH - 64 * (CPL - 1);
   int cx[CPL];
@@ -309,19 +310,19 @@ __global__ __launch_bounds__(WOP_THREADS) void k_wop_apply(const float* __restri
   f32x4 acc[MT];
 #pragma unroll
   for (int t = 0; t < MT; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
-  wop_part<MT, 0>(kh, abase, bq, acc);
+  wop_part<MT, PITCH, PLANE, 0>(kh, abase, bq, acc);
   // partial sums of parts 1 .. KS - 1 through LDS (the tile is no longer read)
   __syncthreads();
   f32x4* part = reinterpret_cast<f32x4*>(tile);
   if (kh > 0)
 #pragma unroll
-    for (int t = 0; t < MT; ++t) part[(((kh - 1) * WOP_WAVES + wc) * MT + t) * 64 + lane] = acc[t];
+    for (int t = 0; t < MT; ++t) part[(((kh - 1) * NCT + wc) * MT + t) * 64 + lane] = acc[t];
   __syncthreads();
   if (kh > 0) return;
 #pragma unroll
   for (int k = 1; k < WOP_KS; ++k)
 #pragma unroll
-    for (int t = 0; t < MT; ++t) acc[t] += part[(((k - 1) * WOP_WAVES + wc) * MT + t) * 64 + lane];
+    for (int t = 0; t < MT; ++t) acc[t] += part[(((k - 1) * NCT + wc) * MT + t) * 64 + lane];
   // D[i][n]: lane holds n = lane % 16 = 5 t + co for pixels i = 4 g + v
   const int n = lane & 15;
   if (n >= NC * WOP_TR) return;
@@ -350,6 +351,16 @@ size_t gen_ws_bytes(const lbm_params* p) {
 constexpr size_t WOP_FIELDS_BYTES = (size_t)(2 + 3) * WOP_GEN * WOP_GEN * 8;
 constexpr size_t WOP_RESP_BYTES = (size_t)NC * WOP_GEN * WOP_GEN * 4;
 constexpr size_t WOP_G_BYTES = (size_t)WOP_SIDE * WOP_SIDE * NC * NC * 4;
+
+template <int MT, int NCT>
+void launch_wop(const lbm_params* p, const WopOperand* op, const float* in, float* out, int batch,
+                hipStream_t st) {
+  using TL = WopTile<MT, NCT>;
+  const int tiles_x = (p->nx + TL::COLS - 1) / TL::COLS;
+  const int tiles_y = (p->ny + WOP_TR - 1) / WOP_TR;
+  hipLaunchKernelGGL((k_wop_apply<MT, NCT>), dim3((unsigned)(tiles_x * tiles_y), (unsigned)batch),
+                     dim3(TL::THREADS), 0, st, in, out, op, p->nx, p->ny, tiles_x);
+}
 
 lbm_status check_window_params(const lbm_params* p) {
   if (!p) return fail(LBM_E_ARG, "null params");
@@ -435,23 +446,30 @@ lbm_status lbm_wop_apply(const lbm_params* p, const void* d_op, const float* d_i
   const int64_t nb = (int64_t)NC * p->nx * p->ny * 4 * batch;
   const char *a = (const char*)d_in, *b = (const char*)d_out;
   if (a < b + nb && b < a + nb) return fail(LBM_E_ARG, "input and output overlap");
-  // Two matrix tiles per wave (half the B traffic per product; one
-  // workgroup of 122 KB LDS per CU) for launches of at most 1024 such
-  // workgroups that compute at most 15% more columns than 64-column
-  // workgroups would; one tile per wave otherwise (two workgroups per CU)
+  // Tile shape by the launch's size (measured on 64^2 .. 512^2, batches 1
+  // to 32): two 16-column matrix tiles per wave (half the B traffic per
+  // product) and two column tiles per workgroup where that gives 512 or
+  // more workgroups, else one column tile per workgroup (more, smaller
+  // workgroups spread over the CUs), else one matrix tile per wave; each
+  // only while it computes at most 15% more columns than 16-column
+  // granularity would.
   const int64_t ty64 = (p->ny + WOP_TR - 1) / WOP_TR;
-  const int64_t c1 = ((int64_t)p->nx + 63) / 64 * 64, c2 = ((int64_t)p->nx + 127) / 128 * 128;
-  const bool wide = p->nx > 64 && c2 * 100 <= c1 * 115 && c2 / 128 * ty64 * batch <= 1024;
-  const int64_t cols = wide ? WopTile<2>::COLS : WopTile<1>::COLS;
-  const int64_t tiles_x = (p->nx + cols - 1) / cols;
-  if (tiles_x * ty64 > 0x7fffffff) return fail(LBM_E_ARG, "window too large");
-  const dim3 grid((unsigned)(tiles_x * ty64), (unsigned)batch);
-  if (wide)
-    hipLaunchKernelGGL(k_wop_apply<2>, grid, dim3(WOP_THREADS), 0, (hipStream_t)hip_stream, d_in,
-                       d_out, (const WopOperand*)d_op, p->nx, p->ny, (int)tiles_x);
+  if ((p->nx / 16 + 1) * ty64 > 0x7fffffff) return fail(LBM_E_ARG, "window too large");
+  const int64_t c16 = ((int64_t)p->nx + 15) / 16 * 16;
+  auto ok = [&](int64_t cols, int64_t min_wgs) {
+    const int64_t n = (p->nx + cols - 1) / cols;
+    return n * cols * 100 <= c16 * 115 && n * ty64 * batch >= min_wgs;
+  };
+  const WopOperand* o = (const WopOperand*)d_op;
+  hipStream_t st = (hipStream_t)hip_stream;
+  if (ok(64, 512))
+    launch_wop<2, 2>(p, o, d_in, d_out, batch, st);
+  else if (ok(32, 512))
+    launch_wop<2, 1>(p, o, d_in, d_out, batch, st);
+  else if (ok(32, 0))
+    launch_wop<1, 2>(p, o, d_in, d_out, batch, st);
   else
-    hipLaunchKernelGGL(k_wop_apply<1>, grid, dim3(WOP_THREADS), 0, (hipStream_t)hip_stream, d_in,
-                       d_out, (const WopOperand*)d_op, p->nx, p->ny, (int)tiles_x);
+    launch_wop<1, 1>(p, o, d_in, d_out, batch, st);
   return launch_check("k_wop_apply launch");
 }
 
