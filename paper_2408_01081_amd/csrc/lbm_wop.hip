@@ -279,13 +279,15 @@ __global__ __launch_bounds__(wop_threads(NCT)) void k_wop_apply(
   for (int c = 0; c < CPL; ++c)
     cx[c] = (c + 1 < CPL || lane < CLAST) ? wrap_index(X0 - WOP_R + 64 * c + lane, nx) : 0;
   __syncthreads();
-  // fill: wave w takes the (field, row) lines w, w + NW, w + 2 NW, ..., four
-  // lines per round so that 4 CPL loads per lane are in flight
+  // fill: wave w takes the (field, row) lines w, w + NW, w + 2 NW, ..., LPR
+  // lines per round so that LPR CPL loads per lane are in flight (the
+  // registers of the products are not live yet)
   constexpr int LINES = NC * WOP_RY;
-  for (int l0 = w; l0 < LINES; l0 += 4 * NW) {
-    float v[4][CPL];
+  constexpr int LPR = 16 / CPL > 4 ? 16 / CPL : 4;
+  for (int l0 = w; l0 < LINES; l0 += LPR * NW) {
+    float v[LPR][CPL];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < LPR; ++k) {
       const int ln = l0 + NW * k;
       if (ln < LINES) {
         const int c = ln / WOP_RY, r = ln - c * WOP_RY;
@@ -295,7 +297,7 @@ __global__ __launch_bounds__(wop_threads(NCT)) void k_wop_apply(
       }
     }
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < LPR; ++k) {
       const int ln = l0 + NW * k;
       if (ln < LINES) {
 #pragma unroll
