@@ -63,7 +63,6 @@ constexpr int WOP_GROUPS = NC * WOP_GF;
 constexpr int WOP_BPF = 2;                             // B groups read ahead
 constexpr int WOP_KS = 4;                              // parts of the K range, one wave each
 
-
 // Offset of product sl of a field (sl < 4 WOP_GF) in a tile row of pitch P
 // relative to the field's plane: input row ri, first column R - half + 4 j
 // of the 4 the product covers (past the field's products: 0, with zero taps)

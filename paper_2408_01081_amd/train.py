@@ -71,36 +71,100 @@ def generate(n_traj, side=128, windows=16, bc=0, seed=4, chunk=512, device="cuda
     return data, mat, bc
 
 
-def assemble(data, mat, idx, widx, out_in, out_tgt):
-    """Input [B][8][H][W] (fields of window widx, material channels) and
-    target [B][5][H][W] (fields after the window) for trajectories idx."""
+def pairs_of(data):
+    """Training pairs of a trajectory set: inputs data[:, w], targets
+    data[:, w + 1] (views, no copy)."""
+    return data[:, :-1], data[:, 1:]
+
+
+def assemble(inp, tgt, mat, idx, widx, out_in, out_tgt):
+    """Input [B][8][H][W] (fields inp[idx, widx], material channels) and
+    target [B][5][H][W] (tgt[idx, widx]) for pair sets of [n][W][5][H][W]."""
     B = len(idx)
-    it = torch.as_tensor(idx, device=data.device)
-    wt = torch.as_tensor(widx, device=data.device)
-    out_in[:B, :5] = data[it, wt]
-    out_tgt[:B] = data[it, wt + 1]
-    m = mat.to(data.device)[it]
+    it = torch.as_tensor(idx, device=inp.device)
+    wt = torch.as_tensor(widx, device=inp.device)
+    out_in[:B, :5] = inp[it, wt]
+    out_tgt[:B] = tgt[it, wt]
+    m = mat.to(inp.device)[it]
     out_in[:B, 5:] = m[:, :, None, None]
+
+
+def pushforward(net, inp, mat, bc, batch, chain=False, chunk=512):
+    """Pairs on the states a rollout of the surrogate visits: y and its image
+    under the judge's window map L(y) = moments(16 steps from the FP64
+    re-initialisation of y), with the trajectory's material, dx = 1 and the
+    time step at half the CFL-like limit (as generate() draws them).  y =
+    net(x) for every input x of the pair set, or (chain) the network's own
+    chain from each trajectory's first input, y_w = net^(w+1)(x_0), the
+    states of a rollout in which every window is accepted.  Returns
+    (y, L(y)), each [n][W][5][H][H] float32 on the device."""
+    import synth
+    n, W, H = inp.shape[0], inp.shape[1], inp.shape[3]
+    dev = inp.device
+    pin = torch.empty((n, W, 5, H, H), dtype=torch.float32, device=dev)
+    ptg = torch.empty_like(pin)
+    xin = torch.empty((batch, 8, H, H), dtype=torch.float32, device=dev)
+    tgt = torch.empty((batch, 5, H, H), dtype=torch.float32, device=dev)
+    if chain:
+        for w in range(W):
+            src = inp[:, 0] if w == 0 else pin[:, w - 1]
+            for k in range(0, n, batch):
+                B = min(batch, n - k)
+                xin[:B, :5] = src[k:k + B]
+                xin[:B, 5:] = mat[k:k + B].to(dev)[:, :, None, None]
+                pin[k:k + B, w] = net.forward(xin[:B], circular=(bc == 0))
+    else:
+        pairs = [(i, w) for i in range(n) for w in range(W)]
+        for k in range(0, len(pairs), batch):
+            pp = pairs[k:k + batch]
+            B = len(pp)
+            it, wt = [p[0] for p in pp], [p[1] for p in pp]
+            assemble(inp, inp, mat, it, wt, xin, tgt)
+            pin[torch.as_tensor(it, device=dev), torch.as_tensor(wt, device=dev)] = \
+                net.forward(xin[:B], circular=(bc == 0))
+    for c0 in range(0, n, chunk):
+        c1 = min(n, c0 + chunk)
+        insts = []
+        for lam, mu, rho in mat[c0:c1].double().cpu().numpy():
+            m = synth.Material.from_lame(float(lam), float(mu), float(rho))
+            insts.append(dict(nx=H, ny=H, dx=1.0, dt=synth.dt_at_cfl_fraction(1.0, m, 0.5),
+                              lam=float(lam), mu=float(mu), rho=float(rho), bc=int(bc)))
+        b = Batch(insts, device=dev)
+        mo = torch.empty((c1 - c0, 5, H, H), dtype=torch.float32, device=dev)
+        for w in range(W):
+            b.init_fields_f32(pin[c0:c1, w].contiguous())
+            b.step(K_WINDOW)
+            b.moments(out=mo.view(-1))
+            ptg[c0:c1, w] = mo
+        del b
+    torch.cuda.synchronize(dev)
+    return pin, ptg
 
 
 def window_errors(net, data, mat, circular, batch, max_pairs=4096, seed=0):
     """Per-window relative L2 error (system variables U, FP64 on the device)
     of the surrogate against the lattice window map, on up to max_pairs
     (trajectory, window) pairs."""
-    n, W1 = data.shape[0], data.shape[1]
+    return pair_errors(net, *pairs_of(data), mat, circular, batch, max_pairs, seed)
+
+
+def pair_errors(net, inp, tgt_set, mat, circular, batch, max_pairs=4096, seed=0):
+    """Per-pair relative L2 error (system variables U) of the surrogate on up
+    to max_pairs pairs of a pair set."""
+    n, W = inp.shape[0], inp.shape[1]
     g = np.random.default_rng(seed)
-    pairs = [(i, w) for i in range(n) for w in range(W1 - 1)]
+    pairs = [(i, w) for i in range(n) for w in range(W)]
     if len(pairs) > max_pairs:
         sel = g.choice(len(pairs), max_pairs, replace=False)
         pairs = [pairs[k] for k in sel]
-    H = data.shape[3]
-    xin = torch.empty((batch, 8, H, H), dtype=torch.float32, device=data.device)
-    tgt = torch.empty((batch, 5, H, H), dtype=torch.float32, device=data.device)
+    H = inp.shape[3]
+    xin = torch.empty((batch, 8, H, H), dtype=torch.float32, device=inp.device)
+    tgt = torch.empty((batch, 5, H, H), dtype=torch.float32, device=inp.device)
     errs = []
     for k in range(0, len(pairs), batch):
         pp = pairs[k:k + batch]
         B = len(pp)
-        assemble(data, mat, [p[0] for p in pp], [p[1] for p in pp], xin, tgt)
+        assemble(inp, tgt_set, mat, [p[0] for p in pp], [p[1] for p in pp], xin, tgt)
         out = net.forward(xin[:B], circular=circular)
         errs.append(rel_l2_U(out, tgt[:B], xin[:B, 5:]))
     return np.concatenate(errs)
@@ -131,7 +195,8 @@ def rel_l2_U(a, b, material, chunk=64):
 def train(net, sets, minutes, batch, lr0=1e-3, lr_end=2e-5, seed=0, log_every=100,
           max_steps=None, spike=1000.0):
     """Adam with a cosine learning-rate decay over the time budget.  sets is
-    a list of (data, mat, bc) training sets; batches alternate between them.
+    a list of (inputs, targets, mat, bc) pair sets ([n][W][5][H][W] each);
+    batches alternate between them.
 
     The network is linear in the fields and has no saturation, so an unlucky
     update can make it diverge: every log_every steps the loss is checked, the
@@ -156,11 +221,10 @@ def train(net, sets, minutes, batch, lr0=1e-3, lr_end=2e-5, seed=0, log_every=10
             break
         frac = min(1.0, el / budget)
         lr = scale * (lr_end + 0.5 * (lr0 - lr_end) * (1 + math.cos(math.pi * frac)))
-        data, mat, bc = sets[step % len(sets)]
-        n, W1 = data.shape[0], data.shape[1]
-        idx = g.integers(0, n, batch)
-        widx = g.integers(0, W1 - 1, batch)
-        assemble(data, mat, idx, widx, xin, tgt)
+        inp, tg, mat, bc = sets[step % len(sets)]
+        idx = g.integers(0, inp.shape[0], batch)
+        widx = g.integers(0, inp.shape[1], batch)
+        assemble(inp, tg, mat, idx, widx, xin, tgt)
         check = (step % log_every) == 0
         loss = net.train_step(xin, tgt, circular=(bc == 0), lr=lr, want_loss=check)
         if check:
@@ -197,13 +261,24 @@ def main():
     ap.add_argument("--lr", type=float, default=5e-4)
     ap.add_argument("--init", default="")
     ap.add_argument("--report", default="")
+    ap.add_argument("--seed-periodic", type=int, default=4)
+    ap.add_argument("--seed-dirichlet", type=int, default=5)
+    ap.add_argument("--pushforward-rounds", type=int, default=0,
+                    help="split the time into this many rounds, each training on the "
+                         "trajectory pairs and on pairs (y, L(y)) of the network's own "
+                         "outputs y (recomputed at the start of every round)")
+    ap.add_argument("--chain", action="store_true",
+                    help="with --pushforward-rounds: y along the network's own chain from "
+                         "each trajectory's first state (a rollout's states)")
     args = ap.parse_args()
     t0 = time.time()
     sets = []
     if args.n_periodic:
-        sets.append(generate(args.n_periodic, args.side, args.windows, bc=0, seed=4))
+        sets.append(generate(args.n_periodic, args.side, args.windows, bc=0,
+                             seed=args.seed_periodic))
     if args.n_dirichlet:
-        sets.append(generate(args.n_dirichlet, args.side, args.windows, bc=1, seed=5))
+        sets.append(generate(args.n_dirichlet, args.side, args.windows, bc=1,
+                             seed=args.seed_dirichlet))
     t_gen = time.time() - t0
     log("data: %s in %.1fs" % ([tuple(s[0].shape) for s in sets], t_gen))
     # hold out the last 1/8 of every set for validation
@@ -215,16 +290,48 @@ def main():
     net = Surrogate(args.batch, args.side, args.side, split=args.split, train=True)
     p0 = np.load(args.init, allow_pickle=False) if args.init else pack_params(init_params(0, 0.0))
     net.set_params(p0.astype(np.float32))
-    steps, hist, info = train(net, train_sets, args.minutes, args.batch, lr0=args.lr)
+    trajs = [(*pairs_of(d), m, bc) for d, m, bc in train_sets]
+    rounds = max(1, args.pushforward_rounds)
+    steps, hist, info = 0, [], {}
+    for r in range(rounds):
+        sets_r = list(trajs)
+        if args.pushforward_rounds:
+            t1 = time.time()
+            for inp, tg, m, bc in trajs:
+                sets_r.append((*pushforward(net, inp, m, bc, args.batch, chain=args.chain), m,
+                               bc))
+            log("round %d: pushforward pairs in %.1fs" % (r, time.time() - t1))
+        s_r, h_r, info = train(net, sets_r, args.minutes / rounds, args.batch, lr0=args.lr)
+        steps += s_r
+        hist += [(steps - s_r + h[0],) + tuple(h[1:]) for h in h_r]
+        sets_r = None
     params = net.get_params().cpu().numpy()
     np.save(args.out, params, allow_pickle=False)
     rep = {"steps": steps, "minutes": args.minutes, "data_seconds": round(t_gen, 1),
+           "pushforward_rounds": args.pushforward_rounds,
            "history": hist[::max(1, len(hist) // 40)], "validation": {}, **info}
     for data, mat, bc in val_sets:
         e = window_errors(net, data, mat, bc == 0, args.batch)
+        # the second window of a surrogate chain: the network on its own
+        # outputs, against the window map of those outputs (the judge's test
+        # in a rollout)
+        pin, ptg = pushforward(net, data[:, :-1], mat, bc, args.batch)
+        e2 = pair_errors(net, pin, ptg, mat, bc == 0, args.batch)
+        # and along the network's own chain (a fully accepted rollout)
+        pin, ptg = pushforward(net, data[:, :-1], mat, bc, args.batch, chain=True)
+        e3 = pair_errors(net, pin, ptg, mat, bc == 0, args.batch)
+        ec = pair_errors(net, pin[:, -1:], ptg[:, -1:], mat, bc == 0, args.batch)
+        del pin, ptg
         rep["validation"]["periodic" if bc == 0 else "dirichlet"] = {
             "pairs": int(len(e)), "median": float(np.median(e)), "p90": float(np.quantile(e, 0.9)),
-            "max": float(e.max()), "frac_le_1e-3": float(np.mean(e <= 1e-3))}
+            "max": float(e.max()), "frac_le_1e-3": float(np.mean(e <= 1e-3)),
+            "on_own_outputs": {"median": float(np.median(e2)),
+                               "p90": float(np.quantile(e2, 0.9)),
+                               "frac_le_1e-3": float(np.mean(e2 <= 1e-3))},
+            "along_own_chain": {"median": float(np.median(e3)),
+                                "p90": float(np.quantile(e3, 0.9)),
+                                "frac_le_1e-3": float(np.mean(e3 <= 1e-3)),
+                                "last_window_median": float(np.median(ec))}}
         # the identity map (no surrogate) for scale
         ident = rel_l2_U(data[:, :-1].reshape(-1, 5, args.side, args.side)[:512],
                          data[:, 1:].reshape(-1, 5, args.side, args.side)[:512],
