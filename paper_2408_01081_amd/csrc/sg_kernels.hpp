@@ -246,16 +246,18 @@ __global__ __launch_bounds__(256) void k_convt(const float* __restrict__ X,
 
   // staging: thread t handles the items t, t + 256, ... of the tile (and of
   // the weights); 256 is a multiple of 4, so its piece q of 8 channels is
-  // the same in every item.  All of a thread's loads of the input tile are
-  // issued before the first one is used, so their latencies overlap.
+  // the same in every item.  A chunk's loads (input tile, gains, weights)
+  // are all issued before the first is used, so their latencies overlap, and
+  // those of the next chunk are in flight during this chunk's products.
   constexpr int NTILE = TR * TW * 4, PER = (NTILE + 255) / 256;
   constexpr int NWT = WL ? 9 * CT * 4 : 1, PERW = (NWT + 255) / 256;
   const int q = threadIdx.x & 3;
-  for (int c0 = 0; c0 < Cin; c0 += 32) {
-    if (c0) __syncthreads();  // every wave is done with the previous chunk
-    // TR rows x TW columns x 4 pieces of 8 channels, hi (and lo)
-    float4 u0[PER], u1[PER];
-    bool valid[PER];
+  float4 u0[PER], u1[PER];
+  bool valid[PER];
+  float sc[8];
+  // (dword arrays: arrays of uint4 were placed in scratch memory)
+  uint32_t wh[WL ? PERW : 1][4], wl[WL ? PERW : 1][4];
+  auto issue = [&](int c0) __attribute__((always_inline)) {
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
       const int i = threadIdx.x + 256 * k;
@@ -275,12 +277,34 @@ __global__ __launch_bounds__(256) void k_convt(const float* __restrict__ X,
         u1[k] = *reinterpret_cast<const float4*>(X + xo + 4);
       }
     }
-    float sc[8];
     if (xscale) {
       const float* sp = xscale + (int64_t)b * Cin + c0 + 8 * q;
 #pragma unroll
       for (int j = 0; j < 8; ++j) sc[j] = sp[j];
     }
+    if (WL) {
+      // 9 taps x CT channels x 4 pieces of 8 input channels (from L2: every
+      // workgroup reads the same weights)
+#pragma unroll
+      for (int k = 0; k < PERW; ++k) {
+        const int i = threadIdx.x + 256 * k;
+        if (i < NWT) {
+          const int co = (i >> 2) % CT, t = (i >> 2) / CT;
+          const int64_t wo = ((int64_t)t * Cout + blockIdx.y * CT + co) * Cin + c0 + 8 * q;
+          const uint4 a = *reinterpret_cast<const uint4*>(Whi + wo);
+          wh[k][0] = a.x; wh[k][1] = a.y; wh[k][2] = a.z; wh[k][3] = a.w;
+          if (SPLIT == 3) {
+            const uint4 c = *reinterpret_cast<const uint4*>(Wlo + wo);
+            wl[k][0] = c.x; wl[k][1] = c.y; wl[k][2] = c.z; wl[k][3] = c.w;
+          }
+        }
+      }
+    }
+  };
+  issue(0);
+  for (int c0 = 0; c0 < Cin; c0 += 32) {
+    if (c0) __syncthreads();  // every wave is done with the previous chunk
+    // TR rows x TW columns x 4 pieces of 8 channels, hi (and lo)
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
       const int i = threadIdx.x + 256 * k;
@@ -313,21 +337,19 @@ __global__ __launch_bounds__(256) void k_convt(const float* __restrict__ X,
       }
     }
     if (WL) {
-      // 9 taps x CT channels x 4 pieces of 8 input channels (from L2: every
-      // workgroup reads the same weights)
 #pragma unroll
       for (int k = 0; k < PERW; ++k) {
         const int i = threadIdx.x + 256 * k;
         if (i < NWT) {
           const int co = (i >> 2) % CT, t = (i >> 2) / CT;
-          const int64_t wo = ((int64_t)t * Cout + blockIdx.y * CT + co) * Cin + c0 + 8 * q;
           const int d = (t * CT + co) * PS + 4 * q;
-          *reinterpret_cast<uint4*>(wtile + d) = *reinterpret_cast<const uint4*>(Whi + wo);
+          *reinterpret_cast<uint4*>(wtile + d) = (uint4){wh[k][0], wh[k][1], wh[k][2], wh[k][3]};
           if (SPLIT == 3)
-            *reinterpret_cast<uint4*>(wtile + WS + d) = *reinterpret_cast<const uint4*>(Wlo + wo);
+            *reinterpret_cast<uint4*>(wtile + WS + d) = (uint4){wl[k][0], wl[k][1], wl[k][2], wl[k][3]};
         }
       }
     }
+    if (c0 + 32 < Cin) issue(c0 + 32);
     __syncthreads();
 #pragma unroll
     for (int t = 0; t < 9; ++t) {
