@@ -324,7 +324,7 @@ struct Plan {
   size_t bytes = 0;
   // workspace offsets
   size_t o_param, o_grad, o_m, o_v, o_wfh, o_wfl, o_wbh, o_wbl, o_s, o_T, o_gam, o_dgam,
-      o_part, o_spart, o_xh, o_xl, o_loss, o_x0, o_z[NL], o_pool[3], o_up[3], o_g[NL], o_gpool[3], o_gup[3],
+      o_part, o_spart, o_loss, o_x0, o_z[NL], o_pool[3], o_up[3], o_g[NL], o_gpool[3], o_gup[3],
       o_gtmp[2], o_wpart;
   int64_t wpart_floats = 0;
 };
@@ -373,18 +373,6 @@ lbm_status make_plan(const sg_config* cfg, Plan* P) {
   P->o_gam = take((size_t)NL * B * 128 * 4);
   P->o_part = take(((size_t)B * P->H * P->W / RT + 1) * 8);
   P->o_spart = take((size_t)B * SB * 3 * 8);
-  {
-    // largest convolution input (elements), forward and data gradient
-    int64_t mx = 0;
-    for (int l = 0; l < NL; ++l) {
-      const int lv = kLayers[l].level;
-      const int c = kLayers[l].cin > kLayers[l].cout ? kLayers[l].cin : kLayers[l].cout;
-      const int64_t e = (int64_t)B * level_h(*P, lv) * level_w(*P, lv) * c;
-      mx = e > mx ? e : mx;
-    }
-    P->o_xh = take((size_t)mx * 2);
-    P->o_xl = take((size_t)mx * 2);
-  }
   P->o_loss = take(8);
   P->o_x0 = take(act(0, CP));
   for (int l = 0; l < NL; ++l) P->o_z[l] = take(act(kLayers[l].level, kLayers[l].cout));
@@ -431,7 +419,6 @@ struct sg_net {
   float* dgam;
   double* part;
   double* spart;  // per-sample statistics partials [B][SB][3]
-  unsigned short *xh, *xl;  // BF16 hi / lo parts of the current convolution's input
   double* loss;
   float* x0;
   Tensor z[NL], pool[3], up[3], g[NL], gpool[3], gup[3], gtmp[2];
@@ -452,12 +439,11 @@ inline unsigned grid1(int64_t n) { return (unsigned)((n + RT - 1) / RT); }
 template <int SPLIT, int NB, int PB, int KS>
 void launch_conv(sg_net* n, const Tensor& x, const float* xscale, const unsigned short* wh,
                  const unsigned short* wl, Tensor& z, int cin, int cout, int accumulate) {
-  (void)xscale;  // applied by the split pass
   const int64_t pixels = (int64_t)n->B * x.H * x.W;
   dim3 grid((unsigned)(pixels / (16 * PB * (4 / KS))), (unsigned)(cout / (16 * NB)));
   hipLaunchKernelGGL((k_conv<SPLIT, NB, PB, KS>), grid, dim3(256), 0, n->stream,
-                     (const unsigned short*)n->xh, (const unsigned short*)n->xl, wh, wl, z.p, x.H,
-                     x.W, cin, cout, n->circular, accumulate);
+                     (const float*)x.p, xscale, wh, wl, z.p, x.H, x.W, cin, cout, n->circular,
+                     accumulate);
 }
 
 // Tile shapes of the convolution, most work per wave first: (NB, PB, KS).
@@ -564,11 +550,8 @@ void conv(sg_net* n, const Tensor& x, const float* xscale, int l, Tensor& z, boo
   if (n->P.split == 3 ? conv_tiled<3>(n, x, xscale, wh, wl, z, cin, cout, accumulate)
                       : conv_tiled<1>(n, x, xscale, wh, wl, z, cin, cout, accumulate))
     return;
-  // the input's BF16 hi/lo parts (with its gain), once for all taps and
-  // output-channel blocks
-  const int64_t n4 = pixels * cin / 4;
-  hipLaunchKernelGGL(k_split_bf16, dim3(grid1(n4)), dim3(RT), 0, n->stream, x.p, xscale, n4,
-                     (int64_t)x.H * x.W * cin, cin, n->xh, n->xl);
+  // the direct kernel splits its input (with its gain) into BF16 hi/lo parts
+  // as it reads it
   const int k = conv_shape(pixels, cin, cout);
   if (n->P.split == 3)
     launch_conv_shape<3>(k, n, x, xscale, wh, wl, z, cin, cout, accumulate);
@@ -812,8 +795,6 @@ lbm_status sg_create(const sg_config* cfg, void* d_ws, size_t ws_bytes, void* hi
   for (int l = 0; l < NL; ++l) n->gam[l] = (float*)(w + P.o_gam) + (size_t)l * P.B * 128;
   n->part = (double*)(w + P.o_part);
   n->spart = (double*)(w + P.o_spart);
-  n->xh = (unsigned short*)(w + P.o_xh);
-  n->xl = (unsigned short*)(w + P.o_xl);
   n->loss = (double*)(w + P.o_loss);
   n->x0 = (float*)(w + P.o_x0);
   for (int l = 0; l < NL; ++l) {

@@ -40,6 +40,28 @@ __device__ inline bf16 as_bf16(unsigned short b) {
   return r;
 }
 
+// BF16 hi (and, SPLIT = 3, lo) parts of 8 activations times their gains,
+// rounded to nearest even (a zero activation gives zero parts)
+template <int SPLIT>
+__device__ __forceinline__ void split8(const float (&x)[8], const float (&s)[8], bool scaled,
+                                       bf16x8& hi, bf16x8& lo) {
+  uint32_t h[4], l[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const float a0 = scaled ? x[2 * j] * s[2 * j] : x[2 * j];
+    const float a1 = scaled ? x[2 * j + 1] * s[2 * j + 1] : x[2 * j + 1];
+    const unsigned short h0 = bf16_bits(a0), h1 = bf16_bits(a1);
+    h[j] = (uint32_t)h0 | ((uint32_t)h1 << 16);
+    if (SPLIT == 3) {
+      const unsigned short l0 = bf16_bits(a0 - bf16_value(h0));
+      const unsigned short l1 = bf16_bits(a1 - bf16_value(h1));
+      l[j] = (uint32_t)l0 | ((uint32_t)l1 << 16);
+    }
+  }
+  __builtin_memcpy(&hi, h, 16);
+  __builtin_memcpy(&lo, l, 16);
+}
+
 // ---------------------------------------------------------------------------
 // 3x3 convolution, implicit GEMM.  Z[b,y,x,o] = sum_{t,i} Wt[t][o][i] * s[b,i] * X[b,y+dy,x+dx,i]
 // Operand layouts of v_mfma_f32_16x16x32_bf16 (checked on gfx950 by an
@@ -52,43 +74,12 @@ __device__ inline bf16 as_bf16(unsigned short b) {
 // added in LDS in slice order, so the result does not depend on timing.  A
 // workgroup covers 16 * PB * 4/KS pixels.  Cin % 32 == 0.
 // Used for the forward pass (Wt = [9][Cout][Cin]) and, with the flipped and
-// transposed weights, for the data gradient.
+// transposed weights, for the data gradient.  The input is read in FP32 and
+// split into BF16 parts (split8) with its gain as it is read.
 // ---------------------------------------------------------------------------
-// Input split once per layer: Xh / Xl = BF16 hi / lo parts of X * s (s the
-// per-sample, per-channel gain, or 1), NHWC like X; 4 elements per thread.
-__global__ __launch_bounds__(256) void k_split_bf16(const float* __restrict__ X,
-                                                    const float* __restrict__ xscale,
-                                                    int64_t n4, int64_t HWC, int C,
-                                                    unsigned short* __restrict__ Xh,
-                                                    unsigned short* __restrict__ Xl) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= n4) return;
-  const int64_t e = 4 * i;
-  const float4 v = *reinterpret_cast<const float4*>(X + e);
-  float a[4] = {v.x, v.y, v.z, v.w};
-  if (xscale) {
-    const int64_t b = e / HWC;
-    const int c = (int)(e % C);
-    const float* sc = xscale + b * C + c;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) a[j] *= sc[j];
-  }
-  ushort4 h, l;
-  unsigned short hb[4], lb[4];
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    hb[j] = bf16_bits(a[j]);
-    lb[j] = bf16_bits(a[j] - bf16_value(hb[j]));
-  }
-  h.x = hb[0]; h.y = hb[1]; h.z = hb[2]; h.w = hb[3];
-  l.x = lb[0]; l.y = lb[1]; l.z = lb[2]; l.w = lb[3];
-  *reinterpret_cast<ushort4*>(Xh + e) = h;
-  *reinterpret_cast<ushort4*>(Xl + e) = l;
-}
-
 template <int SPLIT, int NB, int PB, int KS>
-__global__ __launch_bounds__(256) void k_conv(const unsigned short* __restrict__ Xh,
-                                              const unsigned short* __restrict__ Xl,
+__global__ __launch_bounds__(256) void k_conv(const float* __restrict__ X,
+                                              const float* __restrict__ xscale,
                                               const unsigned short* __restrict__ Whi,
                                               const unsigned short* __restrict__ Wlo,
                                               float* __restrict__ Z, int H, int W, int Cin,
@@ -117,6 +108,13 @@ __global__ __launch_bounds__(256) void k_conv(const unsigned short* __restrict__
     for (int nb = 0; nb < NB; ++nb) acc[pb][nb] = (f32x4){0.f, 0.f, 0.f, 0.f};
 
   for (int c0 = 32 * ks; c0 < Cin; c0 += 32 * KS) {
+    // the gains of this lane's 8 input channels in each pixel block's image
+    float sc[PB][8];
+#pragma unroll
+    for (int pb = 0; pb < PB; ++pb)
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        sc[pb][j] = xscale ? xscale[(int64_t)bb[pb] * Cin + c0 + 8 * kq + j] : 1.f;
 #pragma unroll
     for (int t = 0; t < 9; ++t) {
       const int dy = t / 3 - 1, dx = t % 3 - 1;
@@ -134,9 +132,13 @@ __global__ __launch_bounds__(256) void k_conv(const unsigned short* __restrict__
           xs = xs < 0 ? 0 : (xs >= W ? W - 1 : xs);
         }
         const int64_t xo = (((int64_t)bb[pb] * H + ys) * W + xs) * Cin + 8 * kq + c0;
-        const bf16x8 zero = {};
-        ahi[pb] = valid ? *reinterpret_cast<const bf16x8*>(Xh + xo) : zero;
-        if (SPLIT == 3) alo[pb] = valid ? *reinterpret_cast<const bf16x8*>(Xl + xo) : zero;
+        float4 u0 = {0.f, 0.f, 0.f, 0.f}, u1 = {0.f, 0.f, 0.f, 0.f};
+        if (valid) {
+          u0 = *reinterpret_cast<const float4*>(X + xo);
+          u1 = *reinterpret_cast<const float4*>(X + xo + 4);
+        }
+        const float a[8] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w};
+        split8<SPLIT>(a, sc[pb], xscale != nullptr, ahi[pb], alo[pb]);
       }
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
@@ -194,7 +196,7 @@ __global__ __launch_bounds__(256) void k_conv(const unsigned short* __restrict__
 // WT = W = 32 or 16; RW * WT = 64 or 256) x CT output channels; for every
 // 32-channel chunk of the input the neighbourhood of those pixels (one pixel
 // more on every side) is read from the FP32 activations, multiplied by the gain and
-// split into BF16 hi and lo parts exactly as k_split_bf16 does, and stored in
+// split into BF16 hi and lo parts exactly as split8 does, and stored in
 // LDS (20 dwords per pixel: 16 data + 4 padding, so the 16 lanes of an
 // A-fragment read hit distinct banks), where all 9 taps and all waves read it.  Wave w owns 16 PB pixels (w mod WPX) x
 // 16 NB output channels (w / WPX).  The products are accumulated in the same
