@@ -92,8 +92,8 @@ __device__ inline double wg_sum(double v, double* sh) {
 
 // Per-sample statistics in two passes: SB workgroups per sample sum |U|^2,
 // c_K and c_mu over their pixels (FP64), then one workgroup per sample adds
-// the SB partial sums in a fixed order and forms s_b and the Chebyshev values
-// T[b][m].
+// the SB partial sums in a fixed order and forms s_b, the Chebyshev values
+// T[b][m] and the FiLM gains of every layer.
 constexpr int SB = 64;  // workgroups per sample in the first pass
 
 __global__ __launch_bounds__(RT) void k_stats_partial(const float* __restrict__ in, int HW,
@@ -121,9 +121,18 @@ __global__ __launch_bounds__(RT) void k_stats_partial(const float* __restrict__ 
   }
 }
 
+// the FiLM gains of every layer, gamma[l][b][c] = sum_k a_l[c][k] T[b][k]
+struct GammaArgs {
+  const float* a[NL];
+  float* g[NL];
+  int cout[NL];
+};
+
 __global__ __launch_bounds__(RT) void k_stats(const double* __restrict__ part, int HW,
-                                              float* __restrict__ sv, float* __restrict__ T) {
+                                              float* __restrict__ sv, float* __restrict__ T,
+                                              GammaArgs ga) {
   __shared__ double sh[RT];
+  __shared__ float Ts[NBASIS];
   const int b = blockIdx.x;
   const double* q = part + (int64_t)b * SB * 3;
   const bool mine = (int)threadIdx.x < SB;
@@ -139,7 +148,19 @@ __global__ __launch_bounds__(RT) void k_stats(const double* __restrict__ part, i
     Tm[0] = 1.0;
     Tm[1] = t;
     for (int k = 2; k < NBASIS; ++k) Tm[k] = 2.0 * t * Tm[k - 1] - Tm[k - 2];
-    for (int k = 0; k < NBASIS; ++k) T[b * NBASIS + k] = (float)Tm[k];
+    for (int k = 0; k < NBASIS; ++k) {
+      T[b * NBASIS + k] = (float)Tm[k];
+      Ts[k] = (float)Tm[k];
+    }
+  }
+  __syncthreads();
+  for (int l = 0; l < NL; ++l) {
+    const int C = ga.cout[l];
+    for (int c = threadIdx.x; c < C; c += RT) {
+      float s = 0.f;
+      for (int k = 0; k < NBASIS; ++k) s = fmaf(ga.a[l][c * NBASIS + k], Ts[k], s);
+      ga.g[l][b * C + c] = s;
+    }
   }
 }
 
@@ -159,23 +180,6 @@ __global__ __launch_bounds__(RT) void k_pre(const float* __restrict__ in, int B,
   float* o = x0 + e * CP;
   for (int c = 0; c < 5; ++c) o[c] = U[c] * r;
   for (int c = 5; c < CP; ++c) o[c] = 0.f;
-}
-
-// gamma[l][b][c] for all layers at once
-struct GammaArgs {
-  const float* a[NL];
-  float* g[NL];
-  int cout[NL];
-};
-__global__ __launch_bounds__(RT) void k_gamma(GammaArgs ga, const float* __restrict__ T, int B) {
-  const int l = blockIdx.y;
-  const int C = ga.cout[l];
-  const int e = blockIdx.x * RT + threadIdx.x;
-  if (e >= B * C) return;
-  const int b = e / C, c = e - b * C;
-  float s = 0.f;
-  for (int k = 0; k < NBASIS; ++k) s = fmaf(ga.a[l][c * NBASIS + k], T[b * NBASIS + k], s);
-  ga.g[l][e] = s;
 }
 
 // out[b][5][H][W] physical = fields of U + s gamma z_out[0..4]
@@ -560,14 +564,14 @@ void conv(sg_net* n, const Tensor& x, const float* xscale, int l, Tensor& z, boo
 }
 
 void pool(sg_net* n, const Tensor& in, const float* scale, Tensor& out) {
-  const int64_t e = (int64_t)n->B * out.H * out.W * out.C;
+  const int64_t e = (int64_t)n->B * out.H * out.W * out.C / 4;  // 4 channels per thread
   hipLaunchKernelGGL(k_pool, dim3(grid1(e)), dim3(RT), 0, n->stream, in.p, scale, out.p, n->B,
                      out.H, out.W, out.C);
 }
 
 void upadd(sg_net* n, const Tensor& coarse, const float* sc, const Tensor& skip, const float* ss,
            Tensor& out) {
-  const int64_t e = (int64_t)n->B * out.H * out.W * out.C;
+  const int64_t e = (int64_t)n->B * out.H * out.W * out.C / 4;  // 4 channels per thread
   hipLaunchKernelGGL(k_upadd, dim3(grid1(e)), dim3(RT), 0, n->stream, coarse.p, sc, skip.p, ss,
                      out.p, n->B, out.H, out.W, out.C);
 }
@@ -591,18 +595,16 @@ lbm_status forward(sg_net* n, const float* in, int B, int circular) {
   if (!n->weights_ready) prep_weights(n);
   const int HW = P.H * P.W;
   hipLaunchKernelGGL(k_stats_partial, dim3(SB, B), dim3(RT), 0, n->stream, in, HW, n->spart);
-  hipLaunchKernelGGL(k_stats, dim3(B), dim3(RT), 0, n->stream, (const double*)n->spart, HW, n->s,
-                     n->T);
-  hipLaunchKernelGGL(k_pre, dim3(grid1((int64_t)B * HW)), dim3(RT), 0, n->stream, in, B, HW,
-                     n->s, n->x0);
   GammaArgs ga;
   for (int l = 0; l < NL; ++l) {
     ga.a[l] = n->param + P.aoff[l];
     ga.g[l] = n->gam[l];
     ga.cout[l] = kLayers[l].cout;
   }
-  hipLaunchKernelGGL(k_gamma, dim3(grid1((int64_t)B * 128), NL), dim3(RT), 0, n->stream, ga,
-                     (const float*)n->T, B);
+  hipLaunchKernelGGL(k_stats, dim3(B), dim3(RT), 0, n->stream, (const double*)n->spart, HW, n->s,
+                     n->T, ga);
+  hipLaunchKernelGGL(k_pre, dim3(grid1((int64_t)B * HW)), dim3(RT), 0, n->stream, in, B, HW,
+                     n->s, n->x0);
   Tensor x0{n->x0, P.H, P.W, CP};
   Tensor* z = n->z;
   float** gm = n->gam;
@@ -710,13 +712,13 @@ void conv_back(sg_net* n, int l, const Tensor& gy, const Tensor& xin, const floa
 }
 
 void up_back(sg_net* n, const Tensor& g, Tensor& out) {
-  const int64_t e = (int64_t)n->B * out.H * out.W * out.C;
+  const int64_t e = (int64_t)n->B * out.H * out.W * out.C / 4;  // 4 channels per thread
   hipLaunchKernelGGL(k_up_back, dim3(grid1(e)), dim3(RT), 0, n->stream, g.p, out.p, n->B, out.H,
                      out.W, out.C);
 }
 
 void pool_back(sg_net* n, const Tensor& g, const float* add, Tensor& out) {
-  const int64_t e = (int64_t)n->B * out.H * out.W * out.C;
+  const int64_t e = (int64_t)n->B * out.H * out.W * out.C / 4;  // 4 channels per thread
   hipLaunchKernelGGL(k_pool_back, dim3(grid1(e)), dim3(RT), 0, n->stream, g.p, add, out.p, n->B,
                      out.H, out.W, out.C);
 }

@@ -725,26 +725,47 @@ __global__ __launch_bounds__(256) void k_prep_weights(const float* __restrict__ 
 }
 
 // ---------------------------------------------------------------------------
-// pooling / up-sampling (NHWC, scale on load)
+// pooling / up-sampling (NHWC, scale on load); thread e handles the 4
+// channels 4 (e mod C/4) .. + 3 of one pixel (C % 4 == 0), each with the
+// operations written for one element
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ float4 ld4(const float* p) { return *reinterpret_cast<const float4*>(p); }
+__device__ __forceinline__ float4 scale4(const float* s, int64_t i) {
+  return s ? ld4(s + i) : make_float4(1.f, 1.f, 1.f, 1.f);
+}
+
+// pixel and channel of 4-channel item e of a [B][H][W][C] tensor
+__device__ __forceinline__ void item4(int64_t e, int H, int W, int C, int& b, int& y, int& x,
+                                      int& c) {
+  const int C4 = C >> 2;
+  int64_t r = e / C4;
+  c = 4 * (int)(e - r * C4);
+  x = (int)(r % W);
+  r /= W;
+  y = (int)(r % H);
+  b = (int)(r / H);
+}
+
 // out[b,Y,X,c] = 1/4 sum_{2x2} s[b,c] in[b,2Y+u,2X+v,c]
 __global__ __launch_bounds__(256) void k_pool(const float* __restrict__ in,
                                               const float* __restrict__ scale,
                                               float* __restrict__ out, int B, int Ho, int Wo,
                                               int C) {
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const int64_t n = (int64_t)B * Ho * Wo * C;
-  if (e >= n) return;
-  const int c = (int)(e % C);
-  int64_t r = e / C;
-  const int X = (int)(r % Wo);
-  r /= Wo;
-  const int Y = (int)(r % Ho);
-  const int b = (int)(r / Ho);
+  if (e >= (int64_t)B * Ho * Wo * C / 4) return;
+  int b, Y, X, c;
+  item4(e, Ho, Wo, C, b, Y, X, c);
   const int Wi = 2 * Wo;
   const float* p = in + (((int64_t)b * 2 * Ho + 2 * Y) * Wi + 2 * X) * C + c;
-  const float s = scale ? scale[(int64_t)b * C + c] : 1.f;
-  out[e] = 0.25f * s * ((p[0] + p[C]) + (p[(int64_t)Wi * C] + p[(int64_t)Wi * C + C]));
+  const float4 s = scale4(scale, (int64_t)b * C + c);
+  const float4 p0 = ld4(p), p1 = ld4(p + C), p2 = ld4(p + (int64_t)Wi * C),
+               p3 = ld4(p + (int64_t)Wi * C + C);
+  float4 o;
+  o.x = 0.25f * s.x * ((p0.x + p1.x) + (p2.x + p3.x));
+  o.y = 0.25f * s.y * ((p0.y + p1.y) + (p2.y + p3.y));
+  o.z = 0.25f * s.z * ((p0.z + p1.z) + (p2.z + p3.z));
+  o.w = 0.25f * s.w * ((p0.w + p1.w) + (p2.w + p3.w));
+  *reinterpret_cast<float4*>(out + 4 * e) = o;
 }
 
 // out[b,y,x,c] = sc[b,c] coarse[b,y/2,x/2,c] + ss[b,c] skip[b,y,x,c]
@@ -755,17 +776,18 @@ __global__ __launch_bounds__(256) void k_upadd(const float* __restrict__ coarse,
                                                float* __restrict__ out, int B, int H, int W,
                                                int C) {
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const int64_t n = (int64_t)B * H * W * C;
-  if (e >= n) return;
-  const int c = (int)(e % C);
-  int64_t r = e / C;
-  const int x = (int)(r % W);
-  r /= W;
-  const int y = (int)(r % H);
-  const int b = (int)(r / H);
-  const float cv = coarse[(((int64_t)b * (H / 2) + y / 2) * (W / 2) + x / 2) * C + c];
-  const float a = (sc ? sc[(int64_t)b * C + c] : 1.f) * cv;
-  out[e] = a + (ss ? ss[(int64_t)b * C + c] : 1.f) * skip[e];
+  if (e >= (int64_t)B * H * W * C / 4) return;
+  int b, y, x, c;
+  item4(e, H, W, C, b, y, x, c);
+  const float4 cv = ld4(coarse + (((int64_t)b * (H / 2) + y / 2) * (W / 2) + x / 2) * C + c);
+  const float4 a = scale4(sc, (int64_t)b * C + c), t = scale4(ss, (int64_t)b * C + c);
+  const float4 k = ld4(skip + 4 * e);
+  float4 o;
+  o.x = a.x * cv.x + t.x * k.x;
+  o.y = a.y * cv.y + t.y * k.y;
+  o.z = a.z * cv.z + t.z * k.z;
+  o.w = a.w * cv.w + t.w * k.w;
+  *reinterpret_cast<float4*>(out + 4 * e) = o;
 }
 
 // backward of pooling, plus an optional addend:
@@ -775,16 +797,19 @@ __global__ __launch_bounds__(256) void k_pool_back(const float* __restrict__ g,
                                                    float* __restrict__ out, int B, int H, int W,
                                                    int C) {
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const int64_t n = (int64_t)B * H * W * C;
-  if (e >= n) return;
-  const int c = (int)(e % C);
-  int64_t r = e / C;
-  const int x = (int)(r % W);
-  r /= W;
-  const int y = (int)(r % H);
-  const int b = (int)(r / H);
-  const float v = 0.25f * g[(((int64_t)b * (H / 2) + y / 2) * (W / 2) + x / 2) * C + c];
-  out[e] = add ? v + add[e] : v;
+  if (e >= (int64_t)B * H * W * C / 4) return;
+  int b, y, x, c;
+  item4(e, H, W, C, b, y, x, c);
+  const float4 gv = ld4(g + (((int64_t)b * (H / 2) + y / 2) * (W / 2) + x / 2) * C + c);
+  float4 o = make_float4(0.25f * gv.x, 0.25f * gv.y, 0.25f * gv.z, 0.25f * gv.w);
+  if (add) {
+    const float4 d = ld4(add + 4 * e);
+    o.x += d.x;
+    o.y += d.y;
+    o.z += d.z;
+    o.w += d.w;
+  }
+  *reinterpret_cast<float4*>(out + 4 * e) = o;
 }
 
 // backward of nearest up-sampling: out[b,Y,X,c] = sum_{2x2} g[b,2Y+u,2X+v,c]
@@ -792,17 +817,19 @@ __global__ __launch_bounds__(256) void k_up_back(const float* __restrict__ g,
                                                  float* __restrict__ out, int B, int Ho, int Wo,
                                                  int C) {
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const int64_t n = (int64_t)B * Ho * Wo * C;
-  if (e >= n) return;
-  const int c = (int)(e % C);
-  int64_t r = e / C;
-  const int X = (int)(r % Wo);
-  r /= Wo;
-  const int Y = (int)(r % Ho);
-  const int b = (int)(r / Ho);
+  if (e >= (int64_t)B * Ho * Wo * C / 4) return;
+  int b, Y, X, c;
+  item4(e, Ho, Wo, C, b, Y, X, c);
   const int Wi = 2 * Wo;
   const float* p = g + (((int64_t)b * 2 * Ho + 2 * Y) * Wi + 2 * X) * C + c;
-  out[e] = (p[0] + p[C]) + (p[(int64_t)Wi * C] + p[(int64_t)Wi * C + C]);
+  const float4 p0 = ld4(p), p1 = ld4(p + C), p2 = ld4(p + (int64_t)Wi * C),
+               p3 = ld4(p + (int64_t)Wi * C + C);
+  float4 o;
+  o.x = (p0.x + p1.x) + (p2.x + p3.x);
+  o.y = (p0.y + p1.y) + (p2.y + p3.y);
+  o.z = (p0.z + p1.z) + (p2.z + p3.z);
+  o.w = (p0.w + p1.w) + (p2.w + p3.w);
+  *reinterpret_cast<float4*>(out + 4 * e) = o;
 }
 
 }  // namespace sgk
