@@ -92,8 +92,8 @@ __device__ inline double wg_sum(double v, double* sh) {
 
 // Per-sample statistics in two passes: SB workgroups per sample sum |U|^2,
 // c_K and c_mu over their pixels (FP64), then one workgroup per sample adds
-// the SB partial sums in a fixed order and forms s_b, the Chebyshev values
-// T[b][m] and the FiLM gains of every layer.
+// the SB partial sums in a fixed order and forms s_b and the Chebyshev values
+// T[b][m].
 constexpr int SB = 64;  // workgroups per sample in the first pass
 
 __global__ __launch_bounds__(RT) void k_stats_partial(const float* __restrict__ in, int HW,
@@ -126,13 +126,12 @@ struct GammaArgs {
   const float* a[NL];
   float* g[NL];
   int cout[NL];
+  int total;  // sum of cout
 };
 
 __global__ __launch_bounds__(RT) void k_stats(const double* __restrict__ part, int HW,
-                                              float* __restrict__ sv, float* __restrict__ T,
-                                              GammaArgs ga) {
+                                              float* __restrict__ sv, float* __restrict__ T) {
   __shared__ double sh[RT];
-  __shared__ float Ts[NBASIS];
   const int b = blockIdx.x;
   const double* q = part + (int64_t)b * SB * 3;
   const bool mine = (int)threadIdx.x < SB;
@@ -148,27 +147,25 @@ __global__ __launch_bounds__(RT) void k_stats(const double* __restrict__ part, i
     Tm[0] = 1.0;
     Tm[1] = t;
     for (int k = 2; k < NBASIS; ++k) Tm[k] = 2.0 * t * Tm[k - 1] - Tm[k - 2];
-    for (int k = 0; k < NBASIS; ++k) {
-      T[b * NBASIS + k] = (float)Tm[k];
-      Ts[k] = (float)Tm[k];
-    }
-  }
-  __syncthreads();
-  for (int l = 0; l < NL; ++l) {
-    const int C = ga.cout[l];
-    for (int c = threadIdx.x; c < C; c += RT) {
-      float s = 0.f;
-      for (int k = 0; k < NBASIS; ++k) s = fmaf(ga.a[l][c * NBASIS + k], Ts[k], s);
-      ga.g[l][b * C + c] = s;
-    }
+    for (int k = 0; k < NBASIS; ++k) T[b * NBASIS + k] = (float)Tm[k];
   }
 }
 
-// x0[b][p][c] = U_c / s_b for c < 5, 0 otherwise
+// x0[b][p][c] = U_c / s_b for c < 5, 0 otherwise; threads e < B * total
+// also form the FiLM gain of one (sample, layer, channel)
 __global__ __launch_bounds__(RT) void k_pre(const float* __restrict__ in, int B, int HW,
                                             const float* __restrict__ sv,
-                                            float* __restrict__ x0) {
+                                            float* __restrict__ x0, GammaArgs ga,
+                                            const float* __restrict__ T) {
   const int64_t e = (int64_t)blockIdx.x * RT + threadIdx.x;
+  if (e < (int64_t)B * ga.total) {
+    const int b = (int)(e / ga.total);
+    int c = (int)(e - (int64_t)b * ga.total), l = 0;
+    while (c >= ga.cout[l]) c -= ga.cout[l++];
+    float s = 0.f;
+    for (int k = 0; k < NBASIS; ++k) s = fmaf(ga.a[l][c * NBASIS + k], T[b * NBASIS + k], s);
+    ga.g[l][b * ga.cout[l] + c] = s;
+  }
   if (e >= (int64_t)B * HW) return;
   const int b = (int)(e / HW);
   const int64_t p = e - (int64_t)b * HW;
@@ -504,8 +501,8 @@ void launch_convt(sg_net* n, const Tensor& x, const float* xscale, const unsigne
 // The LDS-tiled kernel where the row is a multiple of 64 pixels or 32 or 16
 // pixels long and it gives at least 256 workgroups: 64 output channels per
 // workgroup (2 x 2 waves of 32 x 32) when that still gives 512 workgroups,
-// else 32 (4 waves of 16 pixels x 32 channels, weights staged in LDS too).
-// Returns false where it does not apply.
+// else 32 (4 waves of 16 pixels x 32 channels, weights staged in LDS too),
+// or 16 where 32 gives fewer than 256 workgroups.
 template <int SPLIT, int WT>
 void conv_tiled_w(sg_net* n, const Tensor& x, const float* xscale, const unsigned short* wh,
                   const unsigned short* wl, Tensor& z, int cin, int cout, int accumulate) {
@@ -519,6 +516,11 @@ void conv_tiled_w(sg_net* n, const Tensor& x, const float* xscale, const unsigne
   }
   if (cout % 64 == 0 && tiles * (cout / 64) >= 512)
     launch_convt<SPLIT, 2, 2, false, WT>(n, x, xscale, wh, wl, z, cin, cout, accumulate);
+  else if (tiles * (cout / 32) < 256 && n->conv_mode == 2)
+    launch_convt<SPLIT, 1, 1, false, WT>(n, x, xscale, wh, wl, z, cin, cout, accumulate);
+  else if (tiles * (cout / 32) < 256)
+    // 16 output channels per workgroup, for enough workgroups
+    launch_convt<SPLIT, 1, 1, true, WT>(n, x, xscale, wh, wl, z, cin, cout, accumulate);
   else if (n->conv_mode == 2)
     launch_convt<SPLIT, 1, 2, false, WT>(n, x, xscale, wh, wl, z, cin, cout, accumulate);
   else
@@ -529,9 +531,9 @@ template <int SPLIT>
 bool conv_tiled(sg_net* n, const Tensor& x, const float* xscale, const unsigned short* wh,
                 const unsigned short* wl, Tensor& z, int cin, int cout, int accumulate) {
   if (n->conv_mode == 1 || cin % 32 || cout % 32 || ((int64_t)x.H * x.W) % 64) return false;
-  // too few workgroups to fill the chip: the direct kernel splits the
-  // reduction over waves instead
-  if ((int64_t)n->B * x.H * x.W / 64 * (cout / 32) < 256) return false;
+  // too few workgroups to fill the chip even with 16 output channels per
+  // workgroup: the direct kernel splits the reduction over waves instead
+  if ((int64_t)n->B * x.H * x.W / 64 * (cout / 16) < 256) return false;
   if (x.W % 64 == 0)
     conv_tiled_w<SPLIT, 64>(n, x, xscale, wh, wl, z, cin, cout, accumulate);
   else if (x.W == 32)
@@ -595,16 +597,19 @@ lbm_status forward(sg_net* n, const float* in, int B, int circular) {
   if (!n->weights_ready) prep_weights(n);
   const int HW = P.H * P.W;
   hipLaunchKernelGGL(k_stats_partial, dim3(SB, B), dim3(RT), 0, n->stream, in, HW, n->spart);
+  hipLaunchKernelGGL(k_stats, dim3(B), dim3(RT), 0, n->stream, (const double*)n->spart, HW, n->s,
+                     n->T);
   GammaArgs ga;
+  ga.total = 0;
   for (int l = 0; l < NL; ++l) {
     ga.a[l] = n->param + P.aoff[l];
     ga.g[l] = n->gam[l];
     ga.cout[l] = kLayers[l].cout;
+    ga.total += kLayers[l].cout;
   }
-  hipLaunchKernelGGL(k_stats, dim3(B), dim3(RT), 0, n->stream, (const double*)n->spart, HW, n->s,
-                     n->T, ga);
-  hipLaunchKernelGGL(k_pre, dim3(grid1((int64_t)B * HW)), dim3(RT), 0, n->stream, in, B, HW,
-                     n->s, n->x0);
+  const int64_t npre = (int64_t)B * (HW > ga.total ? HW : ga.total);
+  hipLaunchKernelGGL(k_pre, dim3(grid1(npre)), dim3(RT), 0, n->stream, in, B, HW, n->s, n->x0, ga,
+                     (const float*)n->T);
   Tensor x0{n->x0, P.H, P.W, CP};
   Tensor* z = n->z;
   float** gm = n->gam;
