@@ -507,11 +507,16 @@ template <int SPLIT, int WT>
 void conv_tiled_w(sg_net* n, const Tensor& x, const float* xscale, const unsigned short* wh,
                   const unsigned short* wl, Tensor& z, int cin, int cout, int accumulate) {
   const int64_t tiles = (int64_t)n->B * x.H * x.W / 64;
-  // blocks of 4 rows x 64 pixels (one wave per row, 32 output channels,
-  // weights in LDS) where they still give 256 workgroups: the weights and
-  // the halo rows are staged once for 4x as many pixels
+  // blocks of 4 rows x 64 pixels (one wave per row, 32 output channels)
+  // where they still give 256 workgroups: the halo rows (and the weights)
+  // are staged once for 4x as many pixels
   if (WT == 64 && n->conv_mode != 2 && x.H % 4 == 0 && tiles / 4 * (cout / 32) >= 256) {
-    launch_convt<SPLIT, 4, 2, true, 64, 4>(n, x, xscale, wh, wl, z, cin, cout, accumulate);
+    // weights read from L2 rather than staged, so that two workgroups share
+    // a CU, where the grid has more than one per CU
+    if (tiles / 4 * (cout / 32) >= 512)
+      launch_convt<SPLIT, 4, 2, false, 64, 4>(n, x, xscale, wh, wl, z, cin, cout, accumulate);
+    else
+      launch_convt<SPLIT, 4, 2, true, 64, 4>(n, x, xscale, wh, wl, z, cin, cout, accumulate);
     return;
   }
   if (cout % 64 == 0 && tiles * (cout / 64) >= 512)
