@@ -244,7 +244,7 @@ def test_full_size_dirichlet_2048x1024_bench_configuration_all_nodes():
     # the benchmark's Dirichlet lattice in the benchmark's launch
     # configuration (autotuner, then the stepping re-rank of bench.py) with
     # its rank-30 time-dependent walls: 1000 steps, every node against the
-    # full-grid FP64 C oracle at the spec bar
+    # full-grid FP64 C oracle at rel-L2 <= 1e-5
     torch = _torch()
     import bench
     prob = synth.plane_wave_problem(2048, 1024, synth.DIRICHLET, seed=2, dx=1.0 / 1024)

@@ -5,7 +5,7 @@ against the library's own lattice replay of the same window.
 Tolerances: the taps come from 16 FP32 lattice steps on unit deltas, so they
 carry FP32 rounding (about 1e-7 of the largest tap per operation, a few
 times that after 16 steps): 2e-6 of the largest tap.  Applied to fields,
-the FP32 products and sums add about 1e-7 relative: the spec bar
+the FP32 products and sums add about 1e-7 relative: the parity bar
 rel-L2 <= 1e-5 against the FP64 oracle holds with margin."""
 import numpy as np
 import pytest
