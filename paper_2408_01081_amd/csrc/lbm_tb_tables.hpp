@@ -30,7 +30,7 @@ constexpr TBVariant kTBVariants[] = {
     {7, 0, 0, 1},  {7, -2, 0, 1}, {6, 0, 0, 1},  {5, 0, 0, 1},  {7, 16, 0, 1}, {7, 24, 0, 1},
     {7, 20, 0, 2}, {7, 30, 0, 2}, {6, 8, 0, 1},  {6, 12, 0, 1}, {6, 20, 0, 2}, {6, 30, 0, 2},
     {8, 20, 0, 2}, {8, 30, 0, 2}, {8, 24, 0, 1}, {8, 32, 0, 1}, {8, 0, 0, 2},  {8, -2, 0, 2},
-    {8, 0, 0, 1},  {7, 0, 0, 2},  {4, 0, 0, 1},  {3, 0, 0, 1}};
+    {8, 0, 0, 1},  {7, 0, 0, 2},  {4, 0, 0, 1},  {3, 0, 0, 1},  {4, 375, 0, 2}, {5, 375, 0, 2}};
 constexpr int kNumTBVariants = (int)(sizeof(kTBVariants) / sizeof(kTBVariants[0]));
 // the load-free tables are filled in two halves per boundary type
 constexpr int kTBSplit = 24;
