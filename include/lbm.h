@@ -293,7 +293,8 @@ lbm_status lbm_autotune(lbm_ctx* ctx, int32_t reps, int32_t use_cache, int32_t* 
  * identical to T single steps.  Variants (h_steps = T in 2..8) differ in rows
  * per segment, store type and rows prefetched ahead (h_prefetch); h_seg_rows
  * 0 means the segment length is chosen at launch so that one wave per
- * resident slot covers the grid, -k that k waves per slot do.  index -1 disables blocking; lbm_autotune
+ * resident slot covers the grid, -k that k waves per slot do, -100 that one
+ * wave per SIMD (4 per CU) does whatever the occupancy.  index -1 disables blocking; lbm_autotune
  * selects a variant when it is faster per step than the best single-step
  * configuration.  With a variant of T steps enabled, lbm_step(n) runs the
  * steps in chunks of floor(420 / T) T steps, T per launch; the r = n mod T

@@ -855,8 +855,9 @@ WallSeq walls_from(const lbm_ctx* c, int s, bool with_walls) {
 }
 
 // Rows per segment of blocked variant k: its seg_rows, or for seg_rows <= 0 as
-// many as give one wave per resident slot (times -seg_rows) across the grid,
-// rounded up to the ring length (*slots caches the device's resident waves).
+// many as give one wave per resident slot (times -seg_rows; for TB_SEG_SIMD
+// one per SIMD whatever the occupancy) across the grid, rounded up to the
+// ring length (*slots caches the device's resident waves).
 int seg_rows_of(lbm_ctx* c, int steps, int seg_rows, int pf, TBFn fn, int* slots) {
   if (seg_rows > 0) return seg_rows;
   if (*slots == 0) {
@@ -870,12 +871,12 @@ int seg_rows_of(lbm_ctx* c, int steps, int seg_rows, int pf, TBFn fn, int* slots
       per_cu = 2;
       cus = 256;
     }
-    *slots = per_cu * 4 * cus;
+    *slots = (seg_rows == TB_SEG_SIMD ? 1 : per_cu) * 4 * cus;
   }
   const int ring = 3 + pf;
   const int valid = TB_LANES - 2 * steps;
   const int nstrips = (c->g.nx + valid - 1) / valid;
-  const int rounds = seg_rows < 0 ? -seg_rows : 1;
+  const int rounds = seg_rows < 0 && seg_rows != TB_SEG_SIMD ? -seg_rows : 1;
   int nseg = *slots * rounds / nstrips;
   if (nseg < 1) nseg = 1;
   int rows = (c->g.ny + nseg - 1) / nseg;
@@ -957,7 +958,7 @@ bool split_plan(lbm_ctx* c, int index, SplitPlan& sp) {
   const int rows = g.ny - 2 * SPLIT_ROWS;
   int seg = k.seg_rows;
   if (seg <= 0) {
-    const int rounds = seg < 0 ? -seg : 1;
+    const int rounds = seg < 0 && seg != TB_SEG_SIMD ? -seg : 1;
     int nseg = (split_slots(c, sp.kernel) * rounds - nband) / (hi - lo);
     if (nseg < 1) nseg = 1;
     const int ring = 3 + k.pf;

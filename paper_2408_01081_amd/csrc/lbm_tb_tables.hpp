@@ -14,11 +14,13 @@ namespace lbmk {
 typedef void (*TBFn)(const float*, float*, Grid, TBConst, WallSeq, TBExtra);
 
 // T steps per launch, output rows per segment (0: as many as give one wave per
-// resident slot across the grid, -k: k waves per slot), nontemporal stores,
-// level-0 rows prefetched ahead.
+// resident slot across the grid, -k: k waves per slot, TB_SEG_SIMD: one wave
+// per SIMD whatever the occupancy), nontemporal stores, level-0 rows
+// prefetched ahead.
 struct TBVariant {
   int steps, seg_rows, nt, pf;
 };
+constexpr int TB_SEG_SIMD = -100;
 
 // Load-free variants; the index is the public variant number
 // (lbm_tblock_config_info), so entries are only ever appended.
@@ -30,7 +32,8 @@ constexpr TBVariant kTBVariants[] = {
     {7, 0, 0, 1},  {7, -2, 0, 1}, {6, 0, 0, 1},  {5, 0, 0, 1},  {7, 16, 0, 1}, {7, 24, 0, 1},
     {7, 20, 0, 2}, {7, 30, 0, 2}, {6, 8, 0, 1},  {6, 12, 0, 1}, {6, 20, 0, 2}, {6, 30, 0, 2},
     {8, 20, 0, 2}, {8, 30, 0, 2}, {8, 24, 0, 1}, {8, 32, 0, 1}, {8, 0, 0, 2},  {8, -2, 0, 2},
-    {8, 0, 0, 1},  {7, 0, 0, 2},  {4, 0, 0, 1},  {3, 0, 0, 1},  {4, 375, 0, 2}, {5, 375, 0, 2}};
+    {8, 0, 0, 1},  {7, 0, 0, 2},  {4, 0, 0, 1},  {3, 0, 0, 1},  {4, 375, 0, 2}, {5, 375, 0, 2},
+    {4, TB_SEG_SIMD, 0, 3}, {5, TB_SEG_SIMD, 0, 3}, {3, TB_SEG_SIMD, 0, 3}, {2, TB_SEG_SIMD, 0, 3}};
 constexpr int kNumTBVariants = (int)(sizeof(kTBVariants) / sizeof(kTBVariants[0]));
 // the load-free tables are filled in two halves per boundary type
 constexpr int kTBSplit = 24;
