@@ -106,6 +106,9 @@ def main():
     forced2 = [int(v) for v in args.tblock_configs.split(",")] if args.tblock_configs else None
     for li, lat in enumerate(lats):
         if forced:
+            # the autotuner's choices for the launches that take the steps after
+            # the last full one (it times every variant), then the forced ones
+            lat.autotune(reps=3, use_cache=True)
             lat.step_config = forced[li]
             lat.tblock_config = forced2[li] if forced2 else -1
         else:

@@ -278,7 +278,8 @@ lbm_status lbm_set_step_config(lbm_ctx* ctx, int32_t index);
  * With use_cache != 0 a previous result for the same (nx, ny, bc) in this
  * process, or in the file named by the environment variable
  * LBM_AUTOTUNE_CACHE, is reused without timing (*h_ms = -1 then).  New
- * results are appended to that file.  *h_ms = best time per step.
+ * results (the selected variants, and those for the last steps of a run) are
+ * appended to that file.  *h_ms = best time per step.
  * Synchronises. */
 lbm_status lbm_autotune(lbm_ctx* ctx, int32_t reps, int32_t use_cache, int32_t* h_index,
                         double* h_ms);
@@ -336,6 +337,13 @@ lbm_status lbm_set_tblock_split(lbm_ctx* ctx, int32_t mode);
 /* 1 if launches of blocked variant `index` run split on this context as
  * configured now, 0 if not, -1 for a NULL context or a bad index. */
 int32_t lbm_tblock_split_active(lbm_ctx* ctx, int32_t index);
+/* The blocked variant lbm_step launches for the last r steps of a run (r = 2
+ * .. 8, fewer than the selected variant's T) after its full launches: the
+ * fastest r-step variant lbm_autotune timed (kept in its cache file as
+ * well), else the r-step variant nearest to the selected one's launch shape;
+ * *h_index = -1 when no variant is selected or r is outside 2 .. 8.
+ * LBM_E_ARG for a NULL argument. */
+lbm_status lbm_get_tblock_remainder(const lbm_ctx* ctx, int32_t r, int32_t* h_index);
 /* Average duration (ms) of one launch of blocked variant `index` (T steps;
  * state-preserving, synchronises). */
 lbm_status lbm_time_tblock_config(lbm_ctx* ctx, int32_t index, int32_t reps, double* h_ms);

@@ -1258,8 +1258,9 @@ int find_config(int vec, int threads, int nt, int xmode) {
 }
 
 // Cache file (path in LBM_AUTOTUNE_CACHE): one line per tuned shape,
-// "nx ny bc vec threads nt xmode tb ms" (tb = blocked variant or -1), for the
-// default split mode only.
+// "nx ny bc vec threads nt xmode tb ms r2 .. r8" (tb = blocked variant or -1,
+// r = the variant for the last r steps of a run or -1; lines without the r
+// fields are read with none), for the default split mode only.
 // Caller holds g_tune_mu.
 void load_tune_file() {
   if (g_tune_file_loaded) return;
@@ -1268,13 +1269,23 @@ void load_tune_file() {
   if (!path || !*path) return;
   FILE* f = fopen(path, "r");
   if (!f) return;
-  int nx, ny, bc, vec, th, nt, xm, s2;
-  double ms;
-  while (fscanf(f, "%d %d %d %d %d %d %d %d %lf", &nx, &ny, &bc, &vec, &th, &nt, &xm, &s2,
-                &ms) == 9) {
+  char line[512];
+  while (fgets(line, sizeof line, f)) {
+    int nx, ny, bc, vec, th, nt, xm, s2, rem[9];
+    double ms;
+    for (int r = 0; r < 9; ++r) rem[r] = -1;
+    const int n = sscanf(line, "%d %d %d %d %d %d %d %d %lf %d %d %d %d %d %d %d", &nx, &ny,
+                         &bc, &vec, &th, &nt, &xm, &s2, &ms, &rem[2], &rem[3], &rem[4], &rem[5],
+                         &rem[6], &rem[7], &rem[8]);
+    if (n != 9 && n != 16) continue;
+    if (n == 9)
+      for (int r = 2; r < 9; ++r) rem[r] = -1;
+    for (int r = 2; r < 9; ++r)
+      if (rem[r] < -1 || rem[r] >= kNumTBVariants || (rem[r] >= 0 && kTBVariants[rem[r]].steps != r))
+        rem[r] = -1;
     const int i = find_config(vec, th, nt, xm);
     if (i >= 0 && step_config_valid(i, nx) && s2 >= -1 && s2 < kNumTBVariants)
-      g_tune_cache[TuneKey{nx, ny, bc, -1}] = tune_val(i, s2, nullptr);
+      g_tune_cache[TuneKey{nx, ny, bc, -1}] = tune_val(i, s2, s2 >= 0 ? rem : nullptr);
   }
   fclose(f);
 }
@@ -1285,8 +1296,10 @@ void append_tune_file(const TuneKey& k, const TuneVal& v, double ms) {
   FILE* f = fopen(path, "a");
   if (!f) return;
   const StepConfig& c = kStepConfigs[v.cfg];
-  fprintf(f, "%d %d %d %d %d %d %d %d %.6f\n", k.nx, k.ny, k.bc, c.vec, c.threads, c.nt,
-          c.xmode, v.cfg2, ms);
+  fprintf(f, "%d %d %d %d %d %d %d %d %.6f", k.nx, k.ny, k.bc, c.vec, c.threads, c.nt, c.xmode,
+          v.cfg2, ms);
+  for (int r = 2; r < 9; ++r) fprintf(f, " %d", v.rem[r]);
+  fprintf(f, "\n");
   fclose(f);
 }
 
@@ -1457,6 +1470,12 @@ lbm_status lbm_set_tblock_config(lbm_ctx* c, int32_t index) {
   if (index >= 0 && !tblock_fits(c->g))
     return fail(LBM_E_ARG, "grid too wide for the blocked kernel (row offsets exceed 2^31 B)");
   c->tb_cfg = index;
+  return LBM_OK;
+}
+
+lbm_status lbm_get_tblock_remainder(const lbm_ctx* c, int32_t r, int32_t* h_index) {
+  if (!c || !h_index) return fail(LBM_E_ARG, "null argument");
+  *h_index = c->tb_cfg >= 0 ? remainder_variant(c, r) : -1;
   return LBM_OK;
 }
 

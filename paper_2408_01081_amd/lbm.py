@@ -266,6 +266,13 @@ class Lattice:
         """Whether launches of blocked variant `index` run split now."""
         return int(self.L.lbm_tblock_split_active(self.ctx, int(index))) == 1
 
+    def tblock_remainder(self, r):
+        """The blocked variant `step` launches for the last r steps of a run
+        (-1: none)."""
+        i = ctypes.c_int32()
+        check(self.L.lbm_get_tblock_remainder(self.ctx, int(r), ctypes.byref(i)))
+        return i.value
+
     @property
     def steps_per_launch(self):
         """Time steps per launch lbm_step uses for this lattice as configured."""

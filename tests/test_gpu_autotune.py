@@ -63,6 +63,50 @@ def test_autotune_keeps_state_and_picks_valid_config():
     assert idx2 == idx and ms2 < 0
 
 
+_TUNE_SCRIPT = r"""
+import json, sys
+import torch
+sys.path.insert(0, sys.argv[1])
+import synth
+from paper_2408_01081_amd.lbm import Lattice
+prob = synth.plane_wave_problem(2048, 512, synth.PERIODIC, seed=3, kmax=4)
+v0, sb0 = (torch.from_numpy(a).cuda() for a in prob.initial_fields())
+lat = Lattice(prob.nx, prob.ny, prob.dx, prob.dt, prob.lam, prob.mu, prob.rho, prob.bc)
+lat.init(v0, sb0)
+idx, ms = lat.autotune(reps=2, use_cache=True)
+print(json.dumps({"ms": ms, "step": lat.step_config, "tb": lat.tblock_config,
+                  "T": lat.steps_per_launch,
+                  "rem": [lat.tblock_remainder(r) for r in range(2, 9)]}))
+"""
+
+
+@gpu
+def test_autotune_cache_file_keeps_every_choice(tmp_path):
+    # the choices, including the variants for the last steps of a run, go
+    # to the file named by LBM_AUTOTUNE_CACHE: a fresh process that reads it
+    # (the file is read once per process) launches the same kernels
+    _torch()
+    import json
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ, LBM_AUTOTUNE_CACHE=str(tmp_path / "tune.txt"))
+    outs = []
+    for _ in range(2):
+        r = subprocess.run([sys.executable, "-c", _TUNE_SCRIPT, root], env=env,
+                           capture_output=True, text=True, timeout=180)
+        assert r.returncode == 0, r.stderr[-2000:]
+        outs.append(json.loads(r.stdout.strip().splitlines()[-1]))
+    first, second = outs
+    assert first["ms"] > 0 and second["ms"] == -1      # timed, then read from the file
+    assert (second["step"], second["tb"]) == (first["step"], first["tb"])
+    assert first["tb"] >= 0                             # blocking wins on this grid
+    assert second["rem"] == first["rem"]
+    for r in range(2, first["T"]):
+        assert first["rem"][r - 2] >= 0, (r, first["rem"])
+
+
 @gpu
 def test_copy_kernel():
     torch = _torch()
