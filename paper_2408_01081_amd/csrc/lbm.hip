@@ -1278,8 +1278,6 @@ void load_tune_file() {
                          &bc, &vec, &th, &nt, &xm, &s2, &ms, &rem[2], &rem[3], &rem[4], &rem[5],
                          &rem[6], &rem[7], &rem[8]);
     if (n != 9 && n != 16) continue;
-    if (n == 9)
-      for (int r = 2; r < 9; ++r) rem[r] = -1;
     for (int r = 2; r < 9; ++r)
       if (rem[r] < -1 || rem[r] >= kNumTBVariants || (rem[r] >= 0 && kTBVariants[rem[r]].steps != r))
         rem[r] = -1;
