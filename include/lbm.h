@@ -337,10 +337,10 @@ lbm_status lbm_set_tblock_split(lbm_ctx* ctx, int32_t mode);
 /* 1 if launches of blocked variant `index` run split on this context as
  * configured now, 0 if not, -1 for a NULL context or a bad index. */
 int32_t lbm_tblock_split_active(lbm_ctx* ctx, int32_t index);
-/* The blocked variant lbm_step launches for the last r steps of a run (r = 2
- * .. 8, fewer than the selected variant's T) after its full launches: the
- * fastest r-step variant lbm_autotune timed (kept in its cache file as
- * well), else the r-step variant nearest to the selected one's launch shape;
+/* The r-step blocked variant (r = 2 .. 8) lbm_step launches for the last r
+ * steps of a run when r is below the selected variant's T: the fastest
+ * r-step variant lbm_autotune timed (kept in its cache file as well), else
+ * the r-step variant nearest to the selected one's launch shape;
  * *h_index = -1 when no variant is selected or r is outside 2 .. 8.
  * LBM_E_ARG for a NULL argument. */
 lbm_status lbm_get_tblock_remainder(const lbm_ctx* ctx, int32_t r, int32_t* h_index);
