@@ -113,7 +113,7 @@ def main():
             lat.tblock_config = forced2[li] if forced2 else -1
         else:
             lat.autotune(reps=10, use_cache=True)
-            rerank(lat, fields[li])
+            rerank(lat, fields[li], min(K, RERANK_STEPS))
         idx, idx2 = lat.step_config, lat.tblock_config
         c = cfgs[idx]
         t = {"lattice": "%dx%d" % (lat.nx, lat.ny), "config": idx, "vec": c["vec"],
@@ -320,20 +320,23 @@ def launch_key(t):
                                                    t["shuffle"])
 
 
-RERANK_STEPS = 840  # a multiple of every steps-per-launch
+RERANK_STEPS = 840  # steps each candidate of the re-rank is timed for
 
 
-def rerank(lat, fields, top=4):
+def rerank(lat, fields, run_steps, top=4):
     """The autotuner times repeated launches from one buffer, which on grids
     smaller than the device's last-level cache stays resident there; real
-    stepping alternates two buffers.  Time the autotuner's choice and the
-    blocked variants its launch timing ranks best by stepping RERANK_STEPS
-    steps each, keep the fastest, and re-initialise the lattice (state and
-    step count as before)."""
+    stepping alternates two buffers, and a run of n steps pays for the launch
+    that takes the n mod T steps after the last full one.  Time the
+    autotuner's choice and the blocked variants its launch timing ranks best
+    per step by stepping runs of the benchmark's own length (run_steps steps
+    per call, repeated up to RERANK_STEPS steps), keep the fastest, and
+    re-initialise the lattice (state and step count as before)."""
     import torch
     per_step = sorted((lat.time_tblock_config(c["index"], 5) / c["steps"], c["index"])
                       for c in lat.tblock_configs())
     cands = [lat.tblock_config] + [i for _, i in per_step[:top] if i != lat.tblock_config]
+    reps = max(1, RERANK_STEPS // run_steps)
     best = None
     for idx in cands:
         lat.init(*fields)
@@ -341,7 +344,8 @@ def rerank(lat, fields, top=4):
         lat.step(64)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
-        lat.step(RERANK_STEPS)
+        for _ in range(reps):
+            lat.step(run_steps)
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1)

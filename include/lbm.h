@@ -291,7 +291,7 @@ lbm_status lbm_autotune(lbm_ctx* ctx, int32_t reps, int32_t use_cache, int32_t* 
  * state.  A wave owns a strip of 64 columns and sweeps a segment of rows,
  * forming the T - 1 intermediate time levels in registers, so T steps read and
  * write the populations once (80 B + 80 B per node for T updates).  Bitwise
- * identical to T single steps.  Variants (h_steps = T in 2..8) differ in rows
+ * identical to T single steps.  Variants (h_steps = T in 2..10) differ in rows
  * per segment, store type and rows prefetched ahead (h_prefetch); h_seg_rows
  * 0 means the segment length is chosen at launch so that one wave per
  * resident slot covers the grid, -k that k waves per slot do, -100 that one
@@ -337,11 +337,11 @@ lbm_status lbm_set_tblock_split(lbm_ctx* ctx, int32_t mode);
 /* 1 if launches of blocked variant `index` run split on this context as
  * configured now, 0 if not, -1 for a NULL context or a bad index. */
 int32_t lbm_tblock_split_active(lbm_ctx* ctx, int32_t index);
-/* The r-step blocked variant (r = 2 .. 8) lbm_step launches for the last r
+/* The r-step blocked variant (r = 2 .. 10) lbm_step launches for the last r
  * steps of a run when r is below the selected variant's T: the fastest
  * r-step variant lbm_autotune timed (kept in its cache file as well), else
  * the r-step variant nearest to the selected one's launch shape;
- * *h_index = -1 when no variant is selected or r is outside 2 .. 8.
+ * *h_index = -1 when no variant is selected or r is outside 2 .. 10.
  * LBM_E_ARG for a NULL argument. */
 lbm_status lbm_get_tblock_remainder(const lbm_ctx* ctx, int32_t r, int32_t* h_index);
 /* Average duration (ms) of one launch of blocked variant `index` (T steps;

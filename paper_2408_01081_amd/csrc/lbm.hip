@@ -400,7 +400,7 @@ struct lbm_ctx {
   int tb_cfg;         // index into kTBVariants, or -1 (single steps only)
   int tb_slots[64];   // resident waves of a blocked variant on this device (0: not known)
   int tbf_slots[48];  // the same for the variants with a load / displacement (3 per variant)
-  int tb_rem[9];      // variant for the last r = 2 .. 8 steps of a run (-1: nearest shape)
+  int tb_rem[TB_MAX_STEPS + 1];  // variant for the last r = 2 .. 10 steps of a run (-1: nearest shape)
   // split Dirichlet blocked launches (mode -1, the default, or 1: wherever a
   // split kernel exists and the lattice allows; 0: never): the wall band
   // with the Dirichlet rule and the interior with the periodic kernel's
@@ -611,7 +611,7 @@ lbm_status lbm_create(const lbm_params* p, void* d_ws, size_t ws_size, void* hip
   hipGetDevice(&c->device);
   c->step_cfg = default_step_config(g.nx);
   c->tb_cfg = -1;
-  for (int r = 0; r < 9; ++r) c->tb_rem[r] = -1;
+  for (int r = 0; r <= TB_MAX_STEPS; ++r) c->tb_rem[r] = -1;
   c->tb_split = -1;
   *out = c;
   g_err.clear();
@@ -998,7 +998,7 @@ void launch_tb(lbm_ctx* c, int index, const float* src, float* dst, const WallSe
 // segment, store type and prefetch, then the same rows per segment and
 // prefetch, then the same rows per segment, then the first); -1 if none.
 int remainder_variant(const lbm_ctx* c, int r) {
-  if (r < 2 || r > 8) return -1;
+  if (r < 2 || r > TB_MAX_STEPS) return -1;
   if (c->tb_rem[r] >= 0) return c->tb_rem[r];
   const TBVariant& t = kTBVariants[c->tb_cfg];
   int best = -1, best_score = -1;
@@ -1231,17 +1231,17 @@ struct TuneKey {
 };
 
 // single-step configuration, blocked variant (-1: none) and the variants for
-// the last r steps of a run (-1: nearest shape; not kept in the cache file)
+// the last r steps of a run (-1: nearest shape)
 struct TuneVal {
   int cfg, cfg2;
-  int rem[9];
+  int rem[TB_MAX_STEPS + 1];
 };
 
 TuneVal tune_val(int cfg, int cfg2, const int* rem) {
   TuneVal v;
   v.cfg = cfg;
   v.cfg2 = cfg2;
-  for (int r = 0; r < 9; ++r) v.rem[r] = rem ? rem[r] : -1;
+  for (int r = 0; r <= TB_MAX_STEPS; ++r) v.rem[r] = rem ? rem[r] : -1;
   return v;
 }
 
@@ -1258,7 +1258,7 @@ int find_config(int vec, int threads, int nt, int xmode) {
 }
 
 // Cache file (path in LBM_AUTOTUNE_CACHE): one line per tuned shape,
-// "nx ny bc vec threads nt xmode tb ms r2 .. r8" (tb = blocked variant or -1,
+// "nx ny bc vec threads nt xmode tb ms r2 .. r10" (tb = blocked variant or -1,
 // r = the variant for the last r steps of a run or -1; lines without the r
 // fields are read with none), for the default split mode only.
 // Caller holds g_tune_mu.
@@ -1271,14 +1271,15 @@ void load_tune_file() {
   if (!f) return;
   char line[512];
   while (fgets(line, sizeof line, f)) {
-    int nx, ny, bc, vec, th, nt, xm, s2, rem[9];
+    int nx, ny, bc, vec, th, nt, xm, s2, rem[TB_MAX_STEPS + 1];
     double ms;
-    for (int r = 0; r < 9; ++r) rem[r] = -1;
-    const int n = sscanf(line, "%d %d %d %d %d %d %d %d %lf %d %d %d %d %d %d %d", &nx, &ny,
-                         &bc, &vec, &th, &nt, &xm, &s2, &ms, &rem[2], &rem[3], &rem[4], &rem[5],
-                         &rem[6], &rem[7], &rem[8]);
-    if (n != 9 && n != 16) continue;
-    for (int r = 2; r < 9; ++r)
+    for (int r = 0; r <= TB_MAX_STEPS; ++r) rem[r] = -1;
+    static_assert(TB_MAX_STEPS == 10, "the line format below lists r = 2 .. 10");
+    const int n = sscanf(line, "%d %d %d %d %d %d %d %d %lf %d %d %d %d %d %d %d %d %d", &nx,
+                         &ny, &bc, &vec, &th, &nt, &xm, &s2, &ms, &rem[2], &rem[3], &rem[4],
+                         &rem[5], &rem[6], &rem[7], &rem[8], &rem[9], &rem[10]);
+    if (n != 9 && n != 18) continue;
+    for (int r = 2; r <= TB_MAX_STEPS; ++r)
       if (rem[r] < -1 || rem[r] >= kNumTBVariants || (rem[r] >= 0 && kTBVariants[rem[r]].steps != r))
         rem[r] = -1;
     const int i = find_config(vec, th, nt, xm);
@@ -1296,7 +1297,7 @@ void append_tune_file(const TuneKey& k, const TuneVal& v, double ms) {
   const StepConfig& c = kStepConfigs[v.cfg];
   fprintf(f, "%d %d %d %d %d %d %d %d %.6f", k.nx, k.ny, k.bc, c.vec, c.threads, c.nt, c.xmode,
           v.cfg2, ms);
-  for (int r = 2; r < 9; ++r) fprintf(f, " %d", v.rem[r]);
+  for (int r = 2; r <= TB_MAX_STEPS; ++r) fprintf(f, " %d", v.rem[r]);
   fprintf(f, "\n");
   fclose(f);
 }
@@ -1343,7 +1344,7 @@ lbm_status lbm_autotune(lbm_ctx* c, int32_t reps, int32_t use_cache, int32_t* h_
     if (it != g_tune_cache.end()) {
       c->step_cfg = it->second.cfg;
       c->tb_cfg = it->second.cfg2 < kNumTBVariants && tblock_fits(c->g) ? it->second.cfg2 : -1;
-      for (int r = 0; r < 9; ++r) c->tb_rem[r] = c->tb_cfg >= 0 ? it->second.rem[r] : -1;
+      for (int r = 0; r <= TB_MAX_STEPS; ++r) c->tb_rem[r] = c->tb_cfg >= 0 ? it->second.rem[r] : -1;
       if (h_index) *h_index = it->second.cfg;
       if (h_ms) *h_ms = -1.0;
       return LBM_OK;
@@ -1386,9 +1387,9 @@ lbm_status lbm_autotune(lbm_ctx* c, int32_t reps, int32_t use_cache, int32_t* h_
   // blocked variants: time per step = time per launch / steps per launch
   int best2 = -1;
   double best2_ms = 1e300;
-  int rem[9];
-  double rem_ms[9];
-  for (int r = 0; r < 9; ++r) {
+  int rem[TB_MAX_STEPS + 1];
+  double rem_ms[TB_MAX_STEPS + 1];
+  for (int r = 0; r <= TB_MAX_STEPS; ++r) {
     rem[r] = -1;
     rem_ms[r] = 1e300;
   }
@@ -1419,7 +1420,7 @@ lbm_status lbm_autotune(lbm_ctx* c, int32_t reps, int32_t use_cache, int32_t* h_
   if (best < 0) return fail(LBM_E_ARG, "no valid launch configuration");
   c->step_cfg = best;
   c->tb_cfg = best2_ms < best_ms ? best2 : -1;
-  for (int r = 0; r < 9; ++r) c->tb_rem[r] = rem[r];
+  for (int r = 0; r <= TB_MAX_STEPS; ++r) c->tb_rem[r] = rem[r];
   const double per_step = best2_ms < best_ms ? best2_ms : best_ms;
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);

@@ -21,6 +21,7 @@ struct TBVariant {
   int steps, seg_rows, nt, pf;
 };
 constexpr int TB_SEG_SIMD = -100;
+constexpr int TB_MAX_STEPS = 10;  // most steps of a launch
 
 // Load-free variants; the index is the public variant number
 // (lbm_tblock_config_info), so entries are only ever appended.
@@ -33,8 +34,15 @@ constexpr TBVariant kTBVariants[] = {
     {7, 20, 0, 2}, {7, 30, 0, 2}, {6, 8, 0, 1},  {6, 12, 0, 1}, {6, 20, 0, 2}, {6, 30, 0, 2},
     {8, 20, 0, 2}, {8, 30, 0, 2}, {8, 24, 0, 1}, {8, 32, 0, 1}, {8, 0, 0, 2},  {8, -2, 0, 2},
     {8, 0, 0, 1},  {7, 0, 0, 2},  {4, 0, 0, 1},  {3, 0, 0, 1},  {4, 375, 0, 2}, {5, 375, 0, 2},
-    {4, TB_SEG_SIMD, 0, 3}, {5, TB_SEG_SIMD, 0, 3}, {3, TB_SEG_SIMD, 0, 3}, {2, TB_SEG_SIMD, 0, 3}};
+    {4, TB_SEG_SIMD, 0, 3}, {5, TB_SEG_SIMD, 0, 3}, {3, TB_SEG_SIMD, 0, 3}, {2, TB_SEG_SIMD, 0, 3},
+    {10, -2, 0, 2}, {10, 0, 0, 2}, {9, 0, 0, 2}};
 constexpr int kNumTBVariants = (int)(sizeof(kTBVariants) / sizeof(kTBVariants[0]));
+constexpr bool tb_steps_in_range() {
+  for (const TBVariant& v : kTBVariants)
+    if (v.steps < 2 || v.steps > TB_MAX_STEPS) return false;
+  return true;
+}
+static_assert(tb_steps_in_range(), "steps per launch in 2 .. TB_MAX_STEPS");
 // the load-free tables are filled in two halves per boundary type
 constexpr int kTBSplit = 24;
 

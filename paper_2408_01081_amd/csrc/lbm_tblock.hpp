@@ -655,7 +655,7 @@ __device__ __forceinline__ void tblock_wave(const float* __restrict__ src, float
                                    const Grid& g, const TBConst& sc, const WallSeq& ws,
                                    int strip, int y0, int y1, const TBExtra& F = TBExtra{},
                                    float* fac = nullptr, double* dring = nullptr) {
-  static_assert(T >= 2 && T <= 8, "2 to 8 time levels per launch");
+  static_assert(T >= 2 && T <= 10, "2 to 10 time levels per launch");
   constexpr int VALID = TB_LANES - 2 * T;  // stored columns per strip
   const int lane = threadIdx.x & 63;
   const int nx = g.nx, ny = g.ny;

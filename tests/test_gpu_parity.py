@@ -256,7 +256,7 @@ def test_full_size_dirichlet_2048x1024_bench_configuration_all_nodes():
     W, T = prob.wall_table(max(n, bench.RERANK_STEPS + 64))
     lat.set_wall_velocity(torch.from_numpy(W).cuda(), torch.from_numpy(T).cuda())
     lat.autotune(reps=10, use_cache=True)
-    bench.rerank(lat, fields)
+    bench.rerank(lat, fields, 20)   # the variant for runs of 20 steps
     cfg = lat.tblock_config
     print("variant %d, %d steps per launch" % (cfg, lat.steps_per_launch), flush=True)
     lat.step(n)
