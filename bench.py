@@ -115,6 +115,7 @@ def main():
         else:
             lat.autotune(reps=10, use_cache=True)
             per_step_pick.append(lat.tblock_config)
+            lat.select_for_steps(min(K, RERANK_STEPS))   # cheapest for the run length
             rerank(lat, fields[li], min(K, RERANK_STEPS))
         idx, idx2 = lat.step_config, lat.tblock_config
         c = cfgs[idx]

@@ -337,6 +337,18 @@ lbm_status lbm_set_tblock_split(lbm_ctx* ctx, int32_t mode);
 /* 1 if launches of blocked variant `index` run split on this context as
  * configured now, 0 if not, -1 for a NULL context or a bad index. */
 int32_t lbm_tblock_split_active(lbm_ctx* ctx, int32_t index);
+/* Select the launch configuration that makes runs of nsteps steps cheapest:
+ * for every blocked variant (and for single steps) the predicted time of such
+ * a run from the launch times the last lbm_autotune of this shape in this
+ * process measured, floor(nsteps / T) full launches plus the launch lbm_step
+ * takes for the nsteps mod T steps left; the cheapest becomes the selected
+ * variant (*h_index, -1: single steps).  A variant that divides nsteps can
+ * win over one that is faster per step (4096^2: T = 10 for 20-step runs,
+ * against T = 8 per step).  Without such launch times (no lbm_autotune, or
+ * its choice read from the cache file) the selection is unchanged.
+ * Applies to lbm_step without a body load, displacement state or error
+ * tracking.  LBM_E_ARG for a NULL argument or nsteps < 1. */
+lbm_status lbm_select_for_steps(lbm_ctx* ctx, int64_t nsteps, int32_t* h_index);
 /* The r-step blocked variant (r = 2 .. 10) lbm_step launches for the last r
  * steps of a run when r is below the selected variant's T: the fastest
  * r-step variant lbm_autotune timed (kept in its cache file as well), else

@@ -70,6 +70,7 @@ SIGNATURES = [
     ("lbm_set_tblock_split", ctypes.c_int, [_VP, _I32]),
     ("lbm_tblock_split_active", _I32, [_VP, _I32]),
     ("lbm_get_tblock_remainder", ctypes.c_int, [_VP, _I32, ctypes.POINTER(_I32)]),
+    ("lbm_select_for_steps", ctypes.c_int, [_VP, _I64, ctypes.POINTER(_I32)]),
     ("lbm_time_tblock_config", ctypes.c_int, [_VP, _I32, _I32, _PD]),
     ("lbm_wop_scratch_bytes", ctypes.c_size_t, [ctypes.POINTER(LbmParams)]),
     ("lbm_wop_operand_bytes", ctypes.c_size_t, []),

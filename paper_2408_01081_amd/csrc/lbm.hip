@@ -401,6 +401,10 @@ struct lbm_ctx {
   int tb_slots[64];   // resident waves of a blocked variant on this device (0: not known)
   int tbf_slots[48];  // the same for the variants with a load / displacement (3 per variant)
   int tb_rem[TB_MAX_STEPS + 1];  // variant for the last r = 2 .. 10 steps of a run (-1: nearest shape)
+  // launch times the autotuner measured for this shape (ms; -1: not timed):
+  // every blocked variant, and the best single-step configuration
+  double tb_launch_ms[kNumTBVariants];
+  double step_launch_ms;
   // split Dirichlet blocked launches (mode -1, the default, or 1: wherever a
   // split kernel exists and the lattice allows; 0: never): the wall band
   // with the Dirichlet rule and the interior with the periodic kernel's
@@ -613,6 +617,8 @@ lbm_status lbm_create(const lbm_params* p, void* d_ws, size_t ws_size, void* hip
   c->tb_cfg = -1;
   for (int r = 0; r <= TB_MAX_STEPS; ++r) c->tb_rem[r] = -1;
   c->tb_split = -1;
+  for (int i = 0; i < kNumTBVariants; ++i) c->tb_launch_ms[i] = -1.0;
+  c->step_launch_ms = -1.0;
   *out = c;
   g_err.clear();
   return LBM_OK;
@@ -1235,13 +1241,17 @@ struct TuneKey {
 struct TuneVal {
   int cfg, cfg2;
   int rem[TB_MAX_STEPS + 1];
+  double launch_ms[kNumTBVariants];  // in this process only (-1: not timed)
+  double step_ms;
 };
 
-TuneVal tune_val(int cfg, int cfg2, const int* rem) {
+TuneVal tune_val(int cfg, int cfg2, const int* rem, const lbm_ctx* timed = nullptr) {
   TuneVal v;
   v.cfg = cfg;
   v.cfg2 = cfg2;
   for (int r = 0; r <= TB_MAX_STEPS; ++r) v.rem[r] = rem ? rem[r] : -1;
+  for (int i = 0; i < kNumTBVariants; ++i) v.launch_ms[i] = timed ? timed->tb_launch_ms[i] : -1.0;
+  v.step_ms = timed ? timed->step_launch_ms : -1.0;
   return v;
 }
 
@@ -1345,6 +1355,8 @@ lbm_status lbm_autotune(lbm_ctx* c, int32_t reps, int32_t use_cache, int32_t* h_
       c->step_cfg = it->second.cfg;
       c->tb_cfg = it->second.cfg2 < kNumTBVariants && tblock_fits(c->g) ? it->second.cfg2 : -1;
       for (int r = 0; r <= TB_MAX_STEPS; ++r) c->tb_rem[r] = c->tb_cfg >= 0 ? it->second.rem[r] : -1;
+      for (int i = 0; i < kNumTBVariants; ++i) c->tb_launch_ms[i] = it->second.launch_ms[i];
+      c->step_launch_ms = it->second.step_ms;
       if (h_index) *h_index = it->second.cfg;
       if (h_ms) *h_ms = -1.0;
       return LBM_OK;
@@ -1404,6 +1416,7 @@ lbm_status lbm_autotune(lbm_ctx* c, int32_t reps, int32_t use_cache, int32_t* h_
     if (s == LBM_OK) s = hip_check(hipEventElapsedTime(&ms, e0, e1), "autotune timing");
     const int steps = kTBVariants[i].steps;
     const double per = (double)ms / reps / steps;
+    if (s == LBM_OK) c->tb_launch_ms[i] = (double)ms / reps;
     if (s == LBM_OK && per < best2_ms) {
       best2_ms = per;
       best2 = i;
@@ -1419,13 +1432,14 @@ lbm_status lbm_autotune(lbm_ctx* c, int32_t reps, int32_t use_cache, int32_t* h_
   if (s) return s;
   if (best < 0) return fail(LBM_E_ARG, "no valid launch configuration");
   c->step_cfg = best;
+  c->step_launch_ms = best_ms;
   c->tb_cfg = best2_ms < best_ms ? best2 : -1;
   for (int r = 0; r <= TB_MAX_STEPS; ++r) c->tb_rem[r] = rem[r];
   const double per_step = best2_ms < best_ms ? best2_ms : best_ms;
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     load_tune_file();
-    g_tune_cache[key] = tune_val(best, c->tb_cfg, rem);
+    g_tune_cache[key] = tune_val(best, c->tb_cfg, rem, c);
     append_tune_file(key, g_tune_cache[key], per_step);
   }
   if (h_index) *h_index = best;
@@ -1469,6 +1483,40 @@ lbm_status lbm_set_tblock_config(lbm_ctx* c, int32_t index) {
   if (index >= 0 && !tblock_fits(c->g))
     return fail(LBM_E_ARG, "grid too wide for the blocked kernel (row offsets exceed 2^31 B)");
   c->tb_cfg = index;
+  return LBM_OK;
+}
+
+lbm_status lbm_select_for_steps(lbm_ctx* c, int64_t nsteps, int32_t* h_index) {
+  if (!c || !h_index || nsteps < 1) return fail(LBM_E_ARG, "null argument or no steps");
+  *h_index = c->tb_cfg;
+  if (c->step_launch_ms <= 0.0) return LBM_OK;  // no launch times: selection unchanged
+  // predicted time of a run of nsteps steps with variant v (-1: single steps):
+  // its full launches, then the launch lbm_step takes for the steps left
+  auto cost = [&](int v) {
+    const int T = v >= 0 ? kTBVariants[v].steps : 1;
+    const double full = v >= 0 ? c->tb_launch_ms[v] : c->step_launch_ms;
+    if (full <= 0.0) return 1e300;
+    const int r = (int)(nsteps % T);
+    double rest = 0.0;
+    if (r == 1) {
+      rest = c->step_launch_ms;
+    } else if (r > 1) {
+      const int ri = remainder_variant(c, r);
+      rest = ri >= 0 && c->tb_launch_ms[ri] > 0.0 ? c->tb_launch_ms[ri] : r * c->step_launch_ms;
+    }
+    return (double)(nsteps / T) * full + rest;
+  };
+  int best = -1;
+  double best_cost = cost(-1);
+  for (int v = 0; v < kNumTBVariants; ++v) {
+    const double cv = cost(v);
+    if (cv < best_cost) {
+      best_cost = cv;
+      best = v;
+    }
+  }
+  c->tb_cfg = best;
+  *h_index = best;
   return LBM_OK;
 }
 

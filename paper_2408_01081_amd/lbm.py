@@ -266,6 +266,14 @@ class Lattice:
         """Whether launches of blocked variant `index` run split now."""
         return int(self.L.lbm_tblock_split_active(self.ctx, int(index))) == 1
 
+    def select_for_steps(self, n):
+        """Select the launch configuration cheapest for runs of n steps
+        (from the last autotune's launch times); returns the blocked variant
+        (-1: single steps)."""
+        i = ctypes.c_int32()
+        check(self.L.lbm_select_for_steps(self.ctx, int(n), ctypes.byref(i)))
+        return i.value
+
     def tblock_remainder(self, r):
         """The blocked variant `step` launches for the last r steps of a run
         (-1: none)."""

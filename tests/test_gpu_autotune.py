@@ -108,6 +108,41 @@ def test_autotune_cache_file_keeps_every_choice(tmp_path):
 
 
 @gpu
+def test_select_for_steps():
+    # the configuration cheapest for runs of n steps, from the autotuner's
+    # launch times: on 4096^2 a 20-step run takes two 10-step launches
+    # (T = 8, the fastest per step, needs a third launch for the last 4
+    # steps); without launch times the selection stays; the state is
+    # bitwise that of single steps whatever is selected
+    torch = _torch()
+    from paper_2408_01081_amd.lbm import Lattice
+    prob = synth.plane_wave_problem(4096, 4096, synth.PERIODIC, seed=5, kmax=4)
+    v0, sb0 = (torch.from_numpy(a).cuda() for a in prob.initial_fields())
+    lat = Lattice(prob.nx, prob.ny, prob.dx, prob.dt, prob.lam, prob.mu, prob.rho, prob.bc)
+    lat.init(v0, sb0)
+    lat.tblock_config = 3
+    assert lat.select_for_steps(20) == 3 == lat.tblock_config   # no launch times yet
+    lat.autotune(reps=3, use_cache=False)
+    steps = {c["index"]: c["steps"] for c in lat.tblock_configs()}
+    per_step = lat.tblock_config
+    assert per_step >= 0
+    idx = lat.select_for_steps(20)
+    assert idx == lat.tblock_config and 20 % steps[idx] == 0, (idx, per_step)
+    if 20 % steps[per_step]:
+        assert idx != per_step
+    lat.init(v0, sb0)
+    lat.step(20)
+    got = lat.populations()
+    lat.init(v0, sb0)
+    lat.tblock_config = -1
+    lat.step(20)
+    assert torch.equal(got.view(torch.int32), lat.populations().view(torch.int32))
+    for n in (1, 7, 840):
+        i = lat.select_for_steps(n)
+        assert i == lat.tblock_config and -1 <= i < len(steps)
+
+
+@gpu
 def test_copy_kernel():
     torch = _torch()
     from paper_2408_01081_amd.lbm import copy_f32
