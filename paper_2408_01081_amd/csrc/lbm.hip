@@ -779,6 +779,8 @@ lbm_status lbm_set_wall_velocity(lbm_ctx* c, int32_t rank, const float* d_W, con
 
 int64_t lbm_step_count(const lbm_ctx* c) { return c ? c->nstep : -1; }
 
+}  // extern "C"
+
 namespace {
 
 // Kernel handles of the blocked variants (lbm_tb_tables.hpp), filled once
@@ -1075,6 +1077,7 @@ int extra_remainder_variant(const lbm_ctx* c, int m, int r) {
 }
 
 }  // namespace
+extern "C" {
 
 // Steps with a body load and/or the displacement state: one step per launch
 // of the one-node-per-thread kernel.  Step n -> n+1 collides at t_{n+1} with
@@ -1226,6 +1229,8 @@ lbm_status lbm_step(lbm_ctx* c, int64_t nsteps) {
 }
 
 // ---- launch configurations and the autotuner ------------------------------
+}  // extern "C"
+
 namespace {
 
 struct TuneKey {
@@ -1313,6 +1318,7 @@ void append_tune_file(const TuneKey& k, const TuneVal& v, double ms) {
 }
 
 }  // namespace
+extern "C" {
 
 int32_t lbm_step_config_count(void) { return kNumStepConfigs; }
 
