@@ -61,7 +61,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py runs on exactly one GPU: the lattice workload is measured on one "
-              "GPU's share; multi-GPU runs are not part of this build (asked for --gpus %d)"
+              "GPU's share; runs over several GPUs are not supported (asked for --gpus %d)"
               % args.gpus, file=sys.stderr)
         sys.exit(2)
 
