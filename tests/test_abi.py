@@ -141,3 +141,14 @@ def test_split_dirichlet_launch_rule():
             assert L.lbm_tblock_split_active(h, len(info)) == -1
         finally:
             L.lbm_destroy(h)
+
+
+def test_launch_selection_calls_reject_null_arguments():
+    # host-side argument checks of the launch-selection calls (no device work)
+    from paper_2408_01081_amd import _lib
+    L = _lib.load()
+    out = ctypes.c_int32(7)
+    assert L.lbm_select_for_steps(None, 20, ctypes.byref(out)) == 1
+    assert L.lbm_get_tblock_remainder(None, 4, ctypes.byref(out)) == 1
+    assert L.lbm_tblock_split_active(None, 0) == -1
+    assert out.value == 7
