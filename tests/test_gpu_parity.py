@@ -152,27 +152,33 @@ def test_errors_reported():
 def test_full_size_periodic_4096_vs_exact_discrete_evolution():
     # 4096^2 periodic plane waves, 1000 steps: sampled nodes against the exact
     # FP64 per-mode evolution of the same scheme (pinned to the C oracle on
-    # small grids in test_oracle_invariants)
+    # small grids in test_oracle_invariants), in the autotuner's launch
+    # configuration and in the one selected for 20-step runs (10 steps per
+    # launch on this lattice)
     torch = _torch()
     from oracle import spectral
     prob = synth.plane_wave_problem(4096, 4096, synth.PERIODIC, seed=2)
-    v0, sb0 = prob.initial_fields()
+    v0, sb0 = (torch.from_numpy(a) for a in prob.initial_fields())
     lat = _lattice(prob)
-    lat.init(torch.from_numpy(v0), torch.from_numpy(sb0))
-    del v0, sb0
+    lat.init(v0, sb0)
     lat.autotune(reps=5)
-    lat.step(1000)
     g = np.random.default_rng(7)
     iy = g.integers(0, 4096, 2000)
     ix = g.integers(0, 4096, 2000)
     iy[:4] = [0, 0, 4095, 4095]
     ix[:4] = [0, 4095, 0, 4095]
-    U = lat.moments_U()
-    got = U[:, torch.from_numpy(iy).cuda(), torch.from_numpy(ix).cuda()].double().cpu().numpy()
     want = spectral.plane_wave_reference(_setup(prob), prob.sol, 1000, iy, ix)
-    err = oracle.rel_l2(got, want)
-    print("4096^2 periodic, 1000 steps, rel-L2 vs exact FP64 evolution: %.3e" % err)
-    assert err < 1e-5
+    for run in (None, 20):
+        if run:
+            lat.select_for_steps(run)
+        lat.init(v0, sb0)
+        lat.step(1000)
+        U = lat.moments_U()
+        got = U[:, torch.from_numpy(iy).cuda(), torch.from_numpy(ix).cuda()].double().cpu().numpy()
+        err = oracle.rel_l2(got, want)
+        print("4096^2 periodic, variant %d (%d steps per launch), 1000 steps, rel-L2 vs exact "
+              "FP64 evolution: %.3e" % (lat.tblock_config, lat.steps_per_launch, err))
+        assert err < 1e-5
 
 
 def _window_reference(prob, cy, cx, n):
