@@ -1001,14 +1001,15 @@ void launch_tb(lbm_ctx* c, int index, const float* src, float* dst, const WallSe
 }
 
 // The variant that takes the last r (2 <= r < T) steps of a run in one
-// launch: the autotuner's fastest r-step variant when it has timed them, else
-// the r-step variant nearest to the selected one's shape (same rows per
-// segment, store type and prefetch, then the same rows per segment and
-// prefetch, then the same rows per segment, then the first); -1 if none.
-int remainder_variant(const lbm_ctx* c, int r) {
-  if (r < 2 || r > TB_MAX_STEPS) return -1;
+// launch after full launches of variant `shape`: the autotuner's fastest
+// r-step variant when it has timed them, else the r-step variant nearest to
+// that shape (same rows per segment, store type and prefetch, then the same
+// rows per segment and prefetch, then the same rows per segment, then the
+// first); -1 if none, or if `shape` is not a blocked variant.
+int remainder_variant(const lbm_ctx* c, int r, int shape) {
+  if (r < 2 || r > TB_MAX_STEPS || shape < 0 || shape >= kNumTBVariants) return -1;
   if (c->tb_rem[r] >= 0) return c->tb_rem[r];
-  const TBVariant& t = kTBVariants[c->tb_cfg];
+  const TBVariant& t = kTBVariants[shape];
   int best = -1, best_score = -1;
   for (int i = 0; i < kNumTBVariants; ++i) {
     const TBVariant& k = kTBVariants[i];
@@ -1211,7 +1212,7 @@ lbm_status lbm_step(lbm_ctx* c, int64_t nsteps) {
         launch_tb(c, c->tb_cfg, c->buf[c->cur], c->buf[c->cur ^ 1], walls_from(c, k, true));
         c->cur ^= 1;
       }
-      const int ri = remainder_variant(c, m - k);
+      const int ri = remainder_variant(c, m - k, c->tb_cfg);
       if (ri >= 0) {
         launch_tb(c, ri, c->buf[c->cur], c->buf[c->cur ^ 1], walls_from(c, k, true));
         c->cur ^= 1;
@@ -1507,7 +1508,7 @@ lbm_status lbm_select_for_steps(lbm_ctx* c, int64_t nsteps, int32_t* h_index) {
     if (r == 1) {
       rest = c->step_launch_ms;
     } else if (r > 1) {
-      const int ri = remainder_variant(c, r);
+      const int ri = remainder_variant(c, r, v);
       rest = ri >= 0 && c->tb_launch_ms[ri] > 0.0 ? c->tb_launch_ms[ri] : r * c->step_launch_ms;
     }
     return (double)(nsteps / T) * full + rest;
@@ -1528,7 +1529,7 @@ lbm_status lbm_select_for_steps(lbm_ctx* c, int64_t nsteps, int32_t* h_index) {
 
 lbm_status lbm_get_tblock_remainder(const lbm_ctx* c, int32_t r, int32_t* h_index) {
   if (!c || !h_index) return fail(LBM_E_ARG, "null argument");
-  *h_index = c->tb_cfg >= 0 ? remainder_variant(c, r) : -1;
+  *h_index = remainder_variant(c, r, c->tb_cfg);
   return LBM_OK;
 }
 
