@@ -5,8 +5,12 @@ TEST INFRASTRUCTURE ONLY (see the package docstring).  The surrogate is not
 part of the paper: it is a small convolutional time-stepper that maps the
 macroscopic fields of a lattice (velocity and Cauchy stress, plus Lame
 constants and density) to the fields 16 lattice steps later.  Parity against
-the paper is therefore unpinned; this reference is pinned instead by
-finite-difference gradients and by scipy's correlation routine (tests).
+the paper is therefore unpinned; this reference is pinned instead (tests) by
+scipy's correlation routine, adjoint identities and finite-difference
+gradients, T_n(cos theta) = cos(n theta) for the Chebyshev basis and the end
+points of the conditioning map, known values of pooling and up-sampling, the
+field conversion against the lattice oracle's (Eq. sigma_num), and the
+closed form of Adam under a constant gradient (n steps move n lr g/(|g|+eps)).
 
 Network (everything in float64 here):
   pre    physical fields -> first-order system variables U (inverse of
