@@ -13,7 +13,7 @@
         --launch 'T=7 seg=48 nt=0 pf=1' \\
         --command CMD --command CMD --out profiles/NAME.json
     python -m paper_2408_01081_amd.profile_summary stats --dir DIR --title T \\
-        --command CMD --note LINE --out profiles/NAME.md
+        --command CMD --note LINE [--only k_batch] --out profiles/NAME.md
 """
 from __future__ import annotations
 
@@ -105,10 +105,15 @@ def stats(a):
     lines = ["# " + a.title, "", "Command (repo root, one MI355X, ROCm 7.2):", ""]
     for c in a.command:
         lines.append("    " + c)
+    if a.only:
+        lines += ["", "Kernels whose names start with %s (share: of all kernel time in the run):"
+                  % ", ".join("`%s`" % o for o in a.only)]
     lines += ["", "| kernel | calls | avg (us) | min (us) | max (us) | share |",
               "|---|---|---|---|---|---|"]
     for r in rows:
         if "k_" not in r["Name"]:
+            continue
+        if a.only and not any(_short(r["Name"]).startswith(o) for o in a.only):
             continue
         lines.append("| %s | %s | %.1f | %.1f | %.1f | %.2f%% |" % (
             _short(r["Name"]), r["Calls"], float(r["AverageNs"]) / 1e3,
@@ -153,6 +158,8 @@ def main():
     s.add_argument("--by-grid", action="append", default=[],
                    help="also list the dispatches of kernels matching this string per "
                         "launch grid (from the kernel trace)")
+    s.add_argument("--only", action="append", default=[],
+                   help="list only the kernels whose names start with this prefix")
     s.add_argument("--out", required=True)
     a = ap.parse_args()
     traffic(a) if a.what == "traffic" else stats(a)
