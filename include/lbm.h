@@ -446,7 +446,10 @@ lbm_status lbm_batch_set_wall_velocity(lbm_batch* b, int32_t i, int32_t rank, co
                                        const float* d_T, int64_t nsteps);
 
 /* Advance every instance n steps: one hipGraph launch of the step kernels
- * (one step per kernel, or T per kernel with a blocked variant selected). */
+ * (one step per kernel, or T per kernel with a blocked variant selected; the
+ * r = n mod T steps after the last full launch as one launch of an r-step
+ * variant for r >= 2 -- the fastest one lbm_batch_autotune timed, else the
+ * one nearest to the selected variant's shape -- or one step for r = 1). */
 lbm_status lbm_batch_step(lbm_batch* b, int64_t n);
 
 /* Same steps launched one kernel at a time (no graph). */
@@ -459,11 +462,13 @@ lbm_status lbm_batch_step_eager(lbm_batch* b, int64_t n);
  * small launch before each blocked launch sums the wall velocities of its T
  * steps into a per-instance table in the workspace (as lbm_set_wall_velocity
  * data are summed for a single lattice), which the blocked kernel reads.
- * Index -1 = single steps.  Selecting a variant synchronises the batch's stream and
- * uploads its wave table into the workspace.  lbm_batch_autotune times the
- * single-step kernel and every usable variant on the live state without
- * changing it (reps launches each, HIP events), selects the fastest per step
- * and returns its index and ms per step; it synchronises. */
+ * Index -1 = single steps.  Every variant's wave table is uploaded into the
+ * workspace at lbm_batch_create; selecting a variant launches nothing.
+ * lbm_batch_autotune times the single-step kernel and every usable variant on
+ * the live state without changing it (reps launches each, HIP events), keeps
+ * the launch times (they pick the launch for the last steps of a run),
+ * selects the fastest per step and returns its index and ms per step; it
+ * synchronises. */
 int32_t lbm_batch_tblock_config_count(void);
 lbm_status lbm_batch_tblock_config_info(int32_t index, int32_t* h_steps, int32_t* h_seg_rows,
                                         int32_t* h_nontemporal, int32_t* h_prefetch);

@@ -324,8 +324,9 @@ struct Layout {
   std::vector<int> tile_inst, tile_count;
   int64_t pool_floats = 0, total_nodes = 0;
   int ntiles = 0;
-  int tb_waves[kNumBatchTB];  // waves of each blocked variant
-  int tb_max_waves = 0;
+  int tb_waves[kNumBatchTB];    // waves of each blocked variant
+  int64_t tb_wave0[kNumBatchTB];  // its wave table's first entry in the tables' region
+  int64_t tb_all_waves = 0;
   bool tb_ok = true;          // every instance fits the blocked kernel
   size_t off_pool[2], off_desc, off_tiles, off_count, off_partial, off_out, off_waves, off_wallv,
       bytes;
@@ -402,7 +403,8 @@ lbm_status plan(int32_t n, const lbm_params* params, Layout* L) {
     }
     if (w > 0x7fffffff) return fail(LBM_E_ARG, "batch too large");
     L->tb_waves[v] = (int)w;
-    if (w > L->tb_max_waves) L->tb_max_waves = (int)w;
+    L->tb_wave0[v] = L->tb_all_waves;
+    L->tb_all_waves += w;
   }
   for (int i = 0; i < n; ++i) L->tb_ok = L->tb_ok && tblock_fits(L->desc[i].g);
   L->tile_inst.resize(L->ntiles);
@@ -421,7 +423,7 @@ lbm_status plan(int32_t n, const lbm_params* params, Layout* L) {
   L->off_count = take(sizeof(int) * n);
   L->off_partial = take(sizeof(double) * 2 * (size_t)L->ntiles);
   L->off_out = take(sizeof(double) * 2 * n);
-  L->off_waves = take(sizeof(int2) * (size_t)L->tb_max_waves);
+  L->off_waves = take(sizeof(int2) * (size_t)(L->tb_ok ? L->tb_all_waves : 0));
   L->off_wallv = take(sizeof(float) * (size_t)wallv_floats);
   L->bytes = o;
   return LBM_OK;
@@ -440,13 +442,14 @@ struct lbm_batch {
   int* d_count;
   double* d_partial;
   double* d_out;
-  int2* d_waves;  // wave table of the selected blocked variant
+  int2* d_waves;  // wave tables of every blocked variant (uploaded at creation)
   int cur;
   bool initialised;
   int64_t nstep;
   std::vector<int64_t> wall_nsteps;
   bool any_wall;
   int tb_cfg;  // selected blocked variant, -1: one step per launch
+  double tb_ms[kNumBatchTB];  // launch time of each variant the autotuner timed, -1: not timed
   // (steps, parity, blocked variant) -> graph, built while no instance has walls
   std::map<std::tuple<int64_t, int, int>, hipGraphExec_t> graphs;
 };
@@ -464,13 +467,49 @@ lbm_status upload_descs(lbm_batch* b) {
                    "descriptor upload");
 }
 
+// The blocked variant that takes the last r (2 <= r < T) steps of a run in
+// one launch after full launches of the selected variant: the fastest r-step
+// variant the autotuner timed, else the r-step variant nearest to the
+// selected one's shape (rows per segment, then store type and prefetch);
+// -1 if none (no variant selected, or r outside 2 .. 7).
+int remainder_variant(const lbm_batch* b, int r) {
+  if (b->tb_cfg < 0 || r < 2 || r >= kBatchTB[b->tb_cfg].steps) return -1;
+  const BatchTBConfig& t = kBatchTB[b->tb_cfg];
+  int best = -1, best_score = -1;
+  double best_ms = 1e300;
+  for (int i = 0; i < kNumBatchTB; ++i) {
+    const BatchTBConfig& k = kBatchTB[i];
+    if (k.steps != r) continue;
+    if (b->tb_ms[i] > 0.0) {
+      if (best_score < 8 || b->tb_ms[i] < best_ms) {
+        best_score = 8;
+        best_ms = b->tb_ms[i];
+        best = i;
+      }
+      continue;
+    }
+    const int score = (k.seg_rows == t.seg_rows ? 4 : 0) + (k.pf == t.pf ? 2 : 0) +
+                      (k.nt == t.nt ? 1 : 0);
+    if (score > best_score) {
+      best_score = score;
+      best = i;
+    }
+  }
+  return best;
+}
+
 // Steps per launch for `steps` steps: T per launch with a blocked variant,
-// the remainder (fewer than T) one at a time.
+// then the r < T steps left as one launch of an r-step variant (r >= 2) or
+// one step.
 std::vector<int> launch_plan(const lbm_batch* b, int64_t steps) {
   std::vector<int> p;
   const int T = b->tb_cfg >= 0 ? kBatchTB[b->tb_cfg].steps : 1;
   int64_t k = 0;
   for (; T > 1 && k + T <= steps; k += T) p.push_back(T);
+  if (T > 1 && steps - k >= 2 && remainder_variant(b, (int)(steps - k)) >= 0) {
+    p.push_back((int)(steps - k));
+    k = steps;
+  }
   for (; k < steps; ++k) p.push_back(1);
   return p;
 }
@@ -494,7 +533,6 @@ void make_launch(const lbm_batch* b, int t, int parity, int64_t step, LaunchArgs
   a->dst = b->pool[parity ^ 1];
   a->descs = b->d_desc;
   a->tiles = b->d_tiles;
-  a->waves = b->d_waves;
   a->ntiles = b->L.ntiles;
   a->step = step;
   memset(&a->kp, 0, sizeof a->kp);
@@ -509,8 +547,11 @@ void make_launch(const lbm_batch* b, int t, int parity, int64_t step, LaunchArgs
     a->kp.func = reinterpret_cast<void*>(&k_batch_step<BT>);
     a->kp.gridDim = dim3((unsigned)a->ntiles);
   } else {
-    const BatchTBConfig& k = kBatchTB[b->tb_cfg];
-    a->nwaves = b->L.tb_waves[b->tb_cfg];
+    // the selected variant, or for the last steps of a run a shorter one
+    const int v = t == kBatchTB[b->tb_cfg].steps ? b->tb_cfg : remainder_variant(b, t);
+    const BatchTBConfig& k = kBatchTB[v];
+    a->waves = b->d_waves + b->L.tb_wave0[v];
+    a->nwaves = b->L.tb_waves[v];
     a->seg_rows = k.seg_rows;
     a->args[0] = (void*)&a->src;
     a->args[1] = (void*)&a->dst;
@@ -654,6 +695,7 @@ lbm_status lbm_batch_create(int32_t n, const lbm_params* params, void* d_ws, siz
   for (int i = 0; i < n; ++i)
     b->L.desc[i].V = b->L.voff[i] >= 0 ? (float*)(b->ws + b->L.off_wallv) + b->L.voff[i] : nullptr;
   b->tb_cfg = -1;
+  for (int v = 0; v < kNumBatchTB; ++v) b->tb_ms[v] = -1.0;
   b->cur = 0;
   b->initialised = false;
   b->nstep = 0;
@@ -668,6 +710,12 @@ lbm_status lbm_batch_create(int32_t n, const lbm_params* params, void* d_ws, siz
     s = hip_check(hipMemcpy(b->d_count, b->L.tile_count.data(), sizeof(int) * n,
                             hipMemcpyHostToDevice),
                   "tile count upload");
+  for (int v = 0; v < kNumBatchTB && s == LBM_OK && b->L.tb_ok; ++v) {
+    const std::vector<int2> t = wave_table(b->L, v);
+    s = hip_check(hipMemcpy(b->d_waves + b->L.tb_wave0[v], t.data(), sizeof(int2) * t.size(),
+                            hipMemcpyHostToDevice),
+                  "wave table upload");
+  }
   if (s) {
     delete b;
     return s;
@@ -811,17 +859,8 @@ lbm_status lbm_batch_set_tblock_config(lbm_batch* b, int32_t index) {
   if (index == b->tb_cfg) return LBM_OK;
   if (index >= 0 && !b->L.tb_ok)
     return fail(LBM_E_ARG, "an instance is too wide for the blocked kernel");
-  // the wave table is shared by every blocked variant: wait for queued work
-  // that may read it, then replace it
-  lbm_status s = hip_check(hipStreamSynchronize(b->stream), "batch sync");
-  if (s) return s;
-  drop_graphs(b);
-  if (index >= 0) {
-    const std::vector<int2> t = wave_table(b->L, index);
-    s = hip_check(hipMemcpy(b->d_waves, t.data(), sizeof(int2) * t.size(), hipMemcpyHostToDevice),
-                  "wave table upload");
-    if (s) return s;
-  }
+  // every variant's wave table stays in the workspace, and cached graphs are
+  // keyed by the variant: nothing to replace
   b->tb_cfg = index;
   return LBM_OK;
 }
@@ -861,6 +900,7 @@ lbm_status lbm_batch_autotune(lbm_batch* b, int32_t reps, int32_t* h_index, doub
     float ms = 0.f;
     if (s == LBM_OK) s = hip_check(hipEventElapsedTime(&ms, e0, e1), "autotune timing");
     const double per = (double)ms / reps / t;
+    if (s == LBM_OK && v >= 0) b->tb_ms[v] = (double)ms / reps;
     if (s == LBM_OK && per < best_ms) {
       best_ms = per;
       best = v;
@@ -869,6 +909,11 @@ lbm_status lbm_batch_autotune(lbm_batch* b, int32_t reps, int32_t* h_index, doub
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   if (s) return s;
+  // the launch times decide the launches for the last steps of a run: rebuild
+  // cached graphs
+  s = hip_check(hipStreamSynchronize(b->stream), "batch sync");
+  if (s) return s;
+  drop_graphs(b);
   s = lbm_batch_set_tblock_config(b, best);
   if (s) return s;
   if (h_index) *h_index = best;

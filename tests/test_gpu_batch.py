@@ -155,6 +155,45 @@ def test_batch_blocked_variants_bitwise_equal_single_steps():
 
 
 @gpu
+def test_batch_remainder_launches_bitwise_equal_single_steps():
+    # a run of n steps ends with one launch of an (n mod T)-step variant:
+    # every remainder of the T = 6 and T = 7 variants, graph and eager, with
+    # the variant for the last steps picked by shape (no launch times yet) and
+    # by the autotuner's launch times
+    torch = _torch()
+    from paper_2408_01081_amd.batch import Batch
+    probs = _problems()
+    fields = [p.initial_fields() for p in probs]
+    b = Batch([_params(p) for p in probs])
+    v0, s0 = b.pack([f[0] for f in fields]), b.pack([f[1] for f in fields])
+    b.init(v0, s0)
+    ref = {}
+    for n in range(1, 14):
+        b.step(1, graph=False)
+        ref[n] = b.moments(system=True).cpu().numpy()
+    long = [c["index"] for c in b.tblock_configs() if c["steps"] >= 6]
+    assert long
+
+    def check_all():
+        for idx in long:
+            T = b.tblock_configs()[idx]["steps"]
+            b.tblock_config = idx
+            for n in range(T + 1, 2 * T):
+                for graph in (True, False):
+                    b.init(v0, s0)
+                    b.step(n, graph=graph)
+                    got = b.moments(system=True).cpu().numpy()
+                    assert b.steps == n
+                    assert np.array_equal(got.view(np.uint32), ref[n].view(np.uint32)), \
+                        (idx, n, graph)
+
+    check_all()
+    b.init(v0, s0)
+    b.autotune(reps=1)
+    check_all()
+
+
+@gpu
 def test_batch_blocked_variants_with_moving_walls_bitwise_equal_single_lattices():
     # instances with moving walls (different ranks and sizes) beside periodic
     # and resting-wall ones: every blocked variant, graph and eager, gives
